@@ -1,0 +1,370 @@
+/*
+ * Determinant-CI oracle, tier B: textbook Slater-Condon rules.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file; it exists so that tests and the CPU baseline can check the
+ * GPU library against a plain, slow, obviously correct evaluation.  It shares
+ * no code with the library.
+ *
+ * What it computes (MetaWave, section 2.1, Eq. (1)):
+ *   H = sum_PQ h_PQ a+_P a_Q + 1/2 sum_PQRS (PQ|RS) a+_P a+_R a_S a_Q
+ * between determinants of a space, sigma_I = sum_J H_IJ c_J for every root,
+ * the diagonal H_II, the list of connected pairs with their phases, and the
+ * transition one- and two-particle density matrices
+ *   gamma_PQ   = sum_IJ conj(bra_I) ket_J <I|a+_P a_Q|J>
+ *   Gamma_PQRS = sum_IJ conj(bra_I) ket_J <I|a+_P a+_R a_S a_Q|J>.
+ *
+ * Conventions:
+ *  - A determinant is two words; global spin-orbital (spinor) position P
+ *    lives in word P/n at bit P%n.  |D> = prod_{P in D, ascending} a+_P |vac>.
+ *  - Spin-free: P < n is (p, alpha), P >= n is (p, beta); h_PQ and (PQ|RS)
+ *    vanish unless the spins pair up as in the spin-free Hamiltonian.
+ *  - Spinor: h is M x M, g is M^4 (M = 2n), complex, used as given.
+ *
+ * Method: for every requested row I, every J of the space is visited in
+ * ascending order; the excitation level follows from the popcount of I^J;
+ * the phase is counted literally, position by position.  All arithmetic is
+ * FP64 (complex as explicit re/im pairs); build with -ffp-contract=off.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct { double re, im; } cx;
+
+static cx cx_add(cx a, cx b) { cx r = {a.re + b.re, a.im + b.im}; return r; }
+static cx cx_sub(cx a, cx b) { cx r = {a.re - b.re, a.im - b.im}; return r; }
+static cx cx_mul(cx a, cx b) { cx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; return r; }
+static cx cx_conj(cx a) { cx r = {a.re, -a.im}; return r; }
+static cx cx_sgn(int s, cx a) { cx r = {s * a.re, s * a.im}; return r; }
+static const cx CX0 = {0.0, 0.0};
+
+typedef struct {
+    int kind;          /* 0 spin-free (real h n x n, g n^4), 1 spinor (complex M x M, M^4) */
+    int n;             /* bits used per word */
+    const double *h;   /* spin-free: real; spinor: interleaved re,im */
+    const double *g;
+    double ecore;
+} ham_t;
+
+static int spin_of(const ham_t *H, int P) { return P / H->n; }
+
+static cx h_so(const ham_t *H, int P, int Q)
+{
+    int n = H->n;
+    if (H->kind == 0) {
+        if (spin_of(H, P) != spin_of(H, Q)) return CX0;
+        cx r = {H->h[(P % n) * n + (Q % n)], 0.0};
+        return r;
+    }
+    int M = 2 * n;
+    cx r = {H->h[2 * ((size_t)P * M + Q)], H->h[2 * ((size_t)P * M + Q) + 1]};
+    return r;
+}
+
+/* (PQ|RS) in the spin-orbital / spinor basis */
+static cx g_so(const ham_t *H, int P, int Q, int R, int S)
+{
+    int n = H->n;
+    if (H->kind == 0) {
+        if (spin_of(H, P) != spin_of(H, Q) || spin_of(H, R) != spin_of(H, S)) return CX0;
+        size_t p = P % n, q = Q % n, r = R % n, s = S % n;
+        cx v = {H->g[((p * n + q) * n + r) * n + s], 0.0};
+        return v;
+    }
+    size_t M = 2 * (size_t)n;
+    size_t k = (((size_t)P * M + Q) * M + R) * M + S;
+    cx v = {H->g[2 * k], H->g[2 * k + 1]};
+    return v;
+}
+
+static int occupied(const uint64_t *d, int n, int P) { return (int)((d[P / n] >> (P % n)) & 1u); }
+
+/* number of occupied positions strictly between lo and hi */
+static int between(const uint64_t *d, int n, int a, int b)
+{
+    int lo = a < b ? a : b, hi = a < b ? b : a, c = 0;
+    for (int X = lo + 1; X < hi; X++) c += occupied(d, n, X);
+    return c;
+}
+
+static int parity(int c) { return (c & 1) ? -1 : 1; }
+
+/* positions occupied in x but not in y, ascending; returns count */
+static int diff_positions(const uint64_t *x, const uint64_t *y, int n, int *out, int cap)
+{
+    int k = 0;
+    for (int P = 0; P < 2 * n; P++)
+        if (occupied(x, n, P) && !occupied(y, n, P)) {
+            if (k < cap) out[k] = P;
+            k++;
+        }
+    return k;
+}
+
+/* Excitation analysis of the pair (I, J).  Returns the level (0, 1, 2) or
+ * -1 when the pair is not connected by H.  For level 1: P (in I), Q (in J).
+ * For level 2: particles P < R (in I), holes Q < S (in J).  sign is
+ * <I| a+_P a_Q |J> or <I| a+_P a+_R a_S a_Q |J>. */
+static int excitation(const uint64_t *I, const uint64_t *J, int n,
+                      int *P, int *Q, int *R, int *S, int *sign)
+{
+    int nel_i = __builtin_popcountll(I[0]) + __builtin_popcountll(I[1]);
+    int nel_j = __builtin_popcountll(J[0]) + __builtin_popcountll(J[1]);
+    if (nel_i != nel_j) return -1;
+    int pc = __builtin_popcountll(I[0] ^ J[0]) + __builtin_popcountll(I[1] ^ J[1]);
+    if (pc == 0) { *sign = 1; return 0; }
+    if (pc > 4) return -1;
+    int part[2], hole[2];
+    int np = diff_positions(I, J, n, part, 2);
+    int nh = diff_positions(J, I, n, hole, 2);
+    if (np != nh) return -1;
+    if (np == 1) {
+        *P = part[0]; *Q = hole[0];
+        *sign = parity(between(J, n, *P, *Q));
+        return 1;
+    }
+    *P = part[0]; *R = part[1]; *Q = hole[0]; *S = hole[1];
+    /* a+_P a+_R a_S a_Q = (a+_P a_Q)(a+_R a_S) since Q != R: apply R<-S to J
+     * first, then P<-Q to the result */
+    uint64_t K[2] = {J[0], J[1]};
+    int s1 = parity(between(K, n, *R, *S));
+    K[*S / n] &= ~(1ull << (*S % n));
+    K[*R / n] |= (1ull << (*R % n));
+    int s2 = parity(between(K, n, *P, *Q));
+    *sign = s1 * s2;
+    return 2;
+}
+
+static cx hij(const ham_t *H, const uint64_t *I, const uint64_t *J, int n)
+{
+    int P = -1, Q = -1, R = -1, S = -1, sign = 0;
+    int lvl = excitation(I, J, n, &P, &Q, &R, &S, &sign);
+    if (lvl < 0) return CX0;
+    if (lvl == 0) {
+        cx e = {H->ecore, 0.0};
+        for (int A = 0; A < 2 * n; A++) {
+            if (!occupied(I, n, A)) continue;
+            e = cx_add(e, h_so(H, A, A));
+            for (int B = A + 1; B < 2 * n; B++) {
+                if (!occupied(I, n, B)) continue;
+                e = cx_add(e, cx_sub(g_so(H, A, A, B, B), g_so(H, A, B, B, A)));
+            }
+        }
+        return e;
+    }
+    if (lvl == 1) {
+        cx e = h_so(H, P, Q);
+        for (int X = 0; X < 2 * n; X++) {
+            if (X == Q || !occupied(J, n, X)) continue;
+            e = cx_add(e, cx_sub(g_so(H, P, Q, X, X), g_so(H, P, X, X, Q)));
+        }
+        return cx_sgn(sign, e);
+    }
+    return cx_sgn(sign, cx_sub(g_so(H, P, Q, R, S), g_so(H, P, S, R, Q)));
+}
+
+/* ------------------------------------------------------------------------ */
+
+/* sigma[r][k] = sum_J H_{I_r J} c[J][k] for each requested row I_r.
+ * c, sigma interleaved complex, [ndet][nroots] and [nrows][nroots]. */
+void orc_sigma_rows(int kind, int n, const double *h, const double *g, double ecore,
+                    long ndet, const uint64_t *dets, int nroots, const double *c,
+                    long nrows, const long *rows, double *sigma)
+{
+    ham_t H = {kind, n, h, g, ecore};
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long r = 0; r < nrows; r++) {
+        const uint64_t *I = dets + 2 * rows[r];
+        cx *acc = (cx *)calloc((size_t)nroots, sizeof(cx));
+        for (long j = 0; j < ndet; j++) {
+            const uint64_t *J = dets + 2 * j;
+            int pc = __builtin_popcountll(I[0] ^ J[0]) + __builtin_popcountll(I[1] ^ J[1]);
+            if (pc > 4) continue;
+            cx v = hij(&H, I, J, n);
+            for (int k = 0; k < nroots; k++) {
+                cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+                acc[k] = cx_add(acc[k], cx_mul(v, cj));
+            }
+        }
+        for (int k = 0; k < nroots; k++) {
+            sigma[2 * (r * nroots + k)] = acc[k].re;
+            sigma[2 * (r * nroots + k) + 1] = acc[k].im;
+        }
+        free(acc);
+    }
+}
+
+/* Matrix elements H_{I J} for explicit (I, J) index pairs. */
+void orc_hij_pairs(int kind, int n, const double *h, const double *g, double ecore,
+                   const uint64_t *dets, long npairs, const long *ij, double *out)
+{
+    ham_t H = {kind, n, h, g, ecore};
+    #pragma omp parallel for schedule(static)
+    for (long t = 0; t < npairs; t++) {
+        cx v = hij(&H, dets + 2 * ij[2 * t], dets + 2 * ij[2 * t + 1], n);
+        out[2 * t] = v.re;
+        out[2 * t + 1] = v.im;
+    }
+}
+
+/* Number of connected J != I for each requested row (level 1 or 2). */
+void orc_degree_rows(int n, long ndet, const uint64_t *dets, long nrows, const long *rows, long *deg)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long r = 0; r < nrows; r++) {
+        const uint64_t *I = dets + 2 * rows[r];
+        long cnt = 0;
+        for (long j = 0; j < ndet; j++) {
+            int P, Q, R, S, sg;
+            if (j == rows[r]) continue;
+            int lvl = excitation(I, dets + 2 * j, n, &P, &Q, &R, &S, &sg);
+            if (lvl == 1 || lvl == 2) cnt++;
+        }
+        deg[r] = cnt;
+    }
+}
+
+/* Connected pairs of the requested rows, J ascending.  Record layout
+ * (int64 x 7): I, J, P, Q, R, S, sign  (R = S = -1 for singles).
+ * First call with out == NULL returns the count. */
+long orc_connect_rows(int n, long ndet, const uint64_t *dets, long nrows, const long *rows,
+                      long *out)
+{
+    long total = 0;
+    for (long r = 0; r < nrows; r++) {
+        const uint64_t *I = dets + 2 * rows[r];
+        for (long j = 0; j < ndet; j++) {
+            int P = -1, Q = -1, R = -1, S = -1, sg = 0;
+            if (j == rows[r]) continue;
+            int lvl = excitation(I, dets + 2 * j, n, &P, &Q, &R, &S, &sg);
+            if (lvl != 1 && lvl != 2) continue;
+            if (out) {
+                long *o = out + 7 * total;
+                o[0] = rows[r]; o[1] = j; o[2] = P; o[3] = Q;
+                o[4] = lvl == 2 ? R : -1; o[5] = lvl == 2 ? S : -1; o[6] = sg;
+            }
+            total++;
+        }
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transition density matrices.  For every connected (I, J) all index tuples
+ * with a nonzero operator element are listed structurally and their phase is
+ * obtained by applying the operators one by one to J.                        */
+
+/* apply a_X (create=0) or a+_X (create=1) to string d in place; returns the
+ * sign, or 0 when the result vanishes */
+static int apply_op(uint64_t *d, int n, int X, int create)
+{
+    int occ = occupied(d, n, X);
+    if (create == occ) return 0;
+    int below = 0;
+    for (int Y = 0; Y < X; Y++) below += occupied(d, n, Y);
+    d[X / n] ^= (1ull << (X % n));
+    return parity(below);
+}
+
+/* <I| a+_P a+_R a_S a_Q |J> by literal application */
+static int op2(const uint64_t *I, const uint64_t *J, int n, int P, int Q, int R, int S)
+{
+    uint64_t d[2] = {J[0], J[1]};
+    int s = apply_op(d, n, Q, 0); if (!s) return 0;
+    int t = apply_op(d, n, S, 0); if (!t) return 0; s *= t;
+    t = apply_op(d, n, R, 1); if (!t) return 0; s *= t;
+    t = apply_op(d, n, P, 1); if (!t) return 0; s *= t;
+    return (d[0] == I[0] && d[1] == I[1]) ? s : 0;
+}
+
+static int op1(const uint64_t *I, const uint64_t *J, int n, int P, int Q)
+{
+    uint64_t d[2] = {J[0], J[1]};
+    int s = apply_op(d, n, Q, 0); if (!s) return 0;
+    int t = apply_op(d, n, P, 1); if (!t) return 0; s *= t;
+    return (d[0] == I[0] && d[1] == I[1]) ? s : 0;
+}
+
+/* Output index maps: spin-free results are spin-summed over the spatial
+ * orbitals (gamma_pq, Gamma_pqrs over n); spinor results are over M. */
+static size_t idx2(int kind, int n, int P, int Q)
+{
+    if (kind == 0) return (size_t)(P % n) * n + (Q % n);
+    return (size_t)P * (2 * n) + Q;
+}
+static size_t idx4(int kind, int n, int P, int Q, int R, int S)
+{
+    size_t m = kind == 0 ? (size_t)n : (size_t)2 * n;
+    size_t p = kind == 0 ? P % n : P, q = kind == 0 ? Q % n : Q;
+    size_t r = kind == 0 ? R % n : R, s = kind == 0 ? S % n : S;
+    return ((p * m + q) * m + r) * m + s;
+}
+
+/* Accumulate for the requested bra rows (all J).  gamma, Gamma interleaved
+ * complex, zero-initialised by the caller.  Single-threaded so that the
+ * summation order is fixed. */
+void orc_rdm_rows(int kind, int n, long ndet, const uint64_t *dets, int nroots,
+                  const double *bra, const double *ket, const double *weights,
+                  long nrows, const long *rows, double *gamma, double *Gamma)
+{
+    int M = 2 * n;
+    int (*tup)[4] = (int (*)[4])malloc(sizeof(int[4]) * (size_t)(2 * M * M + 16));
+    for (long r = 0; r < nrows; r++) {
+        long i = rows[r];
+        const uint64_t *I = dets + 2 * i;
+        for (long j = 0; j < ndet; j++) {
+            const uint64_t *J = dets + 2 * j;
+            int P = -1, Q = -1, R = -1, S = -1, sg = 0;
+            int lvl = excitation(I, J, n, &P, &Q, &R, &S, &sg);
+            if (lvl < 0) continue;
+            cx w = CX0;
+            for (int k = 0; k < nroots; k++) {
+                cx b = {bra[2 * (i * nroots + k)], bra[2 * (i * nroots + k) + 1]};
+                cx kt = {ket[2 * (j * nroots + k)], ket[2 * (j * nroots + k) + 1]};
+                cx t = cx_mul(cx_conj(b), kt);
+                double wk = weights ? weights[k] : 1.0;
+                cx wt = {wk * t.re, wk * t.im};
+                w = cx_add(w, wt);
+            }
+            /* tuples (A,B,C,D) meaning a+_A a+_C a_D a_B */
+            int nt = 0;
+            if (lvl == 0) {
+                for (int A = 0; A < M; A++) {
+                    if (!occupied(I, n, A)) continue;
+                    int s = op1(I, J, n, A, A);
+                    size_t k1 = idx2(kind, n, A, A);
+                    gamma[2 * k1] += s * w.re; gamma[2 * k1 + 1] += s * w.im;
+                    for (int C = 0; C < M; C++) {
+                        if (C == A || !occupied(I, n, C)) continue;
+                        tup[nt][0] = A; tup[nt][1] = A; tup[nt][2] = C; tup[nt][3] = C; nt++;
+                        tup[nt][0] = A; tup[nt][1] = C; tup[nt][2] = C; tup[nt][3] = A; nt++;
+                    }
+                }
+            } else if (lvl == 1) {
+                int s = op1(I, J, n, P, Q);
+                size_t k1 = idx2(kind, n, P, Q);
+                gamma[2 * k1] += s * w.re; gamma[2 * k1 + 1] += s * w.im;
+                for (int X = 0; X < M; X++) {
+                    if (X == Q || !occupied(J, n, X)) continue;
+                    int t4[4][4] = {{P, Q, X, X}, {P, X, X, Q}, {X, Q, P, X}, {X, X, P, Q}};
+                    for (int u = 0; u < 4; u++) { memcpy(tup[nt], t4[u], sizeof t4[u]); nt++; }
+                }
+            } else {
+                int t4[4][4] = {{P, Q, R, S}, {R, S, P, Q}, {P, S, R, Q}, {R, Q, P, S}};
+                for (int u = 0; u < 4; u++) { memcpy(tup[nt], t4[u], sizeof t4[u]); nt++; }
+            }
+            for (int u = 0; u < nt; u++) {
+                /* the spin-summed spin-free Gamma_pqrs only pairs P with Q
+                 * and R with S of equal spin */
+                if (kind == 0 && (tup[u][0] / n != tup[u][1] / n || tup[u][2] / n != tup[u][3] / n))
+                    continue;
+                int s = op2(I, J, n, tup[u][0], tup[u][1], tup[u][2], tup[u][3]);
+                if (!s) continue;
+                size_t k4 = idx4(kind, n, tup[u][0], tup[u][1], tup[u][2], tup[u][3]);
+                Gamma[2 * k4] += s * w.re; Gamma[2 * k4 + 1] += s * w.im;
+            }
+        }
+    }
+    free(tup);
+}

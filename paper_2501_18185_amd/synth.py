@@ -1,0 +1,410 @@
+"""Seeded synthetic inputs: integrals, determinant spaces and CI vectors.
+
+This module is shared by the CPU oracle tests and the GPU path.  It holds
+none of the method's arithmetic (no matrix elements, phases or contractions):
+it only draws numbers and builds sorted occupation bitstrings.
+
+Conventions (shared with the C ABI in ``include/mw.h``):
+
+* A determinant is two 64-bit words ``(w0, w1)``.  Spin-free: ``w0`` holds the
+  alpha string and ``w1`` the beta string, spatial orbital ``p`` at bit ``p``.
+  Spinor (Kramers-paired spinors, paper section 2.1): ``w0`` holds the
+  unbarred (A) spinors and ``w1`` the barred (B) ones, pair ``k`` at bit ``k``.
+  This is the determinant analogue of the occupation bitstrings of section 2.2
+  (orbital 0 in the lowest bit).
+* Spaces are sorted strictly ascending as unsigned 128-bit keys, ``w0`` major.
+* Global spin-orbital / spinor position of word ``w`` bit ``b`` is ``w*n + b``.
+
+Seeds follow ``SeedSequence([2501, 18185, k, i, j])`` with ``k`` the workload
+index, ``i`` the problem index inside a batch and ``j`` the stream
+(0: h, 1: g, 2: space, 3: c).
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_H, SEED_G, SEED_SPACE, SEED_C = 0, 1, 2, 3
+
+
+def rng_for(k: int, i: int, j: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([2501, 18185, k, i, j]))
+
+
+# ---------------------------------------------------------------------------
+# integrals
+# ---------------------------------------------------------------------------
+
+def _orbit_canon_real(n: int):
+    """For every (p,q,r,s) the smallest flat index of its 8-fold orbit."""
+    p, q, r, s = np.meshgrid(*(np.arange(n, dtype=np.int64),) * 4, indexing="ij")
+    def flat(a, b, c, d):
+        return ((a * n + b) * n + c) * n + d
+    cands = [flat(p, q, r, s), flat(q, p, r, s), flat(p, q, s, r), flat(q, p, s, r),
+             flat(r, s, p, q), flat(s, r, p, q), flat(r, s, q, p), flat(s, r, q, p)]
+    canon = cands[0]
+    for c_ in cands[1:]:
+        canon = np.minimum(canon, c_)
+    return canon.reshape(-1)
+
+
+def one_body_real(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Symmetric h: diagonal ascending linearly over [-2, 1], off-diagonal N(0, 0.05^2)."""
+    h = np.zeros((n, n))
+    diag = np.array([-2.0 + 3.0 * p / (n - 1) for p in range(n)]) if n > 1 else np.array([-2.0])
+    off = rng.normal(0.0, 0.05, size=(n, n))
+    iu = np.triu_indices(n, 1)
+    h[iu] = off[iu]
+    h = h + h.T
+    h[np.diag_indices(n)] = diag
+    return h
+
+
+def two_body_real(n: int, rng: np.random.Generator) -> np.ndarray:
+    """8-fold symmetric (pq|rs), shape (n,n,n,n).
+
+    Orbits with p==q and r==s draw U(0.3, 0.7) (Coulomb-like); every other
+    orbit draws N(0, 0.02^2) * exp(-|p-q|/4) with (p,q) of its canonical
+    (smallest flat index) member.
+    """
+    canon = _orbit_canon_real(n)
+    m = n ** 4
+    uni = rng.uniform(0.3, 0.7, size=m)
+    nor = rng.normal(0.0, 0.02, size=m)
+    cp = canon // (n ** 3)
+    cq = (canon // (n ** 2)) % n
+    cr = (canon // n) % n
+    cs = canon % n
+    coul = (cp == cq) & (cr == cs)
+    val_canon = np.where(coul, uni[canon], nor[canon] * np.exp(-np.abs(cp - cq) / 4.0))
+    return val_canon.reshape(n, n, n, n)
+
+
+def one_body_spinor(nk: int, rng: np.random.Generator) -> np.ndarray:
+    """Hermitian h over M = 2*nk spinors (A_k at k, B_k at nk+k).
+
+    Kramers-degenerate diagonal h[A_k,A_k] = h[B_k,B_k] ascending over [-2, 1];
+    off-diagonal magnitude N(0, 0.05^2) with a uniform phase.
+    """
+    M = 2 * nk
+    diag = np.array([-2.0 + 3.0 * k / (nk - 1) for k in range(nk)]) if nk > 1 else np.array([-2.0])
+    mag = rng.normal(0.0, 0.05, size=(M, M))
+    ph = rng.uniform(0.0, 2 * np.pi, size=(M, M))
+    h = np.zeros((M, M), dtype=np.complex128)
+    iu = np.triu_indices(M, 1)
+    h[iu] = (mag * np.exp(1j * ph))[iu]
+    h = h + h.conj().T
+    h[np.diag_indices(M)] = np.concatenate([diag, diag])
+    return h
+
+
+def two_body_spinor(nk: int, rng: np.random.Generator) -> np.ndarray:
+    """Complex (PQ|RS) over M = 2*nk spinors with (PQ|RS) = (RS|PQ) = (QP|SR)*.
+
+    Orbits {(PQ|RS), (RS|PQ), (QP|SR)*, (SR|QP)*} share one value.  Orbits
+    with P==Q and R==S are real U(0.3, 0.7); other self-conjugate orbits
+    (P==S and Q==R) are real N(0, 0.02^2) * exp(-|k(P)-k(Q)|/4); the rest
+    carry that magnitude times a uniform phase.  k(P) is the Kramers pair.
+    """
+    M = 2 * nk
+    P, Q, R, S = np.meshgrid(*(np.arange(M, dtype=np.int64),) * 4, indexing="ij")
+    def flat(a, b, c, d):
+        return ((a * M + b) * M + c) * M + d
+    f1 = flat(P, Q, R, S).reshape(-1)
+    f2 = flat(R, S, P, Q).reshape(-1)
+    f3 = flat(Q, P, S, R).reshape(-1)
+    f4 = flat(S, R, Q, P).reshape(-1)
+    del P, Q, R, S
+    canon = np.minimum(np.minimum(f1, f2), np.minimum(f3, f4))
+    conj = (canon == f3) | (canon == f4)
+    del f1, f2, f3, f4
+    m = M ** 4
+    uni = rng.uniform(0.3, 0.7, size=m)
+    nor = rng.normal(0.0, 0.02, size=m)
+    ph = rng.uniform(0.0, 2 * np.pi, size=m)
+    cp = canon // (M ** 3)
+    cq = (canon // (M ** 2)) % M
+    cr = (canon // M) % M
+    cs = canon % M
+    coul = (cp == cq) & (cr == cs)
+    selfc = coul | ((cp == cs) & (cq == cr))
+    kp, kq = cp % nk, cq % nk
+    mag = nor[canon] * np.exp(-np.abs(kp - kq) / 4.0)
+    val = np.where(coul, uni[canon] + 0j, np.where(selfc, mag + 0j, mag * np.exp(1j * ph[canon])))
+    val = np.where(conj & ~selfc, val.conj(), val)
+    return val.reshape(M, M, M, M)
+
+
+# ---------------------------------------------------------------------------
+# determinant spaces
+# ---------------------------------------------------------------------------
+
+def _words(pos: np.ndarray, n: int):
+    """Global positions (..., k) with -1 padding -> (w0, w1) uint64 masks."""
+    pos = np.asarray(pos, dtype=np.int64)
+    valid = pos >= 0
+    word = np.where(valid, pos // n, 0)
+    bit = np.where(valid, pos % n, 0).astype(np.uint64)
+    one = np.where(valid, np.left_shift(np.uint64(1), bit), np.uint64(0))
+    w0 = np.bitwise_or.reduce(np.where(word == 0, one, np.uint64(0)), axis=-1)
+    w1 = np.bitwise_or.reduce(np.where(word == 1, one, np.uint64(0)), axis=-1)
+    return w0.astype(np.uint64), w1.astype(np.uint64)
+
+
+def sort_unique(w0: np.ndarray, w1: np.ndarray) -> np.ndarray:
+    d = np.stack([np.asarray(w0, np.uint64), np.asarray(w1, np.uint64)], axis=1)
+    order = np.lexsort((d[:, 1], d[:, 0]))
+    d = d[order]
+    if len(d) > 1:
+        keep = np.ones(len(d), bool)
+        keep[1:] = (d[1:, 0] != d[:-1, 0]) | (d[1:, 1] != d[:-1, 1])
+        d = d[keep]
+    return np.ascontiguousarray(d)
+
+
+def space_fci(n: int, na: int, nb: int) -> np.ndarray:
+    """Every determinant with na alpha and nb beta electrons in n orbitals."""
+    def strings(k):
+        out = []
+        for occ in itertools.combinations(range(n), k):
+            v = 0
+            for p in occ:
+                v |= 1 << p
+            out.append(v)
+        return np.array(sorted(out), dtype=np.uint64)
+    a, b = strings(na), strings(nb)
+    w0 = np.repeat(a, len(b))
+    w1 = np.tile(b, len(a))
+    return sort_unique(w0, w1)
+
+
+def _excite(hf0, hf1, n, holes, parts):
+    """Apply hole/particle global-position lists (-1 padded) to the HF words."""
+    h0, h1 = _words(holes, n)
+    p0, p1 = _words(parts, n)
+    return (hf0 ^ h0) | p0, (hf1 ^ h1) | p1
+
+
+def _all_excitations(occ, vir, k):
+    """All (holes, particles) of rank k from occ x vir (global positions)."""
+    hs = list(itertools.combinations(occ, k))
+    ps = list(itertools.combinations(vir, k))
+    if not hs or not ps:
+        return np.zeros((0, k), np.int64), np.zeros((0, k), np.int64)
+    H = np.repeat(np.array(hs, np.int64), len(ps), axis=0)
+    Pp = np.tile(np.array(ps, np.int64), (len(hs), 1))
+    return H, Pp
+
+
+def _hf_and_sd_spinfree(n, na, nb):
+    occa = list(range(na)); vira = list(range(na, n))
+    occb = [n + p for p in range(nb)]; virb = [n + p for p in range(nb, n)]
+    hf0 = np.uint64((1 << na) - 1); hf1 = np.uint64((1 << nb) - 1)
+    ws0 = [np.array([hf0], np.uint64)]; ws1 = [np.array([hf1], np.uint64)]
+    for occ, vir in ((occa, vira), (occb, virb)):
+        for k in (1, 2):
+            H, Pp = _all_excitations(occ, vir, k)
+            if len(H):
+                a, b = _excite(hf0, hf1, n, H, Pp)
+                ws0.append(a); ws1.append(b)
+    Ha, Pa = _all_excitations(occa, vira, 1)
+    Hb, Pb = _all_excitations(occb, virb, 1)
+    if len(Ha) and len(Hb):
+        H = np.concatenate([np.repeat(Ha, len(Hb), 0), np.tile(Hb, (len(Ha), 1))], 1)
+        Pp = np.concatenate([np.repeat(Pa, len(Pb), 0), np.tile(Pb, (len(Pa), 1))], 1)
+        a, b = _excite(hf0, hf1, n, H, Pp)
+        ws0.append(a); ws1.append(b)
+    return hf0, hf1, np.concatenate(ws0), np.concatenate(ws1)
+
+
+def _random_subsets(rng, m, pool, kmax):
+    """m rows of kmax distinct entries of pool, uniformly without replacement."""
+    pool = np.asarray(pool, np.int64)
+    if len(pool) < kmax:
+        raise ValueError("pool too small")
+    idx = np.argsort(rng.random((m, len(pool))), axis=1)[:, :kmax]
+    return pool[idx]
+
+
+def _fill_random(base0, base1, target, gen_batch):
+    """Append unique random determinants from gen_batch() until target."""
+    have = sort_unique(base0, base1)
+    if len(have) > target:
+        raise ValueError(f"singles+doubles ({len(have)}) exceed target {target}")
+    new0, new1 = [], []
+    need = target - len(have)
+    seen = have
+    while need > 0:
+        c0, c1 = gen_batch(int(need * 1.15) + 64)
+        allk = np.concatenate([np.stack([seen[:, 0], seen[:, 1]], 1), np.stack([c0, c1], 1)])
+        rec = np.empty(len(allk), dtype=[("a", "<u8"), ("b", "<u8")])
+        rec["a"], rec["b"] = allk[:, 0], allk[:, 1]
+        _, first = np.unique(rec, return_index=True)
+        first = np.sort(first[first >= len(seen)]) - len(seen)
+        first = first[:need]
+        new0.append(c0[first]); new1.append(c1[first])
+        need -= len(first)
+        seen = sort_unique(np.concatenate([seen[:, 0], c0[first]]),
+                           np.concatenate([seen[:, 1], c1[first]]))
+    if new0:
+        return sort_unique(np.concatenate([have[:, 0]] + new0), np.concatenate([have[:, 1]] + new1))
+    return have
+
+
+def space_selected_spinfree(n, na, nb, target, rng, ranks=(3, 4)):
+    """HF + all singles + all doubles + random higher excitations up to target.
+
+    Random rank uniform over ``ranks``; alpha/beta split uniform over the
+    feasible (k_alpha, k_beta); holes and particles uniform without
+    replacement; duplicates rejected.
+    """
+    hf0, hf1, w0, w1 = _hf_and_sd_spinfree(n, na, nb)
+    occa = np.arange(na); vira = np.arange(na, n)
+    occb = n + np.arange(nb); virb = n + np.arange(nb, n)
+    kmax = max(ranks)
+
+    def gen(m):
+        rank = rng.choice(np.array(ranks), size=m)
+        ka = np.empty(m, np.int64)
+        for r in ranks:
+            feas = [a for a in range(r + 1)
+                    if a <= min(na, n - na) and (r - a) <= min(nb, n - nb)]
+            sel = rank == r
+            ka[sel] = rng.choice(np.array(feas), size=int(sel.sum()))
+        kb = rank - ka
+        ha = _random_subsets(rng, m, occa, min(kmax, na))
+        pa = _random_subsets(rng, m, vira, min(kmax, n - na))
+        hb = _random_subsets(rng, m, occb, min(kmax, nb))
+        pb = _random_subsets(rng, m, virb, min(kmax, n - nb))
+        cols = np.arange(ha.shape[1]); colsp = np.arange(pa.shape[1])
+        colb = np.arange(hb.shape[1]); colpb = np.arange(pb.shape[1])
+        ha = np.where(cols[None, :] < ka[:, None], ha, -1)
+        pa = np.where(colsp[None, :] < ka[:, None], pa, -1)
+        hb = np.where(colb[None, :] < kb[:, None], hb, -1)
+        pb = np.where(colpb[None, :] < kb[:, None], pb, -1)
+        H = np.concatenate([ha, hb], 1); Pp = np.concatenate([pa, pb], 1)
+        return _excite(hf0, hf1, n, H, Pp)
+
+    return _fill_random(w0, w1, target, gen)
+
+
+def space_selected_spinor(nk, nel, target, rng, ranks=(3,)):
+    """Spinor space over M = 2*nk spinors: HF (pairs 0..nel/2-1 in A and B)
+    + all singles + all doubles + random higher excitations (total N kept)."""
+    if nel % 2:
+        raise ValueError("closed-shell Kramers HF needs even nel")
+    half = nel // 2
+    occ = list(range(half)) + [nk + k for k in range(half)]
+    vir = [p for p in range(2 * nk) if p not in occ]
+    hf0 = np.uint64((1 << half) - 1); hf1 = np.uint64((1 << half) - 1)
+    ws0 = [np.array([hf0], np.uint64)]; ws1 = [np.array([hf1], np.uint64)]
+    for k in (1, 2):
+        H, Pp = _all_excitations(occ, vir, k)
+        a, b = _excite(hf0, hf1, nk, H, Pp)
+        ws0.append(a); ws1.append(b)
+    w0, w1 = np.concatenate(ws0), np.concatenate(ws1)
+    kmax = max(ranks)
+
+    def gen(m):
+        rank = rng.choice(np.array(ranks), size=m)
+        H = _random_subsets(rng, m, occ, kmax)
+        Pp = _random_subsets(rng, m, vir, kmax)
+        cols = np.arange(kmax)
+        H = np.where(cols[None, :] < rank[:, None], H, -1)
+        Pp = np.where(cols[None, :] < rank[:, None], Pp, -1)
+        return _excite(hf0, hf1, nk, H, Pp)
+
+    return _fill_random(w0, w1, target, gen)
+
+
+def random_space_spinfree(n, na, nb, ndet, rng):
+    """ndet distinct determinants drawn uniformly from the full space (tiny n)."""
+    full = space_fci(n, na, nb)
+    idx = np.sort(rng.choice(len(full), size=min(ndet, len(full)), replace=False))
+    return np.ascontiguousarray(full[idx])
+
+
+def ci_vectors(ndet, nroots, rng, complex_=False):
+    """[ndet][nroots] N(0,1) entries, each root column normalised to 1."""
+    if complex_:
+        c = rng.normal(size=(ndet, nroots)) + 1j * rng.normal(size=(ndet, nroots))
+    else:
+        c = rng.normal(size=(ndet, nroots))
+    c = c / np.linalg.norm(c, axis=0, keepdims=True)
+    return np.ascontiguousarray(c)
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    kind: str                 # "spinfree" | "spinor"
+    norb: int                 # spatial orbitals or Kramers pairs
+    nalpha: int               # N_alpha (spin-free) or total N (spinor)
+    nbeta: int                # N_beta (spin-free) or -1 (spinor)
+    dets: np.ndarray          # [ndet][2] uint64, sorted
+    h: np.ndarray
+    g: np.ndarray
+    ecore: float = 0.0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndet(self):
+        return len(self.dets)
+
+    @property
+    def is_complex(self):
+        return self.kind == "spinor"
+
+    @property
+    def nelec(self):
+        return self.nalpha + (self.nbeta if self.kind == "spinfree" else 0)
+
+
+def batch_shapes(i: int):
+    """Shape of problem i of the 16-problem batch."""
+    n = 16 + (32 * i) // 15
+    ne = 6 + (6 * i) // 15
+    nd = int(round(1e4 * 50 ** (i / 15)))
+    return n, ne, nd
+
+
+def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
+    """Workload k (0 FCI n=8 4a4b; 1 selected n=64 10a10b 2e6; 2 spinor
+    40 pairs N=20 1e6; 3 batch problem i; 4 FD case n=10 3a3b FCI).
+
+    ``scale`` < 1 shrinks the random part of selected spaces (for tests)."""
+    if k == 0:
+        n, na, nb = 8, 4, 4
+        return Problem("spinfree", n, na, nb, space_fci(n, na, nb),
+                       one_body_real(n, rng_for(0, 0, SEED_H)),
+                       two_body_real(n, rng_for(0, 0, SEED_G)), name="fci-n8-4a4b")
+    if k == 1:
+        n, na = 64, 10
+        target = int(2_000_000 * scale)
+        d = space_selected_spinfree(n, na, na, max(target, 421_471), rng_for(1, 0, SEED_SPACE))
+        return Problem("spinfree", n, na, na, d, one_body_real(n, rng_for(1, 0, SEED_H)),
+                       two_body_real(n, rng_for(1, 0, SEED_G)), name="sci-n64-10a10b")
+    if k == 2:
+        nk, ne = 40, 20
+        target = int(1_000_000 * scale)
+        d = space_selected_spinor(nk, ne, max(target, 337_501), rng_for(2, 0, SEED_SPACE))
+        return Problem("spinor", nk, ne, -1, d, one_body_spinor(nk, rng_for(2, 0, SEED_H)),
+                       two_body_spinor(nk, rng_for(2, 0, SEED_G)), name="spinor-40kp-20e")
+    if k == 3:
+        n, ne, nd = batch_shapes(i)
+        nd = int(nd * scale) if scale != 1.0 else nd
+        d = space_selected_spinfree(n, ne, ne, nd, rng_for(3, i, SEED_SPACE))
+        return Problem("spinfree", n, ne, ne, d, one_body_real(n, rng_for(3, i, SEED_H)),
+                       two_body_real(n, rng_for(3, i, SEED_G)), name=f"batch{i}-n{n}-{ne}a{ne}b")
+    if k == 4:
+        n, na, nb = 10, 3, 3
+        return Problem("spinfree", n, na, nb, space_fci(n, na, nb),
+                       one_body_real(n, rng_for(4, 0, SEED_H)),
+                       two_body_real(n, rng_for(4, 0, SEED_G)), name="fci-n10-3a3b")
+    raise ValueError(k)

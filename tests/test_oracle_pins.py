@@ -1,0 +1,440 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test names the property it pins.  Tier A (literal operator application
+of Eq. (1), section 2.1) and tier B (Slater-Condon in C) are checked against
+closed forms, invariances and brute force, and against each other.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2501_18185_amd import synth
+from oracle import davidson, literal, sc
+
+pytestmark = pytest.mark.filterwarnings("ignore::numpy.exceptions.ComplexWarning")
+
+
+def _prob(kind, n, na, nb, dets, h, g, ecore=0.0):
+    return synth.Problem(kind, n, na, nb, np.ascontiguousarray(dets, np.uint64), h, g, ecore)
+
+
+def _spinor_space(nk, nel):
+    pos = np.array(list(itertools.combinations(range(2 * nk), nel)), np.int64)
+    return synth.sort_unique(*synth._words(pos, nk))
+
+
+def _random_real(n, seed):
+    rng = np.random.default_rng(seed)
+    return synth.one_body_real(n, rng), synth.two_body_real(n, rng)
+
+
+def _random_spinor(nk, seed):
+    rng = np.random.default_rng(seed)
+    return synth.one_body_spinor(nk, rng), synth.two_body_spinor(nk, rng)
+
+
+def _both_dense(p):
+    return literal.hamiltonian(p), sc.dense_h(p)
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("t,U", [(1.0, 4.0), (0.3, 1.7), (1.0, 0.0)])
+def test_hubbard_two_site_closed_form(t, U):
+    """Two-site Hubbard dimer, 1 alpha + 1 beta: E0 = (U - sqrt(U^2+16t^2))/2.
+    The on-site term U n_up n_dn is 1/2 sum (PQ|RS) a+a+aa with (00|00) =
+    (11|11) = U, so a dropped 1/2 or a wrong spin pairing fails here."""
+    h = np.array([[0.0, -t], [-t, 0.0]])
+    g = np.zeros((2, 2, 2, 2))
+    g[0, 0, 0, 0] = g[1, 1, 1, 1] = U
+    p = _prob("spinfree", 2, 1, 1, synth.space_fci(2, 1, 1), h, g)
+    exact = (U - np.sqrt(U * U + 16 * t * t)) / 2
+    for H in _both_dense(p):
+        assert abs(np.linalg.eigvalsh(H)[0] - exact) < 1e-13
+
+
+def test_two_electron_two_orbital_closed_form():
+    """2 electrons in 2 orbitals with h diagonal and only Coulomb
+    J_pq=(pp|qq) and exchange K=(12|21) integrals: the spectrum is the
+    triplet h1+h2+J12-K, the open-shell singlet h1+h2+J12+K and the
+    closed-shell 2x2 block [[2h1+J11, K], [K, 2h2+J22]].  Swapping the
+    (pq|rs) index roles exchanges J12 and K and fails this."""
+    h1, h2, J11, J22, J12, K = -1.3, -0.4, 0.71, 0.55, 0.43, 0.17
+    h = np.diag([h1, h2])
+    g = np.zeros((2, 2, 2, 2))
+    g[0, 0, 0, 0], g[1, 1, 1, 1] = J11, J22
+    g[0, 0, 1, 1] = g[1, 1, 0, 0] = J12
+    for idx in [(0, 1, 1, 0), (1, 0, 0, 1), (0, 1, 0, 1), (1, 0, 1, 0)]:
+        g[idx] = K
+    p = _prob("spinfree", 2, 1, 1, synth.space_fci(2, 1, 1), h, g)
+    closed = np.linalg.eigvalsh(np.array([[2 * h1 + J11, K], [K, 2 * h2 + J22]]))
+    exact = np.sort(np.concatenate([closed, [h1 + h2 + J12 - K, h1 + h2 + J12 + K]]))
+    for H in _both_dense(p):
+        assert np.allclose(np.linalg.eigvalsh(H), exact, atol=1e-13, rtol=0)
+
+
+@pytest.mark.parametrize("n,na,nb", [(4, 2, 2), (5, 3, 1), (4, 1, 2)])
+def test_one_body_closed_form_spinfree(n, na, nb):
+    """g = 0: FCI ground state = sum of the lowest na plus lowest nb
+    eigenvalues of h (independent particles)."""
+    h, _ = _random_real(n, 7 + n)
+    p = _prob("spinfree", n, na, nb, synth.space_fci(n, na, nb), h, np.zeros((n,) * 4))
+    eps = np.linalg.eigvalsh(h)
+    exact = eps[:na].sum() + eps[:nb].sum()
+    for H in _both_dense(p):
+        assert abs(np.linalg.eigvalsh(H)[0] - exact) < 1e-12
+
+
+@pytest.mark.parametrize("nk,nel", [(3, 2), (3, 3)])
+def test_one_body_closed_form_spinor(nk, nel):
+    """g = 0, spinor: lowest eigenvalue = sum of the nel lowest eigenvalues
+    of the Hermitian M x M h."""
+    h, _ = _random_spinor(nk, 11)
+    M = 2 * nk
+    p = _prob("spinor", nk, nel, -1, _spinor_space(nk, nel), h, np.zeros((M,) * 4, complex))
+    exact = np.linalg.eigvalsh(h)[:nel].sum()
+    for H in _both_dense(p):
+        assert abs(np.linalg.eigvalsh(H)[0] - exact) < 1e-12
+
+
+def test_single_electron_sigma_is_h_times_c():
+    """N = 1 (one alpha electron): H_IJ = h_pq exactly, so sigma = h c."""
+    n = 6
+    h, g = _random_real(n, 3)
+    p = _prob("spinfree", n, 1, 0, synth.space_fci(n, 1, 0), h, g)
+    # det I has its electron at orbital I (sorted by the alpha word)
+    c = np.random.default_rng(0).normal(size=n)
+    assert np.array_equal(sc.sigma(p, c), np.array([sum(h[i, j] * c[j] for j in range(n)) for i in range(n)]))
+    assert np.allclose(literal.hamiltonian(p), h, atol=1e-15)
+
+
+def test_single_electron_spinor():
+    """N = 1 spinor: H_IJ = h_{P(I) P(J)} with P the occupied position."""
+    nk = 3
+    h, g = _random_spinor(nk, 5)
+    d = _spinor_space(nk, 1)
+    pos = np.array([int(np.log2(a)) if a else nk + int(np.log2(b)) for a, b in d])
+    p = _prob("spinor", nk, 1, -1, d, h, g)
+    ref = h[np.ix_(pos, pos)]
+    for H in _both_dense(p):
+        assert np.allclose(H, ref, atol=1e-15, rtol=0)
+
+
+def test_diagonal_integrals_closed_form():
+    """h diagonal and g nonzero only on (pp|qq) and (pq|qp):
+    H_II = sum_p h_pp n_p + 1/2 sum_pq (pp|qq) n_p n_q
+           - 1/2 sum_pq (pq|qp) (n_pa n_qa + n_pb n_qb)   (occupation form),
+    and the only off-diagonal elements are the spin exchanges (alpha q->p with
+    beta p->q), which keep every spatial occupation and have |H_IJ| = (pq|qp)."""
+    n = 5
+    rng = np.random.default_rng(4)
+    h = np.diag(rng.normal(size=n))
+    g = np.zeros((n,) * 4)
+    J = rng.uniform(0.2, 0.8, size=(n, n)); J = J + J.T
+    K = rng.uniform(0.0, 0.2, size=(n, n)); K = K + K.T
+    for a in range(n):
+        for b in range(n):
+            g[a, a, b, b] = J[a, b]
+            if a != b:
+                g[a, b, b, a] = K[a, b]
+    for a in range(n):
+        g[a, a, a, a] = J[a, a]
+    p = _prob("spinfree", n, 2, 3, synth.space_fci(n, 2, 3), h, g)
+    E = []
+    for wa, wb in p.dets:
+        na = np.array([(int(wa) >> q) & 1 for q in range(n)])
+        nb = np.array([(int(wb) >> q) & 1 for q in range(n)])
+        nt = na + nb
+        e = np.sum(np.diag(h) * nt)
+        gd = np.array([[g[a, a, b, b] for b in range(n)] for a in range(n)])
+        gx = np.array([[g[a, b, b, a] for b in range(n)] for a in range(n)])
+        e += 0.5 * nt @ gd @ nt - 0.5 * (na @ gx @ na + nb @ gx @ nb)
+        E.append(e)
+    occ = lambda w: np.array([(int(w) >> q) & 1 for q in range(n)])
+    for H in _both_dense(p):
+        assert np.allclose(np.diag(H), E, atol=1e-13, rtol=0)
+        I, Jx = np.nonzero(H - np.diag(np.diag(H)))
+        assert len(I) > 0
+        for i, j in zip(I, Jx):
+            ai, bi, aj, bj = (occ(x) for x in (*p.dets[i], *p.dets[j]))
+            assert np.array_equal(ai + bi, aj + bj)
+            pq = np.nonzero(ai != aj)[0]
+            assert len(pq) == 2 and np.array_equal(bi[pq], aj[pq])
+            assert abs(abs(H[i, j]) - K[pq[0], pq[1]]) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# invariances
+# --------------------------------------------------------------------------
+
+def _rotate(h, g, U):
+    h2 = U.conj().T @ h @ U
+    g2 = np.einsum("pqrs,pa,qb,rc,sd->abcd", g, U.conj(), U, U.conj(), U, optimize=True)
+    return h2, g2
+
+
+def test_rotation_invariance_spinfree():
+    """The FCI spectrum is invariant under a real orthogonal orbital rotation
+    of (h, g)."""
+    n = 4
+    h, g = _random_real(n, 21)
+    U, _ = np.linalg.qr(np.random.default_rng(1).normal(size=(n, n)))
+    h2, g2 = _rotate(h, g, U)
+    d = synth.space_fci(n, 2, 2)
+    for fn in (literal.hamiltonian, sc.dense_h):
+        e1 = np.linalg.eigvalsh(fn(_prob("spinfree", n, 2, 2, d, h, g)))
+        e2 = np.linalg.eigvalsh(fn(_prob("spinfree", n, 2, 2, d, h2, g2)))
+        assert np.allclose(e1, e2, atol=1e-12)
+
+
+def test_rotation_invariance_spinor():
+    """Spinor FCI spectrum is invariant under a unitary mixing of all M
+    spinors (A and B mixed)."""
+    nk = 3
+    h, g = _random_spinor(nk, 22)
+    M = 2 * nk
+    rng = np.random.default_rng(2)
+    U, _ = np.linalg.qr(rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M)))
+    h2, g2 = _rotate(h, g, U)
+    d = _spinor_space(nk, 2)
+    for fn in (literal.hamiltonian, sc.dense_h):
+        e1 = np.linalg.eigvalsh(fn(_prob("spinor", nk, 2, -1, d, h, g)))
+        e2 = np.linalg.eigvalsh(fn(_prob("spinor", nk, 2, -1, d, h2, g2)))
+        assert np.allclose(e1, e2, atol=1e-12)
+
+
+def test_phase_gauge_covariance_spinor():
+    """psi'_P = e^{i theta_P} psi_P gives h'_PQ = e^{-i th_P} h_PQ e^{i th_Q}
+    and the same on each index pair of g; then H'_IJ = e^{-i Th_I} H_IJ
+    e^{i Th_J} with Th_D = sum_{P in D} th_P.  Pins where conjugation sits."""
+    nk = 3
+    h, g = _random_spinor(nk, 23)
+    M = 2 * nk
+    th = np.random.default_rng(3).uniform(0, 2 * np.pi, M)
+    e = np.exp(1j * th)
+    h2 = e.conj()[:, None] * h * e[None, :]
+    g2 = g * (e.conj()[:, None, None, None] * e[None, :, None, None]
+              * e.conj()[None, None, :, None] * e[None, None, None, :])
+    d = _spinor_space(nk, 3)
+    Th = np.array([sum(th[P] for P in range(M) if (int(w[P // nk]) >> (P % nk)) & 1) for w in d])
+    D = np.exp(1j * Th)
+    for fn in (literal.hamiltonian, sc.dense_h):
+        H = fn(_prob("spinor", nk, 3, -1, d, h, g))
+        H2 = fn(_prob("spinor", nk, 3, -1, d, h2, g2))
+        assert np.allclose(H2, D.conj()[:, None] * H * D[None, :], atol=1e-13)
+
+
+def test_spinor_embedding_of_spinfree():
+    """A spin-free problem written as a spinor problem (spin-blocked h, g with
+    zero imaginary part; alpha -> A, beta -> B) gives the same sigma."""
+    n = 4
+    h, g = _random_real(n, 24)
+    d = synth.space_fci(n, 2, 1)
+    p = _prob("spinfree", n, 2, 1, d, h, g)
+    hs, gs = literal.spin_orbital_integrals(p)
+    ps = _prob("spinor", n, 3, -1, d, hs.astype(complex), gs.astype(complex))
+    c = np.random.default_rng(5).normal(size=len(d))
+    s1 = sc.sigma(p, c)
+    s2 = sc.sigma(ps, c.astype(complex))
+    assert np.allclose(s2.imag, 0, atol=0)
+    assert np.allclose(s1, s2.real, atol=1e-14, rtol=0)
+
+
+def test_spin_multiplet_structure():
+    """Spin-free FCI: every eigenvalue of the (Na+1, Nb-1) sector appears in
+    the (Na, Nb) sector (S_- maps a multiplet into the lower M_S sector)."""
+    n = 4
+    h, g = _random_real(n, 25)
+    e22 = np.linalg.eigvalsh(sc.dense_h(_prob("spinfree", n, 2, 2, synth.space_fci(n, 2, 2), h, g)))
+    e31 = np.linalg.eigvalsh(sc.dense_h(_prob("spinfree", n, 3, 1, synth.space_fci(n, 3, 1), h, g)))
+    for e in e31:
+        assert np.min(np.abs(e22 - e)) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# tier A vs tier B (brute force), Hermiticity
+# --------------------------------------------------------------------------
+
+def test_tiers_agree_fci_n8_and_hermitian():
+    """Tier A (literal) and tier B (Slater-Condon) give the same dense H on
+    the 4900-determinant FCI space (n=8, 4a4b); H is symmetric."""
+    p = synth.workload(0)
+    HA, HB = _both_dense(p)
+    scale = np.abs(HA).max()
+    assert np.abs(HA - HB).max() <= 1e-14 * scale * 10
+    assert np.array_equal(HB, HB.T)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiers_agree_random_spaces(seed):
+    """Random subsets of FCI spaces (spin-free n=6 3a2b; spinor 4 pairs N=3):
+    tier A == tier B element by element."""
+    rng = np.random.default_rng(100 + seed)
+    h, g = _random_real(6, 30 + seed)
+    d = synth.random_space_spinfree(6, 3, 2, 90, rng)
+    HA, HB = _both_dense(_prob("spinfree", 6, 3, 2, d, h, g))
+    assert np.abs(HA - HB).max() < 1e-14
+    hs, gs = _random_spinor(4, 40 + seed)
+    full = _spinor_space(4, 3)
+    d = full[np.sort(rng.choice(len(full), 40, replace=False))]
+    HA, HB = _both_dense(_prob("spinor", 4, 3, -1, d, hs, gs))
+    assert np.abs(HA - HB).max() < 1e-14
+    assert np.abs(HB - HB.conj().T).max() == 0.0
+
+
+def test_sigma_rows_equal_dense_product():
+    """orc_sigma_rows (row scan) equals the dense product, several roots."""
+    p = synth.workload(0)
+    c = synth.ci_vectors(p.ndet, 3, np.random.default_rng(0))
+    H = sc.dense_h(p)
+    assert np.abs(sc.sigma(p, c) - H @ c).max() < 1e-13
+
+
+def _structural_pairs(dets, rows):
+    out = []
+    for i in rows:
+        pc = np.bitwise_count(dets[:, 0] ^ dets[i, 0]).astype(int) + np.bitwise_count(dets[:, 1] ^ dets[i, 1]).astype(int)
+        for j in np.nonzero((pc == 2) | (pc == 4))[0]:
+            out.append((i, j))
+    return out
+
+
+def test_connect_rows_signs_match_operator_application():
+    """Every connected pair is listed once, and its phase equals the literal
+    <I|a+_P a_Q|J> or <I|a+_P a+_R a_S a_Q|J> of tier A's operators."""
+    n = 5
+    d = synth.space_fci(n, 2, 2)
+    p = _prob("spinfree", n, 2, 2, d, *_random_real(n, 8))
+    rows = np.arange(0, len(d), 7)
+    rec = sc.connect_rows(p, rows)
+    assert sorted(map(tuple, rec[:, :2])) == sorted(_structural_pairs(d, rows))
+    x = literal.packed(p)
+    for I, J, P, Q, R, S, sg in rec:
+        ops = [(P, True), (Q, False)] if R < 0 else [(P, True), (R, True), (S, False), (Q, False)]
+        y, s, ok = literal._apply(x[[J]], ops)
+        assert ok[0] and y[0] == x[I] and s[0] == sg
+
+
+# --------------------------------------------------------------------------
+# Davidson
+# --------------------------------------------------------------------------
+
+def test_davidson_matches_dense_eigh_fci_n8():
+    """Davidson lowest root on the n=8 FCI space (start: unit vector on the
+    lowest diagonal element) equals eigh of dense H to 1e-12 relative; the
+    Ritz vector matches up to a phase."""
+    p = synth.workload(0)
+    H = sc.dense_h(p)
+    w, V = np.linalg.eigh(H)
+    c0 = davidson.diagonal_guess(np.diag(H), 1)
+    th, X, it, conv = davidson.davidson(lambda v: H @ v, np.diag(H), c0, tol=1e-9)
+    assert conv
+    assert abs(th[0] - w[0]) <= 1e-12 * abs(w[0])
+    assert abs(abs(X[:, 0] @ V[:, 0]) - 1) < 1e-12
+
+
+def test_davidson_several_roots_with_collapse():
+    """Three roots with the subspace collapse exercised (tight tolerance)."""
+    n = 6
+    p = _prob("spinfree", n, 3, 3, synth.space_fci(n, 3, 3), *_random_real(n, 9))
+    H = sc.dense_h(p)
+    w = np.linalg.eigvalsh(H)
+    c0 = davidson.diagonal_guess(sc.diag(p), 3)
+    th, X, it, conv = davidson.davidson(lambda v: sc.sigma(p, v), sc.diag(p), c0, tol=1e-9)
+    assert conv
+    assert np.allclose(th, w[:3], atol=1e-11, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# density matrices
+# --------------------------------------------------------------------------
+
+def test_rdm_tier_b_equals_literal():
+    """Tier-B RDMs (structural tuples + literal phases) equal tier A's RDMs
+    obtained by applying every operator string, spin-summed; transition
+    case with different bra and ket."""
+    n = 4
+    d = synth.space_fci(n, 2, 1)
+    p = _prob("spinfree", n, 2, 1, d, *_random_real(n, 10))
+    rng = np.random.default_rng(3)
+    bra, ket = rng.normal(size=len(d)), rng.normal(size=len(d))
+    gA, GA = literal.spin_sum(p, *literal.rdm(p, bra, ket))
+    gB, GB = sc.rdm(p, bra, ket)
+    assert np.abs(gA - gB).max() < 1e-14 and np.abs(GA - GB).max() < 1e-14
+    nk = 3
+    ds = _spinor_space(nk, 2)
+    ps = _prob("spinor", nk, 2, -1, ds, *_random_spinor(nk, 11))
+    bra = rng.normal(size=len(ds)) + 1j * rng.normal(size=len(ds))
+    ket = rng.normal(size=len(ds)) + 1j * rng.normal(size=len(ds))
+    gA, GA = literal.rdm(ps, bra, ket)
+    gB, GB = sc.rdm(ps, bra, ket)
+    assert np.abs(gA - gB).max() < 1e-14 and np.abs(GA - GB).max() < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["spinfree", "spinor"])
+def test_rdm_identities_and_energy(kind):
+    """tr gamma = N <b|k>, sum_PR Gamma_PPRR = N(N-1)<b|k>, sum_R Gamma_PQRR
+    = (N-1) gamma_PQ, <b|H|k> = ecore<b|k> + sum h gamma + 1/2 sum g Gamma
+    with H from tier A; gamma Hermitian with eigenvalues in [0, 2] (spin-free)
+    or [0, 1] (spinor) for bra = ket normalised."""
+    rng = np.random.default_rng(12)
+    if kind == "spinfree":
+        n, na, nb = 5, 2, 2
+        d = synth.space_fci(n, na, nb)
+        p = _prob(kind, n, na, nb, d, *_random_real(n, 13), ecore=0.37)
+        N, occmax = na + nb, 2.0
+        c = rng.normal(size=len(d))
+    else:
+        nk, N = 3, 3
+        d = _spinor_space(nk, N)
+        p = _prob(kind, nk, N, -1, d, *_random_spinor(nk, 14), ecore=0.37)
+        occmax = 1.0
+        c = rng.normal(size=len(d)) + 1j * rng.normal(size=len(d))
+    c = c / np.linalg.norm(c)
+    k2 = rng.normal(size=len(d)) + (1j * rng.normal(size=len(d)) if kind == "spinor" else 0)
+    H = literal.hamiltonian(p)
+    for bra, ket in ((c, c), (c, k2)):
+        g1, g2 = sc.rdm(p, bra, ket)
+        ov = np.vdot(bra, ket)
+        assert abs(np.trace(g1) - N * ov) < 1e-12
+        assert abs(np.einsum("pprr->", g2) - N * (N - 1) * ov) < 1e-11
+        assert np.abs(np.einsum("pqrr->pq", g2) - (N - 1) * g1).max() < 1e-12
+        E = p.ecore * ov + np.sum(p.h * g1) + 0.5 * np.sum(p.g * g2)
+        assert abs(E - np.vdot(bra, H @ ket)) < 1e-12
+    g1, _ = sc.rdm(p, c, c)
+    assert np.abs(g1 - g1.conj().T).max() < 1e-14
+    ev = np.linalg.eigvalsh(g1)
+    assert ev.min() > -1e-12 and ev.max() < occmax + 1e-12
+
+
+def _sym_direction_real(n, rng):
+    """Random h and g directions carrying the 8-fold symmetry."""
+    dh = rng.normal(size=(n, n)); dh = dh + dh.T
+    dg = rng.normal(size=(n,) * 4)
+    perms = ["pqrs", "qprs", "pqsr", "qpsr", "rspq", "srpq", "rsqp", "srqp"]
+    dg = sum(np.einsum(f"pqrs->{q}", dg) for q in perms)
+    return dh, dg
+
+
+def test_gradient_central_differences():
+    """E(h, g) = c^T H c at fixed c: central differences along symmetric
+    directions equal sum gamma dh + 1/2 sum Gamma dg (E is linear in h, g,
+    so the difference is exact up to rounding)."""
+    n = 5
+    d = synth.space_fci(n, 2, 2)
+    h, g = _random_real(n, 15)
+    rng = np.random.default_rng(16)
+    c = rng.normal(size=len(d))
+    g1, g2 = sc.rdm(_prob("spinfree", n, 2, 2, d, h, g), c, c)
+    dh, dg = _sym_direction_real(n, rng)
+    eps = 1e-6
+
+    def E(hh, gg):
+        return c @ sc.sigma(_prob("spinfree", n, 2, 2, d, hh, gg), c)
+
+    fd = (E(h + eps * dh, g + eps * dg) - E(h - eps * dh, g - eps * dg)) / (2 * eps)
+    an = np.sum(g1 * dh) + 0.5 * np.sum(g2 * dg)
+    assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
