@@ -1,0 +1,171 @@
+/*
+ * mw.h - C ABI of libmw: the Hamiltonian-vector product sigma = H c over a
+ * (selected) space of Slater determinants on one MI355X (gfx950) GPU.
+ *
+ * H is the generic second-quantised Hamiltonian of MetaWave (section 2.1,
+ * Eq. (1)):  H = sum_PQ h_PQ a+_P a_Q + 1/2 sum_PQRS (PQ|RS) a+_P a+_R a_S a_Q,
+ * Mulliken notation, with the operator symmetries of Eq. (2).  Matrix
+ * elements between determinants are never stored: every call recomputes them
+ * from occupation bitstrings and integrals (section 2.4, last paragraph on
+ * diagonalisation through sigma = H X).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Determinant: two 64-bit words {w0, w1}.  Spin-free (MW_SPIN_FREE, tag
+ * "nonrelativistic"): w0 = alpha string, w1 = beta string, spatial orbital p
+ * at bit p.  Spinor (MW_SPINOR, Kramers pairs of section 2.1): w0 = unbarred
+ * (A) spinors, w1 = barred (B) spinors, pair k at bit k.  The global position
+ * of word w, bit b is w*norb + b, and |D> = prod_{P in D, ascending} a+_P |vac>
+ * (all of w0 before w1).  The space is strictly ascending as unsigned 128-bit
+ * keys with w0 the more significant word.
+ *
+ * Scalars: spin-free problems are real FP64; spinor problems are complex128
+ * stored as interleaved (re, im) doubles.  CI vectors c and sigma are laid
+ * out [ndet][nroots] (roots contiguous), in that scalar type.
+ *
+ * Memory ownership: problem data (dets, h, g) are HOST pointers read only
+ * during mw_plan_create.  Every other buffer argument is a DEVICE pointer
+ * owned by the caller unless marked host.  libmw never allocates or frees
+ * device memory: a plan lives in a caller-provided device workspace.
+ *
+ * Streams: device work is enqueued on the given hipStream_t (0 = default
+ * stream) and is asynchronous unless stated otherwise.
+ *
+ * Errors: every call returns an mw_status; on failure nothing has been
+ * enqueued unless stated, outputs are unspecified and mw_last_error() gives
+ * a message (thread-local).  No C++ exception crosses the ABI.
+ */
+#ifndef MW_H
+#define MW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *mw_stream_t; /* a hipStream_t */
+
+typedef enum {
+    MW_OK = 0,
+    MW_EINVAL = -1,       /* bad argument (null pointer, size, nroots...) */
+    MW_ENOTSORTED = -2,   /* determinants not strictly ascending          */
+    MW_EELEC = -3,        /* wrong electron count or bits beyond norb      */
+    MW_ESYM = -4,         /* integrals violate the required symmetry       */
+    MW_EWORKSPACE = -5,   /* workspace missing, too small or misaligned    */
+    MW_EHIP = -6,         /* a HIP runtime call failed                     */
+    MW_ENOCONV = -7,      /* Davidson did not converge (best result kept)  */
+    MW_EUNSUPPORTED = -8  /* outside the supported sizes                   */
+} mw_status;
+
+typedef enum { MW_SPIN_FREE = 0, MW_SPINOR = 1 } mw_kind;
+
+typedef struct {
+    int32_t kind;        /* mw_kind                                               */
+    int32_t norb;        /* spatial orbitals (spin-free) or Kramers pairs (spinor), 1..64 */
+    int32_t nalpha;      /* spin-free: N_alpha; spinor: total electron count N     */
+    int32_t nbeta;       /* spin-free: N_beta;  spinor: must be -1                 */
+    int64_t ndet;        /* number of determinants, 1 .. 2^31-1                    */
+    const uint64_t *dets;/* HOST [ndet][2], see conventions                        */
+    const double *h;     /* HOST one-body integrals h_PQ.  Spin-free: real [n][n].
+                            Spinor: complex [M][M], M = 2n (A_k at k, B_k at n+k)  */
+    const double *g;     /* HOST two-body integrals (PQ|RS) at [((P*m+Q)*m+R)*m+S],
+                            m = n (spin-free, real) or M (spinor, complex)         */
+    double ecore;        /* constant added to every diagonal element               */
+} mw_problem;
+
+typedef struct mw_plan_s *mw_plan;
+
+/* Build a plan for a problem (section 2.3: classify determinant pairs by the
+ * part they share and group them, so that pairs of one group reuse the same
+ * integrals).  Host-side only: validates the problem, groups determinants by
+ * the (N-1)- and (N-2)-electron strings they contain, repacks the integrals
+ * and allocates HOST memory for the result.  Checks: norb in 1..64, electron
+ * counts per determinant (MW_EELEC), strictly ascending dets (MW_ENOTSORTED),
+ * h Hermitian, (PQ|RS) = (RS|PQ) = conj((QP|SR)) and, for spin-free
+ * problems, the real 8-fold symmetry, all to 1e-12 relative (MW_ESYM).
+ * max_roots (>= 1) bounds nroots of later calls.  *out receives the plan. */
+mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out);
+
+/* Device workspace size (bytes, host out) the plan needs, including the
+ * per-call scratch for max_roots roots. */
+mw_status mw_plan_workspace_bytes(mw_plan plan, size_t *bytes);
+
+/* Bind the plan to a device workspace of at least mw_plan_workspace_bytes
+ * bytes, 256-byte aligned, and upload its tables; computes the diagonal H_II
+ * on the device.  Synchronises the stream before returning.  The workspace
+ * must stay allocated and untouched until mw_plan_destroy or a new upload.
+ * A plan is bound to one workspace at a time and must not be used from two
+ * streams concurrently. */
+mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_t stream);
+
+/* Free the plan's host memory (the workspace stays the caller's). */
+mw_status mw_plan_destroy(mw_plan plan);
+
+/* Plan statistics (host): what = 0 ndet, 1 number of groups (buckets),
+ * 2 memberships, 3 structurally connected ordered pairs I != J, 4 pairs of
+ * single excitations, 5 pairs of double excitations, 6 determinant-pair
+ * evaluations per sigma (including the discarded ones), 7 workspace bytes,
+ * 8 scalar size in bytes (8 or 16), 9 norb, 10 kind.  Returns -1 for an
+ * unknown plan or index. */
+int64_t mw_plan_info(mw_plan plan, int32_t what);
+
+/* sigma_I = sum_J H_IJ c_J for nroots (1..max_roots) vectors: the product of
+ * section 2.4 over the nonzero elements of H, recomputed on every call.
+ * c, sigma: device [ndet][nroots] scalars; they must not overlap.
+ * Enqueues the product on stream; bitwise reproducible between calls. */
+mw_status mw_sigma(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream);
+
+/* The same product for nprob independent plans in one launch sequence
+ * (one persistent launch over all problems' work, then one gather launch).
+ * plans, nroots, c, sigma are HOST arrays of length nprob (c[i], sigma[i]
+ * device pointers).  The launch sequence is captured once into a HIP graph
+ * keyed by the argument tuple and replayed on later calls with the same
+ * tuple.  Results equal nprob separate mw_sigma calls bit for bit. */
+mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
+                           const void *const *c, void *const *sigma, mw_stream_t stream);
+
+/* Diagonal H_II (device [ndet] scalars, imaginary part zero for spinor). */
+mw_status mw_diag(mw_plan plan, void *out, mw_stream_t stream);
+
+/* Transition density matrices, the adjoint of sigma with respect to the
+ * integrals (density matrices are listed among the paper's functionality,
+ * section 3.4):  gamma_PQ = sum_k w_k sum_IJ conj(bra_Ik) ket_Jk <I|a+_P a_Q|J>,
+ * Gamma_PQRS = sum_k w_k sum_IJ conj(bra_Ik) ket_Jk <I|a+_P a+_R a_S a_Q|J>.
+ * Spin-free results are spin-summed over spatial orbitals: gamma [n][n],
+ * Gamma [n][n][n][n] real; spinor: [M][M] and [M]^4 complex.  bra, ket
+ * device [ndet][nroots]; weights HOST [nroots] or NULL (all 1); gamma, Gamma
+ * device outputs, overwritten.  For E = c^H H c, dE/dh = gamma and dE/dg =
+ * Gamma / 2.  Connectivity is recomputed, never stored.  Uses device atomics:
+ * results are reproducible to rounding, not bitwise. */
+mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *bra, const void *ket,
+                          const double *weights, void *gamma, void *Gamma, mw_stream_t stream);
+
+/* Lowest nroots eigenpairs by block Davidson-Liu over mw_sigma (section 2.4
+ * uses sigma = H X products for the diagonalisation).  c0: device
+ * [ndet][nroots] start vectors (orthonormalised internally).  work: device
+ * scratch of mw_davidson_work_bytes bytes.  c_out: device [ndet][nroots]
+ * Ritz vectors; evals: HOST [nroots]; iters: HOST.  Convergence when every
+ * residual 2-norm <= tol; subspace collapse above max(8 nroots, 24) vectors.
+ * Host-driven, synchronises once per iteration.  Returns MW_ENOCONV with
+ * the best vectors and values when max_iter is reached. */
+mw_status mw_davidson_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
+mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out, double *evals,
+                      double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
+                      mw_stream_t stream);
+
+/* Debug: connected pairs of all rows with their phases, as int64 records
+ * [I, J, P, Q, R, S, sign] (R = S = -1 for singles; P, R particles in I; Q, S
+ * holes in J; ascending within each pair).  Call with out = NULL to get the
+ * count in *count (host); then with a device buffer of 7*count int64.
+ * Synchronises the stream.  Order of records is unspecified. */
+mw_status mw_connect_dump(mw_plan plan, int64_t *count, int64_t *out, mw_stream_t stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char *mw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MW_H */

@@ -1,0 +1,79 @@
+// Internal declarations shared by the host plan builder and the HIP kernels
+// of libmw.  Not part of the ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mw.h"
+
+namespace mw {
+
+// Group (bucket) kinds.  A single group collects the determinants that
+// contain one (N-1)-electron string K; a double group those that contain one
+// (N-2)-electron string.  Two members of a double group whose added pairs are
+// disjoint differ by exactly that double excitation, and K is their common
+// part; two members of a single group differ by a single excitation.
+enum GroupType : uint8_t {
+    G_SINGLE_A = 0,   // spin-free, added orbital alpha
+    G_SINGLE_B = 1,   // spin-free, added orbital beta
+    G_AA = 2,         // spin-free double, both added orbitals alpha
+    G_AB = 3,         // spin-free double, one alpha one beta
+    G_BB = 4,         // spin-free double, both beta
+    G_SINGLE_S = 5,   // spinor single
+    G_DOUBLE_S = 6,   // spinor double
+};
+
+// Device-side view of a plan (all pointers inside the workspace).
+struct DevPlan {
+    int32_t kind;          // mw_kind
+    int32_t n;             // norb
+    int32_t M;             // 2 n global positions
+    int32_t npair;         // pairs of same-spin orbitals (spin-free) or of spinors
+    int64_t ndet;
+    int64_t nmem;          // memberships
+    int64_t npacket;
+    int32_t max_roots;
+    double ecore;
+    // groups
+    const uint32_t *grp_off;   // [ngroup+1] first member of each group
+    const uint64_t *grp_key;   // [ngroup][2] the shared string K
+    const uint8_t *grp_type;   // [ngroup]
+    // members (group-major)
+    const uint2 *mem;          // [nmem] {det, P | R<<8 | (phi<0)<<16}
+    const uint32_t *mem_grp;   // [nmem] owning group
+    const uint32_t *mem_slot;  // [nmem] slot in the determinant-major partial array
+    const uint32_t *pk_off;    // [npacket+1] packets of <= 64 consecutive members
+    // determinants
+    const uint32_t *rowptr;    // [ndet+1] slots of each determinant
+    const uint64_t *dets;      // [ndet][2]
+    void *diag;                // [ndet] scalar (written at upload)
+    // integrals (scalar = double or double2)
+    const void *h;             // [M'][M'] (spin-free n x n; spinor M x M)
+    const void *w_same;        // singles table [R][P][Q]: (PQ|RR) - (PR|RQ)  (spin-free n^3, spinor M^3)
+    const void *w_opp;         // spin-free only: [r][p][q] (pq|rr)
+    const void *g_ab;          // spin-free only: [q][s][p][r] = (pq|rs)
+    const void *a_pair;        // antisymmetrised pairs [x][y] = (X0 Y0|X1 Y1) - (X0 Y1|X1 Y0)
+    void *partial;             // [nmem][max_roots] scalar scratch
+};
+
+struct HostPlan;
+
+// host side helpers (plan.cpp)
+void set_error(const std::string &msg);
+mw_status fail(mw_status st, const std::string &msg);
+
+// kernel launchers (kernels.hip)
+mw_status launch_diag(const DevPlan &p, hipStream_t s);
+mw_status launch_sigma(const DevPlan &p, int nroots, const void *c, void *sigma, hipStream_t s);
+mw_status launch_sigma_batched(int nprob, const DevPlan *const *plans, const int *nroots,
+                               const void *const *c, void *const *sigma, hipStream_t s);
+mw_status launch_rdm(const DevPlan &p, int nroots, const void *bra, const void *ket,
+                     const double *weights, void *gamma, void *Gamma, hipStream_t s);
+mw_status launch_connect(const DevPlan &p, int64_t *count, int64_t *out, hipStream_t s);
+
+}  // namespace mw

@@ -1,0 +1,682 @@
+// Host side of libmw: problem validation, the grouping of determinants by
+// shared (N-1)/(N-2)-electron strings, integral repacking, workspace layout
+// and the C ABI entry points that do not launch kernels themselves.
+//
+// Grouping (MetaWave section 2.3, reduced pairs and the "bunch" scheme).
+// Two determinants I, J with |I ^ J| = 4 (a double excitation) share exactly
+// one (N-2)-electron string K = I & J; with |I ^ J| = 2 (a single) they share
+// exactly one (N-1)-electron string.  Every determinant D is entered into the
+// group of each string D minus one occupied position (N groups) and D minus
+// two occupied positions (N(N-1)/2 groups).  Inside a double group each member
+// is K plus an added pair (X < Y); members with disjoint pairs are exactly
+// the doubly excited pairs with common part K, each pair found in one group
+// only.  Inside a single group members are K plus one position, and every two
+// members form a single excitation.  Groups with one member are dropped.  The
+// phase of every element factorises over the group: with
+// pi_K(X) = (-1)^{#K below X},  <I|a+_P a+_R a_S a_Q|J> = phi_I phi_J where
+// phi = pi_K(X) pi_K(Y), and <I|a+_P a_Q|J> = pi_K(P) pi_K(Q).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <thread>
+
+#include "mw_internal.h"
+
+namespace mw {
+
+static thread_local std::string g_last_error = "no error";
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+mw_status fail(mw_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+static unsigned n_threads()
+{
+    unsigned t = std::thread::hardware_concurrency();
+    if (t == 0) t = 4;
+    if (t > 64) t = 64;
+    return t;
+}
+
+// Run f(begin, end, thread) over [0, n) split into contiguous chunks.
+static void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, unsigned)> &f)
+{
+    unsigned T = n_threads();
+    if (n < 4096 || T == 1) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + T - 1) / T;
+    for (unsigned t = 0; t < T; t++) {
+        int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back(f, b, e, t);
+    }
+    for (auto &x : th) x.join();
+}
+
+// dynamic-scheduled variant for uneven work items
+static void parallel_items(int64_t n, const std::function<void(int64_t)> &f)
+{
+    unsigned T = n_threads();
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; t++)
+        th.emplace_back([&]() {
+            for (;;) {
+                int64_t i = next.fetch_add(1);
+                if (i >= n) break;
+                f(i);
+            }
+        });
+    for (auto &x : th) x.join();
+}
+
+static inline uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 30; x *= 0xbf58476d1ce4e5b9ULL;
+    x ^= x >> 27; x *= 0x94d049bb133111ebULL;
+    x ^= x >> 31;
+    return x;
+}
+
+struct KeyEntry {
+    uint64_t k0, k1;   // the shared string K (two words)
+    uint32_t det;
+    uint16_t pos;      // X | Y << 8 (Y = 255 for single groups)
+    uint16_t pad;
+};
+
+static inline bool key_less(const KeyEntry &a, const KeyEntry &b)
+{
+    if (a.k0 != b.k0) return a.k0 < b.k0;
+    if (a.k1 != b.k1) return a.k1 < b.k1;
+    return a.det < b.det;
+}
+
+struct HostPlan {
+    int32_t kind = 0, n = 0, M = 0, npair = 0, nalpha = 0, nbeta = 0, max_roots = 1;
+    int64_t ndet = 0;
+    double ecore = 0.0;
+    bool cplx = false;
+    std::vector<uint64_t> dets;
+    std::vector<uint32_t> grp_off;
+    std::vector<uint64_t> grp_key;
+    std::vector<uint8_t> grp_type;
+    std::vector<uint2> mem;
+    std::vector<uint32_t> mem_grp, mem_slot, pk_off, rowptr;
+    std::vector<double> h, w_same, w_opp, g_ab, a_pair;
+    int64_t n_single_pairs = 0, n_double_pairs = 0, n_evals = 0;
+    // device binding
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    DevPlan dev{};
+    size_t layout(DevPlan *d, char *base) const;
+    size_t scalar_bytes() const { return cplx ? 16 : 8; }
+};
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+
+static mw_status validate(const mw_problem *p, int32_t max_roots)
+{
+    if (!p) return fail(MW_EINVAL, "problem is NULL");
+    if (p->kind != MW_SPIN_FREE && p->kind != MW_SPINOR) return fail(MW_EINVAL, "unknown kind");
+    if (p->norb < 1 || p->norb > 64) return fail(MW_EUNSUPPORTED, "norb must be in 1..64");
+    if (p->ndet < 1 || p->ndet > 0x7fffffffLL) return fail(MW_EUNSUPPORTED, "ndet must be in 1..2^31-1");
+    if (!p->dets || !p->h || !p->g) return fail(MW_EINVAL, "dets, h and g must be host pointers");
+    if (max_roots < 1 || max_roots > 64) return fail(MW_EINVAL, "max_roots must be in 1..64");
+    const int n = p->norb;
+    if (p->kind == MW_SPIN_FREE) {
+        if (p->nalpha < 0 || p->nalpha > n || p->nbeta < 0 || p->nbeta > n)
+            return fail(MW_EELEC, "electron counts out of range");
+    } else {
+        if (p->nbeta != -1) return fail(MW_EINVAL, "spinor problems take nbeta = -1");
+        if (p->nalpha < 0 || p->nalpha > 2 * n) return fail(MW_EELEC, "electron count out of range");
+    }
+    const uint64_t mask = n == 64 ? ~0ULL : ((1ULL << n) - 1);
+    const uint64_t *d = p->dets;
+    for (int64_t i = 0; i < p->ndet; i++) {
+        uint64_t a = d[2 * i], b = d[2 * i + 1];
+        if ((a & ~mask) || (b & ~mask))
+            return fail(MW_EELEC, "determinant " + std::to_string(i) + " has bits beyond norb");
+        int na = __builtin_popcountll(a), nb = __builtin_popcountll(b);
+        bool ok = p->kind == MW_SPIN_FREE ? (na == p->nalpha && nb == p->nbeta) : (na + nb == p->nalpha);
+        if (!ok) return fail(MW_EELEC, "determinant " + std::to_string(i) + " has the wrong electron count");
+        if (i > 0) {
+            uint64_t pa = d[2 * i - 2], pb = d[2 * i - 1];
+            if (!(pa < a || (pa == a && pb < b)))
+                return fail(MW_ENOTSORTED, "determinants not strictly ascending at index " + std::to_string(i));
+        }
+    }
+    // integral symmetry
+    if (p->kind == MW_SPIN_FREE) {
+        const double *h = p->h, *g = p->g;
+        double hmax = 0, gmax = 0;
+        for (int i = 0; i < n * n; i++) hmax = std::max(hmax, std::fabs(h[i]));
+        const size_t n4 = (size_t)n * n * n * n;
+        for (size_t i = 0; i < n4; i++) gmax = std::max(gmax, std::fabs(g[i]));
+        double th = 1e-12 * std::max(hmax, 1e-300), tg = 1e-12 * std::max(gmax, 1e-300);
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++)
+                if (std::fabs(h[a * n + b] - h[b * n + a]) > th)
+                    return fail(MW_ESYM, "h is not symmetric");
+        std::atomic<bool> bad{false};
+        parallel_for(n, [&](int64_t b0, int64_t b1, unsigned) {
+            for (int64_t P = b0; P < b1 && !bad; P++)
+                for (int Q = 0; Q < n; Q++)
+                    for (int R = 0; R < n; R++)
+                        for (int S = 0; S < n; S++) {
+                            auto G = [&](int a, int b, int c, int e) { return g[(((size_t)a * n + b) * n + c) * n + e]; };
+                            double v = G(P, Q, R, S);
+                            if (std::fabs(v - G(Q, P, R, S)) > tg || std::fabs(v - G(P, Q, S, R)) > tg ||
+                                std::fabs(v - G(R, S, P, Q)) > tg)
+                                bad = true;
+                        }
+        });
+        if (bad) return fail(MW_ESYM, "g lacks the real 8-fold permutation symmetry");
+    } else {
+        const int Mm = 2 * n;
+        const std::complex<double> *h = reinterpret_cast<const std::complex<double> *>(p->h);
+        const std::complex<double> *g = reinterpret_cast<const std::complex<double> *>(p->g);
+        double hmax = 0, gmax = 0;
+        for (int i = 0; i < Mm * Mm; i++) hmax = std::max(hmax, std::abs(h[i]));
+        const size_t m4 = (size_t)Mm * Mm * Mm * Mm;
+        for (size_t i = 0; i < m4; i++) gmax = std::max(gmax, std::abs(g[i]));
+        double th = 1e-12 * std::max(hmax, 1e-300), tg = 1e-12 * std::max(gmax, 1e-300);
+        for (int a = 0; a < Mm; a++)
+            for (int b = 0; b < Mm; b++)
+                if (std::abs(h[a * Mm + b] - std::conj(h[b * Mm + a])) > th)
+                    return fail(MW_ESYM, "h is not Hermitian");
+        std::atomic<bool> bad{false};
+        parallel_for(Mm, [&](int64_t b0, int64_t b1, unsigned) {
+            for (int64_t P = b0; P < b1 && !bad; P++)
+                for (int Q = 0; Q < Mm; Q++)
+                    for (int R = 0; R < Mm; R++)
+                        for (int S = 0; S < Mm; S++) {
+                            auto G = [&](int a, int b, int c, int e) { return g[(((size_t)a * Mm + b) * Mm + c) * Mm + e]; };
+                            std::complex<double> v = G(P, Q, R, S);
+                            if (std::abs(v - G(R, S, P, Q)) > tg || std::abs(v - std::conj(G(Q, P, S, R))) > tg)
+                                bad = true;
+                        }
+        });
+        if (bad) return fail(MW_ESYM, "g lacks (PQ|RS) = (RS|PQ) = conj((QP|SR))");
+    }
+    return MW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// grouping
+// ---------------------------------------------------------------------------
+
+static inline int occupied_positions(uint64_t w0, uint64_t w1, int n, int *occ)
+{
+    int k = 0;
+    for (uint64_t x = w0; x; x &= x - 1) occ[k++] = __builtin_ctzll(x);
+    for (uint64_t x = w1; x; x &= x - 1) occ[k++] = n + __builtin_ctzll(x);
+    return k;
+}
+
+static inline void remove_pos(uint64_t &w0, uint64_t &w1, int n, int X)
+{
+    if (X < n) w0 &= ~(1ULL << X);
+    else w1 &= ~(1ULL << (X - n));
+}
+
+// (-1)^{# of K's positions below global position X}
+static inline int pi_sign(uint64_t k0, uint64_t k1, int n, int X)
+{
+    int c;
+    if (X < n) c = __builtin_popcountll(k0 & ((1ULL << X) - 1));
+    else {
+        int b = X - n;
+        c = __builtin_popcountll(k0) + __builtin_popcountll(k1 & (b == 64 ? ~0ULL : ((1ULL << b) - 1)));
+    }
+    return (c & 1) ? -1 : 1;
+}
+
+static mw_status build_groups(HostPlan &P)
+{
+    const int n = P.n;
+    const int64_t N = P.ndet;
+    const int nel = P.kind == MW_SPIN_FREE ? P.nalpha + P.nbeta : P.nalpha;
+    const int64_t per_det = nel + (int64_t)nel * (nel - 1) / 2;
+    const int64_t total = N * per_det;
+    if (nel == 0 || total == 0) {
+        P.grp_off.assign(1, 0);
+        P.pk_off.assign(1, 0);
+        P.rowptr.assign(N + 1, 0);
+        return MW_OK;
+    }
+    const int PB = 10;                      // 1024 hash partitions
+    const int NPART = 1 << PB;
+    const unsigned T = n_threads();
+    const int64_t chunk = (N + T - 1) / T;
+    std::vector<int64_t> counts((size_t)T * NPART, 0);
+
+    auto for_each_key = [&](int64_t i, auto &&emit) {
+        int occ[128];
+        uint64_t w0 = P.dets[2 * i], w1 = P.dets[2 * i + 1];
+        int k = occupied_positions(w0, w1, n, occ);
+        for (int a = 0; a < k; a++) {
+            uint64_t k0 = w0, k1 = w1;
+            remove_pos(k0, k1, n, occ[a]);
+            emit(k0, k1, (uint16_t)(occ[a] | (255 << 8)));
+            for (int b = a + 1; b < k; b++) {
+                uint64_t m0 = k0, m1 = k1;
+                remove_pos(m0, m1, n, occ[b]);
+                emit(m0, m1, (uint16_t)(occ[a] | (occ[b] << 8)));
+            }
+        }
+    };
+    auto part_of = [&](uint64_t k0, uint64_t k1) { return (int)(mix64(k0 ^ mix64(k1 + 0x9E3779B97F4A7C15ULL)) >> (64 - PB)); };
+
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; t++)
+        th.emplace_back([&, t]() {
+            int64_t b = t * chunk, e = std::min<int64_t>(N, b + chunk);
+            int64_t *cnt = &counts[(size_t)t * NPART];
+            for (int64_t i = b; i < e; i++)
+                for_each_key(i, [&](uint64_t k0, uint64_t k1, uint16_t) { cnt[part_of(k0, k1)]++; });
+        });
+    for (auto &x : th) x.join();
+    th.clear();
+    // offsets: partition-major, thread-minor
+    std::vector<int64_t> off((size_t)T * NPART);
+    std::vector<int64_t> part_start(NPART + 1, 0);
+    int64_t acc = 0;
+    for (int p = 0; p < NPART; p++) {
+        part_start[p] = acc;
+        for (unsigned t = 0; t < T; t++) {
+            off[(size_t)t * NPART + p] = acc;
+            acc += counts[(size_t)t * NPART + p];
+        }
+    }
+    part_start[NPART] = acc;
+    std::vector<KeyEntry> ent;
+    try {
+        ent.resize((size_t)total);
+    } catch (...) {
+        return fail(MW_EUNSUPPORTED, "host memory exhausted while grouping determinants");
+    }
+    for (unsigned t = 0; t < T; t++)
+        th.emplace_back([&, t]() {
+            int64_t b = t * chunk, e = std::min<int64_t>(N, b + chunk);
+            int64_t *o = &off[(size_t)t * NPART];
+            for (int64_t i = b; i < e; i++)
+                for_each_key(i, [&](uint64_t k0, uint64_t k1, uint16_t pos) {
+                    int p = part_of(k0, k1);
+                    ent[o[p]++] = KeyEntry{k0, k1, (uint32_t)i, pos, 0};
+                });
+        });
+    for (auto &x : th) x.join();
+    th.clear();
+
+    // sort each partition; collect runs of length >= 2
+    struct Run { int64_t start; uint32_t len; };
+    std::vector<std::vector<Run>> runs(NPART);
+    parallel_items(NPART, [&](int64_t p) {
+        auto b = ent.begin() + part_start[p], e = ent.begin() + part_start[p + 1];
+        std::sort(b, e, key_less);
+        int64_t s = part_start[p], E = part_start[p + 1];
+        while (s < E) {
+            int64_t t = s + 1;
+            while (t < E && ent[t].k0 == ent[s].k0 && ent[t].k1 == ent[s].k1) t++;
+            if (t - s >= 2) runs[p].push_back(Run{s, (uint32_t)(t - s)});
+            s = t;
+        }
+    });
+    std::vector<Run> all;
+    for (auto &r : runs) all.insert(all.end(), r.begin(), r.end());
+    runs.clear();
+    runs.shrink_to_fit();
+    // largest groups first (longest-processing-time order); ties keep the
+    // deterministic partition/key order
+    std::stable_sort(all.begin(), all.end(), [](const Run &a, const Run &b) { return a.len > b.len; });
+
+    const int64_t ngroup = (int64_t)all.size();
+    P.grp_off.resize(ngroup + 1);
+    int64_t m = 0;
+    for (int64_t gi = 0; gi < ngroup; gi++) {
+        P.grp_off[gi] = (uint32_t)m;
+        m += all[gi].len;
+        if (m > 0xffffffffLL) return fail(MW_EUNSUPPORTED, "more than 2^32 group memberships");
+    }
+    P.grp_off[ngroup] = (uint32_t)m;
+    const int64_t nmem = m;
+    P.grp_key.resize(2 * ngroup);
+    P.grp_type.resize(ngroup);
+    P.mem.resize(nmem);
+    P.mem_grp.resize(nmem);
+    std::vector<int64_t> single_pairs(ngroup), double_pairs(ngroup);
+    parallel_items((ngroup + 1023) / 1024, [&](int64_t blk) {
+        int64_t g0 = blk * 1024, g1 = std::min<int64_t>(ngroup, g0 + 1024);
+        std::vector<int> freq(128);
+        for (int64_t gi = g0; gi < g1; gi++) {
+            const Run &r = all[gi];
+            const KeyEntry &e0 = ent[r.start];
+            uint64_t k0 = e0.k0, k1 = e0.k1;
+            P.grp_key[2 * gi] = k0;
+            P.grp_key[2 * gi + 1] = k1;
+            int X0 = e0.pos & 255, Y0 = e0.pos >> 8;
+            bool single = Y0 == 255;
+            uint8_t type;
+            if (P.kind == MW_SPIN_FREE) {
+                if (single) type = X0 < n ? G_SINGLE_A : G_SINGLE_B;
+                else type = (X0 < n && Y0 < n) ? G_AA : (X0 >= n && Y0 >= n) ? G_BB : G_AB;
+            } else {
+                type = single ? G_SINGLE_S : G_DOUBLE_S;
+            }
+            P.grp_type[gi] = type;
+            std::fill(freq.begin(), freq.end(), 0);
+            for (uint32_t t = 0; t < r.len; t++) {
+                const KeyEntry &e = ent[r.start + t];
+                int X = e.pos & 255, Y = e.pos >> 8;
+                int phi = pi_sign(k0, k1, n, X) * (single ? 1 : pi_sign(k0, k1, n, Y));
+                int64_t mi = P.grp_off[gi] + t;
+                P.mem[mi] = uint2{e.det, (uint32_t)(X | (Y << 8) | (phi < 0 ? (1u << 16) : 0u))};
+                P.mem_grp[mi] = (uint32_t)gi;
+                freq[X]++;
+                if (!single) freq[Y]++;
+            }
+            int64_t k = r.len;
+            if (single) {
+                single_pairs[gi] = k * (k - 1);
+            } else {
+                int64_t dp = 0;
+                for (uint32_t t = 0; t < r.len; t++) {
+                    const KeyEntry &e = ent[r.start + t];
+                    int X = e.pos & 255, Y = e.pos >> 8;
+                    dp += k - (freq[X] + freq[Y] - 1);
+                }
+                double_pairs[gi] = dp;
+            }
+        }
+    });
+    ent.clear();
+    ent.shrink_to_fit();
+    P.n_single_pairs = P.n_double_pairs = P.n_evals = 0;
+    for (int64_t gi = 0; gi < ngroup; gi++) {
+        P.n_single_pairs += single_pairs[gi];
+        P.n_double_pairs += double_pairs[gi];
+        P.n_evals += (int64_t)all[gi].len * all[gi].len;
+    }
+    // packets: <= 64 consecutive members; large groups are cut into chunks of
+    // 64, small groups are packed whole
+    P.pk_off.clear();
+    P.pk_off.push_back(0);
+    {
+        uint32_t cur_start = 0, cur_cnt = 0;
+        for (int64_t gi = 0; gi < ngroup; gi++) {
+            uint32_t k = all[gi].len, s = P.grp_off[gi];
+            if (k >= 64) {
+                if (cur_cnt) { P.pk_off.push_back(cur_start + cur_cnt); cur_cnt = 0; }
+                for (uint32_t c = 0; c < k; c += 64) P.pk_off.push_back(s + std::min<uint32_t>(k, c + 64));
+                cur_start = s + k;
+            } else {
+                if (cur_cnt + k > 64) { P.pk_off.push_back(cur_start + cur_cnt); cur_start += cur_cnt; cur_cnt = 0; }
+                if (cur_cnt == 0) cur_start = s;
+                cur_cnt += k;
+            }
+        }
+        if (cur_cnt) P.pk_off.push_back(cur_start + cur_cnt);
+    }
+    // determinant-major slots
+    P.rowptr.assign(N + 1, 0);
+    for (int64_t mi = 0; mi < nmem; mi++) P.rowptr[P.mem[mi].x + 1]++;
+    for (int64_t i = 0; i < N; i++) P.rowptr[i + 1] += P.rowptr[i];
+    std::vector<uint32_t> fillc(P.rowptr.begin(), P.rowptr.end() - 1);
+    P.mem_slot.resize(nmem);
+    for (int64_t mi = 0; mi < nmem; mi++) P.mem_slot[mi] = fillc[P.mem[mi].x]++;
+    return MW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// integral repacking
+// ---------------------------------------------------------------------------
+
+static inline int pair_index(int lo, int hi) { return hi * (hi - 1) / 2 + lo; }
+
+static void repack(HostPlan &P, const mw_problem *p)
+{
+    const int n = P.n;
+    if (P.kind == MW_SPIN_FREE) {
+        const double *h = p->h, *g = p->g;
+        auto G = [&](int a, int b, int c, int d) { return g[(((size_t)a * n + b) * n + c) * n + d]; };
+        P.h.assign(h, h + (size_t)n * n);
+        P.w_same.resize((size_t)n * n * n);
+        P.w_opp.resize((size_t)n * n * n);
+        for (int r = 0; r < n; r++)
+            for (int a = 0; a < n; a++)
+                for (int b = 0; b < n; b++) {
+                    P.w_same[((size_t)r * n + a) * n + b] = G(a, b, r, r) - G(a, r, r, b);
+                    P.w_opp[((size_t)r * n + a) * n + b] = G(a, b, r, r);
+                }
+        P.g_ab.resize((size_t)n * n * n * n);
+        parallel_for(n, [&](int64_t q0, int64_t q1, unsigned) {
+            for (int64_t q = q0; q < q1; q++)
+                for (int s = 0; s < n; s++)
+                    for (int a = 0; a < n; a++)
+                        for (int r = 0; r < n; r++)
+                            P.g_ab[(((size_t)q * n + s) * n + a) * n + r] = G(a, q, r, s);
+        });
+        const int np = n * (n - 1) / 2;
+        P.npair = np;
+        P.a_pair.resize((size_t)np * np);
+        parallel_for(n, [&](int64_t x10, int64_t x11, unsigned) {
+            for (int64_t x1 = x10; x1 < x11; x1++)
+                for (int x0 = 0; x0 < x1; x0++)
+                    for (int y1 = 1; y1 < n; y1++)
+                        for (int y0 = 0; y0 < y1; y0++)
+                            P.a_pair[(size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1)] =
+                                G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
+        });
+    } else {
+        const int Mm = 2 * n;
+        using cd = std::complex<double>;
+        const cd *g = reinterpret_cast<const cd *>(p->g);
+        auto G = [&](int a, int b, int c, int d) { return g[(((size_t)a * Mm + b) * Mm + c) * Mm + d]; };
+        P.h.assign(p->h, p->h + 2 * (size_t)Mm * Mm);
+        P.w_same.resize(2 * (size_t)Mm * Mm * Mm);
+        for (int r = 0; r < Mm; r++)
+            for (int a = 0; a < Mm; a++)
+                for (int b = 0; b < Mm; b++) {
+                    cd v = G(a, b, r, r) - G(a, r, r, b);
+                    size_t k = ((size_t)r * Mm + a) * Mm + b;
+                    P.w_same[2 * k] = v.real();
+                    P.w_same[2 * k + 1] = v.imag();
+                }
+        const int np = Mm * (Mm - 1) / 2;
+        P.npair = np;
+        P.a_pair.resize(2 * (size_t)np * np);
+        parallel_for(Mm, [&](int64_t x10, int64_t x11, unsigned) {
+            for (int64_t x1 = x10; x1 < x11; x1++)
+                for (int x0 = 0; x0 < x1; x0++)
+                    for (int y1 = 1; y1 < Mm; y1++)
+                        for (int y0 = 0; y0 < y1; y0++) {
+                            cd v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
+                            size_t k = (size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1);
+                            P.a_pair[2 * k] = v.real();
+                            P.a_pair[2 * k + 1] = v.imag();
+                        }
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+
+size_t HostPlan::layout(DevPlan *d, char *base) const
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = (off + 255) & ~(size_t)255;
+        char *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t sb = scalar_bytes();
+    DevPlan t{};
+    t.kind = kind; t.n = n; t.M = M; t.npair = npair; t.ndet = ndet;
+    t.nmem = (int64_t)mem.size();
+    t.npacket = (int64_t)pk_off.size() - 1;
+    t.max_roots = max_roots;
+    t.ecore = ecore;
+    t.grp_off = (const uint32_t *)take(grp_off.size() * 4);
+    t.grp_key = (const uint64_t *)take(grp_key.size() * 8);
+    t.grp_type = (const uint8_t *)take(grp_type.size());
+    t.mem = (const uint2 *)take(mem.size() * 8);
+    t.mem_grp = (const uint32_t *)take(mem_grp.size() * 4);
+    t.mem_slot = (const uint32_t *)take(mem_slot.size() * 4);
+    t.pk_off = (const uint32_t *)take(pk_off.size() * 4);
+    t.rowptr = (const uint32_t *)take(rowptr.size() * 4);
+    t.dets = (const uint64_t *)take(dets.size() * 8);
+    t.diag = (void *)take((size_t)ndet * sb);
+    t.h = (const void *)take(h.size() * 8);
+    t.w_same = (const void *)take(w_same.size() * 8);
+    t.w_opp = (const void *)take(w_opp.size() * 8);
+    t.g_ab = (const void *)take(g_ab.size() * 8);
+    t.a_pair = (const void *)take(a_pair.size() * 8);
+    t.partial = (void *)take(std::max<size_t>(1, mem.size()) * (size_t)max_roots * sb);
+    if (d) *d = t;
+    return off + 256;
+}
+
+}  // namespace mw
+
+using namespace mw;
+
+struct mw_plan_s {
+    HostPlan p;
+};
+
+extern "C" {
+
+const char *mw_last_error(void) { return g_last_error.c_str(); }
+
+mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out)
+{
+    if (!out) return fail(MW_EINVAL, "out is NULL");
+    *out = nullptr;
+    mw_status st = validate(prob, max_roots);
+    if (st != MW_OK) return st;
+    std::unique_ptr<mw_plan_s> pl;
+    try {
+        pl.reset(new mw_plan_s());
+        HostPlan &P = pl->p;
+        P.kind = prob->kind;
+        P.n = prob->norb;
+        P.M = 2 * prob->norb;
+        P.nalpha = prob->nalpha;
+        P.nbeta = prob->nbeta;
+        P.ndet = prob->ndet;
+        P.ecore = prob->ecore;
+        P.cplx = prob->kind == MW_SPINOR;
+        P.max_roots = max_roots;
+        P.dets.assign(prob->dets, prob->dets + 2 * prob->ndet);
+        st = build_groups(P);
+        if (st != MW_OK) return st;
+        repack(P, prob);
+    } catch (const std::bad_alloc &) {
+        return fail(MW_EUNSUPPORTED, "host memory exhausted while building the plan");
+    } catch (const std::exception &e) {
+        return fail(MW_EINVAL, std::string("plan build failed: ") + e.what());
+    }
+    *out = pl.release();
+    return MW_OK;
+}
+
+mw_status mw_plan_workspace_bytes(mw_plan plan, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(MW_EINVAL, "NULL argument");
+    *bytes = plan->p.layout(nullptr, nullptr);
+    return MW_OK;
+}
+
+mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_t stream)
+{
+    if (!plan || !workspace) return fail(MW_EINVAL, "NULL argument");
+    HostPlan &P = plan->p;
+    size_t need = P.layout(nullptr, nullptr);
+    if (bytes < need) return fail(MW_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace) & 255) return fail(MW_EWORKSPACE, "workspace must be 256-byte aligned");
+    DevPlan d;
+    P.layout(&d, (char *)workspace);
+    hipStream_t s = (hipStream_t)stream;
+    auto up = [&](const void *dst, const void *src, size_t nb) -> bool {
+        if (!nb) return true;
+        return hipMemcpyAsync((void *)dst, src, nb, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool ok = up(d.grp_off, P.grp_off.data(), P.grp_off.size() * 4) &&
+              up(d.grp_key, P.grp_key.data(), P.grp_key.size() * 8) &&
+              up(d.grp_type, P.grp_type.data(), P.grp_type.size()) &&
+              up(d.mem, P.mem.data(), P.mem.size() * 8) &&
+              up(d.mem_grp, P.mem_grp.data(), P.mem_grp.size() * 4) &&
+              up(d.mem_slot, P.mem_slot.data(), P.mem_slot.size() * 4) &&
+              up(d.pk_off, P.pk_off.data(), P.pk_off.size() * 4) &&
+              up(d.rowptr, P.rowptr.data(), P.rowptr.size() * 4) &&
+              up(d.dets, P.dets.data(), P.dets.size() * 8) &&
+              up(d.h, P.h.data(), P.h.size() * 8) &&
+              up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
+              up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) &&
+              up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
+              up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8);
+    if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
+    mw_status st = launch_diag(d, s);
+    if (st != MW_OK) return st;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "hipStreamSynchronize failed after upload");
+    P.ws = workspace;
+    P.ws_bytes = bytes;
+    P.dev = d;
+    P.bound = true;
+    return MW_OK;
+}
+
+mw_status mw_plan_destroy(mw_plan plan)
+{
+    delete plan;
+    return MW_OK;
+}
+
+int64_t mw_plan_info(mw_plan plan, int32_t what)
+{
+    if (!plan) return -1;
+    const HostPlan &P = plan->p;
+    switch (what) {
+    case 0: return P.ndet;
+    case 1: return (int64_t)P.grp_type.size();
+    case 2: return (int64_t)P.mem.size();
+    case 3: return P.n_single_pairs + P.n_double_pairs;
+    case 4: return P.n_single_pairs;
+    case 5: return P.n_double_pairs;
+    case 6: return P.n_evals;
+    case 7: return (int64_t)P.layout(nullptr, nullptr);
+    case 8: return (int64_t)P.scalar_bytes();
+    case 9: return P.n;
+    case 10: return P.kind;
+    case 11: return (int64_t)P.pk_off.size() - 1;
+    default: return -1;
+    }
+}
+
+// accessor for the other translation units
+const mw::DevPlan *mw_internal_devplan(mw_plan plan)
+{
+    if (!plan || !plan->p.bound) return nullptr;
+    return &plan->p.dev;
+}
+
+}  // extern "C"

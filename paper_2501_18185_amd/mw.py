@@ -1,0 +1,244 @@
+"""Python binding of libmw (argument marshalling only).
+
+Every step of sigma = H c, the density matrices and the Davidson iteration
+runs inside ``libmw.so`` (HIP kernels for gfx950).  This module only packs
+arguments, owns the device workspace through PyTorch and raises on errors.
+There is no CPU fallback: without the built library, or without a GPU for
+the calls that need one, it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmw.so")
+
+MW_SPIN_FREE, MW_SPINOR = 0, 1
+STATUS = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOTSORTED", -3: "MW_EELEC", -4: "MW_ESYM",
+          -5: "MW_EWORKSPACE", -6: "MW_EHIP", -7: "MW_ENOCONV", -8: "MW_EUNSUPPORTED"}
+INFO = {"ndet": 0, "groups": 1, "memberships": 2, "pairs": 3, "single_pairs": 4,
+        "double_pairs": 5, "evaluations": 6, "workspace_bytes": 7, "scalar_bytes": 8,
+        "norb": 9, "kind": 10, "packets": 11}
+
+
+class MWError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Problem(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("norb", C.c_int32), ("nalpha", C.c_int32), ("nbeta", C.c_int32),
+                ("ndet", C.c_int64), ("dets", C.c_void_p), ("h", C.c_void_p), ("g", C.c_void_p),
+                ("ecore", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmw.so (built in-tree by ``build.py``); raise if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        L.mw_last_error.restype = C.c_char_p
+        L.mw_plan_create.argtypes = [C.POINTER(_Problem), i32, C.POINTER(vp)]
+        L.mw_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.mw_plan_upload.argtypes = [vp, vp, sz, vp]
+        L.mw_plan_destroy.argtypes = [vp]
+        L.mw_plan_info.argtypes = [vp, i32]
+        L.mw_plan_info.restype = i64
+        L.mw_sigma.argtypes = [vp, i32, vp, vp, vp]
+        L.mw_sigma_batched.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), vp]
+        L.mw_diag.argtypes = [vp, vp, vp]
+        L.mw_rdm_backward.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), vp, vp, vp]
+        L.mw_davidson_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+        L.mw_davidson.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), C.c_double, i32,
+                                  C.POINTER(i32), vp, sz, vp]
+        L.mw_connect_dump.argtypes = [vp, C.POINTER(i64), vp, vp]
+        for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
+                     "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
+                     "mw_davidson", "mw_connect_dump"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise MWError(st, lib().mw_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libmw needs a ROCm GPU (gfx950); none is visible")
+    return torch
+
+
+class Plan:
+    """A problem bound to its device workspace.
+
+    ``problem`` needs ``kind`` ("spinfree"/"spinor"), ``norb``, ``nalpha``,
+    ``nbeta``, ``dets`` ([ndet][2] uint64, sorted), ``h``, ``g`` and
+    ``ecore``.  ``upload=False`` builds the host plan only (no GPU needed),
+    which is enough for :meth:`info`.
+    """
+
+    def __init__(self, problem, max_roots: int = 1, device: str = "cuda", upload: bool = True):
+        L = lib()
+        self.kind = MW_SPIN_FREE if problem.kind == "spinfree" else MW_SPINOR
+        self.is_complex = self.kind == MW_SPINOR
+        self.norb = int(problem.norb)
+        self.ndet = int(len(problem.dets))
+        self.max_roots = int(max_roots)
+        self._dets = np.ascontiguousarray(problem.dets, dtype=np.uint64)
+        if self.is_complex:
+            self._h = np.ascontiguousarray(problem.h, dtype=np.complex128)
+            self._g = np.ascontiguousarray(problem.g, dtype=np.complex128)
+        else:
+            self._h = np.ascontiguousarray(np.real(problem.h), dtype=np.float64)
+            self._g = np.ascontiguousarray(np.real(problem.g), dtype=np.float64)
+        pr = _Problem(self.kind, self.norb, int(problem.nalpha), int(problem.nbeta), self.ndet,
+                      self._dets.ctypes.data, self._h.ctypes.data, self._g.ctypes.data, float(problem.ecore))
+        h = C.c_void_p()
+        _check(L.mw_plan_create(C.byref(pr), self.max_roots, C.byref(h)))
+        self._plan = h
+        # the integrals are repacked inside the plan; drop the big host copies
+        self._g = None
+        self.workspace = None
+        if upload:
+            self.upload(device)
+
+    # -- lifetime -----------------------------------------------------------
+    def upload(self, device="cuda"):
+        torch = _require_gpu()
+        nb = C.c_size_t()
+        _check(lib().mw_plan_workspace_bytes(self._plan, C.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        _check(lib().mw_plan_upload(self._plan, C.c_void_p(self.workspace.data_ptr()), nb.value, _stream()))
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            lib().mw_plan_destroy(self._plan)
+            self._plan = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries ------------------------------------------------------------
+    def info(self, what: str) -> int:
+        return int(lib().mw_plan_info(self._plan, INFO[what]))
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex128 if self.is_complex else torch.float64
+
+    def _vec(self, x, nroots=None):
+        torch = _require_gpu()
+        if not isinstance(x, torch.Tensor):
+            raise TypeError("expected a torch tensor on the GPU")
+        if x.device.type != "cuda" or x.dtype != self.dtype:
+            raise TypeError(f"expected a {self.dtype} tensor on the GPU, got {x.dtype} on {x.device}")
+        if x.shape[0] != self.ndet:
+            raise ValueError(f"leading dimension must be ndet={self.ndet}")
+        return x.contiguous()
+
+    # -- device calls --------------------------------------------------------
+    def sigma(self, c, out=None):
+        """sigma = H c for c of shape [ndet] or [ndet, nroots]."""
+        torch = _require_gpu()
+        c = self._vec(c)
+        nroots = 1 if c.dim() == 1 else c.shape[1]
+        if out is None:
+            out = torch.empty_like(c)
+        _check(lib().mw_sigma(self._plan, nroots, C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def diag(self):
+        torch = _require_gpu()
+        out = torch.empty(self.ndet, dtype=self.dtype, device=self.workspace.device)
+        _check(lib().mw_diag(self._plan, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def connect_dump(self):
+        """All connected (I, J) with phases: int64 [npairs, 7] (I, J, P, Q, R, S, sign)."""
+        torch = _require_gpu()
+        cnt = C.c_int64()
+        _check(lib().mw_connect_dump(self._plan, C.byref(cnt), None, _stream()))
+        out = torch.empty((cnt.value, 7), dtype=torch.int64, device=self.workspace.device)
+        if cnt.value:
+            _check(lib().mw_connect_dump(self._plan, C.byref(cnt), C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def rdm(self, bra, ket, weights: Optional[Sequence[float]] = None):
+        """Transition density matrices (gamma, Gamma); spin-free results are
+        spin-summed over spatial orbitals."""
+        torch = _require_gpu()
+        bra, ket = self._vec(bra), self._vec(ket)
+        nroots = 1 if bra.dim() == 1 else bra.shape[1]
+        m = self.norb if not self.is_complex else 2 * self.norb
+        gam = torch.empty((m, m), dtype=self.dtype, device=bra.device)
+        Gam = torch.empty((m, m, m, m), dtype=self.dtype, device=bra.device)
+        w = None
+        if weights is not None:
+            w = (C.c_double * nroots)(*[float(x) for x in weights])
+        _check(lib().mw_rdm_backward(self._plan, nroots, C.c_void_p(bra.data_ptr()), C.c_void_p(ket.data_ptr()),
+                                     w, C.c_void_p(gam.data_ptr()), C.c_void_p(Gam.data_ptr()), _stream()))
+        return gam, Gam
+
+    def davidson(self, c0, tol=1e-8, max_iter=100, check=True):
+        """Lowest eigenpairs from start vectors c0 [ndet, nroots].
+        Returns (evals numpy, vectors tensor, iterations, converged)."""
+        torch = _require_gpu()
+        c0 = self._vec(c0)
+        if c0.dim() == 1:
+            c0 = c0[:, None].contiguous()
+        nroots = c0.shape[1]
+        nb = C.c_size_t()
+        _check(lib().mw_davidson_work_bytes(self._plan, nroots, C.byref(nb)))
+        work = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=c0.device)
+        out = torch.empty_like(c0)
+        ev = (C.c_double * nroots)()
+        it = C.c_int32()
+        st = lib().mw_davidson(self._plan, nroots, C.c_void_p(c0.data_ptr()), C.c_void_p(out.data_ptr()), ev,
+                               float(tol), int(max_iter), C.byref(it), C.c_void_p(work.data_ptr()), nb.value,
+                               _stream())
+        conv = st == 0
+        if st not in (0, -7) or (check and not conv):
+            _check(st)
+        return np.array(list(ev)), out, it.value, conv
+
+
+def sigma_batched(plans: Sequence[Plan], cs, outs=None):
+    """sigma_i = H_i c_i for several plans in one launch sequence."""
+    torch = _require_gpu()
+    n = len(plans)
+    cs = [p._vec(c) for p, c in zip(plans, cs)]
+    if outs is None:
+        outs = [torch.empty_like(c) for c in cs]
+    P = (C.c_void_p * n)(*[p._plan.value for p in plans])
+    R = (C.c_int32 * n)(*[1 if c.dim() == 1 else c.shape[1] for c in cs])
+    Cp = (C.c_void_p * n)(*[c.data_ptr() for c in cs])
+    Sp = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(lib().mw_sigma_batched(n, P, R, Cp, Sp, _stream()))
+    return outs

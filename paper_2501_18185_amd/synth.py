@@ -236,7 +236,10 @@ def _fill_random(base0, base1, target, gen_batch):
     new0, new1 = [], []
     need = target - len(have)
     seen = have
+    stalls = 0
     while need > 0:
+        if stalls > 20:
+            raise ValueError(f"cannot reach {target} distinct determinants with this recipe")
         c0, c1 = gen_batch(int(need * 1.15) + 64)
         allk = np.concatenate([np.stack([seen[:, 0], seen[:, 1]], 1), np.stack([c0, c1], 1)])
         rec = np.empty(len(allk), dtype=[("a", "<u8"), ("b", "<u8")])
@@ -244,6 +247,7 @@ def _fill_random(base0, base1, target, gen_batch):
         _, first = np.unique(rec, return_index=True)
         first = np.sort(first[first >= len(seen)]) - len(seen)
         first = first[:need]
+        stalls = stalls + 1 if len(first) * 50 < need else 0
         new0.append(c0[first]); new1.append(c1[first])
         need -= len(first)
         seen = sort_unique(np.concatenate([seen[:, 0], c0[first]]),
