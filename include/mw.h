@@ -100,6 +100,14 @@ mw_status mw_plan_workspace_bytes(mw_plan plan, size_t *bytes);
  * streams concurrently. */
 mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_t stream);
 
+/* Replace the integrals (and ecore) of a bound plan without regrouping the
+ * determinants: validates them as mw_plan_create does, repacks them into the
+ * workspace and recomputes the diagonal.  h, g are HOST pointers laid out as
+ * in mw_problem.  Synchronises the stream.  Used when the same space is
+ * evaluated for several Hamiltonians (finite differences, orbital updates). */
+mw_status mw_plan_update_integrals(mw_plan plan, const double *h, const double *g, double ecore,
+                                   mw_stream_t stream);
+
 /* Free the plan's host memory (the workspace stays the caller's). */
 mw_status mw_plan_destroy(mw_plan plan);
 
@@ -117,14 +125,37 @@ int64_t mw_plan_info(mw_plan plan, int32_t what);
  * Enqueues the product on stream; bitwise reproducible between calls. */
 mw_status mw_sigma(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream);
 
-/* The same product for nprob independent plans in one launch sequence
- * (one persistent launch over all problems' work, then one gather launch).
+/* The same product for nprob (1..32) independent plans of one kind in one
+ * launch sequence: one persistent launch whose waves pull work units from a
+ * device counter across all problems (the dynamic task scheduling of the
+ * paper's parallel templates, section 3.1.2), then one gather launch.
  * plans, nroots, c, sigma are HOST arrays of length nprob (c[i], sigma[i]
- * device pointers).  The launch sequence is captured once into a HIP graph
- * keyed by the argument tuple and replayed on later calls with the same
- * tuple.  Results equal nprob separate mw_sigma calls bit for bit. */
+ * device pointers; each plan at most once).  The launch sequence is captured
+ * once into a HIP graph keyed by the argument tuple and replayed on later
+ * calls with the same tuple; destroying or re-binding a plan drops its
+ * graphs.  Results equal nprob separate mw_sigma calls bit for bit. */
 mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                            const void *const *c, void *const *sigma, mw_stream_t stream);
+
+/* The batched product with an explicit persistent grid (blocks_per_cu x the
+ * number of compute units), launched directly without graph capture. */
+mw_status mw_sigma_batched_direct(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
+                                  const void *const *c, void *const *sigma, int32_t blocks_per_cu,
+                                  mw_stream_t stream);
+
+/* Autotuner for mw_sigma: times the partner-loop unroll (4, 8, 16) and the
+ * gather width (8, 16, 32 lanes per determinant) on the caller's vectors and
+ * keeps the fastest in the plan; *choice (host, nullable) = unroll*100+lanes.
+ * Overwrites sigma; synchronises the stream. */
+mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream,
+                      int32_t *choice);
+
+/* Autotuner for mw_sigma_batched: times persistent grids of 1, 2, 4, 8, 16
+ * blocks per compute unit for this argument tuple and uses the fastest for
+ * its graph from then on; *blocks_per_cu (host, nullable) receives it. */
+mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
+                              const void *const *c, void *const *sigma, mw_stream_t stream,
+                              int32_t *blocks_per_cu);
 
 /* Diagonal H_II (device [ndet] scalars, imaginary part zero for spinor). */
 mw_status mw_diag(mw_plan plan, void *out, mw_stream_t stream);
@@ -161,6 +192,15 @@ mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out,
  * count in *count (host); then with a device buffer of 7*count int64.
  * Synchronises the stream.  Order of records is unspecified. */
 mw_status mw_connect_dump(mw_plan plan, int64_t *count, int64_t *out, mw_stream_t stream);
+
+/* Optional timing: while enabled, every kernel launch of the calls above is
+ * bracketed by HIP events recorded on its stream ("group_sigma", "gather",
+ * "rdm_groups", "rdm_diag", "batched_groups", "batched_gather").  Enabling
+ * clears earlier records.  mw_profile_read synchronises on the recorded
+ * events and returns the number of launches and their summed duration (ms,
+ * host outputs) for one kernel name. */
+mw_status mw_profile(int32_t enable);
+mw_status mw_profile_read(const char *kernel, int64_t *launches, double *total_ms);
 
 /* Thread-local description of the last error (never NULL). */
 const char *mw_last_error(void);

@@ -29,6 +29,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { double re, im; } cx;
 
@@ -165,6 +168,16 @@ static cx hij(const ham_t *H, const uint64_t *I, const uint64_t *J, int n)
 }
 
 /* ------------------------------------------------------------------------ */
+
+/* threads an OpenMP loop of this library uses */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* sigma[r][k] = sum_J H_{I_r J} c[J][k] for each requested row I_r.
  * c, sigma interleaved complex, [ndet][nroots] and [nrows][nroots]. */

@@ -30,10 +30,16 @@ def lib():
         L.orc_degree_rows.argtypes = [C.c_int, C.c_long, up, C.c_long, lp, lp]
         L.orc_connect_rows.argtypes = [C.c_int, C.c_long, up, C.c_long, lp, lp]
         L.orc_connect_rows.restype = C.c_long
+        L.orc_num_threads.restype = C.c_int
         L.orc_rdm_rows.argtypes = [C.c_int, C.c_int, C.c_long, up, C.c_int, dp, dp, dp, C.c_long,
                                    lp, dp, dp]
         _lib = L
     return _lib
+
+
+def num_threads():
+    """OpenMP threads the row loops use."""
+    return int(lib().orc_num_threads())
 
 
 def _p(a, t):

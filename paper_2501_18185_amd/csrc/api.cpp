@@ -53,27 +53,3 @@ mw_status mw_connect_dump(mw_plan plan, int64_t *count, int64_t *out, mw_stream_
 
 }  // extern "C"
 
-// Entry points that are filled in by later sources; until then they report
-// MW_EUNSUPPORTED.
-#ifndef MW_HAVE_RDM
-extern "C" mw_status mw_rdm_backward(mw_plan, int32_t, const void *, const void *, const double *, void *, void *,
-                                     mw_stream_t)
-{
-    return fail(MW_EUNSUPPORTED, "mw_rdm_backward not built");
-}
-#endif
-#ifndef MW_HAVE_DAVIDSON
-extern "C" mw_status mw_davidson_work_bytes(mw_plan, int32_t, size_t *) { return fail(MW_EUNSUPPORTED, "not built"); }
-extern "C" mw_status mw_davidson(mw_plan, int32_t, const void *, void *, double *, double, int32_t, int32_t *, void *,
-                                 size_t, mw_stream_t)
-{
-    return fail(MW_EUNSUPPORTED, "mw_davidson not built");
-}
-#endif
-#ifndef MW_HAVE_BATCHED
-extern "C" mw_status mw_sigma_batched(int32_t, const mw_plan *, const int32_t *, const void *const *, void *const *,
-                                      mw_stream_t)
-{
-    return fail(MW_EUNSUPPORTED, "mw_sigma_batched not built");
-}
-#endif

@@ -1,0 +1,268 @@
+// Batched sigma (many problems, one persistent launch, replayed from a HIP
+// graph) and the autotuner for the launch parameters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "mw_internal.h"
+
+using namespace mw;
+
+extern "C" const mw::DevPlan *mw_internal_devplan(mw_plan plan);
+extern "C" void mw_internal_set_tune(mw_plan plan, int32_t u, int32_t gl);
+
+namespace {
+
+struct BatchKey {
+    std::vector<uintptr_t> v;
+    bool operator<(const BatchKey &o) const { return v < o.v; }
+};
+
+struct BatchEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int bpc = 0;  // persistent blocks per compute unit used when captured
+};
+
+std::mutex g_mu;
+std::map<BatchKey, BatchEntry> g_cache;
+std::map<BatchKey, int> g_tuned_bpc;  // autotuned blocks per CU, by batch
+hipStream_t g_capture_stream = nullptr;
+int g_num_cu = 0;
+
+int num_cu()
+{
+    if (!g_num_cu) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            g_num_cu = n;
+        else
+            g_num_cu = 256;
+    }
+    return g_num_cu;
+}
+
+mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, const void *const *c,
+                    void *const *sigma, BatchArgs &a, bool &cplx, BatchKey &key)
+{
+    if (nprob < 1 || nprob > MW_MAXB) return fail(MW_EUNSUPPORTED, "nprob must be in 1..32");
+    if (!plans || !nroots || !c || !sigma) return fail(MW_EINVAL, "NULL argument");
+    std::vector<const DevPlan *> d(nprob);
+    for (int i = 0; i < nprob; i++) {
+        d[i] = mw_internal_devplan(plans[i]);
+        if (!d[i]) return fail(MW_EWORKSPACE, "plan " + std::to_string(i) + " has no workspace");
+        if (nroots[i] < 1 || nroots[i] > d[i]->max_roots) return fail(MW_EINVAL, "nroots out of range");
+        if (!c[i] || !sigma[i] || c[i] == sigma[i]) return fail(MW_EINVAL, "bad c/sigma pointer");
+        if (d[i]->kind != d[0]->kind) return fail(MW_EINVAL, "all plans of a batch must be of one kind");
+        for (int j = 0; j < i; j++)
+            if (plans[j] == plans[i]) return fail(MW_EINVAL, "a plan may appear once per batch");
+    }
+    cplx = d[0]->kind == MW_SPINOR;
+    // largest problems first
+    std::vector<int> ord(nprob);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x]->nmem > d[y]->nmem; });
+    a = BatchArgs{};
+    a.nprob = nprob;
+    a.pk_start[0] = 0;
+    a.det_start[0] = 0;
+    for (int k = 0; k < nprob; k++) {
+        int i = ord[k];
+        a.plans[k] = d[i]->self;
+        a.c[k] = c[i];
+        a.sigma[k] = sigma[i];
+        a.R[k] = nroots[i];
+        a.pk_start[k + 1] = a.pk_start[k] + d[i]->npacket;
+        a.det_start[k + 1] = a.det_start[k] + d[i]->ndet * nroots[i] * 16;
+    }
+    if (a.pk_start[nprob] >= 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many packets in one batch");
+    a.counter = d[ord[0]]->counter;
+    key.v.clear();
+    for (int i = 0; i < nprob; i++) {
+        key.v.push_back((uintptr_t)plans[i]);
+        key.v.push_back((uintptr_t)c[i]);
+        key.v.push_back((uintptr_t)sigma[i]);
+        key.v.push_back((uintptr_t)nroots[i]);
+    }
+    return MW_OK;
+}
+
+mw_status capture(const BatchArgs &a, bool cplx, int bpc, BatchEntry &e)
+{
+    if (!g_capture_stream && hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(MW_EHIP, "hipStreamCreateWithFlags failed");
+    if (hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(MW_EHIP, "hipStreamBeginCapture failed");
+    mw_status st = launch_batched(a, cplx, num_cu() * bpc, g_capture_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(g_capture_stream, &g);
+    if (st != MW_OK) return st;
+    if (ce != hipSuccess || !g) return fail(MW_EHIP, "hipStreamEndCapture failed");
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(MW_EHIP, "hipGraphInstantiate failed");
+    }
+    e.graph = g;
+    e.exec = ex;
+    e.bpc = bpc;
+    return MW_OK;
+}
+
+void drop(BatchEntry &e)
+{
+    if (e.exec) hipGraphExecDestroy(e.exec);
+    if (e.graph) hipGraphDestroy(e.graph);
+    e = BatchEntry{};
+}
+
+}  // namespace
+
+// Forget captured graphs that reference a plan (called when the plan is
+// destroyed or re-bound: the graphs hold its device addresses).
+void mw_internal_batched_forget(mw_plan plan)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+        bool hit = false;
+        for (size_t i = 0; i < it->first.v.size(); i += 4) hit = hit || it->first.v[i] == (uintptr_t)plan;
+        if (hit) {
+            drop(it->second);
+            it = g_cache.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = g_tuned_bpc.begin(); it != g_tuned_bpc.end();) {
+        bool hit = false;
+        for (size_t i = 0; i < it->first.v.size(); i += 4) hit = hit || it->first.v[i] == (uintptr_t)plan;
+        it = hit ? g_tuned_bpc.erase(it) : std::next(it);
+    }
+}
+
+extern "C" mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
+                                      const void *const *c, void *const *sigma, mw_stream_t stream)
+{
+    BatchArgs a;
+    bool cplx;
+    BatchKey key;
+    mw_status st = make_args(nprob, plans, nroots, c, sigma, a, cplx, key);
+    if (st != MW_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int bpc = 8;
+    auto tb = g_tuned_bpc.find(key);
+    if (tb != g_tuned_bpc.end()) bpc = tb->second;
+    auto it = g_cache.find(key);
+    if (it != g_cache.end() && it->second.bpc != bpc) {
+        drop(it->second);
+        g_cache.erase(it);
+        it = g_cache.end();
+    }
+    if (it == g_cache.end()) {
+        BatchEntry e;
+        st = capture(a, cplx, bpc, e);
+        if (st != MW_OK) return st;
+        it = g_cache.emplace(key, e).first;
+    }
+    if (hipGraphLaunch(it->second.exec, (hipStream_t)stream) != hipSuccess) return fail(MW_EHIP, "hipGraphLaunch failed");
+    return MW_OK;
+}
+
+// Direct (uncaptured) batched launch with an explicit persistent grid; used
+// by the tuner and for timing.
+extern "C" mw_status mw_sigma_batched_direct(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
+                                             const void *const *c, void *const *sigma, int32_t blocks_per_cu,
+                                             mw_stream_t stream)
+{
+    BatchArgs a;
+    bool cplx;
+    BatchKey key;
+    mw_status st = make_args(nprob, plans, nroots, c, sigma, a, cplx, key);
+    if (st != MW_OK) return st;
+    if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(MW_EINVAL, "blocks_per_cu must be in 1..64");
+    return launch_batched(a, cplx, num_cu() * blocks_per_cu, (hipStream_t)stream, true);
+}
+
+static double time_ms(hipStream_t s, int reps, const std::function<mw_status()> &f, mw_status *err)
+{
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    *err = f();  // warm-up
+    std::vector<float> ts;
+    for (int r = 0; r < reps && *err == MW_OK; r++) {
+        hipEventRecord(e0, s);
+        *err = f();
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        ts.push_back(ms);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (ts.empty()) return 1e30;
+    std::sort(ts.begin(), ts.end());
+    return ts[ts.size() / 2];
+}
+
+// Autotuner for plain sigma: tries the partner-loop unroll and the gather
+// width on the caller's vectors, keeps the fastest in the plan.  *choice
+// (host, may be NULL) receives unroll * 100 + gather lanes.
+extern "C" mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream,
+                                 int32_t *choice)
+{
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    hipStream_t s = (hipStream_t)stream;
+    const int us[3] = {4, 8, 16};
+    const int gls[3] = {8, 16, 32};
+    double best = 1e30;
+    int bu = 8, bg = 16;
+    mw_status err = MW_OK;
+    for (int u : us) {
+        if (u == 16 && d->kind == MW_SPINOR) continue;
+        for (int gl : gls) {
+            mw_internal_set_tune(plan, u, gl);
+            double t = time_ms(s, 3, [&]() { return mw_sigma(plan, nroots, c, sigma, stream); }, &err);
+            if (err != MW_OK) return err;
+            if (t < best) { best = t; bu = u; bg = gl; }
+        }
+    }
+    mw_internal_set_tune(plan, bu, bg);
+    if (choice) *choice = bu * 100 + bg;
+    return MW_OK;
+}
+
+// Autotuner for batched sigma: tries the persistent grid (blocks per CU) and
+// keeps the fastest for this batch; the captured graph is rebuilt with it.
+extern "C" mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
+                                         const void *const *c, void *const *sigma, mw_stream_t stream,
+                                         int32_t *blocks_per_cu)
+{
+    BatchArgs a;
+    bool cplx;
+    BatchKey key;
+    mw_status st = make_args(nprob, plans, nroots, c, sigma, a, cplx, key);
+    if (st != MW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double best = 1e30;
+    int bb = 8;
+    mw_status err = MW_OK;
+    for (int bpc : {1, 2, 4, 8, 16}) {
+        double t = time_ms(s, 3, [&]() { return launch_batched(a, cplx, num_cu() * bpc, s, false); }, &err);
+        if (err != MW_OK) return err;
+        if (t < best) { best = t; bb = bpc; }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned_bpc[key] = bb;
+    if (blocks_per_cu) *blocks_per_cu = bb;
+    return MW_OK;
+}

@@ -1,0 +1,449 @@
+// Block Davidson-Liu over mw_sigma (the paper diagonalises through products
+// sigma = H X that use only the nonzero elements of H, recomputed each time;
+// section 2.4).  The host drives the iteration; every operation over N-long
+// vectors runs in the kernels below, and only m x m subspace data crosses to
+// the host once per step.
+//
+// Iteration (lowest nroots roots):
+//   V orthonormal basis (vector-major [m][N]), W = H V.
+//   G = V^H W (m x m, Hermitian) -> eigenpairs (theta_k, y_k), lowest nroots.
+//   X_k = V y_k, AX_k = W y_k, r_k = AX_k - theta_k X_k; stop when every
+//   ||r_k||_2 <= tol.  t_k = r_k / (theta_k - H_II) (|denominator| >= 1e-12,
+//   sign kept); two passes of Gram-Schmidt against V; drop ||t|| < 1e-10.
+//   Collapse V to the Ritz vectors when it would exceed max(8 nroots, 24).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "dev_common.h"
+#include "mw_internal.h"
+
+namespace mw {
+
+namespace {
+
+constexpr int DOT_BLOCKS = 256;
+
+// partial[b][q] = sum over this block's slice of conj(X_{a_q}) Y_{b_q}
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_dots(const typename Scal<CPLX>::T *X, const typename Scal<CPLX>::T *Y,
+                                              int64_t N, const int *ia, const int *ib, int npairs,
+                                              typename Scal<CPLX>::T *partial)
+{
+    using T = typename Scal<CPLX>::T;
+    __shared__ T red[256];
+    for (int q = 0; q < npairs; q++) {
+        const T *x = X + (size_t)ia[q] * N;
+        const T *y = Y + (size_t)ib[q] * N;
+        T acc = sc_zero(T());
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x)
+            acc = sc_add(acc, sc_mul(sc_conj(x[t]), y[t]));
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] = sc_add(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * npairs + q] = red[0];
+        __syncthreads();
+    }
+}
+
+// out_k = beta_k * out_k + sum_a coef[a][k] X_a   for k < nout (out vectors
+// are rows of OUT starting at out0)
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_lincomb(const typename Scal<CPLX>::T *X, int na, int64_t N,
+                                                 const typename Scal<CPLX>::T *coef, int nout,
+                                                 typename Scal<CPLX>::T *OUT, const double *beta)
+{
+    using T = typename Scal<CPLX>::T;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < nout; k++) {
+            T acc = sc_zero(T());
+            for (int a = 0; a < na; a++) acc = sc_add(acc, sc_mul(coef[a * nout + k], X[(size_t)a * N + t]));
+            T o = acc;
+            if (beta[k] != 0.0) {  // never read OUT when it is overwritten
+                const T prev = OUT[(size_t)k * N + t];
+                if constexpr (CPLX) o = make_double2(beta[k] * prev.x + acc.x, beta[k] * prev.y + acc.y);
+                else o = beta[k] * prev + acc;
+            }
+            OUT[(size_t)k * N + t] = o;
+        }
+    }
+}
+
+// t = r / (theta - H_II) with the denominator clamped
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_precond(const typename Scal<CPLX>::T *Rv, const typename Scal<CPLX>::T *diag,
+                                                 double theta, int64_t N, typename Scal<CPLX>::T *T_out)
+{
+    using T = typename Scal<CPLX>::T;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        double dg;
+        if constexpr (CPLX) dg = diag[t].x;
+        else dg = diag[t];
+        double den = theta - dg;
+        if (fabs(den) < 1e-12) den = den < 0 ? -1e-12 : 1e-12;
+        T r = Rv[t];
+        if constexpr (CPLX) T_out[t] = make_double2(r.x / den, r.y / den);
+        else T_out[t] = r / den;
+    }
+}
+
+// vector-major [m][N] <-> interleaved [N][m]
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack(const T *src, int m, int64_t N, T *dst, int to_interleaved)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)m * N;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = t / m;
+        int k = (int)(t - i * m);
+        if (to_interleaved) dst[t] = src[(size_t)k * N + i];
+        else dst[(size_t)k * N + i] = src[t];
+    }
+}
+
+using cd = std::complex<double>;
+
+// cyclic Jacobi for a Hermitian m x m matrix (row-major); eigenvalues
+// ascending in w, eigenvectors in the columns of V
+static void jacobi_eigh(int m, std::vector<cd> A, std::vector<double> &w, std::vector<cd> &V)
+{
+    V.assign((size_t)m * m, cd(0));
+    for (int i = 0; i < m; i++) V[(size_t)i * m + i] = 1.0;
+    for (int sweep = 0; sweep < 100; sweep++) {
+        double off = 0, dn = 0;
+        for (int i = 0; i < m; i++)
+            for (int j = 0; j < m; j++) (i == j ? dn : off) += std::norm(A[(size_t)i * m + j]);
+        if (off <= 1e-30 * std::max(dn, 1e-300)) break;
+        for (int p = 0; p < m; p++)
+            for (int q = p + 1; q < m; q++) {
+                cd apq = A[(size_t)p * m + q];
+                double a = std::abs(apq);
+                if (a < 1e-300) continue;
+                double app = A[(size_t)p * m + p].real(), aqq = A[(size_t)q * m + q].real();
+                cd ph = apq / a;  // e^{i phi}
+                double tau = (aqq - app) / (2 * a);
+                double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
+                double c = 1 / std::sqrt(1 + t * t), s = t * c;
+                // rotation J: columns p, q: [c, s ph; -s conj(ph), c]
+                for (int k = 0; k < m; k++) {
+                    cd akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                    A[(size_t)k * m + p] = c * akp - s * std::conj(ph) * akq;
+                    A[(size_t)k * m + q] = s * ph * akp + c * akq;
+                }
+                for (int k = 0; k < m; k++) {
+                    cd apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+                    A[(size_t)p * m + k] = c * apk - s * ph * aqk;
+                    A[(size_t)q * m + k] = s * std::conj(ph) * apk + c * aqk;
+                }
+                for (int k = 0; k < m; k++) {
+                    cd vkp = V[(size_t)k * m + p], vkq = V[(size_t)k * m + q];
+                    V[(size_t)k * m + p] = c * vkp - s * std::conj(ph) * vkq;
+                    V[(size_t)k * m + q] = s * ph * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> idx(m);
+    for (int i = 0; i < m; i++) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int a, int b) { return A[(size_t)a * m + a].real() < A[(size_t)b * m + b].real(); });
+    std::vector<cd> V2((size_t)m * m);
+    w.resize(m);
+    for (int j = 0; j < m; j++) {
+        w[j] = A[(size_t)idx[j] * m + idx[j]].real();
+        for (int k = 0; k < m; k++) V2[(size_t)k * m + j] = V[(size_t)k * m + idx[j]];
+    }
+    V = V2;
+}
+
+template <bool CPLX>
+struct Davidson {
+    using T = typename Scal<CPLX>::T;
+    mw_plan plan;
+    const DevPlan *d;
+    hipStream_t s;
+    int R, mmax;
+    int64_t N;
+    // device buffers carved from the caller's work area
+    T *V, *W, *X, *AX, *Rv, *Tn, *packA, *packB, *coef, *dpart;
+    double *beta;
+    int *ia, *ib;
+    std::vector<cd> Gh;  // host subspace matrix (mmax x mmax)
+
+    static size_t bytes(int R, int64_t N)
+    {
+        const int mmax = std::max(8 * R, 24) + R;
+        const size_t sb = sizeof(T);
+        size_t b = 0;
+        auto take = [&](size_t x) { b = (b + 255) & ~(size_t)255; b += x; };
+        take((size_t)mmax * N * sb);        // V
+        take((size_t)mmax * N * sb);        // W
+        take((size_t)R * N * sb);           // X
+        take((size_t)R * N * sb);           // AX
+        take((size_t)R * N * sb);           // residuals
+        take((size_t)R * N * sb);           // new vectors
+        take((size_t)R * N * sb);           // packed in
+        take((size_t)R * N * sb);           // packed out
+        take((size_t)mmax * mmax * sb);     // coefficients
+        take((size_t)DOT_BLOCKS * mmax * R * sb);  // dot partials
+        take((size_t)mmax * 8);             // beta
+        take((size_t)2 * mmax * R * 4);     // pair indices
+        return b + 256;
+    }
+
+    void carve(char *base)
+    {
+        size_t off = 0;
+        const size_t sb = sizeof(T);
+        auto take = [&](size_t x) { off = (off + 255) & ~(size_t)255; char *p = base + off; off += x; return p; };
+        V = (T *)take((size_t)mmax * N * sb);
+        W = (T *)take((size_t)mmax * N * sb);
+        X = (T *)take((size_t)R * N * sb);
+        AX = (T *)take((size_t)R * N * sb);
+        Rv = (T *)take((size_t)R * N * sb);
+        Tn = (T *)take((size_t)R * N * sb);
+        packA = (T *)take((size_t)R * N * sb);
+        packB = (T *)take((size_t)R * N * sb);
+        coef = (T *)take((size_t)mmax * mmax * sb);
+        dpart = (T *)take((size_t)DOT_BLOCKS * mmax * R * sb);
+        beta = (double *)take((size_t)mmax * 8);
+        ia = (int *)take((size_t)mmax * R * 4);
+        ib = (int *)take((size_t)mmax * R * 4);
+    }
+
+    static cd to_c(double x) { return cd(x, 0); }
+    static cd to_c(double2 x) { return cd(x.x, x.y); }
+    static void from_c(cd v, double &x) { x = v.real(); }
+    static void from_c(cd v, double2 &x) { x = make_double2(v.real(), v.imag()); }
+
+    unsigned grid() const { return (unsigned)std::min<int64_t>((N + 255) / 256, 4096); }
+
+    // dots conj(A_{a_q}) . B_{b_q} for the given pairs; blocking
+    bool dots(const T *A, const T *B, const std::vector<int> &a, const std::vector<int> &b, std::vector<cd> &out)
+    {
+        const int np = (int)a.size();
+        out.assign(np, cd(0));
+        if (!np) return true;
+        for (int c0 = 0; c0 < np; c0 += mmax * R) {
+            int cnt = std::min(np - c0, mmax * R);
+            if (hipMemcpyAsync(ia, a.data() + c0, cnt * 4, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+            if (hipMemcpyAsync(ib, b.data() + c0, cnt * 4, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+            hipLaunchKernelGGL(k_dots<CPLX>, dim3(DOT_BLOCKS), dim3(256), 0, s, A, B, N, ia, ib, cnt, dpart);
+            std::vector<T> h((size_t)DOT_BLOCKS * cnt);
+            if (hipMemcpyAsync(h.data(), dpart, h.size() * sizeof(T), hipMemcpyDeviceToHost, s) != hipSuccess)
+                return false;
+            if (hipStreamSynchronize(s) != hipSuccess) return false;
+            for (int q = 0; q < cnt; q++) {
+                cd acc = 0;
+                for (int blk = 0; blk < DOT_BLOCKS; blk++) acc += to_c(h[(size_t)blk * cnt + q]);
+                out[c0 + q] = acc;
+            }
+        }
+        return true;
+    }
+
+    // OUT_k = beta_k OUT_k + sum_a C[a][k] X_a
+    bool lincomb(const T *Xs, int na, const std::vector<cd> &C, int nout, T *OUT, const std::vector<double> &bt)
+    {
+        std::vector<T> ch((size_t)na * nout);
+        for (size_t i = 0; i < ch.size(); i++) from_c(C[i], ch[i]);
+        if (na && hipMemcpyAsync(coef, ch.data(), ch.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
+            return false;
+        if (hipMemcpyAsync(beta, bt.data(), nout * 8, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+        hipLaunchKernelGGL(k_lincomb<CPLX>, dim3(grid()), dim3(256), 0, s, Xs, na, N, coef, nout, OUT, beta);
+        // the host arrays must stay valid until the copies ran
+        return hipStreamSynchronize(s) == hipSuccess;
+    }
+
+    // W rows [first, first+k) = H V rows [first, first+k)
+    mw_status apply_h(int first, int k)
+    {
+        hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, V + (size_t)first * N, k, N, packA, 1);
+        mw_status st = mw_sigma(plan, k, packA, packB, (mw_stream_t)s);
+        if (st != MW_OK) return st;
+        hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, packB, k, N, W + (size_t)first * N, 0);
+        return MW_OK;
+    }
+
+    // Gram-Schmidt of row `row` of V against rows [0, row); returns the norm
+    bool orthonormalize(int row, double &norm)
+    {
+        T *t = V + (size_t)row * N;
+        for (int pass = 0; pass < 2 && row > 0; pass++) {
+            std::vector<int> a(row), b(row, row);
+            for (int i = 0; i < row; i++) a[i] = i;
+            std::vector<cd> ov;
+            if (!dots(V, V, a, b, ov)) return false;
+            std::vector<cd> C(row);
+            for (int i = 0; i < row; i++) C[i] = -ov[i];
+            if (!lincomb(V, row, C, 1, t, std::vector<double>{1.0})) return false;
+        }
+        std::vector<cd> nn;
+        if (!dots(V, V, std::vector<int>{row}, std::vector<int>{row}, nn)) return false;
+        norm = std::sqrt(std::max(nn[0].real(), 0.0));
+        if (norm >= 1e-10) {
+            std::vector<cd> C;
+            if (!lincomb(V, 0, C, 1, t, std::vector<double>{1.0 / norm})) return false;
+        }
+        return true;
+    }
+
+    mw_status run(const void *c0, void *c_out, double *evals, double tol, int max_iter, int *iters)
+    {
+        const int msub = std::max(8 * R, 24);
+        Gh.assign((size_t)mmax * mmax, cd(0));
+        // start: orthonormalised c0
+        hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, (const T *)c0, R, N, V, 0);
+        int m = 0;
+        for (int k = 0; k < R; k++) {
+            if (k != m)
+                if (hipMemcpyAsync(V + (size_t)m * N, V + (size_t)k * N, N * sizeof(T), hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                    return fail(MW_EHIP, "copy failed");
+            double nrm;
+            if (!orthonormalize(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
+            if (nrm >= 1e-10) m++;
+        }
+        if (m < R) return fail(MW_EINVAL, "start vectors are linearly dependent");
+        mw_status st = apply_h(0, m);
+        if (st != MW_OK) return st;
+        int newfirst = 0;
+        std::vector<double> theta(R);
+        std::vector<cd> Y;
+        bool converged = false;
+        int it = 0;
+        for (it = 1; it <= max_iter; it++) {
+            // G[a][b] for b in the new rows (and its conjugate mirror)
+            std::vector<int> a, b;
+            for (int bb = newfirst; bb < m; bb++)
+                for (int aa = 0; aa < m; aa++) { a.push_back(aa); b.push_back(bb); }
+            std::vector<cd> gv;
+            if (!dots(V, W, a, b, gv)) return fail(MW_EHIP, "dot products failed");
+            for (size_t q = 0; q < gv.size(); q++) {
+                Gh[(size_t)a[q] * mmax + b[q]] = gv[q];
+                Gh[(size_t)b[q] * mmax + a[q]] = std::conj(gv[q]);
+            }
+            std::vector<cd> G((size_t)m * m);
+            for (int i = 0; i < m; i++)
+                for (int j = 0; j < m; j++)
+                    G[(size_t)i * m + j] = 0.5 * (Gh[(size_t)i * mmax + j] + std::conj(Gh[(size_t)j * mmax + i]));
+            std::vector<double> w;
+            std::vector<cd> E;
+            jacobi_eigh(m, G, w, E);
+            Y.assign((size_t)m * R, cd(0));
+            for (int i = 0; i < m; i++)
+                for (int k = 0; k < R; k++) Y[(size_t)i * R + k] = E[(size_t)i * m + k];
+            for (int k = 0; k < R; k++) theta[k] = w[k];
+            std::vector<double> zero(R, 0.0);
+            if (!lincomb(V, m, Y, R, X, zero) || !lincomb(W, m, Y, R, AX, zero)) return fail(MW_EHIP, "Ritz failed");
+            // residuals r_k = AX_k - theta_k X_k
+            if (hipMemcpyAsync(Rv, AX, (size_t)R * N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(MW_EHIP, "copy failed");
+            for (int k = 0; k < R; k++) {
+                std::vector<cd> C{cd(-theta[k], 0)};
+                if (!lincomb(X + (size_t)k * N, 1, C, 1, Rv + (size_t)k * N, std::vector<double>{1.0}))
+                    return fail(MW_EHIP, "residual failed");
+            }
+            std::vector<int> ka(R);
+            for (int k = 0; k < R; k++) ka[k] = k;
+            std::vector<cd> rn;
+            if (!dots(Rv, Rv, ka, ka, rn)) return fail(MW_EHIP, "norms failed");
+            bool all = true;
+            for (int k = 0; k < R; k++) all = all && std::sqrt(std::max(rn[k].real(), 0.0)) <= tol;
+            if (all) { converged = true; break; }
+            if (it == max_iter) break;
+            // corrections
+            int nnew = 0;
+            for (int k = 0; k < R; k++) {
+                if (std::sqrt(std::max(rn[k].real(), 0.0)) <= tol) continue;
+                hipLaunchKernelGGL(k_precond<CPLX>, dim3(grid()), dim3(256), 0, s, Rv + (size_t)k * N,
+                                   (const T *)d->diag, theta[k], N, Tn + (size_t)nnew * N);
+                nnew++;
+            }
+            if (m + nnew > msub) {
+                // collapse onto the Ritz vectors
+                if (hipMemcpyAsync(V, X, (size_t)R * N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                    hipMemcpyAsync(W, AX, (size_t)R * N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    return fail(MW_EHIP, "collapse failed");
+                std::fill(Gh.begin(), Gh.end(), cd(0));
+                for (int k = 0; k < R; k++) Gh[(size_t)k * mmax + k] = theta[k];
+                m = R;
+            }
+            newfirst = m;
+            for (int k = 0; k < nnew; k++) {
+                if (hipMemcpyAsync(V + (size_t)m * N, Tn + (size_t)k * N, N * sizeof(T), hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                    return fail(MW_EHIP, "copy failed");
+                double nrm;
+                if (!orthonormalize(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
+                if (nrm >= 1e-10) m++;
+            }
+            if (m == newfirst) break;  // no new direction: stagnation
+            st = apply_h(newfirst, m - newfirst);
+            if (st != MW_OK) return st;
+        }
+        hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, X, R, N, (T *)c_out, 1);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "final sync failed");
+        for (int k = 0; k < R; k++) evals[k] = theta[k];
+        *iters = std::min(it, max_iter);
+        if (!converged) return fail(MW_ENOCONV, "Davidson did not converge");
+        return MW_OK;
+    }
+};
+
+}  // namespace
+}  // namespace mw
+
+using namespace mw;
+
+extern "C" const mw::DevPlan *mw_internal_devplan(mw_plan plan);
+
+extern "C" mw_status mw_davidson_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(MW_EINVAL, "NULL argument");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots");
+    *bytes = d->kind == MW_SPINOR ? Davidson<true>::bytes(nroots, d->ndet) : Davidson<false>::bytes(nroots, d->ndet);
+    return MW_OK;
+}
+
+template <bool CPLX>
+static mw_status run_davidson(mw_plan plan, const DevPlan *d, int32_t nroots, const void *c0, void *c_out,
+                              double *evals, double tol, int32_t max_iter, int32_t *iters, void *work,
+                              hipStream_t s)
+{
+    Davidson<CPLX> D;
+    D.plan = plan;
+    D.d = d;
+    D.s = s;
+    D.R = nroots;
+    D.mmax = std::max(8 * nroots, 24) + nroots;
+    D.N = d->ndet;
+    D.carve((char *)work);
+    return D.run(c0, c_out, evals, tol, max_iter, iters);
+}
+
+extern "C" mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out, double *evals, double tol,
+                                 int32_t max_iter, int32_t *iters, void *work, size_t work_bytes, mw_stream_t stream)
+{
+    if (!plan) return fail(MW_EINVAL, "plan is NULL");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots");
+    if (!c0 || !c_out || !evals || !iters || !work) return fail(MW_EINVAL, "NULL argument");
+    if (!(tol > 0) || max_iter < 1) return fail(MW_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (nroots > d->ndet) return fail(MW_EINVAL, "more roots than determinants");
+    size_t need;
+    mw_status st = mw_davidson_work_bytes(plan, nroots, &need);
+    if (st != MW_OK) return st;
+    if (work_bytes < need) return fail(MW_EWORKSPACE, "work area too small");
+    if (((uintptr_t)work) & 255) return fail(MW_EWORKSPACE, "work area must be 256-byte aligned");
+    if (d->kind == MW_SPINOR)
+        return run_davidson<true>(plan, d, nroots, c0, c_out, evals, tol, max_iter, iters, work, (hipStream_t)stream);
+    return run_davidson<false>(plan, d, nroots, c0, c_out, evals, tol, max_iter, iters, work, (hipStream_t)stream);
+}

@@ -23,32 +23,9 @@
 #include <vector>
 
 #include "mw_internal.h"
+#include "dev_common.h"
 
 namespace mw {
-
-// ---------------------------------------------------------------------------
-// scalar helpers (double or complex as double2)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double sc_zero(double) { return 0.0; }
-__device__ __forceinline__ double2 sc_zero(double2) { return make_double2(0.0, 0.0); }
-__device__ __forceinline__ double sc_add(double a, double b) { return a + b; }
-__device__ __forceinline__ double2 sc_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double sc_mul(double a, double b) { return a * b; }
-__device__ __forceinline__ double2 sc_mul(double2 a, double2 b)
-{
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double sc_conj(double a) { return a; }
-__device__ __forceinline__ double2 sc_conj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double sc_neg(double a, bool n) { return n ? -a : a; }
-__device__ __forceinline__ double2 sc_neg(double2 a, bool n) { return n ? make_double2(-a.x, -a.y) : a; }
-
-template <bool C> struct Scal;
-template <> struct Scal<false> { using T = double; };
-template <> struct Scal<true> { using T = double2; };
-
-__device__ __forceinline__ int pair_idx(int lo, int hi) { return hi * (hi - 1) / 2 + lo; }
 
 // ---------------------------------------------------------------------------
 // diagonal
@@ -109,68 +86,87 @@ mw_status launch_diag(const DevPlan &p, hipStream_t s)
 // Single-excitation element <K+P_i| H |K+P_j> / (phi_i phi_j), read as the
 // (j, i) entry and conjugated:  F^K_{P_j P_i} = h_{P_j P_i} + sum_{R in K}
 // [(P_j P_i|R R) - (P_j R|R P_i)]  (spin-free: the exchange part only for R
-// of the same spin).
+// of the same spin).  Evaluated from the reference table F^omega plus the
+// positions where K and omega differ.
 template <bool CPLX>
 __device__ __forceinline__ typename Scal<CPLX>::T single_element(const DevPlan &p, uint8_t type, uint64_t k0,
                                                                   uint64_t k1, int Xi, int Xj)
 {
     using T = typename Scal<CPLX>::T;
-    const T *h = (const T *)p.h;
     const T *w = (const T *)p.w_same;
     const int n = p.n;
     if constexpr (CPLX) {
         const int M = p.M;
-        T f = h[(size_t)Xj * M + Xi];
-        const T *row = w + (size_t)Xj * M + Xi;
-        const size_t stride = (size_t)M * M;
-        for (uint64_t x = k0; x; x &= x - 1) f = sc_add(f, row[(size_t)__builtin_ctzll(x) * stride]);
-        for (uint64_t x = k1; x; x &= x - 1) f = sc_add(f, row[(size_t)(n + __builtin_ctzll(x)) * stride]);
+        const size_t base = (size_t)Xj * M + Xi, stride = (size_t)M * M;
+        T f = ((const T *)p.f_ref)[base];
+        T add = sc_zero(T()), sub = sc_zero(T());
+        for (uint64_t x = k0 & ~p.ref0; x; x &= x - 1) add = sc_add(add, w[(size_t)__builtin_ctzll(x) * stride + base]);
+        for (uint64_t x = k1 & ~p.ref1; x; x &= x - 1) add = sc_add(add, w[(size_t)(n + __builtin_ctzll(x)) * stride + base]);
+        for (uint64_t x = p.ref0 & ~k0; x; x &= x - 1) sub = sc_add(sub, w[(size_t)__builtin_ctzll(x) * stride + base]);
+        for (uint64_t x = p.ref1 & ~k1; x; x &= x - 1) sub = sc_add(sub, w[(size_t)(n + __builtin_ctzll(x)) * stride + base]);
+        f = sc_add(f, add);
+        f = make_double2(f.x - sub.x, f.y - sub.y);
         return sc_conj(f);
     } else {
         const T *wo = (const T *)p.w_opp;
-        const int pi = Xi % n, pj = Xj % n;
+        const int s = type == G_SINGLE_A ? 0 : 1;
+        const int pi = Xi - s * n, pj = Xj - s * n;
         const size_t base = (size_t)pj * n + pi, stride = (size_t)n * n;
-        T f = h[base];
-        uint64_t same = type == G_SINGLE_A ? k0 : k1;
-        uint64_t opp = type == G_SINGLE_A ? k1 : k0;
-        for (uint64_t x = same; x; x &= x - 1) f += w[(size_t)__builtin_ctzll(x) * stride + base];
-        for (uint64_t x = opp; x; x &= x - 1) f += wo[(size_t)__builtin_ctzll(x) * stride + base];
-        return f;
+        T f = ((const T *)p.f_ref)[(size_t)s * stride + base];
+        const uint64_t ks = s ? k1 : k0, ko = s ? k0 : k1;
+        const uint64_t rs = s ? p.ref1 : p.ref0, ro = s ? p.ref0 : p.ref1;
+        T add = 0.0, sub = 0.0;
+        for (uint64_t x = ks & ~rs; x; x &= x - 1) add += w[(size_t)__builtin_ctzll(x) * stride + base];
+        for (uint64_t x = ko & ~ro; x; x &= x - 1) add += wo[(size_t)__builtin_ctzll(x) * stride + base];
+        for (uint64_t x = rs & ~ks; x; x &= x - 1) sub += w[(size_t)__builtin_ctzll(x) * stride + base];
+        for (uint64_t x = ro & ~ko; x; x &= x - 1) sub += wo[(size_t)__builtin_ctzll(x) * stride + base];
+        return (f + add) - sub;
     }
 }
 
-// Double-excitation integral A(pair_i, pair_j) = (P Q|R S) - (P S|R Q) with
-// (P,R) the pair added in i and (Q,S) the pair added in j, read as the
-// (j, i) entry of the table and conjugated.
+// Offset of the double-excitation integral A(pair_i, pair_j) = (P Q|R S) -
+// (P S|R Q), with (P,R) added in i and (Q,S) added in j, read as the (j, i)
+// entry of its table: column part (depends on i only) + row part (j only).
+struct DoubleIndex {
+    size_t col;
+    size_t row_stride;
+    int n, off, ab;
+    __device__ __forceinline__ size_t row(int Xj, int Yj) const
+    {
+        if (ab) return ((size_t)Xj * n + (Yj - n)) * row_stride;
+        return (size_t)pair_idx(Xj - off, Yj - off) * row_stride;
+    }
+};
+
 template <bool CPLX>
-__device__ __forceinline__ typename Scal<CPLX>::T double_element(const DevPlan &p, uint8_t type, int Xi, int Yi,
-                                                                  int Xj, int Yj)
+__device__ __forceinline__ DoubleIndex double_index(const DevPlan &p, uint8_t type, int Xi, int Yi)
 {
-    using T = typename Scal<CPLX>::T;
-    const T *a = (const T *)p.a_pair;
-    if constexpr (CPLX) {
-        return sc_conj(a[(size_t)pair_idx(Xj, Yj) * p.npair + pair_idx(Xi, Yi)]);
+    DoubleIndex d;
+    d.n = p.n;
+    if (!CPLX && type == G_AB) {
+        // (p_i q_j | r_i s_j) stored as g_ab[q][s][p][r]
+        d.ab = 1;
+        d.off = 0;
+        d.row_stride = (size_t)p.n * p.n;
+        d.col = (size_t)Xi * p.n + (Yi - p.n);
     } else {
-        const int n = p.n;
-        if (type == G_AB) {
-            // (p_i q_j | r_i s_j) stored as g_ab[q][s][p][r]
-            const T *g = (const T *)p.g_ab;
-            return g[(((size_t)Xj * n + (Yj - n)) * n + Xi) * n + (Yi - n)];
-        }
-        const int o = type == G_BB ? n : 0;
-        return a[(size_t)pair_idx(Xj - o, Yj - o) * p.npair + pair_idx(Xi - o, Yi - o)];
+        d.ab = 0;
+        d.off = (!CPLX && type == G_BB) ? p.n : 0;
+        d.row_stride = p.npair;
+        d.col = pair_idx(Xi - d.off, Yi - d.off);
     }
+    return d;
 }
 
-template <bool CPLX, int RC>
-__global__ __launch_bounds__(256) void k_group_sigma(DevPlan p, int R, int r0,
-                                                     const typename Scal<CPLX>::T *__restrict__ c,
-                                                     typename Scal<CPLX>::T *__restrict__ partial)
+// Double groups.  Lane = member i; the partner loop is unrolled by U so that
+// U member records, U integrals and U coefficient rows are in flight at once
+// (the loop is bound by memory latency, not arithmetic).
+template <bool CPLX, int RC, int U>
+__device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave, int lane, int R, int r0,
+                                                  const typename Scal<CPLX>::T *__restrict__ c,
+                                                  typename Scal<CPLX>::T *__restrict__ partial)
 {
     using T = typename Scal<CPLX>::T;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (wave >= p.npacket) return;
     const uint32_t m = p.pk_off[wave] + lane;
     if (m >= p.pk_off[wave + 1]) return;
     const uint32_t g = p.mem_grp[m];
@@ -178,35 +174,40 @@ __global__ __launch_bounds__(256) void k_group_sigma(DevPlan p, int R, int r0,
     const uint8_t type = p.grp_type[g];
     const uint2 me = p.mem[m];
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
-    const bool negi = (me.y >> 16) & 1;
+    const uint32_t negi = (me.y >> 16) & 1;
+    const DoubleIndex di = double_index<CPLX>(p, type, Xi, Yi);
+    const T *tab = (const T *)((!CPLX && type == G_AB) ? p.g_ab : p.a_pair);
     T acc[RC];
 #pragma unroll
     for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
     const int nr = min(RC, R - r0);
-    if (type == G_SINGLE_A || type == G_SINGLE_B || type == G_SINGLE_S) {
-        const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
-        for (uint32_t j = j0; j < j1; j++) {
-            const uint2 o = p.mem[j];
-            const int Xj = o.y & 255;
-            if (Xj == Xi) continue;
-            T v = single_element<CPLX>(p, type, k0, k1, Xi, Xj);
-            v = sc_neg(v, negi ^ (bool)((o.y >> 16) & 1));
-            const T *cj = c + (size_t)o.x * R + r0;
+    for (uint32_t j = j0; j < j1; j += U) {
+        uint2 o[U];
+        bool hit[U];
 #pragma unroll
-            for (int k = 0; k < RC; k++)
-                if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
+        for (int u = 0; u < U; u++) {
+            const bool in = j + u < j1;
+            o[u] = p.mem[in ? j + u : j0];
+            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
+            hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
         }
-    } else {
-        for (uint32_t j = j0; j < j1; j++) {
-            const uint2 o = p.mem[j];
-            const int Xj = o.y & 255, Yj = (o.y >> 8) & 255;
-            if (Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi) continue;
-            T v = double_element<CPLX>(p, type, Xi, Yi, Xj, Yj);
-            v = sc_neg(v, negi ^ (bool)((o.y >> 16) & 1));
-            const T *cj = c + (size_t)o.x * R + r0;
+        T v[U];
+        T cj[U][RC];
 #pragma unroll
-            for (int k = 0; k < RC; k++)
-                if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
+        for (int u = 0; u < U; u++) {
+            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
+            const size_t idx = hit[u] ? di.row(Xj, Yj) + di.col : 0;
+            v[u] = tab[idx];
+            const T *cr = c + (size_t)(hit[u] ? o[u].x : 0) * R + r0;
+#pragma unroll
+            for (int k = 0; k < RC; k++) cj[u][k] = cr[k < nr ? k : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (!hit[u]) continue;
+            T x = sc_neg(CPLX ? sc_conj(v[u]) : v[u], (negi ^ ((o[u].y >> 16) & 1)) != 0);
+#pragma unroll
+            for (int k = 0; k < RC; k++) acc[k] = sc_add(acc[k], sc_mul(x, cj[u][k]));
         }
     }
     T *out = partial + (size_t)p.mem_slot[m] * R + r0;
@@ -215,20 +216,141 @@ __global__ __launch_bounds__(256) void k_group_sigma(DevPlan p, int R, int r0,
         if (k < nr) out[k] = acc[k];
 }
 
-template <bool CPLX>
+template <bool CPLX, int RC, int U>
+__global__ __launch_bounds__(256) void k_group_double(DevPlan p, int R, int r0,
+                                                      const typename Scal<CPLX>::T *__restrict__ c,
+                                                      typename Scal<CPLX>::T *__restrict__ partial)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= p.npacket_double) return;
+    group_double_body<CPLX, RC, U>(p, wave, threadIdx.x & 63, R, r0, c, partial);
+}
+
+// Single groups (few pairs; each element needs the reference correction).
+template <bool CPLX, int RC>
+__device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave, int lane, int R, int r0,
+                                                  const typename Scal<CPLX>::T *__restrict__ c,
+                                                  typename Scal<CPLX>::T *__restrict__ partial)
+{
+    using T = typename Scal<CPLX>::T;
+    const uint32_t m = p.pk_off[wave] + lane;
+    if (m >= p.pk_off[wave + 1]) return;
+    const uint32_t g = p.mem_grp[m];
+    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
+    const uint8_t type = p.grp_type[g];
+    const uint2 me = p.mem[m];
+    const int Xi = me.y & 255;
+    const uint32_t negi = (me.y >> 16) & 1;
+    const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
+    T acc[RC];
+#pragma unroll
+    for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
+    const int nr = min(RC, R - r0);
+    for (uint32_t j = j0; j < j1; j++) {
+        const uint2 o = p.mem[j];
+        const int Xj = o.y & 255;
+        if (Xj == Xi) continue;
+        T v = single_element<CPLX>(p, type, k0, k1, Xi, Xj);
+        v = sc_neg(v, (negi ^ ((o.y >> 16) & 1)) != 0);
+        const T *cj = c + (size_t)o.x * R + r0;
+#pragma unroll
+        for (int k = 0; k < RC; k++)
+            if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
+    }
+    T *out = partial + (size_t)p.mem_slot[m] * R + r0;
+#pragma unroll
+    for (int k = 0; k < RC; k++)
+        if (k < nr) out[k] = acc[k];
+}
+
+template <bool CPLX, int RC>
+__global__ __launch_bounds__(256) void k_group_single(DevPlan p, int R, int r0,
+                                                      const typename Scal<CPLX>::T *__restrict__ c,
+                                                      typename Scal<CPLX>::T *__restrict__ partial)
+{
+    const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= p.npacket) return;
+    group_single_body<CPLX, RC>(p, wave, threadIdx.x & 63, R, r0, c, partial);
+}
+
+// sigma_I = H_II c_I + sum of I's partials.  GL lanes per (I, root); each
+// lane sums a strided subset of the slots, then a fixed butterfly reduces
+// them (deterministic order).
+template <bool CPLX, int GL>
+__device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
+                                            const typename Scal<CPLX>::T *__restrict__ c,
+                                            const typename Scal<CPLX>::T *__restrict__ partial,
+                                            typename Scal<CPLX>::T *__restrict__ sigma)
+{
+    using T = typename Scal<CPLX>::T;
+    const int64_t t = gt / GL;
+    const int sub = (int)(gt % GL);
+    const bool active = t < p.ndet * R;
+    T acc = sc_zero(T());
+    int64_t I = 0;
+    int k = 0;
+    if (active) {
+        I = t / R;
+        k = (int)(t - I * R);
+        const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
+        for (uint32_t s = s0 + sub; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)s * R + k]);
+    }
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) {
+        if constexpr (CPLX) {
+            acc.x += __shfl_xor(acc.x, off, GL);
+            acc.y += __shfl_xor(acc.y, off, GL);
+        } else {
+            acc += __shfl_xor(acc, off, GL);
+        }
+    }
+    if (active && sub == 0) sigma[t] = sc_add(sc_mul(((const T *)p.diag)[I], c[t]), acc);
+}
+
+template <bool CPLX, int GL>
 __global__ __launch_bounds__(256) void k_gather(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ c,
                                                 const typename Scal<CPLX>::T *__restrict__ partial,
                                                 typename Scal<CPLX>::T *__restrict__ sigma)
 {
-    using T = typename Scal<CPLX>::T;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= p.ndet * R) return;
-    int64_t I = t / R;
-    int k = (int)(t - I * R);
-    T acc = sc_mul(((const T *)p.diag)[I], c[t]);
-    const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
-    for (uint32_t s = s0; s < s1; s++) acc = sc_add(acc, partial[(size_t)s * R + k]);
-    sigma[t] = acc;
+    gather_body<CPLX, GL>(p, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, R, c, partial, sigma);
+}
+
+template <bool CPLX, int RC, int U>
+static void launch_double(const DevPlan &p, int R, int r0, const typename Scal<CPLX>::T *c,
+                          typename Scal<CPLX>::T *part, hipStream_t s)
+{
+    unsigned grid = (unsigned)((p.npacket_double + 3) / 4);
+    hipLaunchKernelGGL((k_group_double<CPLX, RC, U>), dim3(grid), dim3(256), 0, s, p, R, r0, c, part);
+}
+
+template <bool CPLX, int RC>
+static void launch_groups(const DevPlan &p, int R, int r0, const typename Scal<CPLX>::T *c,
+                          typename Scal<CPLX>::T *part, hipStream_t s)
+{
+    if (p.npacket_double > 0) {
+        ProfToken t = prof_begin("group_sigma", s);
+        // partner-loop unroll: tunable (mw_autotune)
+        if (p.tune_u <= 4) launch_double<CPLX, RC, 4>(p, R, r0, c, part, s);
+        else if (p.tune_u <= 8 || CPLX) launch_double<CPLX, RC, 8>(p, R, r0, c, part, s);
+        else launch_double<CPLX, RC, 16>(p, R, r0, c, part, s);
+        prof_end(t, s);
+    }
+    const int64_t ns = p.npacket - p.npacket_double;
+    if (ns > 0) {
+        ProfToken t = prof_begin("group_single", s);
+        unsigned grid = (unsigned)((ns + 3) / 4);
+        hipLaunchKernelGGL((k_group_single<CPLX, RC>), dim3(grid), dim3(256), 0, s, p, R, r0, c, part);
+        prof_end(t, s);
+    }
+}
+
+template <bool CPLX, int GL>
+static void launch_gather(const DevPlan &p, int R, const typename Scal<CPLX>::T *c,
+                          const typename Scal<CPLX>::T *part, typename Scal<CPLX>::T *sigma, hipStream_t s)
+{
+    int64_t tot = p.ndet * R * GL;
+    hipLaunchKernelGGL((k_gather<CPLX, GL>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p, R, c, part,
+                       sigma);
 }
 
 template <bool CPLX>
@@ -237,17 +359,17 @@ static mw_status sigma_t(const DevPlan &p, int R, const void *c, void *sigma, hi
     using T = typename Scal<CPLX>::T;
     const T *cc = (const T *)c;
     T *part = (T *)p.partial;
-    if (p.npacket > 0) {
-        unsigned grid = (unsigned)((p.npacket + 3) / 4);
-        for (int r0 = 0; r0 < R; r0 += 4) {
-            int left = R - r0;
-            if (left == 1) hipLaunchKernelGGL((k_group_sigma<CPLX, 1>), dim3(grid), dim3(256), 0, s, p, R, r0, cc, part);
-            else if (left == 2) hipLaunchKernelGGL((k_group_sigma<CPLX, 2>), dim3(grid), dim3(256), 0, s, p, R, r0, cc, part);
-            else hipLaunchKernelGGL((k_group_sigma<CPLX, 4>), dim3(grid), dim3(256), 0, s, p, R, r0, cc, part);
-        }
+    for (int r0 = 0; r0 < R; r0 += 4) {
+        int left = R - r0;
+        if (left == 1) launch_groups<CPLX, 1>(p, R, r0, cc, part, s);
+        else if (left == 2) launch_groups<CPLX, 2>(p, R, r0, cc, part, s);
+        else launch_groups<CPLX, 4>(p, R, r0, cc, part, s);
     }
-    int64_t tot = p.ndet * R;
-    hipLaunchKernelGGL(k_gather<CPLX>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p, R, cc, part, (T *)sigma);
+    ProfToken t = prof_begin("gather", s);
+    if (p.tune_gl <= 8) launch_gather<CPLX, 8>(p, R, cc, part, (T *)sigma, s);
+    else if (p.tune_gl <= 16) launch_gather<CPLX, 16>(p, R, cc, part, (T *)sigma, s);
+    else launch_gather<CPLX, 32>(p, R, cc, part, (T *)sigma, s);
+    prof_end(t, s);
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "sigma kernel launch failed");
     return MW_OK;
 }
@@ -255,6 +377,79 @@ static mw_status sigma_t(const DevPlan &p, int R, const void *c, void *sigma, hi
 mw_status launch_sigma(const DevPlan &p, int R, const void *c, void *sigma, hipStream_t s)
 {
     return p.kind == MW_SPINOR ? sigma_t<true>(p, R, c, sigma, s) : sigma_t<false>(p, R, c, sigma, s);
+}
+
+// ---------------------------------------------------------------------------
+// batched sigma: one persistent launch over the packets of every problem
+// ---------------------------------------------------------------------------
+
+// Waves pull packet indices from one device counter (the dynamic schedule of
+// the paper's OpenMP/MPI task loops, section 3.1.2, as a GPU work queue);
+// problems are ordered by decreasing work and each problem's packets by
+// decreasing group size.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_batched_groups(BatchArgs a)
+{
+    using T = typename Scal<CPLX>::T;
+    const int lane = threadIdx.x & 63;
+    const int64_t total = a.pk_start[a.nprob];
+    for (;;) {
+        uint32_t u = 0;
+        if (lane == 0) u = atomicAdd(a.counter, 1u);
+        u = __shfl(u, 0);
+        if ((int64_t)u >= total) break;
+        int q = 0;
+        while ((int64_t)u >= a.pk_start[q + 1]) q++;
+        const DevPlan &p = *a.plans[q];
+        const int64_t w = (int64_t)u - a.pk_start[q];
+        const int R = a.R[q];
+        const T *c = (const T *)a.c[q];
+        T *part = (T *)p.partial;
+        for (int r0 = 0; r0 < R; r0 += 4) {
+            if (w < p.npacket_double) group_double_body<CPLX, 4, CPLX ? 4 : 8>(p, w, lane, R, r0, c, part);
+            else group_single_body<CPLX, 4>(p, w, lane, R, r0, c, part);
+        }
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_batched_gather(BatchArgs a)
+{
+    using T = typename Scal<CPLX>::T;
+    constexpr int GL = 16;
+    const int64_t total = a.det_start[a.nprob];
+    // every thread of a block runs the same number of rounds, so the GL-lane
+    // butterflies inside gather_body always see complete groups
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t gt = base + threadIdx.x;
+        const int64_t g = gt < total ? gt : total - 1;
+        int q = 0;
+        while (g >= a.det_start[q + 1]) q++;
+        const DevPlan &p = *a.plans[q];
+        // past the end: an index whose determinant is out of range (inactive)
+        const int64_t local = gt < total ? gt - a.det_start[q] : p.ndet * a.R[q] * GL;
+        gather_body<CPLX, GL>(p, local, a.R[q], (const T *)a.c[q], (const T *)p.partial, (T *)a.sigma[q]);
+    }
+}
+
+__global__ void k_reset_counter(uint32_t *ctr) { *ctr = 0u; }
+
+mw_status launch_batched(const BatchArgs &a, bool cplx, int blocks, hipStream_t s, bool timing)
+{
+    if (a.nprob == 0) return MW_OK;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.counter);
+    ProfToken t = timing ? prof_begin("batched_groups", s) : ProfToken{nullptr, nullptr, ""};
+    if (cplx) hipLaunchKernelGGL(k_batched_groups<true>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_batched_groups<false>, dim3(blocks), dim3(256), 0, s, a);
+    prof_end(t, s);
+    if (timing) t = prof_begin("batched_gather", s);
+    const int64_t tot = a.det_start[a.nprob];
+    const unsigned gg = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+    if (cplx) hipLaunchKernelGGL(k_batched_gather<true>, dim3(gg), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_batched_gather<false>, dim3(gg), dim3(256), 0, s, a);
+    prof_end(t, s);
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "batched launch failed");
+    return MW_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -58,14 +58,44 @@ struct DevPlan {
     const void *w_opp;         // spin-free only: [r][p][q] (pq|rr)
     const void *g_ab;          // spin-free only: [q][s][p][r] = (pq|rs)
     const void *a_pair;        // antisymmetrised pairs [x][y] = (X0 Y0|X1 Y1) - (X0 Y1|X1 Y0)
-    void *partial;             // [nmem][max_roots] scalar scratch
+    const void *f_ref;         // F^omega (spin-free [2][n][n] by spin of the group; spinor [M][M])
+    uint64_t ref0, ref1;       // reference string omega
+    int64_t npacket_double;    // packets [0, npacket_double) hold double groups
+    void *partial;             // [nmem][max_roots] scalar scratch (also RDM accumulators)
+    size_t scratch_bytes;
+    DevPlan *self;             // device copy of this struct (for batched launches)
+    uint32_t *counter;         // device work counter (batched launches)
+    int32_t tune_u, tune_gl;   // tuned partner-loop unroll and gather lanes
 };
 
 struct HostPlan;
 
+// arguments of one batched launch (at most MW_MAXB problems)
+constexpr int MW_MAXB = 32;
+struct BatchArgs {
+    int nprob;
+    const DevPlan *plans[MW_MAXB];   // device copies
+    const void *c[MW_MAXB];
+    void *sigma[MW_MAXB];
+    int R[MW_MAXB];
+    int64_t pk_start[MW_MAXB + 1];   // packet prefix over problems
+    int64_t det_start[MW_MAXB + 1];  // gather-thread prefix over problems
+    uint32_t *counter;
+};
+mw_status launch_batched(const BatchArgs &a, bool cplx, int blocks, hipStream_t s, bool timing);
+
 // host side helpers (plan.cpp)
 void set_error(const std::string &msg);
 mw_status fail(mw_status st, const std::string &msg);
+
+// optional event timing around launches (profile.cpp)
+struct ProfToken {
+    hipEvent_t a, b;
+    const char *name;
+};
+bool prof_enabled();
+ProfToken prof_begin(const char *name, hipStream_t s);
+void prof_end(const ProfToken &t, hipStream_t s);
 
 // kernel launchers (kernels.hip)
 mw_status launch_diag(const DevPlan &p, hipStream_t s);

@@ -115,7 +115,10 @@ struct HostPlan {
     std::vector<uint8_t> grp_type;
     std::vector<uint2> mem;
     std::vector<uint32_t> mem_grp, mem_slot, pk_off, rowptr;
-    std::vector<double> h, w_same, w_opp, g_ab, a_pair;
+    std::vector<double> h, w_same, w_opp, g_ab, a_pair, f_ref;
+    uint64_t ref0 = 0, ref1 = 0;
+    int64_t npacket_double = 0;
+    int32_t tune_u = 8, tune_gl = 16;
     int64_t n_single_pairs = 0, n_double_pairs = 0, n_evals = 0;
     // device binding
     void *ws = nullptr;
@@ -129,6 +132,66 @@ struct HostPlan {
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
+
+// integral symmetry: h Hermitian, (PQ|RS) = (RS|PQ) = conj((QP|SR)); real
+// problems 8-fold; all to 1e-12 relative to the largest element
+static mw_status validate_integrals(int kind, int n, const double *hin, const double *gin)
+{
+    if (!hin || !gin) return fail(MW_EINVAL, "h and g must be host pointers");
+    if (kind == MW_SPIN_FREE) {
+        const double *h = hin, *g = gin;
+        double hmax = 0, gmax = 0;
+        for (int i = 0; i < n * n; i++) hmax = std::max(hmax, std::fabs(h[i]));
+        const size_t n4 = (size_t)n * n * n * n;
+        for (size_t i = 0; i < n4; i++) gmax = std::max(gmax, std::fabs(g[i]));
+        double th = 1e-12 * std::max(hmax, 1e-300), tg = 1e-12 * std::max(gmax, 1e-300);
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++)
+                if (std::fabs(h[a * n + b] - h[b * n + a]) > th)
+                    return fail(MW_ESYM, "h is not symmetric");
+        std::atomic<bool> bad{false};
+        parallel_for(n, [&](int64_t b0, int64_t b1, unsigned) {
+            for (int64_t P = b0; P < b1 && !bad; P++)
+                for (int Q = 0; Q < n; Q++)
+                    for (int R = 0; R < n; R++)
+                        for (int S = 0; S < n; S++) {
+                            auto G = [&](int a, int b, int c, int e) { return g[(((size_t)a * n + b) * n + c) * n + e]; };
+                            double v = G(P, Q, R, S);
+                            if (std::fabs(v - G(Q, P, R, S)) > tg || std::fabs(v - G(P, Q, S, R)) > tg ||
+                                std::fabs(v - G(R, S, P, Q)) > tg)
+                                bad = true;
+                        }
+        });
+        if (bad) return fail(MW_ESYM, "g lacks the real 8-fold permutation symmetry");
+    } else {
+        const int Mm = 2 * n;
+        const std::complex<double> *h = reinterpret_cast<const std::complex<double> *>(hin);
+        const std::complex<double> *g = reinterpret_cast<const std::complex<double> *>(gin);
+        double hmax = 0, gmax = 0;
+        for (int i = 0; i < Mm * Mm; i++) hmax = std::max(hmax, std::abs(h[i]));
+        const size_t m4 = (size_t)Mm * Mm * Mm * Mm;
+        for (size_t i = 0; i < m4; i++) gmax = std::max(gmax, std::abs(g[i]));
+        double th = 1e-12 * std::max(hmax, 1e-300), tg = 1e-12 * std::max(gmax, 1e-300);
+        for (int a = 0; a < Mm; a++)
+            for (int b = 0; b < Mm; b++)
+                if (std::abs(h[a * Mm + b] - std::conj(h[b * Mm + a])) > th)
+                    return fail(MW_ESYM, "h is not Hermitian");
+        std::atomic<bool> bad{false};
+        parallel_for(Mm, [&](int64_t b0, int64_t b1, unsigned) {
+            for (int64_t P = b0; P < b1 && !bad; P++)
+                for (int Q = 0; Q < Mm; Q++)
+                    for (int R = 0; R < Mm; R++)
+                        for (int S = 0; S < Mm; S++) {
+                            auto G = [&](int a, int b, int c, int e) { return g[(((size_t)a * Mm + b) * Mm + c) * Mm + e]; };
+                            std::complex<double> v = G(P, Q, R, S);
+                            if (std::abs(v - G(R, S, P, Q)) > tg || std::abs(v - std::conj(G(Q, P, S, R))) > tg)
+                                bad = true;
+                        }
+        });
+        if (bad) return fail(MW_ESYM, "g lacks (PQ|RS) = (RS|PQ) = conj((QP|SR))");
+    }
+    return MW_OK;
+}
 
 static mw_status validate(const mw_problem *p, int32_t max_roots)
 {
@@ -161,60 +224,7 @@ static mw_status validate(const mw_problem *p, int32_t max_roots)
                 return fail(MW_ENOTSORTED, "determinants not strictly ascending at index " + std::to_string(i));
         }
     }
-    // integral symmetry
-    if (p->kind == MW_SPIN_FREE) {
-        const double *h = p->h, *g = p->g;
-        double hmax = 0, gmax = 0;
-        for (int i = 0; i < n * n; i++) hmax = std::max(hmax, std::fabs(h[i]));
-        const size_t n4 = (size_t)n * n * n * n;
-        for (size_t i = 0; i < n4; i++) gmax = std::max(gmax, std::fabs(g[i]));
-        double th = 1e-12 * std::max(hmax, 1e-300), tg = 1e-12 * std::max(gmax, 1e-300);
-        for (int a = 0; a < n; a++)
-            for (int b = 0; b < n; b++)
-                if (std::fabs(h[a * n + b] - h[b * n + a]) > th)
-                    return fail(MW_ESYM, "h is not symmetric");
-        std::atomic<bool> bad{false};
-        parallel_for(n, [&](int64_t b0, int64_t b1, unsigned) {
-            for (int64_t P = b0; P < b1 && !bad; P++)
-                for (int Q = 0; Q < n; Q++)
-                    for (int R = 0; R < n; R++)
-                        for (int S = 0; S < n; S++) {
-                            auto G = [&](int a, int b, int c, int e) { return g[(((size_t)a * n + b) * n + c) * n + e]; };
-                            double v = G(P, Q, R, S);
-                            if (std::fabs(v - G(Q, P, R, S)) > tg || std::fabs(v - G(P, Q, S, R)) > tg ||
-                                std::fabs(v - G(R, S, P, Q)) > tg)
-                                bad = true;
-                        }
-        });
-        if (bad) return fail(MW_ESYM, "g lacks the real 8-fold permutation symmetry");
-    } else {
-        const int Mm = 2 * n;
-        const std::complex<double> *h = reinterpret_cast<const std::complex<double> *>(p->h);
-        const std::complex<double> *g = reinterpret_cast<const std::complex<double> *>(p->g);
-        double hmax = 0, gmax = 0;
-        for (int i = 0; i < Mm * Mm; i++) hmax = std::max(hmax, std::abs(h[i]));
-        const size_t m4 = (size_t)Mm * Mm * Mm * Mm;
-        for (size_t i = 0; i < m4; i++) gmax = std::max(gmax, std::abs(g[i]));
-        double th = 1e-12 * std::max(hmax, 1e-300), tg = 1e-12 * std::max(gmax, 1e-300);
-        for (int a = 0; a < Mm; a++)
-            for (int b = 0; b < Mm; b++)
-                if (std::abs(h[a * Mm + b] - std::conj(h[b * Mm + a])) > th)
-                    return fail(MW_ESYM, "h is not Hermitian");
-        std::atomic<bool> bad{false};
-        parallel_for(Mm, [&](int64_t b0, int64_t b1, unsigned) {
-            for (int64_t P = b0; P < b1 && !bad; P++)
-                for (int Q = 0; Q < Mm; Q++)
-                    for (int R = 0; R < Mm; R++)
-                        for (int S = 0; S < Mm; S++) {
-                            auto G = [&](int a, int b, int c, int e) { return g[(((size_t)a * Mm + b) * Mm + c) * Mm + e]; };
-                            std::complex<double> v = G(P, Q, R, S);
-                            if (std::abs(v - G(R, S, P, Q)) > tg || std::abs(v - std::conj(G(Q, P, S, R))) > tg)
-                                bad = true;
-                        }
-        });
-        if (bad) return fail(MW_ESYM, "g lacks (PQ|RS) = (RS|PQ) = conj((QP|SR))");
-    }
-    return MW_OK;
+    return validate_integrals(p->kind, n, p->h, p->g);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,9 +352,15 @@ static mw_status build_groups(HostPlan &P)
     for (auto &r : runs) all.insert(all.end(), r.begin(), r.end());
     runs.clear();
     runs.shrink_to_fit();
-    // largest groups first (longest-processing-time order); ties keep the
-    // deterministic partition/key order
-    std::stable_sort(all.begin(), all.end(), [](const Run &a, const Run &b) { return a.len > b.len; });
+    // double groups before single groups, largest first within each class
+    // (longest-processing-time order); ties keep the deterministic
+    // partition/key order
+    auto is_single = [&](const Run &r) { return (ent[r.start].pos >> 8) == 255; };
+    std::stable_sort(all.begin(), all.end(), [&](const Run &a, const Run &b) {
+        bool sa = is_single(a), sb = is_single(b);
+        if (sa != sb) return !sa;
+        return a.len > b.len;
+    });
 
     const int64_t ngroup = (int64_t)all.size();
     P.grp_off.resize(ngroup + 1);
@@ -417,10 +433,21 @@ static mw_status build_groups(HostPlan &P)
     // 64, small groups are packed whole
     P.pk_off.clear();
     P.pk_off.push_back(0);
+    P.npacket_double = 0;
     {
         uint32_t cur_start = 0, cur_cnt = 0;
+        bool in_single = false;
         for (int64_t gi = 0; gi < ngroup; gi++) {
             uint32_t k = all[gi].len, s = P.grp_off[gi];
+            const uint8_t ty = P.grp_type[gi];
+            if (!in_single && (ty == G_SINGLE_A || ty == G_SINGLE_B || ty == G_SINGLE_S)) {
+                in_single = true;
+                // class boundary: close the open packet; packets before this
+                // point hold double groups only
+                if (cur_cnt) { P.pk_off.push_back(cur_start + cur_cnt); cur_cnt = 0; }
+                P.npacket_double = (int64_t)P.pk_off.size() - 1;
+                cur_start = s;
+            }
             if (k >= 64) {
                 if (cur_cnt) { P.pk_off.push_back(cur_start + cur_cnt); cur_cnt = 0; }
                 for (uint32_t c = 0; c < k; c += 64) P.pk_off.push_back(s + std::min<uint32_t>(k, c + 64));
@@ -432,6 +459,7 @@ static mw_status build_groups(HostPlan &P)
             }
         }
         if (cur_cnt) P.pk_off.push_back(cur_start + cur_cnt);
+        if (!in_single) P.npacket_double = (int64_t)P.pk_off.size() - 1;
     }
     // determinant-major slots
     P.rowptr.assign(N + 1, 0);
@@ -515,6 +543,55 @@ static void repack(HostPlan &P, const mw_problem *p)
     }
 }
 
+// Reference string omega for single elements (the closed-shell reference
+// idea of section 2.3): every position occupied in more than half of the
+// determinants.  F^omega = h + sum_{R in omega} [(PQ|RR) - (PR|RQ)] is
+// tabulated once; a single group with string K then needs only the
+// positions where K and omega differ:
+//   F^K = F^omega + sum_{R in K\omega} w_R - sum_{R in omega\K} w_R.
+static void reference(HostPlan &P)
+{
+    const int n = P.n;
+    std::vector<int64_t> cnt(2 * 64, 0);
+    for (int64_t i = 0; i < P.ndet; i++)
+        for (int w = 0; w < 2; w++)
+            for (uint64_t x = P.dets[2 * i + w]; x; x &= x - 1) cnt[w * 64 + __builtin_ctzll(x)]++;
+    P.ref0 = P.ref1 = 0;
+    for (int b = 0; b < n; b++) {
+        if (2 * cnt[b] > P.ndet) P.ref0 |= 1ULL << b;
+        if (2 * cnt[64 + b] > P.ndet) P.ref1 |= 1ULL << b;
+    }
+    if (P.kind == MW_SPIN_FREE) {
+        // f_ref[s][p][q]: s = 0 for alpha single groups, 1 for beta
+        P.f_ref.assign(2 * (size_t)n * n, 0.0);
+        for (int s = 0; s < 2; s++) {
+            uint64_t same = s == 0 ? P.ref0 : P.ref1, opp = s == 0 ? P.ref1 : P.ref0;
+            for (int a = 0; a < n; a++)
+                for (int b = 0; b < n; b++) {
+                    double f = P.h[(size_t)a * n + b];
+                    for (uint64_t x = same; x; x &= x - 1) f += P.w_same[((size_t)__builtin_ctzll(x) * n + a) * n + b];
+                    for (uint64_t x = opp; x; x &= x - 1) f += P.w_opp[((size_t)__builtin_ctzll(x) * n + a) * n + b];
+                    P.f_ref[((size_t)s * n + a) * n + b] = f;
+                }
+        }
+    } else {
+        const int Mm = 2 * n;
+        P.f_ref.assign(2 * (size_t)Mm * Mm, 0.0);
+        for (int a = 0; a < Mm; a++)
+            for (int b = 0; b < Mm; b++) {
+                double re = P.h[2 * ((size_t)a * Mm + b)], im = P.h[2 * ((size_t)a * Mm + b) + 1];
+                for (int w = 0; w < 2; w++)
+                    for (uint64_t x = w ? P.ref1 : P.ref0; x; x &= x - 1) {
+                        size_t k = ((size_t)(w * n + __builtin_ctzll(x)) * Mm + a) * Mm + b;
+                        re += P.w_same[2 * k];
+                        im += P.w_same[2 * k + 1];
+                    }
+                P.f_ref[2 * ((size_t)a * Mm + b)] = re;
+                P.f_ref[2 * ((size_t)a * Mm + b) + 1] = im;
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
@@ -550,7 +627,20 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.w_opp = (const void *)take(w_opp.size() * 8);
     t.g_ab = (const void *)take(g_ab.size() * 8);
     t.a_pair = (const void *)take(a_pair.size() * 8);
-    t.partial = (void *)take(std::max<size_t>(1, mem.size()) * (size_t)max_roots * sb);
+    t.f_ref = (const void *)take(f_ref.size() * 8);
+    t.ref0 = ref0;
+    t.ref1 = ref1;
+    t.npacket_double = npacket_double;
+    // per-call scratch: sigma partials, or the density-matrix accumulators
+    size_t rdm_bytes = kind == MW_SPIN_FREE
+                           ? ((size_t)n * n * n * n + (size_t)npair * npair + 2 * (size_t)n * n) * 8
+                           : ((size_t)npair * npair + (size_t)M * M) * 16;
+    t.scratch_bytes = std::max(std::max<size_t>(1, mem.size()) * (size_t)max_roots * sb, rdm_bytes);
+    t.partial = (void *)take(t.scratch_bytes);
+    t.self = (DevPlan *)take(sizeof(DevPlan));
+    t.counter = (uint32_t *)take(256);
+    t.tune_u = tune_u;
+    t.tune_gl = tune_gl;
     if (d) *d = t;
     return off + 256;
 }
@@ -562,6 +652,8 @@ using namespace mw;
 struct mw_plan_s {
     HostPlan p;
 };
+
+void mw_internal_batched_forget(mw_plan plan);
 
 extern "C" {
 
@@ -590,6 +682,7 @@ mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out
         st = build_groups(P);
         if (st != MW_OK) return st;
         repack(P, prob);
+        reference(P);
     } catch (const std::bad_alloc &) {
         return fail(MW_EUNSUPPORTED, "host memory exhausted while building the plan");
     } catch (const std::exception &e) {
@@ -609,6 +702,7 @@ mw_status mw_plan_workspace_bytes(mw_plan plan, size_t *bytes)
 mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_t stream)
 {
     if (!plan || !workspace) return fail(MW_EINVAL, "NULL argument");
+    mw_internal_batched_forget(plan);
     HostPlan &P = plan->p;
     size_t need = P.layout(nullptr, nullptr);
     if (bytes < need) return fail(MW_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -633,8 +727,11 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
               up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) &&
               up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
-              up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8);
+              up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) &&
+              up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
+    if (hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
     mw_status st = launch_diag(d, s);
     if (st != MW_OK) return st;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "hipStreamSynchronize failed after upload");
@@ -645,8 +742,46 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
     return MW_OK;
 }
 
+mw_status mw_plan_update_integrals(mw_plan plan, const double *h, const double *g, double ecore, mw_stream_t stream)
+{
+    if (!plan) return fail(MW_EINVAL, "plan is NULL");
+    HostPlan &P = plan->p;
+    if (!P.bound) return fail(MW_EWORKSPACE, "plan has no workspace: call mw_plan_upload first");
+    mw_status st = validate_integrals(P.kind, P.n, h, g);
+    if (st != MW_OK) return st;
+    mw_problem q{};
+    q.kind = P.kind;
+    q.norb = P.n;
+    q.h = h;
+    q.g = g;
+    try {
+        repack(P, &q);
+        reference(P);
+    } catch (const std::bad_alloc &) {
+        return fail(MW_EUNSUPPORTED, "host memory exhausted while repacking integrals");
+    }
+    P.ecore = ecore;
+    P.dev.ecore = ecore;
+    const DevPlan &d = P.dev;
+    hipStream_t s = (hipStream_t)stream;
+    auto up = [&](const void *dst, const void *src, size_t nb) -> bool {
+        if (!nb) return true;
+        return hipMemcpyAsync((void *)dst, src, nb, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool ok = up(d.h, P.h.data(), P.h.size() * 8) && up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
+              up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) && up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
+              up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) && up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
+              up(d.self, &P.dev, sizeof(DevPlan));
+    if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during integral update");
+    st = launch_diag(d, s);
+    if (st != MW_OK) return st;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "hipStreamSynchronize failed");
+    return MW_OK;
+}
+
 mw_status mw_plan_destroy(mw_plan plan)
 {
+    if (plan) mw_internal_batched_forget(plan);
     delete plan;
     return MW_OK;
 }
@@ -668,15 +803,27 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     case 9: return P.n;
     case 10: return P.kind;
     case 11: return (int64_t)P.pk_off.size() - 1;
+    case 12: return P.npacket_double;
     default: return -1;
     }
 }
 
-// accessor for the other translation units
-const mw::DevPlan *mw_internal_devplan(mw_plan plan)
+// accessors for the other translation units (not exported)
+__attribute__((visibility("hidden"))) const mw::DevPlan *mw_internal_devplan(mw_plan plan)
 {
     if (!plan || !plan->p.bound) return nullptr;
     return &plan->p.dev;
+}
+
+// set the tunables (host copy; the device copy keeps the upload values,
+// which only the batched kernels read and they do not use these fields)
+__attribute__((visibility("hidden"))) void mw_internal_set_tune(mw_plan plan, int32_t u, int32_t gl)
+{
+    if (!plan) return;
+    plan->p.tune_u = u;
+    plan->p.tune_gl = gl;
+    plan->p.dev.tune_u = u;
+    plan->p.dev.tune_gl = gl;
 }
 
 }  // extern "C"

@@ -1,0 +1,356 @@
+// Transition one- and two-particle density matrices: the adjoint of sigma
+// with respect to the integrals (E = sum h gamma + 1/2 sum g Gamma for the
+// Hamiltonian of section 2.1).  The connectivity is recomputed from the same
+// groups as sigma, never stored.
+//
+// Every ordered pair (I, J) connected inside a group contributes
+// w_IJ = phi_I phi_J sum_k w_k conj(bra_Ik) ket_Jk:
+//  double group, I adds (P<R), J adds (Q<S):  Gamma_PQRS += w, Gamma_RSPQ += w,
+//      Gamma_PSRQ -= w, Gamma_RQPS -= w.  One device atomic per pair goes to
+//      an accumulator (spin-free alpha-beta: a full [n]^4 array G_ab; same
+//      spin and spinor: the antisymmetric pair matrix D[(P,R)][(Q,S)]); a
+//      final pass expands it into Gamma.
+//  single group, I adds P, J adds Q (K the common N-1 string):
+//      gamma_PQ += w and, for every X in K, Gamma_PQXX += w, Gamma_XXPQ += w,
+//      Gamma_PXXQ -= w, Gamma_XQPX -= w (spin-free: the exchange-like two
+//      only for X of the spin of P).  The sum over K is split into the
+//      reference string omega (applied once at the end through the
+//      accumulated S_PQ = sum of w) plus the few positions where K and omega
+//      differ (direct atomics).
+//  diagonal I = J: gamma_PP += w, Gamma_PPRR += w, Gamma_PRRP -= w (P != R).
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "mw_internal.h"
+
+namespace mw {
+
+struct RdmWeights {
+    double w[64];
+};
+
+template <bool CPLX>
+__device__ __forceinline__ typename Scal<CPLX>::T pair_weight(const typename Scal<CPLX>::T *bra,
+                                                              const typename Scal<CPLX>::T *ket, int R, uint32_t I,
+                                                              uint32_t J, const RdmWeights &W)
+{
+    using T = typename Scal<CPLX>::T;
+    T s = sc_zero(T());
+    for (int k = 0; k < R; k++) {
+        T t = sc_mul(sc_conj(bra[(size_t)I * R + k]), ket[(size_t)J * R + k]);
+        if constexpr (CPLX) s = make_double2(s.x + W.w[k] * t.x, s.y + W.w[k] * t.y);
+        else s += W.w[k] * t;
+    }
+    return s;
+}
+
+__device__ __forceinline__ void atom_add(double *a, double v) { atomicAdd(a, v); }
+__device__ __forceinline__ void atom_add(double2 *a, double2 v)
+{
+    atomicAdd(&a->x, v.x);
+    atomicAdd(&a->y, v.y);
+}
+
+// output index of Gamma_ABCD (spin-free: spatial orbitals, spin-summed)
+__device__ __forceinline__ size_t g4(int m, int a, int b, int c, int d)
+{
+    return (((size_t)a * m + b) * m + c) * m + d;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
+                                                    const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
+                                                    double *__restrict__ gab, typename Scal<CPLX>::T *__restrict__ D)
+{
+    using T = typename Scal<CPLX>::T;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= p.npacket_double) return;
+    const uint32_t m = p.pk_off[wave] + lane;
+    if (m >= p.pk_off[wave + 1]) return;
+    const uint32_t g = p.mem_grp[m];
+    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
+    const uint8_t type = p.grp_type[g];
+    const uint2 me = p.mem[m];
+    const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
+    const uint32_t negi = (me.y >> 16) & 1;
+    const int n = p.n;
+    for (uint32_t j = j0; j < j1; j++) {
+        const uint2 o = p.mem[j];
+        const int Xj = o.y & 255, Yj = (o.y >> 8) & 255;
+        if (Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi) continue;
+        T w = pair_weight<CPLX>(bra, ket, R, me.x, o.x, W);
+        w = sc_neg(w, (negi ^ ((o.y >> 16) & 1)) != 0);
+        if constexpr (!CPLX) {
+            if (type == G_AB) {
+                atomicAdd(&gab[g4(n, Xi, Xj, Yi - n, Yj - n)], w);
+                continue;
+            }
+            const int off = type == G_BB ? n : 0;
+            atomicAdd(&D[(size_t)pair_idx(Xi - off, Yi - off) * p.npair + pair_idx(Xj - off, Yj - off)], w);
+        } else {
+            atom_add(&D[(size_t)pair_idx(Xi, Yi) * p.npair + pair_idx(Xj, Yj)], w);
+        }
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
+                                                    const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
+                                                    typename Scal<CPLX>::T *__restrict__ S,
+                                                    typename Scal<CPLX>::T *__restrict__ Gam)
+{
+    using T = typename Scal<CPLX>::T;
+    const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= p.npacket) return;
+    const uint32_t m = p.pk_off[wave] + lane;
+    if (m >= p.pk_off[wave + 1]) return;
+    const uint32_t g = p.mem_grp[m];
+    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
+    const uint8_t type = p.grp_type[g];
+    const uint2 me = p.mem[m];
+    const int Xi = me.y & 255;
+    const uint32_t negi = (me.y >> 16) & 1;
+    const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
+    const int n = p.n;
+    for (uint32_t j = j0; j < j1; j++) {
+        const uint2 o = p.mem[j];
+        const int Xj = o.y & 255;
+        if (Xj == Xi) continue;
+        T w = pair_weight<CPLX>(bra, ket, R, me.x, o.x, W);
+        w = sc_neg(w, (negi ^ ((o.y >> 16) & 1)) != 0);
+        if constexpr (!CPLX) {
+            const int s = type == G_SINGLE_A ? 0 : 1;
+            const int pp = Xi - s * n, qq = Xj - s * n;
+            atomicAdd(&S[((size_t)s * n + pp) * n + qq], w);
+            // positions where K and omega differ: words (same spin, other spin)
+            for (int part = 0; part < 4; part++) {
+                const bool same = part < 2;
+                const uint64_t kw = (same == (s == 0)) ? k0 : k1;
+                const uint64_t rw = (same == (s == 0)) ? p.ref0 : p.ref1;
+                const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
+                const double sw = (part & 1) ? -w : w;
+                for (uint64_t x = bits; x; x &= x - 1) {
+                    const int xx = __builtin_ctzll(x);
+                    atomicAdd(&Gam[g4(n, pp, qq, xx, xx)], sw);
+                    atomicAdd(&Gam[g4(n, xx, xx, pp, qq)], sw);
+                    if (same) {
+                        atomicAdd(&Gam[g4(n, pp, xx, xx, qq)], -sw);
+                        atomicAdd(&Gam[g4(n, xx, qq, pp, xx)], -sw);
+                    }
+                }
+            }
+        } else {
+            const int M = p.M;
+            atom_add(&S[(size_t)Xi * M + Xj], w);
+            for (int part = 0; part < 4; part++) {
+                const uint64_t kw = (part < 2) ? k0 : k1;
+                const uint64_t rw = (part < 2) ? p.ref0 : p.ref1;
+                const int base = (part < 2) ? 0 : n;
+                const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
+                const T sw = sc_neg(w, (part & 1) != 0);
+                const T nsw = sc_neg(sw, true);
+                for (uint64_t x = bits; x; x &= x - 1) {
+                    const int X = base + __builtin_ctzll(x);
+                    atom_add(&Gam[g4(M, Xi, Xj, X, X)], sw);
+                    atom_add(&Gam[g4(M, X, X, Xi, Xj)], sw);
+                    atom_add(&Gam[g4(M, Xi, X, X, Xj)], nsw);
+                    atom_add(&Gam[g4(M, X, Xj, Xi, X)], nsw);
+                }
+            }
+        }
+    }
+}
+
+// Diagonal, spin-free: per block, Gamma_pprr and Gamma_prrp contributions are
+// accumulated in LDS (n <= 64: two n x n arrays of doubles), then flushed.
+__global__ __launch_bounds__(256) void k_rdm_diag_sf(DevPlan p, int R, const double *__restrict__ bra,
+                                                     const double *__restrict__ ket, RdmWeights W,
+                                                     double *__restrict__ gam, double *__restrict__ Gam)
+{
+    extern __shared__ double lds[];
+    const int n = p.n;
+    double *o1 = lds, *o2 = lds + n * n;
+    for (int t = threadIdx.x; t < 2 * n * n; t += blockDim.x) lds[t] = 0.0;
+    __syncthreads();
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < p.ndet) {
+        const double w = pair_weight<false>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
+        const uint64_t d[2] = {p.dets[2 * I], p.dets[2 * I + 1]};
+        for (int sa = 0; sa < 2; sa++)
+            for (uint64_t xa = d[sa]; xa; xa &= xa - 1) {
+                const int a = __builtin_ctzll(xa);
+                atomicAdd(&gam[(size_t)a * n + a], w);
+                for (int sb = 0; sb < 2; sb++)
+                    for (uint64_t xb = d[sb]; xb; xb &= xb - 1) {
+                        const int b = __builtin_ctzll(xb);
+                        if (sa == sb && a == b) continue;
+                        atomicAdd(&o1[a * n + b], w);
+                        if (sa == sb) atomicAdd(&o2[a * n + b], w);
+                    }
+            }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        const int a = t / n, b = t % n;
+        if (o1[t] != 0.0) atomicAdd(&Gam[g4(n, a, a, b, b)], o1[t]);
+        if (o2[t] != 0.0) atomicAdd(&Gam[g4(n, a, b, b, a)], -o2[t]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rdm_diag_spinor(DevPlan p, int R, const double2 *__restrict__ bra,
+                                                         const double2 *__restrict__ ket, RdmWeights W,
+                                                         double2 *__restrict__ gam, double2 *__restrict__ Gam)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= p.ndet) return;
+    const int n = p.n, M = p.M;
+    const double2 w = pair_weight<true>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
+    const double2 nw = make_double2(-w.x, -w.y);
+    const uint64_t d[2] = {p.dets[2 * I], p.dets[2 * I + 1]};
+    for (int sa = 0; sa < 2; sa++)
+        for (uint64_t xa = d[sa]; xa; xa &= xa - 1) {
+            const int A = sa * n + __builtin_ctzll(xa);
+            atom_add(&gam[(size_t)A * M + A], w);
+            for (int sb = 0; sb < 2; sb++)
+                for (uint64_t xb = d[sb]; xb; xb &= xb - 1) {
+                    const int B = sb * n + __builtin_ctzll(xb);
+                    if (A == B) continue;
+                    atom_add(&Gam[g4(M, A, A, B, B)], w);
+                    atom_add(&Gam[g4(M, A, B, B, A)], nw);
+                }
+        }
+}
+
+// D-term of Gamma_abcd from the antisymmetric pair accumulator
+template <typename T>
+__device__ __forceinline__ T d_term(const T *D, int np, int a, int b, int c, int d)
+{
+    if (a == c || b == d) return sc_zero(T());
+    if (a < c) {
+        if (b < d) return D[(size_t)pair_idx(a, c) * np + pair_idx(b, d)];
+        return sc_neg(D[(size_t)pair_idx(a, c) * np + pair_idx(d, b)], true);
+    }
+    if (d < b) return D[(size_t)pair_idx(c, a) * np + pair_idx(d, b)];
+    return sc_neg(D[(size_t)pair_idx(c, a) * np + pair_idx(b, d)], true);
+}
+
+__global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double *__restrict__ gab,
+                                                         const double *__restrict__ D, const double *__restrict__ S,
+                                                         double *__restrict__ gam, double *__restrict__ Gam)
+{
+    const int n = p.n;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n4 = (int64_t)n * n * n * n;
+    if (t >= n4) return;
+    const int dd = t % n, c = (t / n) % n, b = (t / n / n) % n, a = (int)(t / n / n / n);
+    double v = Gam[t] + gab[t] + gab[g4(n, c, dd, a, b)] + d_term(D, p.npair, a, b, c, dd);
+    const double *S0 = S, *S1 = S + (size_t)n * n;
+    auto occ = [&](uint64_t w, int x) { return (double)((w >> x) & 1); };
+    if (c == dd) v += (S0[a * n + b] + S1[a * n + b]) * (occ(p.ref0, c) + occ(p.ref1, c));
+    if (a == b) v += (S0[c * n + dd] + S1[c * n + dd]) * (occ(p.ref0, a) + occ(p.ref1, a));
+    if (b == c) v -= S0[a * n + dd] * occ(p.ref0, b) + S1[a * n + dd] * occ(p.ref1, b);
+    if (a == dd) v -= S0[c * n + b] * occ(p.ref0, a) + S1[c * n + b] * occ(p.ref1, a);
+    Gam[t] = v;
+    if (t < (int64_t)n * n) gam[t] += S0[t] + S1[t];
+}
+
+__global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const double2 *__restrict__ D,
+                                                             const double2 *__restrict__ S,
+                                                             double2 *__restrict__ gam, double2 *__restrict__ Gam)
+{
+    const int M = p.M, n = p.n;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m4 = (int64_t)M * M * M * M;
+    if (t >= m4) return;
+    const int dd = t % M, c = (t / M) % M, b = (t / M / M) % M, a = (int)(t / M / M / M);
+    double2 v = sc_add(Gam[t], d_term(D, p.npair, a, b, c, dd));
+    auto inref = [&](int X) { return X < n ? ((p.ref0 >> X) & 1) : ((p.ref1 >> (X - n)) & 1); };
+    if (c == dd && inref(c)) v = sc_add(v, S[(size_t)a * M + b]);
+    if (a == b && inref(a)) v = sc_add(v, S[(size_t)c * M + dd]);
+    if (b == c && inref(b)) v = sc_add(v, sc_neg(S[(size_t)a * M + dd], true));
+    if (a == dd && inref(a)) v = sc_add(v, sc_neg(S[(size_t)c * M + b], true));
+    Gam[t] = v;
+    if (t < (int64_t)M * M) gam[t] = sc_add(gam[t], S[t]);
+}
+
+__global__ void k_zero(double *x, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        x[t] = 0.0;
+}
+
+static void zero(double *x, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, x, n);
+}
+
+mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, const double *weights, void *gamma,
+                     void *Gamma, hipStream_t s)
+{
+    RdmWeights W;
+    for (int k = 0; k < 64; k++) W.w[k] = (weights && k < R) ? weights[k] : 1.0;
+    const int n = p.n, M = p.M;
+    const unsigned gd = (unsigned)((p.npacket_double + 3) / 4);
+    const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
+    const unsigned gdet = (unsigned)((p.ndet + 255) / 256);
+    if (p.kind == MW_SPIN_FREE) {
+        const int64_t n4 = (int64_t)n * n * n * n, np2 = (int64_t)p.npair * p.npair;
+        double *gab = (double *)p.partial, *D = gab + n4, *S = D + np2;
+        zero(gab, n4 + np2 + 2 * (int64_t)n * n, s);
+        zero((double *)gamma, (int64_t)n * n, s);
+        zero((double *)Gamma, n4, s);
+        ProfToken t = prof_begin("rdm_groups", s);
+        if (gd) hipLaunchKernelGGL(k_rdm_double<false>, dim3(gd), dim3(256), 0, s, p, R, (const double *)bra,
+                                   (const double *)ket, W, gab, D);
+        if (gs) hipLaunchKernelGGL(k_rdm_single<false>, dim3(gs), dim3(256), 0, s, p, R, (const double *)bra,
+                                   (const double *)ket, W, S, (double *)Gamma);
+        prof_end(t, s);
+        t = prof_begin("rdm_diag", s);
+        hipLaunchKernelGGL(k_rdm_diag_sf, dim3(gdet), dim3(256), 2 * n * n * sizeof(double), s, p, R,
+                           (const double *)bra, (const double *)ket, W, (double *)gamma, (double *)Gamma);
+        hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, gab, D, S,
+                           (double *)gamma, (double *)Gamma);
+        prof_end(t, s);
+    } else {
+        const int64_t m4 = (int64_t)M * M * M * M, np2 = (int64_t)p.npair * p.npair;
+        double2 *D = (double2 *)p.partial, *S = D + np2;
+        zero((double *)D, 2 * (np2 + (int64_t)M * M), s);
+        zero((double *)gamma, 2 * (int64_t)M * M, s);
+        zero((double *)Gamma, 2 * m4, s);
+        ProfToken t = prof_begin("rdm_groups", s);
+        if (gd) hipLaunchKernelGGL(k_rdm_double<true>, dim3(gd), dim3(256), 0, s, p, R, (const double2 *)bra,
+                                   (const double2 *)ket, W, (double *)nullptr, D);
+        if (gs) hipLaunchKernelGGL(k_rdm_single<true>, dim3(gs), dim3(256), 0, s, p, R, (const double2 *)bra,
+                                   (const double2 *)ket, W, S, (double2 *)Gamma);
+        prof_end(t, s);
+        t = prof_begin("rdm_diag", s);
+        hipLaunchKernelGGL(k_rdm_diag_spinor, dim3(gdet), dim3(256), 0, s, p, R, (const double2 *)bra,
+                           (const double2 *)ket, W, (double2 *)gamma, (double2 *)Gamma);
+        hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, D, S,
+                           (double2 *)gamma, (double2 *)Gamma);
+        prof_end(t, s);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "rdm kernel launch failed");
+    return MW_OK;
+}
+
+}  // namespace mw
+
+using namespace mw;
+
+extern "C" const mw::DevPlan *mw_internal_devplan(mw_plan plan);
+
+extern "C" mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *bra, const void *ket,
+                                     const double *weights, void *gamma, void *Gamma, mw_stream_t stream)
+{
+    if (!plan) return fail(MW_EINVAL, "plan is NULL");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace: call mw_plan_upload first");
+    if (nroots < 1 || nroots > d->max_roots || nroots > 64) return fail(MW_EINVAL, "nroots must be in 1..max_roots");
+    if (!bra || !ket || !gamma || !Gamma) return fail(MW_EINVAL, "NULL device pointer");
+    return launch_rdm(*d, nroots, bra, ket, weights, gamma, Gamma, (hipStream_t)stream);
+}

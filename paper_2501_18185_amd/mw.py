@@ -63,9 +63,18 @@ def lib():
         L.mw_davidson.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), C.c_double, i32,
                                   C.POINTER(i32), vp, sz, vp]
         L.mw_connect_dump.argtypes = [vp, C.POINTER(i64), vp, vp]
+        L.mw_plan_update_integrals.argtypes = [vp, vp, vp, C.c_double, vp]
+        L.mw_sigma_batched_direct.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp),
+                                              i32, vp]
+        L.mw_autotune.argtypes = [vp, i32, vp, vp, vp, C.POINTER(i32)]
+        L.mw_autotune_batched.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), vp,
+                                          C.POINTER(i32)]
+        L.mw_profile.argtypes = [i32]
+        L.mw_profile_read.argtypes = [C.c_char_p, C.POINTER(i64), C.POINTER(C.c_double)]
         for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
                      "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
-                     "mw_davidson", "mw_connect_dump"):
+                     "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
+                     "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -131,6 +140,28 @@ class Plan:
         _check(lib().mw_plan_workspace_bytes(self._plan, C.byref(nb)))
         self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=device)
         _check(lib().mw_plan_upload(self._plan, C.c_void_p(self.workspace.data_ptr()), nb.value, _stream()))
+
+    def set_integrals(self, h, g, ecore=0.0):
+        """Replace h, g (host arrays in the problem's layout) without regrouping."""
+        if self.is_complex:
+            h = np.ascontiguousarray(h, dtype=np.complex128)
+            g = np.ascontiguousarray(g, dtype=np.complex128)
+        else:
+            h = np.ascontiguousarray(np.real(h), dtype=np.float64)
+            g = np.ascontiguousarray(np.real(g), dtype=np.float64)
+        _check(lib().mw_plan_update_integrals(self._plan, h.ctypes.data, g.ctypes.data, float(ecore), _stream()))
+
+    def autotune(self, c, out=None):
+        """Pick the fastest launch parameters for this plan; returns the choice code."""
+        torch = _require_gpu()
+        c = self._vec(c)
+        nroots = 1 if c.dim() == 1 else c.shape[1]
+        if out is None:
+            out = torch.empty_like(c)
+        ch = C.c_int32()
+        _check(lib().mw_autotune(self._plan, nroots, C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()),
+                                 _stream(), C.byref(ch)))
+        return ch.value
 
     def close(self):
         if getattr(self, "_plan", None):
@@ -229,10 +260,25 @@ class Plan:
         return np.array(list(ev)), out, it.value, conv
 
 
-def sigma_batched(plans: Sequence[Plan], cs, outs=None):
-    """sigma_i = H_i c_i for several plans in one launch sequence."""
+def profile(enable: bool):
+    """Start (clearing earlier records) or stop per-kernel event timing."""
+    _check(lib().mw_profile(1 if enable else 0))
+
+
+def profile_read(kernel: str):
+    """(launches, total milliseconds) recorded for one kernel name."""
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(lib().mw_profile_read(kernel.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def _batch_args(plans, cs, outs):
     torch = _require_gpu()
     n = len(plans)
+    for c in cs:
+        if not c.is_contiguous():
+            raise ValueError("batched inputs must be contiguous (their addresses key the cached graph)")
     cs = [p._vec(c) for p, c in zip(plans, cs)]
     if outs is None:
         outs = [torch.empty_like(c) for c in cs]
@@ -240,5 +286,27 @@ def sigma_batched(plans: Sequence[Plan], cs, outs=None):
     R = (C.c_int32 * n)(*[1 if c.dim() == 1 else c.shape[1] for c in cs])
     Cp = (C.c_void_p * n)(*[c.data_ptr() for c in cs])
     Sp = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    return n, P, R, Cp, Sp, outs
+
+
+def sigma_batched(plans: Sequence[Plan], cs, outs=None):
+    """sigma_i = H_i c_i for several plans: one persistent launch, replayed
+    from a HIP graph keyed by the argument tuple."""
+    n, P, R, Cp, Sp, outs = _batch_args(plans, cs, outs)
     _check(lib().mw_sigma_batched(n, P, R, Cp, Sp, _stream()))
     return outs
+
+
+def sigma_batched_direct(plans: Sequence[Plan], cs, outs=None, blocks_per_cu=8):
+    """The batched product launched directly (no graph)."""
+    n, P, R, Cp, Sp, outs = _batch_args(plans, cs, outs)
+    _check(lib().mw_sigma_batched_direct(n, P, R, Cp, Sp, int(blocks_per_cu), _stream()))
+    return outs
+
+
+def autotune_batched(plans: Sequence[Plan], cs, outs=None):
+    """Pick the persistent grid for this batch; returns blocks per CU."""
+    n, P, R, Cp, Sp, outs = _batch_args(plans, cs, outs)
+    b = C.c_int32()
+    _check(lib().mw_autotune_batched(n, P, R, Cp, Sp, _stream(), C.byref(b)))
+    return b.value

@@ -1,0 +1,86 @@
+"""The C ABI on the CPU: the library loads, exports every symbol the header
+declares, and its host-side validation turns malformed problems into status
+codes before any device work.  Plan statistics equal the oracle's counts."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_18185_amd import mw, synth
+from oracle import sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "mw.h")).read()
+    names = set(re.findall(r"\b(mw_[a-z_]+)\s*\(", hdr))
+    names.discard("mw_status")
+    assert len(names) >= 15
+    L = mw.lib()
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+    out = os.popen(f"nm -D --defined-only {mw.LIB_PATH}").read()
+    exported = set(re.findall(r" T (mw_[a-z_]+)", out))
+    assert exported == names, (exported - names, names - exported)
+
+
+def _problem(**kw):
+    p = synth.workload(0)
+    d = dict(kind=p.kind, norb=p.norb, nalpha=p.nalpha, nbeta=p.nbeta, dets=p.dets, h=p.h, g=p.g, ecore=0.0)
+    d.update(kw)
+    return synth.Problem(d["kind"], d["norb"], d["nalpha"], d["nbeta"], d["dets"], d["h"], d["g"], d["ecore"])
+
+
+def _status(prob, max_roots=1):
+    try:
+        mw.Plan(prob, max_roots=max_roots, upload=False)
+    except mw.MWError as e:
+        return e.status
+    return 0
+
+
+def test_validation_status_codes():
+    p = synth.workload(0)
+    assert _status(_problem()) == 0
+    assert _status(_problem(dets=p.dets[::-1].copy())) == -2            # not ascending
+    dup = np.concatenate([p.dets[:1], p.dets[:-1]])
+    assert _status(_problem(dets=dup)) == -2                             # duplicate
+    bad = p.dets.copy(); bad[5, 0] ^= np.uint64(1 << 7) | np.uint64(1)   # wrong popcount
+    assert _status(_problem(dets=np.sort(bad.view("u8,u8"), axis=0).view(np.uint64).reshape(-1, 2))) in (-2, -3)
+    beyond = p.dets.copy(); beyond[-1, 1] = np.uint64(0xF << 8)           # bits beyond norb
+    assert _status(_problem(dets=beyond)) == -3
+    h = p.h.copy(); h[0, 1] += 1e-6
+    assert _status(_problem(h=h)) == -4                                  # h not symmetric
+    g = p.g.copy(); g[0, 1, 2, 3] += 1e-6
+    assert _status(_problem(g=g)) == -4                                  # g not 8-fold
+    assert _status(_problem(norb=65)) == -8
+    assert _status(_problem(), max_roots=0) == -1
+    assert _status(_problem(kind="spinor")) in (-1, -4)                 # nbeta must be -1
+
+
+def test_sigma_without_workspace_is_an_error():
+    pl = mw.Plan(synth.workload(0), upload=False)
+    st = mw.lib().mw_sigma(pl._plan, 1, C.c_void_p(16), C.c_void_p(32), None)
+    assert st == -5
+
+
+@pytest.mark.parametrize("k", [0, 4])
+def test_plan_pair_counts_equal_oracle(k):
+    p = synth.workload(k)
+    pl = mw.Plan(p, upload=False)
+    deg = sc.degree_rows(p)
+    assert pl.info("pairs") == deg.sum()
+    rec = sc.connect_rows(p, np.arange(0, p.ndet, 3))
+    assert pl.info("single_pairs") + pl.info("double_pairs") == pl.info("pairs")
+    assert pl.info("evaluations") >= pl.info("pairs")
+
+
+def test_plan_pair_counts_spinor():
+    rng = np.random.default_rng(1)
+    d = synth.space_selected_spinor(8, 6, 2000, rng)
+    p = synth.Problem("spinor", 8, 6, -1, d, synth.one_body_spinor(8, rng), synth.two_body_spinor(8, rng))
+    pl = mw.Plan(p, upload=False)
+    assert pl.info("pairs") == sc.degree_rows(p).sum()

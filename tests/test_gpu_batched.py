@@ -1,0 +1,124 @@
+"""Batched sigma (one persistent launch over many problems, replayed from a
+HIP graph) and the autotuner: bit-identical to plain launches and within
+1e-12 of the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_18185_amd import synth
+from oracle import sc
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def _comb(a, b):
+    from math import comb
+    return comb(a, b)
+
+
+def _small_batch(count=6):
+    """Uneven problems of the batch recipe at test size."""
+    probs = []
+    for i in range(count):
+        n = 10 + i
+        ne = 3 + (i % 3)
+        rng = synth.rng_for(3, 100 + i, synth.SEED_SPACE)
+        sd = 1 + 2 * ne * (n - ne) + 2 * _comb(ne, 2) * _comb(n - ne, 2) + (ne * (n - ne)) ** 2
+        target = int(sd * [1.2, 1.6, 2.0, 1.4, 2.5, 1.8][i % 6])
+        d = synth.space_selected_spinfree(n, ne, ne, target, rng)
+        probs.append(synth.Problem("spinfree", n, ne, ne, d, synth.one_body_real(n, synth.rng_for(3, 100 + i, 0)),
+                                   synth.two_body_real(n, synth.rng_for(3, 100 + i, 1)), name=f"b{i}"))
+    return probs
+
+
+@pytest.fixture(scope="module")
+def batch(torch):
+    from paper_2501_18185_amd import mw
+    probs = _small_batch()
+    R = [4, 1, 3, 4, 2, 4]
+    plans = [mw.Plan(p, max_roots=4) for p in probs]
+    cs = [torch.from_numpy(synth.ci_vectors(p.ndet, r, np.random.default_rng(10 + i))).cuda()
+          for i, (p, r) in enumerate(zip(probs, R))]
+    return probs, plans, cs, R
+
+
+def test_batched_equals_plain_bitwise_and_oracle(torch, batch):
+    from paper_2501_18185_amd import mw
+    probs, plans, cs, R = batch
+    plain = [pl.sigma(c).cpu().numpy() for pl, c in zip(plans, cs)]
+    outs = mw.sigma_batched(plans, cs)
+    for i, (o, ref) in enumerate(zip(outs, plain)):
+        assert np.array_equal(o.cpu().numpy(), ref), f"problem {i}"
+    for p, c, o in zip(probs, cs, outs):
+        rows = np.unique(np.concatenate([np.arange(10), [p.ndet - 1], np.arange(0, p.ndet, 97)]))
+        assert _rel(o.cpu().numpy()[rows], sc.sigma(p, c.cpu().numpy(), rows=rows)) <= 1e-12
+
+
+def test_batched_graph_replays(torch, batch):
+    """The captured graph is replayed several times with eager work and
+    synchronisations in between; every replay equals the eager result,
+    also after the inputs change in place."""
+    from paper_2501_18185_amd import mw
+    probs, plans, cs, R = batch
+    outs = [torch.empty_like(c) for c in cs]
+    for rep in range(4):
+        if rep == 2:
+            for c in cs:
+                c.mul_(-0.5)          # same buffers, new values
+        mw.sigma_batched(plans, cs, outs)
+        junk = torch.randn(1000, 1000, device="cuda", dtype=torch.float64).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        float(junk)
+        for i, (pl, c) in enumerate(zip(plans, cs)):
+            assert np.array_equal(outs[i].cpu().numpy(), pl.sigma(c).cpu().numpy()), (rep, i)
+
+
+def test_batched_direct_and_autotune(torch, batch):
+    from paper_2501_18185_amd import mw
+    probs, plans, cs, R = batch
+    ref = [pl.sigma(c).cpu().numpy() for pl, c in zip(plans, cs)]
+    for bpc in (1, 4, 16):
+        outs = mw.sigma_batched_direct(plans, cs, blocks_per_cu=bpc)
+        for o, r in zip(outs, ref):
+            assert np.array_equal(o.cpu().numpy(), r)
+    b = mw.autotune_batched(plans, cs)
+    assert b in (1, 2, 4, 8, 16)
+    outs = mw.sigma_batched(plans, cs)
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o.cpu().numpy(), r)
+
+
+def test_plain_autotune_keeps_accuracy(torch):
+    from paper_2501_18185_amd import mw
+    p = synth.workload(0)
+    pl = mw.Plan(p, max_roots=2)
+    c = torch.from_numpy(synth.ci_vectors(p.ndet, 2, np.random.default_rng(3))).cuda()
+    choice = pl.autotune(c)
+    _say("choice", choice)
+    assert choice // 100 in (4, 8, 16) and choice % 100 in (8, 16, 32)
+    assert _rel(pl.sigma(c).cpu().numpy(), sc.sigma(p, c.cpu().numpy())) <= 1e-12
+
+
+def test_batched_rejects_bad_arguments(torch, batch):
+    from paper_2501_18185_amd import mw
+    probs, plans, cs, R = batch
+    with pytest.raises(mw.MWError):
+        mw.sigma_batched([plans[0], plans[0]], [cs[0], cs[0]])
