@@ -14,8 +14,20 @@ Prints one JSON line:  value = nonzero H_IJ c_J terms per second
 kernel's achieved algorithmic HBM bandwidth against MI355X's 8 TB/s and the
 CPU oracle timed on a bounded sample of rows.
 
+Further legs reported in the same line (skip with --legs none):
+  batched   16 uneven spin-free problems (16-48 orbitals, 6-12 electrons per
+            spin, 1e4-5e5 determinants) with 4 roots each: one graph-replayed
+            persistent launch vs 16 plain 4-root calls vs 64 plain 1-root
+            calls;
+  spinor    complex sigma over 40 Kramers pairs, 20 electrons, 1e6
+            determinants;
+  rdm       forward sigma + energy and backward density matrices (gamma,
+            Gamma) on the headline space;
+  davidson  time per Davidson iteration on the headline space.
+
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
-                       [--workload sci-n64|fci-n8|spinor-40kp] [--cpu-rows 800]
+                       [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
+                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson|none]
 """
 from __future__ import annotations
 
@@ -31,6 +43,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def measured_traffic(workload, R):
+    """HBM bytes per launch of the group kernel from the committed rocprofv3
+    counters (profiles/traffic.json), or None when the kernel sources changed
+    since they were taken or the workload differs."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            t = json.load(f)["k_group_double"]
+        h = hashlib.sha256()
+        for src in t["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest()[:16] != t["source_sha256_16"] or workload != "sci-n64" or R != 1:
+            return None
+        return t["fetch_kib_per_dispatch"] * 1024 * t["fetch_factor"] + \
+            t["write_kib_per_dispatch"] * 1024 * t["write_factor"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -52,7 +84,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--roots", type=int, default=1)
     ap.add_argument("--workload", default="sci-n64", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-rows", type=int, default=800, help="rows of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=30000, help="rows of the CPU oracle sample (0: skip)")
+    ap.add_argument("--legs", default="batched,spinor,rdm,davidson")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -83,6 +118,13 @@ def main():
     sig = torch.empty_like(c)
     stream = torch.cuda.current_stream()
 
+    if args.copy_calib:
+        src = torch.empty(2**27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         plan.sigma(c, out=sig)
     torch.cuda.synchronize()
@@ -147,22 +189,36 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_group_sigma",
+            "kernel": "k_group_double",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, R),
             "bytes_per_launch": bytes_grp_launch,
         },
     }
+
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    if legs:
+        out["legs"] = {}
+    if "rdm" in legs:
+        out["legs"]["rdm"] = leg_rdm(plan, c, prob)
+    if "davidson" in legs:
+        out["legs"]["davidson"] = leg_davidson(plan, prob)
+    del plan, c, sig
+    torch.cuda.empty_cache()
+    if "batched" in legs:
+        out["legs"]["batched"] = leg_batched()
+    if "spinor" in legs:
+        out["legs"]["spinor"] = leg_spinor(args.steps)
 
     if args.cpu_rows > 0:
         from oracle import sc
         rng = np.random.default_rng(2026)
         rows = np.sort(rng.choice(ndet, size=min(args.cpu_rows, ndet), replace=False))
         t0 = time.perf_counter()
-        sc.sigma(prob, c_np, rows=rows)
+        sc.sigma(prob, c_np, rows=rows)  # noqa: the oracle, timed as the CPU baseline
         dt = time.perf_counter() - t0
         deg = sc.degree_rows(prob, rows)
         sample_terms = float((deg + 1).sum() * R)
@@ -176,6 +232,112 @@ def main():
         }
         log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s on {sc.num_threads()} threads")
     print(json.dumps(out), flush=True)
+
+
+def _time(fn, steps, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def leg_rdm(plan, c, prob):
+    """Forward E = c^T H c and backward (gamma, Gamma) on the same space."""
+    import torch
+    from paper_2501_18185_amd import mw
+    c1 = c[:, 0].contiguous() if c.dim() == 2 else c
+    t_fwd = _time(lambda: plan.sigma(c1), 5)
+    mw.profile(True)
+    t_bwd = _time(lambda: plan.rdm(c1, c1), 3, warmup=1)
+    mw.profile(False)
+    ng, mg = mw.profile_read("rdm_groups")
+    log(f"[bench] rdm: forward {t_fwd:.2f} ms, backward {t_bwd:.2f} ms")
+    return {"workload": prob.name, "forward_ms": t_fwd, "backward_ms": t_bwd,
+            "rdm_groups_ms": mg / max(ng, 1), "gamma_shape": [prob.norb] * 2, "Gamma_shape": [prob.norb] * 4}
+
+
+def leg_davidson(plan, prob, iters=10):
+    """Wall time per Davidson iteration (fixed iteration count)."""
+    import time as _t
+
+    import torch
+    from paper_2501_18185_amd import mw
+    dg = plan.diag().cpu().numpy()
+    i0 = int(np.argmin(dg))
+    c0 = torch.zeros((prob.ndet, 1), dtype=plan.dtype, device="cuda")
+    c0[i0, 0] = 1.0
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    ev, X, it, conv = plan.davidson(c0, tol=1e-12, max_iter=iters, check=False)
+    dt = _t.perf_counter() - t0
+    log(f"[bench] davidson: {it} iterations in {dt:.2f}s, E = {ev[0]:.10f}")
+    return {"workload": prob.name, "iterations": it, "ms_per_iteration": dt * 1e3 / max(it, 1),
+            "energy_after": float(ev[0])}
+
+
+def leg_batched():
+    """16 uneven problems x 4 roots: batched graph vs plain launches."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from paper_2501_18185_amd import mw, synth
+    t0 = time.perf_counter()
+    probs = [synth.workload(3, i) for i in range(16)]
+    with ThreadPoolExecutor(4) as ex:
+        plans = list(ex.map(lambda p: mw.Plan(p, max_roots=4, upload=False), probs))
+    for pl in plans:
+        pl.upload()
+    log(f"[bench] batched: 16 problems, {sum(p.ndet for p in probs)} dets, plans in {time.perf_counter() - t0:.1f}s")
+    R = 4
+    cs = [torch.from_numpy(synth.ci_vectors(p.ndet, R, synth.rng_for(3, i, synth.SEED_C))).cuda()
+          for i, p in enumerate(probs)]
+    outs = [torch.empty_like(c) for c in cs]
+    cs1 = [[c[:, k].contiguous() for k in range(R)] for c in cs]
+    outs1 = [[torch.empty_like(x) for x in row] for row in cs1]
+    bpc = mw.autotune_batched(plans, cs, outs)
+    t_batched = _time(lambda: mw.sigma_batched(plans, cs, outs), 10)
+    t_plain4 = _time(lambda: [pl.sigma(c, out=o) for pl, c, o in zip(plans, cs, outs)], 5)
+    t_plain1 = _time(lambda: [pl.sigma(x, out=o) for pl, row, orow in zip(plans, cs1, outs1)
+                              for x, o in zip(row, orow)], 5)
+    pairs = sum(pl.info("pairs") for pl in plans)
+    terms = (pairs + sum(p.ndet for p in probs)) * R
+    log(f"[bench] batched: graph {t_batched:.2f} ms, 16x4-root {t_plain4:.2f} ms, 64x1-root {t_plain1:.2f} ms")
+    return {"workload": "batch16-n16..48-6..12e-1e4..5e5-R4", "ndet_total": sum(p.ndet for p in probs),
+            "pairs_total": pairs, "blocks_per_cu": bpc,
+            "batched_graph_ms": t_batched, "plain_16x4_ms": t_plain4, "plain_64x1_ms": t_plain1,
+            "batched_terms_per_s": terms / (t_batched * 1e-3),
+            "speedup_vs_16x4": t_plain4 / t_batched, "speedup_vs_64x1": t_plain1 / t_batched}
+
+
+def leg_spinor(steps):
+    """Complex spinor sigma, 40 Kramers pairs, 20 electrons, 1e6 dets."""
+    import torch
+    from paper_2501_18185_amd import mw, synth
+    t0 = time.perf_counter()
+    p = synth.workload(2)
+    pl = mw.Plan(p)
+    log(f"[bench] spinor: ndet={p.ndet} pairs={pl.info('pairs')} ready in {time.perf_counter() - t0:.1f}s")
+    c = torch.from_numpy(synth.ci_vectors(p.ndet, 1, synth.rng_for(2, 0, synth.SEED_C), complex_=True)).cuda()
+    o = torch.empty_like(c)
+    mw.profile(True)
+    ms = _time(lambda: pl.sigma(c, out=o), max(steps // 2, 3))
+    mw.profile(False)
+    ng, mg = mw.profile_read("group_sigma")
+    pairs = pl.info("pairs")
+    grp_bytes = pairs * 32.0
+    achieved = grp_bytes / (mg / max(ng, 1) * 1e-3) / 1e9 if ng else 0.0
+    log(f"[bench] spinor: {ms:.2f} ms per sigma")
+    return {"workload": p.name, "ndet": p.ndet, "connected_pairs": pairs, "ms_per_sigma": ms,
+            "terms_per_s": (pairs + p.ndet) / (ms * 1e-3), "group_sigma_ms": mg / max(ng, 1),
+            "group_sigma_GBps": achieved, "hbm_frac": achieved / HBM_PEAK_GBS}
 
 
 if __name__ == "__main__":

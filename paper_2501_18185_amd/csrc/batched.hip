@@ -72,7 +72,7 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
     a = BatchArgs{};
     a.nprob = nprob;
     a.pk_start[0] = 0;
-    a.det_start[0] = 0;
+    a.blk_start[0] = 0;
     for (int k = 0; k < nprob; k++) {
         int i = ord[k];
         a.plans[k] = d[i]->self;
@@ -80,9 +80,10 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
         a.sigma[k] = sigma[i];
         a.R[k] = nroots[i];
         a.pk_start[k + 1] = a.pk_start[k] + d[i]->npacket;
-        a.det_start[k + 1] = a.det_start[k] + d[i]->ndet * nroots[i] * 16;
+        a.blk_start[k + 1] = a.blk_start[k] + (d[i]->ndet * nroots[i] * 16 + 255) / 256;
     }
-    if (a.pk_start[nprob] >= 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many packets in one batch");
+    if (a.pk_start[nprob] >= 0xffffffffLL || a.blk_start[nprob] >= 0x7fffffffLL)
+        return fail(MW_EUNSUPPORTED, "too many packets in one batch");
     a.counter = d[ord[0]]->counter;
     key.v.clear();
     for (int i = 0; i < nprob; i++) {

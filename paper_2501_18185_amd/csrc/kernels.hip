@@ -13,8 +13,10 @@
 //      (singles).  The integral is read through Hermiticity as the entry
 //      (row = j, column = i) and conjugated, so that for a fixed j the lanes
 //      of a wave read consecutive columns of one row.  No atomics.
-//  k_gather       (one thread per determinant and root):
+//  k_gather       (a few lanes per determinant and root):
 //      sigma_I = H_II c_I + sum of I's partials (fixed order), one write.
+//      Partials are written in member order (coalesced) and gathered
+//      through the determinant-major membership list.
 //  k_diag         (one thread per determinant): H_II by Slater-Condon.
 //
 // All sums are in a fixed order, so repeated calls give identical bits.
@@ -127,6 +129,9 @@ __device__ __forceinline__ typename Scal<CPLX>::T single_element(const DevPlan &
 // Offset of the double-excitation integral A(pair_i, pair_j) = (P Q|R S) -
 // (P S|R Q), with (P,R) added in i and (Q,S) added in j, read as the (j, i)
 // entry of its table: column part (depends on i only) + row part (j only).
+// Each member carries a layout bit choosing between two tables that hold
+// the same values with transposed column order, so that the members of a
+// wave read runs of consecutive columns.
 struct DoubleIndex {
     size_t col;
     size_t row_stride;
@@ -138,22 +143,27 @@ struct DoubleIndex {
     }
 };
 
+__device__ __forceinline__ int pair_lex_d(int lo, int hi, int m) { return lo * (2 * m - lo - 1) / 2 + (hi - lo - 1); }
+
 template <bool CPLX>
-__device__ __forceinline__ DoubleIndex double_index(const DevPlan &p, uint8_t type, int Xi, int Yi)
+__device__ __forceinline__ DoubleIndex double_index(const DevPlan &p, uint8_t type, int Xi, int Yi, bool lay)
 {
     DoubleIndex d;
     d.n = p.n;
     if (!CPLX && type == G_AB) {
-        // (p_i q_j | r_i s_j) stored as g_ab[q][s][p][r]
+        // (p_i q_j | r_i s_j) stored as g_ab[q][s][p][r] (layout 0) or
+        // g_ab1[q][s][r][p] (layout 1)
         d.ab = 1;
         d.off = 0;
         d.row_stride = (size_t)p.n * p.n;
-        d.col = (size_t)Xi * p.n + (Yi - p.n);
+        const int pi = Xi, ri = Yi - p.n;
+        d.col = lay ? (size_t)ri * p.n + pi : (size_t)pi * p.n + ri;
     } else {
         d.ab = 0;
         d.off = (!CPLX && type == G_BB) ? p.n : 0;
         d.row_stride = p.npair;
-        d.col = pair_idx(Xi - d.off, Yi - d.off);
+        const int m = CPLX ? p.M : p.n;
+        d.col = lay ? pair_lex_d(Xi - d.off, Yi - d.off, m) : pair_idx(Xi - d.off, Yi - d.off);
     }
     return d;
 }
@@ -175,8 +185,9 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
     const uint2 me = p.mem[m];
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
     const uint32_t negi = (me.y >> 16) & 1;
-    const DoubleIndex di = double_index<CPLX>(p, type, Xi, Yi);
-    const T *tab = (const T *)((!CPLX && type == G_AB) ? p.g_ab : p.a_pair);
+    const bool lay = (me.y >> 17) & 1;
+    const DoubleIndex di = double_index<CPLX>(p, type, Xi, Yi, lay);
+    const T *tab = (const T *)((!CPLX && type == G_AB) ? (lay ? p.g_ab1 : p.g_ab) : (lay ? p.a_pair1 : p.a_pair));
     T acc[RC];
 #pragma unroll
     for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
@@ -210,10 +221,28 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
             for (int k = 0; k < RC; k++) acc[k] = sc_add(acc[k], sc_mul(x, cj[u][k]));
         }
     }
-    T *out = partial + (size_t)p.mem_slot[m] * R + r0;
+    T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
         if (k < nr) out[k] = acc[k];
+}
+
+// Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8).
+// Remap so that runs of XCD_CHUNK consecutive logical blocks (the packets of
+// one large group, which read the same partner records and coefficients)
+// share an XCD and its L2, while successive runs rotate over the XCDs.  The
+// grid is a multiple of 8 * XCD_CHUNK, so the map is a bijection.
+constexpr int XCD_CHUNK = 16;
+__device__ __forceinline__ int64_t xcd_block(int64_t b)
+{
+    const int64_t x = b & 7, r = b >> 3;
+    return ((r / XCD_CHUNK) * 8 + x) * XCD_CHUNK + (r % XCD_CHUNK);
+}
+
+static inline unsigned xcd_grid(int64_t blocks)
+{
+    const int64_t q = 8 * XCD_CHUNK;
+    return (unsigned)((blocks + q - 1) / q * q);
 }
 
 template <bool CPLX, int RC, int U>
@@ -221,7 +250,7 @@ __global__ __launch_bounds__(256) void k_group_double(DevPlan p, int R, int r0,
                                                       const typename Scal<CPLX>::T *__restrict__ c,
                                                       typename Scal<CPLX>::T *__restrict__ partial)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = xcd_block(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (wave >= p.npacket_double) return;
     group_double_body<CPLX, RC, U>(p, wave, threadIdx.x & 63, R, r0, c, partial);
 }
@@ -257,7 +286,7 @@ __device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave
         for (int k = 0; k < RC; k++)
             if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
     }
-    T *out = partial + (size_t)p.mem_slot[m] * R + r0;
+    T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
         if (k < nr) out[k] = acc[k];
@@ -293,7 +322,7 @@ __device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
         I = t / R;
         k = (int)(t - I * R);
         const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
-        for (uint32_t s = s0 + sub; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)s * R + k]);
+        for (uint32_t s = s0 + sub; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
     }
 #pragma unroll
     for (int off = GL / 2; off > 0; off >>= 1) {
@@ -319,7 +348,7 @@ template <bool CPLX, int RC, int U>
 static void launch_double(const DevPlan &p, int R, int r0, const typename Scal<CPLX>::T *c,
                           typename Scal<CPLX>::T *part, hipStream_t s)
 {
-    unsigned grid = (unsigned)((p.npacket_double + 3) / 4);
+    unsigned grid = xcd_grid((p.npacket_double + 3) / 4);
     hipLaunchKernelGGL((k_group_double<CPLX, RC, U>), dim3(grid), dim3(256), 0, s, p, R, r0, c, part);
 }
 
@@ -393,58 +422,72 @@ __global__ __launch_bounds__(256) void k_batched_groups(BatchArgs a)
     using T = typename Scal<CPLX>::T;
     const int lane = threadIdx.x & 63;
     const int64_t total = a.pk_start[a.nprob];
-    for (;;) {
-        uint32_t u = 0;
-        if (lane == 0) u = atomicAdd(a.counter, 1u);
-        u = __shfl(u, 0);
-        if ((int64_t)u >= total) break;
-        int q = 0;
-        while ((int64_t)u >= a.pk_start[q + 1]) q++;
-        const DevPlan &p = *a.plans[q];
-        const int64_t w = (int64_t)u - a.pk_start[q];
-        const int R = a.R[q];
-        const T *c = (const T *)a.c[q];
-        T *part = (T *)p.partial;
-        for (int r0 = 0; r0 < R; r0 += 4) {
-            if (w < p.npacket_double) group_double_body<CPLX, 4, CPLX ? 4 : 8>(p, w, lane, R, r0, c, part);
-            else group_single_body<CPLX, 4>(p, w, lane, R, r0, c, part);
+    // Work queue per XCD (block b runs on XCD b % 8): the packet sequence is
+    // cut into chunks of CHUNK packets and chunk ch belongs to XCD ch % 8,
+    // so the packets of one group meet in one L2.  A wave claims the next
+    // chunk of its own XCD; when that queue is empty it takes chunks from
+    // the others.  All counters start at zero.
+    constexpr uint32_t CHUNK = 16;
+    const int64_t nchunk = (total + CHUNK - 1) / CHUNK;
+    const int home = blockIdx.x & 7;
+    for (int qi = 0; qi < 8; qi++) {
+        const int xq = (home + qi) & 7;
+        for (;;) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(&a.counter[xq], 1u);
+            t = __shfl(t, 0);
+            const int64_t ch = (int64_t)t * 8 + xq;
+            if (ch >= nchunk) break;
+            const int64_t u1 = min<int64_t>(total, (ch + 1) * CHUNK);
+            for (int64_t u = ch * CHUNK; u < u1; u++) {
+                int q = 0;
+                while (u >= a.pk_start[q + 1]) q++;
+                const DevPlan &p = *a.plans[q];
+                const int64_t w = u - a.pk_start[q];
+                const int R = a.R[q];
+                const T *c = (const T *)a.c[q];
+                T *part = (T *)p.partial;
+                for (int r0 = 0; r0 < R; r0 += 4) {
+                    // unroll 4: four roots of four partners keep the register
+                    // count at the plain kernel's occupancy
+                    if (w < p.npacket_double) group_double_body<CPLX, 4, 4>(p, w, lane, R, r0, c, part);
+                    else group_single_body<CPLX, 4>(p, w, lane, R, r0, c, part);
+                }
+            }
         }
     }
 }
 
+// Gather for all problems: block b belongs to the problem whose block range
+// holds b (block-uniform, so the plan fields are scalar loads).
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_batched_gather(BatchArgs a)
 {
     using T = typename Scal<CPLX>::T;
     constexpr int GL = 16;
-    const int64_t total = a.det_start[a.nprob];
-    // every thread of a block runs the same number of rounds, so the GL-lane
-    // butterflies inside gather_body always see complete groups
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t gt = base + threadIdx.x;
-        const int64_t g = gt < total ? gt : total - 1;
-        int q = 0;
-        while (g >= a.det_start[q + 1]) q++;
-        const DevPlan &p = *a.plans[q];
-        // past the end: an index whose determinant is out of range (inactive)
-        const int64_t local = gt < total ? gt - a.det_start[q] : p.ndet * a.R[q] * GL;
-        gather_body<CPLX, GL>(p, local, a.R[q], (const T *)a.c[q], (const T *)p.partial, (T *)a.sigma[q]);
-    }
+    const int64_t b = blockIdx.x;
+    int q = 0;
+    while (b >= a.blk_start[q + 1]) q++;
+    const DevPlan &p = *a.plans[q];
+    const int64_t local = (b - a.blk_start[q]) * blockDim.x + threadIdx.x;
+    gather_body<CPLX, GL>(p, local, a.R[q], (const T *)a.c[q], (const T *)p.partial, (T *)a.sigma[q]);
 }
 
-__global__ void k_reset_counter(uint32_t *ctr) { *ctr = 0u; }
+__global__ void k_reset_counter(uint32_t *ctr)
+{
+    if (threadIdx.x < 8) ctr[threadIdx.x] = 0u;
+}
 
 mw_status launch_batched(const BatchArgs &a, bool cplx, int blocks, hipStream_t s, bool timing)
 {
     if (a.nprob == 0) return MW_OK;
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, a.counter);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, a.counter);
     ProfToken t = timing ? prof_begin("batched_groups", s) : ProfToken{nullptr, nullptr, ""};
     if (cplx) hipLaunchKernelGGL(k_batched_groups<true>, dim3(blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_batched_groups<false>, dim3(blocks), dim3(256), 0, s, a);
     prof_end(t, s);
     if (timing) t = prof_begin("batched_gather", s);
-    const int64_t tot = a.det_start[a.nprob];
-    const unsigned gg = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+    const unsigned gg = (unsigned)a.blk_start[a.nprob];
     if (cplx) hipLaunchKernelGGL(k_batched_gather<true>, dim3(gg), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_batched_gather<false>, dim3(gg), dim3(256), 0, s, a);
     prof_end(t, s);

@@ -44,12 +44,12 @@ struct DevPlan {
     const uint64_t *grp_key;   // [ngroup][2] the shared string K
     const uint8_t *grp_type;   // [ngroup]
     // members (group-major)
-    const uint2 *mem;          // [nmem] {det, P | R<<8 | (phi<0)<<16}
+    const uint2 *mem;          // [nmem] {det, X | Y<<8 | (phi<0)<<16 | layout<<17}
     const uint32_t *mem_grp;   // [nmem] owning group
-    const uint32_t *mem_slot;  // [nmem] slot in the determinant-major partial array
+    const uint32_t *slot_mem;  // [nmem] memberships listed determinant by determinant
     const uint32_t *pk_off;    // [npacket+1] packets of <= 64 consecutive members
     // determinants
-    const uint32_t *rowptr;    // [ndet+1] slots of each determinant
+    const uint32_t *rowptr;    // [ndet+1] range of each determinant in slot_mem
     const uint64_t *dets;      // [ndet][2]
     void *diag;                // [ndet] scalar (written at upload)
     // integrals (scalar = double or double2)
@@ -57,11 +57,13 @@ struct DevPlan {
     const void *w_same;        // singles table [R][P][Q]: (PQ|RR) - (PR|RQ)  (spin-free n^3, spinor M^3)
     const void *w_opp;         // spin-free only: [r][p][q] (pq|rr)
     const void *g_ab;          // spin-free only: [q][s][p][r] = (pq|rs)
-    const void *a_pair;        // antisymmetrised pairs [x][y] = (X0 Y0|X1 Y1) - (X0 Y1|X1 Y0)
+    const void *g_ab1;         // same values as [q][s][r][p]
+    const void *a_pair;        // antisymmetrised pairs [x][y] = (X0 Y0|X1 Y1) - (X0 Y1|X1 Y0), y colex
+    const void *a_pair1;       // same values with the column pair y in lexicographic order
     const void *f_ref;         // F^omega (spin-free [2][n][n] by spin of the group; spinor [M][M])
     uint64_t ref0, ref1;       // reference string omega
     int64_t npacket_double;    // packets [0, npacket_double) hold double groups
-    void *partial;             // [nmem][max_roots] scalar scratch (also RDM accumulators)
+    void *partial;             // [nmem][R] per-membership partial sums, member order (also RDM accumulators)
     size_t scratch_bytes;
     DevPlan *self;             // device copy of this struct (for batched launches)
     uint32_t *counter;         // device work counter (batched launches)
@@ -79,7 +81,7 @@ struct BatchArgs {
     void *sigma[MW_MAXB];
     int R[MW_MAXB];
     int64_t pk_start[MW_MAXB + 1];   // packet prefix over problems
-    int64_t det_start[MW_MAXB + 1];  // gather-thread prefix over problems
+    int64_t blk_start[MW_MAXB + 1];  // gather-block prefix over problems (256 threads each)
     uint32_t *counter;
 };
 mw_status launch_batched(const BatchArgs &a, bool cplx, int blocks, hipStream_t s, bool timing);

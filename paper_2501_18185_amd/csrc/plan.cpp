@@ -114,8 +114,8 @@ struct HostPlan {
     std::vector<uint64_t> grp_key;
     std::vector<uint8_t> grp_type;
     std::vector<uint2> mem;
-    std::vector<uint32_t> mem_grp, mem_slot, pk_off, rowptr;
-    std::vector<double> h, w_same, w_opp, g_ab, a_pair, f_ref;
+    std::vector<uint32_t> mem_grp, slot_mem, pk_off, rowptr;
+    std::vector<double> h, w_same, w_opp, g_ab, g_ab1, a_pair, a_pair1, f_ref;
     uint64_t ref0 = 0, ref1 = 0;
     int64_t npacket_double = 0;
     int32_t tune_u = 8, tune_gl = 16;
@@ -408,6 +408,33 @@ static mw_status build_groups(HostPlan &P)
                 if (!single) freq[Y]++;
             }
             int64_t k = r.len;
+            if (!single) {
+                // integral layout per member: the kernel reads the integrals
+                // of member i at a column of a row fixed by the partner, so
+                // the members of one wave should sit at neighbouring
+                // columns.  Within the member's 64-member window (its packet)
+                // count the members sharing its first added position X and
+                // those sharing the second Y; the larger run decides which
+                // index varies fastest: layout 0 keeps Y fastest for
+                // alpha-beta groups (X fastest for pair tables, colex order),
+                // layout 1 is the transposed column order.
+                const bool ab = type == G_AB;
+                const int64_t g0 = P.grp_off[gi];
+                for (uint32_t t = 0; t < r.len; t++) {
+                    const int64_t w0 = g0 + (t / 64) * 64, w1 = std::min<int64_t>(g0 + r.len, w0 + 64);
+                    const int64_t mi = g0 + t;
+                    const int X = P.mem[mi].y & 255, Y = (P.mem[mi].y >> 8) & 255;
+                    int cx = 0, cy = 0;
+                    for (int64_t o = w0; o < w1; o++) {
+                        if (o == mi) continue;
+                        cx += (int)((P.mem[o].y & 255) == (uint32_t)X);
+                        cy += (int)(((P.mem[o].y >> 8) & 255) == (uint32_t)Y);
+                    }
+                    // X shared -> Y varies: alpha-beta layout 0, pairs layout 1
+                    const int lay = cx >= cy ? (ab ? 0 : 1) : (ab ? 1 : 0);
+                    if (lay == 1) P.mem[mi].y |= 1u << 17;
+                }
+            }
             if (single) {
                 single_pairs[gi] = k * (k - 1);
             } else {
@@ -461,13 +488,13 @@ static mw_status build_groups(HostPlan &P)
         if (cur_cnt) P.pk_off.push_back(cur_start + cur_cnt);
         if (!in_single) P.npacket_double = (int64_t)P.pk_off.size() - 1;
     }
-    // determinant-major slots
+    // determinant-major list of each determinant's memberships
     P.rowptr.assign(N + 1, 0);
     for (int64_t mi = 0; mi < nmem; mi++) P.rowptr[P.mem[mi].x + 1]++;
     for (int64_t i = 0; i < N; i++) P.rowptr[i + 1] += P.rowptr[i];
     std::vector<uint32_t> fillc(P.rowptr.begin(), P.rowptr.end() - 1);
-    P.mem_slot.resize(nmem);
-    for (int64_t mi = 0; mi < nmem; mi++) P.mem_slot[mi] = fillc[P.mem[mi].x]++;
+    P.slot_mem.resize(nmem);
+    for (int64_t mi = 0; mi < nmem; mi++) P.slot_mem[fillc[P.mem[mi].x]++] = (uint32_t)mi;
     return MW_OK;
 }
 
@@ -476,6 +503,8 @@ static mw_status build_groups(HostPlan &P)
 // ---------------------------------------------------------------------------
 
 static inline int pair_index(int lo, int hi) { return hi * (hi - 1) / 2 + lo; }
+// lexicographic index of the pair lo < hi among m positions
+static inline int pair_lex(int lo, int hi, int m) { return lo * (2 * m - lo - 1) / 2 + (hi - lo - 1); }
 
 static void repack(HostPlan &P, const mw_problem *p)
 {
@@ -493,23 +522,29 @@ static void repack(HostPlan &P, const mw_problem *p)
                     P.w_opp[((size_t)r * n + a) * n + b] = G(a, b, r, r);
                 }
         P.g_ab.resize((size_t)n * n * n * n);
+        P.g_ab1.resize((size_t)n * n * n * n);
         parallel_for(n, [&](int64_t q0, int64_t q1, unsigned) {
             for (int64_t q = q0; q < q1; q++)
                 for (int s = 0; s < n; s++)
                     for (int a = 0; a < n; a++)
-                        for (int r = 0; r < n; r++)
+                        for (int r = 0; r < n; r++) {
                             P.g_ab[(((size_t)q * n + s) * n + a) * n + r] = G(a, q, r, s);
+                            P.g_ab1[(((size_t)q * n + s) * n + r) * n + a] = G(a, q, r, s);
+                        }
         });
         const int np = n * (n - 1) / 2;
         P.npair = np;
         P.a_pair.resize((size_t)np * np);
+        P.a_pair1.resize((size_t)np * np);
         parallel_for(n, [&](int64_t x10, int64_t x11, unsigned) {
             for (int64_t x1 = x10; x1 < x11; x1++)
                 for (int x0 = 0; x0 < x1; x0++)
                     for (int y1 = 1; y1 < n; y1++)
-                        for (int y0 = 0; y0 < y1; y0++)
-                            P.a_pair[(size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1)] =
-                                G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
+                        for (int y0 = 0; y0 < y1; y0++) {
+                            const double v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
+                            P.a_pair[(size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1)] = v;
+                            P.a_pair1[(size_t)pair_index(x0, (int)x1) * np + pair_lex(y0, y1, n)] = v;
+                        }
         });
     } else {
         const int Mm = 2 * n;
@@ -529,6 +564,7 @@ static void repack(HostPlan &P, const mw_problem *p)
         const int np = Mm * (Mm - 1) / 2;
         P.npair = np;
         P.a_pair.resize(2 * (size_t)np * np);
+        P.a_pair1.resize(2 * (size_t)np * np);
         parallel_for(Mm, [&](int64_t x10, int64_t x11, unsigned) {
             for (int64_t x1 = x10; x1 < x11; x1++)
                 for (int x0 = 0; x0 < x1; x0++)
@@ -536,8 +572,11 @@ static void repack(HostPlan &P, const mw_problem *p)
                         for (int y0 = 0; y0 < y1; y0++) {
                             cd v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
                             size_t k = (size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1);
+                            size_t k1 = (size_t)pair_index(x0, (int)x1) * np + pair_lex(y0, y1, Mm);
                             P.a_pair[2 * k] = v.real();
                             P.a_pair[2 * k + 1] = v.imag();
+                            P.a_pair1[2 * k1] = v.real();
+                            P.a_pair1[2 * k1 + 1] = v.imag();
                         }
         });
     }
@@ -617,7 +656,7 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.grp_type = (const uint8_t *)take(grp_type.size());
     t.mem = (const uint2 *)take(mem.size() * 8);
     t.mem_grp = (const uint32_t *)take(mem_grp.size() * 4);
-    t.mem_slot = (const uint32_t *)take(mem_slot.size() * 4);
+    t.slot_mem = (const uint32_t *)take(slot_mem.size() * 4);
     t.pk_off = (const uint32_t *)take(pk_off.size() * 4);
     t.rowptr = (const uint32_t *)take(rowptr.size() * 4);
     t.dets = (const uint64_t *)take(dets.size() * 8);
@@ -626,7 +665,9 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.w_same = (const void *)take(w_same.size() * 8);
     t.w_opp = (const void *)take(w_opp.size() * 8);
     t.g_ab = (const void *)take(g_ab.size() * 8);
+    t.g_ab1 = (const void *)take(g_ab1.size() * 8);
     t.a_pair = (const void *)take(a_pair.size() * 8);
+    t.a_pair1 = (const void *)take(a_pair1.size() * 8);
     t.f_ref = (const void *)take(f_ref.size() * 8);
     t.ref0 = ref0;
     t.ref1 = ref1;
@@ -719,7 +760,7 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.grp_type, P.grp_type.data(), P.grp_type.size()) &&
               up(d.mem, P.mem.data(), P.mem.size() * 8) &&
               up(d.mem_grp, P.mem_grp.data(), P.mem_grp.size() * 4) &&
-              up(d.mem_slot, P.mem_slot.data(), P.mem_slot.size() * 4) &&
+              up(d.slot_mem, P.slot_mem.data(), P.slot_mem.size() * 4) &&
               up(d.pk_off, P.pk_off.data(), P.pk_off.size() * 4) &&
               up(d.rowptr, P.rowptr.data(), P.rowptr.size() * 4) &&
               up(d.dets, P.dets.data(), P.dets.size() * 8) &&
@@ -727,7 +768,9 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
               up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) &&
               up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
+              up(d.g_ab1, P.g_ab1.data(), P.g_ab1.size() * 8) &&
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) &&
+              up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
               up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
     if (hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -770,6 +813,7 @@ mw_status mw_plan_update_integrals(mw_plan plan, const double *h, const double *
     };
     bool ok = up(d.h, P.h.data(), P.h.size() * 8) && up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
               up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) && up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
+              up(d.g_ab1, P.g_ab1.data(), P.g_ab1.size() * 8) && up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) && up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
               up(d.self, &P.dev, sizeof(DevPlan));
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during integral update");
