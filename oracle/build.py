@@ -11,7 +11,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC])
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 

@@ -26,6 +26,7 @@
  * the phase is counted literally, position by position.  All arithmetic is
  * FP64 (complex as explicit re/im pairs); build with -ffp-contract=off.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -145,12 +146,16 @@ static cx hij(const ham_t *H, const uint64_t *I, const uint64_t *J, int n)
     int lvl = excitation(I, J, n, &P, &Q, &R, &S, &sign);
     if (lvl < 0) return CX0;
     if (lvl == 0) {
+        /* occupied positions ascending, then every pair A < B */
+        int occ[128], no = 0;
+        for (int A = 0; A < 2 * n; A++)
+            if (occupied(I, n, A)) occ[no++] = A;
         cx e = {H->ecore, 0.0};
-        for (int A = 0; A < 2 * n; A++) {
-            if (!occupied(I, n, A)) continue;
+        for (int a = 0; a < no; a++) {
+            int A = occ[a];
             e = cx_add(e, h_so(H, A, A));
-            for (int B = A + 1; B < 2 * n; B++) {
-                if (!occupied(I, n, B)) continue;
+            for (int b = a + 1; b < no; b++) {
+                int B = occ[b];
                 e = cx_add(e, cx_sub(g_so(H, A, A, B, B), g_so(H, A, B, B, A)));
             }
         }
@@ -380,4 +385,153 @@ void orc_rdm_rows(int kind, int n, long ndet, const uint64_t *dets, int nroots,
         }
     }
     free(tup);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Epstein-Nesbet second-order energy (section 2.5, Eq. (ENPT2E)) with the
+ * primary space equal to the whole space P:
+ *   E2_k = sum_{A in Q} |sum_{J in P} H_AJ c_Jk|^2 / (E0_k - H_AA),
+ * Q = the determinants outside P that one or two excitations reach from
+ * some J in P (spin-free: N_alpha and N_beta kept).  Screening as in the
+ * paper's PT2 procedure (step 4): a doubly excited pair (A, J) is left out
+ * when |H_AJ| max_k |c_Jk| < qmin; qmin = 0 keeps everything.
+ * Steps: every J lists its excitations A outside P; the (A, J) list is
+ * sorted by A, then J; each numerator is summed in ascending J; the
+ * contributions are added in ascending A. */
+
+typedef struct { uint64_t a0, a1; long j; } pt2_rec;
+
+static int rec_cmp(const void *x, const void *y)
+{
+    const pt2_rec *a = (const pt2_rec *)x, *b = (const pt2_rec *)y;
+    if (a->a0 != b->a0) return a->a0 < b->a0 ? -1 : 1;
+    if (a->a1 != b->a1) return a->a1 < b->a1 ? -1 : 1;
+    return (a->j > b->j) - (a->j < b->j);
+}
+
+/* is (d0, d1) one of the sorted determinants? */
+static int in_space(long ndet, const uint64_t *dets, uint64_t d0, uint64_t d1)
+{
+    long lo = 0, hi = ndet;
+    while (lo < hi) {
+        long mid = lo + (hi - lo) / 2;
+        uint64_t m0 = dets[2 * mid], m1 = dets[2 * mid + 1];
+        if (m0 < d0 || (m0 == d0 && m1 < d1)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < ndet && dets[2 * lo] == d0 && dets[2 * lo + 1] == d1;
+}
+
+static double cx_abs(cx a) { return sqrt(a.re * a.re + a.im * a.im); }
+
+typedef struct { pt2_rec *r; long n, cap; } rec_buf;
+
+static void rec_push(rec_buf *b, uint64_t a0, uint64_t a1, long j)
+{
+    if (b->n == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1024;
+        b->r = (pt2_rec *)realloc(b->r, sizeof(pt2_rec) * (size_t)b->cap);
+    }
+    b->r[b->n].a0 = a0; b->r[b->n].a1 = a1; b->r[b->n].j = j;
+    b->n++;
+}
+
+static void flip(uint64_t *d, int n, int X) { d[X / n] ^= (1ull << (X % n)); }
+
+/* stats (nullable): [0] kept (A, J) pairs, [1] distinct A in Q */
+void orc_pt2(int kind, int n, const double *h, const double *g, double ecore,
+             long ndet, const uint64_t *dets, int nroots, const double *c,
+             const double *e0, double qmin, double *e2, long *stats)
+{
+    ham_t H = {kind, n, h, g, ecore};
+    const int M = 2 * n;
+    rec_buf B = {NULL, 0, 0};
+    for (long j = 0; j < ndet; j++) {
+        const uint64_t *J = dets + 2 * j;
+        for (int Q = 0; Q < M; Q++) {
+            if (!occupied(J, n, Q)) continue;
+            /* singles Q -> P */
+            for (int P = 0; P < M; P++) {
+                if (occupied(J, n, P)) continue;
+                if (kind == 0 && P / n != Q / n) continue;
+                uint64_t A[2] = {J[0], J[1]};
+                flip(A, n, Q); flip(A, n, P);
+                if (!in_space(ndet, dets, A[0], A[1])) rec_push(&B, A[0], A[1], j);
+            }
+            /* doubles Q < S -> P < R */
+            for (int S = Q + 1; S < M; S++) {
+                if (!occupied(J, n, S)) continue;
+                for (int P = 0; P < M; P++) {
+                    if (occupied(J, n, P)) continue;
+                    for (int R = P + 1; R < M; R++) {
+                        if (occupied(J, n, R)) continue;
+                        if (kind == 0) {
+                            int hs = (Q / n) + (S / n), ps = (P / n) + (R / n);
+                            if (hs != ps) continue;
+                        }
+                        uint64_t A[2] = {J[0], J[1]};
+                        flip(A, n, Q); flip(A, n, S); flip(A, n, P); flip(A, n, R);
+                        if (!in_space(ndet, dets, A[0], A[1])) rec_push(&B, A[0], A[1], j);
+                    }
+                }
+            }
+        }
+    }
+    qsort(B.r, (size_t)B.n, sizeof(pt2_rec), rec_cmp);
+    /* largest |c_Jk| per J for the screening */
+    double *cmax = (double *)calloc((size_t)(ndet > 0 ? ndet : 1), sizeof(double));
+    for (long j = 0; j < ndet; j++)
+        for (int k = 0; k < nroots; k++) {
+            cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+            double a = cx_abs(cj);
+            if (a > cmax[j]) cmax[j] = a;
+        }
+    /* first record of every distinct A */
+    long nA = 0;
+    long *head = (long *)malloc(sizeof(long) * (size_t)(B.n + 1));
+    for (long s = 0; s < B.n; s++)
+        if (s == 0 || B.r[s].a0 != B.r[s - 1].a0 || B.r[s].a1 != B.r[s - 1].a1) head[nA++] = s;
+    head[nA] = B.n;
+    /* per-A contributions (independent, any thread), then summed in ascending A */
+    double *contrib = (double *)calloc((size_t)(nA > 0 ? nA : 1) * (size_t)(nroots > 0 ? nroots : 1), sizeof(double));
+    long *used = (long *)calloc((size_t)(nA > 0 ? nA : 1), sizeof(long));
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (long a = 0; a < nA; a++) {
+        cx num[64];
+        const uint64_t A[2] = {B.r[head[a]].a0, B.r[head[a]].a1};
+        for (int k = 0; k < nroots; k++) num[k] = CX0;
+        long u_cnt = 0;
+        for (long u = head[a]; u < head[a + 1]; u++) {
+            long j = B.r[u].j;
+            const uint64_t *J = dets + 2 * j;
+            int pc = __builtin_popcountll(A[0] ^ J[0]) + __builtin_popcountll(A[1] ^ J[1]);
+            cx v = hij(&H, A, J, n);
+            if (pc == 4 && cx_abs(v) * cmax[j] < qmin) continue;
+            u_cnt++;
+            for (int k = 0; k < nroots; k++) {
+                cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+                num[k] = cx_add(num[k], cx_mul(v, cj));
+            }
+        }
+        used[a] = u_cnt;
+        if (u_cnt) {
+            double haa = hij(&H, A, A, n).re;
+            for (int k = 0; k < nroots; k++)
+                contrib[a * nroots + k] = (num[k].re * num[k].re + num[k].im * num[k].im) / (e0[k] - haa);
+        }
+    }
+    for (int k = 0; k < nroots; k++) e2[k] = 0.0;
+    long kept = 0, nq = 0;
+    for (long a = 0; a < nA; a++) {
+        if (!used[a]) continue;
+        kept += used[a];
+        nq++;
+        for (int k = 0; k < nroots; k++) e2[k] += contrib[a * nroots + k];
+    }
+    if (stats) { stats[0] = kept; stats[1] = nq; }
+    free(head);
+    free(contrib);
+    free(used);
+    free(cmax);
+    free(B.r);
 }

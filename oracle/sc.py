@@ -33,6 +33,8 @@ def lib():
         L.orc_num_threads.restype = C.c_int
         L.orc_rdm_rows.argtypes = [C.c_int, C.c_int, C.c_long, up, C.c_int, dp, dp, dp, C.c_long,
                                    lp, dp, dp]
+        L.orc_pt2.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_long, up, C.c_int, dp, dp,
+                              C.c_double, dp, lp]
         _lib = L
     return _lib
 
@@ -159,3 +161,25 @@ def rdm(prob, bra, ket, weights=None, rows=None):
     if kind == 0 and not (np.iscomplexobj(bra) or np.iscomplexobj(ket)):
         return gam.real.copy(), Gam.real.copy()
     return gam, Gam
+
+
+def pt2(prob, c, e0, qmin=0.0):
+    """Epstein-Nesbet second-order energies E2_k over the determinants that
+    single and double excitations reach from the space (outside it), with
+    the doubles screening |H_AJ| max_k |c_Jk| < qmin.  ``c`` [ndet] or
+    [ndet][nroots], ``e0`` scalar or [nroots].  Returns (e2 [nroots],
+    kept (A, J) pairs, number of external A)."""
+    kind, h, g = _ham(prob)
+    c = np.asarray(c)
+    c2 = np.ascontiguousarray(c.reshape(len(c), -1), dtype=np.complex128)
+    nroots = c2.shape[1]
+    if nroots > 64:
+        raise ValueError("at most 64 roots")
+    e0 = np.ascontiguousarray(np.broadcast_to(np.asarray(e0, np.float64), (nroots,)))
+    e2 = np.zeros(nroots)
+    stats = np.zeros(2, dtype=np.int64)
+    dets = np.ascontiguousarray(prob.dets, dtype=np.uint64)
+    lib().orc_pt2(kind, prob.norb, _p(h, C.c_double), _p(g, C.c_double), float(prob.ecore), len(dets),
+                  _p(dets, C.c_uint64), nroots, _p(c2.view(np.float64), C.c_double), _p(e0, C.c_double),
+                  float(qmin), _p(e2, C.c_double), _p(stats, C.c_long))
+    return e2, int(stats[0]), int(stats[1])

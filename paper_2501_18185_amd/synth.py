@@ -294,6 +294,40 @@ def space_selected_spinfree(n, na, nb, target, rng, ranks=(3, 4)):
     return _fill_random(w0, w1, target, gen)
 
 
+def space_truncated_spinfree(n, na, nb, target, rng):
+    """HF + all singles + random doubles up to target (a small variational
+    space whose external space is dominated by its doubles' excitations).
+
+    Double spin split uniform over the feasible (k_alpha, k_beta); holes and
+    particles uniform without replacement; duplicates rejected."""
+    hf0 = np.uint64((1 << na) - 1); hf1 = np.uint64((1 << nb) - 1)
+    occa = np.arange(na); vira = np.arange(na, n)
+    occb = n + np.arange(nb); virb = n + np.arange(nb, n)
+    ws0 = [np.array([hf0], np.uint64)]; ws1 = [np.array([hf1], np.uint64)]
+    for occ, vir in ((list(occa), list(vira)), (list(occb), list(virb))):
+        H, Pp = _all_excitations(occ, vir, 1)
+        if len(H):
+            a, b = _excite(hf0, hf1, n, H, Pp)
+            ws0.append(a); ws1.append(b)
+    feas = np.array([a for a in range(3) if a <= min(na, n - na) and (2 - a) <= min(nb, n - nb)])
+
+    def gen(m):
+        ka = rng.choice(feas, size=m)
+        kb = 2 - ka
+        ha = _random_subsets(rng, m, occa, min(2, na))
+        pa = _random_subsets(rng, m, vira, min(2, n - na))
+        hb = _random_subsets(rng, m, occb, min(2, nb))
+        pb = _random_subsets(rng, m, virb, min(2, n - nb))
+        ha = np.where(np.arange(ha.shape[1])[None, :] < ka[:, None], ha, -1)
+        pa = np.where(np.arange(pa.shape[1])[None, :] < ka[:, None], pa, -1)
+        hb = np.where(np.arange(hb.shape[1])[None, :] < kb[:, None], hb, -1)
+        pb = np.where(np.arange(pb.shape[1])[None, :] < kb[:, None], pb, -1)
+        H = np.concatenate([ha, hb], 1); Pp = np.concatenate([pa, pb], 1)
+        return _excite(hf0, hf1, n, H, Pp)
+
+    return _fill_random(np.concatenate(ws0), np.concatenate(ws1), target, gen)
+
+
 def space_selected_spinor(nk, nel, target, rng, ranks=(3,)):
     """Spinor space over M = 2*nk spinors: HF (pairs 0..nel/2-1 in A and B)
     + all singles + all doubles + random higher excitations (total N kept)."""
@@ -380,7 +414,8 @@ def batch_shapes(i: int):
 
 def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
     """Workload k (0 FCI n=8 4a4b; 1 selected n=64 10a10b 2e6; 2 spinor
-    40 pairs N=20 1e6; 3 batch problem i; 4 FD case n=10 3a3b FCI).
+    40 pairs N=20 1e6; 3 batch problem i; 4 FD case n=10 3a3b FCI; 5 the
+    variational space of the second-order energy, n=64 10a10b 2e4).
 
     ``scale`` < 1 shrinks the random part of selected spaces (for tests)."""
     if k == 0:
@@ -406,6 +441,14 @@ def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
         d = space_selected_spinfree(n, ne, ne, nd, rng_for(3, i, SEED_SPACE))
         return Problem("spinfree", n, ne, ne, d, one_body_real(n, rng_for(3, i, SEED_H)),
                        two_body_real(n, rng_for(3, i, SEED_G)), name=f"batch{i}-n{n}-{ne}a{ne}b")
+    if k == 5:
+        # variational space of the second-order energy: n=64 10a10b with the
+        # integrals of workload 1, HF + singles + random doubles
+        n, na = 64, 10
+        target = int(20_000 * scale)
+        d = space_truncated_spinfree(n, na, na, max(target, 1081), rng_for(5, 0, SEED_SPACE))
+        return Problem("spinfree", n, na, na, d, one_body_real(n, rng_for(1, 0, SEED_H)),
+                       two_body_real(n, rng_for(1, 0, SEED_G)), name="pt2-n64-10a10b")
     if k == 4:
         n, na, nb = 10, 3, 3
         return Problem("spinfree", n, na, nb, space_fci(n, na, nb),

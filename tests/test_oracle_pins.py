@@ -438,3 +438,124 @@ def test_gradient_central_differences():
     fd = (E(h + eps * dh, g + eps * dg) - E(h - eps * dh, g - eps * dg)) / (2 * eps)
     an = np.sum(g1 * dh) + 0.5 * np.sum(g2 * dg)
     assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+# --------------------------------------------------------------------------
+# Epstein-Nesbet second-order energy (section 2.5)
+# --------------------------------------------------------------------------
+
+def _pt2_dense(p_full, H, pidx, c, e0, qmin=0.0):
+    """E2_k = sum over A outside P of |sum_J H_AJ c_Jk|^2 / (e0_k - H_AA)
+    from a dense H over a complete space (tier A), doubles (A, J) dropped
+    when |H_AJ| max_k |c_Jk| < qmin; also the structural counts (connected
+    (A, J) pairs kept, distinct A)."""
+    x = literal.packed(p_full)
+    N = len(x)
+    outside = np.setdiff1d(np.arange(N), pidx)
+    lvl = np.bitwise_count(x[outside][:, None] ^ x[pidx][None, :]).astype(np.int64)
+    conn = (lvl == 2) | (lvl == 4)
+    c2 = np.asarray(c).reshape(len(pidx), -1)
+    cmax = np.abs(c2).max(axis=1)
+    HAP = H[np.ix_(outside, pidx)]
+    keep = conn & ~((lvl == 4) & (np.abs(HAP) * cmax[None, :] < qmin))
+    num = (HAP * keep) @ c2
+    den = np.asarray(e0)[None, :] - np.real(np.diag(H)[outside])[:, None]
+    has = keep.any(axis=1)
+    e2 = (np.abs(num[has]) ** 2 / den[has]).sum(axis=0)
+    return e2, int(keep.sum()), int(has.sum())
+
+
+def test_pt2_hubbard_closed_form():
+    """Two-site Hubbard, P = {|0a 0b>}, c = 1: the two single hops couple
+    with -t, the double with (10|10) = 0, the singles have H_AA = 0, so
+    E2 = 2 t^2 / E0 exactly."""
+    for t, U, e0 in [(1.0, 4.0, -1.0), (0.3, 1.7, -0.25)]:
+        h = np.array([[0.0, -t], [-t, 0.0]])
+        g = np.zeros((2, 2, 2, 2))
+        g[0, 0, 0, 0] = g[1, 1, 1, 1] = U
+        p = _prob("spinfree", 2, 1, 1, np.array([[1, 1]], np.uint64), h, g)
+        e2, kept, nq = sc.pt2(p, [1.0], e0)
+        assert abs(e2[0] - 2 * t * t / e0) < 1e-15
+        assert (kept, nq) == (3, 3)
+
+
+def _pt2_case(kind, seed, npick, nroots=2):
+    rng = np.random.default_rng(seed)
+    if kind == "spinfree":
+        n, na, nb = 6, 2, 2
+        full = _prob("spinfree", n, na, nb, synth.space_fci(n, na, nb), *_random_real(n, seed))
+    else:
+        nk, nel = 4, 3
+        full = _prob("spinor", nk, nel, -1, _spinor_space(nk, nel), *_random_spinor(nk, seed))
+    H = literal.hamiltonian(full)
+    pidx = np.sort(rng.choice(full.ndet, npick, replace=False))
+    P = _prob(kind, full.norb, full.nalpha, full.nbeta, full.dets[pidx], full.h, full.g)
+    c = rng.normal(size=(npick, nroots))
+    if kind == "spinor":
+        c = c + 1j * rng.normal(size=(npick, nroots))
+    d = np.real(np.diag(H))
+    e0 = d.min() - 1.0 - np.arange(nroots)
+    return full, H, pidx, P, c, e0
+
+
+@pytest.mark.parametrize("kind,seed,npick", [("spinfree", 0, 40), ("spinfree", 1, 7), ("spinor", 2, 12),
+                                              ("spinor", 3, 30)])
+def test_pt2_equals_dense_literal(kind, seed, npick):
+    """E2 and the structural counts against the dense literal H over the
+    complete space (independent of the tier-B excitation enumeration and
+    Slater-Condon rules): catches a missed excitation class, a wrong phase
+    (numerators interfere), a wrong diagonal or conjugation."""
+    full, H, pidx, P, c, e0 = _pt2_case(kind, seed, npick)
+    e2, kept, nq = sc.pt2(P, c, e0)
+    ref, rk, rq = _pt2_dense(full, H, pidx, c, e0)
+    assert (kept, nq) == (rk, rq)
+    assert np.abs(e2 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kind", ["spinfree", "spinor"])
+def test_pt2_screening_rule(kind):
+    """qmin drops a double (A, J) when |H_AJ| max_k |c_Jk| < qmin: a huge
+    qmin leaves the singles only, a middle one a mask of the doubles."""
+    full, H, pidx, P, c, e0 = _pt2_case(kind, 4, 25)
+    for qmin in (1e9, 0.02, 0.002):
+        e2, kept, nq = sc.pt2(P, c, e0, qmin=qmin)
+        ref, rk, rq = _pt2_dense(full, H, pidx, c, e0, qmin=qmin)
+        assert (kept, nq) == (rk, rq)
+        assert np.abs(e2 - ref).max() <= 1e-12 * np.abs(ref).max()
+    e_all = sc.pt2(P, c, e0)
+    e_sing = sc.pt2(P, c, e0, qmin=1e9)
+    assert e_sing[1] < e_all[1]
+
+
+def test_pt2_complete_space_is_zero():
+    """P = the complete space leaves nothing outside: E2 = 0."""
+    p = _prob("spinfree", 5, 2, 2, synth.space_fci(5, 2, 2), *_random_real(5, 7))
+    e2, kept, nq = sc.pt2(p, np.ones(p.ndet), -3.0)
+    assert e2[0] == 0.0 and kept == 0 and nq == 0
+
+
+def test_pt2_w_minus_p_identity():
+    """The rewriting of the second-order energy used by the paper: E2[Q] =
+    E2[W] - E2[P], with W = P + Q, E2[W] over every I of W without the
+    I = J term, and E2[P] = sum over P of |sigma_I - H_II c_I|^2 /
+    (E0 - H_II); and at an eigenvector of the P block, E2[P] =
+    sum c_I^2 (E0 - H_II)."""
+    full, H, pidx, P, c, e0 = _pt2_case("spinfree", 5, 30, nroots=1)
+    x = literal.packed(full)
+    outside = np.setdiff1d(np.arange(full.ndet), pidx)
+    lvl = np.bitwise_count(x[:, None] ^ x[pidx][None, :]).astype(np.int64)
+    W = np.concatenate([pidx, outside[(lvl[outside] == 2).any(1) | (lvl[outside] == 4).any(1)]])
+    Hoff = H.copy()
+    np.fill_diagonal(Hoff, 0.0)
+    # eigenvector of the P block
+    w, V = np.linalg.eigh(H[np.ix_(pidx, pidx)])
+    for cc, ee in [(c[:, 0], e0[0]), (V[:, 0], w[0])]:
+        num_w = Hoff[np.ix_(W, pidx)] @ cc
+        e2w = np.sum(num_w ** 2 / (ee - np.diag(H)[W]))
+        sig = H[np.ix_(pidx, pidx)] @ cc
+        dP = np.diag(H)[pidx]
+        e2p = np.sum((sig - dP * cc) ** 2 / (ee - dP))
+        e2, _, _ = sc.pt2(P, cc, ee)
+        assert abs(e2[0] - (e2w - e2p)) <= 1e-11 * abs(e2[0])
+        if ee == w[0]:
+            assert abs(e2p - np.sum(cc ** 2 * (ee - dP))) <= 1e-11 * abs(e2p)
