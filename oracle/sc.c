@@ -520,14 +520,22 @@ void orc_pt2(int kind, int n, const double *h, const double *g, double ecore,
                 contrib[a * nroots + k] = (num[k].re * num[k].re + num[k].im * num[k].im) / (e0[k] - haa);
         }
     }
-    for (int k = 0; k < nroots; k++) e2[k] = 0.0;
+    /* millions of terms: compensated (Neumaier) summation in ascending A, so
+     * that the total carries no O(N eps) accumulation error */
     long kept = 0, nq = 0;
-    for (long a = 0; a < nA; a++) {
-        if (!used[a]) continue;
-        kept += used[a];
-        nq++;
-        for (int k = 0; k < nroots; k++) e2[k] += contrib[a * nroots + k];
+    for (int k = 0; k < nroots; k++) {
+        double s = 0.0, comp = 0.0;
+        for (long a = 0; a < nA; a++) {
+            if (!used[a]) continue;
+            double x = contrib[a * nroots + k], t = s + x;
+            if (fabs(s) >= fabs(x)) comp += (s - t) + x;
+            else comp += (x - t) + s;
+            s = t;
+        }
+        e2[k] = s + comp;
     }
+    for (long a = 0; a < nA; a++)
+        if (used[a]) { kept += used[a]; nq++; }
     if (stats) { stats[0] = kept; stats[1] = nq; }
     free(head);
     free(contrib);
