@@ -23,11 +23,14 @@ Further legs reported in the same line (skip with --legs none):
             determinants;
   rdm       forward sigma + energy and backward density matrices (gamma,
             Gamma) on the headline space;
-  davidson  time per Davidson iteration on the headline space.
+  davidson  time per Davidson iteration on the headline space;
+  pt2       Epstein-Nesbet second-order energy of the lowest root of a
+            20,000-determinant n=64 10a10b space over its external space
+            (exact and screened).
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
                        [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
-                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson|none]
+                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson,pt2|none]
 """
 from __future__ import annotations
 
@@ -85,7 +88,7 @@ def main():
     ap.add_argument("--roots", type=int, default=1)
     ap.add_argument("--workload", default="sci-n64", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=30000, help="rows of the CPU oracle sample (0: skip)")
-    ap.add_argument("--legs", default="batched,spinor,rdm,davidson")
+    ap.add_argument("--legs", default="batched,spinor,rdm,davidson,pt2")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -212,6 +215,8 @@ def main():
         out["legs"]["batched"] = leg_batched()
     if "spinor" in legs:
         out["legs"]["spinor"] = leg_spinor(args.steps)
+    if "pt2" in legs:
+        out["legs"]["pt2"] = leg_pt2()
 
     if args.cpu_rows > 0:
         from oracle import sc
@@ -304,7 +309,13 @@ def leg_batched():
     outs1 = [[torch.empty_like(x) for x in row] for row in cs1]
     bpc = mw.autotune_batched(plans, cs, outs)
     t_batched = _time(lambda: mw.sigma_batched(plans, cs, outs), 10)
-    t_plain4 = _time(lambda: [pl.sigma(c, out=o) for pl, c, o in zip(plans, cs, outs)], 5)
+    # per-problem baseline: the better of the default and the tuned launch
+    # parameters of each plan
+    t_plain4_default = _time(lambda: [pl.sigma(c, out=o) for pl, c, o in zip(plans, cs, outs)], 5)
+    for pl, c, o in zip(plans, cs, outs):
+        pl.autotune(c, o)
+    t_plain4_tuned = _time(lambda: [pl.sigma(c, out=o) for pl, c, o in zip(plans, cs, outs)], 5)
+    t_plain4 = min(t_plain4_default, t_plain4_tuned)
     t_plain1 = _time(lambda: [pl.sigma(x, out=o) for pl, row, orow in zip(plans, cs1, outs1)
                               for x, o in zip(row, orow)], 5)
     pairs = sum(pl.info("pairs") for pl in plans)
@@ -312,9 +323,48 @@ def leg_batched():
     log(f"[bench] batched: graph {t_batched:.2f} ms, 16x4-root {t_plain4:.2f} ms, 64x1-root {t_plain1:.2f} ms")
     return {"workload": "batch16-n16..48-6..12e-1e4..5e5-R4", "ndet_total": sum(p.ndet for p in probs),
             "pairs_total": pairs, "blocks_per_cu": bpc,
-            "batched_graph_ms": t_batched, "plain_16x4_ms": t_plain4, "plain_64x1_ms": t_plain1,
+            "batched_graph_ms": t_batched, "plain_16x4_ms": t_plain4,
+            "plain_16x4_default_ms": t_plain4_default, "plain_16x4_tuned_ms": t_plain4_tuned,
+            "plain_64x1_ms": t_plain1,
             "batched_terms_per_s": terms / (t_batched * 1e-3),
             "speedup_vs_16x4": t_plain4 / t_batched, "speedup_vs_64x1": t_plain1 / t_batched}
+
+
+def leg_pt2():
+    """Second-order energy of the lowest root of a 20,000-determinant
+    n=64 10a10b variational space over its external space (exact, and with
+    the doubles screening at Q_min = 1e-7)."""
+    import torch
+    from paper_2501_18185_amd import mw, synth
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    p = synth.workload(5)
+    pl = mw.Plan(p, max_roots=1)
+    dg = pl.diag().cpu().numpy()
+    c0 = np.zeros((p.ndet, 1))
+    c0[int(np.argmin(dg)), 0] = 1.0
+    ev, X, it, conv = pl.davidson(torch.from_numpy(c0).cuda(), tol=1e-6, max_iter=100, check=False)
+    x = X[:, 0].contiguous()
+    log(f"[bench] pt2: space {p.ndet} dets, E0 = {ev[0]:.10f} after {it} Davidson iterations "
+        f"({time.perf_counter() - t0:.1f}s)")
+    res = {"workload": "pt2-n64-10a10b-2e4", "ndet": p.ndet, "e0": float(ev[0])}
+    for qmin in (0.0, 1e-7):
+        torch.cuda.synchronize()
+        mw.profile(True)
+        t1 = time.perf_counter()
+        e2, st = pl.pt2(x, ev[0], qmin=qmin)
+        dt = time.perf_counter() - t1
+        mw.profile(False)
+        _, t_enum = mw.profile_read("pt2_enum")
+        _, t_bucket = mw.profile_read("pt2_bucket")
+        key = "exact" if qmin == 0.0 else "screened"
+        res[key] = {"qmin": qmin, "e2": float(e2[0]), "seconds": dt, "excitations_enumerated": st["enumerated"],
+                    "pairs_kept": st["kept_pairs"], "external_dets": st["external"], "passes": st["passes"],
+                    "buckets": st["buckets"], "kept_pairs_per_s": st["kept_pairs"] / dt,
+                    "emit_ms": t_enum, "bucket_ms": t_bucket}
+        log(f"[bench] pt2 {key}: E2 = {e2[0]:.10f}, {st['kept_pairs']} pairs, {st['external']} external dets, "
+            f"{st['passes']} passes, {dt:.2f}s (emit {t_enum:.0f} ms, buckets {t_bucket:.0f} ms)")
+    return res
 
 
 def leg_spinor(steps):

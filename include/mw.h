@@ -138,7 +138,9 @@ mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *n
                            const void *const *c, void *const *sigma, mw_stream_t stream);
 
 /* The batched product with an explicit persistent grid (blocks_per_cu x the
- * number of compute units), launched directly without graph capture. */
+ * number of compute units, each wave pulling packets from per-XCD work
+ * queues) or, with blocks_per_cu = 0, one hardware-dispatched wave per
+ * packet of all problems; launched directly without graph capture. */
 mw_status mw_sigma_batched_direct(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                                   const void *const *c, void *const *sigma, int32_t blocks_per_cu,
                                   mw_stream_t stream);
@@ -150,9 +152,11 @@ mw_status mw_sigma_batched_direct(int32_t nprob, const mw_plan *plans, const int
 mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream,
                       int32_t *choice);
 
-/* Autotuner for mw_sigma_batched: times persistent grids of 1, 2, 4, 8, 16
- * blocks per compute unit for this argument tuple and uses the fastest for
- * its graph from then on; *blocks_per_cu (host, nullable) receives it. */
+/* Autotuner for mw_sigma_batched: times the flat grid and persistent grids
+ * of 1, 2, 4, 8, 16 blocks per compute unit, each with a partner unroll of
+ * 4 or 8 for four-root passes, for this argument tuple, and uses the
+ * fastest for its graph from then on; *blocks_per_cu (host, nullable)
+ * receives the grid (0 = flat). */
 mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                               const void *const *c, void *const *sigma, mw_stream_t stream,
                               int32_t *blocks_per_cu);
@@ -185,6 +189,26 @@ mw_status mw_davidson_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
 mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out, double *evals,
                       double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
                       mw_stream_t stream);
+
+/* Epstein-Nesbet second-order energies (section 2.5, Eq. (ENPT2E), with
+ * the primary space equal to the plan's space P):
+ *   e2[k] = sum_{A in Q} |sum_{J in P} H_AJ c[J][k]|^2 / (e0[k] - H_AA),
+ * Q = every determinant outside P that one or two excitations reach from a
+ * J of P (spin-free: N_alpha and N_beta kept).  Screening as in the paper's
+ * PT2 procedure: a doubly excited pair (A, J) is left out when
+ * |H_AJ| max_k |c[J][k]| < qmin (qmin = 0 keeps every pair).
+ * c: device [ndet][nroots] (complex for spinor plans), 1 <= nroots <= 8;
+ * e0, e2: HOST [nroots].  work: device scratch of work_bytes bytes; the
+ * connections are generated in passes over hash buckets of A sized to fit
+ * it (mw_pt2_work_bytes gives the size for one pass without screening;
+ * less memory means more passes; MW_EWORKSPACE if too small for the bucket
+ * tables or one bucket).  stats: HOST int64[5], nullable: kept (A, J)
+ * pairs with A in Q, number of A in Q, passes, buckets, excitations
+ * enumerated per pass (ndet x singles and doubles of one determinant).
+ * Host-driven, synchronises the stream; repeated calls give identical bits. */
+mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
+mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const double *e0, double qmin, void *work,
+                 size_t work_bytes, double *e2, int64_t *stats, mw_stream_t stream);
 
 /* Debug: connected pairs of all rows with their phases, as int64 records
  * [I, J, P, Q, R, S, sign] (R = S = -1 for singles; P, R particles in I; Q, S

@@ -28,11 +28,12 @@ struct BatchEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int bpc = 0;  // persistent blocks per compute unit used when captured
+    int u4 = 0;   // four-root partner unroll used when captured
 };
 
 std::mutex g_mu;
 std::map<BatchKey, BatchEntry> g_cache;
-std::map<BatchKey, int> g_tuned_bpc;  // autotuned blocks per CU, by batch
+std::map<BatchKey, std::pair<int, int>> g_tuned;  // autotuned (blocks per CU, four-root unroll), by batch
 hipStream_t g_capture_stream = nullptr;
 int g_num_cu = 0;
 
@@ -50,7 +51,7 @@ int num_cu()
 }
 
 mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, const void *const *c,
-                    void *const *sigma, BatchArgs &a, bool &cplx, BatchKey &key)
+                    void *const *sigma, BatchSet &b, bool &cplx, BatchKey &key)
 {
     if (nprob < 1 || nprob > MW_MAXB) return fail(MW_EUNSUPPORTED, "nprob must be in 1..32");
     if (!plans || !nroots || !c || !sigma) return fail(MW_EINVAL, "NULL argument");
@@ -69,6 +70,7 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
     std::vector<int> ord(nprob);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x]->nmem > d[y]->nmem; });
+    BatchArgs &a = b.all;
     a = BatchArgs{};
     a.nprob = nprob;
     a.pk_start[0] = 0;
@@ -85,6 +87,28 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
     if (a.pk_start[nprob] >= 0xffffffffLL || a.blk_start[nprob] >= 0x7fffffffLL)
         return fail(MW_EUNSUPPORTED, "too many packets in one batch");
     a.counter = d[ord[0]]->counter;
+    // per root-chunk width: problems with a chunk of 4, 2 or 1 roots
+    for (int cl = 0; cl < 3; cl++) {
+        BatchArgs &e = b.cls[cl];
+        e = BatchArgs{};
+        e.pk_start[0] = 0;
+        e.counter = a.counter + 8 * cl;
+        for (int k = 0; k < nprob; k++) {
+            const int R = a.R[k];
+            bool has = false;
+            for (int r0 = 0; r0 < R; r0 += 4) {
+                const int left = R - r0, wd = left == 1 ? 1 : (left == 2 ? 2 : 4);
+                has = has || wd == (cl == 0 ? 4 : (cl == 1 ? 2 : 1));
+            }
+            if (!has) continue;
+            const int j = e.nprob++;
+            e.plans[j] = a.plans[k];
+            e.c[j] = a.c[k];
+            e.sigma[j] = a.sigma[k];
+            e.R[j] = R;
+            e.pk_start[j + 1] = e.pk_start[j] + (a.pk_start[k + 1] - a.pk_start[k]);
+        }
+    }
     key.v.clear();
     for (int i = 0; i < nprob; i++) {
         key.v.push_back((uintptr_t)plans[i]);
@@ -95,7 +119,7 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
     return MW_OK;
 }
 
-mw_status capture(const BatchArgs &a, bool cplx, int bpc, BatchEntry &e)
+mw_status capture(const BatchSet &a, bool cplx, int bpc, BatchEntry &e)
 {
     if (!g_capture_stream && hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(MW_EHIP, "hipStreamCreateWithFlags failed");
@@ -114,6 +138,7 @@ mw_status capture(const BatchArgs &a, bool cplx, int bpc, BatchEntry &e)
     e.graph = g;
     e.exec = ex;
     e.bpc = bpc;
+    e.u4 = a.u4;
     return MW_OK;
 }
 
@@ -141,27 +166,30 @@ void mw_internal_batched_forget(mw_plan plan)
             ++it;
         }
     }
-    for (auto it = g_tuned_bpc.begin(); it != g_tuned_bpc.end();) {
+    for (auto it = g_tuned.begin(); it != g_tuned.end();) {
         bool hit = false;
         for (size_t i = 0; i < it->first.v.size(); i += 4) hit = hit || it->first.v[i] == (uintptr_t)plan;
-        it = hit ? g_tuned_bpc.erase(it) : std::next(it);
+        it = hit ? g_tuned.erase(it) : std::next(it);
     }
 }
 
 extern "C" mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                                       const void *const *c, void *const *sigma, mw_stream_t stream)
 {
-    BatchArgs a;
+    BatchSet a;
     bool cplx;
     BatchKey key;
     mw_status st = make_args(nprob, plans, nroots, c, sigma, a, cplx, key);
     if (st != MW_OK) return st;
     std::lock_guard<std::mutex> lk(g_mu);
     int bpc = 8;
-    auto tb = g_tuned_bpc.find(key);
-    if (tb != g_tuned_bpc.end()) bpc = tb->second;
+    auto tb = g_tuned.find(key);
+    if (tb != g_tuned.end()) {
+        bpc = tb->second.first;
+        a.u4 = tb->second.second;
+    }
     auto it = g_cache.find(key);
-    if (it != g_cache.end() && it->second.bpc != bpc) {
+    if (it != g_cache.end() && (it->second.bpc != bpc || it->second.u4 != a.u4)) {
         drop(it->second);
         g_cache.erase(it);
         it = g_cache.end();
@@ -182,12 +210,12 @@ extern "C" mw_status mw_sigma_batched_direct(int32_t nprob, const mw_plan *plans
                                              const void *const *c, void *const *sigma, int32_t blocks_per_cu,
                                              mw_stream_t stream)
 {
-    BatchArgs a;
+    BatchSet a;
     bool cplx;
     BatchKey key;
     mw_status st = make_args(nprob, plans, nroots, c, sigma, a, cplx, key);
     if (st != MW_OK) return st;
-    if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(MW_EINVAL, "blocks_per_cu must be in 1..64");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(MW_EINVAL, "blocks_per_cu must be in 0..64");
     return launch_batched(a, cplx, num_cu() * blocks_per_cu, (hipStream_t)stream, true);
 }
 
@@ -243,27 +271,32 @@ extern "C" mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, vo
 }
 
 // Autotuner for batched sigma: tries the persistent grid (blocks per CU) and
-// keeps the fastest for this batch; the captured graph is rebuilt with it.
+// the partner unroll of the four-root launch, keeps the fastest for this
+// batch; the captured graph is rebuilt with it.
 extern "C" mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                                          const void *const *c, void *const *sigma, mw_stream_t stream,
                                          int32_t *blocks_per_cu)
 {
-    BatchArgs a;
+    BatchSet a;
     bool cplx;
     BatchKey key;
     mw_status st = make_args(nprob, plans, nroots, c, sigma, a, cplx, key);
     if (st != MW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     double best = 1e30;
-    int bb = 8;
+    int bb = 8, bu = 4;
     mw_status err = MW_OK;
-    for (int bpc : {1, 2, 4, 8, 16}) {
-        double t = time_ms(s, 3, [&]() { return launch_batched(a, cplx, num_cu() * bpc, s, false); }, &err);
-        if (err != MW_OK) return err;
-        if (t < best) { best = t; bb = bpc; }
+    for (int u4 : {4, 8}) {
+        a.u4 = u4;
+        // bpc 0: the flat (hardware-dispatched) grid instead of the work queue
+        for (int bpc : {0, 1, 2, 4, 8, 16}) {
+            double t = time_ms(s, 3, [&]() { return launch_batched(a, cplx, num_cu() * bpc, s, false); }, &err);
+            if (err != MW_OK) return err;
+            if (t < best) { best = t; bb = bpc; bu = u4; }
+        }
     }
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned_bpc[key] = bb;
+    g_tuned[key] = {bb, bu};
     if (blocks_per_cu) *blocks_per_cu = bb;
     return MW_OK;
 }

@@ -39,36 +39,7 @@ __global__ __launch_bounds__(256) void k_diag(DevPlan p)
     using T = typename Scal<CPLX>::T;
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= p.ndet) return;
-    const int n = p.n;
-    const T *h = (const T *)p.h;
-    const T *w = (const T *)p.w_same;
-    const T *wo = (const T *)p.w_opp;
-    uint64_t d0 = p.dets[2 * I], d1 = p.dets[2 * I + 1];
-    T e = sc_zero(T());
-    if constexpr (CPLX) e = make_double2(p.ecore, 0.0);
-    else e = p.ecore;
-    const int M = p.M;
-    // positions ascending: word 0 then word 1
-    for (int wa = 0; wa < 2; wa++) {
-        for (uint64_t xa = wa ? d1 : d0; xa; xa &= xa - 1) {
-            int a = __builtin_ctzll(xa);
-            int A = wa * n + a;
-            if constexpr (CPLX) e = sc_add(e, h[(size_t)A * M + A]);
-            else e = sc_add(e, h[(size_t)a * n + a]);
-            // partners B > A
-            for (int wb = wa; wb < 2; wb++) {
-                uint64_t xb = wb ? d1 : d0;
-                if (wb == wa) xb &= (a == 63) ? 0ULL : ~((2ULL << a) - 1);
-                for (; xb; xb &= xb - 1) {
-                    int b = __builtin_ctzll(xb);
-                    int B = wb * n + b;
-                    if constexpr (CPLX) e = sc_add(e, w[((size_t)B * M + A) * M + A]);
-                    else e = sc_add(e, (wb == wa) ? w[((size_t)b * n + a) * n + a] : wo[((size_t)b * n + a) * n + a]);
-                }
-            }
-        }
-    }
-    ((T *)p.diag)[I] = e;
+    ((T *)p.diag)[I] = diag_value<CPLX>(p, p.dets[2 * I], p.dets[2 * I + 1]);
 }
 
 mw_status launch_diag(const DevPlan &p, hipStream_t s)
@@ -85,47 +56,6 @@ mw_status launch_diag(const DevPlan &p, hipStream_t s)
 // group contraction
 // ---------------------------------------------------------------------------
 
-// Single-excitation element <K+P_i| H |K+P_j> / (phi_i phi_j), read as the
-// (j, i) entry and conjugated:  F^K_{P_j P_i} = h_{P_j P_i} + sum_{R in K}
-// [(P_j P_i|R R) - (P_j R|R P_i)]  (spin-free: the exchange part only for R
-// of the same spin).  Evaluated from the reference table F^omega plus the
-// positions where K and omega differ.
-template <bool CPLX>
-__device__ __forceinline__ typename Scal<CPLX>::T single_element(const DevPlan &p, uint8_t type, uint64_t k0,
-                                                                  uint64_t k1, int Xi, int Xj)
-{
-    using T = typename Scal<CPLX>::T;
-    const T *w = (const T *)p.w_same;
-    const int n = p.n;
-    if constexpr (CPLX) {
-        const int M = p.M;
-        const size_t base = (size_t)Xj * M + Xi, stride = (size_t)M * M;
-        T f = ((const T *)p.f_ref)[base];
-        T add = sc_zero(T()), sub = sc_zero(T());
-        for (uint64_t x = k0 & ~p.ref0; x; x &= x - 1) add = sc_add(add, w[(size_t)__builtin_ctzll(x) * stride + base]);
-        for (uint64_t x = k1 & ~p.ref1; x; x &= x - 1) add = sc_add(add, w[(size_t)(n + __builtin_ctzll(x)) * stride + base]);
-        for (uint64_t x = p.ref0 & ~k0; x; x &= x - 1) sub = sc_add(sub, w[(size_t)__builtin_ctzll(x) * stride + base]);
-        for (uint64_t x = p.ref1 & ~k1; x; x &= x - 1) sub = sc_add(sub, w[(size_t)(n + __builtin_ctzll(x)) * stride + base]);
-        f = sc_add(f, add);
-        f = make_double2(f.x - sub.x, f.y - sub.y);
-        return sc_conj(f);
-    } else {
-        const T *wo = (const T *)p.w_opp;
-        const int s = type == G_SINGLE_A ? 0 : 1;
-        const int pi = Xi - s * n, pj = Xj - s * n;
-        const size_t base = (size_t)pj * n + pi, stride = (size_t)n * n;
-        T f = ((const T *)p.f_ref)[(size_t)s * stride + base];
-        const uint64_t ks = s ? k1 : k0, ko = s ? k0 : k1;
-        const uint64_t rs = s ? p.ref1 : p.ref0, ro = s ? p.ref0 : p.ref1;
-        T add = 0.0, sub = 0.0;
-        for (uint64_t x = ks & ~rs; x; x &= x - 1) add += w[(size_t)__builtin_ctzll(x) * stride + base];
-        for (uint64_t x = ko & ~ro; x; x &= x - 1) add += wo[(size_t)__builtin_ctzll(x) * stride + base];
-        for (uint64_t x = rs & ~ks; x; x &= x - 1) sub += w[(size_t)__builtin_ctzll(x) * stride + base];
-        for (uint64_t x = ro & ~ko; x; x &= x - 1) sub += wo[(size_t)__builtin_ctzll(x) * stride + base];
-        return (f + add) - sub;
-    }
-}
-
 // Offset of the double-excitation integral A(pair_i, pair_j) = (P Q|R S) -
 // (P S|R Q), with (P,R) added in i and (Q,S) added in j, read as the (j, i)
 // entry of its table: column part (depends on i only) + row part (j only).
@@ -135,10 +65,12 @@ __device__ __forceinline__ typename Scal<CPLX>::T single_element(const DevPlan &
 struct DoubleIndex {
     size_t col;
     size_t row_stride;
-    int n, off, ab;
+    int n, off, ab, lay;
     __device__ __forceinline__ size_t row(int Xj, int Yj) const
     {
-        if (ab) return ((size_t)Xj * n + (Yj - n)) * row_stride;
+        // alpha-beta, layout 1: the row (s_j, q_j) of the same table holds
+        // the row (q_j, s_j) with the column indices transposed
+        if (ab) return (lay ? (size_t)(Yj - n) * n + Xj : (size_t)Xj * n + (Yj - n)) * row_stride;
         return (size_t)pair_idx(Xj - off, Yj - off) * row_stride;
     }
 };
@@ -150,9 +82,10 @@ __device__ __forceinline__ DoubleIndex double_index(const DevPlan &p, uint8_t ty
 {
     DoubleIndex d;
     d.n = p.n;
+    d.lay = lay;
     if (!CPLX && type == G_AB) {
-        // (p_i q_j | r_i s_j) stored as g_ab[q][s][p][r] (layout 0) or
-        // g_ab1[q][s][r][p] (layout 1)
+        // (p_i q_j | r_i s_j) = g_ab[q][s][p][r] (layout 0) = g_ab[s][q][r][p]
+        // (layout 1: p fastest across the lanes)
         d.ab = 1;
         d.off = 0;
         d.row_stride = (size_t)p.n * p.n;
@@ -171,14 +104,170 @@ __device__ __forceinline__ DoubleIndex double_index(const DevPlan &p, uint8_t ty
 // Double groups.  Lane = member i; the partner loop is unrolled by U so that
 // U member records, U integrals and U coefficient rows are in flight at once
 // (the loop is bound by memory latency, not arithmetic).
+// ---------------------------------------------------------------------------
+// Large double groups (k >= 64): each unordered pair once
+// ---------------------------------------------------------------------------
+
+// Wave sum of 8 values per lane, scattered: afterwards lane l holds the sum
+// over all 64 lanes of value vi(l) = 4 b5 + 2 b4 + b3 (bits of l); the 8
+// lanes that differ only in bits 0-2 hold the same value.  Fixed butterfly
+// (10 shuffles), so the result does not depend on timing.
+__device__ __forceinline__ double shx(double v, int m) { return __shfl_xor(v, m); }
+__device__ __forceinline__ double2 shx(double2 v, int m) { return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m)); }
+__device__ __forceinline__ double shl(double v, int s) { return __shfl(v, s); }
+__device__ __forceinline__ double2 shl(double2 v, int s) { return make_double2(__shfl(v.x, s), __shfl(v.y, s)); }
+
+constexpr int RS_NV = 8;
+
+template <typename T>
+__device__ __forceinline__ T reduce_scatter8(const T (&col)[RS_NV], int lane)
+{
+    T w4[4], w2[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+#pragma unroll
+    for (int v = 0; v < 4; v++) w4[v] = sc_add(h5 ? col[v + 4] : col[v], shx(h5 ? col[v] : col[v + 4], 32));
+#pragma unroll
+    for (int v = 0; v < 2; v++) w2[v] = sc_add(h4 ? w4[v + 2] : w4[v], shx(h4 ? w4[v] : w4[v + 2], 16));
+    T w = sc_add(h3 ? w2[1] : w2[0], shx(h3 ? w2[0] : w2[1], 8));
+    w = sc_add(w, shx(w, 4));
+    w = sc_add(w, shx(w, 2));
+    return sc_add(w, shx(w, 1));
+}
+
+__device__ __forceinline__ int rs_value_of_lane(int l) { return ((l >> 5) & 1) * 4 + ((l >> 4) & 1) * 2 + ((l >> 3) & 1); }
+__device__ __forceinline__ int rs_lane_of_value(int v) { return ((v >> 2) & 1) << 5 | ((v >> 1) & 1) << 4 | (v & 1) << 3; }
+
+// One wave = block a (64 consecutive members) of a group with k >= 64
+// members.  It visits the partners in blocks b >= a (strictly later members
+// inside block a), evaluates H_ij once per unordered pair, adds H_ij c_j to
+// the row sum of i, and sums H_ji c_i = conj(H_ij) c_i over its lanes: for
+// b == a the sum goes to the lane holding j, for b > a it is written to the
+// column-partial slot of (a, j) that the gather adds to j's determinant.
+template <bool CPLX, int RC>
+__device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfirst, uint32_t mend, int lane, int R,
+                                                  int r0, const typename Scal<CPLX>::T *__restrict__ c,
+                                                  typename Scal<CPLX>::T *__restrict__ partial)
+{
+    using T = typename Scal<CPLX>::T;
+    constexpr int JS = RS_NV / RC;         // partners per reduction pass (all loaded at once)
+    const uint32_t g = p.mem_grp[mfirst];
+    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
+    const uint32_t k = j1 - j0;
+    const uint32_t a = (mfirst - j0) >> 6;
+    const uint32_t nb = (k + 63) >> 6;
+    const uint8_t type = p.grp_type[g];
+    const uint32_t m = mfirst + lane;
+    const bool act = m < mend;
+    const uint2 me = p.mem[act ? m : mfirst];
+    const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
+    const uint32_t negi = (me.y >> 16) & 1;
+    const bool lay = (me.y >> 17) & 1;
+    const DoubleIndex di = double_index<CPLX>(p, type, Xi, Yi, lay);
+    const T *tab = (const T *)((!CPLX && type == G_AB) ? p.g_ab : (lay ? p.a_pair1 : p.a_pair));
+    const int nr = min(RC, R - r0);
+    // acc: row sum in partner order; dacc: the one column sum delivered from
+    // the member's own block, added at the end so that the result does not
+    // depend on how partners are batched into passes
+    T ci[RC], acc[RC], dacc[RC];
+#pragma unroll
+    for (int kk = 0; kk < RC; kk++) {
+        ci[kk] = act ? c[(size_t)me.x * R + r0 + (kk < nr ? kk : 0)] : sc_zero(T());
+        acc[kk] = sc_zero(T());
+        dacc[kk] = sc_zero(T());
+    }
+    const size_t colbase = (size_t)p.nmem + p.grp_col[g] + (size_t)a * k - 32 * (size_t)a * (a + 1);
+    for (uint32_t b = a; b < nb; b++) {
+        const uint32_t jb0 = j0 + 64 * b, jb1 = min(j1, jb0 + 64);
+        for (uint32_t jj = jb0; jj < jb1; jj += JS) {
+            T col[RS_NV];
+            {
+                uint2 o[JS];
+                bool hit[JS];
+                T v[JS];
+                T cj[JS][RC];
+#pragma unroll
+                for (int u = 0; u < JS; u++) {
+                    const uint32_t j = jj + u;
+                    const bool in = act && j < jb1 && (b > a || j > m);
+                    o[u] = p.mem[j < jb1 ? j : jb0];
+                    const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
+                    hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
+                    v[u] = tab[hit[u] ? di.row(Xj, Yj) + di.col : 0];
+                    const T *cr = c + (size_t)(hit[u] ? o[u].x : 0) * R + r0;
+#pragma unroll
+                    for (int kk = 0; kk < RC; kk++) cj[u][kk] = cr[kk < nr ? kk : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < JS; u++) {
+                    T x = sc_neg(CPLX ? sc_conj(v[u]) : v[u], (negi ^ ((o[u].y >> 16) & 1)) != 0);
+                    if (!hit[u]) x = sc_zero(T());
+                    const T xh = CPLX ? sc_conj(x) : x;
+#pragma unroll
+                    for (int kk = 0; kk < RC; kk++) {
+                        acc[kk] = sc_add(acc[kk], sc_mul(x, cj[u][kk]));
+                        col[u * RC + kk] = sc_mul(xh, ci[kk]);
+                    }
+                }
+            }
+            const T s = reduce_scatter8(col, lane);
+            if (b == a) {
+                // members jj .. jj+JS-1 live in lanes jj-jb0 .. of this wave
+                const int t0 = (int)(jj - jb0);
+                const bool tgt = lane >= t0 && lane < t0 + JS;
+#pragma unroll
+                for (int kk = 0; kk < RC; kk++) {
+                    const int vi = (tgt ? lane - t0 : 0) * RC + kk;
+                    const T got = shl(s, rs_lane_of_value(vi));
+                    if (tgt && kk < nr) dacc[kk] = got;
+                }
+            } else if ((lane & 7) == 0) {
+                const int vi = rs_value_of_lane(lane);
+                const uint32_t j = jj + vi / RC;
+                const int kk = vi % RC;
+                if (j < jb1 && kk < nr)
+                    partial[(colbase + (j - j0) - 64 * (a + 1)) * R + r0 + kk] = s;
+            }
+        }
+    }
+    if (act) {
+        T *out = partial + (size_t)m * R + r0;
+#pragma unroll
+        for (int kk = 0; kk < RC; kk++)
+            if (kk < nr) out[kk] = sc_add(acc[kk], dacc[kk]);
+    }
+}
+
 template <bool CPLX, int RC, int U>
 __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave, int lane, int R, int r0,
                                                   const typename Scal<CPLX>::T *__restrict__ c,
                                                   typename Scal<CPLX>::T *__restrict__ partial)
 {
     using T = typename Scal<CPLX>::T;
-    const uint32_t m = p.pk_off[wave] + lane;
-    if (m >= p.pk_off[wave + 1]) return;
+    const uint32_t mfirst = p.pk_off[wave], mend = p.pk_off[wave + 1];
+    {
+        // a packet of a large group is one 64-member block of it (uniform)
+        const uint32_t g0 = p.mem_grp[mfirst];
+        const uint32_t k = p.grp_off[g0 + 1] - p.grp_off[g0];
+        if (k >= 64) {
+            if (RC <= 2) {
+                group_double_half<CPLX, RC>(p, mfirst, mend, lane, R, r0, c, partial);
+                return;
+            }
+            // With four roots per pass the integral load is already shared
+            // by the roots and the column reductions would dominate, so the
+            // block does the full row sums; the column slots it owns (which
+            // the gather still reads) carry nothing for these roots.
+            const uint32_t a = (mfirst - p.grp_off[g0]) >> 6;
+            if (k > 64 * (a + 1)) {
+                const size_t colbase = (size_t)p.nmem + p.grp_col[g0] + (size_t)a * k - 32 * (size_t)a * (a + 1);
+                const int nr = min(RC, R - r0);
+                for (uint32_t t = lane; t < k - 64 * (a + 1); t += 64)
+                    for (int kk = 0; kk < nr; kk++) partial[(colbase + t) * R + r0 + kk] = sc_zero(T());
+            }
+        }
+    }
+    const uint32_t m = mfirst + lane;
+    if (m >= mend) return;
     const uint32_t g = p.mem_grp[m];
     const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
     const uint8_t type = p.grp_type[g];
@@ -187,7 +276,7 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
     const uint32_t negi = (me.y >> 16) & 1;
     const bool lay = (me.y >> 17) & 1;
     const DoubleIndex di = double_index<CPLX>(p, type, Xi, Yi, lay);
-    const T *tab = (const T *)((!CPLX && type == G_AB) ? (lay ? p.g_ab1 : p.g_ab) : (lay ? p.a_pair1 : p.a_pair));
+    const T *tab = (const T *)((!CPLX && type == G_AB) ? p.g_ab : (lay ? p.a_pair1 : p.a_pair));
     T acc[RC];
 #pragma unroll
     for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
@@ -250,7 +339,8 @@ __global__ __launch_bounds__(256) void k_group_double(DevPlan p, int R, int r0,
                                                       const typename Scal<CPLX>::T *__restrict__ c,
                                                       typename Scal<CPLX>::T *__restrict__ partial)
 {
-    const int64_t wave = xcd_block(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    // wave-uniform packet index, kept in a scalar register
+    const int64_t wave = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(xcd_block(blockIdx.x) * 4 + (threadIdx.x >> 6)));
     if (wave >= p.npacket_double) return;
     group_double_body<CPLX, RC, U>(p, wave, threadIdx.x & 63, R, r0, c, partial);
 }
@@ -297,7 +387,8 @@ __global__ __launch_bounds__(256) void k_group_single(DevPlan p, int R, int r0,
                                                       const typename Scal<CPLX>::T *__restrict__ c,
                                                       typename Scal<CPLX>::T *__restrict__ partial)
 {
-    const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int64_t wave =
+        p.npacket_double + (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     if (wave >= p.npacket) return;
     group_single_body<CPLX, RC>(p, wave, threadIdx.x & 63, R, r0, c, partial);
 }
@@ -322,7 +413,19 @@ __device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
         I = t / R;
         k = (int)(t - I * R);
         const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
-        for (uint32_t s = s0 + sub; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
+        // four slots in flight per lane; the additions keep their order
+        uint32_t s = s0 + sub;
+        for (; s + 3 * GL < s1; s += 4 * GL) {
+            uint32_t m[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) m[u] = p.slot_mem[s + u * GL];
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) v[u] = partial[(size_t)m[u] * R + k];
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc = sc_add(acc, v[u]);
+        }
+        for (; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
     }
 #pragma unroll
     for (int off = GL / 2; off > 0; off >>= 1) {
@@ -416,18 +519,24 @@ mw_status launch_sigma(const DevPlan &p, int R, const void *c, void *sigma, hipS
 // the paper's OpenMP/MPI task loops, section 3.1.2, as a GPU work queue);
 // problems are ordered by decreasing work and each problem's packets by
 // decreasing group size.
-template <bool CPLX>
+// One launch per root-chunk width (4, 2 or 1 roots per pass, the widths
+// the plain launches use, so that both give identical bits); each launch
+// only visits the problems that have a chunk of its width, and has its own
+// register budget.
+template <bool CPLX, int RC, int U>
 __global__ __launch_bounds__(256) void k_batched_groups(BatchArgs a)
 {
     using T = typename Scal<CPLX>::T;
     const int lane = threadIdx.x & 63;
     const int64_t total = a.pk_start[a.nprob];
     // Work queue per XCD (block b runs on XCD b % 8): the packet sequence is
-    // cut into chunks of CHUNK packets and chunk ch belongs to XCD ch % 8,
-    // so the packets of one group meet in one L2.  A wave claims the next
-    // chunk of its own XCD; when that queue is empty it takes chunks from
-    // the others.  All counters start at zero.
-    constexpr uint32_t CHUNK = 16;
+    // cut into chunks of CHUNK packets, and runs of SUPER chunks (the
+    // packets of the same 64 x 16 members as one XCD slice of the plain
+    // launch) belong to XCD (run index) % 8, so the packets of one group
+    // meet in one L2.  A wave claims the next chunk of its own XCD; when
+    // that queue is empty it takes chunks from the others.  All counters
+    // start at zero.
+    constexpr uint32_t CHUNK = 16, SUPER = 4;
     const int64_t nchunk = (total + CHUNK - 1) / CHUNK;
     const int home = blockIdx.x & 7;
     for (int qi = 0; qi < 8; qi++) {
@@ -435,8 +544,8 @@ __global__ __launch_bounds__(256) void k_batched_groups(BatchArgs a)
         for (;;) {
             uint32_t t = 0;
             if (lane == 0) t = atomicAdd(&a.counter[xq], 1u);
-            t = __shfl(t, 0);
-            const int64_t ch = (int64_t)t * 8 + xq;
+            t = __builtin_amdgcn_readfirstlane(t);
+            const int64_t ch = ((int64_t)(t / SUPER) * 8 + xq) * SUPER + t % SUPER;
             if (ch >= nchunk) break;
             const int64_t u1 = min<int64_t>(total, (ch + 1) * CHUNK);
             for (int64_t u = ch * CHUNK; u < u1; u++) {
@@ -448,13 +557,38 @@ __global__ __launch_bounds__(256) void k_batched_groups(BatchArgs a)
                 const T *c = (const T *)a.c[q];
                 T *part = (T *)p.partial;
                 for (int r0 = 0; r0 < R; r0 += 4) {
-                    // unroll 4: four roots of four partners keep the register
-                    // count at the plain kernel's occupancy
-                    if (w < p.npacket_double) group_double_body<CPLX, 4, 4>(p, w, lane, R, r0, c, part);
-                    else group_single_body<CPLX, 4>(p, w, lane, R, r0, c, part);
+                    const int left = R - r0;
+                    if ((left == 1 ? 1 : (left == 2 ? 2 : 4)) != RC) continue;
+                    if (w < p.npacket_double) group_double_body<CPLX, RC, U>(p, w, lane, R, r0, c, part);
+                    else group_single_body<CPLX, RC>(p, w, lane, R, r0, c, part);
                 }
             }
         }
+    }
+}
+
+// Flat variant: one wave per packet over the packets of every problem
+// (hardware-dispatched, with the same XCD-aware block order as the plain
+// launches); the tuner picks it or the work queue above.
+template <bool CPLX, int RC, int U>
+__global__ __launch_bounds__(256) void k_batched_flat(BatchArgs a)
+{
+    using T = typename Scal<CPLX>::T;
+    const int64_t u = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(xcd_block(blockIdx.x) * 4 + (threadIdx.x >> 6)));
+    if (u >= a.pk_start[a.nprob]) return;
+    const int lane = threadIdx.x & 63;
+    int q = 0;
+    while (u >= a.pk_start[q + 1]) q++;
+    const DevPlan &p = *a.plans[q];
+    const int64_t w = u - a.pk_start[q];
+    const int R = a.R[q];
+    const T *c = (const T *)a.c[q];
+    T *part = (T *)p.partial;
+    for (int r0 = 0; r0 < R; r0 += 4) {
+        const int left = R - r0;
+        if ((left == 1 ? 1 : (left == 2 ? 2 : 4)) != RC) continue;
+        if (w < p.npacket_double) group_double_body<CPLX, RC, U>(p, w, lane, R, r0, c, part);
+        else group_single_body<CPLX, RC>(p, w, lane, R, r0, c, part);
     }
 }
 
@@ -475,16 +609,51 @@ __global__ __launch_bounds__(256) void k_batched_gather(BatchArgs a)
 
 __global__ void k_reset_counter(uint32_t *ctr)
 {
-    if (threadIdx.x < 8) ctr[threadIdx.x] = 0u;
+    if (threadIdx.x < 8 * 3) ctr[threadIdx.x] = 0u;
 }
 
-mw_status launch_batched(const BatchArgs &a, bool cplx, int blocks, hipStream_t s, bool timing)
+template <bool CPLX>
+static void launch_batched_flat(const BatchSet &b, hipStream_t s)
 {
+    for (int cl = 0; cl < 3; cl++) {
+        const BatchArgs &a = b.cls[cl];
+        if (!a.nprob) continue;
+        const unsigned grid = xcd_grid((a.pk_start[a.nprob] + 3) / 4);
+        if (cl == 0) {
+            if (b.u4 == 8) hipLaunchKernelGGL((k_batched_flat<CPLX, 4, 8>), dim3(grid), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_batched_flat<CPLX, 4, 4>), dim3(grid), dim3(256), 0, s, a);
+        } else if (cl == 1) {
+            hipLaunchKernelGGL((k_batched_flat<CPLX, 2, 8>), dim3(grid), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_batched_flat<CPLX, 1, 8>), dim3(grid), dim3(256), 0, s, a);
+        }
+    }
+}
+
+template <bool CPLX>
+static void launch_batched_groups(const BatchSet &b, int blocks, hipStream_t s)
+{
+    if (blocks <= 0) {
+        launch_batched_flat<CPLX>(b, s);
+        return;
+    }
+    // four-root chunks: partner unroll 4 or 8 (tuned; registers vs loads in flight)
+    if (b.cls[0].nprob) {
+        if (b.u4 == 8) hipLaunchKernelGGL((k_batched_groups<CPLX, 4, 8>), dim3(blocks), dim3(256), 0, s, b.cls[0]);
+        else hipLaunchKernelGGL((k_batched_groups<CPLX, 4, 4>), dim3(blocks), dim3(256), 0, s, b.cls[0]);
+    }
+    if (b.cls[1].nprob) hipLaunchKernelGGL((k_batched_groups<CPLX, 2, 8>), dim3(blocks), dim3(256), 0, s, b.cls[1]);
+    if (b.cls[2].nprob) hipLaunchKernelGGL((k_batched_groups<CPLX, 1, 8>), dim3(blocks), dim3(256), 0, s, b.cls[2]);
+}
+
+mw_status launch_batched(const BatchSet &b, bool cplx, int blocks, hipStream_t s, bool timing)
+{
+    const BatchArgs &a = b.all;
     if (a.nprob == 0) return MW_OK;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, a.counter);
     ProfToken t = timing ? prof_begin("batched_groups", s) : ProfToken{nullptr, nullptr, ""};
-    if (cplx) hipLaunchKernelGGL(k_batched_groups<true>, dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_batched_groups<false>, dim3(blocks), dim3(256), 0, s, a);
+    if (cplx) launch_batched_groups<true>(b, blocks, s);
+    else launch_batched_groups<false>(b, blocks, s);
     prof_end(t, s);
     if (timing) t = prof_begin("batched_gather", s);
     const unsigned gg = (unsigned)a.blk_start[a.nprob];

@@ -43,10 +43,12 @@ struct DevPlan {
     const uint32_t *grp_off;   // [ngroup+1] first member of each group
     const uint64_t *grp_key;   // [ngroup][2] the shared string K
     const uint8_t *grp_type;   // [ngroup]
+    const uint32_t *grp_col;   // [ngroup] first column partial of a large double group
+    int64_t ncol;              // column partials (stored after the nmem row partials)
     // members (group-major)
     const uint2 *mem;          // [nmem] {det, X | Y<<8 | (phi<0)<<16 | layout<<17}
     const uint32_t *mem_grp;   // [nmem] owning group
-    const uint32_t *slot_mem;  // [nmem] memberships listed determinant by determinant
+    const uint32_t *slot_mem;  // partial-sum indices listed determinant by determinant
     const uint32_t *pk_off;    // [npacket+1] packets of <= 64 consecutive members
     // determinants
     const uint32_t *rowptr;    // [ndet+1] range of each determinant in slot_mem
@@ -56,8 +58,8 @@ struct DevPlan {
     const void *h;             // [M'][M'] (spin-free n x n; spinor M x M)
     const void *w_same;        // singles table [R][P][Q]: (PQ|RR) - (PR|RQ)  (spin-free n^3, spinor M^3)
     const void *w_opp;         // spin-free only: [r][p][q] (pq|rr)
-    const void *g_ab;          // spin-free only: [q][s][p][r] = (pq|rs)
-    const void *g_ab1;         // same values as [q][s][r][p]
+    const void *g_ab;          // spin-free only: [q][s][p][r] = (pq|rs); by (pq|rs) = (rs|pq),
+                               // [s][q][r][p] holds the same value (transposed column order)
     const void *a_pair;        // antisymmetrised pairs [x][y] = (X0 Y0|X1 Y1) - (X0 Y1|X1 Y0), y colex
     const void *a_pair1;       // same values with the column pair y in lexicographic order
     const void *f_ref;         // F^omega (spin-free [2][n][n] by spin of the group; spinor [M][M])
@@ -84,7 +86,14 @@ struct BatchArgs {
     int64_t blk_start[MW_MAXB + 1];  // gather-block prefix over problems (256 threads each)
     uint32_t *counter;
 };
-mw_status launch_batched(const BatchArgs &a, bool cplx, int blocks, hipStream_t s, bool timing);
+// all problems (gather) and, per root-chunk width 4 / 2 / 1, the problems
+// that have a chunk of that width (group launches; counters at +8 per class)
+struct BatchSet {
+    BatchArgs all;
+    BatchArgs cls[3];
+    int u4 = 4;  // partner unroll of the four-root launch (4 or 8)
+};
+mw_status launch_batched(const BatchSet &b, bool cplx, int blocks, hipStream_t s, bool timing);
 
 // host side helpers (plan.cpp)
 void set_error(const std::string &msg);

@@ -114,8 +114,9 @@ struct HostPlan {
     std::vector<uint64_t> grp_key;
     std::vector<uint8_t> grp_type;
     std::vector<uint2> mem;
-    std::vector<uint32_t> mem_grp, slot_mem, pk_off, rowptr;
-    std::vector<double> h, w_same, w_opp, g_ab, g_ab1, a_pair, a_pair1, f_ref;
+    std::vector<uint32_t> mem_grp, slot_mem, pk_off, rowptr, grp_col;
+    int64_t ncol = 0;  // column partial sums of large double groups
+    std::vector<double> h, w_same, w_opp, g_ab, a_pair, a_pair1, f_ref;
     uint64_t ref0 = 0, ref1 = 0;
     int64_t npacket_double = 0;
     int32_t tune_u = 8, tune_gl = 16;
@@ -488,13 +489,50 @@ static mw_status build_groups(HostPlan &P)
         if (cur_cnt) P.pk_off.push_back(cur_start + cur_cnt);
         if (!in_single) P.npacket_double = (int64_t)P.pk_off.size() - 1;
     }
-    // determinant-major list of each determinant's memberships
+    // Column partials of large double groups (k >= 64).  Their packets are
+    // the 64-member blocks of the group; the wave of block a evaluates each
+    // unordered pair with a partner in a block b >= a once (Hermiticity), keeps
+    // the row sum and hands H_ji c_i summed over its lanes to member j of
+    // block b > a through slot col(a, j) = nmem + grp_col[g] + a k -
+    // 32 a (a + 1) + (t_j - 64 (a + 1)), t_j the member's index in the group.
+    P.grp_col.assign(ngroup, 0);
+    int64_t ncol = 0;
+    for (int64_t gi = 0; gi < ngroup; gi++) {
+        const int64_t k = (int64_t)P.grp_off[gi + 1] - P.grp_off[gi];
+        const uint8_t ty = P.grp_type[gi];
+        if (k < 64 || ty == G_SINGLE_A || ty == G_SINGLE_B || ty == G_SINGLE_S) continue;
+        P.grp_col[gi] = (uint32_t)ncol;
+        const int64_t nb = (k + 63) / 64;
+        for (int64_t a = 0; a + 1 < nb; a++) ncol += k - 64 * (a + 1);
+        if (nmem + ncol > 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many partial sums");
+    }
+    P.ncol = ncol;
+    // determinant-major list of each determinant's partial sums: its
+    // memberships (row sums) and the column partials of its large groups
     P.rowptr.assign(N + 1, 0);
-    for (int64_t mi = 0; mi < nmem; mi++) P.rowptr[P.mem[mi].x + 1]++;
+    for (int64_t mi = 0; mi < nmem; mi++) {
+        const uint32_t gi = P.mem_grp[mi];
+        const int64_t t = (int64_t)mi - P.grp_off[gi];
+        const int64_t k = (int64_t)P.grp_off[gi + 1] - P.grp_off[gi];
+        const uint8_t ty = P.grp_type[gi];
+        const bool big = k >= 64 && !(ty == G_SINGLE_A || ty == G_SINGLE_B || ty == G_SINGLE_S);
+        P.rowptr[P.mem[mi].x + 1] += 1 + (big ? t / 64 : 0);
+    }
     for (int64_t i = 0; i < N; i++) P.rowptr[i + 1] += P.rowptr[i];
     std::vector<uint32_t> fillc(P.rowptr.begin(), P.rowptr.end() - 1);
-    P.slot_mem.resize(nmem);
-    for (int64_t mi = 0; mi < nmem; mi++) P.slot_mem[fillc[P.mem[mi].x]++] = (uint32_t)mi;
+    P.slot_mem.resize(P.rowptr[N]);
+    for (int64_t mi = 0; mi < nmem; mi++) {
+        const uint32_t det = P.mem[mi].x;
+        P.slot_mem[fillc[det]++] = (uint32_t)mi;
+        const uint32_t gi = P.mem_grp[mi];
+        const int64_t t = (int64_t)mi - P.grp_off[gi];
+        const int64_t k = (int64_t)P.grp_off[gi + 1] - P.grp_off[gi];
+        const uint8_t ty = P.grp_type[gi];
+        if (k < 64 || ty == G_SINGLE_A || ty == G_SINGLE_B || ty == G_SINGLE_S) continue;
+        for (int64_t a = 0; a < t / 64; a++)
+            P.slot_mem[fillc[det]++] =
+                (uint32_t)(nmem + P.grp_col[gi] + a * k - 32 * a * (a + 1) + (t - 64 * (a + 1)));
+    }
     return MW_OK;
 }
 
@@ -522,15 +560,12 @@ static void repack(HostPlan &P, const mw_problem *p)
                     P.w_opp[((size_t)r * n + a) * n + b] = G(a, b, r, r);
                 }
         P.g_ab.resize((size_t)n * n * n * n);
-        P.g_ab1.resize((size_t)n * n * n * n);
         parallel_for(n, [&](int64_t q0, int64_t q1, unsigned) {
             for (int64_t q = q0; q < q1; q++)
                 for (int s = 0; s < n; s++)
                     for (int a = 0; a < n; a++)
-                        for (int r = 0; r < n; r++) {
+                        for (int r = 0; r < n; r++)
                             P.g_ab[(((size_t)q * n + s) * n + a) * n + r] = G(a, q, r, s);
-                            P.g_ab1[(((size_t)q * n + s) * n + r) * n + a] = G(a, q, r, s);
-                        }
         });
         const int np = n * (n - 1) / 2;
         P.npair = np;
@@ -654,6 +689,8 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.grp_off = (const uint32_t *)take(grp_off.size() * 4);
     t.grp_key = (const uint64_t *)take(grp_key.size() * 8);
     t.grp_type = (const uint8_t *)take(grp_type.size());
+    t.grp_col = (const uint32_t *)take(grp_col.size() * 4);
+    t.ncol = ncol;
     t.mem = (const uint2 *)take(mem.size() * 8);
     t.mem_grp = (const uint32_t *)take(mem_grp.size() * 4);
     t.slot_mem = (const uint32_t *)take(slot_mem.size() * 4);
@@ -665,7 +702,6 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.w_same = (const void *)take(w_same.size() * 8);
     t.w_opp = (const void *)take(w_opp.size() * 8);
     t.g_ab = (const void *)take(g_ab.size() * 8);
-    t.g_ab1 = (const void *)take(g_ab1.size() * 8);
     t.a_pair = (const void *)take(a_pair.size() * 8);
     t.a_pair1 = (const void *)take(a_pair1.size() * 8);
     t.f_ref = (const void *)take(f_ref.size() * 8);
@@ -674,9 +710,9 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.npacket_double = npacket_double;
     // per-call scratch: sigma partials, or the density-matrix accumulators
     size_t rdm_bytes = kind == MW_SPIN_FREE
-                           ? ((size_t)n * n * n * n + (size_t)npair * npair + 2 * (size_t)n * n) * 8
-                           : ((size_t)npair * npair + (size_t)M * M) * 16;
-    t.scratch_bytes = std::max(std::max<size_t>(1, mem.size()) * (size_t)max_roots * sb, rdm_bytes);
+                           ? ((size_t)n * n * n * n + 2 * (size_t)npair * npair + 2 * (size_t)n * n) * 8
+                           : (2 * (size_t)npair * npair + (size_t)M * M) * 16;
+    t.scratch_bytes = std::max(std::max<size_t>(1, mem.size() + (size_t)ncol) * (size_t)max_roots * sb, rdm_bytes);
     t.partial = (void *)take(t.scratch_bytes);
     t.self = (DevPlan *)take(sizeof(DevPlan));
     t.counter = (uint32_t *)take(256);
@@ -758,6 +794,7 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
     bool ok = up(d.grp_off, P.grp_off.data(), P.grp_off.size() * 4) &&
               up(d.grp_key, P.grp_key.data(), P.grp_key.size() * 8) &&
               up(d.grp_type, P.grp_type.data(), P.grp_type.size()) &&
+              up(d.grp_col, P.grp_col.data(), P.grp_col.size() * 4) &&
               up(d.mem, P.mem.data(), P.mem.size() * 8) &&
               up(d.mem_grp, P.mem_grp.data(), P.mem_grp.size() * 4) &&
               up(d.slot_mem, P.slot_mem.data(), P.slot_mem.size() * 4) &&
@@ -768,7 +805,6 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
               up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) &&
               up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
-              up(d.g_ab1, P.g_ab1.data(), P.g_ab1.size() * 8) &&
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) &&
               up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
               up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8);
@@ -813,7 +849,7 @@ mw_status mw_plan_update_integrals(mw_plan plan, const double *h, const double *
     };
     bool ok = up(d.h, P.h.data(), P.h.size() * 8) && up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
               up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) && up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
-              up(d.g_ab1, P.g_ab1.data(), P.g_ab1.size() * 8) && up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
+              up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) && up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
               up(d.self, &P.dev, sizeof(DevPlan));
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during integral update");

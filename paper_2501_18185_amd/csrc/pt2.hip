@@ -1,0 +1,771 @@
+// Epstein-Nesbet second-order energy over the external space (section 2.5,
+// Eq. (ENPT2E), primary space = the whole variational space P):
+//
+//   E2_k = sum_{A in Q} |sum_{J in P} H_AJ c_Jk|^2 / (E0_k - H_AA),
+//
+// Q = determinants outside P reached from P by one or two excitations.
+// The paper splits the space W of all such excitations into disjoint
+// subspaces W_i (by constraints on the highest occupied orbitals), stores
+// the connections of a batch of W_i, sorts them to find each A with its
+// partners J, and drops doubly excited A whose integral bound times
+// max_k |c_Jk| is below Q_min.  Here the disjoint subspaces are hash
+// buckets of A: every (A, J) pair generated from a J of P lands in the
+// bucket of A, so one bucket holds every partner of its A's.
+//
+//   k_pt2_enum<0>     every J lists its excitations (one workgroup per J),
+//                     drops A in P (exact hash set of the space) and counts
+//                     the kept pairs (doubles screened with Q_min)
+//   k_pt2_enum<1>     the same pairs, counted per bucket
+//   k_pt2_enum<2>     the pairs of the buckets of one pass, written as
+//                     records {A, J} with H_AJ c_J at the bucket's offset
+//   k_pt2_bucket      one workgroup per bucket: sorts its records by (A, J)
+//                     in LDS, sums each numerator in ascending J, adds
+//                     |num|^2 / (E0 - H_AA) in sorted order
+//   k_pt2_sum         per pass: bucket partial sums in a fixed order
+//
+// Passes over bucket ranges keep the records within the caller's work
+// buffer (the pipelined memory bound of the paper's procedure).  Every sum
+// has a fixed order, so repeated calls give identical bits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "dev_common.h"
+#include "mw_internal.h"
+
+namespace mw {
+
+namespace {
+
+constexpr int PT2_CAP = 2048;    // records one bucket may hold (LDS sort)
+constexpr int PT2_MEAN = 512;    // target records per bucket
+constexpr int PT2_MAXR = 8;      // roots per call
+
+struct Rec {
+    uint64_t a0, a1;
+    uint64_t j;
+};
+
+// Excitation classes of a determinant of the space; the counts are equal
+// for every J (fixed particle numbers).  Spin-free: sector 0 = alpha
+// positions, 1 = beta; classes single a, single b, double aa, double bb,
+// double ab.  Spinor: one sector; classes single, double.
+struct ExcClasses {
+    int nclass;
+    int type[5];      // 0 single, 1 double in one sector, 2 alpha-beta double
+    int sec[5];
+    int start[6];     // prefix of the class sizes (fewer than 2^31 per J)
+    int no[2], nv[2];
+};
+
+struct Roots {
+    double e0[PT2_MAXR];
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    // SplitMix64 finaliser (Steele, Lea and Flood, 2014)
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ULL;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ uint64_t hash_det(uint64_t a0, uint64_t a1)
+{
+    return mix64(a0 ^ mix64(a1 + 0x9E3779B97F4A7C15ULL));
+}
+
+// bucket = the top lognb bits of the hash
+__device__ __forceinline__ uint32_t bucket_of(uint64_t h, int lognb)
+{
+    return lognb ? (uint32_t)(h >> (64 - lognb)) : 0u;
+}
+
+// Exact membership in the space: open addressing on the low hash bits,
+// linear probing, keys {a0, a1}, empty slots all ones (no determinant of a
+// space with excitations has every position occupied).
+struct DetSet {
+    const ulonglong2 *key;
+    uint64_t mask;
+};
+
+__device__ __forceinline__ bool in_set(const DetSet &s, uint64_t h, uint64_t a0, uint64_t a1)
+{
+    for (uint64_t i = h & s.mask;; i = (i + 1) & s.mask) {
+        const ulonglong2 k = s.key[i];
+        if (k.x == a0 && k.y == a1) return true;
+        if (k.x == ~0ULL && k.y == ~0ULL) return false;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_set_insert(const uint64_t *__restrict__ dets, int64_t ndet, uint32_t *slot,
+                                                    uint64_t mask)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ndet) return;
+    const uint64_t a0 = dets[2 * i], a1 = dets[2 * i + 1];
+    // at most ndet < table size / 2 insertions: a free slot is always found
+    for (uint64_t s = hash_det(a0, a1) & mask;; s = (s + 1) & mask)
+        if (atomicCAS(&slot[s], 0xffffffffu, (uint32_t)i) == 0xffffffffu) return;
+}
+
+__global__ __launch_bounds__(256) void k_set_keys(const uint64_t *__restrict__ dets, const uint32_t *__restrict__ slot,
+                                                  uint64_t size, ulonglong2 *key)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)size) return;
+    const uint32_t d = slot[i];
+    key[i] = d == 0xffffffffu ? make_ulonglong2(~0ULL, ~0ULL) : make_ulonglong2(dets[2 * (size_t)d], dets[2 * (size_t)d + 1]);
+}
+
+// colex pair k -> (lo, hi), k = hi (hi - 1) / 2 + lo
+__device__ __forceinline__ void pair_of(int k, int &lo, int &hi)
+{
+    int b = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)k)) * 0.5f);
+    while (b * (b - 1) / 2 > k) b--;
+    while ((b + 1) * b / 2 <= k) b++;
+    hi = b;
+    lo = k - b * (b - 1) / 2;
+}
+
+__device__ __forceinline__ void flip(uint64_t &d0, uint64_t &d1, int n, int X)
+{
+    if (X < n) d0 ^= 1ULL << X;
+    else d1 ^= 1ULL << (X - n);
+}
+
+// occupied positions of (d0, d1) below global position X
+__device__ __forceinline__ int below(uint64_t d0, uint64_t d1, int n, int X)
+{
+    if (X < n) return __popcll(d0 & ((1ULL << X) - 1));
+    return __popcll(d0) + __popcll(d1 & ((1ULL << (X - n)) - 1));
+}
+
+__device__ __forceinline__ bool occ(uint64_t d0, uint64_t d1, int n, int X)
+{
+    return X < n ? (d0 >> X) & 1 : (d1 >> (X - n)) & 1;
+}
+
+// occupied positions strictly between a and b
+__device__ __forceinline__ int between(uint64_t d0, uint64_t d1, int n, int a, int b)
+{
+    const int lo = min(a, b), hi = max(a, b);
+    return below(d0, d1, n, hi) - below(d0, d1, n, lo) - (int)occ(d0, d1, n, lo);
+}
+
+__device__ __forceinline__ double mag(double v) { return fabs(v); }
+// |v| without contraction, as re*re + im*im rounded term by term
+__device__ __forceinline__ double mag(double2 v) { return sqrt(__dadd_rn(__dmul_rn(v.x, v.x), __dmul_rn(v.y, v.y))); }
+
+// Antisymmetrised double integral (PQ|RS) - (PS|RQ) for particles P < R
+// (in A) and holes Q < S (in J), without the phase.
+template <bool CPLX>
+__device__ __forceinline__ typename Scal<CPLX>::T double_value(const DevPlan &p, int P, int Q, int R, int S)
+{
+    using T = typename Scal<CPLX>::T;
+    const int n = p.n;
+    if constexpr (!CPLX) {
+        if (P < n && R >= n)  // alpha-beta: (pq|rs), p q alpha, r s beta
+            return ((const double *)p.g_ab)[(((size_t)Q * n + (S - n)) * n + P) * n + (R - n)];
+        const int off = P >= n ? n : 0;
+        return ((const double *)p.a_pair)[(size_t)pair_idx(P - off, R - off) * p.npair +
+                                          pair_idx(Q - off, S - off)];
+    } else {
+        return ((const T *)p.a_pair)[(size_t)pair_idx(P, R) * p.npair + pair_idx(Q, S)];
+    }
+}
+
+// Decode item e of the excitation list of J (occupied / virtual position
+// lists of each sector in LDS) into holes Q (< S) and particles P (< R);
+// S = R = -1 for a single.
+__device__ __forceinline__ void decode(const ExcClasses &ex, const uint8_t (*ol)[128], const uint8_t (*vl)[128],
+                                       int e, int &Q, int &S, int &P, int &R)
+{
+    int c = 0;
+    while (e >= ex.start[c + 1]) c++;
+    const int i = e - ex.start[c];
+    const int t = ex.type[c], s = ex.sec[c];
+    if (t == 0) {
+        const int nv = ex.nv[s];
+        Q = ol[s][i / nv];
+        P = vl[s][i % nv];
+        S = R = -1;
+    } else if (t == 1) {
+        const int nv = ex.nv[s];
+        const int vp = nv * (nv - 1) / 2;
+        int a, b, x, y;
+        pair_of(i / vp, a, b);
+        pair_of(i % vp, x, y);
+        Q = ol[s][a];
+        S = ol[s][b];
+        P = vl[s][x];
+        R = vl[s][y];
+    } else {
+        const int nvv = ex.nv[0] * ex.nv[1];
+        const int hp = i / nvv, vp = i % nvv;
+        Q = ol[0][hp / ex.no[1]];
+        S = ol[1][hp % ex.no[1]];
+        P = vl[0][vp / ex.nv[1]];
+        R = vl[1][vp % ex.nv[1]];
+    }
+}
+
+// Largest |c_Jk| over the roots (the screening weight of J).
+template <bool CPLX>
+__device__ __forceinline__ double cmax_of(const typename Scal<CPLX>::T *c, int R, int64_t J)
+{
+    double m = 0.0;
+    for (int k = 0; k < R; k++) m = fmax(m, mag(c[(size_t)J * R + k]));
+    return m;
+}
+
+// <A|H|J> for A = J with holes Q (< S) replaced by particles P (< R)
+// (S = R = -1: a single): the integral with the phase of
+// a+_P a_Q or a+_P a+_R a_S a_Q on J.
+template <bool CPLX>
+__device__ __forceinline__ typename Scal<CPLX>::T exc_value(const DevPlan &p, uint64_t j0, uint64_t j1, int Q,
+                                                            int S, int P, int R)
+{
+    using T = typename Scal<CPLX>::T;
+    const int n = p.n;
+    if (S < 0) {
+        uint64_t k0 = j0, k1 = j1;
+        flip(k0, k1, n, Q);
+        const uint8_t type = CPLX ? G_SINGLE_S : (P < n ? G_SINGLE_A : G_SINGLE_B);
+        return sc_neg(single_element<CPLX>(p, type, k0, k1, P, Q), between(j0, j1, n, P, Q) & 1);
+    }
+    // R <- S first, then P <- Q on the result
+    int sg = between(j0, j1, n, R, S);
+    uint64_t k0 = j0, k1 = j1;
+    flip(k0, k1, n, S);
+    flip(k0, k1, n, R);
+    sg += between(k0, k1, n, P, Q);
+    return sc_neg(double_value<CPLX>(p, P, Q, R, S), sg & 1);
+}
+
+// Pairs with A in P are dropped here (exact hash-set test).
+// MODE 0: total kept pairs (atomic per workgroup); 1: per-bucket counts;
+// 2: records {A, J} of buckets [b0, b1) at off[b] + running fill, with
+// val[record][k] = H_AJ c_Jk (the integral rows are read by neighbouring
+// lanes here, not scattered over the buckets).
+template <bool CPLX, int MODE>
+__global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetSet inP, int R,
+                                                  const typename Scal<CPLX>::T *__restrict__ c, double qmin,
+                                                  int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt,
+                                                  const uint64_t *__restrict__ off, uint32_t *fill, Rec *rec,
+                                                  typename Scal<CPLX>::T *val, unsigned long long *total)
+{
+    using T = typename Scal<CPLX>::T;
+    __shared__ uint8_t ol[2][128], vl[2][128];
+    __shared__ double s_cmax;
+    __shared__ T s_c[PT2_MAXR];
+    __shared__ unsigned long long s_tot;
+    const int64_t J = blockIdx.x;
+    const uint64_t j0 = p.dets[2 * J], j1 = p.dets[2 * J + 1];
+    const int n = p.n;
+    if (threadIdx.x == 0) {
+        // sector lists: spin-free sector 0 = alpha, 1 = beta; spinor one sector
+        int no[2] = {0, 0}, nv[2] = {0, 0};
+        for (int X = 0; X < 2 * n; X++) {
+            const int s = CPLX ? 0 : X / n;
+            if (occ(j0, j1, n, X)) ol[s][no[s]++] = (uint8_t)X;
+            else vl[s][nv[s]++] = (uint8_t)X;
+        }
+        s_cmax = qmin > 0.0 ? cmax_of<CPLX>(c, R, J) : 0.0;
+        for (int k = 0; k < R; k++) s_c[k] = c[(size_t)J * R + k];
+        s_tot = 0;
+    }
+    __syncthreads();
+    const double cm = s_cmax;
+    const int E = ex.start[ex.nclass];
+    unsigned long long mine = 0;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        int Q, S, P, Rr;
+        decode(ex, ol, vl, e, Q, S, P, Rr);
+        if (S >= 0 && qmin > 0.0 && __dmul_rn(mag(double_value<CPLX>(p, P, Q, Rr, S)), cm) < qmin) continue;
+        uint64_t a0 = j0, a1 = j1;
+        flip(a0, a1, n, Q);
+        flip(a0, a1, n, P);
+        if (S >= 0) {
+            flip(a0, a1, n, S);
+            flip(a0, a1, n, Rr);
+        }
+        const uint64_t h = hash_det(a0, a1);
+        if (in_set(inP, h, a0, a1)) continue;  // A in P: not external
+        if constexpr (MODE == 0) {
+            mine++;
+        } else {
+            const uint32_t b = bucket_of(h, lognb);
+            if constexpr (MODE == 1) {
+                atomicAdd(&cnt[b], 1u);
+            } else {
+                if (b < b0 || b >= b1) continue;
+                const uint32_t k = atomicAdd(&fill[b], 1u);
+                if (k >= cnt[b]) continue;
+                const uint64_t slot = off[b] + k;
+                rec[slot] = Rec{a0, a1, (uint64_t)J};
+                const T v = exc_value<CPLX>(p, j0, j1, Q, S, P, Rr);
+                for (int q = 0; q < R; q++) val[slot * R + q] = sc_mul(v, s_c[q]);
+            }
+        }
+    }
+    if constexpr (MODE == 0) {
+        atomicAdd(&s_tot, mine);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(total, s_tot);
+    }
+}
+
+// eps[J][X] = h_XX + sum_{Y in J, Y != X} V(X, Y) and vg[X][Y] = V(X, Y),
+// V(X, Y) = (XX|YY) - (XY|YX) (spin-free: the exchange only for equal
+// spins); then H_AA = H_JJ + the difference of a single or double
+// excitation in O(1) (see diag_from).
+template <bool CPLX>
+__device__ __forceinline__ double vpair(const DevPlan &p, int X, int Y)
+{
+    const int n = p.n;
+    if constexpr (CPLX) {
+        const int M = p.M;
+        return ((const double2 *)p.w_same)[((size_t)Y * M + X) * M + X].x;
+    } else {
+        const int x = X % n, y = Y % n;
+        const double *w = (const double *)((X < n) == (Y < n) ? p.w_same : p.w_opp);
+        return w[((size_t)y * n + x) * n + x];
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_pt2_tables(DevPlan p, double *eps, double *vg)
+{
+    const int M = p.M, n = p.n;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (int64_t)M * M) {
+        const int X = (int)(t / M), Y = (int)(t % M);
+        vg[t] = X == Y ? 0.0 : vpair<CPLX>(p, X, Y);
+    }
+    if (t >= p.ndet * M) return;
+    const int64_t J = t / M;
+    const int X = (int)(t % M);
+    const uint64_t j0 = p.dets[2 * J], j1 = p.dets[2 * J + 1];
+    double e;
+    if constexpr (CPLX) e = ((const double2 *)p.h)[(size_t)X * M + X].x;
+    else e = ((const double *)p.h)[(size_t)(X % n) * n + (X % n)];
+    for (int Y = 0; Y < M; Y++)
+        if (Y != X && occ(j0, j1, n, Y)) e += vpair<CPLX>(p, X, Y);
+    eps[t] = e;
+}
+
+
+// H_AA from H_JJ of a partner J: A = J with holes Q (< S) replaced by
+// particles P (< R):  single  eps_P - eps_Q - V_PQ;  double  eps_P + eps_R
+// - eps_Q - eps_S - V_PQ - V_PS - V_RQ - V_RS + V_PR + V_QS  (eps of J).
+__device__ __forceinline__ double diag_from(const DevPlan &p, double hjj, const double *eps, const double *vg,
+                                            uint64_t a0, uint64_t a1, uint64_t j0, uint64_t j1)
+{
+    const int n = p.n, M = p.M;
+    const uint64_t x0 = a0 ^ j0, x1 = a1 ^ j1;
+    int hol[2] = {0, 0}, par[2] = {0, 0}, nh = 0, np = 0;
+    for (uint64_t x = j0 & x0; x && nh < 2; x &= x - 1) hol[nh++] = __builtin_ctzll(x);
+    for (uint64_t x = j1 & x1; x && nh < 2; x &= x - 1) hol[nh++] = n + __builtin_ctzll(x);
+    for (uint64_t x = a0 & x0; x && np < 2; x &= x - 1) par[np++] = __builtin_ctzll(x);
+    for (uint64_t x = a1 & x1; x && np < 2; x &= x - 1) par[np++] = n + __builtin_ctzll(x);
+    auto V = [&](int X, int Y) { return vg[(size_t)X * M + Y]; };
+    const int P = par[0], Q = hol[0];
+    if (nh == 1) return hjj + ((eps[P] - eps[Q]) - V(P, Q));
+    const int R = par[1], S = hol[1];
+    const double d = (eps[P] + eps[R]) - (eps[Q] + eps[S]) - ((V(P, Q) + V(P, S)) + (V(R, Q) + V(R, S))) +
+                     (V(P, R) + V(Q, S));
+    return hjj + d;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_pt2_bucket(DevPlan p, int R, Roots roots, uint32_t b0,
+                                                    const uint32_t *__restrict__ cnt,
+                                                    const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
+                                                    const typename Scal<CPLX>::T *__restrict__ val,
+                                                    const double *__restrict__ eps, const double *__restrict__ vg,
+                                                    double *__restrict__ part, unsigned long long *__restrict__ partc)
+{
+    using T = typename Scal<CPLX>::T;
+    __shared__ uint64_t s0[PT2_CAP], s1[PT2_CAP];
+    __shared__ uint32_t sj[PT2_CAP];
+    __shared__ uint16_t si[PT2_CAP];
+    __shared__ double red[256];
+    __shared__ unsigned long long redc[256];
+    const uint32_t b = b0 + blockIdx.x;
+    const int m = (int)cnt[b];
+    const uint64_t base = off[b];
+    int np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+        if (i < m) {
+            const Rec r = rec[base + i];
+            s0[i] = r.a0;
+            s1[i] = r.a1;
+            sj[i] = (uint32_t)r.j;
+        } else {
+            s0[i] = ~0ULL;
+            s1[i] = ~0ULL;
+            sj[i] = ~0u;
+        }
+        si[i] = (uint16_t)i;
+    }
+    __syncthreads();
+    // bitonic sort by (A, J) ascending
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t x0 = s0[i], x1 = s1[i], y0 = s0[l], y1 = s1[l];
+                    const uint32_t xj = sj[i], yj = sj[l];
+                    const bool gt = x0 != y0 ? x0 > y0 : (x1 != y1 ? x1 > y1 : xj > yj);
+                    if (gt == up) {
+                        const uint16_t xi = si[i];
+                        s0[i] = y0; s1[i] = y1; sj[i] = yj; si[i] = si[l];
+                        s0[l] = x0; s1[l] = x1; sj[l] = xj; si[l] = xi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double acc[PT2_MAXR];
+#pragma unroll
+    for (int k = 0; k < PT2_MAXR; k++) acc[k] = 0.0;
+    unsigned long long kept = 0, nq = 0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const uint64_t a0 = s0[i], a1 = s1[i];
+        if (i > 0 && s0[i - 1] == a0 && s1[i - 1] == a1) continue;  // not the first record of its A
+        int e = i + 1;
+        while (e < m && s0[e] == a0 && s1[e] == a1) e++;
+        // numerators in ascending J (records are the kept pairs)
+        T num[PT2_MAXR];
+#pragma unroll
+        for (int k = 0; k < PT2_MAXR; k++) num[k] = sc_zero(T());
+        for (int u = i; u < e; u++) {
+            const T *v = val + (base + si[u]) * R;
+#pragma unroll
+            for (int k = 0; k < PT2_MAXR; k++)
+                if (k < R) num[k] = sc_add(num[k], v[k]);
+        }
+        kept += (unsigned long long)(e - i);
+        nq++;
+        const uint32_t J = sj[i];
+        double hjj;
+        if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
+        else hjj = ((const double *)p.diag)[J];
+        const double haa = diag_from(p, hjj, eps + (size_t)J * p.M, vg, a0, a1, p.dets[2 * (size_t)J],
+                                     p.dets[2 * (size_t)J + 1]);
+#pragma unroll
+        for (int k = 0; k < PT2_MAXR; k++) {
+            if (k >= R) continue;
+            double q;
+            if constexpr (CPLX) q = num[k].x * num[k].x + num[k].y * num[k].y;
+            else q = num[k] * num[k];
+            acc[k] += q / (roots.e0[k] - haa);
+        }
+    }
+    // fixed-order block reductions
+    for (int k = 0; k < R; k++) {
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * R + k] = red[0];
+        __syncthreads();
+    }
+    for (int w = 0; w < 2; w++) {
+        redc[threadIdx.x] = w ? nq : kept;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) redc[threadIdx.x] += redc[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partc[2 * (size_t)blockIdx.x + w] = redc[0];
+        __syncthreads();
+    }
+}
+
+// out[k] = sum over nb buckets of part[b][k] (k < R), out[R + w] = sum of
+// partc[b][w]; one block, fixed order.
+__global__ __launch_bounds__(256) void k_pt2_sum(int64_t nb, int R, const double *__restrict__ part,
+                                                 const unsigned long long *__restrict__ partc, double *out,
+                                                 unsigned long long *outc)
+{
+    __shared__ double red[256];
+    __shared__ unsigned long long redc[256];
+    for (int k = 0; k < R + 2; k++) {
+        double a = 0.0;
+        unsigned long long ac = 0;
+        for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+            if (k < R) a += part[b * R + k];
+            else ac += partc[2 * b + (k - R)];
+        }
+        red[threadIdx.x] = a;
+        redc[threadIdx.x] = ac;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                red[threadIdx.x] += red[threadIdx.x + s];
+                redc[threadIdx.x] += redc[threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (k < R) out[k] = red[0];
+            else outc[k - R] = redc[0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *x, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+void fill_u32(uint32_t *x, int64_t n, hipStream_t s, uint32_t v = 0u)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+}
+
+uint64_t set_size(int64_t ndet)
+{
+    uint64_t z = 256;
+    while (z < 2 * (uint64_t)ndet) z <<= 1;
+    return z;
+}
+
+int64_t choose(int a, int b)
+{
+    if (b < 0 || b > a) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= b; i++) r = r * (a - b + i) / i;
+    return r;
+}
+
+bool classes(const DevPlan &d, int na, int nb_, ExcClasses &ex)
+{
+    ex = ExcClasses{};
+    int64_t cntc[5];
+    if (d.kind == MW_SPIN_FREE) {
+        ex.no[0] = na; ex.nv[0] = d.n - na;
+        ex.no[1] = nb_; ex.nv[1] = d.n - nb_;
+        ex.nclass = 5;
+        const int t[5] = {0, 0, 1, 1, 2}, s[5] = {0, 1, 0, 1, 0};
+        for (int c = 0; c < 5; c++) { ex.type[c] = t[c]; ex.sec[c] = s[c]; }
+        cntc[0] = (int64_t)ex.no[0] * ex.nv[0];
+        cntc[1] = (int64_t)ex.no[1] * ex.nv[1];
+        cntc[2] = choose(ex.no[0], 2) * choose(ex.nv[0], 2);
+        cntc[3] = choose(ex.no[1], 2) * choose(ex.nv[1], 2);
+        cntc[4] = (int64_t)ex.no[0] * ex.no[1] * ex.nv[0] * ex.nv[1];
+    } else {
+        ex.no[0] = na; ex.nv[0] = d.M - na;
+        ex.nclass = 2;
+        ex.type[0] = 0; ex.type[1] = 1; ex.sec[0] = ex.sec[1] = 0;
+        cntc[0] = (int64_t)ex.no[0] * ex.nv[0];
+        cntc[1] = choose(ex.no[0], 2) * choose(ex.nv[0], 2);
+    }
+    int64_t acc = 0;
+    ex.start[0] = 0;
+    for (int c = 0; c < ex.nclass; c++) {
+        acc += cntc[c];
+        if (acc >= ((int64_t)1 << 31)) return false;
+        ex.start[c + 1] = (int)acc;
+    }
+    for (int c = ex.nclass + 1; c < 6; c++) ex.start[c] = ex.start[ex.nclass];
+    return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <bool CPLX>
+mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, double qmin, void *work,
+                size_t work_bytes, double *e2, int64_t *stats, hipStream_t s)
+{
+    using T = typename Scal<CPLX>::T;
+    const T *c = (const T *)cv;
+    // particle numbers from the first determinant
+    uint64_t first[2];
+    if (hipMemcpyAsync(first, d.dets, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(MW_EHIP, "pt2: reading the space failed");
+    const int na = __builtin_popcountll(first[0]) + (CPLX ? __builtin_popcountll(first[1]) : 0);
+    const int nbeta = CPLX ? 0 : __builtin_popcountll(first[1]);
+    ExcClasses ex;
+    if (!classes(d, na, nbeta, ex)) return fail(MW_EUNSUPPORTED, "pt2: more than 2^31 excitations per determinant");
+    Roots roots{};
+    for (int k = 0; k < R; k++) roots.e0[k] = e0[k];
+    for (int k = 0; k < R; k++) e2[k] = 0.0;
+    int64_t st[5] = {0, 0, 0, 0, 0};  // kept pairs, external A, passes, buckets, excitations enumerated
+
+    char *w = (char *)work;
+    size_t used = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *x = w + used;
+        used += align256(bytes);
+        return x;
+    };
+    unsigned long long *tot = (unsigned long long *)take(8 * 16);
+    double *sums = (double *)take(8 * (PT2_MAXR + 2));
+    unsigned long long *sumc = (unsigned long long *)(sums + PT2_MAXR);
+    double *eps = (double *)take(8 * (size_t)d.ndet * d.M);
+    double *vg = (double *)take(8 * (size_t)d.M * d.M);
+    const uint64_t zs = set_size(d.ndet);
+    uint32_t *sslot = (uint32_t *)take(4 * zs);
+    ulonglong2 *skey = (ulonglong2 *)take(16 * zs);
+    if (used > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small");
+    const DetSet inP{skey, zs - 1};
+    const unsigned grid = (unsigned)d.ndet;
+    if (d.ndet > 0 && ex.start[ex.nclass] > 0) {
+        fill_u32(sslot, (int64_t)zs, s, 0xffffffffu);
+        hipLaunchKernelGGL(k_set_insert, dim3((unsigned)((d.ndet + 255) / 256)), dim3(256), 0, s, d.dets, d.ndet, sslot,
+                           zs - 1);
+        hipLaunchKernelGGL(k_set_keys, dim3((unsigned)((zs + 255) / 256)), dim3(256), 0, s, d.dets,
+                           (const uint32_t *)sslot, zs, skey);
+        hipMemsetAsync(tot, 0, 8, s);
+        hipLaunchKernelGGL((k_pt2_enum<CPLX, 0>), dim3(grid), dim3(256), 0, s, d, ex, inP, R, c, qmin, 0, 0u, 0u,
+                           (uint32_t *)nullptr, (const uint64_t *)nullptr, (uint32_t *)nullptr, (Rec *)nullptr,
+                           (T *)nullptr, tot);
+        const int64_t nt = std::max<int64_t>(d.ndet * d.M, (int64_t)d.M * d.M);
+        hipLaunchKernelGGL(k_pt2_tables<CPLX>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, d, eps, vg);
+        unsigned long long T_ = 0;
+        if (hipMemcpyAsync(&T_, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return fail(MW_EHIP, "pt2: counting pass failed");
+        st[4] = d.ndet * (int64_t)ex.start[ex.nclass];  // excitations enumerated per pass
+        if (T_ > 0) {
+            int lognb = 0;
+            while (((uint64_t)PT2_MEAN << lognb) < T_ && lognb < 40) lognb++;
+            const size_t fixed = used;
+            std::vector<uint32_t> hc;
+            for (;;) {
+                const int64_t NB = (int64_t)1 << lognb;
+                used = fixed;
+                uint32_t *cnt = (uint32_t *)take(4 * (size_t)NB);
+                uint32_t *fill = (uint32_t *)take(4 * (size_t)NB);
+                uint64_t *off = (uint64_t *)take(8 * (size_t)NB);
+                double *part = (double *)take(8 * (size_t)NB * R);
+                unsigned long long *partc = (unsigned long long *)take(16 * (size_t)NB);
+                if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small for the bucket tables");
+                fill_u32(cnt, NB, s);
+                hipLaunchKernelGGL((k_pt2_enum<CPLX, 1>), dim3(grid), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb, 0u,
+                                   0u, cnt, (const uint64_t *)nullptr, (uint32_t *)nullptr, (Rec *)nullptr,
+                                   (T *)nullptr, (unsigned long long *)nullptr);
+                hc.resize(NB);
+                if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return fail(MW_EHIP, "pt2: bucket counting failed");
+                const uint32_t mx = *std::max_element(hc.begin(), hc.end());
+                if (mx > (uint32_t)PT2_CAP) {
+                    // a bucket too large for one workgroup: split the buckets
+                    if (lognb >= 40) return fail(MW_EUNSUPPORTED, "pt2: bucket overflow");
+                    lognb++;
+                    continue;
+                }
+                // passes over bucket ranges whose records (24 B + R values
+                // each) fit the rest of the buffer
+                const size_t per = sizeof(Rec) + (size_t)R * sizeof(T);
+                const uint64_t cap_rec = (work_bytes - used - 512) / per;
+                Rec *rec = (Rec *)(w + used);
+                T *val = (T *)(w + used + align256(cap_rec * sizeof(Rec)));
+                if ((char *)(val + cap_rec * R) > w + work_bytes) return fail(MW_EWORKSPACE, "pt2: layout overflow");
+                std::vector<uint64_t> ho(NB);
+                int64_t b0 = 0;
+                while (b0 < NB) {
+                    uint64_t acc = 0;
+                    int64_t b1 = b0;
+                    while (b1 < NB && acc + hc[b1] <= cap_rec) {
+                        ho[b1] = acc;
+                        acc += hc[b1];
+                        b1++;
+                    }
+                    if (b1 == b0) return fail(MW_EWORKSPACE, "pt2: work buffer too small for one bucket");
+                    hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
+                    fill_u32(fill + b0, b1 - b0, s);
+                    ProfToken t = prof_begin("pt2_enum", s);
+                    hipLaunchKernelGGL((k_pt2_enum<CPLX, 2>), dim3(grid), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb,
+                                       (uint32_t)b0, (uint32_t)b1, cnt, (const uint64_t *)off, fill, rec, val,
+                                       (unsigned long long *)nullptr);
+                    prof_end(t, s);
+                    t = prof_begin("pt2_bucket", s);
+                    hipLaunchKernelGGL(k_pt2_bucket<CPLX>, dim3((unsigned)(b1 - b0)), dim3(256), 0, s, d, R, roots,
+                                       (uint32_t)b0, (const uint32_t *)cnt, (const uint64_t *)off, (const Rec *)rec,
+                                       (const T *)val, (const double *)eps, (const double *)vg, part, partc);
+                    prof_end(t, s);
+                    hipLaunchKernelGGL(k_pt2_sum, dim3(1), dim3(256), 0, s, b1 - b0, R, (const double *)part,
+                                       (const unsigned long long *)partc, sums, sumc);
+                    double hs[PT2_MAXR + 2];
+                    if (hipMemcpyAsync(hs, sums, 8 * (PT2_MAXR + 2), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess)
+                        return fail(MW_EHIP, "pt2: pass failed");
+                    for (int k = 0; k < R; k++) e2[k] += hs[k];
+                    unsigned long long hcnt[2];
+                    memcpy(hcnt, hs + PT2_MAXR, 16);
+                    st[0] += (int64_t)hcnt[0];
+                    st[1] += (int64_t)hcnt[1];
+                    st[2]++;
+                    b0 = b1;
+                }
+                st[3] = NB;
+                break;
+            }
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2 kernel launch failed");
+    if (stats)
+        for (int i = 0; i < 5; i++) stats[i] = st[i];
+    return MW_OK;
+}
+
+}  // namespace
+
+}  // namespace mw
+
+extern "C" const mw::DevPlan *mw_internal_devplan(mw_plan plan);
+
+extern "C" mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes)
+{
+    using namespace mw;
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (!bytes) return fail(MW_EINVAL, "NULL bytes");
+    if (nroots < 1 || nroots > PT2_MAXR) return fail(MW_EUNSUPPORTED, "pt2: nroots must be in 1..8");
+    // one pass without screening: every excitation of every J as a record
+    uint64_t first[2];
+    if (hipMemcpy(first, d->dets, 16, hipMemcpyDeviceToHost) != hipSuccess) return fail(MW_EHIP, "reading the space failed");
+    const bool cplx = d->kind == MW_SPINOR;
+    const int na = __builtin_popcountll(first[0]) + (cplx ? __builtin_popcountll(first[1]) : 0);
+    const int nbeta = cplx ? 0 : __builtin_popcountll(first[1]);
+    ExcClasses ex;
+    if (!classes(*d, na, nbeta, ex)) return fail(MW_EUNSUPPORTED, "pt2: more than 2^31 excitations per determinant");
+    const uint64_t T = (uint64_t)d->ndet * (uint64_t)ex.start[ex.nclass];
+    uint64_t NB = 1;
+    while (NB * PT2_MEAN < T) NB <<= 1;
+    const size_t sc = cplx ? 16 : 8;
+    *bytes = 8192 + 8 * (size_t)d->ndet * d->M + 8 * (size_t)d->M * d->M + 20 * set_size(d->ndet) +
+             NB * (4 + 4 + 8 + 8 * (size_t)nroots + 16) + T * (sizeof(Rec) + sc * nroots);
+    return MW_OK;
+}
+
+extern "C" mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const double *e0, double qmin,
+                            void *work, size_t work_bytes, double *e2, int64_t *stats, mw_stream_t stream)
+{
+    using namespace mw;
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (nroots < 1 || nroots > PT2_MAXR) return fail(MW_EUNSUPPORTED, "pt2: nroots must be in 1..8");
+    if (!c || !e0 || !e2 || !work) return fail(MW_EINVAL, "NULL argument");
+    if (!(qmin >= 0.0)) return fail(MW_EINVAL, "qmin must be >= 0");
+    if (d->ndet > 0x7fffffffLL) return fail(MW_EUNSUPPORTED, "pt2: at most 2^31 - 1 determinants");
+    hipStream_t s = (hipStream_t)stream;
+    return d->kind == MW_SPINOR ? pt2_t<true>(*d, nroots, c, e0, qmin, work, work_bytes, e2, stats, s)
+                                : pt2_t<false>(*d, nroots, c, e0, qmin, work, work_bytes, e2, stats, s);
+}

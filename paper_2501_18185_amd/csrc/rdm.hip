@@ -45,6 +45,15 @@ __device__ __forceinline__ typename Scal<CPLX>::T pair_weight(const typename Sca
 }
 
 __device__ __forceinline__ void atom_add(double *a, double v) { atomicAdd(a, v); }
+
+__device__ __forceinline__ int rdm_pair_lex(int lo, int hi, int m) { return lo * (2 * m - lo - 1) / 2 + (hi - lo - 1); }
+
+// same XCD-aware block order as the sigma kernels
+__device__ __forceinline__ int64_t xcd_block_r(int64_t b)
+{
+    const int64_t x = b & 7, r = b >> 3;
+    return ((r / 16) * 8 + x) * 16 + (r % 16);
+}
 __device__ __forceinline__ void atom_add(double2 *a, double2 v)
 {
     atomicAdd(&a->x, v.x);
@@ -57,13 +66,24 @@ __device__ __forceinline__ size_t g4(int m, int a, int b, int c, int d)
     return (((size_t)a * m + b) * m + c) * m + d;
 }
 
-template <bool CPLX>
+// Double pairs.  The accumulators are laid out like the integral tables of
+// sigma (row from the partner j, column from the member i) and use the same
+// per-member layout bit, so the 64 lanes of a wave add into a run of
+// neighbouring entries.  Alpha-beta: D_ab[q][s][p][r] holds G(p,q,r,s) =
+// sum of w over pairs with i adding (p alpha, r beta) and j adding (q, s);
+// layout-1 lanes add into D_ab[s][q][r][p], i.e. G(r,s,p,q), which changes
+// nothing because Gamma only needs G(p,q,r,s) + G(r,s,p,q).  Pair
+// accumulators DT0 (colex columns) and DT1 (lex columns) hold the
+// transposed antisymmetric pair matrix, D[(P,R)][(Q,S)] = DT0[QS][PR] +
+// DT1[QS][lex PR].
+template <bool CPLX, int U>
 __global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
-                                                    double *__restrict__ gab, typename Scal<CPLX>::T *__restrict__ D)
+                                                    double *__restrict__ dab, typename Scal<CPLX>::T *__restrict__ dt0,
+                                                    typename Scal<CPLX>::T *__restrict__ dt1)
 {
     using T = typename Scal<CPLX>::T;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = xcd_block_r(blockIdx.x) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (wave >= p.npacket_double) return;
     const uint32_t m = p.pk_off[wave] + lane;
@@ -74,22 +94,39 @@ __global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const type
     const uint2 me = p.mem[m];
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
     const uint32_t negi = (me.y >> 16) & 1;
+    const bool lay = (me.y >> 17) & 1;
     const int n = p.n;
-    for (uint32_t j = j0; j < j1; j++) {
-        const uint2 o = p.mem[j];
-        const int Xj = o.y & 255, Yj = (o.y >> 8) & 255;
-        if (Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi) continue;
-        T w = pair_weight<CPLX>(bra, ket, R, me.x, o.x, W);
-        w = sc_neg(w, (negi ^ ((o.y >> 16) & 1)) != 0);
-        if constexpr (!CPLX) {
-            if (type == G_AB) {
-                atomicAdd(&gab[g4(n, Xi, Xj, Yi - n, Yj - n)], w);
-                continue;
+    const bool ab = !CPLX && type == G_AB;
+    const int off = (!CPLX && type == G_BB) ? n : 0;
+    const int mpos = CPLX ? p.M : n;
+    size_t col;
+    if (ab) col = lay ? (size_t)(Yi - n) * n + Xi : (size_t)Xi * n + (Yi - n);
+    else col = lay ? (size_t)rdm_pair_lex(Xi - off, Yi - off, mpos) : (size_t)pair_idx(Xi - off, Yi - off);
+    T *dst_pair = lay ? dt1 : dt0;
+    for (uint32_t j = j0; j < j1; j += U) {
+        uint2 o[U];
+        bool hit[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const bool in = j + u < j1;
+            o[u] = p.mem[in ? j + u : j0];
+            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
+            hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (!hit[u]) continue;
+            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
+            T w = pair_weight<CPLX>(bra, ket, R, me.x, o[u].x, W);
+            w = sc_neg(w, (negi ^ ((o[u].y >> 16) & 1)) != 0);
+            if constexpr (!CPLX) {
+                if (ab) {
+                    const size_t row = lay ? (size_t)(Yj - n) * n + Xj : (size_t)Xj * n + (Yj - n);
+                    atomicAdd(&dab[row * n * n + col], w);
+                    continue;
+                }
             }
-            const int off = type == G_BB ? n : 0;
-            atomicAdd(&D[(size_t)pair_idx(Xi - off, Yi - off) * p.npair + pair_idx(Xj - off, Yj - off)], w);
-        } else {
-            atom_add(&D[(size_t)pair_idx(Xi, Yi) * p.npair + pair_idx(Xj, Yj)], w);
+            atom_add(&dst_pair[(size_t)pair_idx(Xj - off, Yj - off) * p.npair + col], w);
         }
     }
 }
@@ -223,21 +260,31 @@ __global__ __launch_bounds__(256) void k_rdm_diag_spinor(DevPlan p, int R, const
         }
 }
 
-// D-term of Gamma_abcd from the antisymmetric pair accumulator
+// D[(P,R)][(Q,S)] (P<R added in the bra determinant, Q<S in the ket one)
+// from the transposed accumulators
 template <typename T>
-__device__ __forceinline__ T d_term(const T *D, int np, int a, int b, int c, int d)
+__device__ __forceinline__ T d_pair(const T *dt0, const T *dt1, int np, int m, int p, int r, int q, int s)
+{
+    const size_t row = (size_t)pair_idx(q, s) * np;
+    return sc_add(dt0[row + pair_idx(p, r)], dt1[row + rdm_pair_lex(p, r, m)]);
+}
+
+// D-term of Gamma_abcd: the one tuple of the expansion that lands on (a,b,c,d)
+template <typename T>
+__device__ __forceinline__ T d_term(const T *dt0, const T *dt1, int np, int m, int a, int b, int c, int d)
 {
     if (a == c || b == d) return sc_zero(T());
     if (a < c) {
-        if (b < d) return D[(size_t)pair_idx(a, c) * np + pair_idx(b, d)];
-        return sc_neg(D[(size_t)pair_idx(a, c) * np + pair_idx(d, b)], true);
+        if (b < d) return d_pair(dt0, dt1, np, m, a, c, b, d);
+        return sc_neg(d_pair(dt0, dt1, np, m, a, c, d, b), true);
     }
-    if (d < b) return D[(size_t)pair_idx(c, a) * np + pair_idx(d, b)];
-    return sc_neg(D[(size_t)pair_idx(c, a) * np + pair_idx(b, d)], true);
+    if (d < b) return d_pair(dt0, dt1, np, m, c, a, d, b);
+    return sc_neg(d_pair(dt0, dt1, np, m, c, a, b, d), true);
 }
 
-__global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double *__restrict__ gab,
-                                                         const double *__restrict__ D, const double *__restrict__ S,
+__global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double *__restrict__ dab,
+                                                         const double *__restrict__ dt0,
+                                                         const double *__restrict__ dt1, const double *__restrict__ S,
                                                          double *__restrict__ gam, double *__restrict__ Gam)
 {
     const int n = p.n;
@@ -245,7 +292,9 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double
     const int64_t n4 = (int64_t)n * n * n * n;
     if (t >= n4) return;
     const int dd = t % n, c = (t / n) % n, b = (t / n / n) % n, a = (int)(t / n / n / n);
-    double v = Gam[t] + gab[t] + gab[g4(n, c, dd, a, b)] + d_term(D, p.npair, a, b, c, dd);
+    // G(p,q,r,s) lives at dab[q][s][p][r]
+    const double gpqrs = dab[g4(n, b, dd, a, c)] + dab[g4(n, dd, b, c, a)];
+    double v = Gam[t] + gpqrs + d_term(dt0, dt1, p.npair, n, a, b, c, dd);
     const double *S0 = S, *S1 = S + (size_t)n * n;
     auto occ = [&](uint64_t w, int x) { return (double)((w >> x) & 1); };
     if (c == dd) v += (S0[a * n + b] + S1[a * n + b]) * (occ(p.ref0, c) + occ(p.ref1, c));
@@ -256,7 +305,8 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double
     if (t < (int64_t)n * n) gam[t] += S0[t] + S1[t];
 }
 
-__global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const double2 *__restrict__ D,
+__global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const double2 *__restrict__ dt0,
+                                                             const double2 *__restrict__ dt1,
                                                              const double2 *__restrict__ S,
                                                              double2 *__restrict__ gam, double2 *__restrict__ Gam)
 {
@@ -265,7 +315,7 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
     const int64_t m4 = (int64_t)M * M * M * M;
     if (t >= m4) return;
     const int dd = t % M, c = (t / M) % M, b = (t / M / M) % M, a = (int)(t / M / M / M);
-    double2 v = sc_add(Gam[t], d_term(D, p.npair, a, b, c, dd));
+    double2 v = sc_add(Gam[t], d_term(dt0, dt1, p.npair, M, a, b, c, dd));
     auto inref = [&](int X) { return X < n ? ((p.ref0 >> X) & 1) : ((p.ref1 >> (X - n)) & 1); };
     if (c == dd && inref(c)) v = sc_add(v, S[(size_t)a * M + b]);
     if (a == b && inref(a)) v = sc_add(v, S[(size_t)c * M + dd]);
@@ -279,6 +329,12 @@ __global__ void k_zero(double *x, int64_t n)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
         x[t] = 0.0;
+}
+
+static unsigned xcd_grid_r(int64_t blocks)
+{
+    const int64_t q = 8 * 16;
+    return (unsigned)((blocks + q - 1) / q * q);
 }
 
 static void zero(double *x, int64_t n, hipStream_t s)
@@ -297,40 +353,41 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
     const unsigned gd = (unsigned)((p.npacket_double + 3) / 4);
     const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
     const unsigned gdet = (unsigned)((p.ndet + 255) / 256);
+    const unsigned gdx = xcd_grid_r((p.npacket_double + 3) / 4);
     if (p.kind == MW_SPIN_FREE) {
         const int64_t n4 = (int64_t)n * n * n * n, np2 = (int64_t)p.npair * p.npair;
-        double *gab = (double *)p.partial, *D = gab + n4, *S = D + np2;
-        zero(gab, n4 + np2 + 2 * (int64_t)n * n, s);
+        double *dab = (double *)p.partial, *dt0 = dab + n4, *dt1 = dt0 + np2, *S = dt1 + np2;
+        zero(dab, n4 + 2 * np2 + 2 * (int64_t)n * n, s);
         zero((double *)gamma, (int64_t)n * n, s);
         zero((double *)Gamma, n4, s);
         ProfToken t = prof_begin("rdm_groups", s);
-        if (gd) hipLaunchKernelGGL(k_rdm_double<false>, dim3(gd), dim3(256), 0, s, p, R, (const double *)bra,
-                                   (const double *)ket, W, gab, D);
+        if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8>), dim3(gdx), dim3(256), 0, s, p, R, (const double *)bra,
+                                   (const double *)ket, W, dab, dt0, dt1);
         if (gs) hipLaunchKernelGGL(k_rdm_single<false>, dim3(gs), dim3(256), 0, s, p, R, (const double *)bra,
                                    (const double *)ket, W, S, (double *)Gamma);
         prof_end(t, s);
         t = prof_begin("rdm_diag", s);
         hipLaunchKernelGGL(k_rdm_diag_sf, dim3(gdet), dim3(256), 2 * n * n * sizeof(double), s, p, R,
                            (const double *)bra, (const double *)ket, W, (double *)gamma, (double *)Gamma);
-        hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, gab, D, S,
-                           (double *)gamma, (double *)Gamma);
+        hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, dab, dt0, dt1,
+                           S, (double *)gamma, (double *)Gamma);
         prof_end(t, s);
     } else {
         const int64_t m4 = (int64_t)M * M * M * M, np2 = (int64_t)p.npair * p.npair;
-        double2 *D = (double2 *)p.partial, *S = D + np2;
-        zero((double *)D, 2 * (np2 + (int64_t)M * M), s);
+        double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2;
+        zero((double *)dt0, 2 * (2 * np2 + (int64_t)M * M), s);
         zero((double *)gamma, 2 * (int64_t)M * M, s);
         zero((double *)Gamma, 2 * m4, s);
         ProfToken t = prof_begin("rdm_groups", s);
-        if (gd) hipLaunchKernelGGL(k_rdm_double<true>, dim3(gd), dim3(256), 0, s, p, R, (const double2 *)bra,
-                                   (const double2 *)ket, W, (double *)nullptr, D);
+        if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4>), dim3(gdx), dim3(256), 0, s, p, R, (const double2 *)bra,
+                                   (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
         if (gs) hipLaunchKernelGGL(k_rdm_single<true>, dim3(gs), dim3(256), 0, s, p, R, (const double2 *)bra,
                                    (const double2 *)ket, W, S, (double2 *)Gamma);
         prof_end(t, s);
         t = prof_begin("rdm_diag", s);
         hipLaunchKernelGGL(k_rdm_diag_spinor, dim3(gdet), dim3(256), 0, s, p, R, (const double2 *)bra,
                            (const double2 *)ket, W, (double2 *)gamma, (double2 *)Gamma);
-        hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, D, S,
+        hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, dt0, dt1, S,
                            (double2 *)gamma, (double2 *)Gamma);
         prof_end(t, s);
     }

@@ -71,10 +71,14 @@ def lib():
                                           C.POINTER(i32)]
         L.mw_profile.argtypes = [i32]
         L.mw_profile_read.argtypes = [C.c_char_p, C.POINTER(i64), C.POINTER(C.c_double)]
+        L.mw_pt2_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+        L.mw_pt2.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, C.POINTER(C.c_double),
+                             C.POINTER(i64), vp]
         for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
                      "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
-                     "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched"):
+                     "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched",
+                     "mw_pt2_work_bytes", "mw_pt2"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -258,6 +262,35 @@ class Plan:
         if st not in (0, -7) or (check and not conv):
             _check(st)
         return np.array(list(ev)), out, it.value, conv
+
+
+    def pt2_work_bytes(self, nroots=1):
+        """Work bytes for a one-pass second-order energy without screening."""
+        nb = C.c_size_t()
+        _check(lib().mw_pt2_work_bytes(self._plan, int(nroots), C.byref(nb)))
+        return nb.value
+
+    def pt2(self, c, e0, qmin=0.0, work_bytes=None):
+        """Epstein-Nesbet second-order energies of the states c [ndet] or
+        [ndet, nroots] with zeroth-order energies e0 over the external
+        space.  Returns (e2 numpy [nroots], stats dict)."""
+        torch = _require_gpu()
+        c = self._vec(c)
+        if c.dim() == 1:
+            c = c[:, None].contiguous()
+        nroots = c.shape[1]
+        e0 = np.broadcast_to(np.asarray(e0, dtype=np.float64), (nroots,)).copy()
+        if work_bytes is None:
+            free = torch.cuda.mem_get_info(c.device)[0]
+            work_bytes = min(self.pt2_work_bytes(nroots), int(free * 0.6))
+        work = torch.empty(max(int(work_bytes), 1), dtype=torch.uint8, device=c.device)
+        e2 = (C.c_double * nroots)()
+        st = (C.c_int64 * 5)()
+        e0c = (C.c_double * nroots)(*e0)
+        _check(lib().mw_pt2(self._plan, nroots, C.c_void_p(c.data_ptr()), e0c, float(qmin),
+                            C.c_void_p(work.data_ptr()), int(work_bytes), e2, st, _stream()))
+        stats = dict(zip(["kept_pairs", "external", "passes", "buckets", "enumerated"], list(st)))
+        return np.array(list(e2)), stats
 
 
 def profile(enable: bool):

@@ -16,14 +16,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_library_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "mw.h")).read()
-    names = set(re.findall(r"\b(mw_[a-z_]+)\s*\(", hdr))
+    names = set(re.findall(r"\b(mw_[a-z0-9_]+)\s*\(", hdr))
     names.discard("mw_status")
     assert len(names) >= 15
     L = mw.lib()
     missing = [n for n in sorted(names) if not hasattr(L, n)]
     assert not missing, missing
     out = os.popen(f"nm -D --defined-only {mw.LIB_PATH}").read()
-    exported = set(re.findall(r" T (mw_[a-z_]+)", out))
+    exported = set(re.findall(r" T (mw_[a-z0-9_]+)", out))
     assert exported == names, (exported - names, names - exported)
 
 

@@ -111,6 +111,32 @@ def test_sigma_fci_n8(torch, R):
     assert _rel(s, ref) <= TOL
 
 
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 5])
+def test_sigma_roots_large_groups(torch, R):
+    """FCI n=12 4a4b (245,025 dets): its alpha-beta groups hold 81 members,
+    so every root-chunk width (1, 2, 4 and the ragged tails of 3 and 5
+    roots) meets groups above one 64-member block; sampled rows vs the
+    oracle, and every root agrees with a single-root call (1e-12: root
+    chunks of different width sum in different orders)."""
+    from math import comb
+    n, ne = 12, 4
+    rng = synth.rng_for(0, 12, synth.SEED_SPACE)
+    p = _prob("spinfree", n, ne, ne, synth.space_fci(n, ne, ne), synth.one_body_real(n, rng),
+              synth.two_body_real(n, rng))
+    assert p.ndet == comb(n, ne) ** 2
+    pl = _plan(p, max_roots=R)
+    c = synth.ci_vectors(p.ndet, R, np.random.default_rng(20 + R))
+    s = pl.sigma(_dev(torch, c)).cpu().numpy().reshape(p.ndet, R)
+    rows = np.unique(np.concatenate([np.arange(20), np.random.default_rng(21).choice(p.ndet, 80), [p.ndet - 1]]))
+    ref = sc.sigma(p, c, rows=rows).reshape(len(rows), R)
+    _say("rel err", _rel(s[rows], ref))
+    assert _rel(s[rows], ref) <= TOL
+    one = _plan(p, max_roots=1)
+    for k in range(R):
+        sk = one.sigma(_dev(torch, np.ascontiguousarray(c.reshape(p.ndet, R)[:, k]))).cpu().numpy()
+        assert _rel(sk, s[:, k]) <= TOL, f"root {k}"
+
+
 def test_sigma_reproducible_bits(torch):
     p = synth.workload(0)
     pl = _plan(p)
