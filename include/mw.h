@@ -115,8 +115,9 @@ mw_status mw_plan_destroy(mw_plan plan);
  * 2 memberships, 3 structurally connected ordered pairs I != J, 4 pairs of
  * single excitations, 5 pairs of double excitations, 6 determinant-pair
  * evaluations per sigma (including the discarded ones), 7 workspace bytes,
- * 8 scalar size in bytes (8 or 16), 9 norb, 10 kind.  Returns -1 for an
- * unknown plan or index. */
+ * 8 scalar size in bytes (8 or 16), 9 norb, 10 kind, 11 packets (waves of
+ * the group launches), 12 packets of double groups, 13 column partial sums
+ * of the large double groups.  Returns -1 for an unknown plan or index. */
 int64_t mw_plan_info(mw_plan plan, int32_t what);
 
 /* sigma_I = sum_J H_IJ c_J for nroots (1..max_roots) vectors: the product of

@@ -84,7 +84,8 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
         a.pk_start[k + 1] = a.pk_start[k] + d[i]->npacket;
         a.blk_start[k + 1] = a.blk_start[k] + (d[i]->ndet * nroots[i] * 16 + 255) / 256;
     }
-    if (a.pk_start[nprob] >= 0xffffffffLL || a.blk_start[nprob] >= 0x7fffffffLL)
+    // one dispatch counts its work-items in 32 bits
+    if (a.pk_start[nprob] * 64 >= 0xffffffffLL - (1 << 20) || a.blk_start[nprob] * 256 >= 0xffffffffLL)
         return fail(MW_EUNSUPPORTED, "too many packets in one batch");
     a.counter = d[ord[0]]->counter;
     // per root-chunk width: problems with a chunk of 4, 2 or 1 roots

@@ -22,6 +22,7 @@
 // All sums are in a fixed order, so repeated calls give identical bits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "mw_internal.h"
@@ -413,19 +414,7 @@ __device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
         I = t / R;
         k = (int)(t - I * R);
         const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
-        // four slots in flight per lane; the additions keep their order
-        uint32_t s = s0 + sub;
-        for (; s + 3 * GL < s1; s += 4 * GL) {
-            uint32_t m[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) m[u] = p.slot_mem[s + u * GL];
-            T v[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) v[u] = partial[(size_t)m[u] * R + k];
-#pragma unroll
-            for (int u = 0; u < 4; u++) acc = sc_add(acc, v[u]);
-        }
-        for (; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
+        for (uint32_t s = s0 + sub; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
     }
 #pragma unroll
     for (int off = GL / 2; off > 0; off >>= 1) {
@@ -442,9 +431,9 @@ __device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
 template <bool CPLX, int GL>
 __global__ __launch_bounds__(256) void k_gather(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ c,
                                                 const typename Scal<CPLX>::T *__restrict__ partial,
-                                                typename Scal<CPLX>::T *__restrict__ sigma)
+                                                typename Scal<CPLX>::T *__restrict__ sigma, int64_t base)
 {
-    gather_body<CPLX, GL>(p, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, R, c, partial, sigma);
+    gather_body<CPLX, GL>(p, base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x, R, c, partial, sigma);
 }
 
 template <bool CPLX, int RC, int U>
@@ -480,9 +469,13 @@ template <bool CPLX, int GL>
 static void launch_gather(const DevPlan &p, int R, const typename Scal<CPLX>::T *c,
                           const typename Scal<CPLX>::T *part, typename Scal<CPLX>::T *sigma, hipStream_t s)
 {
-    int64_t tot = p.ndet * R * GL;
-    hipLaunchKernelGGL((k_gather<CPLX, GL>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p, R, c, part,
-                       sigma);
+    // a dispatch counts its work-items in 32 bits: at most 2^22 blocks each
+    const int64_t tot = p.ndet * R * GL, chunk = (int64_t)256 << 22;
+    for (int64_t b = 0; b < tot; b += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, tot - b);
+        hipLaunchKernelGGL((k_gather<CPLX, GL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, R, c, part,
+                           sigma, b);
+    }
 }
 
 template <bool CPLX>

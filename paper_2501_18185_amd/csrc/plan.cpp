@@ -489,6 +489,9 @@ static mw_status build_groups(HostPlan &P)
         if (cur_cnt) P.pk_off.push_back(cur_start + cur_cnt);
         if (!in_single) P.npacket_double = (int64_t)P.pk_off.size() - 1;
     }
+    // one wave per packet in one dispatch, whose work-item count is 32 bits
+    if (((int64_t)P.pk_off.size() + 1024) * 64 > 0xffffffffLL)
+        return fail(MW_EUNSUPPORTED, "too many packets for one launch");
     // Column partials of large double groups (k >= 64).  Their packets are
     // the 64-member blocks of the group; the wave of block a evaluates each
     // unordered pair with a partner in a block b >= a once (Hermiticity), keeps
@@ -884,6 +887,7 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     case 10: return P.kind;
     case 11: return (int64_t)P.pk_off.size() - 1;
     case 12: return P.npacket_double;
+    case 13: return P.ncol;
     default: return -1;
     }
 }

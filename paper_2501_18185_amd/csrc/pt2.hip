@@ -21,7 +21,7 @@
 //   k_pt2_bucket      one workgroup per bucket: sorts its records by (A, J)
 //                     in LDS, sums each numerator in ascending J, adds
 //                     |num|^2 / (E0 - H_AA) in sorted order
-//   k_pt2_sum         per pass: bucket partial sums in a fixed order
+//   k_pt2_sum1/2      per pass: bucket partial sums in a fixed order
 //
 // Passes over bucket ranges keep the records within the caller's work
 // buffer (the pipelined memory bound of the paper's procedure).  Every sum
@@ -39,12 +39,14 @@ namespace mw {
 
 namespace {
 
-constexpr int PT2_CAP = 2048;    // records one bucket may hold (LDS sort)
-constexpr int PT2_MEAN = 512;    // target records per bucket
-constexpr int PT2_MAXR = 8;      // roots per call
+constexpr int PT2_CAP = 1024;      // records of a bucket sorted by the common kernel (26 KB LDS)
+constexpr int PT2_CAP_BIG = 4096;  // oversized buckets (rare): a kernel with 92 KB LDS
+constexpr int PT2_MEAN = 400;      // target records per bucket
+constexpr int PT2_MAXR = 8;        // roots per call
 
 struct Rec {
     uint64_t a0, a1;
+    double haa;   // H_AA from this record's partner J (the first J of A is used)
     uint64_t j;
 };
 
@@ -223,6 +225,19 @@ __device__ __forceinline__ double cmax_of(const typename Scal<CPLX>::T *c, int R
     return m;
 }
 
+// H_AA - H_JJ for A = J with holes Q (< S) replaced by particles P (< R)
+// (S = R = -1: a single), from the orbital energies of J, eps_X = h_XX +
+// sum_{Y in J, Y != X} V(X, Y), and V(X, Y) = (XX|YY) - (XY|YX):
+//   single  eps_P - eps_Q - V_PQ
+//   double  eps_P + eps_R - eps_Q - eps_S - V_PQ - V_PS - V_RQ - V_RS + V_PR + V_QS
+__device__ __forceinline__ double diag_delta(const double *eps, const double *__restrict__ vg, int M, int Q, int S,
+                                             int P, int R)
+{
+    auto V = [&](int X, int Y) { return vg[(size_t)X * M + Y]; };
+    if (S < 0) return (eps[P] - eps[Q]) - V(P, Q);
+    return (eps[P] + eps[R]) - (eps[Q] + eps[S]) - ((V(P, Q) + V(P, S)) + (V(R, Q) + V(R, S))) + (V(P, R) + V(Q, S));
+}
+
 // <A|H|J> for A = J with holes Q (< S) replaced by particles P (< R)
 // (S = R = -1: a single): the integral with the phase of
 // a+_P a_Q or a+_P a+_R a_S a_Q on J.
@@ -257,16 +272,20 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
                                                   const typename Scal<CPLX>::T *__restrict__ c, double qmin,
                                                   int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt,
                                                   const uint64_t *__restrict__ off, uint32_t *fill, Rec *rec,
-                                                  typename Scal<CPLX>::T *val, unsigned long long *total)
+                                                  typename Scal<CPLX>::T *val, const double *__restrict__ eps,
+                                                  const double *__restrict__ vg, unsigned long long *total,
+                                                  int64_t jbase)
 {
     using T = typename Scal<CPLX>::T;
     __shared__ uint8_t ol[2][128], vl[2][128];
     __shared__ double s_cmax;
     __shared__ T s_c[PT2_MAXR];
+    __shared__ double s_eps[128];
     __shared__ unsigned long long s_tot;
-    const int64_t J = blockIdx.x;
+    const int64_t J = jbase + blockIdx.x;
     const uint64_t j0 = p.dets[2 * J], j1 = p.dets[2 * J + 1];
     const int n = p.n;
+    if (MODE == 2 && (int)threadIdx.x < p.M) s_eps[threadIdx.x] = eps[J * p.M + threadIdx.x];
     if (threadIdx.x == 0) {
         // sector lists: spin-free sector 0 = alpha, 1 = beta; spinor one sector
         int no[2] = {0, 0}, nv[2] = {0, 0};
@@ -307,7 +326,10 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
                 const uint32_t k = atomicAdd(&fill[b], 1u);
                 if (k >= cnt[b]) continue;
                 const uint64_t slot = off[b] + k;
-                rec[slot] = Rec{a0, a1, (uint64_t)J};
+                double hjj;
+                if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
+                else hjj = ((const double *)p.diag)[J];
+                rec[slot] = Rec{a0, a1, hjj + diag_delta(s_eps, vg, p.M, Q, S, P, Rr), (uint64_t)J};
                 const T v = exc_value<CPLX>(p, j0, j1, Q, S, P, Rr);
                 for (int q = 0; q < R; q++) val[slot * R + q] = sc_mul(v, s_c[q]);
             }
@@ -323,7 +345,7 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
 // eps[J][X] = h_XX + sum_{Y in J, Y != X} V(X, Y) and vg[X][Y] = V(X, Y),
 // V(X, Y) = (XX|YY) - (XY|YX) (spin-free: the exchange only for equal
 // spins); then H_AA = H_JJ + the difference of a single or double
-// excitation in O(1) (see diag_from).
+// excitation in O(1) (diag_delta).
 template <bool CPLX>
 __device__ __forceinline__ double vpair(const DevPlan &p, int X, int Y)
 {
@@ -360,50 +382,33 @@ __global__ __launch_bounds__(256) void k_pt2_tables(DevPlan p, double *eps, doub
 }
 
 
-// H_AA from H_JJ of a partner J: A = J with holes Q (< S) replaced by
-// particles P (< R):  single  eps_P - eps_Q - V_PQ;  double  eps_P + eps_R
-// - eps_Q - eps_S - V_PQ - V_PS - V_RQ - V_RS + V_PR + V_QS  (eps of J).
-__device__ __forceinline__ double diag_from(const DevPlan &p, double hjj, const double *eps, const double *vg,
-                                            uint64_t a0, uint64_t a1, uint64_t j0, uint64_t j1)
-{
-    const int n = p.n, M = p.M;
-    const uint64_t x0 = a0 ^ j0, x1 = a1 ^ j1;
-    int hol[2] = {0, 0}, par[2] = {0, 0}, nh = 0, np = 0;
-    for (uint64_t x = j0 & x0; x && nh < 2; x &= x - 1) hol[nh++] = __builtin_ctzll(x);
-    for (uint64_t x = j1 & x1; x && nh < 2; x &= x - 1) hol[nh++] = n + __builtin_ctzll(x);
-    for (uint64_t x = a0 & x0; x && np < 2; x &= x - 1) par[np++] = __builtin_ctzll(x);
-    for (uint64_t x = a1 & x1; x && np < 2; x &= x - 1) par[np++] = n + __builtin_ctzll(x);
-    auto V = [&](int X, int Y) { return vg[(size_t)X * M + Y]; };
-    const int P = par[0], Q = hol[0];
-    if (nh == 1) return hjj + ((eps[P] - eps[Q]) - V(P, Q));
-    const int R = par[1], S = hol[1];
-    const double d = (eps[P] + eps[R]) - (eps[Q] + eps[S]) - ((V(P, Q) + V(P, S)) + (V(R, Q) + V(R, S))) +
-                     (V(P, R) + V(Q, S));
-    return hjj + d;
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_pt2_bucket(DevPlan p, int R, Roots roots, uint32_t b0,
+// One workgroup per bucket (blockIdx.x -> bucket b0 + blockIdx.x, or
+// list[blockIdx.x] for the oversized ones).  Buckets with more than CAP
+// records are left to the larger instance (their sums are written there).
+template <bool CPLX, int CAP>
+__global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t b0, const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ cnt,
                                                     const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
                                                     const typename Scal<CPLX>::T *__restrict__ val,
-                                                    const double *__restrict__ eps, const double *__restrict__ vg,
-                                                    double *__restrict__ part, unsigned long long *__restrict__ partc)
+                                                    double *__restrict__ part, unsigned long long *__restrict__ partc,
+                                                    uint32_t boff)
 {
     using T = typename Scal<CPLX>::T;
-    __shared__ uint64_t s0[PT2_CAP], s1[PT2_CAP];
-    __shared__ uint32_t sj[PT2_CAP];
-    __shared__ uint16_t si[PT2_CAP];
+    __shared__ uint64_t s0[CAP], s1[CAP];
+    __shared__ uint32_t sj[CAP];
+    __shared__ uint16_t si[CAP];
     __shared__ double red[256];
     __shared__ unsigned long long redc[256];
-    const uint32_t b = b0 + blockIdx.x;
+    const uint32_t b = list ? list[boff + blockIdx.x] : b0 + boff + blockIdx.x;
+    const uint32_t slot_out = b - b0;
     const int m = (int)cnt[b];
+    if (m > CAP) return;  // handled by the larger instance
     const uint64_t base = off[b];
     int np2 = 1;
     while (np2 < m) np2 <<= 1;
     for (int i = threadIdx.x; i < np2; i += blockDim.x) {
         if (i < m) {
-            const Rec r = rec[base + i];
+            const Rec &r = rec[base + i];
             s0[i] = r.a0;
             s1[i] = r.a1;
             sj[i] = (uint32_t)r.j;
@@ -444,7 +449,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(DevPlan p, int R, Roots root
         if (i > 0 && s0[i - 1] == a0 && s1[i - 1] == a1) continue;  // not the first record of its A
         int e = i + 1;
         while (e < m && s0[e] == a0 && s1[e] == a1) e++;
-        // numerators in ascending J (records are the kept pairs)
+        // numerators in ascending J (the records are the kept pairs)
         T num[PT2_MAXR];
 #pragma unroll
         for (int k = 0; k < PT2_MAXR; k++) num[k] = sc_zero(T());
@@ -456,12 +461,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(DevPlan p, int R, Roots root
         }
         kept += (unsigned long long)(e - i);
         nq++;
-        const uint32_t J = sj[i];
-        double hjj;
-        if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
-        else hjj = ((const double *)p.diag)[J];
-        const double haa = diag_from(p, hjj, eps + (size_t)J * p.M, vg, a0, a1, p.dets[2 * (size_t)J],
-                                     p.dets[2 * (size_t)J + 1]);
+        const double haa = rec[base + si[i]].haa;  // from the first (smallest) J
 #pragma unroll
         for (int k = 0; k < PT2_MAXR; k++) {
             if (k >= R) continue;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(DevPlan p, int R, Roots root
             if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * R + k] = red[0];
+        if (threadIdx.x == 0) part[(size_t)slot_out * R + k] = red[0];
         __syncthreads();
     }
     for (int w = 0; w < 2; w++) {
@@ -489,28 +489,59 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(DevPlan p, int R, Roots root
             if ((int)threadIdx.x < s) redc[threadIdx.x] += redc[threadIdx.x + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0) partc[2 * (size_t)blockIdx.x + w] = redc[0];
+        if (threadIdx.x == 0) partc[2 * (size_t)slot_out + w] = redc[0];
         __syncthreads();
     }
 }
 
-// out[k] = sum over nb buckets of part[b][k] (k < R), out[R + w] = sum of
-// partc[b][w]; one block, fixed order.
-__global__ __launch_bounds__(256) void k_pt2_sum(int64_t nb, int R, const double *__restrict__ part,
-                                                 const unsigned long long *__restrict__ partc, double *out,
-                                                 unsigned long long *outc)
+// Fixed-order sums over the nb buckets of a pass in two stages: block g of
+// k_pt2_sum1 reduces buckets [g*chunk, (g+1)*chunk) into tmp[g][R + 2]
+// (R energies, then the two counts as doubles-free integers); k_pt2_sum2
+// reduces the blocks.
+constexpr int PT2_SUMB = 256;
+
+__global__ __launch_bounds__(256) void k_pt2_sum1(int64_t nb, int R, const double *__restrict__ part,
+                                                  const unsigned long long *__restrict__ partc, double *tmp,
+                                                  unsigned long long *tmpc)
 {
     __shared__ double red[256];
     __shared__ unsigned long long redc[256];
+    const int64_t chunk = (nb + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(nb, lo + chunk);
     for (int k = 0; k < R + 2; k++) {
         double a = 0.0;
         unsigned long long ac = 0;
-        for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        for (int64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) {
             if (k < R) a += part[b * R + k];
             else ac += partc[2 * b + (k - R)];
         }
         red[threadIdx.x] = a;
         redc[threadIdx.x] = ac;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                red[threadIdx.x] += red[threadIdx.x + s];
+                redc[threadIdx.x] += redc[threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (k < R) tmp[(size_t)blockIdx.x * R + k] = red[0];
+            else tmpc[2 * (size_t)blockIdx.x + (k - R)] = redc[0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pt2_sum2(int R, const double *__restrict__ tmp,
+                                                  const unsigned long long *__restrict__ tmpc, double *out,
+                                                  unsigned long long *outc)
+{
+    __shared__ double red[256];
+    __shared__ unsigned long long redc[256];
+    for (int k = 0; k < R + 2; k++) {
+        red[threadIdx.x] = k < R ? tmp[(size_t)threadIdx.x * R + k] : 0.0;
+        redc[threadIdx.x] = k < R ? 0ULL : tmpc[2 * (size_t)threadIdx.x + (k - R)];
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
             if ((int)threadIdx.x < s) {
@@ -538,12 +569,6 @@ void fill_u32(uint32_t *x, int64_t n, hipStream_t s, uint32_t v = 0u)
     if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
 }
 
-uint64_t set_size(int64_t ndet)
-{
-    uint64_t z = 256;
-    while (z < 2 * (uint64_t)ndet) z <<= 1;
-    return z;
-}
 
 int64_t choose(int a, int b)
 {
@@ -586,7 +611,57 @@ bool classes(const DevPlan &d, int na, int nb_, ExcClasses &ex)
     return true;
 }
 
+uint64_t set_size(int64_t ndet)
+{
+    uint64_t z = 256;
+    while (z < 2 * (uint64_t)ndet) z <<= 1;
+    return z;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// work-buffer layout (both the call and the size query use these)
+size_t fixed_bytes(int64_t ndet, int M)
+{
+    return align256(8 * 16) + align256(8 * (PT2_MAXR + 2)) + align256(8 * (size_t)PT2_SUMB * PT2_MAXR) +
+           align256(16 * (size_t)PT2_SUMB) + align256(8 * (size_t)ndet * M) + align256(8 * (size_t)M * M) +
+           align256(4 * set_size(ndet)) + align256(16 * set_size(ndet));
+}
+
+size_t table_bytes(int64_t NB, int R)
+{
+    return align256(4 * (size_t)NB) * 3 + align256(8 * (size_t)NB) + align256(8 * (size_t)NB * R) +
+           align256(16 * (size_t)NB) + 1024 + 512;
+}
+
+// A dispatch counts its work-items in 32 bits: grids are cut into chunks of
+// at most 2^22 workgroups of 256.
+constexpr int64_t PT2_MAXGRID = (int64_t)1 << 22;
+
+template <bool CPLX, int MODE>
+void launch_enum(const DevPlan &d, const ExcClasses &ex, const DetSet &inP, int R, const typename Scal<CPLX>::T *c,
+                 double qmin, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt, const uint64_t *off, uint32_t *fill,
+                 Rec *rec, typename Scal<CPLX>::T *val, const double *eps, const double *vg, unsigned long long *tot,
+                 hipStream_t s)
+{
+    for (int64_t j = 0; j < d.ndet; j += PT2_MAXGRID) {
+        const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, d.ndet - j);
+        hipLaunchKernelGGL((k_pt2_enum<CPLX, MODE>), dim3(g), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb, b0, b1,
+                           cnt, off, fill, rec, val, eps, vg, tot, j);
+    }
+}
+
+template <bool CPLX, int CAP>
+void launch_bucket(int64_t nblocks, int R, const Roots &roots, uint32_t b0, const uint32_t *list, const uint32_t *cnt,
+                   const uint64_t *off, const Rec *rec, const typename Scal<CPLX>::T *val, double *part,
+                   unsigned long long *partc, hipStream_t s)
+{
+    for (int64_t o = 0; o < nblocks; o += PT2_MAXGRID) {
+        const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, nblocks - o);
+        hipLaunchKernelGGL((k_pt2_bucket<CPLX, CAP>), dim3(g), dim3(256), 0, s, R, roots, b0, list, cnt, off, rec, val,
+                           part, partc, (uint32_t)o);
+    }
+}
 
 template <bool CPLX>
 mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, double qmin, void *work,
@@ -617,6 +692,8 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
     unsigned long long *tot = (unsigned long long *)take(8 * 16);
     double *sums = (double *)take(8 * (PT2_MAXR + 2));
     unsigned long long *sumc = (unsigned long long *)(sums + PT2_MAXR);
+    double *stmp = (double *)take(8 * (size_t)PT2_SUMB * PT2_MAXR);
+    unsigned long long *stmpc = (unsigned long long *)take(16 * (size_t)PT2_SUMB);
     double *eps = (double *)take(8 * (size_t)d.ndet * d.M);
     double *vg = (double *)take(8 * (size_t)d.M * d.M);
     const uint64_t zs = set_size(d.ndet);
@@ -624,22 +701,24 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
     ulonglong2 *skey = (ulonglong2 *)take(16 * zs);
     if (used > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small");
     const DetSet inP{skey, zs - 1};
-    const unsigned grid = (unsigned)d.ndet;
     if (d.ndet > 0 && ex.start[ex.nclass] > 0) {
         fill_u32(sslot, (int64_t)zs, s, 0xffffffffu);
         hipLaunchKernelGGL(k_set_insert, dim3((unsigned)((d.ndet + 255) / 256)), dim3(256), 0, s, d.dets, d.ndet, sslot,
                            zs - 1);
         hipLaunchKernelGGL(k_set_keys, dim3((unsigned)((zs + 255) / 256)), dim3(256), 0, s, d.dets,
                            (const uint32_t *)sslot, zs, skey);
-        hipMemsetAsync(tot, 0, 8, s);
-        hipLaunchKernelGGL((k_pt2_enum<CPLX, 0>), dim3(grid), dim3(256), 0, s, d, ex, inP, R, c, qmin, 0, 0u, 0u,
-                           (uint32_t *)nullptr, (const uint64_t *)nullptr, (uint32_t *)nullptr, (Rec *)nullptr,
-                           (T *)nullptr, tot);
         const int64_t nt = std::max<int64_t>(d.ndet * d.M, (int64_t)d.M * d.M);
         hipLaunchKernelGGL(k_pt2_tables<CPLX>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, d, eps, vg);
-        unsigned long long T_ = 0;
-        if (hipMemcpyAsync(&T_, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-            return fail(MW_EHIP, "pt2: counting pass failed");
+        // kept pairs: counted when screening, else bounded by every excitation
+        unsigned long long T_ = (unsigned long long)d.ndet * (unsigned long long)ex.start[ex.nclass];
+        if (qmin > 0.0) {
+            hipMemsetAsync(tot, 0, 8, s);
+            launch_enum<CPLX, 0>(d, ex, inP, R, c, qmin, 0, 0u, 0u, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 nullptr, tot, s);
+            if (hipMemcpyAsync(&T_, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(MW_EHIP, "pt2: counting pass failed");
+        }
         st[4] = d.ndet * (int64_t)ex.start[ex.nclass];  // excitations enumerated per pass
         if (T_ > 0) {
             int lognb = 0;
@@ -656,21 +735,24 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
                 unsigned long long *partc = (unsigned long long *)take(16 * (size_t)NB);
                 if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small for the bucket tables");
                 fill_u32(cnt, NB, s);
-                hipLaunchKernelGGL((k_pt2_enum<CPLX, 1>), dim3(grid), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb, 0u,
-                                   0u, cnt, (const uint64_t *)nullptr, (uint32_t *)nullptr, (Rec *)nullptr,
-                                   (T *)nullptr, (unsigned long long *)nullptr);
+                launch_enum<CPLX, 1>(d, ex, inP, R, c, qmin, lognb, 0u, 0u, cnt, nullptr, nullptr, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, s);
+                if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: counting launch failed");
                 hc.resize(NB);
                 if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
                     return fail(MW_EHIP, "pt2: bucket counting failed");
                 const uint32_t mx = *std::max_element(hc.begin(), hc.end());
-                if (mx > (uint32_t)PT2_CAP) {
-                    // a bucket too large for one workgroup: split the buckets
-                    if (lognb >= 40) return fail(MW_EUNSUPPORTED, "pt2: bucket overflow");
+                if (mx > (uint32_t)PT2_CAP_BIG) {
+                    // a bucket too large even for the larger kernel: split the
+                    // buckets (one A with more partners than that cannot be split)
+                    if (lognb >= 34) return fail(MW_EUNSUPPORTED, "pt2: an external determinant has too many partners");
                     lognb++;
                     continue;
                 }
-                // passes over bucket ranges whose records (24 B + R values
+                uint32_t *big = (uint32_t *)take(4 * (size_t)NB);
+                if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small for the bucket tables");
+                // passes over bucket ranges whose records (32 B + R values
                 // each) fit the rest of the buffer
                 const size_t per = sizeof(Rec) + (size_t)R * sizeof(T);
                 const uint64_t cap_rec = (work_bytes - used - 512) / per;
@@ -691,17 +773,27 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
                     hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
                     fill_u32(fill + b0, b1 - b0, s);
                     ProfToken t = prof_begin("pt2_enum", s);
-                    hipLaunchKernelGGL((k_pt2_enum<CPLX, 2>), dim3(grid), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb,
-                                       (uint32_t)b0, (uint32_t)b1, cnt, (const uint64_t *)off, fill, rec, val,
-                                       (unsigned long long *)nullptr);
+                    launch_enum<CPLX, 2>(d, ex, inP, R, c, qmin, lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, rec,
+                                         val, eps, vg, nullptr, s);
                     prof_end(t, s);
+                    // oversized buckets of this pass go to the larger instance
+                    std::vector<uint32_t> hb;
+                    for (int64_t b = b0; b < b1; b++)
+                        if (hc[b] > (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
                     t = prof_begin("pt2_bucket", s);
-                    hipLaunchKernelGGL(k_pt2_bucket<CPLX>, dim3((unsigned)(b1 - b0)), dim3(256), 0, s, d, R, roots,
-                                       (uint32_t)b0, (const uint32_t *)cnt, (const uint64_t *)off, (const Rec *)rec,
-                                       (const T *)val, (const double *)eps, (const double *)vg, part, partc);
+                    launch_bucket<CPLX, PT2_CAP>(b1 - b0, R, roots, (uint32_t)b0, nullptr, cnt, off, rec, val, part,
+                                                 partc, s);
+                    if (!hb.empty()) {
+                        hipMemcpyAsync(big, hb.data(), 4 * hb.size(), hipMemcpyHostToDevice, s);
+                        launch_bucket<CPLX, PT2_CAP_BIG>((int64_t)hb.size(), R, roots, (uint32_t)b0, big, cnt, off, rec,
+                                                         val, part, partc, s);
+                    }
+                    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: pass launch failed");
                     prof_end(t, s);
-                    hipLaunchKernelGGL(k_pt2_sum, dim3(1), dim3(256), 0, s, b1 - b0, R, (const double *)part,
-                                       (const unsigned long long *)partc, sums, sumc);
+                    hipLaunchKernelGGL(k_pt2_sum1, dim3(PT2_SUMB), dim3(256), 0, s, b1 - b0, R, (const double *)part,
+                                       (const unsigned long long *)partc, stmp, stmpc);
+                    hipLaunchKernelGGL(k_pt2_sum2, dim3(1), dim3(PT2_SUMB), 0, s, R, (const double *)stmp,
+                                       (const unsigned long long *)stmpc, sums, sumc);
                     double hs[PT2_MAXR + 2];
                     if (hipMemcpyAsync(hs, sums, 8 * (PT2_MAXR + 2), hipMemcpyDeviceToHost, s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess)
@@ -750,8 +842,7 @@ extern "C" mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *byt
     uint64_t NB = 1;
     while (NB * PT2_MEAN < T) NB <<= 1;
     const size_t sc = cplx ? 16 : 8;
-    *bytes = 8192 + 8 * (size_t)d->ndet * d->M + 8 * (size_t)d->M * d->M + 20 * set_size(d->ndet) +
-             NB * (4 + 4 + 8 + 8 * (size_t)nroots + 16) + T * (sizeof(Rec) + sc * nroots);
+    *bytes = fixed_bytes(d->ndet, d->M) + table_bytes((int64_t)NB, nroots) + 256 + T * (sizeof(Rec) + sc * nroots);
     return MW_OK;
 }
 

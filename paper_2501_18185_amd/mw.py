@@ -22,7 +22,7 @@ STATUS = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOTSORTED", -3: "MW_EELEC", -4: 
           -5: "MW_EWORKSPACE", -6: "MW_EHIP", -7: "MW_ENOCONV", -8: "MW_EUNSUPPORTED"}
 INFO = {"ndet": 0, "groups": 1, "memberships": 2, "pairs": 3, "single_pairs": 4,
         "double_pairs": 5, "evaluations": 6, "workspace_bytes": 7, "scalar_bytes": 8,
-        "norb": 9, "kind": 10, "packets": 11}
+        "norb": 9, "kind": 10, "packets": 11, "double_packets": 12, "column_partials": 13}
 
 
 class MWError(RuntimeError):
