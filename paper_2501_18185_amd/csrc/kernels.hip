@@ -64,15 +64,19 @@ mw_status launch_diag(const DevPlan &p, hipStream_t s)
 // the same values with transposed column order, so that the members of a
 // wave read runs of consecutive columns.
 struct DoubleIndex {
-    size_t col;
-    size_t row_stride;
-    int n, off, ab, lay;
-    __device__ __forceinline__ size_t row(int Xj, int Yj) const
+    uint32_t col;
+    uint32_t row_stride;
+    int n, offx, offy, ab, lay;
+    // element index (below 2^32 for every table), without branches: the
+    // lanes of a wave mix group types and layouts
+    __device__ __forceinline__ uint32_t at(int Xj, int Yj) const
     {
+        const int x = Xj - offx, y = Yj - offy;
         // alpha-beta, layout 1: the row (s_j, q_j) of the same table holds
         // the row (q_j, s_j) with the column indices transposed
-        if (ab) return (lay ? (size_t)(Yj - n) * n + Xj : (size_t)Xj * n + (Yj - n)) * row_stride;
-        return (size_t)pair_idx(Xj - off, Yj - off) * row_stride;
+        const uint32_t rab = lay ? (uint32_t)(y * n + x) : (uint32_t)(x * n + y);
+        const uint32_t rpr = (uint32_t)((y * (y - 1)) >> 1) + (uint32_t)x;
+        return (ab ? rab : rpr) * row_stride + col;
     }
 };
 
@@ -88,16 +92,17 @@ __device__ __forceinline__ DoubleIndex double_index(const DevPlan &p, uint8_t ty
         // (p_i q_j | r_i s_j) = g_ab[q][s][p][r] (layout 0) = g_ab[s][q][r][p]
         // (layout 1: p fastest across the lanes)
         d.ab = 1;
-        d.off = 0;
-        d.row_stride = (size_t)p.n * p.n;
+        d.offx = 0;
+        d.offy = p.n;
+        d.row_stride = (uint32_t)(p.n * p.n);
         const int pi = Xi, ri = Yi - p.n;
-        d.col = lay ? (size_t)ri * p.n + pi : (size_t)pi * p.n + ri;
+        d.col = lay ? (uint32_t)(ri * p.n + pi) : (uint32_t)(pi * p.n + ri);
     } else {
         d.ab = 0;
-        d.off = (!CPLX && type == G_BB) ? p.n : 0;
-        d.row_stride = p.npair;
+        d.offx = d.offy = (!CPLX && type == G_BB) ? p.n : 0;
+        d.row_stride = (uint32_t)p.npair;
         const int m = CPLX ? p.M : p.n;
-        d.col = lay ? pair_lex_d(Xi - d.off, Yi - d.off, m) : pair_idx(Xi - d.off, Yi - d.off);
+        d.col = lay ? (uint32_t)pair_lex_d(Xi - d.offx, Yi - d.offx, m) : (uint32_t)pair_idx(Xi - d.offx, Yi - d.offx);
     }
     return d;
 }
@@ -186,14 +191,18 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
                 bool hit[JS];
                 T v[JS];
                 T cj[JS][RC];
+                // partner records first (wave-uniform addresses), then the
+                // coefficients (uniform, loaded whether or not a lane hits)
+                // and the integrals
+#pragma unroll
+                for (int u = 0; u < JS; u++) o[u] = p.mem[jj + u < jb1 ? jj + u : jb0];
 #pragma unroll
                 for (int u = 0; u < JS; u++) {
                     const uint32_t j = jj + u;
                     const bool in = act && j < jb1 && (b > a || j > m);
-                    o[u] = p.mem[j < jb1 ? j : jb0];
                     const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
                     hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
-                    v[u] = tab[hit[u] ? di.row(Xj, Yj) + di.col : 0];
+                    v[u] = tab[hit[u] ? di.at(Xj, Yj) : 0u];
                     const T *cr = c + (size_t)(hit[u] ? o[u].x : 0) * R + r0;
 #pragma unroll
                     for (int kk = 0; kk < RC; kk++) cj[u][kk] = cr[kk < nr ? kk : 0];
@@ -285,23 +294,22 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
     for (uint32_t j = j0; j < j1; j += U) {
         uint2 o[U];
         bool hit[U];
+        // all partner records first, then coefficients and integrals
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const bool in = j + u < j1;
-            o[u] = p.mem[in ? j + u : j0];
-            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
-            hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
-        }
+        for (int u = 0; u < U; u++) o[u] = p.mem[j + u < j1 ? j + u : j0];
         T v[U];
         T cj[U][RC];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
-            const size_t idx = hit[u] ? di.row(Xj, Yj) + di.col : 0;
-            v[u] = tab[idx];
-            const T *cr = c + (size_t)(hit[u] ? o[u].x : 0) * R + r0;
+            const T *cr = c + (size_t)o[u].x * R + r0;
 #pragma unroll
             for (int k = 0; k < RC; k++) cj[u][k] = cr[k < nr ? k : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
+            hit[u] = j + u < j1 && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
+            v[u] = tab[hit[u] ? di.at(Xj, Yj) : 0u];
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {

@@ -245,7 +245,6 @@ template <bool CPLX>
 __device__ __forceinline__ typename Scal<CPLX>::T exc_value(const DevPlan &p, uint64_t j0, uint64_t j1, int Q,
                                                             int S, int P, int R)
 {
-    using T = typename Scal<CPLX>::T;
     const int n = p.n;
     if (S < 0) {
         uint64_t k0 = j0, k1 = j1;

@@ -135,7 +135,8 @@ template <bool CPLX>
 __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
                                                     typename Scal<CPLX>::T *__restrict__ S,
-                                                    typename Scal<CPLX>::T *__restrict__ Gam)
+                                                    typename Scal<CPLX>::T *__restrict__ Cc,
+                                                    double *__restrict__ Ee)
 {
     using T = typename Scal<CPLX>::T;
     const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -161,7 +162,11 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
             const int s = type == G_SINGLE_A ? 0 : 1;
             const int pp = Xi - s * n, qq = Xj - s * n;
             atomicAdd(&S[((size_t)s * n + pp) * n + qq], w);
-            // positions where K and omega differ: words (same spin, other spin)
+            // positions where K and omega differ: words (same spin, other
+            // spin); C[p][q][x] collects the Coulomb-like terms of every X,
+            // E[p][q][x] the exchange-like ones of X of the same spin (both
+            // n^3, L2-resident; expanded into Gamma by the final pass)
+            double *Cpq = Cc + ((size_t)pp * n + qq) * n, *Epq = Ee + ((size_t)pp * n + qq) * n;
             for (int part = 0; part < 4; part++) {
                 const bool same = part < 2;
                 const uint64_t kw = (same == (s == 0)) ? k0 : k1;
@@ -170,94 +175,83 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
                 const double sw = (part & 1) ? -w : w;
                 for (uint64_t x = bits; x; x &= x - 1) {
                     const int xx = __builtin_ctzll(x);
-                    atomicAdd(&Gam[g4(n, pp, qq, xx, xx)], sw);
-                    atomicAdd(&Gam[g4(n, xx, xx, pp, qq)], sw);
-                    if (same) {
-                        atomicAdd(&Gam[g4(n, pp, xx, xx, qq)], -sw);
-                        atomicAdd(&Gam[g4(n, xx, qq, pp, xx)], -sw);
-                    }
+                    atomicAdd(&Cpq[xx], sw);
+                    if (same) atomicAdd(&Epq[xx], sw);
                 }
             }
         } else {
             const int M = p.M;
             atom_add(&S[(size_t)Xi * M + Xj], w);
+            // C[P][Q][X] (M^3) collects the four terms of every X
+            T *Cpq = Cc + ((size_t)Xi * M + Xj) * M;
             for (int part = 0; part < 4; part++) {
                 const uint64_t kw = (part < 2) ? k0 : k1;
                 const uint64_t rw = (part < 2) ? p.ref0 : p.ref1;
                 const int base = (part < 2) ? 0 : n;
                 const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
                 const T sw = sc_neg(w, (part & 1) != 0);
-                const T nsw = sc_neg(sw, true);
-                for (uint64_t x = bits; x; x &= x - 1) {
-                    const int X = base + __builtin_ctzll(x);
-                    atom_add(&Gam[g4(M, Xi, Xj, X, X)], sw);
-                    atom_add(&Gam[g4(M, X, X, Xi, Xj)], sw);
-                    atom_add(&Gam[g4(M, Xi, X, X, Xj)], nsw);
-                    atom_add(&Gam[g4(M, X, Xj, Xi, X)], nsw);
-                }
+                for (uint64_t x = bits; x; x &= x - 1) atom_add(&Cpq[base + __builtin_ctzll(x)], sw);
             }
         }
     }
 }
 
-// Diagonal, spin-free: per block, Gamma_pprr and Gamma_prrp contributions are
-// accumulated in LDS (n <= 64: two n x n arrays of doubles), then flushed.
-__global__ __launch_bounds__(256) void k_rdm_diag_sf(DevPlan p, int R, const double *__restrict__ bra,
-                                                     const double *__restrict__ ket, RdmWeights W,
-                                                     double *__restrict__ gam, double *__restrict__ Gam)
-{
-    extern __shared__ double lds[];
-    const int n = p.n;
-    double *o1 = lds, *o2 = lds + n * n;
-    for (int t = threadIdx.x; t < 2 * n * n; t += blockDim.x) lds[t] = 0.0;
-    __syncthreads();
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I < p.ndet) {
-        const double w = pair_weight<false>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
-        const uint64_t d[2] = {p.dets[2 * I], p.dets[2 * I + 1]};
-        for (int sa = 0; sa < 2; sa++)
-            for (uint64_t xa = d[sa]; xa; xa &= xa - 1) {
-                const int a = __builtin_ctzll(xa);
-                atomicAdd(&gam[(size_t)a * n + a], w);
-                for (int sb = 0; sb < 2; sb++)
-                    for (uint64_t xb = d[sb]; xb; xb &= xb - 1) {
-                        const int b = __builtin_ctzll(xb);
-                        if (sa == sb && a == b) continue;
-                        atomicAdd(&o1[a * n + b], w);
-                        if (sa == sb) atomicAdd(&o2[a * n + b], w);
-                    }
-            }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-        const int a = t / n, b = t % n;
-        if (o1[t] != 0.0) atomicAdd(&Gam[g4(n, a, a, b, b)], o1[t]);
-        if (o2[t] != 0.0) atomicAdd(&Gam[g4(n, a, b, b, a)], -o2[t]);
-    }
-}
+// Diagonal terms: with w_I = sum_k w_k conj(bra_Ik) ket_Ik, the occupation
+// correlation D[A][B] = sum_I w_I n_A(I) n_B(I) over global positions gives
+// gamma_AA = D[A][A] and the diagonal parts of Gamma (Gamma_AABB += D[A][B],
+// Gamma_ABBA -= D[A][B] for A != B; spin-free: summed over spins, the
+// exchange-like part for equal spins only).  Block (x, y): determinants of
+// chunk x, positions A of chunk y (AW per wave); lane l holds B = l, l + 64;
+// one partial matrix per determinant chunk, reduced in a fixed order.
+constexpr int RDM_OCC_CHUNKS = 256;
 
-__global__ __launch_bounds__(256) void k_rdm_diag_spinor(DevPlan p, int R, const double2 *__restrict__ bra,
-                                                         const double2 *__restrict__ ket, RdmWeights W,
-                                                         double2 *__restrict__ gam, double2 *__restrict__ Gam)
+template <bool CPLX, int AW>
+__global__ __launch_bounds__(256) void k_rdm_occ(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
+                                                 const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
+                                                 typename Scal<CPLX>::T *__restrict__ part)
 {
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= p.ndet) return;
+    using T = typename Scal<CPLX>::T;
     const int n = p.n, M = p.M;
-    const double2 w = pair_weight<true>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
-    const double2 nw = make_double2(-w.x, -w.y);
-    const uint64_t d[2] = {p.dets[2 * I], p.dets[2 * I + 1]};
-    for (int sa = 0; sa < 2; sa++)
-        for (uint64_t xa = d[sa]; xa; xa &= xa - 1) {
-            const int A = sa * n + __builtin_ctzll(xa);
-            atom_add(&gam[(size_t)A * M + A], w);
-            for (int sb = 0; sb < 2; sb++)
-                for (uint64_t xb = d[sb]; xb; xb &= xb - 1) {
-                    const int B = sb * n + __builtin_ctzll(xb);
-                    if (A == B) continue;
-                    atom_add(&Gam[g4(M, A, A, B, B)], w);
-                    atom_add(&Gam[g4(M, A, B, B, A)], nw);
-                }
+    const int lane = threadIdx.x & 63;
+    const int A0 = (int)blockIdx.y * 4 * AW + (int)(threadIdx.x >> 6) * AW;
+    const int64_t chunk = (p.ndet + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(p.ndet, lo + chunk);
+    auto occ = [&](uint64_t d0, uint64_t d1, int X) { return X < n ? ((d0 >> X) & 1) : ((d1 >> (X - n)) & 1); };
+    T acc[AW][2];
+#pragma unroll
+    for (int a = 0; a < AW; a++) acc[a][0] = acc[a][1] = sc_zero(T());
+    const int B0 = lane, B1 = lane + 64;
+    for (int64_t I = lo; I < hi; I++) {
+        const uint64_t d0 = p.dets[2 * I], d1 = p.dets[2 * I + 1];
+        const T w = pair_weight<CPLX>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
+        const bool o0 = B0 < M && occ(d0, d1, B0), o1 = B1 < M && occ(d0, d1, B1);
+#pragma unroll
+        for (int a = 0; a < AW; a++) {
+            const int A = A0 + a;
+            if (A < M && occ(d0, d1, A)) {
+                if (o0) acc[a][0] = sc_add(acc[a][0], w);
+                if (o1) acc[a][1] = sc_add(acc[a][1], w);
+            }
         }
+    }
+    T *out = part + (size_t)blockIdx.x * M * M;
+#pragma unroll
+    for (int a = 0; a < AW; a++) {
+        const int A = A0 + a;
+        if (A >= M) continue;
+        if (B0 < M) out[(size_t)A * M + B0] = acc[a][0];
+        if (B1 < M) out[(size_t)A * M + B1] = acc[a][1];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rdm_occ_reduce(int M, int nchunk, const T *__restrict__ part, T *__restrict__ D)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M * M) return;
+    T s = sc_zero(T());
+    for (int c = 0; c < nchunk; c++) s = sc_add(s, part[(size_t)c * M * M + t]);
+    D[t] = s;
 }
 
 // D[(P,R)][(Q,S)] (P<R added in the bra determinant, Q<S in the ket one)
@@ -285,29 +279,46 @@ __device__ __forceinline__ T d_term(const T *dt0, const T *dt1, int np, int m, i
 __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double *__restrict__ dab,
                                                          const double *__restrict__ dt0,
                                                          const double *__restrict__ dt1, const double *__restrict__ S,
-                                                         double *__restrict__ gam, double *__restrict__ Gam)
+                                                         const double *__restrict__ Cc, const double *__restrict__ Ee,
+                                                         const double *__restrict__ D, double *__restrict__ gam,
+                                                         double *__restrict__ Gam)
 {
-    const int n = p.n;
+    const int n = p.n, M = p.M;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n4 = (int64_t)n * n * n * n;
     if (t >= n4) return;
     const int dd = t % n, c = (t / n) % n, b = (t / n / n) % n, a = (int)(t / n / n / n);
     // G(p,q,r,s) lives at dab[q][s][p][r]
     const double gpqrs = dab[g4(n, b, dd, a, c)] + dab[g4(n, dd, b, c, a)];
-    double v = Gam[t] + gpqrs + d_term(dt0, dt1, p.npair, n, a, b, c, dd);
+    double v = gpqrs + d_term(dt0, dt1, p.npair, n, a, b, c, dd);
     const double *S0 = S, *S1 = S + (size_t)n * n;
     auto occ = [&](uint64_t w, int x) { return (double)((w >> x) & 1); };
-    if (c == dd) v += (S0[a * n + b] + S1[a * n + b]) * (occ(p.ref0, c) + occ(p.ref1, c));
-    if (a == b) v += (S0[c * n + dd] + S1[c * n + dd]) * (occ(p.ref0, a) + occ(p.ref1, a));
-    if (b == c) v -= S0[a * n + dd] * occ(p.ref0, b) + S1[a * n + dd] * occ(p.ref1, b);
-    if (a == dd) v -= S0[c * n + b] * occ(p.ref0, a) + S1[c * n + b] * occ(p.ref1, a);
+    auto cpq = [&](const double *X, int pp, int qq, int xx) { return X[((size_t)pp * n + qq) * n + xx]; };
+    // single excitations: reference string omega (through S) + corrections
+    if (c == dd) v += (S0[a * n + b] + S1[a * n + b]) * (occ(p.ref0, c) + occ(p.ref1, c)) + cpq(Cc, a, b, c);
+    if (a == b) v += (S0[c * n + dd] + S1[c * n + dd]) * (occ(p.ref0, a) + occ(p.ref1, a)) + cpq(Cc, c, dd, a);
+    if (b == c) v -= S0[a * n + dd] * occ(p.ref0, b) + S1[a * n + dd] * occ(p.ref1, b) + cpq(Ee, a, dd, b);
+    if (a == dd) v -= S0[c * n + b] * occ(p.ref0, a) + S1[c * n + b] * occ(p.ref1, a) + cpq(Ee, c, b, a);
+    // diagonal terms from the occupation correlations D over 2n positions
+    auto Dg = [&](int A, int B) { return D[(size_t)A * M + B]; };
+    if (a == b && c == dd) {
+        double s = Dg(a, n + c) + Dg(n + a, c);
+        if (a != c) s += Dg(a, c) + Dg(n + a, n + c);
+        v += s;
+    }
+    if (a == dd && b == c && a != b) v -= Dg(a, b) + Dg(n + a, n + b);
     Gam[t] = v;
-    if (t < (int64_t)n * n) gam[t] += S0[t] + S1[t];
+    if (t < (int64_t)n * n) {
+        const int pa = (int)(t / n), qa = (int)(t % n);
+        gam[t] = S0[t] + S1[t] + (pa == qa ? Dg(pa, pa) + Dg(n + pa, n + pa) : 0.0);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const double2 *__restrict__ dt0,
                                                              const double2 *__restrict__ dt1,
                                                              const double2 *__restrict__ S,
+                                                             const double2 *__restrict__ Cc,
+                                                             const double2 *__restrict__ D,
                                                              double2 *__restrict__ gam, double2 *__restrict__ Gam)
 {
     const int M = p.M, n = p.n;
@@ -315,14 +326,20 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
     const int64_t m4 = (int64_t)M * M * M * M;
     if (t >= m4) return;
     const int dd = t % M, c = (t / M) % M, b = (t / M / M) % M, a = (int)(t / M / M / M);
-    double2 v = sc_add(Gam[t], d_term(dt0, dt1, p.npair, M, a, b, c, dd));
+    double2 v = d_term(dt0, dt1, p.npair, M, a, b, c, dd);
     auto inref = [&](int X) { return X < n ? ((p.ref0 >> X) & 1) : ((p.ref1 >> (X - n)) & 1); };
-    if (c == dd && inref(c)) v = sc_add(v, S[(size_t)a * M + b]);
-    if (a == b && inref(a)) v = sc_add(v, S[(size_t)c * M + dd]);
-    if (b == c && inref(b)) v = sc_add(v, sc_neg(S[(size_t)a * M + dd], true));
-    if (a == dd && inref(a)) v = sc_add(v, sc_neg(S[(size_t)c * M + b], true));
+    auto cpq = [&](int P, int Q, int X) { return Cc[((size_t)P * M + Q) * M + X]; };
+    if (c == dd) v = sc_add(v, sc_add(inref(c) ? S[(size_t)a * M + b] : sc_zero(double2()), cpq(a, b, c)));
+    if (a == b) v = sc_add(v, sc_add(inref(a) ? S[(size_t)c * M + dd] : sc_zero(double2()), cpq(c, dd, a)));
+    if (b == c) v = sc_add(v, sc_neg(sc_add(inref(b) ? S[(size_t)a * M + dd] : sc_zero(double2()), cpq(a, dd, b)), true));
+    if (a == dd) v = sc_add(v, sc_neg(sc_add(inref(a) ? S[(size_t)c * M + b] : sc_zero(double2()), cpq(c, b, a)), true));
+    if (a == b && c == dd && a != c) v = sc_add(v, D[(size_t)a * M + c]);
+    if (a == dd && b == c && a != b) v = sc_add(v, sc_neg(D[(size_t)a * M + b], true));
     Gam[t] = v;
-    if (t < (int64_t)M * M) gam[t] = sc_add(gam[t], S[t]);
+    if (t < (int64_t)M * M) {
+        const int A = (int)(t / M), B = (int)(t % M);
+        gam[t] = sc_add(S[t], A == B ? D[t] : sc_zero(double2()));
+    }
 }
 
 __global__ void k_zero(double *x, int64_t n)
@@ -352,43 +369,46 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
     const int n = p.n, M = p.M;
     const unsigned gd = (unsigned)((p.npacket_double + 3) / 4);
     const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
-    const unsigned gdet = (unsigned)((p.ndet + 255) / 256);
     const unsigned gdx = xcd_grid_r((p.npacket_double + 3) / 4);
+    const int64_t mm = (int64_t)M * M;
+    const unsigned gred = (unsigned)((mm + 255) / 256);
     if (p.kind == MW_SPIN_FREE) {
-        const int64_t n4 = (int64_t)n * n * n * n, np2 = (int64_t)p.npair * p.npair;
+        const int64_t n4 = (int64_t)n * n * n * n, np2 = (int64_t)p.npair * p.npair, n3 = (int64_t)n * n * n;
         double *dab = (double *)p.partial, *dt0 = dab + n4, *dt1 = dt0 + np2, *S = dt1 + np2;
-        zero(dab, n4 + 2 * np2 + 2 * (int64_t)n * n, s);
-        zero((double *)gamma, (int64_t)n * n, s);
-        zero((double *)Gamma, n4, s);
+        double *Cc = S + 2 * (int64_t)n * n, *Ee = Cc + n3, *D = Ee + n3, *part = D + mm;
+        zero(dab, n4 + 2 * np2 + 2 * (int64_t)n * n + 2 * n3, s);
         ProfToken t = prof_begin("rdm_groups", s);
         if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8>), dim3(gdx), dim3(256), 0, s, p, R, (const double *)bra,
                                    (const double *)ket, W, dab, dt0, dt1);
         if (gs) hipLaunchKernelGGL(k_rdm_single<false>, dim3(gs), dim3(256), 0, s, p, R, (const double *)bra,
-                                   (const double *)ket, W, S, (double *)Gamma);
+                                   (const double *)ket, W, S, Cc, Ee);
         prof_end(t, s);
         t = prof_begin("rdm_diag", s);
-        hipLaunchKernelGGL(k_rdm_diag_sf, dim3(gdet), dim3(256), 2 * n * n * sizeof(double), s, p, R,
-                           (const double *)bra, (const double *)ket, W, (double *)gamma, (double *)Gamma);
+        hipLaunchKernelGGL((k_rdm_occ<false, 16>), dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(256), 0, s,
+                           p, R, (const double *)bra, (const double *)ket, W, part);
+        hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
+                           (const double *)part, D);
         hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, dab, dt0, dt1,
-                           S, (double *)gamma, (double *)Gamma);
+                           S, Cc, Ee, D, (double *)gamma, (double *)Gamma);
         prof_end(t, s);
     } else {
-        const int64_t m4 = (int64_t)M * M * M * M, np2 = (int64_t)p.npair * p.npair;
-        double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2;
-        zero((double *)dt0, 2 * (2 * np2 + (int64_t)M * M), s);
-        zero((double *)gamma, 2 * (int64_t)M * M, s);
-        zero((double *)Gamma, 2 * m4, s);
+        const int64_t m4 = mm * mm, np2 = (int64_t)p.npair * p.npair, m3 = mm * M;
+        double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2, *Cc = S + mm, *D = Cc + m3,
+                *part = D + mm;
+        zero((double *)dt0, 2 * (2 * np2 + mm + m3), s);
         ProfToken t = prof_begin("rdm_groups", s);
         if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4>), dim3(gdx), dim3(256), 0, s, p, R, (const double2 *)bra,
                                    (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
         if (gs) hipLaunchKernelGGL(k_rdm_single<true>, dim3(gs), dim3(256), 0, s, p, R, (const double2 *)bra,
-                                   (const double2 *)ket, W, S, (double2 *)Gamma);
+                                   (const double2 *)ket, W, S, Cc, (double *)nullptr);
         prof_end(t, s);
         t = prof_begin("rdm_diag", s);
-        hipLaunchKernelGGL(k_rdm_diag_spinor, dim3(gdet), dim3(256), 0, s, p, R, (const double2 *)bra,
-                           (const double2 *)ket, W, (double2 *)gamma, (double2 *)Gamma);
+        hipLaunchKernelGGL((k_rdm_occ<true, 8>), dim3(RDM_OCC_CHUNKS, (unsigned)((M + 31) / 32)), dim3(256), 0, s, p,
+                           R, (const double2 *)bra, (const double2 *)ket, W, part);
+        hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
+                           (const double2 *)part, D);
         hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, dt0, dt1, S,
-                           (double2 *)gamma, (double2 *)Gamma);
+                           Cc, D, (double2 *)gamma, (double2 *)Gamma);
         prof_end(t, s);
     }
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "rdm kernel launch failed");
