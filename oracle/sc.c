@@ -543,3 +543,80 @@ void orc_pt2(int kind, int n, const double *h, const double *g, double ecore,
     free(cmax);
     free(B.r);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Selection of external determinants by the iCIPT2 criterion (section 2.4):
+ * A outside P, reached from some J in P by one or two excitations, is
+ * selected when for that J
+ *   max_k |H_AJ c_Jk| >= cmin  and  max_k |H_AJ c_Jk / (E0_k - H_AA)| >= cmin.
+ * (The extra condition on the double-excitation upper bound is the first
+ * one again for determinants, whose double element is a single
+ * antisymmetrised integral.)  out (nullable): [max_out][2]; returns the
+ * number of distinct selected determinants, which are written sorted. */
+typedef struct { uint64_t a0, a1; } det_key;
+
+static int key_cmp(const void *x, const void *y)
+{
+    const det_key *a = (const det_key *)x, *b = (const det_key *)y;
+    if (a->a0 != b->a0) return a->a0 < b->a0 ? -1 : 1;
+    return (a->a1 > b->a1) - (a->a1 < b->a1);
+}
+
+long orc_select(int kind, int n, const double *h, const double *g, double ecore,
+                long ndet, const uint64_t *dets, int nroots, const double *c,
+                const double *e0, double cmin, uint64_t *out, long max_out)
+{
+    ham_t H = {kind, n, h, g, ecore};
+    const int M = 2 * n;
+    det_key *sel = NULL;
+    long ns = 0, cap = 0;
+    for (long j = 0; j < ndet; j++) {
+        const uint64_t *J = dets + 2 * j;
+        for (int Q = 0; Q < M; Q++) {
+            if (!occupied(J, n, Q)) continue;
+            for (int S = Q; S < M; S++) {          /* S == Q: a single */
+                if (!occupied(J, n, S)) continue;
+                for (int P = 0; P < M; P++) {
+                    if (occupied(J, n, P)) continue;
+                    for (int R = (S == Q ? P : P + 1); R < M; R++) {
+                        if (S == Q && R != P) break;
+                        if (S != Q && occupied(J, n, R)) continue;
+                        if (kind == 0) {
+                            int hs = (Q / n) + (S == Q ? Q / n : S / n);
+                            int ps = (P / n) + (S == Q ? P / n : R / n);
+                            if (hs != ps) continue;
+                        }
+                        uint64_t A[2] = {J[0], J[1]};
+                        flip(A, n, Q); flip(A, n, P);
+                        if (S != Q) { flip(A, n, S); flip(A, n, R); }
+                        if (in_space(ndet, dets, A[0], A[1])) continue;
+                        cx v = hij(&H, A, J, n);
+                        double haa = hij(&H, A, A, n).re;
+                        double m1 = 0.0, m2 = 0.0;
+                        for (int k = 0; k < nroots; k++) {
+                            cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+                            double a = cx_abs(cx_mul(v, cj));
+                            if (a > m1) m1 = a;
+                            double b = a / fabs(e0[k] - haa);
+                            if (b > m2) m2 = b;
+                        }
+                        if (!(m1 >= cmin && m2 >= cmin)) continue;
+                        if (ns == cap) {
+                            cap = cap ? 2 * cap : 1024;
+                            sel = (det_key *)realloc(sel, sizeof(det_key) * (size_t)cap);
+                        }
+                        sel[ns].a0 = A[0]; sel[ns].a1 = A[1]; ns++;
+                    }
+                }
+            }
+        }
+    }
+    qsort(sel, (size_t)ns, sizeof(det_key), key_cmp);
+    long u = 0;
+    for (long i = 0; i < ns; i++)
+        if (i == 0 || sel[i].a0 != sel[u - 1].a0 || sel[i].a1 != sel[u - 1].a1) sel[u++] = sel[i];
+    if (out)
+        for (long i = 0; i < u && i < max_out; i++) { out[2 * i] = sel[i].a0; out[2 * i + 1] = sel[i].a1; }
+    free(sel);
+    return u;
+}

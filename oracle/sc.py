@@ -35,6 +35,9 @@ def lib():
                                    lp, dp, dp]
         L.orc_pt2.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_long, up, C.c_int, dp, dp,
                               C.c_double, dp, lp]
+        L.orc_select.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_long, up, C.c_int, dp, dp,
+                                 C.c_double, up, C.c_long]
+        L.orc_select.restype = C.c_long
         _lib = L
     return _lib
 
@@ -183,3 +186,21 @@ def pt2(prob, c, e0, qmin=0.0):
                   _p(dets, C.c_uint64), nroots, _p(c2.view(np.float64), C.c_double), _p(e0, C.c_double),
                   float(qmin), _p(e2, C.c_double), _p(stats, C.c_long))
     return e2, int(stats[0]), int(stats[1])
+
+
+def select(prob, c, e0, cmin):
+    """Determinants outside the space selected by the iCIPT2 criterion
+    (max_k |H_AJ c_Jk| >= cmin and max_k |H_AJ c_Jk / (E0_k - H_AA)| >= cmin
+    for some J of the space); sorted [nsel][2] uint64."""
+    kind, h, g = _ham(prob)
+    c = np.asarray(c)
+    c2 = np.ascontiguousarray(c.reshape(len(c), -1), dtype=np.complex128)
+    nroots = c2.shape[1]
+    e0 = np.ascontiguousarray(np.broadcast_to(np.asarray(e0, np.float64), (nroots,)))
+    dets = np.ascontiguousarray(prob.dets, dtype=np.uint64)
+    args = (kind, prob.norb, _p(h, C.c_double), _p(g, C.c_double), float(prob.ecore), len(dets),
+            _p(dets, C.c_uint64), nroots, _p(c2.view(np.float64), C.c_double), _p(e0, C.c_double), float(cmin))
+    n = lib().orc_select(*args, C.POINTER(C.c_uint64)(), 0)
+    out = np.zeros((max(n, 1), 2), dtype=np.uint64)
+    lib().orc_select(*args, _p(out, C.c_uint64), n)
+    return out[:n]

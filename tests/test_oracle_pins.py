@@ -559,3 +559,76 @@ def test_pt2_w_minus_p_identity():
         assert abs(e2[0] - (e2w - e2p)) <= 1e-11 * abs(e2[0])
         if ee == w[0]:
             assert abs(e2p - np.sum(cc ** 2 * (ee - dP))) <= 1e-11 * abs(e2p)
+
+
+# --------------------------------------------------------------------------
+# iCIPT2 selection of external determinants (section 2.4)
+# --------------------------------------------------------------------------
+
+def _select_dense(p_full, H, pidx, c, e0, cmin):
+    """The selection criterion evaluated on a dense H over a complete space:
+    A outside P is kept when some connected J of P has max_k |H_AJ c_Jk| >=
+    cmin and max_k |H_AJ c_Jk| / |E0_k - H_AA| >= cmin."""
+    x = literal.packed(p_full)
+    outside = np.setdiff1d(np.arange(len(x)), pidx)
+    lvl = np.bitwise_count(x[outside][:, None] ^ x[pidx][None, :]).astype(np.int64)
+    conn = (lvl == 2) | (lvl == 4)
+    c2 = np.asarray(c).reshape(len(pidx), -1)
+    hc = np.abs(H[np.ix_(outside, pidx)][:, :, None] * c2[None, :, :])   # [A][J][k]
+    den = np.abs(np.asarray(e0)[None, None, :] - np.real(np.diag(H))[outside][:, None, None])
+    ok = conn & (hc.max(axis=2) >= cmin) & ((hc / den).max(axis=2) >= cmin)
+    sel = outside[ok.any(axis=1)]
+    return np.ascontiguousarray(p_full.dets[sel], dtype=np.uint64)
+
+
+def test_select_hubbard():
+    """Two-site Hubbard from |0a 0b>: the hops have |H c| = t and
+    |H c / (E0 - 0)| = t / |E0|; the double has H = 0."""
+    h = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    g = np.zeros((2, 2, 2, 2))
+    g[0, 0, 0, 0] = g[1, 1, 1, 1] = 4.0
+    p = _prob("spinfree", 2, 1, 1, np.array([[1, 1]], np.uint64), h, g)
+    assert sc.select(p, [1.0], -2.0, 0.4).tolist() == [[1, 2], [2, 1]]
+    assert sc.select(p, [1.0], -2.0, 0.6).tolist() == []
+    assert len(sc.select(p, [1.0], -2.0, 0.0)) == 3
+
+
+@pytest.mark.parametrize("kind,seed,npick", [("spinfree", 10, 40), ("spinor", 11, 12)])
+def test_select_equals_dense_literal(kind, seed, npick):
+    """Selected sets equal the criterion on the dense literal H (several
+    roots, thresholds from everything to nothing)."""
+    full, H, pidx, P, c, e0 = _pt2_case(kind, seed, npick)
+    for cmin in (0.0, 1e-3, 1e-2, 5e-2, 1e9):
+        got = sc.select(P, c, e0, cmin)
+        ref = _select_dense(full, H, pidx, c, e0, cmin)
+        assert got.tolist() == ref.tolist(), cmin
+    # everything connected at cmin = 0: the external space of the
+    # second-order energy
+    assert len(sc.select(P, c, e0, 0.0)) == sc.pt2(P, c, e0)[2]
+
+
+def test_select_iterations_reach_fci():
+    """Iterated selection from HF with diagonalisation of the selected space
+    (dense, literal H) lowers the variational energy monotonically and ends
+    at the FCI energy when the threshold admits every coupled determinant."""
+    n, na, nb = 6, 3, 3
+    full = _prob("spinfree", n, na, nb, synth.space_fci(n, na, nb), *_random_real(n, 12))
+    H = literal.hamiltonian(full)
+    efci = np.linalg.eigvalsh(H)[0]
+    x = literal.packed(full)
+    index = {int(v): i for i, v in enumerate(x)}
+    hf = np.array([[(1 << na) - 1, (1 << nb) - 1]], np.uint64)
+    dets = hf
+    last = None
+    for it in range(8):
+        pidx = np.array(sorted(index[int(d[0] | (d[1] << np.uint64(n)))] for d in dets))
+        w, V = np.linalg.eigh(H[np.ix_(pidx, pidx)])
+        if last is not None:
+            assert w[0] <= last + 1e-12
+        last = w[0]
+        P = _prob("spinfree", n, na, nb, full.dets[pidx], full.h, full.g)
+        new = sc.select(P, V[:, 0], w[0], 1e-14)
+        if len(new) == 0:
+            break
+        dets = np.concatenate([full.dets[pidx], new])
+    assert abs(last - efci) <= 1e-10 * abs(efci)
