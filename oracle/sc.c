@@ -570,46 +570,63 @@ long orc_select(int kind, int n, const double *h, const double *g, double ecore,
     const int M = 2 * n;
     det_key *sel = NULL;
     long ns = 0, cap = 0;
-    for (long j = 0; j < ndet; j++) {
-        const uint64_t *J = dets + 2 * j;
-        for (int Q = 0; Q < M; Q++) {
-            if (!occupied(J, n, Q)) continue;
-            for (int S = Q; S < M; S++) {          /* S == Q: a single */
-                if (!occupied(J, n, S)) continue;
-                for (int P = 0; P < M; P++) {
-                    if (occupied(J, n, P)) continue;
-                    for (int R = (S == Q ? P : P + 1); R < M; R++) {
-                        if (S == Q && R != P) break;
-                        if (S != Q && occupied(J, n, R)) continue;
-                        if (kind == 0) {
-                            int hs = (Q / n) + (S == Q ? Q / n : S / n);
-                            int ps = (P / n) + (S == Q ? P / n : R / n);
-                            if (hs != ps) continue;
+    /* every J independently (any thread), its selections appended in turn */
+    #pragma omp parallel
+    {
+        det_key *mine = NULL;
+        long nm = 0, cm = 0;
+        #pragma omp for schedule(dynamic, 1)
+        for (long j = 0; j < ndet; j++) {
+            const uint64_t *J = dets + 2 * j;
+            for (int Q = 0; Q < M; Q++) {
+                if (!occupied(J, n, Q)) continue;
+                for (int S = Q; S < M; S++) {          /* S == Q: a single */
+                    if (!occupied(J, n, S)) continue;
+                    for (int P = 0; P < M; P++) {
+                        if (occupied(J, n, P)) continue;
+                        for (int R = (S == Q ? P : P + 1); R < M; R++) {
+                            if (S == Q && R != P) break;
+                            if (S != Q && occupied(J, n, R)) continue;
+                            if (kind == 0) {
+                                int hs = (Q / n) + (S == Q ? Q / n : S / n);
+                                int ps = (P / n) + (S == Q ? P / n : R / n);
+                                if (hs != ps) continue;
+                            }
+                            uint64_t A[2] = {J[0], J[1]};
+                            flip(A, n, Q); flip(A, n, P);
+                            if (S != Q) { flip(A, n, S); flip(A, n, R); }
+                            if (in_space(ndet, dets, A[0], A[1])) continue;
+                            cx v = hij(&H, A, J, n);
+                            double haa = hij(&H, A, A, n).re;
+                            double m1 = 0.0, m2 = 0.0;
+                            for (int k = 0; k < nroots; k++) {
+                                cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+                                double a = cx_abs(cx_mul(v, cj));
+                                if (a > m1) m1 = a;
+                                double b = a / fabs(e0[k] - haa);
+                                if (b > m2) m2 = b;
+                            }
+                            if (!(m1 >= cmin && m2 >= cmin)) continue;
+                            if (nm == cm) {
+                                cm = cm ? 2 * cm : 1024;
+                                mine = (det_key *)realloc(mine, sizeof(det_key) * (size_t)cm);
+                            }
+                            mine[nm].a0 = A[0]; mine[nm].a1 = A[1]; nm++;
                         }
-                        uint64_t A[2] = {J[0], J[1]};
-                        flip(A, n, Q); flip(A, n, P);
-                        if (S != Q) { flip(A, n, S); flip(A, n, R); }
-                        if (in_space(ndet, dets, A[0], A[1])) continue;
-                        cx v = hij(&H, A, J, n);
-                        double haa = hij(&H, A, A, n).re;
-                        double m1 = 0.0, m2 = 0.0;
-                        for (int k = 0; k < nroots; k++) {
-                            cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
-                            double a = cx_abs(cx_mul(v, cj));
-                            if (a > m1) m1 = a;
-                            double b = a / fabs(e0[k] - haa);
-                            if (b > m2) m2 = b;
-                        }
-                        if (!(m1 >= cmin && m2 >= cmin)) continue;
-                        if (ns == cap) {
-                            cap = cap ? 2 * cap : 1024;
-                            sel = (det_key *)realloc(sel, sizeof(det_key) * (size_t)cap);
-                        }
-                        sel[ns].a0 = A[0]; sel[ns].a1 = A[1]; ns++;
                     }
                 }
             }
         }
+        #pragma omp critical
+        {
+            if (ns + nm > cap) {
+                cap = ns + nm;
+                sel = (det_key *)realloc(sel, sizeof(det_key) * (size_t)(cap > 0 ? cap : 1));
+            }
+            if (nm) memcpy(sel + ns, mine, sizeof(det_key) * (size_t)nm);
+            ns += nm;
+        }
+        free(mine);
     }
     qsort(sel, (size_t)ns, sizeof(det_key), key_cmp);
     long u = 0;
