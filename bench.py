@@ -26,7 +26,8 @@ Further legs reported in the same line (skip with --legs none):
   davidson  time per Davidson iteration on the headline space;
   pt2       Epstein-Nesbet second-order energy of the lowest root of a
             20,000-determinant n=64 10a10b space over its external space
-            (exact and screened).
+            (exact and screened), and the iCIPT2 selection of the next
+            determinants from it.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
                        [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
@@ -364,6 +365,17 @@ def leg_pt2():
                     "emit_ms": t_enum, "bucket_ms": t_bucket}
         log(f"[bench] pt2 {key}: E2 = {e2[0]:.10f}, {st['kept_pairs']} pairs, {st['external']} external dets, "
             f"{st['passes']} passes, {dt:.2f}s (emit {t_enum:.0f} ms, buckets {t_bucket:.0f} ms)")
+    # selection of the next determinants from the same state (one call,
+    # output buffer large enough)
+    cmin = 1e-5
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sel = pl.select(x, ev[0], cmin, max_out=50_000_000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    res["select"] = {"cmin": cmin, "selected_dets": int(sel.shape[0]), "seconds": dt,
+                     "excitations_per_s": st["enumerated"] / dt}
+    log(f"[bench] select: C_min = {cmin}: {sel.shape[0]} determinants in {dt:.2f}s")
     return res
 
 

@@ -211,6 +211,22 @@ mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
 mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const double *e0, double qmin, void *work,
                  size_t work_bytes, double *e2, int64_t *stats, mw_stream_t stream);
 
+/* Selection of external determinants by the iCIPT2 criterion (section 2.4):
+ * A outside the plan's space P, reached from some J of P by one or two
+ * excitations, is selected when for that J
+ *   max_k |H_AJ c[J][k]| >= cmin  and  max_k |H_AJ c[J][k] / (e0[k] - H_AA)| >= cmin
+ * (for determinants the upper bound of a double element is the element
+ * itself, so the criterion for doubles reduces to the same two tests).
+ * c: device [ndet][nroots] (complex for spinor plans), 1 <= nroots <= 8;
+ * e0: HOST [nroots].  work / work_bytes: device scratch as for mw_pt2 (the
+ * size mw_pt2_work_bytes gives is enough for one pass).  out: device
+ * [max_out][2] uint64 receiving the distinct selected determinants (grouped
+ * by hash bucket, sorted within a bucket; the same order on every call);
+ * *count (HOST) = how many were selected; when it exceeds max_out only the
+ * first max_out are written.  Host-driven, synchronises the stream. */
+mw_status mw_select(mw_plan plan, int32_t nroots, const void *c, const double *e0, double cmin, void *work,
+                    size_t work_bytes, uint64_t *out, int64_t max_out, int64_t *count, mw_stream_t stream);
+
 /* Debug: connected pairs of all rows with their phases, as int64 records
  * [I, J, P, Q, R, S, sign] (R = S = -1 for singles; P, R particles in I; Q, S
  * holes in J; ascending within each pair).  Call with out = NULL to get the

@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "dev_common.h"
@@ -633,6 +634,161 @@ size_t table_bytes(int64_t NB, int R)
            align256(16 * (size_t)NB) + 1024 + 512;
 }
 
+// ---------------------------------------------------------------------------
+// selection of external determinants (iCIPT2 criterion, section 2.4)
+// ---------------------------------------------------------------------------
+
+// A is kept from J when max_k |H_AJ c_Jk| >= cmin and max_k |H_AJ c_Jk| /
+// |E0_k - H_AA| >= cmin (for determinants the bound on a double element is
+// the element itself).  MODE 0: count kept pairs; 1: per bucket; 2: write
+// the keys of the buckets [b0, b1).
+template <bool CPLX, int MODE>
+__global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetSet inP, int R,
+                                                  const typename Scal<CPLX>::T *__restrict__ c, Roots roots,
+                                                  double cmin, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt,
+                                                  const uint64_t *__restrict__ off, uint32_t *fill, ulonglong2 *keys,
+                                                  const double *__restrict__ eps, const double *__restrict__ vg,
+                                                  unsigned long long *total, int64_t jbase)
+{
+    using T = typename Scal<CPLX>::T;
+    __shared__ uint8_t ol[2][128], vl[2][128];
+    __shared__ T s_c[PT2_MAXR];
+    __shared__ double s_eps[128];
+    __shared__ unsigned long long s_tot;
+    const int64_t J = jbase + blockIdx.x;
+    const uint64_t j0 = p.dets[2 * J], j1 = p.dets[2 * J + 1];
+    const int n = p.n;
+    if ((int)threadIdx.x < p.M) s_eps[threadIdx.x] = eps[J * p.M + threadIdx.x];
+    if (threadIdx.x == 0) {
+        int no[2] = {0, 0}, nv[2] = {0, 0};
+        for (int X = 0; X < 2 * n; X++) {
+            const int s = CPLX ? 0 : X / n;
+            if (occ(j0, j1, n, X)) ol[s][no[s]++] = (uint8_t)X;
+            else vl[s][nv[s]++] = (uint8_t)X;
+        }
+        for (int k = 0; k < R; k++) s_c[k] = c[(size_t)J * R + k];
+        s_tot = 0;
+    }
+    __syncthreads();
+    double hjj;
+    if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
+    else hjj = ((const double *)p.diag)[J];
+    const int E = ex.start[ex.nclass];
+    unsigned long long mine = 0;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        int Q, S, P, Rr;
+        decode(ex, ol, vl, e, Q, S, P, Rr);
+        uint64_t a0 = j0, a1 = j1;
+        flip(a0, a1, n, Q);
+        flip(a0, a1, n, P);
+        if (S >= 0) {
+            flip(a0, a1, n, S);
+            flip(a0, a1, n, Rr);
+        }
+        const uint64_t h = hash_det(a0, a1);
+        if (in_set(inP, h, a0, a1)) continue;
+        const T v = exc_value<CPLX>(p, j0, j1, Q, S, P, Rr);
+        const double haa = hjj + diag_delta(s_eps, vg, p.M, Q, S, P, Rr);
+        double m1 = 0.0, m2 = 0.0;
+        for (int k = 0; k < R; k++) {
+            const double a = mag(sc_mul(v, s_c[k]));
+            m1 = fmax(m1, a);
+            m2 = fmax(m2, a / fabs(roots.e0[k] - haa));
+        }
+        if (!(m1 >= cmin && m2 >= cmin)) continue;
+        if constexpr (MODE == 0) {
+            mine++;
+        } else {
+            const uint32_t b = bucket_of(h, lognb);
+            if constexpr (MODE == 1) {
+                atomicAdd(&cnt[b], 1u);
+            } else {
+                if (b < b0 || b >= b1) continue;
+                const uint32_t k = atomicAdd(&fill[b], 1u);
+                if (k < cnt[b]) keys[off[b] + k] = make_ulonglong2(a0, a1);
+            }
+        }
+    }
+    if constexpr (MODE == 0) {
+        atomicAdd(&s_tot, mine);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(total, s_tot);
+    }
+}
+
+// One workgroup per bucket: sort its keys in LDS, write the distinct ones
+// back to the front of the bucket's slice, ucnt[b] = how many.
+template <int CAP>
+__global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ off,
+                                                    ulonglong2 *keys, uint32_t *ucnt, uint32_t boff)
+{
+    __shared__ uint64_t s0[CAP], s1[CAP];
+    __shared__ uint32_t s_u;
+    const uint32_t b = list ? list[boff + blockIdx.x] : b0 + boff + blockIdx.x;
+    const int m = (int)cnt[b];
+    if (m > CAP) return;  // handled by the larger instance
+    ulonglong2 *kb = keys + off[b];
+    int np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+        if (i < m) {
+            const ulonglong2 k = kb[i];
+            s0[i] = k.x;
+            s1[i] = k.y;
+        } else {
+            s0[i] = ~0ULL;
+            s1[i] = ~0ULL;
+        }
+    }
+    if (threadIdx.x == 0) s_u = 0;
+    __syncthreads();
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t x0 = s0[i], x1 = s1[i], y0 = s0[l], y1 = s1[l];
+                    const bool gt = x0 != y0 ? x0 > y0 : x1 > y1;
+                    if (gt == up) {
+                        s0[i] = y0; s1[i] = y1;
+                        s0[l] = x0; s1[l] = x1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // one thread compacts (a bucket holds a few hundred keys)
+    if (threadIdx.x == 0) {
+        uint32_t u = 0;
+        for (int i = 0; i < m; i++)
+            if (i == 0 || s0[i] != s0[i - 1] || s1[i] != s1[i - 1]) kb[u++] = make_ulonglong2(s0[i], s1[i]);
+        ucnt[b] = u;
+    }
+}
+
+// out[uoff[b] + i] = the i-th distinct key of bucket b (b in [b0, b0 + nb))
+__global__ __launch_bounds__(256) void k_sel_copy(uint32_t b0, int64_t nb, const uint32_t *__restrict__ ucnt,
+                                                  const uint64_t *__restrict__ off, const uint64_t *__restrict__ uoff,
+                                                  const ulonglong2 *__restrict__ keys, uint64_t *out, uint64_t max_out,
+                                                  uint32_t boff)
+{
+    const int64_t bi = (int64_t)boff + blockIdx.x;
+    if (bi >= nb) return;
+    const uint32_t b = b0 + (uint32_t)bi;
+    const uint32_t u = ucnt[b];
+    for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) {
+        const uint64_t o = uoff[b] + i;
+        if (o < max_out) {
+            const ulonglong2 k = keys[off[b] + i];
+            out[2 * o] = k.x;
+            out[2 * o + 1] = k.y;
+        }
+    }
+}
+
 // A dispatch counts its work-items in 32 bits: grids are cut into chunks of
 // at most 2^22 workgroups of 256.
 constexpr int64_t PT2_MAXGRID = (int64_t)1 << 22;
@@ -816,6 +972,144 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
     return MW_OK;
 }
 
+template <bool CPLX>
+mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, double cmin, void *work,
+                   size_t work_bytes, uint64_t *out, int64_t max_out, int64_t *count, hipStream_t s)
+{
+    using T = typename Scal<CPLX>::T;
+    const T *c = (const T *)cv;
+    uint64_t first[2];
+    if (hipMemcpyAsync(first, d.dets, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(MW_EHIP, "select: reading the space failed");
+    const int na = __builtin_popcountll(first[0]) + (CPLX ? __builtin_popcountll(first[1]) : 0);
+    const int nbeta = CPLX ? 0 : __builtin_popcountll(first[1]);
+    ExcClasses ex;
+    if (!classes(d, na, nbeta, ex)) return fail(MW_EUNSUPPORTED, "select: more than 2^31 excitations per determinant");
+    Roots roots{};
+    for (int k = 0; k < R; k++) roots.e0[k] = e0[k];
+    *count = 0;
+    char *w = (char *)work;
+    size_t used = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *x = w + used;
+        used += align256(bytes);
+        return x;
+    };
+    unsigned long long *tot = (unsigned long long *)take(8 * 16);
+    double *eps = (double *)take(8 * (size_t)d.ndet * d.M);
+    double *vg = (double *)take(8 * (size_t)d.M * d.M);
+    const uint64_t zs = set_size(d.ndet);
+    uint32_t *sslot = (uint32_t *)take(4 * zs);
+    ulonglong2 *skey = (ulonglong2 *)take(16 * zs);
+    if (used > work_bytes) return fail(MW_EWORKSPACE, "select: work buffer too small");
+    const DetSet inP{skey, zs - 1};
+    if (d.ndet == 0 || ex.start[ex.nclass] == 0) return MW_OK;
+    fill_u32(sslot, (int64_t)zs, s, 0xffffffffu);
+    hipLaunchKernelGGL(k_set_insert, dim3((unsigned)((d.ndet + 255) / 256)), dim3(256), 0, s, d.dets, d.ndet, sslot,
+                       zs - 1);
+    hipLaunchKernelGGL(k_set_keys, dim3((unsigned)((zs + 255) / 256)), dim3(256), 0, s, d.dets, (const uint32_t *)sslot,
+                       zs, skey);
+    const int64_t nt = std::max<int64_t>(d.ndet * d.M, (int64_t)d.M * d.M);
+    hipLaunchKernelGGL(k_pt2_tables<CPLX>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, d, eps, vg);
+    auto enumerate = [&](auto mode, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt, const uint64_t *off,
+                         uint32_t *fill, ulonglong2 *keys) {
+        constexpr int MODE = decltype(mode)::value;
+        for (int64_t j = 0; j < d.ndet; j += PT2_MAXGRID) {
+            const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, d.ndet - j);
+            hipLaunchKernelGGL((k_sel_enum<CPLX, MODE>), dim3(g), dim3(256), 0, s, d, ex, inP, R, c, roots, cmin, lognb,
+                               b0, b1, cnt, off, fill, keys, (const double *)eps, (const double *)vg, tot, j);
+        }
+    };
+    hipMemsetAsync(tot, 0, 8, s);
+    enumerate(std::integral_constant<int, 0>(), 0, 0u, 0u, nullptr, nullptr, nullptr, nullptr);
+    unsigned long long T_ = 0;
+    if (hipMemcpyAsync(&T_, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(MW_EHIP, "select: counting pass failed");
+    if (T_ == 0) return MW_OK;
+    int lognb = 0;
+    while (((uint64_t)PT2_MEAN << lognb) < T_ && lognb < 40) lognb++;
+    const size_t fixed = used;
+    std::vector<uint32_t> hc, hu;
+    for (;;) {
+        const int64_t NB = (int64_t)1 << lognb;
+        used = fixed;
+        uint32_t *cnt = (uint32_t *)take(4 * (size_t)NB);
+        uint32_t *fill = (uint32_t *)take(4 * (size_t)NB);
+        uint32_t *ucnt = (uint32_t *)take(4 * (size_t)NB);
+        uint32_t *big = (uint32_t *)take(4 * (size_t)NB);
+        uint64_t *off = (uint64_t *)take(8 * (size_t)NB);
+        uint64_t *uoff = (uint64_t *)take(8 * (size_t)NB);
+        if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "select: work buffer too small for the bucket tables");
+        fill_u32(cnt, NB, s);
+        enumerate(std::integral_constant<int, 1>(), lognb, 0u, 0u, cnt, nullptr, nullptr, nullptr);
+        if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "select: counting launch failed");
+        hc.resize(NB);
+        if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(MW_EHIP, "select: bucket counting failed");
+        if (*std::max_element(hc.begin(), hc.end()) > (uint32_t)PT2_CAP_BIG) {
+            if (lognb >= 34) return fail(MW_EUNSUPPORTED, "select: a determinant is selected from too many partners");
+            lognb++;
+            continue;
+        }
+        const uint64_t cap = (work_bytes - used - 512) / sizeof(ulonglong2);
+        ulonglong2 *keys = (ulonglong2 *)(w + used);
+        std::vector<uint64_t> ho(NB), huo(NB);
+        hu.resize(NB);
+        uint64_t written = 0;
+        int64_t b0 = 0;
+        while (b0 < NB) {
+            uint64_t acc = 0;
+            int64_t b1 = b0;
+            while (b1 < NB && acc + hc[b1] <= cap) {
+                ho[b1] = acc;
+                acc += hc[b1];
+                b1++;
+            }
+            if (b1 == b0) return fail(MW_EWORKSPACE, "select: work buffer too small for one bucket");
+            hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
+            fill_u32(fill + b0, b1 - b0, s);
+            enumerate(std::integral_constant<int, 2>(), lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, keys);
+            std::vector<uint32_t> hb;
+            for (int64_t b = b0; b < b1; b++)
+                if (hc[b] > (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
+            for (int64_t o = 0; o < b1 - b0; o += PT2_MAXGRID)
+                hipLaunchKernelGGL(k_sel_unique<PT2_CAP>, dim3((unsigned)std::min<int64_t>(PT2_MAXGRID, b1 - b0 - o)),
+                                   dim3(256), 0, s, (uint32_t)b0, (const uint32_t *)nullptr, (const uint32_t *)cnt,
+                                   (const uint64_t *)off, keys, ucnt, (uint32_t)o);
+            if (!hb.empty()) {
+                hipMemcpyAsync(big, hb.data(), 4 * hb.size(), hipMemcpyHostToDevice, s);
+                for (int64_t o = 0; o < (int64_t)hb.size(); o += PT2_MAXGRID)
+                    hipLaunchKernelGGL(k_sel_unique<PT2_CAP_BIG>,
+                                       dim3((unsigned)std::min<int64_t>(PT2_MAXGRID, (int64_t)hb.size() - o)), dim3(256),
+                                       0, s, (uint32_t)b0, (const uint32_t *)big, (const uint32_t *)cnt,
+                                       (const uint64_t *)off, keys, ucnt, (uint32_t)o);
+            }
+            if (hipMemcpyAsync(hu.data() + b0, ucnt + b0, 4 * (size_t)(b1 - b0), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(MW_EHIP, "select: pass failed");
+            for (int64_t b = b0; b < b1; b++) {
+                huo[b] = written;
+                written += hu[b];
+            }
+            if (out && max_out > 0) {
+                hipMemcpyAsync(uoff + b0, huo.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
+                for (int64_t o = 0; o < b1 - b0; o += PT2_MAXGRID)
+                    hipLaunchKernelGGL(k_sel_copy, dim3((unsigned)std::min<int64_t>(PT2_MAXGRID, b1 - b0 - o)), dim3(256),
+                                       0, s, (uint32_t)b0, b1 - b0, (const uint32_t *)ucnt, (const uint64_t *)off,
+                                       (const uint64_t *)uoff, (const ulonglong2 *)keys, out, (uint64_t)max_out,
+                                       (uint32_t)o);
+                if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "select: copy failed");
+            }
+            if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "select: pass launch failed");
+            b0 = b1;
+        }
+        *count = (int64_t)written;
+        break;
+    }
+    return MW_OK;
+}
+
 }  // namespace
 
 }  // namespace mw
@@ -858,4 +1152,19 @@ extern "C" mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const d
     hipStream_t s = (hipStream_t)stream;
     return d->kind == MW_SPINOR ? pt2_t<true>(*d, nroots, c, e0, qmin, work, work_bytes, e2, stats, s)
                                 : pt2_t<false>(*d, nroots, c, e0, qmin, work, work_bytes, e2, stats, s);
+}
+
+extern "C" mw_status mw_select(mw_plan plan, int32_t nroots, const void *c, const double *e0, double cmin, void *work,
+                               size_t work_bytes, uint64_t *out, int64_t max_out, int64_t *count, mw_stream_t stream)
+{
+    using namespace mw;
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (nroots < 1 || nroots > PT2_MAXR) return fail(MW_EUNSUPPORTED, "select: nroots must be in 1..8");
+    if (!c || !e0 || !work || !count || (max_out > 0 && !out)) return fail(MW_EINVAL, "NULL argument");
+    if (!(cmin >= 0.0)) return fail(MW_EINVAL, "cmin must be >= 0");
+    if (d->ndet > 0x7fffffffLL) return fail(MW_EUNSUPPORTED, "select: at most 2^31 - 1 determinants");
+    hipStream_t s = (hipStream_t)stream;
+    return d->kind == MW_SPINOR ? select_t<true>(*d, nroots, c, e0, cmin, work, work_bytes, out, max_out, count, s)
+                                : select_t<false>(*d, nroots, c, e0, cmin, work, work_bytes, out, max_out, count, s);
 }

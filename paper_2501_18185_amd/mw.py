@@ -74,11 +74,12 @@ def lib():
         L.mw_pt2_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
         L.mw_pt2.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, C.POINTER(C.c_double),
                              C.POINTER(i64), vp]
+        L.mw_select.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, vp, i64, C.POINTER(i64), vp]
         for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
                      "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
                      "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched",
-                     "mw_pt2_work_bytes", "mw_pt2"):
+                     "mw_pt2_work_bytes", "mw_pt2", "mw_select"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -291,6 +292,34 @@ class Plan:
                             C.c_void_p(work.data_ptr()), int(work_bytes), e2, st, _stream()))
         stats = dict(zip(["kept_pairs", "external", "passes", "buckets", "enumerated"], list(st)))
         return np.array(list(e2)), stats
+
+
+    def select(self, c, e0, cmin, work_bytes=None, max_out=None):
+        """Determinants outside the space selected by the iCIPT2 criterion
+        for the states c [ndet] or [ndet, nroots] with energies e0.  Returns
+        a device int64 tensor [count, 2] (the two uint64 words, bit for
+        bit), grouped by hash bucket."""
+        torch = _require_gpu()
+        c = self._vec(c)
+        if c.dim() == 1:
+            c = c[:, None].contiguous()
+        nroots = c.shape[1]
+        e0 = np.broadcast_to(np.asarray(e0, dtype=np.float64), (nroots,)).copy()
+        if work_bytes is None:
+            free = torch.cuda.mem_get_info(c.device)[0]
+            work_bytes = min(self.pt2_work_bytes(nroots), int(free * 0.5))
+        work = torch.empty(max(int(work_bytes), 1), dtype=torch.uint8, device=c.device)
+        e0c = (C.c_double * nroots)(*e0)
+        cnt = C.c_int64()
+        if max_out is None:
+            _check(lib().mw_select(self._plan, nroots, C.c_void_p(c.data_ptr()), e0c, float(cmin),
+                                   C.c_void_p(work.data_ptr()), int(work_bytes), None, 0, C.byref(cnt), _stream()))
+            max_out = cnt.value
+        out = torch.empty((max(int(max_out), 1), 2), dtype=torch.int64, device=c.device)
+        _check(lib().mw_select(self._plan, nroots, C.c_void_p(c.data_ptr()), e0c, float(cmin),
+                               C.c_void_p(work.data_ptr()), int(work_bytes), C.c_void_p(out.data_ptr()), int(max_out),
+                               C.byref(cnt), _stream()))
+        return out[:min(cnt.value, int(max_out))]
 
 
 def profile(enable: bool):
