@@ -237,6 +237,18 @@ def main():
                       f"({int(sample_terms)} terms, {dt:.1f} s)",
         }
         log(f"[bench] cpu oracle: {len(rows)} rows in {dt:.1f}s on {sc.num_threads()} threads")
+        # the same oracle on one thread, on a tenth of the sample
+        threads = sc.num_threads()
+        sc.set_threads(1)
+        rows1 = rows[:max(1, len(rows) // 10)]
+        t0 = time.perf_counter()
+        sc.sigma(prob, c_np, rows=rows1)  # noqa: the oracle, timed as the CPU baseline
+        dt1 = time.perf_counter() - t0
+        sc.set_threads(threads)
+        terms1 = float((sc.degree_rows(prob, rows1) + 1).sum() * R)
+        out["cpu_baseline"]["value_1_thread"] = terms1 / dt1
+        out["cpu_baseline"]["sample_1_thread"] = f"{len(rows1)} of the same rows ({int(terms1)} terms, {dt1:.1f} s)"
+        log(f"[bench] cpu oracle, 1 thread: {len(rows1)} rows in {dt1:.1f}s")
     print(json.dumps(out), flush=True)
 
 

@@ -127,14 +127,17 @@ int64_t mw_plan_info(mw_plan plan, int32_t what);
 mw_status mw_sigma(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream);
 
 /* The same product for nprob (1..32) independent plans of one kind in one
- * launch sequence: one persistent launch whose waves pull work units from a
- * device counter across all problems (the dynamic task scheduling of the
- * paper's parallel templates, section 3.1.2), then one gather launch.
+ * launch sequence: per root-chunk width one launch over the work units of
+ * all problems (a persistent grid whose waves pull them from per-XCD device
+ * counters, the dynamic task scheduling of the paper's parallel templates,
+ * section 3.1.2, or a flat grid, as tuned), then one gather launch.
  * plans, nroots, c, sigma are HOST arrays of length nprob (c[i], sigma[i]
  * device pointers; each plan at most once).  The launch sequence is captured
  * once into a HIP graph keyed by the argument tuple and replayed on later
  * calls with the same tuple; destroying or re-binding a plan drops its
- * graphs.  Results equal nprob separate mw_sigma calls bit for bit. */
+ * graphs.  With the default launch parameters results equal nprob separate
+ * mw_sigma calls with default parameters bit for bit; a tuned gather width
+ * sums each determinant's partials in another fixed order. */
 mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                            const void *const *c, void *const *sigma, mw_stream_t stream);
 
@@ -154,10 +157,10 @@ mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, void *sigma, 
                       int32_t *choice);
 
 /* Autotuner for mw_sigma_batched: times the flat grid and persistent grids
- * of 1, 2, 4, 8, 16 blocks per compute unit, each with a partner unroll of
- * 4 or 8 for four-root passes, for this argument tuple, and uses the
- * fastest for its graph from then on; *blocks_per_cu (host, nullable)
- * receives the grid (0 = flat). */
+ * of 1, 2, 4, 8, 16 blocks per compute unit, a partner unroll of 4 or 8 for
+ * four-root passes and a gather width of 8, 16 or 32 lanes per determinant,
+ * for this argument tuple, and uses the fastest for its graph from then on;
+ * *blocks_per_cu (host, nullable) receives the grid (0 = flat). */
 mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                               const void *const *c, void *const *sigma, mw_stream_t stream,
                               int32_t *blocks_per_cu);

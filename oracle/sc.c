@@ -174,6 +174,16 @@ static cx hij(const ham_t *H, const uint64_t *I, const uint64_t *J, int n)
 
 /* ------------------------------------------------------------------------ */
 
+/* set the threads the OpenMP loops of this library use (n <= 0: leave) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* threads an OpenMP loop of this library uses */
 int orc_num_threads(void)
 {

@@ -31,6 +31,7 @@ def lib():
         L.orc_connect_rows.argtypes = [C.c_int, C.c_long, up, C.c_long, lp, lp]
         L.orc_connect_rows.restype = C.c_long
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_rdm_rows.argtypes = [C.c_int, C.c_int, C.c_long, up, C.c_int, dp, dp, dp, C.c_long,
                                    lp, dp, dp]
         L.orc_pt2.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_long, up, C.c_int, dp, dp,
@@ -45,6 +46,11 @@ def lib():
 def num_threads():
     """OpenMP threads the row loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_threads(n):
+    """Threads for the row loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def _p(a, t):

@@ -17,6 +17,14 @@ using namespace mw;
 extern "C" const mw::DevPlan *mw_internal_devplan(mw_plan plan);
 extern "C" void mw_internal_set_tune(mw_plan plan, int32_t u, int32_t gl);
 
+void mw::batch_set_gather(BatchSet &b, int gl)
+{
+    BatchArgs &a = b.all;
+    b.gl = gl;
+    a.blk_start[0] = 0;
+    for (int k = 0; k < a.nprob; k++) a.blk_start[k + 1] = a.blk_start[k] + (a.ndet[k] * a.R[k] * gl + 255) / 256;
+}
+
 namespace {
 
 struct BatchKey {
@@ -29,11 +37,15 @@ struct BatchEntry {
     hipGraphExec_t exec = nullptr;
     int bpc = 0;  // persistent blocks per compute unit used when captured
     int u4 = 0;   // four-root partner unroll used when captured
+    int gl = 0;   // gather lanes used when captured
 };
 
 std::mutex g_mu;
 std::map<BatchKey, BatchEntry> g_cache;
-std::map<BatchKey, std::pair<int, int>> g_tuned;  // autotuned (blocks per CU, four-root unroll), by batch
+struct Tuned {
+    int bpc, u4, gl;
+};
+std::map<BatchKey, Tuned> g_tuned;  // autotuned launch parameters, by batch
 hipStream_t g_capture_stream = nullptr;
 int g_num_cu = 0;
 
@@ -74,6 +86,8 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
     a = BatchArgs{};
     a.nprob = nprob;
     a.pk_start[0] = 0;
+    a.pkd_start[0] = 0;
+    a.pks_start[0] = 0;
     a.blk_start[0] = 0;
     for (int k = 0; k < nprob; k++) {
         int i = ord[k];
@@ -81,11 +95,17 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
         a.c[k] = c[i];
         a.sigma[k] = sigma[i];
         a.R[k] = nroots[i];
+        a.ndet[k] = d[i]->ndet;
         a.pk_start[k + 1] = a.pk_start[k] + d[i]->npacket;
-        a.blk_start[k + 1] = a.blk_start[k] + (d[i]->ndet * nroots[i] * 16 + 255) / 256;
+        a.pkd_start[k + 1] = a.pkd_start[k] + d[i]->npacket_double;
+        a.pks_start[k + 1] = a.pks_start[k] + (d[i]->npacket - d[i]->npacket_double);
     }
-    // one dispatch counts its work-items in 32 bits
-    if (a.pk_start[nprob] * 64 >= 0xffffffffLL - (1 << 20) || a.blk_start[nprob] * 256 >= 0xffffffffLL)
+    batch_set_gather(b, 16);
+    // one dispatch counts its work-items in 32 bits (gather laid out for the
+    // widest width the tuner tries)
+    int64_t blk32 = 0;
+    for (int k = 0; k < nprob; k++) blk32 += (a.ndet[k] * a.R[k] * 32 + 255) / 256;
+    if (a.pk_start[nprob] * 64 >= 0xffffffffLL - (1 << 20) || blk32 * 256 >= 0xffffffffLL)
         return fail(MW_EUNSUPPORTED, "too many packets in one batch");
     a.counter = d[ord[0]]->counter;
     // per root-chunk width: problems with a chunk of 4, 2 or 1 roots
@@ -93,6 +113,8 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
         BatchArgs &e = b.cls[cl];
         e = BatchArgs{};
         e.pk_start[0] = 0;
+        e.pkd_start[0] = 0;
+        e.pks_start[0] = 0;
         e.counter = a.counter + 8 * cl;
         for (int k = 0; k < nprob; k++) {
             const int R = a.R[k];
@@ -108,6 +130,8 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
             e.sigma[j] = a.sigma[k];
             e.R[j] = R;
             e.pk_start[j + 1] = e.pk_start[j] + (a.pk_start[k + 1] - a.pk_start[k]);
+            e.pkd_start[j + 1] = e.pkd_start[j] + (a.pkd_start[k + 1] - a.pkd_start[k]);
+            e.pks_start[j + 1] = e.pks_start[j] + (a.pks_start[k + 1] - a.pks_start[k]);
         }
     }
     key.v.clear();
@@ -140,6 +164,7 @@ mw_status capture(const BatchSet &a, bool cplx, int bpc, BatchEntry &e)
     e.exec = ex;
     e.bpc = bpc;
     e.u4 = a.u4;
+    e.gl = a.gl;
     return MW_OK;
 }
 
@@ -186,11 +211,12 @@ extern "C" mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const
     int bpc = 8;
     auto tb = g_tuned.find(key);
     if (tb != g_tuned.end()) {
-        bpc = tb->second.first;
-        a.u4 = tb->second.second;
+        bpc = tb->second.bpc;
+        a.u4 = tb->second.u4;
+        batch_set_gather(a, tb->second.gl);
     }
     auto it = g_cache.find(key);
-    if (it != g_cache.end() && (it->second.bpc != bpc || it->second.u4 != a.u4)) {
+    if (it != g_cache.end() && (it->second.bpc != bpc || it->second.u4 != a.u4 || it->second.gl != a.gl)) {
         drop(it->second);
         g_cache.erase(it);
         it = g_cache.end();
@@ -271,9 +297,10 @@ extern "C" mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, vo
     return MW_OK;
 }
 
-// Autotuner for batched sigma: tries the persistent grid (blocks per CU) and
-// the partner unroll of the four-root launch, keeps the fastest for this
-// batch; the captured graph is rebuilt with it.
+// Autotuner for batched sigma: tries the persistent grid (blocks per CU) or
+// the flat grid, the partner unroll of the four-root launch and the gather
+// width, keeps the fastest for this batch; the captured graph is rebuilt
+// with it.
 extern "C" mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
                                          const void *const *c, void *const *sigma, mw_stream_t stream,
                                          int32_t *blocks_per_cu)
@@ -285,19 +312,22 @@ extern "C" mw_status mw_autotune_batched(int32_t nprob, const mw_plan *plans, co
     if (st != MW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     double best = 1e30;
-    int bb = 8, bu = 4;
+    int bb = 8, bu = 4, bg = 16;
     mw_status err = MW_OK;
-    for (int u4 : {4, 8}) {
-        a.u4 = u4;
-        // bpc 0: the flat (hardware-dispatched) grid instead of the work queue
-        for (int bpc : {0, 1, 2, 4, 8, 16}) {
-            double t = time_ms(s, 3, [&]() { return launch_batched(a, cplx, num_cu() * bpc, s, false); }, &err);
-            if (err != MW_OK) return err;
-            if (t < best) { best = t; bb = bpc; bu = u4; }
+    for (int gl : {8, 16, 32}) {
+        batch_set_gather(a, gl);
+        for (int u4 : {4, 8}) {
+            a.u4 = u4;
+            // bpc 0: the flat (hardware-dispatched) grid instead of the work queue
+            for (int bpc : {0, 1, 2, 4, 8, 16}) {
+                double t = time_ms(s, 3, [&]() { return launch_batched(a, cplx, num_cu() * bpc, s, false); }, &err);
+                if (err != MW_OK) return err;
+                if (t < best) { best = t; bb = bpc; bu = u4; bg = gl; }
+            }
         }
     }
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[key] = {bb, bu};
+    g_tuned[key] = Tuned{bb, bu, bg};
     if (blocks_per_cu) *blocks_per_cu = bb;
     return MW_OK;
 }

@@ -258,22 +258,11 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
         // a packet of a large group is one 64-member block of it (uniform)
         const uint32_t g0 = p.mem_grp[mfirst];
         const uint32_t k = p.grp_off[g0 + 1] - p.grp_off[g0];
+        // every root-chunk width (1, 2 or 4 roots per pass) takes the
+        // Hermitian half-work on large groups
         if (k >= 64) {
-            if (RC <= 2) {
-                group_double_half<CPLX, RC>(p, mfirst, mend, lane, R, r0, c, partial);
-                return;
-            }
-            // With four roots per pass the integral load is already shared
-            // by the roots and the column reductions would dominate, so the
-            // block does the full row sums; the column slots it owns (which
-            // the gather still reads) carry nothing for these roots.
-            const uint32_t a = (mfirst - p.grp_off[g0]) >> 6;
-            if (k > 64 * (a + 1)) {
-                const size_t colbase = (size_t)p.nmem + p.grp_col[g0] + (size_t)a * k - 32 * (size_t)a * (a + 1);
-                const int nr = min(RC, R - r0);
-                for (uint32_t t = lane; t < k - 64 * (a + 1); t += 64)
-                    for (int kk = 0; kk < nr; kk++) partial[(colbase + t) * R + r0 + kk] = sc_zero(T());
-            }
+            group_double_half<CPLX, RC>(p, mfirst, mend, lane, R, r0, c, partial);
+            return;
         }
     }
     const uint32_t m = mfirst + lane;
@@ -570,36 +559,38 @@ __global__ __launch_bounds__(256) void k_batched_groups(BatchArgs a)
 
 // Flat variant: one wave per packet over the packets of every problem
 // (hardware-dispatched, with the same XCD-aware block order as the plain
-// launches); the tuner picks it or the work queue above.
-template <bool CPLX, int RC, int U>
-__global__ __launch_bounds__(256) void k_batched_flat(BatchArgs a)
+// launches), the double-group and the single-group packets in launches of
+// their own (each with its own register budget, as the plain launches);
+// the tuner picks it or the work queue above.
+template <bool CPLX, int RC, int U, bool SGL, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_batched_flat(BatchArgs a)
 {
     using T = typename Scal<CPLX>::T;
+    const int64_t *pre = SGL ? a.pks_start : a.pkd_start;
     const int64_t u = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(xcd_block(blockIdx.x) * 4 + (threadIdx.x >> 6)));
-    if (u >= a.pk_start[a.nprob]) return;
+    if (u >= pre[a.nprob]) return;
     const int lane = threadIdx.x & 63;
     int q = 0;
-    while (u >= a.pk_start[q + 1]) q++;
+    while (u >= pre[q + 1]) q++;
     const DevPlan &p = *a.plans[q];
-    const int64_t w = u - a.pk_start[q];
+    const int64_t w = (SGL ? p.npacket_double : 0) + (u - pre[q]);
     const int R = a.R[q];
     const T *c = (const T *)a.c[q];
     T *part = (T *)p.partial;
     for (int r0 = 0; r0 < R; r0 += 4) {
         const int left = R - r0;
         if ((left == 1 ? 1 : (left == 2 ? 2 : 4)) != RC) continue;
-        if (w < p.npacket_double) group_double_body<CPLX, RC, U>(p, w, lane, R, r0, c, part);
-        else group_single_body<CPLX, RC>(p, w, lane, R, r0, c, part);
+        if constexpr (SGL) group_single_body<CPLX, RC>(p, w, lane, R, r0, c, part);
+        else group_double_body<CPLX, RC, U>(p, w, lane, R, r0, c, part);
     }
 }
 
 // Gather for all problems: block b belongs to the problem whose block range
 // holds b (block-uniform, so the plan fields are scalar loads).
-template <bool CPLX>
+template <bool CPLX, int GL>
 __global__ __launch_bounds__(256) void k_batched_gather(BatchArgs a)
 {
     using T = typename Scal<CPLX>::T;
-    constexpr int GL = 16;
     const int64_t b = blockIdx.x;
     int q = 0;
     while (b >= a.blk_start[q + 1]) q++;
@@ -613,22 +604,28 @@ __global__ void k_reset_counter(uint32_t *ctr)
     if (threadIdx.x < 8 * 3) ctr[threadIdx.x] = 0u;
 }
 
+// WAVES: minimum waves per SIMD the register allocation must allow (the
+// plain launches of the same bodies reach it; the batched bookkeeping
+// would otherwise cost a wave)
+template <bool CPLX, int RC, int U, int WAVES>
+static void launch_flat_class(const BatchArgs &a, hipStream_t s)
+{
+    const int64_t nd = a.pkd_start[a.nprob], ns = a.pks_start[a.nprob];
+    if (nd > 0)
+        hipLaunchKernelGGL((k_batched_flat<CPLX, RC, U, false, WAVES>), dim3(xcd_grid((nd + 3) / 4)), dim3(256), 0, s, a);
+    if (ns > 0)
+        hipLaunchKernelGGL((k_batched_flat<CPLX, RC, U, true, 1>), dim3(xcd_grid((ns + 3) / 4)), dim3(256), 0, s, a);
+}
+
 template <bool CPLX>
 static void launch_batched_flat(const BatchSet &b, hipStream_t s)
 {
-    for (int cl = 0; cl < 3; cl++) {
-        const BatchArgs &a = b.cls[cl];
-        if (!a.nprob) continue;
-        const unsigned grid = xcd_grid((a.pk_start[a.nprob] + 3) / 4);
-        if (cl == 0) {
-            if (b.u4 == 8) hipLaunchKernelGGL((k_batched_flat<CPLX, 4, 8>), dim3(grid), dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_batched_flat<CPLX, 4, 4>), dim3(grid), dim3(256), 0, s, a);
-        } else if (cl == 1) {
-            hipLaunchKernelGGL((k_batched_flat<CPLX, 2, 8>), dim3(grid), dim3(256), 0, s, a);
-        } else {
-            hipLaunchKernelGGL((k_batched_flat<CPLX, 1, 8>), dim3(grid), dim3(256), 0, s, a);
-        }
+    if (b.cls[0].nprob) {
+        if (b.u4 == 8) launch_flat_class<CPLX, 4, 8, CPLX ? 2 : 3>(b.cls[0], s);
+        else launch_flat_class<CPLX, 4, 4, CPLX ? 3 : 5>(b.cls[0], s);
     }
+    if (b.cls[1].nprob) launch_flat_class<CPLX, 2, 8, CPLX ? 3 : 5>(b.cls[1], s);
+    if (b.cls[2].nprob) launch_flat_class<CPLX, 1, 8, CPLX ? 3 : 5>(b.cls[2], s);
 }
 
 template <bool CPLX>
@@ -657,9 +654,18 @@ mw_status launch_batched(const BatchSet &b, bool cplx, int blocks, hipStream_t s
     else launch_batched_groups<false>(b, blocks, s);
     prof_end(t, s);
     if (timing) t = prof_begin("batched_gather", s);
+    // gather lanes per determinant: the width blk_start was laid out for
     const unsigned gg = (unsigned)a.blk_start[a.nprob];
-    if (cplx) hipLaunchKernelGGL(k_batched_gather<true>, dim3(gg), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_batched_gather<false>, dim3(gg), dim3(256), 0, s, a);
+    if (b.gl == 8) {
+        if (cplx) hipLaunchKernelGGL((k_batched_gather<true, 8>), dim3(gg), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_batched_gather<false, 8>), dim3(gg), dim3(256), 0, s, a);
+    } else if (b.gl == 32) {
+        if (cplx) hipLaunchKernelGGL((k_batched_gather<true, 32>), dim3(gg), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_batched_gather<false, 32>), dim3(gg), dim3(256), 0, s, a);
+    } else {
+        if (cplx) hipLaunchKernelGGL((k_batched_gather<true, 16>), dim3(gg), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_batched_gather<false, 16>), dim3(gg), dim3(256), 0, s, a);
+    }
     prof_end(t, s);
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "batched launch failed");
     return MW_OK;

@@ -84,6 +84,9 @@ struct BatchArgs {
     int R[MW_MAXB];
     int64_t pk_start[MW_MAXB + 1];   // packet prefix over problems
     int64_t blk_start[MW_MAXB + 1];  // gather-block prefix over problems (256 threads each)
+    int64_t ndet[MW_MAXB];           // determinants per problem (host side, for the gather layout)
+    int64_t pkd_start[MW_MAXB + 1];  // prefix of the double-group packets over problems
+    int64_t pks_start[MW_MAXB + 1];  // prefix of the single-group packets over problems
     uint32_t *counter;
 };
 // all problems (gather) and, per root-chunk width 4 / 2 / 1, the problems
@@ -92,7 +95,10 @@ struct BatchSet {
     BatchArgs all;
     BatchArgs cls[3];
     int u4 = 4;  // partner unroll of the four-root launch (4 or 8)
+    int gl = 16; // gather lanes per determinant (8, 16 or 32); blk_start is laid out for it
 };
+// lay blk_start out for gl gather lanes per determinant
+void batch_set_gather(BatchSet &b, int gl);
 mw_status launch_batched(const BatchSet &b, bool cplx, int blocks, hipStream_t s, bool timing);
 
 // host side helpers (plan.cpp)
