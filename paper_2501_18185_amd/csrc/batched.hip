@@ -105,7 +105,7 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
     // widest width the tuner tries)
     int64_t blk32 = 0;
     for (int k = 0; k < nprob; k++) blk32 += (a.ndet[k] * a.R[k] * 32 + 255) / 256;
-    if (a.pk_start[nprob] * 64 >= 0xffffffffLL - (1 << 20) || blk32 * 256 >= 0xffffffffLL)
+    if (a.pk_start[nprob] * 64 >= 0xffffffffLL - (1 << 20) || (blk32 + 8) * 256 >= 0xffffffffLL)
         return fail(MW_EUNSUPPORTED, "too many packets in one batch");
     a.counter = d[ord[0]]->counter;
     // per root-chunk width: problems with a chunk of 4, 2 or 1 roots

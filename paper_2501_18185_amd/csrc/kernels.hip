@@ -332,6 +332,14 @@ static inline unsigned xcd_grid(int64_t blocks)
     return (unsigned)((blocks + q - 1) / q * q);
 }
 
+// Gather launches: each XCD takes one contiguous eighth of the logical
+// blocks (grid a multiple of 8), so determinants that are neighbours in the
+// given order, whose partial sums the plan places close together, share an L2.
+__device__ __forceinline__ int64_t xcd_range_block(int64_t b, int64_t grid)
+{
+    return (b & 7) * (grid >> 3) + (b >> 3);
+}
+
 // Real one-root launches fit six waves per SIMD in 80 registers without
 // spilling (measured faster than the five the compiler picks by itself).
 template <bool CPLX, int RC, int U>
@@ -432,7 +440,8 @@ __global__ __launch_bounds__(256) void k_gather(DevPlan p, int R, const typename
                                                 const typename Scal<CPLX>::T *__restrict__ partial,
                                                 typename Scal<CPLX>::T *__restrict__ sigma, int64_t base)
 {
-    gather_body<CPLX, GL>(p, base + (int64_t)blockIdx.x * blockDim.x + threadIdx.x, R, c, partial, sigma);
+    gather_body<CPLX, GL>(p, base + xcd_range_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x, R, c, partial,
+                          sigma);
 }
 
 template <bool CPLX, int RC, int U>
@@ -468,12 +477,14 @@ template <bool CPLX, int GL>
 static void launch_gather(const DevPlan &p, int R, const typename Scal<CPLX>::T *c,
                           const typename Scal<CPLX>::T *part, typename Scal<CPLX>::T *sigma, hipStream_t s)
 {
-    // a dispatch counts its work-items in 32 bits: at most 2^22 blocks each
+    // a dispatch counts its work-items in 32 bits: at most 2^22 blocks each.
+    // Only the last chunk is partial; its grid is rounded up to a multiple of
+    // 8 and the extra blocks lie past the end (inactive).
     const int64_t tot = p.ndet * R * GL, chunk = (int64_t)256 << 22;
     for (int64_t b = 0; b < tot; b += chunk) {
         const int64_t n = std::min<int64_t>(chunk, tot - b);
-        hipLaunchKernelGGL((k_gather<CPLX, GL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, R, c, part,
-                           sigma, b);
+        hipLaunchKernelGGL((k_gather<CPLX, GL>), dim3((unsigned)((n + 2047) / 2048 * 8)), dim3(256), 0, s, p, R, c,
+                           part, sigma, b);
     }
 }
 
@@ -593,7 +604,8 @@ template <bool CPLX, int GL>
 __global__ __launch_bounds__(256) void k_batched_gather(BatchArgs a)
 {
     using T = typename Scal<CPLX>::T;
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_range_block(blockIdx.x, gridDim.x);
+    if (b >= a.blk_start[a.nprob]) return;
     int q = 0;
     while (b >= a.blk_start[q + 1]) q++;
     const DevPlan &p = *a.plans[q];
@@ -657,7 +669,7 @@ mw_status launch_batched(const BatchSet &b, bool cplx, int blocks, hipStream_t s
     prof_end(t, s);
     if (timing) t = prof_begin("batched_gather", s);
     // gather lanes per determinant: the width blk_start was laid out for
-    const unsigned gg = (unsigned)a.blk_start[a.nprob];
+    const unsigned gg = (unsigned)((a.blk_start[a.nprob] + 7) / 8 * 8);
     if (b.gl == 8) {
         if (cplx) hipLaunchKernelGGL((k_batched_gather<true, 8>), dim3(gg), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_batched_gather<false, 8>), dim3(gg), dim3(256), 0, s, a);

@@ -82,6 +82,31 @@ static void parallel_items(int64_t n, const std::function<void(int64_t)> &f)
     for (auto &x : th) x.join();
 }
 
+// Sort under a strict total order: contiguous chunks in parallel, then
+// pairwise merges of neighbouring chunks.
+template <class T, class Less>
+static void parallel_sort(std::vector<T> &v, Less less)
+{
+    const int64_t n = (int64_t)v.size();
+    const int64_t T_ = std::min<int64_t>(n_threads(), std::max<int64_t>(1, n >> 16));
+    if (T_ <= 1) {
+        std::sort(v.begin(), v.end(), less);
+        return;
+    }
+    std::vector<int64_t> cut(T_ + 1);
+    for (int64_t t = 0; t <= T_; t++) cut[t] = n * t / T_;
+    parallel_items(T_, [&](int64_t t) { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1], less); });
+    for (int64_t w = 1; w < T_; w *= 2) {
+        std::vector<int64_t> jobs;
+        for (int64_t t = 0; t + w < T_; t += 2 * w) jobs.push_back(t);
+        parallel_items((int64_t)jobs.size(), [&](int64_t k) {
+            const int64_t t = jobs[k];
+            std::inplace_merge(v.begin() + cut[t], v.begin() + cut[t + w], v.begin() + cut[std::min(t + 2 * w, T_)],
+                               less);
+        });
+    }
+}
+
 static inline uint64_t mix64(uint64_t x)
 {
     x ^= x >> 30; x *= 0xbf58476d1ce4e5b9ULL;
@@ -335,8 +360,10 @@ static mw_status build_groups(HostPlan &P)
     for (auto &x : th) x.join();
     th.clear();
 
-    // sort each partition; collect runs of length >= 2
-    struct Run { int64_t start; uint32_t len; };
+    // sort each partition; collect runs of length >= 2 with their ordering
+    // keys: single or double, kind (which spins lost the electrons), first
+    // member (the smallest determinant index)
+    struct Run { int64_t start; uint32_t len, det; uint8_t single, kind; };
     std::vector<std::vector<Run>> runs(NPART);
     parallel_items(NPART, [&](int64_t p) {
         auto b = ent.begin() + part_start[p], e = ent.begin() + part_start[p + 1];
@@ -345,7 +372,12 @@ static mw_status build_groups(HostPlan &P)
         while (s < E) {
             int64_t t = s + 1;
             while (t < E && ent[t].k0 == ent[s].k0 && ent[t].k1 == ent[s].k1) t++;
-            if (t - s >= 2) runs[p].push_back(Run{s, (uint32_t)(t - s)});
+            if (t - s >= 2) {
+                const int X = ent[s].pos & 255, Y = ent[s].pos >> 8;
+                const uint8_t single = Y == 255;
+                const uint8_t kind = single ? (X < n ? 0 : 1) : ((X < n && Y < n) ? 0 : (X >= n && Y >= n) ? 1 : 2);
+                runs[p].push_back(Run{s, (uint32_t)(t - s), ent[s].det, single, kind});
+            }
             s = t;
         }
     });
@@ -354,13 +386,18 @@ static mw_status build_groups(HostPlan &P)
     runs.clear();
     runs.shrink_to_fit();
     // double groups before single groups, largest first within each class
-    // (longest-processing-time order); ties keep the deterministic
-    // partition/key order
-    auto is_single = [&](const Run &r) { return (ent[r.start].pos >> 8) == 255; };
-    std::stable_sort(all.begin(), all.end(), [&](const Run &a, const Run &b) {
-        bool sa = is_single(a), sb = is_single(b);
-        if (sa != sb) return !sa;
-        return a.len > b.len;
+    // (longest-processing-time order).  Groups of one size are ordered by
+    // kind and then by their first member, so that determinants close in the
+    // given order find their partial sums close together when the gather
+    // reads them (and a packet's members read neighbouring coefficients);
+    // remaining ties by position in the partition/key order, so the order is
+    // total and deterministic.
+    parallel_sort(all, [](const Run &a, const Run &b) {
+        if (a.single != b.single) return a.single < b.single;
+        if (a.len != b.len) return a.len > b.len;
+        if (a.kind != b.kind) return a.kind < b.kind;
+        if (a.det != b.det) return a.det < b.det;
+        return a.start < b.start;
     });
 
     const int64_t ngroup = (int64_t)all.size();

@@ -724,7 +724,6 @@ __global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t 
                                                     ulonglong2 *keys, uint32_t *ucnt, uint32_t boff)
 {
     __shared__ uint64_t s0[CAP], s1[CAP];
-    __shared__ uint32_t s_u;
     const uint32_t b = list ? list[boff + blockIdx.x] : b0 + boff + blockIdx.x;
     const int m = (int)cnt[b];
     if (m > CAP) return;  // handled by the larger instance
@@ -741,7 +740,6 @@ __global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t 
             s1[i] = ~0ULL;
         }
     }
-    if (threadIdx.x == 0) s_u = 0;
     __syncthreads();
     for (int k = 2; k <= np2; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
