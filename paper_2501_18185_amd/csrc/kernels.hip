@@ -421,7 +421,16 @@ __device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
         I = t / R;
         k = (int)(t - I * R);
         const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
-        for (uint32_t s = s0 + sub; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
+        // four slots in flight per lane; the additions keep the slot order
+        uint32_t s = s0 + sub;
+        for (; s < s1 && s1 - s > 3u * GL; s += 4 * GL) {
+            const uint32_t i0 = p.slot_mem[s], i1 = p.slot_mem[s + GL], i2 = p.slot_mem[s + 2 * GL],
+                           i3 = p.slot_mem[s + 3 * GL];
+            const T v0 = partial[(size_t)i0 * R + k], v1 = partial[(size_t)i1 * R + k],
+                    v2 = partial[(size_t)i2 * R + k], v3 = partial[(size_t)i3 * R + k];
+            acc = sc_add(sc_add(sc_add(sc_add(acc, v0), v1), v2), v3);
+        }
+        for (; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
     }
 #pragma unroll
     for (int off = GL / 2; off > 0; off >>= 1) {
