@@ -76,7 +76,11 @@ __device__ __forceinline__ size_t g4(int m, int a, int b, int c, int d)
 // accumulators DT0 (colex columns) and DT1 (lex columns) hold the
 // transposed antisymmetric pair matrix, D[(P,R)][(Q,S)] = DT0[QS][PR] +
 // DT1[QS][lex PR].
-template <bool CPLX, int U>
+// SYM (bra and ket are one vector): the reversed pair (J, I) adds the
+// complex conjugate of w_IJ to the mirrored entry, so each unordered pair is
+// visited once (partners j after i in the group) and the final pass adds
+// the mirror image.
+template <bool CPLX, int U, bool SYM>
 __global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
                                                     double *__restrict__ dab, typename Scal<CPLX>::T *__restrict__ dt0,
@@ -103,12 +107,14 @@ __global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const type
     if (ab) col = lay ? (size_t)(Yi - n) * n + Xi : (size_t)Xi * n + (Yi - n);
     else col = lay ? (size_t)rdm_pair_lex(Xi - off, Yi - off, mpos) : (size_t)pair_idx(Xi - off, Yi - off);
     T *dst_pair = lay ? dt1 : dt0;
-    for (uint32_t j = j0; j < j1; j += U) {
+    // SYM: a large group's blocks before this packet hold no later partner
+    const uint32_t js = SYM ? max(j0, p.pk_off[wave]) : j0;
+    for (uint32_t j = js; j < j1; j += U) {
         uint2 o[U];
         bool hit[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const bool in = j + u < j1;
+            const bool in = j + u < j1 && (!SYM || j + u > m);
             o[u] = p.mem[in ? j + u : j0];
             const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
             hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
@@ -131,7 +137,7 @@ __global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const type
     }
 }
 
-template <bool CPLX>
+template <bool CPLX, bool SYM>
 __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
                                                     typename Scal<CPLX>::T *__restrict__ S,
@@ -152,7 +158,8 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
     const uint32_t negi = (me.y >> 16) & 1;
     const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
     const int n = p.n;
-    for (uint32_t j = j0; j < j1; j++) {
+    // SYM: partners after i only; k_rdm_mirror adds the reversed pairs
+    for (uint32_t j = SYM ? max(j0, m + 1) : j0; j < j1; j++) {
         const uint2 o = p.mem[j];
         const int Xj = o.y & 255;
         if (Xj == Xi) continue;
@@ -276,21 +283,43 @@ __device__ __forceinline__ T d_term(const T *dt0, const T *dt1, int np, int m, i
     return sc_neg(d_pair(dt0, dt1, np, m, c, a, b, d), true);
 }
 
+// SYM pass for the single-excitation accumulators: X[P][Q][x] and
+// X[Q][P][x] (P < Q; x over `inner` entries) both become their sum with the
+// other's conjugate.  `outer` blocks of the matrix (spin-free: the two spin
+// blocks of S) are independent.
+template <class T>
+__global__ __launch_bounds__(256) void k_rdm_mirror(T *X, int m, int inner, int outer)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)m * m * inner;
+    if (t >= per * outer) return;
+    const int64_t o = t / per, r = t % per;
+    const int x = (int)(r % inner);
+    const int P = (int)(r / inner / m), Q = (int)(r / inner % m);
+    if (P >= Q) return;
+    T *a = X + o * per + ((int64_t)P * m + Q) * inner + x;
+    T *b = X + o * per + ((int64_t)Q * m + P) * inner + x;
+    const T va = *a, vb = *b;
+    *a = sc_add(va, sc_conj(vb));
+    *b = sc_add(vb, sc_conj(va));
+}
+
 __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double *__restrict__ dab,
                                                          const double *__restrict__ dt0,
                                                          const double *__restrict__ dt1, const double *__restrict__ S,
                                                          const double *__restrict__ Cc, const double *__restrict__ Ee,
                                                          const double *__restrict__ D, double *__restrict__ gam,
-                                                         double *__restrict__ Gam)
+                                                         double *__restrict__ Gam, int sym)
 {
     const int n = p.n, M = p.M;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n4 = (int64_t)n * n * n * n;
     if (t >= n4) return;
     const int dd = t % n, c = (t / n) % n, b = (t / n / n) % n, a = (int)(t / n / n / n);
-    // G(p,q,r,s) lives at dab[q][s][p][r]
-    const double gpqrs = dab[g4(n, b, dd, a, c)] + dab[g4(n, dd, b, c, a)];
-    double v = gpqrs + d_term(dt0, dt1, p.npair, n, a, b, c, dd);
+    // G(p,q,r,s) lives at dab[q][s][p][r]; with sym the double pairs were
+    // visited once and the reversed ones add the entry (q,p,s,r)
+    double v = dab[g4(n, b, dd, a, c)] + dab[g4(n, dd, b, c, a)] + d_term(dt0, dt1, p.npair, n, a, b, c, dd);
+    if (sym) v += dab[g4(n, a, c, b, dd)] + dab[g4(n, c, a, dd, b)] + d_term(dt0, dt1, p.npair, n, b, a, dd, c);
     const double *S0 = S, *S1 = S + (size_t)n * n;
     auto occ = [&](uint64_t w, int x) { return (double)((w >> x) & 1); };
     auto cpq = [&](const double *X, int pp, int qq, int xx) { return X[((size_t)pp * n + qq) * n + xx]; };
@@ -319,7 +348,8 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
                                                              const double2 *__restrict__ S,
                                                              const double2 *__restrict__ Cc,
                                                              const double2 *__restrict__ D,
-                                                             double2 *__restrict__ gam, double2 *__restrict__ Gam)
+                                                             double2 *__restrict__ gam, double2 *__restrict__ Gam,
+                                                             int sym)
 {
     const int M = p.M, n = p.n;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,6 +357,7 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
     if (t >= m4) return;
     const int dd = t % M, c = (t / M) % M, b = (t / M / M) % M, a = (int)(t / M / M / M);
     double2 v = d_term(dt0, dt1, p.npair, M, a, b, c, dd);
+    if (sym) v = sc_add(v, sc_conj(d_term(dt0, dt1, p.npair, M, b, a, dd, c)));
     auto inref = [&](int X) { return X < n ? ((p.ref0 >> X) & 1) : ((p.ref1 >> (X - n)) & 1); };
     auto cpq = [&](int P, int Q, int X) { return Cc[((size_t)P * M + Q) * M + X]; };
     if (c == dd) v = sc_add(v, sc_add(inref(c) ? S[(size_t)a * M + b] : sc_zero(double2()), cpq(a, b, c)));
@@ -366,6 +397,8 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
 {
     RdmWeights W;
     for (int k = 0; k < 64; k++) W.w[k] = (weights && k < R) ? weights[k] : 1.0;
+    // one vector as bra and ket (real weights): w_JI = conj(w_IJ)
+    const bool sym = bra == ket;
     const int n = p.n, M = p.M;
     const unsigned gd = (unsigned)((p.npacket_double + 3) / 4);
     const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
@@ -378,18 +411,31 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         double *Cc = S + 2 * (int64_t)n * n, *Ee = Cc + n3, *D = Ee + n3, *part = D + mm;
         zero(dab, n4 + 2 * np2 + 2 * (int64_t)n * n + 2 * n3, s);
         ProfToken t = prof_begin("rdm_groups", s);
-        if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8>), dim3(gdx), dim3(256), 0, s, p, R, (const double *)bra,
-                                   (const double *)ket, W, dab, dt0, dt1);
-        if (gs) hipLaunchKernelGGL(k_rdm_single<false>, dim3(gs), dim3(256), 0, s, p, R, (const double *)bra,
-                                   (const double *)ket, W, S, Cc, Ee);
+        if (sym) {
+            if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8, true>), dim3(gdx), dim3(256), 0, s, p, R,
+                                       (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
+            if (gs) hipLaunchKernelGGL((k_rdm_single<false, true>), dim3(gs), dim3(256), 0, s, p, R,
+                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee);
+        } else {
+            if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8, false>), dim3(gdx), dim3(256), 0, s, p, R,
+                                       (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
+            if (gs) hipLaunchKernelGGL((k_rdm_single<false, false>), dim3(gs), dim3(256), 0, s, p, R,
+                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee);
+        }
         prof_end(t, s);
+        if (sym) {
+            hipLaunchKernelGGL(k_rdm_mirror<double>, dim3((unsigned)((2 * (int64_t)n * n + 255) / 256)), dim3(256), 0,
+                               s, S, n, 1, 2);
+            hipLaunchKernelGGL(k_rdm_mirror<double>, dim3((unsigned)((2 * n3 + 255) / 256)), dim3(256), 0, s, Cc, n,
+                               n, 2);
+        }
         t = prof_begin("rdm_diag", s);
         hipLaunchKernelGGL((k_rdm_occ<false, 16>), dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(256), 0, s,
                            p, R, (const double *)bra, (const double *)ket, W, part);
         hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
                            (const double *)part, D);
         hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, dab, dt0, dt1,
-                           S, Cc, Ee, D, (double *)gamma, (double *)Gamma);
+                           S, Cc, Ee, D, (double *)gamma, (double *)Gamma, (int)sym);
         prof_end(t, s);
     } else {
         const int64_t m4 = mm * mm, np2 = (int64_t)p.npair * p.npair, m3 = mm * M;
@@ -397,18 +443,30 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
                 *part = D + mm;
         zero((double *)dt0, 2 * (2 * np2 + mm + m3), s);
         ProfToken t = prof_begin("rdm_groups", s);
-        if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4>), dim3(gdx), dim3(256), 0, s, p, R, (const double2 *)bra,
-                                   (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
-        if (gs) hipLaunchKernelGGL(k_rdm_single<true>, dim3(gs), dim3(256), 0, s, p, R, (const double2 *)bra,
-                                   (const double2 *)ket, W, S, Cc, (double *)nullptr);
+        if (sym) {
+            if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4, true>), dim3(gdx), dim3(256), 0, s, p, R,
+                                       (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
+            if (gs) hipLaunchKernelGGL((k_rdm_single<true, true>), dim3(gs), dim3(256), 0, s, p, R,
+                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr);
+        } else {
+            if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4, false>), dim3(gdx), dim3(256), 0, s, p, R,
+                                       (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
+            if (gs) hipLaunchKernelGGL((k_rdm_single<true, false>), dim3(gs), dim3(256), 0, s, p, R,
+                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr);
+        }
         prof_end(t, s);
+        if (sym) {
+            hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, S, M, 1, 1);
+            hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Cc, M, M,
+                               1);
+        }
         t = prof_begin("rdm_diag", s);
         hipLaunchKernelGGL((k_rdm_occ<true, 8>), dim3(RDM_OCC_CHUNKS, (unsigned)((M + 31) / 32)), dim3(256), 0, s, p,
                            R, (const double2 *)bra, (const double2 *)ket, W, part);
         hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
                            (const double2 *)part, D);
         hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, dt0, dt1, S,
-                           Cc, D, (double2 *)gamma, (double2 *)Gamma);
+                           Cc, D, (double2 *)gamma, (double2 *)Gamma, (int)sym);
         prof_end(t, s);
     }
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "rdm kernel launch failed");

@@ -65,6 +65,29 @@ def test_rdm_fci_n8(torch):
     assert _rel(g1, r1) <= TOL and _rel(g2, r2) <= TOL
 
 
+@pytest.mark.parametrize("kind", ["spinfree", "spinor"])
+def test_rdm_one_vector_half_pairs(torch, kind):
+    """bra and ket the same device vector (two weighted roots): each
+    unordered pair is visited once and the mirror image added at the end.
+    Equal to the oracle (1e-12) and to the all-pairs path, which a separate
+    copy of the same vector takes (1e-13)."""
+    if kind == "spinfree":
+        p = synth.workload(4)
+        c = synth.ci_vectors(p.ndet, 2, np.random.default_rng(11))
+    else:
+        p = _spinor_problem(8, 6, 2000, 3)
+        c = synth.ci_vectors(p.ndet, 2, np.random.default_rng(11), complex_=True)
+    pl = _plan(p, max_roots=2)
+    w = [0.6, 0.4]
+    cd = _dev(torch, c)
+    g1, g2 = (x.cpu().numpy() for x in pl.rdm(cd, cd, weights=w))
+    a1, a2 = (x.cpu().numpy() for x in pl.rdm(cd, cd.clone(), weights=w))
+    r1, r2 = sc.rdm(p, c, c, weights=w)
+    _say(kind, "half", _rel(g1, r1), _rel(g2, r2), "all pairs", _rel(a1, r1), _rel(a2, r2))
+    assert _rel(g1, r1) <= TOL and _rel(g2, r2) <= TOL
+    assert _rel(g1, a1) <= 1e-13 and _rel(g2, a2) <= 1e-13
+
+
 def test_rdm_transition_weighted_roots(torch):
     """Transition matrices, two roots with weights, different bra and ket
     (n=10 3a3b FCI)."""
