@@ -18,9 +18,9 @@
 //   k_pt2_enum<1>     the same pairs, counted per bucket
 //   k_pt2_enum<2>     the pairs of the buckets of one pass, written as
 //                     records {A, J} with H_AJ c_J at the bucket's offset
-//   k_pt2_bucket      one workgroup per bucket: sorts its records by (A, J)
-//                     in LDS, sums each numerator in ascending J, adds
-//                     |num|^2 / (E0 - H_AA) in sorted order
+//   k_pt2_bucket      one workgroup per bucket: sorts its records by (hash
+//                     bits of A, J) in LDS, sums each numerator in ascending
+//                     J, adds |num|^2 / (E0 - H_AA) in sorted order
 //   k_pt2_sum1/2      per pass: bucket partial sums in a fixed order
 //
 // Passes over bucket ranges keep the records within the caller's work
@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 #include <vector>
@@ -41,14 +42,14 @@ namespace mw {
 namespace {
 
 constexpr int PT2_CAP = 1024;      // records of a bucket sorted by the common kernel (26 KB LDS)
-constexpr int PT2_CAP_BIG = 4096;  // oversized buckets (rare): a kernel with 92 KB LDS
+constexpr int PT2_CAP_BIG = 4096;  // oversized buckets (rare): a kernel with 104 KB LDS
 constexpr int PT2_MEAN = 400;      // target records per bucket
 constexpr int PT2_MAXR = 8;        // roots per call
 
 struct Rec {
     uint64_t a0, a1;
-    double haa;   // H_AA from this record's partner J (the first J of A is used)
-    uint64_t j;
+    double haa;    // H_AA from this record's partner J (the first J of A is used)
+    uint64_t key;  // low 32 bits of the hash of A (high word), then J
 };
 
 // Excitation classes of a determinant of the space; the counts are equal
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
                                                   const uint64_t *__restrict__ off, uint32_t *fill, Rec *rec,
                                                   typename Scal<CPLX>::T *val, const double *__restrict__ eps,
                                                   const double *__restrict__ vg, unsigned long long *total,
-                                                  int64_t jbase)
+                                                  int64_t jbase, uint32_t kmask)
 {
     using T = typename Scal<CPLX>::T;
     __shared__ uint8_t ol[2][128], vl[2][128];
@@ -329,7 +330,8 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
                 double hjj;
                 if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
                 else hjj = ((const double *)p.diag)[J];
-                rec[slot] = Rec{a0, a1, hjj + diag_delta(s_eps, vg, p.M, Q, S, P, Rr), (uint64_t)J};
+                rec[slot] = Rec{a0, a1, hjj + diag_delta(s_eps, vg, p.M, Q, S, P, Rr),
+                                ((h & kmask) << 32) | (uint64_t)(uint32_t)J};
                 const T v = exc_value<CPLX>(p, j0, j1, Q, S, P, Rr);
                 for (int q = 0; q < R; q++) val[slot * R + q] = sc_mul(v, s_c[q]);
             }
@@ -385,6 +387,9 @@ __global__ __launch_bounds__(256) void k_pt2_tables(DevPlan p, double *eps, doub
 // One workgroup per bucket (blockIdx.x -> bucket b0 + blockIdx.x, or
 // list[blockIdx.x] for the oversized ones).  Buckets with more than CAP
 // records are left to the larger instance (their sums are written there).
+// The records are sorted by one 64-bit key (low hash bits of A, then J), so
+// the records of one A form a run in ascending J; a run whose hash bits are
+// shared by several A (a collision) takes its A's in ascending (a0, a1).
 template <bool CPLX, int CAP>
 __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t b0, const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ cnt,
@@ -394,11 +399,11 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
                                                     uint32_t boff)
 {
     using T = typename Scal<CPLX>::T;
-    __shared__ uint64_t s0[CAP], s1[CAP];
-    __shared__ uint32_t sj[CAP];
-    __shared__ uint16_t si[CAP];
-    __shared__ double red[256];
-    __shared__ unsigned long long redc[256];
+    static_assert(3 * CAP >= (PT2_MAXR + 2) * 256, "reduction area");
+    __shared__ uint64_t sm[3 * CAP];
+    __shared__ uint16_t si[CAP];  // record index of sorted position
+    uint64_t *sk = sm;            // sorted keys
+    uint64_t *s0 = sm + CAP, *s1 = sm + 2 * CAP;  // A of record i (bucket order)
     const uint32_t b = list ? list[boff + blockIdx.x] : b0 + boff + blockIdx.x;
     const uint32_t slot_out = b - b0;
     const int m = (int)cnt[b];
@@ -409,31 +414,28 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
     for (int i = threadIdx.x; i < np2; i += blockDim.x) {
         if (i < m) {
             const Rec &r = rec[base + i];
+            sk[i] = r.key;
             s0[i] = r.a0;
             s1[i] = r.a1;
-            sj[i] = (uint32_t)r.j;
         } else {
-            s0[i] = ~0ULL;
-            s1[i] = ~0ULL;
-            sj[i] = ~0u;
+            sk[i] = ~0ULL;
         }
         si[i] = (uint16_t)i;
     }
     __syncthreads();
-    // bitonic sort by (A, J) ascending
+    // bitonic sort of (key, index) ascending; keys within a bucket are
+    // distinct unless two A share the hash bits and a partner J
     for (int k = 2; k <= np2; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
             for (int i = threadIdx.x; i < np2; i += blockDim.x) {
                 const int l = i ^ jj;
                 if (l > i) {
                     const bool up = (i & k) == 0;
-                    const uint64_t x0 = s0[i], x1 = s1[i], y0 = s0[l], y1 = s1[l];
-                    const uint32_t xj = sj[i], yj = sj[l];
-                    const bool gt = x0 != y0 ? x0 > y0 : (x1 != y1 ? x1 > y1 : xj > yj);
-                    if (gt == up) {
+                    const uint64_t x = sk[i], y = sk[l];
+                    if ((x > y) == up) {
                         const uint16_t xi = si[i];
-                        s0[i] = y0; s1[i] = y1; sj[i] = yj; si[i] = si[l];
-                        s0[l] = x0; s1[l] = x1; sj[l] = xj; si[l] = xi;
+                        sk[i] = y; si[i] = si[l];
+                        sk[l] = x; si[l] = xi;
                     }
                 }
             }
@@ -444,24 +446,25 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
 #pragma unroll
     for (int k = 0; k < PT2_MAXR; k++) acc[k] = 0.0;
     unsigned long long kept = 0, nq = 0;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const uint64_t a0 = s0[i], a1 = s1[i];
-        if (i > 0 && s0[i - 1] == a0 && s1[i - 1] == a1) continue;  // not the first record of its A
-        int e = i + 1;
-        while (e < m && s0[e] == a0 && s1[e] == a1) e++;
-        // numerators in ascending J (the records are the kept pairs)
+    // |sum over the records u of run [i, e) whose A is (a0, a1), in run
+    // order| ^ 2 / (E0 - H_AA), H_AA from the first of them
+    auto add_a = [&](int i, int e, uint64_t a0, uint64_t a1) {
         T num[PT2_MAXR];
 #pragma unroll
         for (int k = 0; k < PT2_MAXR; k++) num[k] = sc_zero(T());
+        int first = -1;
         for (int u = i; u < e; u++) {
-            const T *v = val + (base + si[u]) * R;
+            const int ru = si[u];
+            if (s0[ru] != a0 || s1[ru] != a1) continue;
+            if (first < 0) first = ru;
+            const T *v = val + (base + ru) * R;
 #pragma unroll
             for (int k = 0; k < PT2_MAXR; k++)
                 if (k < R) num[k] = sc_add(num[k], v[k]);
+            kept++;
         }
-        kept += (unsigned long long)(e - i);
         nq++;
-        const double haa = rec[base + si[i]].haa;  // from the first (smallest) J
+        const double haa = rec[base + first].haa;
 #pragma unroll
         for (int k = 0; k < PT2_MAXR; k++) {
             if (k >= R) continue;
@@ -470,27 +473,53 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
             else q = num[k] * num[k];
             acc[k] += q / (roots.e0[k] - haa);
         }
-    }
-    // fixed-order block reductions
-    for (int k = 0; k < R; k++) {
-        red[threadIdx.x] = acc[k];
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
+    };
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const uint32_t hi = (uint32_t)(sk[i] >> 32);
+        if (i > 0 && (uint32_t)(sk[i - 1] >> 32) == hi) continue;  // not the first record of its run
+        int e = i + 1;
+        while (e < m && (uint32_t)(sk[e] >> 32) == hi) e++;
+        uint64_t c0 = s0[si[i]], c1 = s1[si[i]];
+        bool multi = false;
+        for (int u = i + 1; u < e && !multi; u++) multi = s0[si[u]] != c0 || s1[si[u]] != c1;
+        // several A in the run (rare): each in ascending (a0, a1), starting
+        // from the smallest
+        bool have = false;
+        for (;;) {
+            if (multi) {
+                bool found = false;
+                uint64_t b0_ = 0, b1_ = 0;
+                for (int u = i; u < e; u++) {
+                    const uint64_t x0 = s0[si[u]], x1 = s1[si[u]];
+                    if (have && (x0 < c0 || (x0 == c0 && x1 <= c1))) continue;
+                    if (!found || x0 < b0_ || (x0 == b0_ && x1 < b1_)) { b0_ = x0; b1_ = x1; found = true; }
+                }
+                if (!found) break;
+                c0 = b0_;
+                c1 = b1_;
+            }
+            add_a(i, e, c0, c1);
+            have = true;
+            if (!multi) break;
         }
-        if (threadIdx.x == 0) part[(size_t)slot_out * R + k] = red[0];
+    }
+    // fixed-order block reductions of the R sums and the two counts (as
+    // doubles: a block's counts are below 2^13, exact) in the freed sort area
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(sm);
+    for (int k = 0; k < R; k++) red[k * 256 + threadIdx.x] = acc[k];
+    red[R * 256 + threadIdx.x] = (double)kept;
+    red[(R + 1) * 256 + threadIdx.x] = (double)nq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < R + 2; k++) red[k * 256 + threadIdx.x] += red[k * 256 + threadIdx.x + s];
         __syncthreads();
     }
-    for (int w = 0; w < 2; w++) {
-        redc[threadIdx.x] = w ? nq : kept;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) redc[threadIdx.x] += redc[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) partc[2 * (size_t)slot_out + w] = redc[0];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < R; k++) part[(size_t)slot_out * R + k] = red[k * 256];
+        partc[2 * (size_t)slot_out] = (unsigned long long)red[R * 256];
+        partc[2 * (size_t)slot_out + 1] = (unsigned long long)red[(R + 1) * 256];
     }
 }
 
@@ -758,13 +787,27 @@ __global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t 
             __syncthreads();
         }
     }
-    // one thread compacts (a bucket holds a few hundred keys)
-    if (threadIdx.x == 0) {
-        uint32_t u = 0;
-        for (int i = 0; i < m; i++)
-            if (i == 0 || s0[i] != s0[i - 1] || s1[i] != s1[i - 1]) kb[u++] = make_ulonglong2(s0[i], s1[i]);
-        ucnt[b] = u;
+    // compaction in sorted order: each thread takes a contiguous run of
+    // positions, an exclusive scan of the per-thread counts gives its output
+    // offset
+    __shared__ uint32_t sc[256];
+    const int per = (m + 255) / 256;
+    const int lo = min(m, (int)threadIdx.x * per), hi = min(m, lo + per);
+    auto first = [&](int i) { return i == 0 || s0[i] != s0[i - 1] || s1[i] != s1[i - 1]; };
+    uint32_t c = 0;
+    for (int i = lo; i < hi; i++) c += first(i) ? 1u : 0u;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
     }
+    uint32_t u = sc[threadIdx.x] - c;
+    for (int i = lo; i < hi; i++)
+        if (first(i)) kb[u++] = make_ulonglong2(s0[i], s1[i]);
+    if (threadIdx.x == 255) ucnt[b] = sc[255];
 }
 
 // out[uoff[b] + i] = the i-th distinct key of bucket b (b in [b0, b0 + nb))
@@ -797,10 +840,17 @@ void launch_enum(const DevPlan &d, const ExcClasses &ex, const DetSet &inP, int 
                  Rec *rec, typename Scal<CPLX>::T *val, const double *eps, const double *vg, unsigned long long *tot,
                  hipStream_t s)
 {
+    // hash bits kept in the records' sort key: all 32, or fewer when the
+    // environment sets MW_PT2_KEY_BITS (1..31) to test runs of several A
+    uint32_t kmask = 0xffffffffu;
+    if (const char *e = getenv("MW_PT2_KEY_BITS")) {
+        const int bits = atoi(e);
+        if (bits >= 1 && bits < 32) kmask = (1u << bits) - 1u;
+    }
     for (int64_t j = 0; j < d.ndet; j += PT2_MAXGRID) {
         const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, d.ndet - j);
         hipLaunchKernelGGL((k_pt2_enum<CPLX, MODE>), dim3(g), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb, b0, b1,
-                           cnt, off, fill, rec, val, eps, vg, tot, j);
+                           cnt, off, fill, rec, val, eps, vg, tot, j, kmask);
     }
 }
 

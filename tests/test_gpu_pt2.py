@@ -123,6 +123,31 @@ def test_pt2_passes_and_reproducibility(torch):
     assert abs(e_c[0] - e_a[0]) <= 1e-13 * abs(e_a[0])
 
 
+@pytest.mark.parametrize("bits", [1, 3])
+def test_pt2_shared_hash_bits(torch, monkeypatch, bits):
+    """Records are sorted by a few hash bits of A then J: with only 1 or 3
+    bits kept (MW_PT2_KEY_BITS) nearly every run holds several external
+    determinants, which the bucket kernel must separate.  Counts exact,
+    energies within 1e-12 of the oracle (real two roots, and complex);
+    repeated calls identical bits."""
+    n = 12
+    rng = synth.rng_for(5, 15, synth.SEED_SPACE)
+    d = synth.random_space_spinfree(n, 4, 4, 400, rng)
+    p = _prob("spinfree", n, 4, 4, d, synth.one_body_real(n, rng), synth.two_body_real(n, rng))
+    p.name = "sf-n12-keybits"
+    c = synth.ci_vectors(p.ndet, 2, np.random.default_rng(5))
+    monkeypatch.setenv("MW_PT2_KEY_BITS", str(bits))
+    e_a, _ = _check(torch, p, c, -12.0 - np.arange(2))
+    e_b, _ = _plan(p, max_roots=2).pt2(_dev(torch, c), -12.0 - np.arange(2))
+    assert np.array_equal(e_a.view(np.uint64), e_b.view(np.uint64))
+    nk = 8
+    rs = synth.rng_for(5, 16, synth.SEED_SPACE)
+    ds = synth.space_selected_spinor(nk, 4, 600, rs)
+    q = _prob("spinor", nk, 4, -1, ds, synth.one_body_spinor(nk, rs), synth.two_body_spinor(nk, rs))
+    q.name = "spinor-keybits"
+    _check(torch, q, synth.ci_vectors(q.ndet, 1, np.random.default_rng(6), complex_=True), -9.0)
+
+
 def test_pt2_complete_space_and_edges(torch):
     """P = complete space: E2 = 0 (every excitation lands in P); a space
     with no virtual orbital: nothing generated."""
