@@ -177,7 +177,10 @@ mw_status mw_diag(mw_plan plan, void *out, mw_stream_t stream);
  * device [ndet][nroots]; weights HOST [nroots] or NULL (all 1); gamma, Gamma
  * device outputs, overwritten.  For E = c^H H c, dE/dh = gamma and dE/dg =
  * Gamma / 2.  Connectivity is recomputed, never stored.  Uses device atomics:
- * results are reproducible to rounding, not bitwise. */
+ * results are reproducible to rounding, not bitwise.  When bra and ket are
+ * the same pointer, each unordered pair is visited once and the reversed
+ * pair's contribution (the complex conjugate) is added in the final pass:
+ * the same matrices to rounding, half the atomics. */
 mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *bra, const void *ket,
                           const double *weights, void *gamma, void *Gamma, mw_stream_t stream);
 
@@ -209,7 +212,10 @@ mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out,
  * tables or one bucket).  stats: HOST int64[5], nullable: kept (A, J)
  * pairs with A in Q, number of A in Q, passes, buckets, excitations
  * enumerated per pass (ndet x singles and doubles of one determinant).
- * Host-driven, synchronises the stream; repeated calls give identical bits. */
+ * Host-driven, synchronises the stream; repeated calls give identical bits.
+ * Testing knob: the environment variable MW_PT2_KEY_BITS (1..31) keeps only
+ * that many hash bits of A in the records' sort key, so that many external
+ * determinants share a run (the result is the same to rounding). */
 mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
 mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const double *e0, double qmin, void *work,
                  size_t work_bytes, double *e2, int64_t *stats, mw_stream_t stream);
