@@ -76,6 +76,10 @@ struct HostPlan;
 
 // arguments of one batched launch (at most MW_MAXB problems)
 constexpr int MW_MAXB = 32;
+
+// copies of the single-excitation density accumulators (S, C, E) that the
+// single-pair kernel spreads its atomics over
+constexpr int RDM_COPIES = 32;
 struct BatchArgs {
     int nprob;
     const DevPlan *plans[MW_MAXB];   // device copies

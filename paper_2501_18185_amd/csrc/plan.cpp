@@ -749,13 +749,14 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.ref1 = ref1;
     t.npacket_double = npacket_double;
     // per-call scratch: sigma partials, or the density-matrix accumulators
-    // density-matrix accumulators: double pairs, S, single corrections (n^3
-    // or M^3), occupation correlations and their 256 per-chunk partials
+    // density-matrix accumulators: double pairs, RDM_COPIES copies of S and
+    // the single corrections (n^3 or M^3), occupation correlations and their
+    // 256 per-chunk partials
     const size_t mm = (size_t)M * M;
     size_t rdm_bytes = kind == MW_SPIN_FREE
-                           ? ((size_t)n * n * n * n + 2 * (size_t)npair * npair + 2 * (size_t)n * n +
-                              2 * (size_t)n * n * n + 257 * mm) * 8
-                           : (2 * (size_t)npair * npair + mm + mm * M + 257 * mm) * 16;
+                           ? ((size_t)n * n * n * n + 2 * (size_t)npair * npair +
+                              RDM_COPIES * (2 * (size_t)n * n + 2 * (size_t)n * n * n) + 257 * mm) * 8
+                           : (2 * (size_t)npair * npair + RDM_COPIES * (mm + mm * M) + 257 * mm) * 16;
     t.scratch_bytes = std::max(std::max<size_t>(1, mem.size() + (size_t)ncol) * (size_t)max_roots * sb, rdm_bytes);
     t.partial = (void *)take(t.scratch_bytes);
     t.self = (DevPlan *)take(sizeof(DevPlan));

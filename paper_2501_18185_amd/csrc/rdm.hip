@@ -142,12 +142,20 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
                                                     typename Scal<CPLX>::T *__restrict__ S,
                                                     typename Scal<CPLX>::T *__restrict__ Cc,
-                                                    double *__restrict__ Ee)
+                                                    double *__restrict__ Ee, int64_t copy_stride)
 {
     using T = typename Scal<CPLX>::T;
     const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (wave >= p.npacket) return;
+    // the few S, C, E entries take many additions: spread them over
+    // RDM_COPIES copies (folded before the final pass) by block
+    {
+        const int64_t o = (int64_t)(blockIdx.x % RDM_COPIES) * copy_stride;
+        S += o;
+        Cc += o;
+        if (Ee) Ee += o;
+    }
     const uint32_t m = p.pk_off[wave] + lane;
     if (m >= p.pk_off[wave + 1]) return;
     const uint32_t g = p.mem_grp[m];
@@ -283,6 +291,17 @@ __device__ __forceinline__ T d_term(const T *dt0, const T *dt1, int np, int m, i
     return sc_neg(d_pair(dt0, dt1, np, m, c, a, b, d), true);
 }
 
+// X[t] = sum of the copies X[c * stride + t], c = 0 .. copies-1, in order
+template <class T>
+__global__ __launch_bounds__(256) void k_rdm_fold(T *X, int64_t stride, int copies)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= stride) return;
+    T v = X[t];
+    for (int c = 1; c < copies; c++) v = sc_add(v, X[c * stride + t]);
+    X[t] = v;
+}
+
 // SYM pass for the single-excitation accumulators: X[P][Q][x] and
 // X[Q][P][x] (P < Q; x over `inner` entries) both become their sum with the
 // other's conjugate.  `outer` blocks of the matrix (spin-free: the two spin
@@ -407,22 +426,26 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
     const unsigned gred = (unsigned)((mm + 255) / 256);
     if (p.kind == MW_SPIN_FREE) {
         const int64_t n4 = (int64_t)n * n * n * n, np2 = (int64_t)p.npair * p.npair, n3 = (int64_t)n * n * n;
+        // S | C | E, RDM_COPIES times
+        const int64_t cs = 2 * (int64_t)n * n + 2 * n3;
         double *dab = (double *)p.partial, *dt0 = dab + n4, *dt1 = dt0 + np2, *S = dt1 + np2;
-        double *Cc = S + 2 * (int64_t)n * n, *Ee = Cc + n3, *D = Ee + n3, *part = D + mm;
-        zero(dab, n4 + 2 * np2 + 2 * (int64_t)n * n + 2 * n3, s);
+        double *Cc = S + 2 * (int64_t)n * n, *Ee = Cc + n3, *D = S + RDM_COPIES * cs, *part = D + mm;
+        zero(dab, n4 + 2 * np2 + RDM_COPIES * cs, s);
         ProfToken t = prof_begin("rdm_groups", s);
         if (sym) {
             if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8, true>), dim3(gdx), dim3(256), 0, s, p, R,
                                        (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
             if (gs) hipLaunchKernelGGL((k_rdm_single<false, true>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee);
+                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
         } else {
             if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8, false>), dim3(gdx), dim3(256), 0, s, p, R,
                                        (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
             if (gs) hipLaunchKernelGGL((k_rdm_single<false, false>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee);
+                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
         }
         prof_end(t, s);
+        hipLaunchKernelGGL(k_rdm_fold<double>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
+                           RDM_COPIES);
         if (sym) {
             hipLaunchKernelGGL(k_rdm_mirror<double>, dim3((unsigned)((2 * (int64_t)n * n + 255) / 256)), dim3(256), 0,
                                s, S, n, 1, 2);
@@ -439,22 +462,26 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         prof_end(t, s);
     } else {
         const int64_t m4 = mm * mm, np2 = (int64_t)p.npair * p.npair, m3 = mm * M;
-        double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2, *Cc = S + mm, *D = Cc + m3,
-                *part = D + mm;
-        zero((double *)dt0, 2 * (2 * np2 + mm + m3), s);
+        // S | C, RDM_COPIES times
+        const int64_t cs = mm + m3;
+        double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2, *Cc = S + mm,
+                *D = S + RDM_COPIES * cs, *part = D + mm;
+        zero((double *)dt0, 2 * (2 * np2 + RDM_COPIES * cs), s);
         ProfToken t = prof_begin("rdm_groups", s);
         if (sym) {
             if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4, true>), dim3(gdx), dim3(256), 0, s, p, R,
                                        (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
             if (gs) hipLaunchKernelGGL((k_rdm_single<true, true>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr);
+                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
         } else {
             if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4, false>), dim3(gdx), dim3(256), 0, s, p, R,
                                        (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
             if (gs) hipLaunchKernelGGL((k_rdm_single<true, false>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr);
+                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
         }
         prof_end(t, s);
+        hipLaunchKernelGGL(k_rdm_fold<double2>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
+                           RDM_COPIES);
         if (sym) {
             hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, S, M, 1, 1);
             hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Cc, M, M,
