@@ -215,48 +215,62 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
 // correlation D[A][B] = sum_I w_I n_A(I) n_B(I) over global positions gives
 // gamma_AA = D[A][A] and the diagonal parts of Gamma (Gamma_AABB += D[A][B],
 // Gamma_ABBA -= D[A][B] for A != B; spin-free: summed over spins, the
-// exchange-like part for equal spins only).  Block (x, y): determinants of
-// chunk x, positions A of chunk y (AW per wave); lane l holds B = l, l + 64;
-// one partial matrix per determinant chunk, reduced in a fixed order.
+// exchange-like part for equal spins only).  One partial matrix per
+// determinant chunk, reduced in a fixed order.
 constexpr int RDM_OCC_CHUNKS = 256;
 
-template <bool CPLX, int AW>
-__global__ __launch_bounds__(256) void k_rdm_occ(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
-                                                 const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
-                                                 typename Scal<CPLX>::T *__restrict__ part)
+// Block (x, y) of 1024 threads adds w_I into an LDS copy of rows
+// [A0, A0 + ROWS) of D for every determinant of chunk x, each lane holding
+// B = lane, lane + 64 and the wave walking the occupied A of the
+// determinant (LDS atomics: the 16 waves take different determinants); then
+// it writes its rows of the chunk's partial matrix.
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
+                                                      const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
+                                                      typename Scal<CPLX>::T *__restrict__ part)
 {
     using T = typename Scal<CPLX>::T;
+    constexpr int ROWS = CPLX ? 64 : 128;  // 128 KB of LDS
+    __shared__ T ds[ROWS * 128];
     const int n = p.n, M = p.M;
-    const int lane = threadIdx.x & 63;
-    const int A0 = (int)blockIdx.y * 4 * AW + (int)(threadIdx.x >> 6) * AW;
+    const int A0 = (int)blockIdx.y * ROWS, A1 = min(M, A0 + ROWS);
+    const int rows = A1 - A0;
+    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) ds[t] = sc_zero(T());
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int64_t chunk = (p.ndet + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(p.ndet, lo + chunk);
-    auto occ = [&](uint64_t d0, uint64_t d1, int X) { return X < n ? ((d0 >> X) & 1) : ((d1 >> (X - n)) & 1); };
-    T acc[AW][2];
-#pragma unroll
-    for (int a = 0; a < AW; a++) acc[a][0] = acc[a][1] = sc_zero(T());
-    const int B0 = lane, B1 = lane + 64;
-    for (int64_t I = lo; I < hi; I++) {
+    // occupied global positions of the row range, as two masks over the words
+    auto rowmask = [&](uint64_t d0, uint64_t d1, uint64_t &m0, uint64_t &m1) {
+        // word 0 holds positions [0, n), word 1 positions [n, 2n)
+        auto range = [](int a, int b) -> uint64_t {  // bits [a, b) of a word, 0 <= a <= b <= 64
+            if (a >= b) return 0ULL;
+            const uint64_t hi_ = b >= 64 ? ~0ULL : ((1ULL << b) - 1);
+            return hi_ & ~((1ULL << a) - 1);
+        };
+        m0 = d0 & range(min(A0, n), min(A1, n));
+        m1 = d1 & range(max(A0 - n, 0), max(min(A1 - n, 64), 0));
+    };
+    for (int64_t I = lo + wv; I < hi; I += nw) {
         const uint64_t d0 = p.dets[2 * I], d1 = p.dets[2 * I + 1];
         const T w = pair_weight<CPLX>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
-        const bool o0 = B0 < M && occ(d0, d1, B0), o1 = B1 < M && occ(d0, d1, B1);
-#pragma unroll
-        for (int a = 0; a < AW; a++) {
-            const int A = A0 + a;
-            if (A < M && occ(d0, d1, A)) {
-                if (o0) acc[a][0] = sc_add(acc[a][0], w);
-                if (o1) acc[a][1] = sc_add(acc[a][1], w);
+        const int B0 = lane, B1 = lane + 64;
+        const bool o0 = B0 < M && (B0 < n ? (d0 >> B0) & 1 : (d1 >> (B0 - n)) & 1);
+        const bool o1 = B1 < M && (B1 < n ? (d0 >> B1) & 1 : (d1 >> (B1 - n)) & 1);
+        uint64_t m0, m1;
+        rowmask(d0, d1, m0, m1);
+        for (int word = 0; word < 2; word++) {
+            for (uint64_t x = word ? m1 : m0; x; x &= x - 1) {
+                const int A = __builtin_ctzll(x) + (word ? n : 0);
+                T *row = ds + (size_t)(A - A0) * M;
+                if (o0) atom_add(row + B0, w);
+                if (o1) atom_add(row + B1, w);
             }
         }
     }
-    T *out = part + (size_t)blockIdx.x * M * M;
-#pragma unroll
-    for (int a = 0; a < AW; a++) {
-        const int A = A0 + a;
-        if (A >= M) continue;
-        if (B0 < M) out[(size_t)A * M + B0] = acc[a][0];
-        if (B1 < M) out[(size_t)A * M + B1] = acc[a][1];
-    }
+    __syncthreads();
+    T *out = part + (size_t)blockIdx.x * M * M + (size_t)A0 * M;
+    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) out[t] = ds[t];
 }
 
 template <typename T>
@@ -453,7 +467,7 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
                                n, 2);
         }
         t = prof_begin("rdm_diag", s);
-        hipLaunchKernelGGL((k_rdm_occ<false, 16>), dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_rdm_occ_lds<false>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 127) / 128)), dim3(1024), 0, s,
                            p, R, (const double *)bra, (const double *)ket, W, part);
         hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
                            (const double *)part, D);
@@ -488,7 +502,7 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
                                1);
         }
         t = prof_begin("rdm_diag", s);
-        hipLaunchKernelGGL((k_rdm_occ<true, 8>), dim3(RDM_OCC_CHUNKS, (unsigned)((M + 31) / 32)), dim3(256), 0, s, p,
+        hipLaunchKernelGGL(k_rdm_occ_lds<true>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(1024), 0, s, p,
                            R, (const double2 *)bra, (const double2 *)ket, W, part);
         hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
                            (const double2 *)part, D);
