@@ -100,7 +100,7 @@ mw_status make_args(int32_t nprob, const mw_plan *plans, const int32_t *nroots, 
         a.pkd_start[k + 1] = a.pkd_start[k] + d[i]->npacket_double;
         a.pks_start[k + 1] = a.pks_start[k] + (d[i]->npacket - d[i]->npacket_double);
     }
-    batch_set_gather(b, 16);
+    batch_set_gather(b, cplx ? 32 : 16);  // the plain default width of the kind
     // one dispatch counts its work-items in 32 bits (gather laid out for the
     // widest width the tuner tries)
     int64_t blk32 = 0;

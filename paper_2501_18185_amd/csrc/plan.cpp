@@ -144,7 +144,10 @@ struct HostPlan {
     std::vector<double> h, w_same, w_opp, g_ab, a_pair, a_pair1, f_ref;
     uint64_t ref0 = 0, ref1 = 0;
     int64_t npacket_double = 0;
-    int32_t tune_u = 8, tune_gl = 16;
+    // launch defaults until mw_autotune picks its own: partner-loop unroll 4,
+    // 16 gather lanes (32 for complex), the fastest measured on the n = 64
+    // spin-free and 40-pair spinor spaces for one, two and four roots
+    int32_t tune_u = 4, tune_gl = 0;
     int64_t n_single_pairs = 0, n_double_pairs = 0, n_evals = 0;
     // device binding
     void *ws = nullptr;
@@ -762,7 +765,7 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.self = (DevPlan *)take(sizeof(DevPlan));
     t.counter = (uint32_t *)take(256);
     t.tune_u = tune_u;
-    t.tune_gl = tune_gl;
+    t.tune_gl = tune_gl ? tune_gl : (kind == MW_SPINOR ? 32 : 16);
     if (d) *d = t;
     return off + 256;
 }
