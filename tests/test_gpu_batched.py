@@ -114,6 +114,29 @@ def test_batched_direct_and_autotune(torch, batch):
         assert np.array_equal(o.cpu().numpy(), f)
 
 
+def test_batched_complex_equals_plain_bitwise(torch):
+    """Three complex spinor problems (different sizes, 1, 3 and 4 roots):
+    default batched launches (graph and flat grid) equal plain calls bit for
+    bit, and sampled rows match the oracle to 1e-12."""
+    from paper_2501_18185_amd import mw
+    probs, cs = [], []
+    for i, (nk, ne, nd, R) in enumerate([(8, 4, 700, 1), (10, 4, 1500, 3), (9, 6, 1200, 4)]):
+        rng = np.random.default_rng(40 + i)
+        d = synth.space_selected_spinor(nk, ne, nd, rng)
+        p = synth.Problem("spinor", nk, ne, -1, np.ascontiguousarray(d, np.uint64), synth.one_body_spinor(nk, rng),
+                          synth.two_body_spinor(nk, rng))
+        probs.append(p)
+        cs.append(torch.from_numpy(synth.ci_vectors(p.ndet, R, np.random.default_rng(50 + i), complex_=True)).cuda())
+    plans = [mw.Plan(p, max_roots=4) for p in probs]
+    plain = [pl.sigma(c).cpu().numpy() for pl, c in zip(plans, cs)]
+    for outs in (mw.sigma_batched(plans, cs), mw.sigma_batched_direct(plans, cs, blocks_per_cu=0)):
+        for i, (o, ref) in enumerate(zip(outs, plain)):
+            assert np.array_equal(o.cpu().numpy(), ref), f"problem {i}"
+    for p, c, ref in zip(probs, cs, plain):
+        rows = np.unique(np.concatenate([np.arange(5), [p.ndet - 1], np.arange(0, p.ndet, 53)]))
+        assert _rel(ref[rows], sc.sigma(p, c.cpu().numpy(), rows=rows)) <= 1e-12
+
+
 def test_plain_autotune_keeps_accuracy(torch):
     from paper_2501_18185_amd import mw
     p = synth.workload(0)
