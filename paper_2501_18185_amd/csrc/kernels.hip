@@ -254,24 +254,24 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
 {
     using T = typename Scal<CPLX>::T;
     const uint32_t mfirst = p.pk_off[wave], mend = p.pk_off[wave + 1];
-    {
-        // a packet of a large group is one 64-member block of it (uniform)
-        const uint32_t g0 = p.mem_grp[mfirst];
-        const uint32_t k = p.grp_off[g0 + 1] - p.grp_off[g0];
-        // every root-chunk width (1, 2 or 4 roots per pass) takes the
-        // Hermitian half-work on large groups
-        if (k >= 64) {
-            group_double_half<CPLX, RC>(p, mfirst, mend, lane, R, r0, c, partial);
-            return;
-        }
+    // a packet of a large group is one 64-member block of it (uniform); its
+    // members carry 0 as group size.  Every root-chunk width (1, 2 or 4
+    // roots per pass) takes the Hermitian half-work on large groups.
+    if (((p.mem[mfirst].y >> 24) & 63) == 0) {
+        group_double_half<CPLX, RC>(p, mfirst, mend, lane, R, r0, c, partial);
+        return;
     }
     const uint32_t m = mfirst + lane;
     if (m >= mend) return;
-    const uint32_t g = p.mem_grp[m];
-    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
-    const uint8_t type = p.grp_type[g];
     const uint2 me = p.mem[m];
+    // small group: partners from the member's index in it and its size
+    const uint32_t j0 = m - ((me.y >> 18) & 63), j1 = j0 + ((me.y >> 24) & 63);
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
+    // the group kind follows from the added positions (two alpha, two beta
+    // or one of each)
+    const int n_ = p.n;
+    const uint8_t type = CPLX ? (uint8_t)G_DOUBLE_S
+                              : (uint8_t)((Xi < n_ && Yi < n_) ? G_AA : (Xi >= n_ && Yi >= n_) ? G_BB : G_AB);
     const uint32_t negi = (me.y >> 16) & 1;
     const bool lay = (me.y >> 17) & 1;
     const DoubleIndex di = double_index<CPLX>(p, type, Xi, Yi, lay);

@@ -475,6 +475,12 @@ static mw_status build_groups(HostPlan &P)
                     const int lay = cx >= cy ? (ab ? 0 : 1) : (ab ? 1 : 0);
                     if (lay == 1) P.mem[mi].y |= 1u << 17;
                 }
+                // groups of fewer than 64 members: the member's index in the
+                // group (bits 18-23) and the group size (bits 24-29), so the
+                // kernels find the partners without the group tables; 0 in
+                // bits 24-29 marks a large group
+                if (k < 64)
+                    for (uint32_t t = 0; t < r.len; t++) P.mem[g0 + t].y |= (t << 18) | ((uint32_t)k << 24);
             }
             if (single) {
                 single_pairs[gi] = k * (k - 1);
