@@ -261,11 +261,16 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
         group_double_half<CPLX, RC>(p, mfirst, mend, lane, R, r0, c, partial);
         return;
     }
+    // small groups: the packet holds whole groups in decreasing size, so a
+    // member's partners are other lanes of this wave (their records come by
+    // shuffles) and the first group is the largest: every lane runs that
+    // many partner steps, so the shuffles see the whole wave
+    const uint32_t kmax = (p.mem[mfirst].y >> 24) & 63;
     const uint32_t m = mfirst + lane;
-    if (m >= mend) return;
-    const uint2 me = p.mem[m];
-    // small group: partners from the member's index in it and its size
-    const uint32_t j0 = m - ((me.y >> 18) & 63), j1 = j0 + ((me.y >> 24) & 63);
+    const bool live = m < mend;
+    const uint2 me = p.mem[live ? m : mfirst];
+    const uint32_t kk = live ? (me.y >> 24) & 63 : 0u;  // partners of this lane: steps [0, kk)
+    const int lane0 = lane - (int)((me.y >> 18) & 63);  // lane of its group's first member
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
     // the group kind follows from the added positions (two alpha, two beta
     // or one of each)
@@ -280,12 +285,16 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
 #pragma unroll
     for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
     const int nr = min(RC, R - r0);
-    for (uint32_t j = j0; j < j1; j += U) {
+    for (uint32_t t = 0; t < kmax; t += U) {
         uint2 o[U];
         bool hit[U];
         // all partner records first, then coefficients and integrals
 #pragma unroll
-        for (int u = 0; u < U; u++) o[u] = p.mem[j + u < j1 ? j + u : j0];
+        for (int u = 0; u < U; u++) {
+            const int src = t + u < kk ? lane0 + (int)(t + u) : lane;
+            o[u].x = (uint32_t)__shfl((int)me.x, src);
+            o[u].y = (uint32_t)__shfl((int)me.y, src);
+        }
         T v[U];
         T cj[U][RC];
 #pragma unroll
@@ -297,7 +306,7 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
-            hit[u] = j + u < j1 && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
+            hit[u] = t + u < kk && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
             v[u] = tab[hit[u] ? di.at(Xj, Yj) : 0u];
         }
 #pragma unroll
@@ -308,6 +317,7 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
             for (int k = 0; k < RC; k++) acc[k] = sc_add(acc[k], sc_mul(x, cj[u][k]));
         }
     }
+    if (!live) return;
     T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
