@@ -370,29 +370,63 @@ __device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave
                                                   typename Scal<CPLX>::T *__restrict__ partial)
 {
     using T = typename Scal<CPLX>::T;
-    const uint32_t m = p.pk_off[wave] + lane;
-    if (m >= p.pk_off[wave + 1]) return;
-    const uint32_t g = p.mem_grp[m];
-    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
-    const uint8_t type = p.grp_type[g];
-    const uint2 me = p.mem[m];
-    const int Xi = me.y & 255;
-    const uint32_t negi = (me.y >> 16) & 1;
-    const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
+    const uint32_t mfirst = p.pk_off[wave], mend = p.pk_off[wave + 1];
+    const uint32_t m = mfirst + lane;
     T acc[RC];
 #pragma unroll
     for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
     const int nr = min(RC, R - r0);
-    for (uint32_t j = j0; j < j1; j++) {
-        const uint2 o = p.mem[j];
-        const int Xj = o.y & 255;
-        if (Xj == Xi) continue;
-        T v = single_element<CPLX>(p, type, k0, k1, Xi, Xj);
-        v = sc_neg(v, (negi ^ ((o.y >> 16) & 1)) != 0);
-        const T *cj = c + (size_t)o.x * R + r0;
+    // size of the packet's first (largest) group; 0 marks a large group
+    const uint32_t kmax = (p.mem[mfirst].y >> 24) & 63;
+    if (kmax == 0) {
+        // a block of a large group: group tables, partner records from memory
+        if (m >= mend) return;
+        const uint32_t g = p.mem_grp[m];
+        const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
+        const uint8_t type = p.grp_type[g];
+        const uint2 me = p.mem[m];
+        const int Xi = me.y & 255;
+        const uint32_t negi = (me.y >> 16) & 1;
+        const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
+        for (uint32_t j = j0; j < j1; j++) {
+            const uint2 o = p.mem[j];
+            const int Xj = o.y & 255;
+            if (Xj == Xi) continue;
+            T v = single_element<CPLX>(p, type, k0, k1, Xi, Xj);
+            v = sc_neg(v, (negi ^ ((o.y >> 16) & 1)) != 0);
+            const T *cj = c + (size_t)o.x * R + r0;
 #pragma unroll
-        for (int k = 0; k < RC; k++)
-            if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
+            for (int k = 0; k < RC; k++)
+                if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
+        }
+    } else {
+        // whole small groups in decreasing size: partners are lanes of this
+        // wave (records by shuffles), K is the member's determinant without
+        // its added position, the kind follows from that position
+        const bool live = m < mend;
+        const uint2 me = p.mem[live ? m : mfirst];
+        const uint32_t kk = live ? (me.y >> 24) & 63 : 0u;
+        const int lane0 = lane - (int)((me.y >> 18) & 63);
+        const int Xi = me.y & 255;
+        const uint32_t negi = (me.y >> 16) & 1;
+        const int n = p.n;
+        uint64_t k0 = p.dets[2 * (size_t)me.x], k1 = p.dets[2 * (size_t)me.x + 1];
+        if (Xi < n) k0 &= ~(1ULL << Xi);
+        else k1 &= ~(1ULL << (Xi - n));
+        const uint8_t type = CPLX ? (uint8_t)G_SINGLE_S : (uint8_t)(Xi < n ? G_SINGLE_A : G_SINGLE_B);
+        for (uint32_t t = 0; t < kmax; t++) {
+            const int src = t < kk ? lane0 + (int)t : lane;
+            const uint32_t ox = (uint32_t)__shfl((int)me.x, src), oy = (uint32_t)__shfl((int)me.y, src);
+            const int Xj = oy & 255;
+            if (t >= kk || Xj == Xi) continue;
+            T v = single_element<CPLX>(p, type, k0, k1, Xi, Xj);
+            v = sc_neg(v, (negi ^ ((oy >> 16) & 1)) != 0);
+            const T *cj = c + (size_t)ox * R + r0;
+#pragma unroll
+            for (int k = 0; k < RC; k++)
+                if (k < nr) acc[k] = sc_add(acc[k], sc_mul(v, cj[k]));
+        }
+        if (!live) return;
     }
     T *out = partial + (size_t)m * R + r0;
 #pragma unroll

@@ -475,15 +475,20 @@ static mw_status build_groups(HostPlan &P)
                     const int lay = cx >= cy ? (ab ? 0 : 1) : (ab ? 1 : 0);
                     if (lay == 1) P.mem[mi].y |= 1u << 17;
                 }
-                // groups of fewer than 64 members: the member's index in the
-                // group (bits 18-23) and the group size (bits 24-29), so the
-                // kernels find the partners without the group tables; 0 in
-                // bits 24-29 marks a large group
+                // groups of fewer than 64 members (double and single): the
+                // member's index in the group (bits 18-23) and the group size
+                // (bits 24-29), so the kernels find the partners without the
+                // group tables; 0 in bits 24-29 marks a large group
                 if (k < 64)
                     for (uint32_t t = 0; t < r.len; t++) P.mem[g0 + t].y |= (t << 18) | ((uint32_t)k << 24);
             }
             if (single) {
                 single_pairs[gi] = k * (k - 1);
+                // as for double groups: index in the group and group size
+                if (k < 64) {
+                    const int64_t s0 = P.grp_off[gi];
+                    for (uint32_t t = 0; t < r.len; t++) P.mem[s0 + t].y |= (t << 18) | ((uint32_t)k << 24);
+                }
             } else {
                 int64_t dp = 0;
                 for (uint32_t t = 0; t < r.len; t++) {
