@@ -182,20 +182,28 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
         dacc[kk] = sc_zero(T());
     }
     const size_t colbase = (size_t)p.nmem + p.grp_col[g] + (size_t)a * k - 32 * (size_t)a * (a + 1);
-    for (uint32_t b = a; b < nb; b++) {
+    (void)nb;
+    // passes of JS partners over the blocks b >= a (64 is a multiple of JS,
+    // so a pass never straddles two blocks); the partner records of the next
+    // pass (wave-uniform) are loaded while this pass runs
+    uint2 onext[JS];
+#pragma unroll
+    for (int u = 0; u < JS; u++) onext[u] = p.mem[min(j0 + 64 * a + u, j1 - 1)];
+    for (uint32_t jj = j0 + 64 * a; jj < j1; jj += JS) {
+        const uint32_t b = (jj - j0) >> 6;
         const uint32_t jb0 = j0 + 64 * b, jb1 = min(j1, jb0 + 64);
-        for (uint32_t jj = jb0; jj < jb1; jj += JS) {
+        {
             T col[RS_NV];
             {
                 uint2 o[JS];
                 bool hit[JS];
                 T v[JS];
                 T cj[JS][RC];
-                // partner records first (wave-uniform addresses), then the
-                // coefficients (uniform, loaded whether or not a lane hits)
-                // and the integrals
 #pragma unroll
-                for (int u = 0; u < JS; u++) o[u] = p.mem[jj + u < jb1 ? jj + u : jb0];
+                for (int u = 0; u < JS; u++) {
+                    o[u] = onext[u];
+                    onext[u] = p.mem[min(jj + JS + u, j1 - 1)];
+                }
 #pragma unroll
                 for (int u = 0; u < JS; u++) {
                     const uint32_t j = jj + u;
