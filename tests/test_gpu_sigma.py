@@ -137,6 +137,47 @@ def test_sigma_roots_large_groups(torch, R):
         assert _rel(sk, s[:, k]) <= TOL, f"root {k}"
 
 
+def _spinor_fci_two(nk):
+    """Every determinant of two electrons over 2 nk spinors, ascending as
+    128-bit keys (word 0 major)."""
+    M = 2 * nk
+    d = []
+    for a in range(M):
+        for b in range(a + 1, M):
+            w = [0, 0]
+            for x in (a, b):
+                w[x // nk] |= 1 << (x % nk)
+            d.append((w[0], w[1]))
+    return np.array(sorted(d), dtype=np.uint64)
+
+
+def test_sigma_large_single_groups(torch):
+    """Single groups of 64 members and more, which are cut into 64-member
+    packets: n = 64 with one alpha and one beta electron (FCI, 4096
+    determinants; single groups of 64, one double group of 4096) with
+    integer integrals and coefficients, every row bit-exact; a two-electron
+    spinor FCI over 40 Kramers pairs (3160 determinants, single groups of 79),
+    every row within 1e-12."""
+    rng = np.random.default_rng(31)
+    n = 64
+    h, g = _integer_real(n, rng)
+    p = _prob("spinfree", n, 1, 1, synth.space_fci(n, 1, 1), h, g)
+    pl = _plan(p, max_roots=2)
+    c = rng.integers(-5, 6, size=(p.ndet, 2)).astype(float)
+    s = pl.sigma(_dev(torch, c)).cpu().numpy()
+    assert np.array_equal(s, sc.sigma(p, c))
+    nk = 40
+    rs = np.random.default_rng(32)
+    q = _prob("spinor", nk, 2, -1, _spinor_fci_two(nk), synth.one_body_spinor(nk, rs), synth.two_body_spinor(nk, rs))
+    assert q.ndet == 3160
+    plq = _plan(q)
+    cq = synth.ci_vectors(q.ndet, 1, np.random.default_rng(33), complex_=True)[:, 0]
+    sq = plq.sigma(_dev(torch, cq)).cpu().numpy()
+    ref = sc.sigma(q, cq)
+    _say("spinor large singles rel", _rel(sq, ref))
+    assert _rel(sq, ref) <= TOL
+
+
 def test_sigma_reproducible_bits(torch):
     p = synth.workload(0)
     pl = _plan(p)
