@@ -153,3 +153,28 @@ def test_batched_rejects_bad_arguments(torch, batch):
     probs, plans, cs, R = batch
     with pytest.raises(mw.MWError):
         mw.sigma_batched([plans[0], plans[0]], [cs[0], cs[0]])
+
+
+def test_batched_full_workload_sampled(torch):
+    """The sixteen problems of the batch recipe at full size (2.1 million
+    determinants, four roots each) in the configuration the benchmark times:
+    tuned batched launch replayed from its graph; sampled rows of every
+    problem against the oracle, and equal to the tuned graph's own replay."""
+    from paper_2501_18185_amd import mw
+    probs = [synth.workload(3, i) for i in range(16)]
+    plans = [mw.Plan(p, max_roots=4) for p in probs]
+    R = 4
+    cs = [torch.from_numpy(synth.ci_vectors(p.ndet, R, synth.rng_for(3, i, synth.SEED_C))).cuda()
+          for i, p in enumerate(probs)]
+    outs = [torch.empty_like(c) for c in cs]
+    mw.autotune_batched(plans, cs, outs)
+    mw.sigma_batched(plans, cs, outs)
+    first = [o.cpu().numpy().copy() for o in outs]
+    mw.sigma_batched(plans, cs, outs)
+    rng = np.random.default_rng(15)
+    for i, (p, c, o) in enumerate(zip(probs, cs, outs)):
+        got = o.cpu().numpy()
+        assert np.array_equal(got, first[i]), f"replay {i}"
+        rows = np.unique(np.concatenate([[0, p.ndet - 1], rng.choice(p.ndet, 6, replace=False)]))
+        ref = sc.sigma(p, c.cpu().numpy(), rows=rows)
+        assert _rel(got[rows], ref) <= 1e-12, f"problem {i}"

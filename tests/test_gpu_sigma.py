@@ -293,3 +293,19 @@ def test_sigma_selected_n64_sampled(torch):
     ci = np.random.default_rng(13).integers(-3, 4, size=p.ndet).astype(float)
     si = pl.sigma(_dev(torch, ci)).cpu().numpy()
     assert np.array_equal(si[rows], sc.sigma(pi, ci, rows=rows))
+
+
+def test_sigma_spinor_full_sampled(torch):
+    """Complex spinor space of the 40-pair N=20 recipe, 1,000,000
+    determinants, in the default launch configuration that the benchmark
+    times; sampled rows (first, last, random) against the oracle."""
+    p = synth.workload(2)
+    _say("space", p.ndet)
+    pl = _plan(p)
+    c = synth.ci_vectors(p.ndet, 1, synth.rng_for(2, 0, synth.SEED_C), complex_=True)
+    s = pl.sigma(_dev(torch, c)).cpu().numpy()
+    rng = np.random.default_rng(14)
+    rows = np.unique(np.concatenate([np.arange(6), rng.choice(p.ndet, 30, replace=False), [p.ndet - 1]]))
+    ref = sc.sigma(p, c, rows=rows)
+    _say("rel err sampled", _rel(s[rows], ref))
+    assert _rel(s[rows], ref) <= TOL
