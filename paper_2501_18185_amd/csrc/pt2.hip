@@ -41,7 +41,8 @@ namespace mw {
 
 namespace {
 
-constexpr int PT2_CAP = 1024;      // records of a bucket sorted by the common kernel (26 KB LDS)
+constexpr int PT2_WCAP = 512;      // records of a bucket sorted by one wave in registers
+constexpr int PT2_CAP = 1024;      // records of a bucket sorted by the block kernel (26 KB LDS)
 constexpr int PT2_CAP_BIG = 4096;  // oversized buckets (rare): a kernel with 104 KB LDS
 constexpr int PT2_MEAN = 400;      // target records per bucket
 constexpr int PT2_MAXR = 8;        // roots per call
@@ -523,6 +524,181 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
     }
 }
 
+// One wave per bucket of at most PT2_WCAP records (four buckets per block):
+// the records are sorted in registers by a bitonic network over one 64-bit
+// key (23 hash bits of A, then J, then the record's index), E = 1, 2, 4 or
+// 8 keys per lane at positions lane * E + r, exchanged between lanes by
+// shuffles.  The sorted keys go to LDS (one barrier) and each lane takes the
+// runs that start at its positions, as the block kernel does; the energy and
+// the counts of the bucket are summed over the wave by a fixed butterfly.
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src), hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[8], int lane)
+{
+    constexpr int N = 64 * E;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+#pragma unroll
+                for (int q = 0; q < E; q++) {
+                    const int pq = q ^ j;
+                    if (pq > q) {
+                        const bool up = (((lane * E + q) & k) == 0);
+                        const uint64_t x = v[q], y = v[pq];
+                        if ((x > y) == up) {
+                            v[q] = y;
+                            v[pq] = x;
+                        }
+                    }
+                }
+            } else {
+                const int lj = j / E;
+                const bool lower = (lane & lj) == 0;
+#pragma unroll
+                for (int q = 0; q < E; q++) {
+                    const uint64_t o = shfl64(v[q], lane ^ lj);
+                    const bool up = (((lane * E + q) & k) == 0);
+                    v[q] = (lower == up) ? (v[q] < o ? v[q] : o) : (v[q] > o ? v[q] : o);
+                }
+            }
+        }
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uint32_t b0, int64_t nb,
+                                                         const uint32_t *__restrict__ cnt,
+                                                         const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
+                                                         const typename Scal<CPLX>::T *__restrict__ val,
+                                                         double *__restrict__ part,
+                                                         unsigned long long *__restrict__ partc, int64_t boff)
+{
+    using T = typename Scal<CPLX>::T;
+    __shared__ uint64_t sk[4][PT2_WCAP];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t bi = boff + (int64_t)blockIdx.x * 4 + wv;  // wave-uniform
+    const uint32_t b = b0 + (uint32_t)(bi < nb ? bi : 0);
+    const int m = bi < nb ? (int)cnt[b] : 0;
+    const bool mine = bi < nb && m <= PT2_WCAP;  // larger buckets go to the block kernels
+    const uint64_t base = mine ? off[b] : 0;
+    if (mine) {
+        int E = 1;
+        while (64 * E < m) E <<= 1;
+        uint64_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int i = lane * E + q;
+            v[q] = ~0ULL;
+            if (q < E && i < m) {
+                const uint64_t key = rec[base + i].key;
+                v[q] = (((key >> 32) & 0x7FFFFFULL) << 41) | ((key & 0xFFFFFFFFULL) << 9) | (uint64_t)i;
+            }
+        }
+        if (E == 1) wave_bitonic<1>(v, lane);
+        else if (E == 2) wave_bitonic<2>(v, lane);
+        else if (E == 4) wave_bitonic<4>(v, lane);
+        else wave_bitonic<8>(v, lane);
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (q < E) sk[wv][lane * E + q] = v[q];
+    }
+    __syncthreads();
+    if (!mine) return;
+    double acc[PT2_MAXR];
+#pragma unroll
+    for (int k = 0; k < PT2_MAXR; k++) acc[k] = 0.0;
+    uint32_t kept = 0, nq = 0;
+    const uint64_t *s = sk[wv];
+    auto hib = [](uint64_t x) { return (uint32_t)(x >> 41); };
+    auto ridx = [](uint64_t x) { return (int)(x & 511); };
+    // |sum over the records of run [i, e) whose A is (a0, a1), in run order
+    // (ascending J)|^2 / (E0 - H_AA), H_AA from the first of them
+    auto add_a = [&](int i, int e, uint64_t a0, uint64_t a1) {
+        T num[PT2_MAXR];
+#pragma unroll
+        for (int k = 0; k < PT2_MAXR; k++) num[k] = sc_zero(T());
+        int first = -1;
+        for (int u = i; u < e; u++) {
+            const int ru = ridx(s[u]);
+            const Rec &x = rec[base + ru];
+            if (x.a0 != a0 || x.a1 != a1) continue;
+            if (first < 0) first = ru;
+            const T *vv = val + (base + ru) * R;
+#pragma unroll
+            for (int k = 0; k < PT2_MAXR; k++)
+                if (k < R) num[k] = sc_add(num[k], vv[k]);
+            kept++;
+        }
+        nq++;
+        const double haa = rec[base + first].haa;
+#pragma unroll
+        for (int k = 0; k < PT2_MAXR; k++) {
+            if (k >= R) continue;
+            double q;
+            if constexpr (CPLX) q = num[k].x * num[k].x + num[k].y * num[k].y;
+            else q = num[k] * num[k];
+            acc[k] += q / (roots.e0[k] - haa);
+        }
+    };
+    for (int i = lane; i < m; i += 64) {
+        const uint32_t h = hib(s[i]);
+        if (i > 0 && hib(s[i - 1]) == h) continue;  // not the first record of its run
+        int e = i + 1;
+        while (e < m && hib(s[e]) == h) e++;
+        const Rec &f0 = rec[base + ridx(s[i])];
+        uint64_t c0 = f0.a0, c1 = f0.a1;
+        bool multi = false;
+        for (int u = i + 1; u < e && !multi; u++) {
+            const Rec &x = rec[base + ridx(s[u])];
+            multi = x.a0 != c0 || x.a1 != c1;
+        }
+        // several A in the run: each in ascending (a0, a1)
+        bool have = false;
+        for (;;) {
+            if (multi) {
+                bool found = false;
+                uint64_t n0 = 0, n1 = 0;
+                for (int u = i; u < e; u++) {
+                    const Rec &x = rec[base + ridx(s[u])];
+                    if (have && (x.a0 < c0 || (x.a0 == c0 && x.a1 <= c1))) continue;
+                    if (!found || x.a0 < n0 || (x.a0 == n0 && x.a1 < n1)) { n0 = x.a0; n1 = x.a1; found = true; }
+                }
+                if (!found) break;
+                c0 = n0;
+                c1 = n1;
+            }
+            add_a(i, e, c0, c1);
+            have = true;
+            if (!multi) break;
+        }
+    }
+    // fixed butterfly over the wave
+#pragma unroll
+    for (int k = 0; k < PT2_MAXR; k++) {
+        if (k >= R) continue;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kept += (uint32_t)__shfl_xor((int)kept, o);
+        nq += (uint32_t)__shfl_xor((int)nq, o);
+    }
+    if (lane == 0) {
+        const uint64_t slot = (uint64_t)bi;
+        for (int k = 0; k < R; k++) part[slot * R + k] = acc[k];
+        partc[2 * slot] = kept;
+        partc[2 * slot + 1] = nq;
+    }
+}
+
 // Fixed-order sums over the nb buckets of a pass in two stages: block g of
 // k_pt2_sum1 reduces buckets [g*chunk, (g+1)*chunk) into tmp[g][R + 2]
 // (R energies, then the two counts as doubles-free integers); k_pt2_sum2
@@ -867,6 +1043,19 @@ void launch_bucket(int64_t nblocks, int R, const Roots &roots, uint32_t b0, cons
 }
 
 template <bool CPLX>
+void launch_bucket_wave(int64_t nb, int R, const Roots &roots, uint32_t b0, const uint32_t *cnt, const uint64_t *off,
+                        const Rec *rec, const typename Scal<CPLX>::T *val, double *part, unsigned long long *partc,
+                        hipStream_t s)
+{
+    const int64_t nblocks = (nb + 3) / 4;
+    for (int64_t o = 0; o < nblocks; o += PT2_MAXGRID) {
+        const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, nblocks - o);
+        hipLaunchKernelGGL((k_pt2_bucket_wave<CPLX>), dim3(g), dim3(256), 0, s, R, roots, b0, nb, cnt, off, rec, val,
+                           part, partc, o * 4);
+    }
+}
+
+template <bool CPLX>
 mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, double qmin, void *work,
                 size_t work_bytes, double *e2, int64_t *stats, hipStream_t s)
 {
@@ -979,17 +1168,24 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
                     launch_enum<CPLX, 2>(d, ex, inP, R, c, qmin, lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, rec,
                                          val, eps, vg, nullptr, s);
                     prof_end(t, s);
-                    // oversized buckets of this pass go to the larger instance
+                    // buckets of this pass: up to PT2_WCAP records one wave
+                    // each; larger ones, listed, to the block kernels
                     std::vector<uint32_t> hb;
+                    for (int64_t b = b0; b < b1; b++)
+                        if (hc[b] > (uint32_t)PT2_WCAP && hc[b] <= (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
+                    const int64_t nmid = (int64_t)hb.size();
                     for (int64_t b = b0; b < b1; b++)
                         if (hc[b] > (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
                     t = prof_begin("pt2_bucket", s);
-                    launch_bucket<CPLX, PT2_CAP>(b1 - b0, R, roots, (uint32_t)b0, nullptr, cnt, off, rec, val, part,
-                                                 partc, s);
+                    launch_bucket_wave<CPLX>(b1 - b0, R, roots, (uint32_t)b0, cnt, off, rec, val, part, partc, s);
                     if (!hb.empty()) {
                         hipMemcpyAsync(big, hb.data(), 4 * hb.size(), hipMemcpyHostToDevice, s);
-                        launch_bucket<CPLX, PT2_CAP_BIG>((int64_t)hb.size(), R, roots, (uint32_t)b0, big, cnt, off, rec,
-                                                         val, part, partc, s);
+                        if (nmid)
+                            launch_bucket<CPLX, PT2_CAP>(nmid, R, roots, (uint32_t)b0, big, cnt, off, rec, val, part,
+                                                         partc, s);
+                        if ((int64_t)hb.size() > nmid)
+                            launch_bucket<CPLX, PT2_CAP_BIG>((int64_t)hb.size() - nmid, R, roots, (uint32_t)b0,
+                                                             big + nmid, cnt, off, rec, val, part, partc, s);
                     }
                     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: pass launch failed");
                     prof_end(t, s);
