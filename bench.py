@@ -340,6 +340,10 @@ def leg_batched():
             "plain_16x4_default_ms": t_plain4_default, "plain_16x4_tuned_ms": t_plain4_tuned,
             "plain_64x1_ms": t_plain1,
             "batched_terms_per_s": terms / (t_batched * 1e-3),
+            # algorithmic bytes of the whole batch: per connected pair one
+            # integral word and the partner's R coefficients
+            "batched_algorithmic_GBps": pairs * (8 * R + 8) / (t_batched * 1e-3) / 1e9,
+            "batched_hbm_frac": pairs * (8 * R + 8) / (t_batched * 1e-3) / (HBM_PEAK_GBS * 1e9),
             "speedup_vs_16x4": t_plain4 / t_batched, "speedup_vs_64x1": t_plain1 / t_batched}
 
 
