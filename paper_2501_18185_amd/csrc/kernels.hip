@@ -160,7 +160,6 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
     const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
     const uint32_t k = j1 - j0;
     const uint32_t a = (mfirst - j0) >> 6;
-    const uint32_t nb = (k + 63) >> 6;
     const uint8_t type = p.grp_type[g];
     const uint32_t m = mfirst + lane;
     const bool act = m < mend;
@@ -182,7 +181,6 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
         dacc[kk] = sc_zero(T());
     }
     const size_t colbase = (size_t)p.nmem + p.grp_col[g] + (size_t)a * k - 32 * (size_t)a * (a + 1);
-    (void)nb;
     // passes of JS partners over the blocks b >= a (64 is a multiple of JS,
     // so a pass never straddles two blocks); the partner records of the next
     // pass (wave-uniform) are loaded while this pass runs
