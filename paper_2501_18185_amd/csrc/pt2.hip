@@ -528,9 +528,10 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
 // the records are sorted in registers by a bitonic network over one 64-bit
 // key (23 hash bits of A, then J, then the record's index), E = 1, 2, 4 or
 // 8 keys per lane at positions lane * E + r, exchanged between lanes by
-// shuffles.  The sorted keys go to LDS (one barrier) and each lane takes the
-// runs that start at its positions, as the block kernel does; the energy and
-// the counts of the bucket are summed over the wave by a fixed butterfly.
+// shuffles.  The sorted keys go to LDS (one barrier); the runs are then
+// reduced across the wave's lanes (below), so a long run of a much-connected
+// external determinant does not serialise one lane; the energy and the
+// counts of the bucket are summed over the wave by a fixed butterfly.
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
 {
     const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src), hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
@@ -647,37 +648,123 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
             acc[k] += q / (roots.e0[k] - haa);
         }
     };
-    for (int i = lane; i < m; i += 64) {
-        const uint32_t h = hib(s[i]);
-        if (i > 0 && hib(s[i - 1]) == h) continue;  // not the first record of its run
-        int e = i + 1;
-        while (e < m && hib(s[e]) == h) e++;
-        const Rec &f0 = rec[base + ridx(s[i])];
-        uint64_t c0 = f0.a0, c1 = f0.a1;
-        bool multi = false;
-        for (int u = i + 1; u < e && !multi; u++) {
-            const Rec &x = rec[base + ridx(s[u])];
-            multi = x.a0 != c0 || x.a1 != c1;
+    // Runs by a segmented reduction over the sorted positions, 64 per round
+    // (lane = position - t0): the values of a run, its length, the H_AA of
+    // its first record, its first position and whether any record has
+    // another A than the one before it are combined left to right by a fixed
+    // butterfly, and the state of the run still open at the end of a round
+    // carries into the next.  A run of one A then adds its term at its last
+    // position; the rare run shared by several A takes the serial path.
+    auto shT = [](T x, int src) {
+        if constexpr (CPLX) return make_double2(__shfl(x.x, src), __shfl(x.y, src));
+        else return __shfl(x, src);
+    };
+    T cs[PT2_MAXR];
+#pragma unroll
+    for (int k = 0; k < PT2_MAXR; k++) cs[k] = sc_zero(T());
+    uint32_t ccnt = 0;
+    double chaa = 0.0;
+    int chead = 0, cmul = 0;
+    uint64_t ca0 = 0, ca1 = 0;
+    for (int t0 = 0; t0 < m; t0 += 64) {
+        const int p = t0 + lane;
+        const bool act = p < m;
+        const uint64_t key = act ? s[p] : 0;
+        T x[PT2_MAXR];
+#pragma unroll
+        for (int k = 0; k < PT2_MAXR; k++) x[k] = sc_zero(T());
+        uint64_t a0 = 0, a1 = 0;
+        double hh = 0.0;
+        if (act) {
+            const uint64_t ri = base + (uint64_t)ridx(key);
+            a0 = rec[ri].a0;
+            a1 = rec[ri].a1;
+            hh = rec[ri].haa;
+#pragma unroll
+            for (int k = 0; k < PT2_MAXR; k++)
+                if (k < R) x[k] = val[ri * R + k];
         }
-        // several A in the run: each in ascending (a0, a1)
-        bool have = false;
-        for (;;) {
-            if (multi) {
-                bool found = false;
-                uint64_t n0 = 0, n1 = 0;
-                for (int u = i; u < e; u++) {
-                    const Rec &x = rec[base + ridx(s[u])];
-                    if (have && (x.a0 < c0 || (x.a0 == c0 && x.a1 <= c1))) continue;
-                    if (!found || x.a0 < n0 || (x.a0 == n0 && x.a1 < n1)) { n0 = x.a0; n1 = x.a1; found = true; }
-                }
-                if (!found) break;
-                c0 = n0;
-                c1 = n1;
+        const uint64_t u0 = shfl64(a0, lane ? lane - 1 : 0), u1 = shfl64(a1, lane ? lane - 1 : 0);
+        const uint64_t pa0 = lane ? u0 : ca0, pa1 = lane ? u1 : ca1;
+        const bool head = act && (p == 0 || hib(s[p - 1]) != hib(key));
+        int mul = (act && !head && (a0 != pa0 || a1 != pa1)) ? 1 : 0;
+        uint32_t cn = act ? 1u : 0u;
+        int hp = p;
+        if (lane == 0 && act && !head) {
+            // the run began in an earlier round: fold in its state
+#pragma unroll
+            for (int k = 0; k < PT2_MAXR; k++) x[k] = sc_add(cs[k], x[k]);
+            cn += ccnt;
+            hh = chaa;
+            hp = chead;
+            mul |= cmul;
+        }
+        int fl = (head || lane == 0 || !act) ? 1 : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int src = lane >= d ? lane - d : lane;
+            T xu[PT2_MAXR];
+#pragma unroll
+            for (int k = 0; k < PT2_MAXR; k++)
+                if (k < R) xu[k] = shT(x[k], src);
+            const int fu = __shfl(fl, src), mu = __shfl(mul, src), hpu = __shfl(hp, src);
+            const uint32_t cu = (uint32_t)__shfl((int)cn, src);
+            const double hu = __shfl(hh, src);
+            if (lane >= d && !fl) {
+#pragma unroll
+                for (int k = 0; k < PT2_MAXR; k++)
+                    if (k < R) x[k] = sc_add(xu[k], x[k]);
+                cn += cu;
+                hh = hu;
+                hp = hpu;
+                mul |= mu;
+                fl = fu;
             }
-            add_a(i, e, c0, c1);
-            have = true;
-            if (!multi) break;
         }
+        const bool last = act && (p == m - 1 || hib(s[p + 1]) != hib(key));
+        if (last) {
+            if (!mul) {
+#pragma unroll
+                for (int k = 0; k < PT2_MAXR; k++) {
+                    if (k >= R) continue;
+                    double q;
+                    if constexpr (CPLX) q = x[k].x * x[k].x + x[k].y * x[k].y;
+                    else q = x[k] * x[k];
+                    acc[k] += q / (roots.e0[k] - hh);
+                }
+                kept += cn;
+                nq++;
+            } else {
+                // several A in the run [hp, p]: each in ascending (a0, a1)
+                const int i = hp, e = p + 1;
+                bool have = false;
+                uint64_t c0 = 0, c1 = 0;
+                for (;;) {
+                    bool found = false;
+                    uint64_t n0 = 0, n1 = 0;
+                    for (int u = i; u < e; u++) {
+                        const Rec &y = rec[base + ridx(s[u])];
+                        if (have && (y.a0 < c0 || (y.a0 == c0 && y.a1 <= c1))) continue;
+                        if (!found || y.a0 < n0 || (y.a0 == n0 && y.a1 < n1)) { n0 = y.a0; n1 = y.a1; found = true; }
+                    }
+                    if (!found) break;
+                    c0 = n0;
+                    c1 = n1;
+                    add_a(i, e, c0, c1);
+                    have = true;
+                }
+            }
+        }
+        // state of the run open at the end of this round
+#pragma unroll
+        for (int k = 0; k < PT2_MAXR; k++)
+            if (k < R) cs[k] = shT(x[k], 63);
+        ccnt = (uint32_t)__shfl((int)cn, 63);
+        chaa = __shfl(hh, 63);
+        chead = __shfl(hp, 63);
+        cmul = __shfl(mul, 63);
+        ca0 = shfl64(a0, 63);
+        ca1 = shfl64(a1, 63);
     }
     // fixed butterfly over the wave
 #pragma unroll
