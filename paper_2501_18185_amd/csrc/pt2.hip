@@ -573,7 +573,7 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&v)[8], int lane)
     }
 }
 
-template <bool CPLX>
+template <bool CPLX, int RM>
 __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uint32_t b0, int64_t nb,
                                                          const uint32_t *__restrict__ cnt,
                                                          const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
@@ -612,9 +612,9 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
     }
     __syncthreads();
     if (!mine) return;
-    double acc[PT2_MAXR];
+    double acc[RM];
 #pragma unroll
-    for (int k = 0; k < PT2_MAXR; k++) acc[k] = 0.0;
+    for (int k = 0; k < RM; k++) acc[k] = 0.0;
     uint32_t kept = 0, nq = 0;
     const uint64_t *s = sk[wv];
     auto hib = [](uint64_t x) { return (uint32_t)(x >> 41); };
@@ -622,9 +622,9 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
     // |sum over the records of run [i, e) whose A is (a0, a1), in run order
     // (ascending J)|^2 / (E0 - H_AA), H_AA from the first of them
     auto add_a = [&](int i, int e, uint64_t a0, uint64_t a1) {
-        T num[PT2_MAXR];
+        T num[RM];
 #pragma unroll
-        for (int k = 0; k < PT2_MAXR; k++) num[k] = sc_zero(T());
+        for (int k = 0; k < RM; k++) num[k] = sc_zero(T());
         int first = -1;
         for (int u = i; u < e; u++) {
             const int ru = ridx(s[u]);
@@ -633,14 +633,14 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
             if (first < 0) first = ru;
             const T *vv = val + (base + ru) * R;
 #pragma unroll
-            for (int k = 0; k < PT2_MAXR; k++)
+            for (int k = 0; k < RM; k++)
                 if (k < R) num[k] = sc_add(num[k], vv[k]);
             kept++;
         }
         nq++;
         const double haa = rec[base + first].haa;
 #pragma unroll
-        for (int k = 0; k < PT2_MAXR; k++) {
+        for (int k = 0; k < RM; k++) {
             if (k >= R) continue;
             double q;
             if constexpr (CPLX) q = num[k].x * num[k].x + num[k].y * num[k].y;
@@ -659,9 +659,9 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         if constexpr (CPLX) return make_double2(__shfl(x.x, src), __shfl(x.y, src));
         else return __shfl(x, src);
     };
-    T cs[PT2_MAXR];
+    T cs[RM];
 #pragma unroll
-    for (int k = 0; k < PT2_MAXR; k++) cs[k] = sc_zero(T());
+    for (int k = 0; k < RM; k++) cs[k] = sc_zero(T());
     uint32_t ccnt = 0;
     double chaa = 0.0;
     int chead = 0, cmul = 0;
@@ -670,9 +670,9 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         const int p = t0 + lane;
         const bool act = p < m;
         const uint64_t key = act ? s[p] : 0;
-        T x[PT2_MAXR];
+        T x[RM];
 #pragma unroll
-        for (int k = 0; k < PT2_MAXR; k++) x[k] = sc_zero(T());
+        for (int k = 0; k < RM; k++) x[k] = sc_zero(T());
         uint64_t a0 = 0, a1 = 0;
         double hh = 0.0;
         if (act) {
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
             a1 = rec[ri].a1;
             hh = rec[ri].haa;
 #pragma unroll
-            for (int k = 0; k < PT2_MAXR; k++)
+            for (int k = 0; k < RM; k++)
                 if (k < R) x[k] = val[ri * R + k];
         }
         const uint64_t u0 = shfl64(a0, lane ? lane - 1 : 0), u1 = shfl64(a1, lane ? lane - 1 : 0);
@@ -693,7 +693,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         if (lane == 0 && act && !head) {
             // the run began in an earlier round: fold in its state
 #pragma unroll
-            for (int k = 0; k < PT2_MAXR; k++) x[k] = sc_add(cs[k], x[k]);
+            for (int k = 0; k < RM; k++) x[k] = sc_add(cs[k], x[k]);
             cn += ccnt;
             hh = chaa;
             hp = chead;
@@ -703,16 +703,16 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int src = lane >= d ? lane - d : lane;
-            T xu[PT2_MAXR];
+            T xu[RM];
 #pragma unroll
-            for (int k = 0; k < PT2_MAXR; k++)
+            for (int k = 0; k < RM; k++)
                 if (k < R) xu[k] = shT(x[k], src);
             const int fu = __shfl(fl, src), mu = __shfl(mul, src), hpu = __shfl(hp, src);
             const uint32_t cu = (uint32_t)__shfl((int)cn, src);
             const double hu = __shfl(hh, src);
             if (lane >= d && !fl) {
 #pragma unroll
-                for (int k = 0; k < PT2_MAXR; k++)
+                for (int k = 0; k < RM; k++)
                     if (k < R) x[k] = sc_add(xu[k], x[k]);
                 cn += cu;
                 hh = hu;
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         if (last) {
             if (!mul) {
 #pragma unroll
-                for (int k = 0; k < PT2_MAXR; k++) {
+                for (int k = 0; k < RM; k++) {
                     if (k >= R) continue;
                     double q;
                     if constexpr (CPLX) q = x[k].x * x[k].x + x[k].y * x[k].y;
@@ -757,7 +757,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         }
         // state of the run open at the end of this round
 #pragma unroll
-        for (int k = 0; k < PT2_MAXR; k++)
+        for (int k = 0; k < RM; k++)
             if (k < R) cs[k] = shT(x[k], 63);
         ccnt = (uint32_t)__shfl((int)cn, 63);
         chaa = __shfl(hh, 63);
@@ -768,7 +768,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
     }
     // fixed butterfly over the wave
 #pragma unroll
-    for (int k = 0; k < PT2_MAXR; k++) {
+    for (int k = 0; k < RM; k++) {
         if (k >= R) continue;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
@@ -1137,8 +1137,13 @@ void launch_bucket_wave(int64_t nb, int R, const Roots &roots, uint32_t b0, cons
     const int64_t nblocks = (nb + 3) / 4;
     for (int64_t o = 0; o < nblocks; o += PT2_MAXGRID) {
         const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, nblocks - o);
-        hipLaunchKernelGGL((k_pt2_bucket_wave<CPLX>), dim3(g), dim3(256), 0, s, R, roots, b0, nb, cnt, off, rec, val,
-                           part, partc, o * 4);
+        // one root: arrays of one slot (fewer registers, more waves)
+        if (R == 1)
+            hipLaunchKernelGGL((k_pt2_bucket_wave<CPLX, 1>), dim3(g), dim3(256), 0, s, R, roots, b0, nb, cnt, off, rec,
+                               val, part, partc, o * 4);
+        else
+            hipLaunchKernelGGL((k_pt2_bucket_wave<CPLX, PT2_MAXR>), dim3(g), dim3(256), 0, s, R, roots, b0, nb, cnt, off,
+                               rec, val, part, partc, o * 4);
     }
 }
 
