@@ -41,7 +41,7 @@ namespace mw {
 
 namespace {
 
-constexpr int PT2_WCAP = 512;      // records of a bucket sorted by one wave in registers
+constexpr int PT2_WCAP = 1024;     // records of a bucket sorted by one wave in registers
 constexpr int PT2_CAP = 1024;      // records of a bucket sorted by the block kernel (26 KB LDS)
 constexpr int PT2_CAP_BIG = 4096;  // oversized buckets (rare): a kernel with 104 KB LDS
 constexpr int PT2_MEAN = 400;      // target records per bucket
@@ -526,8 +526,8 @@ __global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t
 
 // One wave per bucket of at most PT2_WCAP records (four buckets per block):
 // the records are sorted in registers by a bitonic network over one 64-bit
-// key (23 hash bits of A, then J, then the record's index), E = 1, 2, 4 or
-// 8 keys per lane at positions lane * E + r, exchanged between lanes by
+// key (22 hash bits of A, then J, then the record's index), E = 1, 2, 4, 8
+// or 16 keys per lane at positions lane * E + r, exchanged between lanes by
 // shuffles.  The sorted keys go to LDS (one barrier); the runs are then
 // reduced across the wave's lanes (below), so a long run of a much-connected
 // external determinant does not serialise one lane; the energy and the
@@ -539,7 +539,7 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
 }
 
 template <int E>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[8], int lane)
+__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[16], int lane)
 {
     constexpr int N = 64 * E;
 #pragma unroll
@@ -592,22 +592,23 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
     if (mine) {
         int E = 1;
         while (64 * E < m) E <<= 1;
-        uint64_t v[8];
+        uint64_t v[16];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
+        for (int q = 0; q < 16; q++) {
             const int i = lane * E + q;
             v[q] = ~0ULL;
             if (q < E && i < m) {
                 const uint64_t key = rec[base + i].key;
-                v[q] = (((key >> 32) & 0x7FFFFFULL) << 41) | ((key & 0xFFFFFFFFULL) << 9) | (uint64_t)i;
+                v[q] = (((key >> 32) & 0x3FFFFFULL) << 42) | ((key & 0xFFFFFFFFULL) << 10) | (uint64_t)i;
             }
         }
         if (E == 1) wave_bitonic<1>(v, lane);
         else if (E == 2) wave_bitonic<2>(v, lane);
         else if (E == 4) wave_bitonic<4>(v, lane);
-        else wave_bitonic<8>(v, lane);
+        else if (E == 8) wave_bitonic<8>(v, lane);
+        else wave_bitonic<16>(v, lane);
 #pragma unroll
-        for (int q = 0; q < 8; q++)
+        for (int q = 0; q < 16; q++)
             if (q < E) sk[wv][lane * E + q] = v[q];
     }
     __syncthreads();
@@ -617,8 +618,8 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
     for (int k = 0; k < RM; k++) acc[k] = 0.0;
     uint32_t kept = 0, nq = 0;
     const uint64_t *s = sk[wv];
-    auto hib = [](uint64_t x) { return (uint32_t)(x >> 41); };
-    auto ridx = [](uint64_t x) { return (int)(x & 511); };
+    auto hib = [](uint64_t x) { return (uint32_t)(x >> 42); };
+    auto ridx = [](uint64_t x) { return (int)(x & 1023); };
     // |sum over the records of run [i, e) whose A is (a0, a1), in run order
     // (ascending J)|^2 / (E0 - H_AA), H_AA from the first of them
     auto add_a = [&](int i, int e, uint64_t a0, uint64_t a1) {
