@@ -1357,14 +1357,12 @@ mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, do
                                b0, b1, cnt, off, fill, keys, (const double *)eps, (const double *)vg, tot, j);
         }
     };
-    hipMemsetAsync(tot, 0, 8, s);
-    enumerate(std::integral_constant<int, 0>(), 0, 0u, 0u, nullptr, nullptr, nullptr, nullptr);
-    unsigned long long T_ = 0;
-    if (hipMemcpyAsync(&T_, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-        return fail(MW_EHIP, "select: counting pass failed");
-    if (T_ == 0) return MW_OK;
-    int lognb = 0;
-    while (((uint64_t)PT2_MEAN << lognb) < T_ && lognb < 40) lognb++;
+    // bucket count: 16 per determinant of the space to start with; the
+    // per-bucket counting pass also gives the total, and when a bucket holds
+    // more than the sort takes the count is redone with buckets sized from
+    // that total (no separate counting pass in the usual case)
+    int lognb = 10;
+    while (((int64_t)1 << lognb) < d.ndet * 16 && lognb < 24) lognb++;
     const size_t fixed = used;
     std::vector<uint32_t> hc, hu;
     for (;;) {
@@ -1384,9 +1382,14 @@ mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, do
         if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return fail(MW_EHIP, "select: bucket counting failed");
+        uint64_t T_ = 0;
+        for (uint32_t x : hc) T_ += x;
+        if (T_ == 0) return MW_OK;
         if (*std::max_element(hc.begin(), hc.end()) > (uint32_t)PT2_CAP_BIG) {
             if (lognb >= 34) return fail(MW_EUNSUPPORTED, "select: a determinant is selected from too many partners");
-            lognb++;
+            int want = lognb + 1;
+            while (((uint64_t)PT2_MEAN << want) < T_ && want < 34) want++;
+            lognb = want;
             continue;
         }
         const uint64_t cap = (work_bytes - used - 512) / sizeof(ulonglong2);
