@@ -6,18 +6,24 @@
 // (N-2)-electron string K; members of a group are K plus an added position
 // (single groups) or an added pair (double groups).
 //
-//  k_group_sigma  (one wave per packet of <= 64 consecutive members; lane =
-//                  member i, loop over the members j of i's group):
+//  k_group_double, k_group_single (one wave per packet of <= 64 consecutive
+//                  members; lane = member i, loop over the members j of i's
+//                  group):
 //      partial_i += H_ij c_j   for every j connected to i in this group,
 //      H_ij = phi_i phi_j A(pair_i, pair_j) (doubles) or phi_i phi_j F^K
 //      (singles).  The integral is read through Hermiticity as the entry
 //      (row = j, column = i) and conjugated, so that for a fixed j the lanes
-//      of a wave read consecutive columns of one row.  No atomics.
+//      of a wave read consecutive columns of one row.  Small groups are
+//      packed whole, so their partners are lanes of the same wave (records
+//      by shuffles); large groups are cut into 64-member blocks and evaluate
+//      each unordered pair once, the mirrored term going to a column
+//      partial.  No atomics.
 //  k_gather       (a few lanes per determinant and root):
 //      sigma_I = H_II c_I + sum of I's partials (fixed order), one write.
 //      Partials are written in member order (coalesced) and gathered
 //      through the determinant-major membership list.
 //  k_diag         (one thread per determinant): H_II by Slater-Condon.
+//  k_batched_*    the same bodies over the packets of many problems.
 //
 // All sums are in a fixed order, so repeated calls give identical bits.
 #include <hip/hip_runtime.h>
