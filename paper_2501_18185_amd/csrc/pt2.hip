@@ -18,9 +18,14 @@
 //   k_pt2_enum<1>     the same pairs, counted per bucket
 //   k_pt2_enum<2>     the pairs of the buckets of one pass, written as
 //                     records {A, J} with H_AJ c_J at the bucket's offset
-//   k_pt2_bucket      one workgroup per bucket: sorts its records by (hash
-//                     bits of A, J) in LDS, sums each numerator in ascending
-//                     J, adds |num|^2 / (E0 - H_AA) in sorted order
+//   k_pt2_bucket_wave one wave per bucket (up to 1024 records): sorts its
+//                     records by (hash bits of A, J) in registers, sums each
+//                     run's numerator across the wave by segmented scans,
+//                     adds |num|^2 / (E0 - H_AA) per external A
+//   k_pt2_bucket      the same for the rare larger buckets, one workgroup
+//                     each, sorting in LDS
+//   k_sel_*           the iCIPT2 selection: the same walk, the test per
+//                     pair, kept keys bucketed, sorted and made distinct
 //   k_pt2_sum1/2      per pass: bucket partial sums in a fixed order
 //
 // Passes over bucket ranges keep the records within the caller's work

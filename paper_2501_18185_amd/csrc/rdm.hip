@@ -16,8 +16,12 @@
 //      only for X of the spin of P).  The sum over K is split into the
 //      reference string omega (applied once at the end through the
 //      accumulated S_PQ = sum of w) plus the few positions where K and omega
-//      differ (direct atomics).
-//  diagonal I = J: gamma_PP += w, Gamma_PPRR += w, Gamma_PRRP -= w (P != R).
+//      differ (direct atomics into compact C and E arrays, spread over
+//      copies that are folded before the final pass).
+//  diagonal I = J: gamma_PP += w, Gamma_PPRR += w, Gamma_PRRP -= w (P != R),
+//      from the occupation correlations of every determinant.
+//  One vector as bra and ket: each unordered pair once; the final pass adds
+//  the mirror image (the reversed pair's weight is the conjugate).
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
