@@ -14,6 +14,9 @@ Two independent tiers follow the paper's second-quantised Hamiltonian
   one row at a time, scanning the whole space for connected determinants.
 * ``davidson`` - block Davidson-Liu over a sigma callback (numpy ``eigh`` for
   the subspace problem).
+* ``csf``      - configuration state functions of section 2.3 (genealogical
+  spin coupling, Yamanouchi-Kotani phase) written out in determinants, and
+  sigma in that basis as T^T H T c.
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against closed
 forms, invariances, brute force and the other tier (see the test docstrings).

@@ -357,6 +357,40 @@ def space_selected_spinor(nk, nel, target, rng, ranks=(3,)):
     return _fill_random(w0, w1, target, gen)
 
 
+def complete_configurations(dets, n):
+    """Close a spin-free space over its configurations: for every
+    determinant, all determinants with the same doubly occupied orbitals,
+    the same singly occupied (open) orbitals and the same number of alpha
+    electrons (every placement of the alpha spins over the open shells)."""
+    d = np.asarray(dets, np.uint64).reshape(-1, 2)
+    if len(d) == 0:
+        return d
+    a, b = d[:, 0], d[:, 1]
+    docc, opn = a & b, a ^ b
+    cfg = np.unique(np.stack([docc, opn], 1), axis=0)
+    na = int(np.bitwise_count(a[0]))
+    nd = np.bitwise_count(cfg[:, 0]).astype(np.int64)
+    k = np.bitwise_count(cfg[:, 1]).astype(np.int64)
+    out0, out1 = [], []
+    for kk in np.unique(k):
+        sel = cfg[k == kk]
+        nup = na - int(nd[k == kk][0])
+        # open positions, ascending, one row per configuration
+        pos = np.zeros((len(sel), kk), np.int64)
+        col = np.zeros(len(sel), np.int64)
+        for p in range(n):
+            hit = (sel[:, 1] >> np.uint64(p)) & np.uint64(1) == 1
+            pos[hit, col[hit]] = p
+            col[hit] += 1
+        for combo in itertools.combinations(range(int(kk)), nup):
+            up = np.zeros(len(sel), np.uint64)
+            for j in combo:
+                up |= np.left_shift(np.uint64(1), pos[:, j].astype(np.uint64))
+            out0.append(sel[:, 0] | up)
+            out1.append(sel[:, 0] | (sel[:, 1] & ~up))
+    return sort_unique(np.concatenate(out0), np.concatenate(out1))
+
+
 def random_space_spinfree(n, na, nb, ndet, rng):
     """ndet distinct determinants drawn uniformly from the full space (tiny n)."""
     full = space_fci(n, na, nb)
