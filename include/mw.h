@@ -236,6 +236,51 @@ mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const double *e0, 
 mw_status mw_select(mw_plan plan, int32_t nroots, const void *c, const double *e0, double cmin, void *work,
                     size_t work_bytes, uint64_t *out, int64_t max_out, int64_t *count, mw_stream_t stream);
 
+/* Spin-adapted basis: configuration state functions (section 2.3: an orbital
+ * configuration generates several CSFs, told apart by their spin coupling,
+ * with the Yamanouchi-Kotani phase; section 2.2 stores a configuration as its
+ * doubly and singly occupied orbitals).  Built over the configurations of a
+ * spin-free plan's determinants at M_S = S, 2S = N_alpha - N_beta.
+ * Configuration (d_1 < .. < d_m doubly occupied, o_1 < .. < o_k open); CSF mu =
+ *   sum_s Theta_mu(s) a+_{d_1 alpha} a+_{d_1 beta} .. a+_{d_m beta} a+_{o_1 s_1} .. a+_{o_k s_k} |vac>,
+ * Theta_mu the genealogical spin function of coupling path mu (intermediate
+ * spins S_1 .. S_k = S, one spin 1/2 added at a time with Condon-Shortley
+ * Clebsch-Gordan coefficients), written in the plan's determinants (the sign
+ * of reordering the operators into ascending positions included).
+ * Numbering: configurations in the order of their first determinant; the
+ * paths of one configuration lexicographically, step up before step down.
+ * With T [ndet][ncsf] that expansion, the calls below give T x, T^T y and
+ * sigma_CSF = T^T H T c, which equals the Hamiltonian in the CSF basis
+ * applied to c because the space holds every determinant of each of its
+ * configurations (checked).
+ *
+ * mw_csf_create (host only): plan from mw_plan_create (spin-free), two_s =
+ * N_alpha - N_beta >= 0.  MW_EINVAL if 2S differs or a configuration lacks
+ * one of its C(k, (k + 2S)/2) determinants; MW_EUNSUPPORTED for spinor
+ * plans, more than 14 open shells in a configuration, or more than 2^31 - 1
+ * determinants or CSFs.  The CSF basis keeps the plan handle: the plan must
+ * outlive it.
+ * mw_csf_info: 0 ncsf, 1 configurations, 2 largest open-shell count,
+ * 3 workspace bytes, 4 coupling-table entries, 5 ndet; -1 otherwise.
+ * mw_csf_upload: binds a device workspace (>= mw_csf_workspace_bytes,
+ * 256-byte aligned, caller-owned, untouched until destroy) and copies the
+ * tables; synchronises the stream.
+ * mw_csf_to_det: y [ndet][nroots] = T x, x [ncsf][nroots] (device, FP64).
+ * mw_csf_from_det: x [ncsf][nroots] = T^T y.
+ * mw_csf_sigma: sigma [ncsf][nroots] = T^T H T c; work: device scratch of
+ * 2 ndet nroots doubles; the plan must be uploaded and nroots <= its
+ * max_roots.  Asynchronous on stream; repeated calls give identical bits. */
+typedef struct mw_csf_s *mw_csf;
+mw_status mw_csf_create(mw_plan plan, int32_t two_s, mw_csf *out);
+int64_t mw_csf_info(mw_csf csf, int32_t what);
+mw_status mw_csf_workspace_bytes(mw_csf csf, size_t *bytes);
+mw_status mw_csf_upload(mw_csf csf, void *workspace, size_t bytes, mw_stream_t stream);
+mw_status mw_csf_to_det(mw_csf csf, int32_t nroots, const double *x, double *y, mw_stream_t stream);
+mw_status mw_csf_from_det(mw_csf csf, int32_t nroots, const double *y, double *x, mw_stream_t stream);
+mw_status mw_csf_sigma(mw_csf csf, int32_t nroots, const double *c, double *sigma, double *work,
+                       mw_stream_t stream);
+mw_status mw_csf_destroy(mw_csf csf);
+
 /* Debug: connected pairs of all rows with their phases, as int64 records
  * [I, J, P, Q, R, S, sign] (R = S = -1 for singles; P, R particles in I; Q, S
  * holes in J; ascending within each pair).  Call with out = NULL to get the

@@ -120,6 +120,25 @@ def configurations(dets):
     return cfgs, np.array(of, np.int64)
 
 
+def config_block(dmask, omask, n, two_s):
+    """The CSFs of one configuration (doubly occupied and open orbital
+    masks) as entries (mu, alpha word, beta word, coefficient), and their
+    number."""
+    docc, opn = _bits(dmask), _bits(omask)
+    k = len(opn)
+    products = [s for s in itertools.product((1, -1), repeat=k) if sum(s) == two_s]
+    out = []
+    ps = paths(k, two_s)
+    for mu, path in enumerate(ps):
+        for spins in products:
+            v = spin_coefficient(path, spins)
+            if v == 0.0:
+                continue
+            sign, w0, w1 = operator_determinant(docc, opn, spins, n)
+            out.append((mu, w0, w1, sign * v))
+    return out, len(ps)
+
+
 def expansion(prob, two_s):
     """The CSF basis of the space: T [ndet][ncsf] (scipy CSC) with column
     mu of configuration I holding |I mu> in determinants, and the first CSF
@@ -140,22 +159,16 @@ def expansion(prob, two_s):
     rows, cols, vals, first = [], [], [], [0]
     col = 0
     for ci, (dmask, omask) in enumerate(cfgs):
-        docc, opn = _bits(dmask), _bits(omask)
-        k = len(opn)
+        k = bin(omask).count("1")
         nup = (k + two_s) // 2
         if count[ci] != math.comb(k, nup):
             raise ValueError("configuration %d holds %d of its %d determinants" % (ci, count[ci], math.comb(k, nup)))
-        products = [s for s in itertools.product((1, -1), repeat=k) if sum(s) == two_s]
-        for path in paths(k, two_s):
-            for spins in products:
-                v = spin_coefficient(path, spins)
-                if v == 0.0:
-                    continue
-                sign, w0, w1 = operator_determinant(docc, opn, spins, n)
-                rows.append(index[(w0, w1)])
-                cols.append(col)
-                vals.append(sign * v)
-            col += 1
+        block, f = config_block(dmask, omask, n, two_s)
+        for mu, w0, w1, v in block:
+            rows.append(index[(w0, w1)])
+            cols.append(col + mu)
+            vals.append(v)
+        col += f
         first.append(col)
     T = sp.csc_matrix((np.array(vals, np.float64), (np.array(rows, np.int64), np.array(cols, np.int64))),
                       shape=(len(dets), col))

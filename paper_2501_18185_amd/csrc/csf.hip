@@ -1,0 +1,470 @@
+// Spin-adapted basis: configuration state functions (CSFs) over the
+// configurations of a spin-free plan's determinants (section 2.3: an orbital
+// configuration generates several CSFs, told apart by their spin coupling;
+// the Yamanouchi-Kotani phase lets doubly occupied orbitals move freely).
+//
+// Convention (M_S = S, N_alpha - N_beta = 2S).  A configuration is the pair
+// (doubly occupied orbitals d_1 < ... < d_m, open orbitals o_1 < ... < o_k).
+// Its CSF mu is
+//   sum over spin products s of Theta_mu(s) a+_{d_1 a} a+_{d_1 b} ... a+_{d_m b}
+//                                           a+_{o_1 s_1} ... a+_{o_k s_k} |vac>,
+// Theta_mu the genealogical function of coupling path mu (intermediate spins
+// S_1 .. S_k = S, paths ordered lexicographically with the step up first):
+// the product of the Clebsch-Gordan coefficients of adding one spin 1/2 at a
+// time (Condon-Shortley phase).  Rewriting the operator product in the
+// determinant order of the space (ascending positions, alpha orbital p at p,
+// beta orbital p at n + p) costs a sign with two factors: one fixed by the
+// configuration (m(m-1)/2 + m t + #{(d, o): o < d}, t the open alpha count)
+// and one by the spin product (pairs of open shells i < j with s_i beta and
+// s_j alpha).  Configurations are numbered in the order of their first
+// determinant, CSFs of one configuration by path.
+//
+// The basis lives inside the span of the space's determinants when every
+// determinant of each configuration is present, so with T the [ndet][ncsf]
+// expansion sigma_CSF = T^T (H (T c)) exactly: the determinant sigma of the
+// plan runs unchanged between two block-diagonal transforms.
+//
+// Host: configurations by hashing (docc, open), a completeness check, the
+// coupling tables per open-shell count k (rows = placements of the t open
+// alpha spins, in increasing bit-pattern order; columns = paths), and the
+// per-determinant (configuration, sign, placement rank).
+// Device: k_csf_to_det (one thread per determinant and root: a row of the
+// table times the configuration's CSF coefficients) and k_csf_from_det (one
+// thread per CSF and root: a column of the table against the
+// configuration's determinants).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "mw_internal.h"
+
+using namespace mw;
+
+extern "C" const mw::DevPlan *mw_internal_devplan(mw_plan plan);
+extern "C" int mw_internal_space(mw_plan plan, const uint64_t **dets, int64_t *ndet, int32_t *kind, int32_t *n,
+                                 int32_t *na, int32_t *nb);
+
+namespace mw_csf_impl {
+
+constexpr int CSF_MAXOPEN = 14;   // C(14,7) x 429 doubles = 11.8 MB of table at most
+
+struct DevCsf {
+    int64_t ndet, ncsf, ncfg;
+    const uint2 *det_info;     // [ndet] {configuration | negative << 31, placement rank}
+    const uint32_t *cfg_det;   // [ncfg+1] offsets into cfg_dets
+    const uint32_t *cfg_dets;  // [ndet] determinant | negative << 31, by configuration then rank
+    const uint32_t *cfg_csf;   // [ncfg+1] first CSF of each configuration
+    const uint32_t *cfg_tab;   // [ncfg] offset of its table (doubles)
+    const uint32_t *csf_cfg;   // [ncsf] configuration of each CSF
+    const double *tab;         // coupling tables, [placements][paths] per open-shell count
+};
+
+template <class T>
+size_t take(size_t &off, size_t n)
+{
+    off = (off + 255) & ~(size_t)255;
+    size_t at = off;
+    off += n * sizeof(T);
+    return at;
+}
+
+// <S1 M1; 1/2 ms | S M>, doubled arguments
+double cg_half(int s1, int m1, int ms, int s, int m)
+{
+    if (m1 + ms != m || std::abs(m) > s || std::abs(m1) > s1) return 0.0;
+    const double S = 0.5 * s, M = 0.5 * m, h = 0.5 * ms;
+    if (s == s1 + 1) return std::sqrt((S + 2.0 * h * M) / (2.0 * S));
+    if (s == s1 - 1) return -2.0 * h * std::sqrt((S + 1.0 - 2.0 * h * M) / (2.0 * S + 2.0));
+    return 0.0;
+}
+
+// coupling paths of k spins ending at 2S = s, step up first
+void enumerate_paths(int k, int s, std::vector<int> &cur, std::vector<std::vector<int>> &out)
+{
+    const int i = (int)cur.size();
+    if (i == k) {
+        if ((cur.empty() ? 0 : cur.back()) == s) out.push_back(cur);
+        return;
+    }
+    const int b = cur.empty() ? 0 : cur.back();
+    for (int step : {1, -1}) {
+        const int nb = b + step;
+        if (nb < 0 || std::abs(nb - s) > k - i - 1) continue;
+        cur.push_back(nb);
+        enumerate_paths(k, s, cur, out);
+        cur.pop_back();
+    }
+}
+
+int64_t binom(int n, int r)
+{
+    if (r < 0 || r > n) return 0;
+    int64_t v = 1;
+    for (int i = 1; i <= r; i++) v = v * (n - r + i) / i;
+    return v;
+}
+
+struct PairHash {
+    size_t operator()(const std::pair<uint64_t, uint64_t> &k) const
+    {
+        uint64_t x = k.first * 0x9E3779B97F4A7C15ULL ^ (k.second + 0x632BE59BD9B4E019ULL);
+        x ^= x >> 31;
+        x *= 0xbf58476d1ce4e5b9ULL;
+        x ^= x >> 29;
+        return (size_t)x;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_csf_to_det(DevCsf q, int R, const double *__restrict__ x,
+                                                     double *__restrict__ y)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= q.ndet * R) return;
+    const int64_t I = t / R;
+    const int r = (int)(t - I * R);
+    const uint2 info = q.det_info[I];
+    const uint32_t cfg = info.x & 0x7fffffffu;
+    const uint32_t c0 = q.cfg_csf[cfg], f = q.cfg_csf[cfg + 1] - c0;
+    const double *row = q.tab + q.cfg_tab[cfg] + (size_t)info.y * f;
+    const double *xc = x + (size_t)c0 * R + r;
+    double acc = 0.0;
+    for (uint32_t mu = 0; mu < f; mu++) acc = fma(row[mu], xc[(size_t)mu * R], acc);
+    y[t] = (info.x >> 31) ? -acc : acc;
+}
+
+__global__ __launch_bounds__(256) void k_csf_from_det(DevCsf q, int R, const double *__restrict__ y,
+                                                       double *__restrict__ x)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= q.ncsf * R) return;
+    const int64_t j = t / R;
+    const int r = (int)(t - j * R);
+    const uint32_t cfg = q.csf_cfg[j];
+    const uint32_t c0 = q.cfg_csf[cfg], f = q.cfg_csf[cfg + 1] - c0, mu = (uint32_t)j - c0;
+    const uint32_t d0 = q.cfg_det[cfg], nd = q.cfg_det[cfg + 1] - d0;
+    const double *col = q.tab + q.cfg_tab[cfg] + mu;
+    double acc = 0.0;
+    for (uint32_t k = 0; k < nd; k++) {
+        const uint32_t e = q.cfg_dets[d0 + k];
+        const double v = y[(size_t)(e & 0x7fffffffu) * R + r];
+        acc = fma(col[(size_t)k * f], (e >> 31) ? -v : v, acc);
+    }
+    x[t] = acc;
+}
+
+}  // namespace mw_csf_impl
+
+using namespace mw_csf_impl;
+
+struct mw_csf_s {
+    mw_plan plan = nullptr;
+    int32_t two_s = 0, max_open = 0;
+    int64_t ndet = 0, ncsf = 0, ncfg = 0;
+    std::vector<uint2> det_info;
+    std::vector<uint32_t> cfg_det, cfg_dets, cfg_csf, cfg_tab, csf_cfg;
+    std::vector<double> tab;
+    bool bound = false;
+    DevCsf dev{};
+
+    size_t layout(DevCsf *d, char *base) const
+    {
+        size_t off = 0;
+        DevCsf t{};
+        t.ndet = ndet;
+        t.ncsf = ncsf;
+        t.ncfg = ncfg;
+        size_t a_info = take<uint2>(off, det_info.size()), a_cd = take<uint32_t>(off, cfg_det.size()),
+               a_cds = take<uint32_t>(off, cfg_dets.size()), a_cc = take<uint32_t>(off, cfg_csf.size()),
+               a_ct = take<uint32_t>(off, cfg_tab.size()), a_sc = take<uint32_t>(off, csf_cfg.size()),
+               a_tab = take<double>(off, tab.size());
+        if (d && base) {
+            t.det_info = (const uint2 *)(base + a_info);
+            t.cfg_det = (const uint32_t *)(base + a_cd);
+            t.cfg_dets = (const uint32_t *)(base + a_cds);
+            t.cfg_csf = (const uint32_t *)(base + a_cc);
+            t.cfg_tab = (const uint32_t *)(base + a_ct);
+            t.csf_cfg = (const uint32_t *)(base + a_sc);
+            t.tab = (const double *)(base + a_tab);
+            *d = t;
+        }
+        return off + 256;
+    }
+};
+
+static mw_status build_csf(mw_csf_s &C, const uint64_t *dets, int64_t N, int n, int na, int nb)
+{
+    const int s = C.two_s;
+    // configurations in the order of their first determinant
+    std::unordered_map<std::pair<uint64_t, uint64_t>, uint32_t, PairHash> id;
+    id.reserve((size_t)N);
+    std::vector<uint32_t> of(N);
+    std::vector<std::pair<uint64_t, uint64_t>> cfgs;
+    for (int64_t i = 0; i < N; i++) {
+        const uint64_t A = dets[2 * i], B = dets[2 * i + 1];
+        auto key = std::make_pair(A & B, A ^ B);
+        auto it = id.find(key);
+        if (it == id.end()) {
+            it = id.emplace(key, (uint32_t)cfgs.size()).first;
+            cfgs.push_back(key);
+        }
+        of[i] = it->second;
+    }
+    const int64_t ncfg = (int64_t)cfgs.size();
+    // open-shell counts, CSF and determinant offsets
+    std::vector<int> kc(ncfg);
+    C.cfg_det.assign(ncfg + 1, 0);
+    C.cfg_csf.assign(ncfg + 1, 0);
+    std::vector<int64_t> fk(CSF_MAXOPEN + 1, 0);
+    for (int k = 0; k <= CSF_MAXOPEN; k++)
+        if (k >= s && (k - s) % 2 == 0) fk[k] = binom(k, (k - s) / 2) - binom(k, (k - s) / 2 - 1);
+    int max_open = 0;
+    int64_t ncsf = 0;
+    for (int64_t c = 0; c < ncfg; c++) {
+        const int k = __builtin_popcountll(cfgs[c].second);
+        if (k > CSF_MAXOPEN)
+            return fail(MW_EUNSUPPORTED, "a configuration has more than 14 open shells");
+        kc[c] = k;
+        max_open = std::max(max_open, k);
+        const int t = (k + s) / 2;   // open alpha spins (N_alpha - N_beta = 2S)
+        C.cfg_det[c + 1] = C.cfg_det[c] + (uint32_t)binom(k, t);
+        ncsf += fk[k];
+        if (ncsf > 0x7fffffffLL) return fail(MW_EUNSUPPORTED, "more than 2^31 - 1 CSFs");
+        C.cfg_csf[c + 1] = (uint32_t)ncsf;
+    }
+    if ((int64_t)C.cfg_det[ncfg] != N) {
+        // some configuration misses determinants: find one to report
+        std::vector<uint32_t> cnt(ncfg, 0);
+        for (int64_t i = 0; i < N; i++) cnt[of[i]]++;
+        for (int64_t c = 0; c < ncfg; c++)
+            if (cnt[c] != C.cfg_det[c + 1] - C.cfg_det[c])
+                return fail(MW_EINVAL, "configuration " + std::to_string(c) + " (of its first determinant's order) holds " +
+                                           std::to_string(cnt[c]) + " of its " +
+                                           std::to_string(C.cfg_det[c + 1] - C.cfg_det[c]) +
+                                           " determinants: the space must contain every determinant of its configurations");
+        return fail(MW_EINVAL, "configuration count mismatch");
+    }
+    // coupling tables per open-shell count: [placements in increasing
+    // alpha-pattern order][paths], each entry the genealogical coefficient
+    // times the sign of the open-shell reordering
+    std::vector<int64_t> toff(CSF_MAXOPEN + 1, -1);
+    std::vector<char> used(CSF_MAXOPEN + 1, 0);
+    for (int64_t c = 0; c < ncfg; c++) used[kc[c]] = 1;
+    C.tab.clear();
+    for (int k = 0; k <= CSF_MAXOPEN; k++) {
+        if (!used[k]) continue;
+        const int t = (k + s) / 2;
+        std::vector<std::vector<int>> paths;
+        std::vector<int> cur;
+        enumerate_paths(k, s, cur, paths);
+        if ((int64_t)paths.size() != fk[k]) return fail(MW_EINVAL, "internal: path count");
+        toff[k] = (int64_t)C.tab.size();
+        if (C.tab.size() + (size_t)binom(k, t) * paths.size() > 0xffffffffULL)
+            return fail(MW_EUNSUPPORTED, "coupling tables too large");
+        for (uint32_t pat = 0; pat < (1u << k); pat++) {
+            if (__builtin_popcount(pat) != t) continue;
+            // open shell i is alpha when bit i of pat is set
+            int inv = 0, betas = 0;
+            for (int i = 0; i < k; i++) {
+                if ((pat >> i) & 1) inv += betas;
+                else betas++;
+            }
+            const double sg = (inv & 1) ? -1.0 : 1.0;
+            for (const auto &path : paths) {
+                double v = 1.0;
+                int b = 0, m = 0;
+                for (int i = 0; i < k && v != 0.0; i++) {
+                    const int ms = ((pat >> i) & 1) ? 1 : -1;
+                    v *= cg_half(b, m, ms, path[i], m + ms);
+                    b = path[i];
+                    m += ms;
+                }
+                C.tab.push_back(sg * v);
+            }
+        }
+    }
+    C.cfg_tab.resize(ncfg);
+    for (int64_t c = 0; c < ncfg; c++) C.cfg_tab[c] = (uint32_t)toff[kc[c]];
+    C.csf_cfg.resize(ncsf);
+    for (int64_t c = 0; c < ncfg; c++)
+        for (uint32_t j = C.cfg_csf[c]; j < C.cfg_csf[c + 1]; j++) C.csf_cfg[j] = (uint32_t)c;
+    // per determinant: placement rank (combinatorial number system over the
+    // open shells) and the configuration's reordering sign
+    C.det_info.resize(N);
+    C.cfg_dets.assign(N, 0xffffffffu);
+    for (int64_t i = 0; i < N; i++) {
+        const uint64_t A = dets[2 * i], B = dets[2 * i + 1];
+        const uint64_t docc = A & B, open = A ^ B, up = A & ~B;
+        const int m = __builtin_popcountll(docc), t = __builtin_popcountll(up);
+        int64_t rank = 0;
+        int idx = 0, seen = 0;
+        for (uint64_t x = open; x; x &= x - 1, idx++) {
+            const int p = __builtin_ctzll(x);
+            if ((up >> p) & 1) rank += binom(idx, ++seen);
+        }
+        int64_t below = 0;   // pairs (d, o) with o < d
+        for (uint64_t x = docc; x; x &= x - 1) {
+            const int d = __builtin_ctzll(x);
+            below += __builtin_popcountll(open & ((1ULL << d) - 1));
+        }
+        const int64_t e = (int64_t)m * (m - 1) / 2 + (int64_t)m * t + below;
+        const uint32_t neg = (uint32_t)(e & 1);
+        const uint32_t c = of[i];
+        if (rank >= (int64_t)(C.cfg_det[c + 1] - C.cfg_det[c])) return fail(MW_EINVAL, "internal: placement rank");
+        C.det_info[i] = uint2{c | (neg << 31), (uint32_t)rank};
+        uint32_t &slot = C.cfg_dets[C.cfg_det[c] + rank];
+        if (slot != 0xffffffffu) return fail(MW_EINVAL, "internal: two determinants share a placement");
+        slot = (uint32_t)i | (neg << 31);
+    }
+    (void)n;
+    (void)na;
+    (void)nb;
+    C.ndet = N;
+    C.ncsf = ncsf;
+    C.ncfg = ncfg;
+    C.max_open = max_open;
+    return MW_OK;
+}
+
+static mw_status csf_bound(mw_csf csf, int32_t nroots)
+{
+    if (!csf) return fail(MW_EINVAL, "csf is NULL");
+    if (!csf->bound) return fail(MW_EWORKSPACE, "CSF basis has no workspace: call mw_csf_upload first");
+    if (nroots < 1) return fail(MW_EINVAL, "nroots must be >= 1");
+    return MW_OK;
+}
+
+static unsigned grid_of(int64_t items)
+{
+    return (unsigned)((items + 255) / 256);
+}
+
+extern "C" {
+
+mw_status mw_csf_create(mw_plan plan, int32_t two_s, mw_csf *out)
+{
+    if (!out) return fail(MW_EINVAL, "out is NULL");
+    *out = nullptr;
+    const uint64_t *dets;
+    int64_t N;
+    int32_t kind, n, na, nb;
+    if (!plan || !mw_internal_space(plan, &dets, &N, &kind, &n, &na, &nb)) return fail(MW_EINVAL, "plan is NULL");
+    if (kind != MW_SPIN_FREE) return fail(MW_EUNSUPPORTED, "CSFs are built for spin-free plans");
+    if (two_s < 0 || na - nb != two_s)
+        return fail(MW_EINVAL, "2S must equal N_alpha - N_beta (CSFs are built at M_S = S)");
+    if (N > 0x7fffffffLL) return fail(MW_EUNSUPPORTED, "more than 2^31 - 1 determinants");
+    try {
+        std::unique_ptr<mw_csf_s> C(new mw_csf_s());
+        C->plan = plan;
+        C->two_s = two_s;
+        mw_status st = build_csf(*C, dets, N, n, na, nb);
+        if (st != MW_OK) return st;
+        *out = C.release();
+    } catch (const std::bad_alloc &) {
+        return fail(MW_EUNSUPPORTED, "host memory exhausted while building the CSF basis");
+    }
+    return MW_OK;
+}
+
+int64_t mw_csf_info(mw_csf csf, int32_t what)
+{
+    if (!csf) return -1;
+    switch (what) {
+    case 0: return csf->ncsf;
+    case 1: return csf->ncfg;
+    case 2: return csf->max_open;
+    case 3: return (int64_t)csf->layout(nullptr, nullptr);
+    case 4: return (int64_t)csf->tab.size();
+    case 5: return csf->ndet;
+    default: return -1;
+    }
+}
+
+mw_status mw_csf_workspace_bytes(mw_csf csf, size_t *bytes)
+{
+    if (!csf || !bytes) return fail(MW_EINVAL, "NULL argument");
+    *bytes = csf->layout(nullptr, nullptr);
+    return MW_OK;
+}
+
+mw_status mw_csf_upload(mw_csf csf, void *workspace, size_t bytes, mw_stream_t stream)
+{
+    if (!csf || !workspace) return fail(MW_EINVAL, "NULL argument");
+    const size_t need = csf->layout(nullptr, nullptr);
+    if (bytes < need) return fail(MW_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace) & 255) return fail(MW_EWORKSPACE, "workspace must be 256-byte aligned");
+    DevCsf d{};
+    csf->layout(&d, (char *)workspace);
+    hipStream_t s = (hipStream_t)stream;
+    auto up = [&](const void *dst, const void *src, size_t nb) -> bool {
+        if (!nb) return true;
+        return hipMemcpyAsync((void *)dst, src, nb, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    const mw_csf_s &C = *csf;
+    bool ok = up(d.det_info, C.det_info.data(), C.det_info.size() * sizeof(uint2)) &&
+              up(d.cfg_det, C.cfg_det.data(), C.cfg_det.size() * 4) &&
+              up(d.cfg_dets, C.cfg_dets.data(), C.cfg_dets.size() * 4) &&
+              up(d.cfg_csf, C.cfg_csf.data(), C.cfg_csf.size() * 4) &&
+              up(d.cfg_tab, C.cfg_tab.data(), C.cfg_tab.size() * 4) &&
+              up(d.csf_cfg, C.csf_cfg.data(), C.csf_cfg.size() * 4) && up(d.tab, C.tab.data(), C.tab.size() * 8);
+    if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during CSF upload");
+    // the host vectors are read by the copies above: wait before returning
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "hipStreamSynchronize failed after CSF upload");
+    csf->dev = d;
+    csf->bound = true;
+    return MW_OK;
+}
+
+mw_status mw_csf_to_det(mw_csf csf, int32_t nroots, const double *x, double *y, mw_stream_t stream)
+{
+    mw_status st = csf_bound(csf, nroots);
+    if (st != MW_OK) return st;
+    if (!x || !y) return fail(MW_EINVAL, "x and y must be device pointers");
+    const int64_t items = csf->ndet * nroots;
+    if (items == 0) return MW_OK;
+    // one dispatch counts its work-items in 32 bits
+    if (items > ((int64_t)1 << 32) - 256) return fail(MW_EUNSUPPORTED, "too many determinants x roots");
+    hipLaunchKernelGGL(k_csf_to_det, dim3(grid_of(items)), dim3(256), 0, (hipStream_t)stream, csf->dev, nroots, x, y);
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
+    return MW_OK;
+}
+
+mw_status mw_csf_from_det(mw_csf csf, int32_t nroots, const double *y, double *x, mw_stream_t stream)
+{
+    mw_status st = csf_bound(csf, nroots);
+    if (st != MW_OK) return st;
+    if (!x || !y) return fail(MW_EINVAL, "x and y must be device pointers");
+    const int64_t items = csf->ncsf * nroots;
+    if (items == 0) return MW_OK;
+    if (items > ((int64_t)1 << 32) - 256) return fail(MW_EUNSUPPORTED, "too many CSFs x roots");
+    hipLaunchKernelGGL(k_csf_from_det, dim3(grid_of(items)), dim3(256), 0, (hipStream_t)stream, csf->dev, nroots, y,
+                       x);
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
+    return MW_OK;
+}
+
+mw_status mw_csf_sigma(mw_csf csf, int32_t nroots, const double *c, double *sigma, double *work, mw_stream_t stream)
+{
+    mw_status st = csf_bound(csf, nroots);
+    if (st != MW_OK) return st;
+    if (!c || !sigma || !work) return fail(MW_EINVAL, "c, sigma and work must be device pointers");
+    const DevPlan *d = mw_internal_devplan(csf->plan);
+    if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace: call mw_plan_upload first");
+    if (nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
+    double *cd = work, *sd = work + (size_t)csf->ndet * nroots;
+    if ((st = mw_csf_to_det(csf, nroots, c, cd, stream)) != MW_OK) return st;
+    if (csf->ndet > 0 && (st = launch_sigma(*d, nroots, cd, sd, (hipStream_t)stream)) != MW_OK) return st;
+    return mw_csf_from_det(csf, nroots, sd, sigma, stream);
+}
+
+mw_status mw_csf_destroy(mw_csf csf)
+{
+    delete csf;
+    return MW_OK;
+}
+
+}  // extern "C"

@@ -955,6 +955,20 @@ __attribute__((visibility("hidden"))) const mw::DevPlan *mw_internal_devplan(mw_
     return &plan->p.dev;
 }
 
+// the host copy of the space: sorted determinants, orbitals, electron counts
+__attribute__((visibility("hidden"))) int mw_internal_space(mw_plan plan, const uint64_t **dets, int64_t *ndet,
+                                                            int32_t *kind, int32_t *n, int32_t *na, int32_t *nb)
+{
+    if (!plan) return 0;
+    *dets = plan->p.dets.data();
+    *ndet = plan->p.ndet;
+    *kind = plan->p.kind;
+    *n = plan->p.n;
+    *na = plan->p.nalpha;
+    *nb = plan->p.nbeta;
+    return 1;
+}
+
 // set the tunables (host copy; the device copy keeps the upload values,
 // which only the batched kernels read and they do not use these fields)
 __attribute__((visibility("hidden"))) void mw_internal_set_tune(mw_plan plan, int32_t u, int32_t gl)

@@ -75,6 +75,18 @@ def lib():
         L.mw_pt2.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, C.POINTER(C.c_double),
                              C.POINTER(i64), vp]
         L.mw_select.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, vp, i64, C.POINTER(i64), vp]
+        L.mw_csf_create.argtypes = [vp, i32, C.POINTER(vp)]
+        L.mw_csf_info.argtypes = [vp, i32]
+        L.mw_csf_info.restype = i64
+        L.mw_csf_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.mw_csf_upload.argtypes = [vp, vp, sz, vp]
+        L.mw_csf_to_det.argtypes = [vp, i32, vp, vp, vp]
+        L.mw_csf_from_det.argtypes = [vp, i32, vp, vp, vp]
+        L.mw_csf_sigma.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.mw_csf_destroy.argtypes = [vp]
+        for name in ("mw_csf_create", "mw_csf_workspace_bytes", "mw_csf_upload", "mw_csf_to_det",
+                     "mw_csf_from_det", "mw_csf_sigma", "mw_csf_destroy"):
+            getattr(L, name).restype = C.c_int
         for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
                      "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
@@ -320,6 +332,88 @@ class Plan:
                                C.c_void_p(work.data_ptr()), int(work_bytes), C.c_void_p(out.data_ptr()), int(max_out),
                                C.byref(cnt), _stream()))
         return out[:min(cnt.value, int(max_out))]
+
+
+class Csf:
+    """Configuration state functions over the configurations of a spin-free
+    plan's space at M_S = S (2S = N_alpha - N_beta), written out in that
+    space's determinants; ``sigma`` applies the Hamiltonian in this basis.
+    ``upload=False`` builds the host tables only (no GPU needed)."""
+
+    CSF_INFO = {"ncsf": 0, "configurations": 1, "max_open": 2, "workspace_bytes": 3, "table_entries": 4,
+                "ndet": 5}
+
+    def __init__(self, plan: Plan, two_s: int, upload: bool = True):
+        self.plan = plan          # keeps the plan alive as long as the basis
+        h = C.c_void_p()
+        _check(lib().mw_csf_create(plan._plan, int(two_s), C.byref(h)))
+        self._csf = h
+        self.two_s = int(two_s)
+        self.ncsf = self.info("ncsf")
+        self.workspace = None
+        if upload:
+            torch = _require_gpu()
+            nb = C.c_size_t()
+            _check(lib().mw_csf_workspace_bytes(self._csf, C.byref(nb)))
+            self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=plan.workspace.device)
+            _check(lib().mw_csf_upload(self._csf, C.c_void_p(self.workspace.data_ptr()), nb.value, _stream()))
+
+    def info(self, what: str) -> int:
+        return int(lib().mw_csf_info(self._csf, self.CSF_INFO[what]))
+
+    def close(self):
+        if getattr(self, "_csf", None):
+            lib().mw_csf_destroy(self._csf)
+            self._csf = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, x, n):
+        torch = _require_gpu()
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float64:
+            raise TypeError("expected a float64 tensor on the GPU")
+        if x.shape[0] != n:
+            raise ValueError(f"leading dimension must be {n}")
+        return x.contiguous()
+
+    def to_det(self, x, out=None):
+        """Determinant coefficients T x of CSF vector(s) x [ncsf] or [ncsf, nroots]."""
+        torch = _require_gpu()
+        x = self._vec(x, self.ncsf)
+        R = 1 if x.dim() == 1 else x.shape[1]
+        if out is None:
+            out = torch.empty((self.plan.ndet,) + tuple(x.shape[1:]), dtype=torch.float64, device=x.device)
+        _check(lib().mw_csf_to_det(self._csf, R, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def from_det(self, y, out=None):
+        """CSF components T^T y of determinant vector(s) y."""
+        torch = _require_gpu()
+        y = self._vec(y, self.plan.ndet)
+        R = 1 if y.dim() == 1 else y.shape[1]
+        if out is None:
+            out = torch.empty((self.ncsf,) + tuple(y.shape[1:]), dtype=torch.float64, device=y.device)
+        _check(lib().mw_csf_from_det(self._csf, R, C.c_void_p(y.data_ptr()), C.c_void_p(out.data_ptr()),
+                                     _stream()))
+        return out
+
+    def sigma(self, c, out=None, work=None):
+        """sigma = H c in the CSF basis (T^T H T c) for c [ncsf] or [ncsf, nroots]."""
+        torch = _require_gpu()
+        c = self._vec(c, self.ncsf)
+        R = 1 if c.dim() == 1 else c.shape[1]
+        if out is None:
+            out = torch.empty_like(c)
+        if work is None:
+            work = torch.empty(2 * self.plan.ndet * R, dtype=torch.float64, device=c.device)
+        _check(lib().mw_csf_sigma(self._csf, R, C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()),
+                                  C.c_void_p(work.data_ptr()), _stream()))
+        return out
 
 
 def profile(enable: bool):

@@ -84,3 +84,35 @@ def test_plan_pair_counts_spinor():
     p = synth.Problem("spinor", 8, 6, -1, d, synth.one_body_spinor(8, rng), synth.two_body_spinor(8, rng))
     pl = mw.Plan(p, upload=False)
     assert pl.info("pairs") == sc.degree_rows(p).sum()
+
+
+def test_csf_host_counts_and_errors():
+    """mw_csf_create on the host: CSF and configuration counts equal the
+    oracle's expansion; 2S, spinor plans and incomplete configurations are
+    refused with status codes; transforms need an uploaded basis."""
+    from oracle import csf
+    n, na, nb = 6, 4, 2
+    rng = np.random.default_rng(3)
+    d = synth.space_fci(n, na, nb)
+    p = synth.Problem("spinfree", n, na, nb, d, synth.one_body_real(n, rng), synth.two_body_real(n, rng))
+    pl = mw.Plan(p, upload=False)
+    cb = mw.Csf(pl, 2, upload=False)
+    T, first = csf.expansion(p, 2)
+    assert cb.ncsf == T.shape[1] and cb.info("configurations") == len(first) - 1
+    assert cb.info("max_open") == 6 and cb.info("ndet") == len(d)
+    h = C.c_void_p()
+    assert mw.lib().mw_csf_create(pl._plan, 0, C.byref(h)) == -1          # 2S != Na - Nb
+    assert mw.lib().mw_csf_to_det(cb._csf, 1, C.c_void_p(16), C.c_void_p(32), None) == -5
+    # one determinant of a configuration with four open shells (four
+    # determinants at S = 1) missing
+    k = np.bitwise_count(d[:, 0] ^ d[:, 1])
+    q = synth.Problem("spinfree", n, na, nb, np.delete(d, int(np.nonzero(k == 4)[0][0]), axis=0), p.h, p.g)
+    assert mw.lib().mw_csf_create(mw.Plan(q, upload=False)._plan, 2, C.byref(h)) == -1
+    sp = synth.workload(0)
+    nk = 3
+    rs = np.random.default_rng(4)
+    pos = np.array([[0, 1, 4], [0, 2, 5]], np.int64)
+    ds = synth.sort_unique(*synth._words(pos, nk))
+    ps = synth.Problem("spinor", nk, 3, -1, ds, synth.one_body_spinor(nk, rs), synth.two_body_spinor(nk, rs))
+    assert mw.lib().mw_csf_create(mw.Plan(ps, upload=False)._plan, 1, C.byref(h)) == -8
+    del sp

@@ -1,0 +1,151 @@
+"""GPU parity of the CSF basis (libmw ``mw_csf_*`` through its C ABI)
+against the CPU oracle (``oracle/csf.py`` with the Slater-Condon tier).
+
+Bar: T x, T^T y and sigma_CSF = T^T H T c within 1e-12 relative in the max
+norm on spaces the oracle expands whole (FCI at S = 0, 1/2, 1, 3/2 and
+configuration-complete selected spaces up to six open shells); on the
+configuration-complete n = 64 10a10b singles-and-doubles space (421,471
+determinants), sampled rows of T x against the oracle's configuration
+blocks, T^T T = 1 and the symmetry <a, sigma b> = <sigma a, b>.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_18185_amd import synth
+from oracle import csf, sc
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def _dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _prob(n, na, nb, dets, seed):
+    rng = np.random.default_rng(seed)
+    return synth.Problem("spinfree", n, na, nb, np.ascontiguousarray(dets, np.uint64),
+                         synth.one_body_real(n, rng), synth.two_body_real(n, rng), 0.5)
+
+
+def _case(name):
+    if name.startswith("fci"):
+        n, na, nb = (int(v) for v in name.split("-")[1:])
+        return _prob(n, na, nb, synth.space_fci(n, na, nb), seed=n * 10 + na)
+    if name == "trunc-16-4a4b":
+        d = synth.space_truncated_spinfree(16, 4, 4, 3000, np.random.default_rng(21))
+        return _prob(16, 4, 4, synth.complete_configurations(d, 16), seed=22)
+    if name == "trunc-14-5a3b":
+        d = synth.space_truncated_spinfree(14, 5, 3, 2000, np.random.default_rng(23))
+        return _prob(14, 5, 3, synth.complete_configurations(d, 14), seed=24)
+    if name == "random-12-3a3b":
+        d = synth.random_space_spinfree(12, 3, 3, 300, np.random.default_rng(25))
+        return _prob(12, 3, 3, synth.complete_configurations(d, 12), seed=26)
+    raise ValueError(name)
+
+
+CASES = ["fci-6-3-3", "fci-6-4-2", "fci-7-4-3", "fci-5-4-1", "trunc-16-4a4b", "trunc-14-5a3b", "random-12-3a3b"]
+
+
+def _basis(prob, max_roots):
+    from paper_2501_18185_amd import mw
+    pl = mw.Plan(prob, max_roots=max_roots)
+    return pl, mw.Csf(pl, prob.nalpha - prob.nbeta)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_csf_transforms_equal_oracle(torch, name):
+    prob = _case(name)
+    two_s = prob.nalpha - prob.nbeta
+    _say(f"case {name}: ndet {prob.ndet}")
+    T, first = csf.expansion(prob, two_s)
+    pl, cb = _basis(prob, 2)
+    assert cb.ncsf == T.shape[1] and cb.info("configurations") == len(first) - 1
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((T.shape[1], 2))
+    y = rng.standard_normal((prob.ndet, 2))
+    gx = cb.to_det(_dev(torch, x)).cpu().numpy()
+    gy = cb.from_det(_dev(torch, y)).cpu().numpy()
+    assert _rel(gx, T @ x) < TOL
+    assert _rel(gy, T.T @ y) < TOL
+    # one root (vector layout)
+    assert _rel(cb.to_det(_dev(torch, x[:, 0])).cpu().numpy(), T @ x[:, 0]) < TOL
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("R", [1, 3])
+def test_csf_sigma_equals_oracle(torch, name, R):
+    prob = _case(name)
+    two_s = prob.nalpha - prob.nbeta
+    _say(f"case {name}: ndet {prob.ndet}, {R} roots")
+    pl, cb = _basis(prob, R)
+    c = np.random.default_rng(R).standard_normal((cb.ncsf, R))
+    ref = csf.sigma(prob, two_s, c, sc.sigma)
+    got = cb.sigma(_dev(torch, c)).cpu().numpy()
+    assert _rel(got, ref) < TOL
+    again = cb.sigma(_dev(torch, c)).cpu().numpy()
+    assert np.array_equal(got, again)
+
+
+def test_csf_sd_space_n64(torch):
+    """Configuration-complete singles and doubles of n = 64 10a10b (the
+    integrals of the 2,000,000-determinant workload)."""
+    n, na = 64, 10
+    _, _, w0, w1 = synth._hf_and_sd_spinfree(n, na, na)
+    d = synth.sort_unique(w0, w1)
+    base = synth.workload(5)
+    prob = synth.Problem("spinfree", n, na, na, d, base.h, base.g)
+    _say(f"case sd-n64: ndet {prob.ndet}")
+    pl, cb = _basis(prob, 2)
+    ncsf = cb.ncsf
+    rng = np.random.default_rng(9)
+    c = rng.standard_normal((ncsf, 2))
+    c /= np.linalg.norm(c, axis=0)
+    gc = _dev(torch, c)
+    x = cb.to_det(gc)
+    back = cb.from_det(x).cpu().numpy()
+    assert _rel(back, c) < 1e-13
+    # sampled rows of T c against the oracle's blocks of their configurations
+    cfgs, of = csf.configurations(d)
+    fk = {}
+    offs = np.zeros(len(cfgs) + 1, np.int64)
+    for i, (dm, om) in enumerate(cfgs):
+        k = bin(om).count("1")
+        if k not in fk:
+            fk[k] = len(csf.paths(k, 0))
+        offs[i + 1] = offs[i] + fk[k]
+    assert offs[-1] == ncsf
+    xs = x.cpu().numpy()
+    index = {(int(a), int(b)): i for i, (a, b) in enumerate(d)}
+    for I in rng.choice(prob.ndet, 200, replace=False):
+        ci = of[I]
+        block, f = csf.config_block(cfgs[ci][0], cfgs[ci][1], n, 0)
+        ref = np.zeros(2)
+        for mu, a, b, v in block:
+            if index[(a, b)] == I:
+                ref += v * c[offs[ci] + mu]
+        assert np.abs(xs[I] - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    # symmetry of the CSF Hamiltonian: <a, H b> = <H a, b>
+    s = cb.sigma(gc).cpu().numpy()
+    lhs, rhs = c[:, 0] @ s[:, 1], s[:, 0] @ c[:, 1]
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
