@@ -27,11 +27,15 @@ Further legs reported in the same line (skip with --legs none):
   pt2       Epstein-Nesbet second-order energy of the lowest root of a
             20,000-determinant n=64 10a10b space over its external space
             (exact and screened), and the iCIPT2 selection of the next
-            determinants from it.
+            determinants from it;
+  csf       sigma in the CSF basis (spin-adapted, S = 0) of the
+            configuration-complete singles-and-doubles space of n=64
+            10a10b, 1 and 4 roots, against the determinant sigma of the
+            same space.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
                        [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
-                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson,pt2|none]
+                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson,pt2,csf|none]
 """
 from __future__ import annotations
 
@@ -89,7 +93,7 @@ def main():
     ap.add_argument("--roots", type=int, default=1)
     ap.add_argument("--workload", default="sci-n64", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=30000, help="rows of the CPU oracle sample (0: skip)")
-    ap.add_argument("--legs", default="batched,spinor,rdm,davidson,pt2")
+    ap.add_argument("--legs", default="batched,spinor,rdm,davidson,pt2,csf")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -218,6 +222,8 @@ def main():
         out["legs"]["spinor"] = leg_spinor(args.steps)
     if "pt2" in legs:
         out["legs"]["pt2"] = leg_pt2()
+    if "csf" in legs:
+        out["legs"]["csf"] = leg_csf(args.steps)
 
     if args.cpu_rows > 0:
         from oracle import sc
@@ -416,6 +422,39 @@ def leg_spinor(steps):
     return {"workload": p.name, "ndet": p.ndet, "connected_pairs": pairs, "ms_per_sigma": ms,
             "terms_per_s": (pairs + p.ndet) / (ms * 1e-3), "group_sigma_ms": mg / max(ng, 1),
             "group_sigma_GBps": achieved, "hbm_frac": achieved / HBM_PEAK_GBS}
+
+
+def leg_csf(steps):
+    """CSF-basis sigma (T^T H T c) against the determinant sigma of the same
+    configuration-complete space."""
+    import torch
+    from paper_2501_18185_amd import mw, synth
+    t0 = time.perf_counter()
+    p = synth.workload(6)
+    res = {"workload": p.name, "ndet": p.ndet}
+    for R in (1, 4):
+        pl = mw.Plan(p, max_roots=R)
+        cb = mw.Csf(pl, 0)
+        if R == 1:
+            log(f"[bench] csf: ndet={p.ndet} ncsf={cb.ncsf} configurations={cb.info('configurations')} "
+                f"ready in {time.perf_counter() - t0:.1f}s")
+            res.update({"ncsf": cb.ncsf, "configurations": cb.info("configurations")})
+        c = torch.from_numpy(synth.ci_vectors(cb.ncsf, R, synth.rng_for(6, 0, synth.SEED_C))).cuda()
+        o = torch.empty_like(c)
+        x = cb.to_det(c)
+        y = torch.empty_like(x)
+        work = torch.empty(2 * p.ndet * R, dtype=torch.float64, device="cuda")
+        n = max(steps // 2, 3)
+        ms_csf = _time(lambda: cb.sigma(c, out=o, work=work), n)
+        ms_det = _time(lambda: pl.sigma(x, out=y), n)
+        ms_t = _time(lambda: cb.to_det(c, out=x), n)
+        ms_tt = _time(lambda: cb.from_det(y, out=o), n)
+        log(f"[bench] csf: {R} roots, {ms_csf:.2f} ms per CSF sigma, {ms_det:.2f} ms determinant sigma")
+        res[f"roots{R}"] = {"ms_per_csf_sigma": ms_csf, "ms_per_det_sigma": ms_det, "to_det_ms": ms_t,
+                            "from_det_ms": ms_tt}
+        del pl, cb, c, o, x, y, work
+        torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

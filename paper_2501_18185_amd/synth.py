@@ -449,7 +449,9 @@ def batch_shapes(i: int):
 def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
     """Workload k (0 FCI n=8 4a4b; 1 selected n=64 10a10b 2e6; 2 spinor
     40 pairs N=20 1e6; 3 batch problem i; 4 FD case n=10 3a3b FCI; 5 the
-    variational space of the second-order energy, n=64 10a10b 2e4).
+    variational space of the second-order energy, n=64 10a10b 2e4; 6 the
+    singles-and-doubles space of n=64 10a10b, complete over its
+    configurations, for the CSF basis).
 
     ``scale`` < 1 shrinks the random part of selected spaces (for tests)."""
     if k == 0:
@@ -483,6 +485,14 @@ def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
         d = space_truncated_spinfree(n, na, na, max(target, 1081), rng_for(5, 0, SEED_SPACE))
         return Problem("spinfree", n, na, na, d, one_body_real(n, rng_for(1, 0, SEED_H)),
                        two_body_real(n, rng_for(1, 0, SEED_G)), name="pt2-n64-10a10b")
+    if k == 6:
+        # configuration-complete space for the CSF basis: HF, all singles and
+        # all doubles of n=64 10a10b (closed under the configurations) with
+        # the integrals of workload 1
+        n, na = 64, 10
+        _, _, w0, w1 = _hf_and_sd_spinfree(n, na, na)
+        return Problem("spinfree", n, na, na, sort_unique(w0, w1), one_body_real(n, rng_for(1, 0, SEED_H)),
+                       two_body_real(n, rng_for(1, 0, SEED_G)), name="sd-n64-10a10b")
     if k == 4:
         n, na, nb = 10, 3, 3
         return Problem("spinfree", n, na, nb, space_fci(n, na, nb),

@@ -110,11 +110,9 @@ def test_csf_sigma_equals_oracle(torch, name, R):
 def test_csf_sd_space_n64(torch):
     """Configuration-complete singles and doubles of n = 64 10a10b (the
     integrals of the 2,000,000-determinant workload)."""
-    n, na = 64, 10
-    _, _, w0, w1 = synth._hf_and_sd_spinfree(n, na, na)
-    d = synth.sort_unique(w0, w1)
-    base = synth.workload(5)
-    prob = synth.Problem("spinfree", n, na, na, d, base.h, base.g)
+    n = 64
+    prob = synth.workload(6)
+    d = prob.dets
     _say(f"case sd-n64: ndet {prob.ndet}")
     pl, cb = _basis(prob, 2)
     ncsf = cb.ncsf
