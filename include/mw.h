@@ -281,6 +281,19 @@ mw_status mw_csf_sigma(mw_csf csf, int32_t nroots, const double *c, double *sigm
                        mw_stream_t stream);
 mw_status mw_csf_destroy(mw_csf csf);
 
+/* Lowest nroots eigenpairs of the Hamiltonian in the CSF basis (spin-pure
+ * states of spin S): the block Davidson-Liu of mw_davidson over
+ * mw_csf_sigma, preconditioned with D_mu = sum_I T_I,mu^2 H_II.  c0, c_out:
+ * device [ncsf][nroots] FP64; evals, iters: HOST.  work: device scratch of
+ * mw_csf_davidson_work_bytes bytes, 256-byte aligned (Davidson vectors over
+ * the CSFs, two determinant vectors per root and the diagonal).  Both the
+ * CSF basis and its plan must be uploaded; nroots <= the plan's max_roots.
+ * Host-driven, synchronises once per iteration; MW_ENOCONV with the best
+ * vectors and values when max_iter is reached. */
+mw_status mw_csf_davidson_work_bytes(mw_csf csf, int32_t nroots, size_t *bytes);
+mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c0, double *c_out, double *evals, double tol,
+                          int32_t max_iter, int32_t *iters, void *work, size_t work_bytes, mw_stream_t stream);
+
 /* Debug: connected pairs of all rows with their phases, as int64 records
  * [I, J, P, Q, R, S, sign] (R = S = -1 for singles; P, R particles in I; Q, S
  * holes in J; ascending within each pair).  Call with out = NULL to get the

@@ -157,6 +157,24 @@ __global__ __launch_bounds__(256) void k_csf_from_det(DevCsf q, int R, const dou
     x[t] = acc;
 }
 
+// D_mu = sum over the configuration's determinants of T_I,mu^2 H_II
+__global__ __launch_bounds__(256) void k_csf_diag(DevCsf q, const double *__restrict__ hdiag,
+                                                   double *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q.ncsf) return;
+    const uint32_t cfg = q.csf_cfg[j];
+    const uint32_t c0 = q.cfg_csf[cfg], f = q.cfg_csf[cfg + 1] - c0, mu = (uint32_t)j - c0;
+    const uint32_t d0 = q.cfg_det[cfg], nd = q.cfg_det[cfg + 1] - d0;
+    const double *col = q.tab + q.cfg_tab[cfg] + mu;
+    double acc = 0.0;
+    for (uint32_t k = 0; k < nd; k++) {
+        const double t = col[(size_t)k * f];
+        acc = fma(t * t, hdiag[q.cfg_dets[d0 + k] & 0x7fffffffu], acc);
+    }
+    out[j] = acc;
+}
+
 }  // namespace mw_csf_impl
 
 using namespace mw_csf_impl;
@@ -341,6 +359,27 @@ static mw_status csf_bound(mw_csf csf, int32_t nroots)
 static unsigned grid_of(int64_t items)
 {
     return (unsigned)((items + 255) / 256);
+}
+
+// accessors for the Davidson driver (not exported)
+extern "C" __attribute__((visibility("hidden"))) int mw_internal_csf_dims(mw_csf csf, mw_plan *plan, int64_t *ndet,
+                                                                         int64_t *ncsf)
+{
+    if (!csf || !csf->bound) return 0;
+    *plan = csf->plan;
+    *ndet = csf->ndet;
+    *ncsf = csf->ncsf;
+    return 1;
+}
+
+extern "C" __attribute__((visibility("hidden"))) mw_status mw_internal_csf_diag(mw_csf csf, const double *hdiag,
+                                                                               double *out, hipStream_t s)
+{
+    if (!csf || !csf->bound) return fail(MW_EWORKSPACE, "CSF basis has no workspace");
+    if (csf->ncsf == 0) return MW_OK;
+    hipLaunchKernelGGL(k_csf_diag, dim3(grid_of(csf->ncsf)), dim3(256), 0, s, csf->dev, hdiag, out);
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
+    return MW_OK;
 }
 
 extern "C" {

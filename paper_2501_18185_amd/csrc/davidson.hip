@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "dev_common.h"
@@ -163,8 +164,9 @@ static void jacobi_eigh(int m, std::vector<cd> A, std::vector<double> &w, std::v
 template <bool CPLX>
 struct Davidson {
     using T = typename Scal<CPLX>::T;
-    mw_plan plan;
-    const DevPlan *d;
+    // sigma of k packed vectors ([N][k] in, [N][k] out) on stream s
+    std::function<mw_status(int, const T *, T *)> sigma;
+    const T *diag;   // [N] preconditioner diagonal (device)
     hipStream_t s;
     int R, mmax;
     int64_t N;
@@ -263,7 +265,7 @@ struct Davidson {
     mw_status apply_h(int first, int k)
     {
         hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, V + (size_t)first * N, k, N, packA, 1);
-        mw_status st = mw_sigma(plan, k, packA, packB, (mw_stream_t)s);
+        mw_status st = sigma(k, packA, packB);
         if (st != MW_OK) return st;
         hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, packB, k, N, W + (size_t)first * N, 0);
         return MW_OK;
@@ -361,7 +363,7 @@ struct Davidson {
             for (int k = 0; k < R; k++) {
                 if (std::sqrt(std::max(rn[k].real(), 0.0)) <= tol) continue;
                 hipLaunchKernelGGL(k_precond<CPLX>, dim3(grid()), dim3(256), 0, s, Rv + (size_t)k * N,
-                                   (const T *)d->diag, theta[k], N, Tn + (size_t)nnew * N);
+                                   diag, theta[k], N, Tn + (size_t)nnew * N);
                 nnew++;
             }
             if (m + nnew > msub) {
@@ -417,9 +419,10 @@ static mw_status run_davidson(mw_plan plan, const DevPlan *d, int32_t nroots, co
                               double *evals, double tol, int32_t max_iter, int32_t *iters, void *work,
                               hipStream_t s)
 {
+    using T = typename Scal<CPLX>::T;
     Davidson<CPLX> D;
-    D.plan = plan;
-    D.d = d;
+    D.sigma = [plan, s](int k, const T *in, T *out) { return mw_sigma(plan, k, in, out, (mw_stream_t)s); };
+    D.diag = (const T *)d->diag;
     D.s = s;
     D.R = nroots;
     D.mmax = std::max(8 * nroots, 24) + nroots;
@@ -446,4 +449,75 @@ extern "C" mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, v
     if (d->kind == MW_SPINOR)
         return run_davidson<true>(plan, d, nroots, c0, c_out, evals, tol, max_iter, iters, work, (hipStream_t)stream);
     return run_davidson<false>(plan, d, nroots, c0, c_out, evals, tol, max_iter, iters, work, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Davidson in a CSF basis: sigma through mw_csf_sigma, preconditioned with
+// the determinant diagonal carried into the CSF basis,
+// D_mu = sum_I T_I,mu^2 H_II (the CSF diagonal without its off-diagonal
+// determinant couplings inside the configuration).
+// ---------------------------------------------------------------------------
+
+extern "C" int mw_internal_csf_dims(mw_csf csf, mw_plan *plan, int64_t *ndet, int64_t *ncsf);
+extern "C" mw_status mw_internal_csf_diag(mw_csf csf, const double *hdiag, double *out, hipStream_t s);
+
+static size_t csf_dav_bytes(int R, int64_t ndet, int64_t ncsf)
+{
+    size_t b = Davidson<false>::bytes(R, ncsf);
+    b = (b + 255) & ~(size_t)255;
+    b += (size_t)2 * ndet * R * 8;   // determinant vectors of mw_csf_sigma
+    b = (b + 255) & ~(size_t)255;
+    b += (size_t)ncsf * 8;           // preconditioner diagonal
+    return b + 256;
+}
+
+extern "C" mw_status mw_csf_davidson_work_bytes(mw_csf csf, int32_t nroots, size_t *bytes)
+{
+    mw_plan plan;
+    int64_t ndet, ncsf;
+    if (!csf || !bytes) return fail(MW_EINVAL, "NULL argument");
+    if (!mw_internal_csf_dims(csf, &plan, &ndet, &ncsf))
+        return fail(MW_EWORKSPACE, "CSF basis has no workspace: call mw_csf_upload first");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
+    *bytes = csf_dav_bytes(nroots, ndet, ncsf);
+    return MW_OK;
+}
+
+extern "C" mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c0, double *c_out, double *evals,
+                                     double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
+                                     mw_stream_t stream)
+{
+    mw_plan plan;
+    int64_t ndet, ncsf;
+    if (!csf) return fail(MW_EINVAL, "csf is NULL");
+    if (!mw_internal_csf_dims(csf, &plan, &ndet, &ncsf))
+        return fail(MW_EWORKSPACE, "CSF basis has no workspace: call mw_csf_upload first");
+    if (!c0 || !c_out || !evals || !iters || !work) return fail(MW_EINVAL, "NULL argument");
+    if (!(tol > 0) || max_iter < 1) return fail(MW_EINVAL, "tol must be > 0 and max_iter >= 1");
+    size_t need;
+    mw_status st = mw_csf_davidson_work_bytes(csf, nroots, &need);
+    if (st != MW_OK) return st;
+    if (nroots > ncsf) return fail(MW_EINVAL, "more roots than CSFs");
+    if (work_bytes < need) return fail(MW_EWORKSPACE, "work area too small");
+    if (((uintptr_t)work) & 255) return fail(MW_EWORKSPACE, "work area must be 256-byte aligned");
+    const DevPlan *d = mw_internal_devplan(plan);
+    hipStream_t s = (hipStream_t)stream;
+    size_t off = (Davidson<false>::bytes(nroots, ncsf) + 255) & ~(size_t)255;
+    double *dwork = (double *)((char *)work + off);
+    off = (off + (size_t)2 * ndet * nroots * 8 + 255) & ~(size_t)255;
+    double *pdiag = (double *)((char *)work + off);
+    if ((st = mw_internal_csf_diag(csf, (const double *)d->diag, pdiag, s)) != MW_OK) return st;
+    Davidson<false> D;
+    D.sigma = [csf, dwork, s](int k, const double *in, double *out) {
+        return mw_csf_sigma(csf, k, in, out, dwork, (mw_stream_t)s);
+    };
+    D.diag = pdiag;
+    D.s = s;
+    D.R = nroots;
+    D.mmax = std::max(8 * nroots, 24) + nroots;
+    D.N = ncsf;
+    D.carve((char *)work);
+    return D.run(c0, c_out, evals, tol, max_iter, iters);
 }

@@ -147,3 +147,40 @@ def test_csf_sd_space_n64(torch):
     s = cb.sigma(gc).cpu().numpy()
     lhs, rhs = c[:, 0] @ s[:, 1], s[:, 0] @ c[:, 1]
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+    # singlet ground state: its energy is the determinant-basis Rayleigh
+    # quotient of T x, and no lower than the lowest determinant eigenvalue
+    # (start: the lowest-diagonal determinant, a closed shell, projected)
+    d0 = np.zeros((prob.ndet, 1))
+    d0[int(np.argmin(pl.diag().cpu().numpy())), 0] = 1.0
+    c0 = cb.from_det(_dev(torch, d0))
+    assert abs(float(torch.linalg.norm(c0)) - 1.0) < 1e-14
+    ev, X, it, conv = cb.davidson(c0, tol=1e-6, max_iter=200)
+    assert conv
+    xd = cb.to_det(X)
+    e_det = float((xd[:, 0] @ pl.sigma(xd)[:, 0]).item())
+    assert abs(e_det - ev[0]) < 1e-9 * max(1.0, abs(ev[0]))
+    evd, _, _, convd = pl.davidson(_dev(torch, d0), tol=1e-6, max_iter=200)
+    assert convd and ev[0] >= evd[0] - 1e-9
+
+
+@pytest.mark.parametrize("name,R", [("fci-6-3-3", 3), ("fci-6-4-2", 2), ("fci-7-4-3", 2), ("trunc-14-5a3b", 2)])
+def test_csf_davidson_equals_dense(torch, name, R):
+    """Lowest spin-S eigenvalues from the CSF Davidson equal those of the
+    oracle's dense T^T H T; the vectors' residuals there are small."""
+    prob = _case(name)
+    two_s = prob.nalpha - prob.nbeta
+    _say(f"case {name}: CSF Davidson, {R} roots")
+    T, _ = csf.expansion(prob, two_s)
+    Td = T.toarray()
+    Hc = Td.T @ sc.dense_h(prob) @ Td
+    w = np.linalg.eigvalsh(Hc)[:R]
+    pl, cb = _basis(prob, R)
+    c0 = np.zeros((cb.ncsf, R))
+    c0[np.arange(R), np.arange(R)] = 1.0
+    c0 += 1e-3 * np.random.default_rng(4).standard_normal(c0.shape)
+    ev, X, it, conv = cb.davidson(_dev(torch, c0), tol=1e-9, max_iter=300)
+    assert conv
+    assert np.abs(ev - w).max() < 1e-10 * max(1.0, np.abs(w).max())
+    Xn = X.cpu().numpy()
+    res = Hc @ Xn - Xn * ev[None, :]
+    assert np.abs(res).max() < 1e-8
