@@ -51,7 +51,7 @@ extern "C" int mw_internal_space(mw_plan plan, const uint64_t **dets, int64_t *n
 
 namespace mw_csf_impl {
 
-constexpr int CSF_MAXOPEN = 14;   // C(14,7) x 429 doubles = 11.8 MB of table at most
+constexpr int CSF_MAXOPEN = 14;   // largest table: 14 open shells at S = 1, C(14,8) x 1001 doubles = 24 MB
 
 struct DevCsf {
     int64_t ndet, ncsf, ncfg;

@@ -184,3 +184,56 @@ def test_csf_davidson_equals_dense(torch, name, R):
     Xn = X.cpu().numpy()
     res = Hc @ Xn - Xn * ev[None, :]
     assert np.abs(res).max() < 1e-8
+
+
+def _all_open(n, na):
+    """The one configuration with every orbital singly occupied, na alpha."""
+    import itertools
+    al = [sum(1 << q for q in a) for a in itertools.combinations(range(n), na)]
+    be = [((1 << n) - 1) & ~a for a in al]
+    return synth.sort_unique(np.array(al, np.uint64), np.array(be, np.uint64))
+
+
+def test_csf_twelve_open_shells_equals_oracle(torch):
+    """One configuration with 12 open shells (924 determinants, 132
+    singlets): transforms and sigma against the oracle."""
+    n = 12
+    prob = _prob(n, 6, 6, _all_open(n, 6), seed=31)
+    _say(f"case all-open n=12: ndet {prob.ndet}")
+    T, first = csf.expansion(prob, 0)
+    pl, cb = _basis(prob, 2)
+    assert cb.ncsf == 132 and cb.info("max_open") == 12 and cb.info("configurations") == 1
+    c = np.random.default_rng(6).standard_normal((cb.ncsf, 2))
+    assert _rel(cb.to_det(_dev(torch, c)).cpu().numpy(), T @ c) < TOL
+    assert _rel(cb.sigma(_dev(torch, c)).cpu().numpy(), csf.sigma(prob, 0, c, sc.sigma)) < TOL
+
+
+@pytest.mark.parametrize("two_s", [0, 2])
+def test_csf_fourteen_open_shells_properties(torch, two_s):
+    """The largest open-shell count (14; 3432 or 3003 determinants, 429 or
+    1001 CSFs, the largest coupling table): T^T T = 1 and a symmetric CSF
+    Hamiltonian."""
+    n = 14
+    na = 7 + two_s // 2
+    prob = _prob(n, na, n - na, _all_open(n, na), seed=32)
+    _say(f"case all-open n=14, 2S={two_s}: ndet {prob.ndet}")
+    pl, cb = _basis(prob, 2)
+    assert cb.ncsf == len(csf.paths(14, two_s)) and cb.info("max_open") == 14
+    c = np.random.default_rng(7).standard_normal((cb.ncsf, 2))
+    gc = _dev(torch, c)
+    assert _rel(cb.from_det(cb.to_det(gc)).cpu().numpy(), c) < 1e-13
+    s = cb.sigma(gc).cpu().numpy()
+    lhs, rhs = c[:, 0] @ s[:, 1], s[:, 0] @ c[:, 1]
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_csf_single_closed_shell(torch):
+    """A one-determinant space (closed shell): one CSF, T = [1], sigma = H_II c."""
+    n = 6
+    d = synth.sort_unique(np.array([7], np.uint64), np.array([7], np.uint64))
+    prob = _prob(n, 3, 3, d, seed=33)
+    pl, cb = _basis(prob, 1)
+    assert cb.ncsf == 1
+    c = np.array([[0.75]])
+    ref = csf.sigma(prob, 0, c, sc.sigma)
+    assert _rel(cb.sigma(_dev(torch, c)).cpu().numpy(), ref) < TOL
