@@ -349,6 +349,8 @@ class Csf:
 
     def __init__(self, plan: Plan, two_s: int, upload: bool = True):
         self.plan = plan          # keeps the plan alive as long as the basis
+        if upload and plan.workspace is None:
+            raise RuntimeError("upload the plan before the CSF basis (Plan(..., upload=True))")
         h = C.c_void_p()
         _check(lib().mw_csf_create(plan._plan, int(two_s), C.byref(h)))
         self._csf = h
