@@ -109,12 +109,13 @@ def test_csf_sigma_equals_oracle(torch, name, R):
 
 def test_csf_sd_space_n64(torch):
     """Configuration-complete singles and doubles of n = 64 10a10b (the
-    integrals of the 2,000,000-determinant workload)."""
+    integrals of the 2,000,000-determinant workload), as the benchmark runs
+    it (one and four roots)."""
     n = 64
     prob = synth.workload(6)
     d = prob.dets
     _say(f"case sd-n64: ndet {prob.ndet}")
-    pl, cb = _basis(prob, 2)
+    pl, cb = _basis(prob, 4)
     ncsf = cb.ncsf
     rng = np.random.default_rng(9)
     c = rng.standard_normal((ncsf, 2))
@@ -143,8 +144,21 @@ def test_csf_sd_space_n64(torch):
             if index[(a, b)] == I:
                 ref += v * c[offs[ci] + mu]
         assert np.abs(xs[I] - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    # sampled CSF components of T^T y against the oracle's blocks
+    y = rng.standard_normal((prob.ndet, 2))
+    gy = cb.from_det(_dev(torch, y)).cpu().numpy()
+    for ci in rng.choice(len(cfgs), 200, replace=False):
+        block, f = csf.config_block(cfgs[ci][0], cfgs[ci][1], n, 0)
+        ref = np.zeros((f, 2))
+        for mu, a, b, v in block:
+            ref[mu] += v * y[index[(a, b)]]
+        got = gy[offs[ci]:offs[ci] + f]
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    # the CSF sigma is exactly its three steps (bitwise, same kernels)
+    s3 = cb.from_det(pl.sigma(cb.to_det(gc))).cpu().numpy()
     # symmetry of the CSF Hamiltonian: <a, H b> = <H a, b>
     s = cb.sigma(gc).cpu().numpy()
+    assert np.array_equal(s, s3)
     lhs, rhs = c[:, 0] @ s[:, 1], s[:, 0] @ c[:, 1]
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
     # singlet ground state: its energy is the determinant-basis Rayleigh
@@ -161,6 +175,12 @@ def test_csf_sd_space_n64(torch):
     assert abs(e_det - ev[0]) < 1e-9 * max(1.0, abs(ev[0]))
     evd, _, _, convd = pl.davidson(_dev(torch, d0), tol=1e-6, max_iter=200)
     assert convd and ev[0] >= evd[0] - 1e-9
+    # four roots at once: each column equals the one-root call
+    c4 = _dev(torch, rng.standard_normal((ncsf, 4)))
+    s4 = cb.sigma(c4).cpu().numpy()
+    for k in range(4):
+        s1 = cb.sigma(c4[:, k].contiguous()).cpu().numpy()
+        assert _rel(s4[:, k], s1) < 1e-13
 
 
 @pytest.mark.parametrize("name,R", [("fci-6-3-3", 3), ("fci-6-4-2", 2), ("fci-7-4-3", 2), ("trunc-14-5a3b", 2)])
