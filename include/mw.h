@@ -197,6 +197,29 @@ mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out,
                       double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
                       mw_stream_t stream);
 
+/* Iterative vector interaction (section 2.4: trial vectors from
+ * perturbation theory and conjugate gradients, a search space of fixed
+ * dimension set by the number of roots, direct access to interior roots).
+ * The space holds the current R vectors X, their first-order corrections
+ * t_k = r_k / (theta_k - H_II) (r_k the residual) and the previous step's
+ * directions (the part of the new X outside the old one), 3R vectors at
+ * most; each step diagonalises H there and keeps R Ritz pairs: the lowest
+ * when target is NaN, otherwise the R nearest target (energy-selected), so
+ * roots below the target are never computed.  c0: device [ndet][nroots]
+ * start vectors (orthonormalised internally; for a target, e.g. unit
+ * vectors on the determinants whose H_II is nearest it); c_out: device
+ * [ndet][nroots] Ritz vectors; evals, iters: HOST.  Convergence when every
+ * residual 2-norm <= tol.  work: device scratch of mw_ivi_work_bytes
+ * bytes, 256-byte aligned (4 nroots vectors and their H products).
+ * Host-driven, synchronises once per step; MW_ENOCONV with the last Ritz
+ * pairs when max_iter is reached.  Roots inside a dense cluster of
+ * eigenvalues converge slowly: the energy selection can move between
+ * states of the cluster; targets separated from their neighbours converge
+ * in a few tens of steps. */
+mw_status mw_ivi_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
+mw_status mw_ivi(mw_plan plan, int32_t nroots, double target, const void *c0, void *c_out, double *evals,
+                 double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes, mw_stream_t stream);
+
 /* Epstein-Nesbet second-order energies (section 2.5, Eq. (ENPT2E), with
  * the primary space equal to the plan's space P):
  *   e2[k] = sum_{A in Q} |sum_{J in P} H_AJ c[J][k]|^2 / (e0[k] - H_AA),

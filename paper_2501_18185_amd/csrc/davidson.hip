@@ -176,9 +176,11 @@ struct Davidson {
     int *ia, *ib;
     std::vector<cd> Gh;  // host subspace matrix (mmax x mmax)
 
-    static size_t bytes(int R, int64_t N)
+    static size_t bytes(int R, int64_t N) { return bytes_m(std::max(8 * R, 24) + R, R, N); }
+
+    // the same buffers for a basis of at most mmax vectors
+    static size_t bytes_m(int mmax, int R, int64_t N)
     {
-        const int mmax = std::max(8 * R, 24) + R;
         const size_t sb = sizeof(T);
         size_t b = 0;
         auto take = [&](size_t x) { b = (b + 255) & ~(size_t)255; b += x; };
@@ -395,6 +397,159 @@ struct Davidson {
         if (!converged) return fail(MW_ENOCONV, "Davidson did not converge");
         return MW_OK;
     }
+
+    // Gram-Schmidt of row `row` of V against rows [0, row) with the same
+    // combination applied to W, so that W stays H V; returns the norm
+    bool orthonormalize_vw(int row, double &norm)
+    {
+        T *t = V + (size_t)row * N, *tw = W + (size_t)row * N;
+        for (int pass = 0; pass < 2 && row > 0; pass++) {
+            std::vector<int> a(row), b(row, row);
+            for (int i = 0; i < row; i++) a[i] = i;
+            std::vector<cd> ov;
+            if (!dots(V, V, a, b, ov)) return false;
+            std::vector<cd> C(row);
+            for (int i = 0; i < row; i++) C[i] = -ov[i];
+            if (!lincomb(V, row, C, 1, t, std::vector<double>{1.0}) ||
+                !lincomb(W, row, C, 1, tw, std::vector<double>{1.0}))
+                return false;
+        }
+        std::vector<cd> nn;
+        if (!dots(V, V, std::vector<int>{row}, std::vector<int>{row}, nn)) return false;
+        norm = std::sqrt(std::max(nn[0].real(), 0.0));
+        if (norm >= 1e-10) {
+            std::vector<cd> C;
+            if (!lincomb(V, 0, C, 1, t, std::vector<double>{1.0 / norm}) ||
+                !lincomb(W, 0, C, 1, tw, std::vector<double>{1.0 / norm}))
+                return false;
+        }
+        return true;
+    }
+
+    // Iterative vector interaction over a search space of fixed dimension
+    // (at most 3R): the current vectors X, their first-order corrections
+    // t_k = r_k / (theta_k - H_II) and the directions of the last step
+    // P = X_new - X_old (X_old^H X_new), whose H P is carried along.  Each
+    // step diagonalises H in that space and keeps R Ritz pairs: the lowest
+    // (target NaN) or those nearest the target energy, without the roots
+    // below them.  One sigma of the corrections per step.  Buffers: V, W
+    // rows [0, 3R) for the space, rows [3R, 4R) for P and H P (mmax = 4R).
+    mw_status run_ivi(const void *c0, void *c_out, double *evals, double tol, int max_iter, int *iters,
+                      double target)
+    {
+        const bool lowest = std::isnan(target);
+        T *Pv = V + (size_t)3 * R * N, *PA = W + (size_t)3 * R * N;
+        hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, (const T *)c0, R, N, V, 0);
+        int m = 0;
+        for (int k = 0; k < R; k++) {
+            if (k != m)
+                if (hipMemcpyAsync(V + (size_t)m * N, V + (size_t)k * N, N * sizeof(T), hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                    return fail(MW_EHIP, "copy failed");
+            double nrm;
+            if (!orthonormalize(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
+            if (nrm >= 1e-10) m++;
+        }
+        if (m < R) return fail(MW_EINVAL, "start vectors are linearly dependent");
+        mw_status st = apply_h(0, m);
+        if (st != MW_OK) return st;
+        int np = 0;
+        std::vector<double> theta(R);
+        bool converged = false;
+        int it = 0;
+        for (it = 1; it <= max_iter; it++) {
+            // Rayleigh-Ritz in the current space
+            std::vector<int> a, b;
+            for (int bb = 0; bb < m; bb++)
+                for (int aa = 0; aa < m; aa++) { a.push_back(aa); b.push_back(bb); }
+            std::vector<cd> gv;
+            if (!dots(V, W, a, b, gv)) return fail(MW_EHIP, "dot products failed");
+            std::vector<cd> G((size_t)m * m);
+            for (size_t q = 0; q < gv.size(); q++) G[(size_t)a[q] * m + b[q]] = gv[q];
+            for (int i = 0; i < m; i++)
+                for (int j = 0; j < i; j++) {
+                    const cd v = 0.5 * (G[(size_t)i * m + j] + std::conj(G[(size_t)j * m + i]));
+                    G[(size_t)i * m + j] = v;
+                    G[(size_t)j * m + i] = std::conj(v);
+                }
+            for (int i = 0; i < m; i++) G[(size_t)i * m + i] = cd(G[(size_t)i * m + i].real(), 0.0);
+            std::vector<double> w;
+            std::vector<cd> E;
+            jacobi_eigh(m, G, w, E);
+            std::vector<int> sel(m);
+            for (int i = 0; i < m; i++) sel[i] = i;
+            if (!lowest)
+                std::stable_sort(sel.begin(), sel.end(),
+                                 [&](int x, int y) { return std::fabs(w[x] - target) < std::fabs(w[y] - target); });
+            sel.resize(R);
+            std::sort(sel.begin(), sel.end());   // ascending energy among the kept
+            std::vector<cd> Y((size_t)m * R), Ytp((size_t)std::max(m - R, 0) * R);
+            for (int i = 0; i < m; i++)
+                for (int k = 0; k < R; k++) {
+                    Y[(size_t)i * R + k] = E[(size_t)i * m + sel[k]];
+                    if (i >= R) Ytp[(size_t)(i - R) * R + k] = E[(size_t)i * m + sel[k]];
+                }
+            for (int k = 0; k < R; k++) theta[k] = w[sel[k]];
+            std::vector<double> zero(R, 0.0);
+            if (!lincomb(V, m, Y, R, X, zero) || !lincomb(W, m, Y, R, AX, zero)) return fail(MW_EHIP, "Ritz failed");
+            np = 0;
+            if (m > R) {
+                // the step's direction outside the old X (its H P alike)
+                if (!lincomb(V + (size_t)R * N, m - R, Ytp, R, Pv, zero) ||
+                    !lincomb(W + (size_t)R * N, m - R, Ytp, R, PA, zero))
+                    return fail(MW_EHIP, "direction failed");
+                np = R;
+            }
+            if (hipMemcpyAsync(V, X, (size_t)R * N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(W, AX, (size_t)R * N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(MW_EHIP, "copy failed");
+            // residuals r_k = AX_k - theta_k X_k
+            if (hipMemcpyAsync(Rv, AX, (size_t)R * N * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(MW_EHIP, "copy failed");
+            for (int k = 0; k < R; k++) {
+                std::vector<cd> C{cd(-theta[k], 0)};
+                if (!lincomb(X + (size_t)k * N, 1, C, 1, Rv + (size_t)k * N, std::vector<double>{1.0}))
+                    return fail(MW_EHIP, "residual failed");
+            }
+            std::vector<int> ka(R);
+            for (int k = 0; k < R; k++) ka[k] = k;
+            std::vector<cd> rn;
+            if (!dots(Rv, Rv, ka, ka, rn)) return fail(MW_EHIP, "norms failed");
+            bool all = true;
+            for (int k = 0; k < R; k++) all = all && std::sqrt(std::max(rn[k].real(), 0.0)) <= tol;
+            if (all) { converged = true; break; }
+            if (it == max_iter) break;
+            // first-order corrections of the unconverged roots, then the
+            // directions of the last step
+            m = R;
+            for (int k = 0; k < R; k++) {
+                if (std::sqrt(std::max(rn[k].real(), 0.0)) <= tol) continue;
+                hipLaunchKernelGGL(k_precond<CPLX>, dim3(grid()), dim3(256), 0, s, Rv + (size_t)k * N, diag, theta[k],
+                                   N, V + (size_t)m * N);
+                double nrm;
+                if (!orthonormalize(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
+                if (nrm >= 1e-10) m++;
+            }
+            if (m > R && (st = apply_h(R, m - R)) != MW_OK) return st;
+            for (int k = 0; k < np; k++) {
+                if (hipMemcpyAsync(V + (size_t)m * N, Pv + (size_t)k * N, N * sizeof(T), hipMemcpyDeviceToDevice, s) !=
+                        hipSuccess ||
+                    hipMemcpyAsync(W + (size_t)m * N, PA + (size_t)k * N, N * sizeof(T), hipMemcpyDeviceToDevice, s) !=
+                        hipSuccess)
+                    return fail(MW_EHIP, "copy failed");
+                double nrm;
+                if (!orthonormalize_vw(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
+                if (nrm >= 1e-10) m++;
+            }
+            if (m == R) break;  // no new direction: stagnation
+        }
+        hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, X, R, N, (T *)c_out, 1);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "final sync failed");
+        for (int k = 0; k < R; k++) evals[k] = theta[k];
+        *iters = std::min(it, max_iter);
+        if (!converged) return fail(MW_ENOCONV, "iVI did not converge");
+        return MW_OK;
+    }
 };
 
 }  // namespace
@@ -449,6 +604,63 @@ extern "C" mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, v
     if (d->kind == MW_SPINOR)
         return run_davidson<true>(plan, d, nroots, c0, c_out, evals, tol, max_iter, iters, work, (hipStream_t)stream);
     return run_davidson<false>(plan, d, nroots, c0, c_out, evals, tol, max_iter, iters, work, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Iterative vector interaction (section 2.4): fixed search space of 3R
+// vectors, lowest roots or the roots nearest a target energy
+// ---------------------------------------------------------------------------
+
+extern "C" mw_status mw_ivi_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(MW_EINVAL, "NULL argument");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots");
+    *bytes = d->kind == MW_SPINOR ? Davidson<true>::bytes_m(4 * nroots, nroots, d->ndet)
+                                  : Davidson<false>::bytes_m(4 * nroots, nroots, d->ndet);
+    return MW_OK;
+}
+
+template <bool CPLX>
+static mw_status run_ivi_t(mw_plan plan, const DevPlan *d, int32_t nroots, double target, const void *c0,
+                           void *c_out, double *evals, double tol, int32_t max_iter, int32_t *iters, void *work,
+                           hipStream_t s)
+{
+    using T = typename Scal<CPLX>::T;
+    Davidson<CPLX> D;
+    D.sigma = [plan, s](int k, const T *in, T *out) { return mw_sigma(plan, k, in, out, (mw_stream_t)s); };
+    D.diag = (const T *)d->diag;
+    D.s = s;
+    D.R = nroots;
+    D.mmax = 4 * nroots;
+    D.N = d->ndet;
+    D.carve((char *)work);
+    return D.run_ivi(c0, c_out, evals, tol, max_iter, iters, target);
+}
+
+extern "C" mw_status mw_ivi(mw_plan plan, int32_t nroots, double target, const void *c0, void *c_out, double *evals,
+                            double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
+                            mw_stream_t stream)
+{
+    if (!plan) return fail(MW_EINVAL, "plan is NULL");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots");
+    if (!c0 || !c_out || !evals || !iters || !work) return fail(MW_EINVAL, "NULL argument");
+    if (!(tol > 0) || max_iter < 1) return fail(MW_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (std::isinf(target)) return fail(MW_EINVAL, "target must be finite (NaN for the lowest roots)");
+    if (nroots > d->ndet) return fail(MW_EINVAL, "more roots than determinants");
+    size_t need;
+    mw_status st = mw_ivi_work_bytes(plan, nroots, &need);
+    if (st != MW_OK) return st;
+    if (work_bytes < need) return fail(MW_EWORKSPACE, "work area too small");
+    if (((uintptr_t)work) & 255) return fail(MW_EWORKSPACE, "work area must be 256-byte aligned");
+    if (d->kind == MW_SPINOR)
+        return run_ivi_t<true>(plan, d, nroots, target, c0, c_out, evals, tol, max_iter, iters, work,
+                               (hipStream_t)stream);
+    return run_ivi_t<false>(plan, d, nroots, target, c0, c_out, evals, tol, max_iter, iters, work,
+                            (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

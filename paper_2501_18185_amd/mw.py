@@ -75,6 +75,11 @@ def lib():
         L.mw_pt2.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, C.POINTER(C.c_double),
                              C.POINTER(i64), vp]
         L.mw_select.argtypes = [vp, i32, vp, C.POINTER(C.c_double), C.c_double, vp, sz, vp, i64, C.POINTER(i64), vp]
+        L.mw_ivi_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+        L.mw_ivi.argtypes = [vp, i32, C.c_double, vp, vp, C.POINTER(C.c_double), C.c_double, i32, C.POINTER(i32),
+                             vp, sz, vp]
+        L.mw_ivi_work_bytes.restype = C.c_int
+        L.mw_ivi.restype = C.c_int
         L.mw_csf_create.argtypes = [vp, i32, C.POINTER(vp)]
         L.mw_csf_info.argtypes = [vp, i32]
         L.mw_csf_info.restype = i64
@@ -280,6 +285,29 @@ class Plan:
             _check(st)
         return np.array(list(ev)), out, it.value, conv
 
+
+    def ivi(self, c0, target=None, tol=1e-8, max_iter=200, check=True):
+        """Iterative vector interaction from start vectors c0 [ndet, nroots]:
+        the lowest roots (target None) or the roots nearest ``target``.
+        Returns (evals numpy, vectors tensor, iterations, converged)."""
+        torch = _require_gpu()
+        c0 = self._vec(c0)
+        if c0.dim() == 1:
+            c0 = c0[:, None].contiguous()
+        nroots = c0.shape[1]
+        nb = C.c_size_t()
+        _check(lib().mw_ivi_work_bytes(self._plan, nroots, C.byref(nb)))
+        work = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=c0.device)
+        out = torch.empty_like(c0)
+        ev = (C.c_double * nroots)()
+        it = C.c_int32()
+        tgt = float("nan") if target is None else float(target)
+        st = lib().mw_ivi(self._plan, nroots, tgt, C.c_void_p(c0.data_ptr()), C.c_void_p(out.data_ptr()), ev,
+                          float(tol), int(max_iter), C.byref(it), C.c_void_p(work.data_ptr()), nb.value, _stream())
+        conv = st == 0
+        if st not in (0, -7) or (check and not conv):
+            _check(st)
+        return np.array(list(ev)), out, it.value, conv
 
     def pt2_work_bytes(self, nroots=1):
         """Work bytes for a one-pass second-order energy without screening."""

@@ -82,6 +82,20 @@ def two_body_real(n: int, rng: np.random.Generator) -> np.ndarray:
     return val_canon.reshape(n, n, n, n)
 
 
+def chemistry_like_real(n: int, rng: np.random.Generator, off: float = 0.03):
+    """(h, g) with the structure of molecular integrals: orbital energies
+    h_pp = -2 + 0.6 p on the diagonal, Coulomb-like (pp|qq) = 0.3 added,
+    and the random integrals of ``one_body_real``/``two_body_real`` scaled
+    by ``off`` elsewhere, so the determinant Hamiltonian is diagonally
+    dominant (off-diagonal row sums ~0.1 against a diagonal spread ~10)."""
+    h = off * one_body_real(n, rng)
+    h[np.diag_indices(n)] = -2.0 + 0.6 * np.arange(n)
+    g = off * two_body_real(n, rng)
+    idx = np.arange(n)
+    g[idx[:, None], idx[:, None], idx[None, :], idx[None, :]] += 0.3
+    return h, g
+
+
 def one_body_spinor(nk: int, rng: np.random.Generator) -> np.ndarray:
     """Hermitian h over M = 2*nk spinors (A_k at k, B_k at nk+k).
 

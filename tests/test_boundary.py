@@ -116,3 +116,14 @@ def test_csf_host_counts_and_errors():
     ps = synth.Problem("spinor", nk, 3, -1, ds, synth.one_body_spinor(nk, rs), synth.two_body_spinor(nk, rs))
     assert mw.lib().mw_csf_create(mw.Plan(ps, upload=False)._plan, 1, C.byref(h)) == -8
     del sp
+
+
+def test_ivi_needs_uploaded_plan():
+    """mw_ivi and its work size refuse a plan without a workspace."""
+    pl = mw.Plan(synth.workload(0), upload=False)
+    nb = C.c_size_t()
+    assert mw.lib().mw_ivi_work_bytes(pl._plan, 1, C.byref(nb)) == -5
+    ev = (C.c_double * 1)()
+    it = C.c_int32()
+    assert mw.lib().mw_ivi(pl._plan, 1, float("nan"), C.c_void_p(16), C.c_void_p(32), ev, 1e-8, 10, C.byref(it),
+                           C.c_void_p(256), 1 << 20, None) == -5
