@@ -24,6 +24,8 @@ Further legs reported in the same line (skip with --legs none):
   rdm       forward sigma + energy and backward density matrices (gamma,
             Gamma) on the headline space;
   davidson  time per Davidson iteration on the headline space;
+  ivi       time per step of the iterative vector interaction solver
+            (lowest root) on the headline space;
   pt2       Epstein-Nesbet second-order energy of the lowest root of a
             20,000-determinant n=64 10a10b space over its external space
             (exact and screened), and the iCIPT2 selection of the next
@@ -35,7 +37,7 @@ Further legs reported in the same line (skip with --legs none):
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
                        [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
-                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson,pt2,csf|none]
+                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson,ivi,pt2,csf|none]
 """
 from __future__ import annotations
 
@@ -93,7 +95,7 @@ def main():
     ap.add_argument("--roots", type=int, default=1)
     ap.add_argument("--workload", default="sci-n64", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=30000, help="rows of the CPU oracle sample (0: skip)")
-    ap.add_argument("--legs", default="batched,spinor,rdm,davidson,pt2,csf")
+    ap.add_argument("--legs", default="batched,spinor,rdm,davidson,ivi,pt2,csf")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -214,6 +216,8 @@ def main():
         out["legs"]["rdm"] = leg_rdm(plan, c, prob)
     if "davidson" in legs:
         out["legs"]["davidson"] = leg_davidson(plan, prob)
+    if "ivi" in legs:
+        out["legs"]["ivi"] = leg_ivi(plan, prob)
     del plan, c, sig
     torch.cuda.empty_cache()
     if "batched" in legs:
@@ -305,6 +309,22 @@ def leg_davidson(plan, prob, iters=10):
     log(f"[bench] davidson: {it} iterations in {dt:.2f}s, E = {ev[0]:.10f}")
     return {"workload": prob.name, "iterations": it, "ms_per_iteration": dt * 1e3 / max(it, 1),
             "energy_after": float(ev[0])}
+
+
+def leg_ivi(plan, prob, steps=10):
+    """Wall time per iVI step (fixed step count, lowest root)."""
+    import time as _t
+
+    import torch
+    dg = plan.diag().cpu().numpy()
+    c0 = torch.zeros((prob.ndet, 1), dtype=plan.dtype, device="cuda")
+    c0[int(np.argmin(dg)), 0] = 1.0
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    ev, X, it, conv = plan.ivi(c0, tol=1e-12, max_iter=steps, check=False)
+    dt = _t.perf_counter() - t0
+    log(f"[bench] ivi: {it} steps in {dt:.2f}s, E = {ev[0]:.10f}")
+    return {"workload": prob.name, "steps": it, "ms_per_step": dt * 1e3 / max(it, 1), "energy_after": float(ev[0])}
 
 
 def leg_batched():
