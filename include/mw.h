@@ -201,7 +201,8 @@ mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out,
  * perturbation theory and conjugate gradients, a search space of fixed
  * dimension set by the number of roots, direct access to interior roots).
  * The space holds the current R vectors X, their first-order corrections
- * t_k = r_k / (theta_k - H_II) (r_k the residual) and the previous step's
+ * t_k = (r_k - eps_k x_k) / (theta_k - H_II) (r_k the residual, eps_k
+ * Olsen's: t_k orthogonal to x_k) and the previous step's
  * directions (the part of the new X outside the old one), 3R vectors at
  * most; each step diagonalises H there and keeps R Ritz pairs: the lowest
  * when target is NaN, otherwise the R nearest target (energy-selected), so
@@ -212,10 +213,11 @@ mw_status mw_davidson(mw_plan plan, int32_t nroots, const void *c0, void *c_out,
  * residual 2-norm <= tol.  work: device scratch of mw_ivi_work_bytes
  * bytes, 256-byte aligned (4 nroots vectors and their H products).
  * Host-driven, synchronises once per step; MW_ENOCONV with the last Ritz
- * pairs when max_iter is reached.  Roots inside a dense cluster of
- * eigenvalues converge slowly: the energy selection can move between
- * states of the cluster; targets separated from their neighbours converge
- * in a few tens of steps. */
+ * pairs when max_iter is reached.  Interior roots need a diagonally
+ * dominant H (the corrections divide by theta - H_II) and a target whose
+ * roots are separated from their neighbours; inside a dense cluster of
+ * eigenvalues the energy selection can move between states of the
+ * cluster and the iteration may not converge. */
 mw_status mw_ivi_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
 mw_status mw_ivi(mw_plan plan, int32_t nroots, double target, const void *c0, void *c_out, double *evals,
                  double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes, mw_stream_t stream);
@@ -316,6 +318,14 @@ mw_status mw_csf_destroy(mw_csf csf);
 mw_status mw_csf_davidson_work_bytes(mw_csf csf, int32_t nroots, size_t *bytes);
 mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c0, double *c_out, double *evals, double tol,
                           int32_t max_iter, int32_t *iters, void *work, size_t work_bytes, mw_stream_t stream);
+
+/* The iterative vector interaction of mw_ivi (same search space, selection
+ * and stop) in the CSF basis: spin-pure lowest roots (target NaN) or the
+ * spin-S roots nearest target, preconditioned as mw_csf_davidson.  c0,
+ * c_out: device [ncsf][nroots]; work: mw_csf_ivi_work_bytes bytes. */
+mw_status mw_csf_ivi_work_bytes(mw_csf csf, int32_t nroots, size_t *bytes);
+mw_status mw_csf_ivi(mw_csf csf, int32_t nroots, double target, const double *c0, double *c_out, double *evals,
+                     double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes, mw_stream_t stream);
 
 /* Debug: connected pairs of all rows with their phases, as int64 records
  * [I, J, P, Q, R, S, sign] (R = S = -1 for singles; P, R particles in I; Q, S

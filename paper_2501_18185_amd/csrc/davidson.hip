@@ -428,11 +428,13 @@ struct Davidson {
 
     // Iterative vector interaction over a search space of fixed dimension
     // (at most 3R): the current vectors X, their first-order corrections
-    // t_k = r_k / (theta_k - H_II) and the directions of the last step
+    // t_k = (r_k - eps_k x_k) / (theta_k - H_II) (Olsen's choice of eps_k
+    // makes t_k orthogonal to x_k) and the directions of the last step
     // P = X_new - X_old (X_old^H X_new), whose H P is carried along.  Each
     // step diagonalises H in that space and keeps R Ritz pairs: the lowest
     // (target NaN) or those nearest the target energy, without the roots
-    // below them.  One sigma of the corrections per step.  Buffers: V, W
+    // below them.  One sigma of the corrections per step (and of the
+    // directions in the last steps, see below).  Buffers: V, W
     // rows [0, 3R) for the space, rows [3R, 4R) for P and H P (mmax = 4R).
     mw_status run_ivi(const void *c0, void *c_out, double *evals, double tol, int max_iter, int *iters,
                       double target)
@@ -524,13 +526,33 @@ struct Davidson {
             m = R;
             for (int k = 0; k < R; k++) {
                 if (std::sqrt(std::max(rn[k].real(), 0.0)) <= tol) continue;
+                T *t = V + (size_t)m * N;
                 hipLaunchKernelGGL(k_precond<CPLX>, dim3(grid()), dim3(256), 0, s, Rv + (size_t)k * N, diag, theta[k],
-                                   N, V + (size_t)m * N);
+                                   N, t);
+                // Olsen: t - eps u with u = x / (theta - H_II) and eps
+                // = <x, t> / <x, u>, so that the correction is orthogonal
+                // to x (first order in the residual)
+                hipLaunchKernelGGL(k_precond<CPLX>, dim3(grid()), dim3(256), 0, s, X + (size_t)k * N, diag, theta[k],
+                                   N, Tn);
+                std::vector<cd> xt, xu;
+                if (!dots(X + (size_t)k * N, t, std::vector<int>{0}, std::vector<int>{0}, xt) ||
+                    !dots(X + (size_t)k * N, Tn, std::vector<int>{0}, std::vector<int>{0}, xu))
+                    return fail(MW_EHIP, "dot products failed");
+                if (std::abs(xu[0]) > 1e-300) {
+                    std::vector<cd> C{-xt[0] / xu[0]};
+                    if (!lincomb(Tn, 1, C, 1, t, std::vector<double>{1.0})) return fail(MW_EHIP, "correction failed");
+                }
                 double nrm;
                 if (!orthonormalize(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
                 if (nrm >= 1e-10) m++;
             }
             if (m > R && (st = apply_h(R, m - R)) != MW_OK) return st;
+            // H P is carried along with P, but normalising a direction that
+            // Gram-Schmidt left short divides the rounding error of its
+            // carried product by that length: below 1e-2 the products of
+            // the directions are computed afresh (near convergence only)
+            const int p0 = m;
+            bool fresh = false;
             for (int k = 0; k < np; k++) {
                 if (hipMemcpyAsync(V + (size_t)m * N, Pv + (size_t)k * N, N * sizeof(T), hipMemcpyDeviceToDevice, s) !=
                         hipSuccess ||
@@ -539,8 +561,12 @@ struct Davidson {
                     return fail(MW_EHIP, "copy failed");
                 double nrm;
                 if (!orthonormalize_vw(m, nrm)) return fail(MW_EHIP, "Gram-Schmidt failed");
-                if (nrm >= 1e-10) m++;
+                if (nrm >= 1e-10) {
+                    m++;
+                    fresh = fresh || nrm < 1e-2;
+                }
             }
+            if (fresh && (st = apply_h(p0, m - p0)) != MW_OK) return st;
             if (m == R) break;  // no new direction: stagnation
         }
         hipLaunchKernelGGL(k_pack<T>, dim3(grid()), dim3(256), 0, s, X, R, N, (T *)c_out, 1);
@@ -673,9 +699,9 @@ extern "C" mw_status mw_ivi(mw_plan plan, int32_t nroots, double target, const v
 extern "C" int mw_internal_csf_dims(mw_csf csf, mw_plan *plan, int64_t *ndet, int64_t *ncsf);
 extern "C" mw_status mw_internal_csf_diag(mw_csf csf, const double *hdiag, double *out, hipStream_t s);
 
-static size_t csf_dav_bytes(int R, int64_t ndet, int64_t ncsf)
+static size_t csf_dav_bytes(int R, int64_t ndet, int64_t ncsf, int mmax)
 {
-    size_t b = Davidson<false>::bytes(R, ncsf);
+    size_t b = Davidson<false>::bytes_m(mmax, R, ncsf);
     b = (b + 255) & ~(size_t)255;
     b += (size_t)2 * ndet * R * 8;   // determinant vectors of mw_csf_sigma
     b = (b + 255) & ~(size_t)255;
@@ -693,13 +719,14 @@ extern "C" mw_status mw_csf_davidson_work_bytes(mw_csf csf, int32_t nroots, size
     const DevPlan *d = mw_internal_devplan(plan);
     if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace");
     if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
-    *bytes = csf_dav_bytes(nroots, ndet, ncsf);
+    *bytes = csf_dav_bytes(nroots, ndet, ncsf, std::max(8 * nroots, 24) + nroots);
     return MW_OK;
 }
 
-extern "C" mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c0, double *c_out, double *evals,
-                                     double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
-                                     mw_stream_t stream)
+// solver 0: Davidson (mmax = max(8R, 24) + R); 1: iVI (mmax = 4R)
+static mw_status csf_solve(int solver, mw_csf csf, int32_t nroots, double target, const double *c0, double *c_out,
+                           double *evals, double tol, int32_t max_iter, int32_t *iters, void *work,
+                           size_t work_bytes, mw_stream_t stream)
 {
     mw_plan plan;
     int64_t ndet, ncsf;
@@ -708,19 +735,21 @@ extern "C" mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c
         return fail(MW_EWORKSPACE, "CSF basis has no workspace: call mw_csf_upload first");
     if (!c0 || !c_out || !evals || !iters || !work) return fail(MW_EINVAL, "NULL argument");
     if (!(tol > 0) || max_iter < 1) return fail(MW_EINVAL, "tol must be > 0 and max_iter >= 1");
-    size_t need;
-    mw_status st = mw_csf_davidson_work_bytes(csf, nroots, &need);
-    if (st != MW_OK) return st;
-    if (nroots > ncsf) return fail(MW_EINVAL, "more roots than CSFs");
-    if (work_bytes < need) return fail(MW_EWORKSPACE, "work area too small");
-    if (((uintptr_t)work) & 255) return fail(MW_EWORKSPACE, "work area must be 256-byte aligned");
+    if (solver == 1 && std::isinf(target)) return fail(MW_EINVAL, "target must be finite (NaN for the lowest roots)");
     const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
+    if (nroots > ncsf) return fail(MW_EINVAL, "more roots than CSFs");
+    const int mmax = solver == 1 ? 4 * nroots : std::max(8 * nroots, 24) + nroots;
+    if (work_bytes < csf_dav_bytes(nroots, ndet, ncsf, mmax)) return fail(MW_EWORKSPACE, "work area too small");
+    if (((uintptr_t)work) & 255) return fail(MW_EWORKSPACE, "work area must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    size_t off = (Davidson<false>::bytes(nroots, ncsf) + 255) & ~(size_t)255;
+    size_t off = (Davidson<false>::bytes_m(mmax, nroots, ncsf) + 255) & ~(size_t)255;
     double *dwork = (double *)((char *)work + off);
     off = (off + (size_t)2 * ndet * nroots * 8 + 255) & ~(size_t)255;
     double *pdiag = (double *)((char *)work + off);
-    if ((st = mw_internal_csf_diag(csf, (const double *)d->diag, pdiag, s)) != MW_OK) return st;
+    mw_status st = mw_internal_csf_diag(csf, (const double *)d->diag, pdiag, s);
+    if (st != MW_OK) return st;
     Davidson<false> D;
     D.sigma = [csf, dwork, s](int k, const double *in, double *out) {
         return mw_csf_sigma(csf, k, in, out, dwork, (mw_stream_t)s);
@@ -728,8 +757,37 @@ extern "C" mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c
     D.diag = pdiag;
     D.s = s;
     D.R = nroots;
-    D.mmax = std::max(8 * nroots, 24) + nroots;
+    D.mmax = mmax;
     D.N = ncsf;
     D.carve((char *)work);
+    if (solver == 1) return D.run_ivi(c0, c_out, evals, tol, max_iter, iters, target);
     return D.run(c0, c_out, evals, tol, max_iter, iters);
+}
+
+extern "C" mw_status mw_csf_ivi_work_bytes(mw_csf csf, int32_t nroots, size_t *bytes)
+{
+    mw_plan plan;
+    int64_t ndet, ncsf;
+    if (!csf || !bytes) return fail(MW_EINVAL, "NULL argument");
+    if (!mw_internal_csf_dims(csf, &plan, &ndet, &ncsf))
+        return fail(MW_EWORKSPACE, "CSF basis has no workspace: call mw_csf_upload first");
+    const DevPlan *d = mw_internal_devplan(plan);
+    if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace");
+    if (nroots < 1 || nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
+    *bytes = csf_dav_bytes(nroots, ndet, ncsf, 4 * nroots);
+    return MW_OK;
+}
+
+extern "C" mw_status mw_csf_ivi(mw_csf csf, int32_t nroots, double target, const double *c0, double *c_out,
+                                double *evals, double tol, int32_t max_iter, int32_t *iters, void *work,
+                                size_t work_bytes, mw_stream_t stream)
+{
+    return csf_solve(1, csf, nroots, target, c0, c_out, evals, tol, max_iter, iters, work, work_bytes, stream);
+}
+
+extern "C" mw_status mw_csf_davidson(mw_csf csf, int32_t nroots, const double *c0, double *c_out, double *evals,
+                                     double tol, int32_t max_iter, int32_t *iters, void *work, size_t work_bytes,
+                                     mw_stream_t stream)
+{
+    return csf_solve(0, csf, nroots, 0.0, c0, c_out, evals, tol, max_iter, iters, work, work_bytes, stream);
 }

@@ -92,9 +92,12 @@ def lib():
         L.mw_csf_davidson_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
         L.mw_csf_davidson.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), C.c_double, i32, C.POINTER(i32), vp,
                                       sz, vp]
+        L.mw_csf_ivi_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+        L.mw_csf_ivi.argtypes = [vp, i32, C.c_double, vp, vp, C.POINTER(C.c_double), C.c_double, i32,
+                                 C.POINTER(i32), vp, sz, vp]
         for name in ("mw_csf_create", "mw_csf_workspace_bytes", "mw_csf_upload", "mw_csf_to_det",
                      "mw_csf_from_det", "mw_csf_sigma", "mw_csf_destroy", "mw_csf_davidson_work_bytes",
-                     "mw_csf_davidson"):
+                     "mw_csf_davidson", "mw_csf_ivi_work_bytes", "mw_csf_ivi"):
             getattr(L, name).restype = C.c_int
         for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
                      "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
@@ -449,27 +452,40 @@ class Csf:
                                   C.c_void_p(work.data_ptr()), _stream()))
         return out
 
-    def davidson(self, c0, tol=1e-8, max_iter=100, check=True):
-        """Lowest spin-S eigenpairs from start vectors c0 [ncsf, nroots].
-        Returns (evals numpy, vectors tensor, iterations, converged)."""
+    def _solve(self, c0, target, tol, max_iter, check):
         torch = _require_gpu()
         c0 = self._vec(c0, self.ncsf)
         if c0.dim() == 1:
             c0 = c0[:, None].contiguous()
         nroots = c0.shape[1]
         nb = C.c_size_t()
-        _check(lib().mw_csf_davidson_work_bytes(self._csf, nroots, C.byref(nb)))
+        L = lib()
+        wb = L.mw_csf_davidson_work_bytes if target is False else L.mw_csf_ivi_work_bytes
+        _check(wb(self._csf, nroots, C.byref(nb)))
         work = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=c0.device)
         out = torch.empty_like(c0)
         ev = (C.c_double * nroots)()
         it = C.c_int32()
-        st = lib().mw_csf_davidson(self._csf, nroots, C.c_void_p(c0.data_ptr()), C.c_void_p(out.data_ptr()), ev,
-                                   float(tol), int(max_iter), C.byref(it), C.c_void_p(work.data_ptr()), nb.value,
-                                   _stream())
+        args = (C.c_void_p(c0.data_ptr()), C.c_void_p(out.data_ptr()), ev, float(tol), int(max_iter), C.byref(it),
+                C.c_void_p(work.data_ptr()), nb.value, _stream())
+        if target is False:
+            st = L.mw_csf_davidson(self._csf, nroots, *args)
+        else:
+            st = L.mw_csf_ivi(self._csf, nroots, float("nan") if target is None else float(target), *args)
         conv = st == 0
         if st not in (0, -7) or (check and not conv):
             _check(st)
         return np.array(list(ev)), out, it.value, conv
+
+    def davidson(self, c0, tol=1e-8, max_iter=100, check=True):
+        """Lowest spin-S eigenpairs from start vectors c0 [ncsf, nroots].
+        Returns (evals numpy, vectors tensor, iterations, converged)."""
+        return self._solve(c0, False, tol, max_iter, check)
+
+    def ivi(self, c0, target=None, tol=1e-8, max_iter=200, check=True):
+        """Spin-S roots by iterative vector interaction: the lowest (target
+        None) or those nearest ``target``; returns as :meth:`davidson`."""
+        return self._solve(c0, target, tol, max_iter, check)
 
 
 def profile(enable: bool):

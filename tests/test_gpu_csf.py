@@ -257,3 +257,43 @@ def test_csf_single_closed_shell(torch):
     c = np.array([[0.75]])
     ref = csf.sigma(prob, 0, c, sc.sigma)
     assert _rel(cb.sigma(_dev(torch, c)).cpu().numpy(), ref) < TOL
+
+
+@pytest.mark.parametrize("seed", [5, 7])
+def test_csf_ivi_interior_singlets(torch, seed):
+    """Spin-pure interior roots: the two singlets nearest a target inside
+    the singlet spectrum of a diagonally dominant FCI problem (n = 8, 4a4b),
+    against the oracle's dense T^T H T; the best-separated pair among the
+    5th-200th singlets (for seed 6 that pair lies within twice its own
+    spacing of the next singlet, outside the solver's stated regime).  Also
+    the lowest singlet."""
+    from paper_2501_18185_amd import mw
+    h, g = synth.chemistry_like_real(8, np.random.default_rng(seed))
+    prob = synth.Problem("spinfree", 8, 4, 4, synth.space_fci(8, 4, 4), h, g)
+    T, _ = csf.expansion(prob, 0)
+    Td = T.toarray()
+    Hc = Td.T @ sc.dense_h(prob) @ Td
+    e = np.linalg.eigvalsh(Hc)
+    dgc = np.diag(Hc)
+    cand = []
+    for i in range(5, 200):
+        inner, outer = e[i + 1] - e[i], min(e[i] - e[i - 1], e[i + 2] - e[i + 1])
+        if inner < outer:
+            cand.append((outer, i))
+    cand.sort(reverse=True)
+    i = cand[0][1]
+    tau = 0.5 * (e[i] + e[i + 1])
+    _say(f"case chem-n8 seed {seed}: CSF iVI target {tau:.6f} (singlets {i}, {i + 1})")
+    pl, cb = _basis(prob, 2)
+    c0 = np.zeros((cb.ncsf, 2))
+    c0[np.argsort(np.abs(dgc - tau), kind="stable")[:2], [0, 1]] = 1.0
+    ev, X, it, conv = cb.ivi(_dev(torch, c0), target=tau, tol=1e-9, max_iter=300)
+    _say(f"  {it} steps")
+    assert conv
+    assert np.abs(ev - e[i:i + 2]).max() < 1e-10 * max(1.0, np.abs(e).max())
+    Xn = X.cpu().numpy()
+    assert np.abs(Hc @ Xn - Xn * ev[None, :]).max() < 1e-7
+    c1 = np.zeros((cb.ncsf, 1))
+    c1[int(np.argmin(dgc)), 0] = 1.0
+    ev1, _, it1, conv1 = cb.ivi(_dev(torch, c1), tol=1e-9, max_iter=300)
+    assert conv1 and abs(ev1[0] - e[0]) < 1e-10 * max(1.0, abs(e[0]))
