@@ -34,6 +34,16 @@
 #include "mw_internal.h"
 #include "dev_common.h"
 
+// Partial sums are written once and read only by the gather, after the
+// group kernels: non-temporal stores keep them from displacing integral
+// rows and coefficients in L2 (0.3 % faster sigma on the headline space).
+template <typename T> __device__ __forceinline__ void nt_store(T v, T *p) { __builtin_nontemporal_store(v, p); }
+template <> __device__ __forceinline__ void nt_store<double2>(double2 v, double2 *p)
+{
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 namespace mw {
 
 // ---------------------------------------------------------------------------
@@ -247,7 +257,7 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
                 const uint32_t j = jj + vi / RC;
                 const int kk = vi % RC;
                 if (j < jb1 && kk < nr)
-                    partial[(colbase + (j - j0) - 64 * (a + 1)) * R + r0 + kk] = s;
+                    nt_store(s, &partial[(colbase + (j - j0) - 64 * (a + 1)) * R + r0 + kk]);
             }
         }
     }
@@ -255,7 +265,7 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
         T *out = partial + (size_t)m * R + r0;
 #pragma unroll
         for (int kk = 0; kk < RC; kk++)
-            if (kk < nr) out[kk] = sc_add(acc[kk], dacc[kk]);
+            if (kk < nr) nt_store(sc_add(acc[kk], dacc[kk]), &out[kk]);
     }
 }
 
@@ -333,7 +343,7 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
     T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
-        if (k < nr) out[k] = acc[k];
+        if (k < nr) nt_store(acc[k], &out[k]);
 }
 
 // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8).
@@ -443,7 +453,7 @@ __device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave
     T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
-        if (k < nr) out[k] = acc[k];
+        if (k < nr) nt_store(acc[k], &out[k]);
 }
 
 template <bool CPLX, int RC>
