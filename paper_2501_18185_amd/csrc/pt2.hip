@@ -278,7 +278,7 @@ template <bool CPLX, int MODE>
 __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetSet inP, int R,
                                                   const typename Scal<CPLX>::T *__restrict__ c, double qmin,
                                                   int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt,
-                                                  const uint64_t *__restrict__ off, uint32_t *fill, Rec *rec,
+                                                  const uint64_t *__restrict__ off, unsigned long long *fill, Rec *rec,
                                                   typename Scal<CPLX>::T *val, const double *__restrict__ eps,
                                                   const double *__restrict__ vg, unsigned long long *total,
                                                   int64_t jbase, uint32_t kmask)
@@ -330,8 +330,11 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
                 atomicAdd(&cnt[b], 1u);
             } else {
                 if (b < b0 || b >= b1) continue;
-                const uint32_t k = atomicAdd(&fill[b], 1u);
-                if (k >= cnt[b]) continue;
+                // one 64-bit word per bucket: the claim count below, the
+                // bucket's capacity above, so the claim needs no second read
+                const unsigned long long wv = atomicAdd(&fill[b], 1ULL);
+                const uint32_t k = (uint32_t)wv;
+                if (k >= (uint32_t)(wv >> 32)) continue;
                 const uint64_t slot = off[b] + k;
                 double hjj;
                 if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
@@ -876,6 +879,14 @@ __global__ void k_fill_u32(uint32_t *x, int64_t n, uint32_t v)
     if (i < n) x[i] = v;
 }
 
+// claim words of the emit pass: capacity (the bucket's count) in the high
+// half, claims (0) in the low half
+__global__ void k_fill_cap(unsigned long long *w, const uint32_t *cnt, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = (unsigned long long)cnt[i] << 32;
+}
+
 void fill_u32(uint32_t *x, int64_t n, hipStream_t s, uint32_t v = 0u)
 {
     if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
@@ -942,7 +953,7 @@ size_t fixed_bytes(int64_t ndet, int M)
 
 size_t table_bytes(int64_t NB, int R)
 {
-    return align256(4 * (size_t)NB) * 3 + align256(8 * (size_t)NB) + align256(8 * (size_t)NB * R) +
+    return align256(4 * (size_t)NB) * 2 + align256(8 * (size_t)NB) * 2 + align256(8 * (size_t)NB * R) +
            align256(16 * (size_t)NB) + 1024 + 512;
 }
 
@@ -1122,7 +1133,8 @@ constexpr int64_t PT2_MAXGRID = (int64_t)1 << 22;
 
 template <bool CPLX, int MODE>
 void launch_enum(const DevPlan &d, const ExcClasses &ex, const DetSet &inP, int R, const typename Scal<CPLX>::T *c,
-                 double qmin, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt, const uint64_t *off, uint32_t *fill,
+                 double qmin, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt, const uint64_t *off,
+                 unsigned long long *fill,
                  Rec *rec, typename Scal<CPLX>::T *val, const double *eps, const double *vg, unsigned long long *tot,
                  hipStream_t s)
 {
@@ -1236,7 +1248,7 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
                 const int64_t NB = (int64_t)1 << lognb;
                 used = fixed;
                 uint32_t *cnt = (uint32_t *)take(4 * (size_t)NB);
-                uint32_t *fill = (uint32_t *)take(4 * (size_t)NB);
+                unsigned long long *fill = (unsigned long long *)take(8 * (size_t)NB);
                 uint64_t *off = (uint64_t *)take(8 * (size_t)NB);
                 double *part = (double *)take(8 * (size_t)NB * R);
                 unsigned long long *partc = (unsigned long long *)take(16 * (size_t)NB);
@@ -1278,7 +1290,8 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
                     }
                     if (b1 == b0) return fail(MW_EWORKSPACE, "pt2: work buffer too small for one bucket");
                     hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
-                    fill_u32(fill + b0, b1 - b0, s);
+                    hipLaunchKernelGGL(k_fill_cap, dim3((unsigned)((b1 - b0 + 255) / 256)), dim3(256), 0, s, fill + b0,
+                                       (const uint32_t *)cnt + b0, (int64_t)(b1 - b0));
                     ProfToken t = prof_begin("pt2_enum", s);
                     launch_enum<CPLX, 2>(d, ex, inP, R, c, qmin, lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, rec,
                                          val, eps, vg, nullptr, s);
