@@ -35,13 +35,23 @@
 #include "dev_common.h"
 
 // Partial sums are written once and read only by the gather, after the
-// group kernels: non-temporal stores keep them from displacing integral
-// rows and coefficients in L2 (0.3 % faster sigma on the headline space).
-template <typename T> __device__ __forceinline__ void nt_store(T v, T *p) { __builtin_nontemporal_store(v, p); }
-template <> __device__ __forceinline__ void nt_store<double2>(double2 v, double2 *p)
+// group kernels: for one root, non-temporal stores keep them from
+// displacing integral rows and coefficients in L2 (0.3 % faster sigma on
+// the headline space); for 2-4 roots per lane (four times the bytes) they
+// were slower (4 roots: 18.66 against 17.91 ms) and plain stores are kept.
+template <int RC, typename T> __device__ __forceinline__ void nt_store(T v, T *p)
 {
-    __builtin_nontemporal_store(v.x, &p->x);
-    __builtin_nontemporal_store(v.y, &p->y);
+    if constexpr (RC == 1) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <int RC> __device__ __forceinline__ void nt_store(double2 v, double2 *p)
+{
+    if constexpr (RC == 1) {
+        __builtin_nontemporal_store(v.x, &p->x);
+        __builtin_nontemporal_store(v.y, &p->y);
+    } else {
+        *p = v;
+    }
 }
 
 namespace mw {
@@ -257,7 +267,7 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
                 const uint32_t j = jj + vi / RC;
                 const int kk = vi % RC;
                 if (j < jb1 && kk < nr)
-                    nt_store(s, &partial[(colbase + (j - j0) - 64 * (a + 1)) * R + r0 + kk]);
+                    nt_store<RC>(s, &partial[(colbase + (j - j0) - 64 * (a + 1)) * R + r0 + kk]);
             }
         }
     }
@@ -265,7 +275,7 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
         T *out = partial + (size_t)m * R + r0;
 #pragma unroll
         for (int kk = 0; kk < RC; kk++)
-            if (kk < nr) nt_store(sc_add(acc[kk], dacc[kk]), &out[kk]);
+            if (kk < nr) nt_store<RC>(sc_add(acc[kk], dacc[kk]), &out[kk]);
     }
 }
 
@@ -343,7 +353,7 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
     T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
-        if (k < nr) nt_store(acc[k], &out[k]);
+        if (k < nr) nt_store<RC>(acc[k], &out[k]);
 }
 
 // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8).
@@ -453,7 +463,7 @@ __device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave
     T *out = partial + (size_t)m * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
-        if (k < nr) nt_store(acc[k], &out[k]);
+        if (k < nr) nt_store<RC>(acc[k], &out[k]);
 }
 
 template <bool CPLX, int RC>
