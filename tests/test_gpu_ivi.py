@@ -125,3 +125,21 @@ def test_ivi_equals_davidson_n64(torch):
     _say(f"  iVI {it} steps, Davidson {itd}")
     assert conv and convd
     assert abs(ev[0] - evd[0]) < 1e-10 * max(1.0, abs(evd[0]))
+
+
+def test_ivi_not_converged_returns_last_ritz_pairs(torch):
+    """max_iter reached: MW_ENOCONV with the last Ritz pairs (finite, above
+    the lowest eigenvalue, vectors orthonormal); with check=True it raises."""
+    from paper_2501_18185_amd import mw
+    p = synth.workload(0)
+    pl = mw.Plan(p, max_roots=2)
+    dg = pl.diag().cpu().numpy()
+    H = sc.dense_h(p)
+    e0 = np.linalg.eigvalsh(H)[0]
+    ev, X, it, conv = pl.ivi(_start(torch, dg, 2), tol=1e-12, max_iter=2, check=False)
+    assert not conv and it == 2
+    assert np.all(np.isfinite(ev)) and ev[0] >= e0 - 1e-10
+    Xn = X.cpu().numpy()
+    assert np.abs(Xn.T @ Xn - np.eye(2)).max() < 1e-12
+    with pytest.raises(mw.MWError):
+        pl.ivi(_start(torch, dg, 2), tol=1e-12, max_iter=2)
