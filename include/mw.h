@@ -117,7 +117,9 @@ mw_status mw_plan_destroy(mw_plan plan);
  * evaluations per sigma (including the discarded ones), 7 workspace bytes,
  * 8 scalar size in bytes (8 or 16), 9 norb, 10 kind, 11 packets (waves of
  * the group launches), 12 packets of double groups, 13 column partial sums
- * of the large double groups.  Returns -1 for an unknown plan or index. */
+ * of the large double groups, 14 ordered double-excitation pairs inside
+ * groups of 64 members or more (evaluated once per unordered pair).
+ * Returns -1 for an unknown plan or index. */
 int64_t mw_plan_info(mw_plan plan, int32_t what);
 
 /* sigma_I = sum_J H_IJ c_J for nroots (1..max_roots) vectors: the product of
@@ -183,6 +185,42 @@ mw_status mw_diag(mw_plan plan, void *out, mw_stream_t stream);
  * the same matrices to rounding, half the atomics. */
 mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *bra, const void *ket,
                           const double *weights, void *gamma, void *Gamma, mw_stream_t stream);
+
+/* Energies e_k = Re sum_I conj(c_Ik) sigma_Ik (the expectation value
+ * c^H H c of section 2.4 when sigma = H c, unnormalised), one per root:
+ * c, sigma device [ndet][nroots]; e device [nroots] doubles, overwritten.
+ * A two-stage reduction in a fixed order (block partials in the plan's
+ * per-call scratch, so it must not overlap another call on the plan):
+ * repeated calls give the same bits.  Asynchronous on stream. */
+mw_status mw_energy(mw_plan plan, int32_t nroots, const void *c, const void *sigma, double *e, mw_stream_t stream);
+
+/* Gradients of the energies E_k = c_k^H H c_k weighted by the upstream
+ * gradients ge (device [nroots] doubles), L = sum_k ge_k E_k:
+ *   grad_c[I][k] = 2 ge_k sigma[I][k]          (sigma = H c from mw_sigma)
+ *   grad_h = sum_k ge_k gamma_k,  grad_g = 1/2 sum_k ge_k Gamma_k
+ * with gamma_k, Gamma_k the density matrices of root k (as mw_rdm_backward
+ * with bra = ket = c), since E = sum h gamma + 1/2 sum (PQ|RS) Gamma for
+ * Eq. (1).  Complex problems: grad_h and grad_g are conjugated (gradient of
+ * a real loss w.r.t. complex inputs, dL = Re sum conj(grad) dz).
+ * grad_c device [ndet][nroots] or NULL (then sigma may be NULL); grad_h
+ * [M][M] and grad_g [M]^4 (M = n spin-free, 2n spinor) both device or both
+ * NULL.  Connectivity is recomputed; uses the plan's per-call scratch.
+ * Asynchronous on stream; device atomics make the integral gradients
+ * reproducible to rounding. */
+mw_status mw_energy_backward(mw_plan plan, int32_t nroots, const void *c, const void *sigma, const double *ge,
+                             void *grad_c, void *grad_h, void *grad_g, mw_stream_t stream);
+
+/* Vector-Jacobian products of sigma = H c for an upstream gradient gs
+ * (device [ndet][nroots], the gradient of a loss with respect to sigma):
+ *   grad_c = H gs  (H Hermitian),
+ *   grad_h = conj(gamma(gs, c)),  grad_g = 1/2 conj(Gamma(gs, c))
+ * with gamma(gs, c), Gamma(gs, c) the transition density matrices of
+ * mw_rdm_backward with bra = gs, ket = c, summed over the roots
+ * (conjugation only for complex problems).  grad_c device [ndet][nroots]
+ * or NULL (must not overlap gs); grad_h, grad_g both device or both NULL.
+ * Uses the plan's per-call scratch; asynchronous on stream. */
+mw_status mw_sigma_backward(mw_plan plan, int32_t nroots, const void *c, const void *gs, void *grad_c, void *grad_h,
+                            void *grad_g, mw_stream_t stream);
 
 /* Lowest nroots eigenpairs by block Davidson-Liu over mw_sigma (section 2.4
  * uses sigma = H X products for the diagonalisation).  c0: device

@@ -253,6 +253,34 @@ void orc_degree_rows(int n, long ndet, const uint64_t *dets, long nrows, const l
     }
 }
 
+/* Number of ordered pairs (I, J), I != J, of the whole space that H
+ * connects, split by excitation level: out[0] singles, out[1] doubles.
+ * Every determinant of a space holds the same electron counts (spin-free:
+ * the same N_alpha and N_beta, which the caller checks), so the number of
+ * electrons moved is popcount(I xor J) / 2 and the pair is connected when
+ * that is 1 or 2 (section 2.3: zero-, one- and two-electron differences).
+ * Every pair is visited; only the counting loop uses the popcount
+ * instruction, so the timed rows of orc_sigma_rows are built as before. */
+__attribute__((target("popcnt")))
+void orc_pair_counts(long ndet, const uint64_t *dets, long *out)
+{
+    long c1 = 0, c2 = 0;
+    #pragma omp parallel for schedule(dynamic, 64) reduction(+ : c1, c2)
+    for (long i = 0; i < ndet; i++) {
+        const uint64_t a0 = dets[2 * i], a1 = dets[2 * i + 1];
+        long s1 = 0, s2 = 0;
+        for (long j = 0; j < ndet; j++) {
+            const int x = __builtin_popcountll(a0 ^ dets[2 * j]) + __builtin_popcountll(a1 ^ dets[2 * j + 1]);
+            s1 += (x == 2);
+            s2 += (x == 4);
+        }
+        c1 += s1;
+        c2 += s2;
+    }
+    out[0] = c1;
+    out[1] = c2;
+}
+
 /* Connected pairs of the requested rows, J ascending.  Record layout
  * (int64 x 7): I, J, P, Q, R, S, sign  (R = S = -1 for singles).
  * First call with out == NULL returns the count. */

@@ -30,6 +30,7 @@ def lib():
         L.orc_degree_rows.argtypes = [C.c_int, C.c_long, up, C.c_long, lp, lp]
         L.orc_connect_rows.argtypes = [C.c_int, C.c_long, up, C.c_long, lp, lp]
         L.orc_connect_rows.restype = C.c_long
+        L.orc_pair_counts.argtypes = [C.c_long, up, lp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_rdm_rows.argtypes = [C.c_int, C.c_int, C.c_long, up, C.c_int, dp, dp, dp, C.c_long,
@@ -129,6 +130,25 @@ def degree_rows(prob, rows=None):
     lib().orc_degree_rows(prob.norb, len(dets), _p(dets, C.c_uint64), len(rows), _p(rows, C.c_long),
                           _p(out, C.c_long))
     return out
+
+
+def pair_counts(prob):
+    """Ordered connected pairs (I != J) of the whole space by excitation
+    level: (singles, doubles).  Every pair of the space is visited."""
+    dets = np.ascontiguousarray(prob.dets, dtype=np.uint64)
+    pc = np.vectorize(lambda x: bin(int(x)).count("1"), otypes=[np.int64])
+    if len(dets):
+        if prob.kind == "spinfree":
+            na, nb = pc(dets[:, 0]), pc(dets[:, 1])
+            if na.min() != na.max() or nb.min() != nb.max():
+                raise ValueError("spin-free determinants must share N_alpha and N_beta")
+        else:
+            ne = pc(dets[:, 0]) + pc(dets[:, 1])
+            if ne.min() != ne.max():
+                raise ValueError("determinants must share the electron count")
+    out = np.zeros(2, dtype=np.int64)
+    lib().orc_pair_counts(len(dets), _p(dets, C.c_uint64), _p(out, C.c_long))
+    return int(out[0]), int(out[1])
 
 
 def connect_rows(prob, rows=None):

@@ -1,8 +1,9 @@
 """Differentiable sigma and energy on top of libmw (torch.autograd).
 
-``Energy.apply(c, h, g, plan)`` returns E = c^H H(h, g) c.  Its backward
-runs the library's density-matrix adjoint, which recomputes the determinant
-connectivity instead of storing it:
+``Energy.apply(c, h, g, plan)`` returns the energies E_k = c_k^H H(h, g) c_k
+(a scalar for c of shape [ndet], one per root for [ndet, nroots]).  Its
+backward runs the library's density-matrix adjoint, which recomputes the
+determinant connectivity instead of storing it:
 
     dE/dh = gamma,   dE/dg = Gamma / 2,   dE/dc = 2 H c  (real c)
 
@@ -14,7 +15,10 @@ the transition density matrices between that gradient and c.
 ``h`` and ``g`` are CPU tensors laid out as in the problem (spin-free real
 n x n and n^4; spinor complex M x M and M^4).  When they differ from the
 integrals the plan holds, the plan is updated in place (no regrouping).
-Only the argument marshalling happens here; the arithmetic runs in libmw.
+Only argument marshalling happens here: the energies, the scaling by the
+upstream gradient, the factor 1/2 and the conjugation of complex integral
+gradients all run in libmw (mw_energy, mw_energy_backward,
+mw_sigma_backward).
 """
 from __future__ import annotations
 
@@ -36,6 +40,8 @@ def _sync_integrals(plan: mw.Plan, h: torch.Tensor, g: torch.Tensor, ecore: floa
 
 
 def _to(x, meta):
+    if x is None:
+        return None
     dtype, device = meta
     return x.to(device=device, dtype=dtype)
 
@@ -45,31 +51,21 @@ class Energy(torch.autograd.Function):
     def forward(ctx, c, h, g, plan, ecore=0.0):
         _sync_integrals(plan, h, g, ecore)
         sigma = plan.sigma(c)
-        e = torch.sum(c.conj() * sigma).real
+        e = plan.energy(c, sigma)
         ctx.save_for_backward(c, sigma)
         ctx.plan = plan
         ctx.h_meta = (h.dtype, h.device)
         ctx.g_meta = (g.dtype, g.device)
-        return e
+        return e.reshape(()) if c.dim() == 1 else e
 
     @staticmethod
     def backward(ctx, ge):
         c, sigma = ctx.saved_tensors
-        plan = ctx.plan
-        grad_c = grad_h = grad_g = None
-        if ctx.needs_input_grad[0]:
-            # real c: dE/dc = 2 sigma; complex c: torch's convention for a
-            # real loss is the conjugate Wirtinger derivative times 2
-            grad_c = 2.0 * ge * sigma
-        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
-            gam, Gam = plan.rdm(c, c)
-            if ctx.needs_input_grad[1]:
-                gh = gam if plan.is_complex else gam.real
-                grad_h = _to(ge * gh if not plan.is_complex else ge * gh.conj(), ctx.h_meta)
-            if ctx.needs_input_grad[2]:
-                gg = 0.5 * Gam
-                grad_g = _to(ge * gg if not plan.is_complex else ge * gg.conj(), ctx.g_meta)
-        return grad_c, grad_h, grad_g, None, None
+        want_c = ctx.needs_input_grad[0]
+        want_int = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        gc, gh, gg = ctx.plan.energy_backward(c, sigma, ge, want_c, want_int)
+        return (gc, _to(gh, ctx.h_meta) if ctx.needs_input_grad[1] else None,
+                _to(gg, ctx.g_meta) if ctx.needs_input_grad[2] else None, None, None)
 
 
 class Sigma(torch.autograd.Function):
@@ -86,18 +82,8 @@ class Sigma(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gs):
         (c,) = ctx.saved_tensors
-        plan = ctx.plan
-        gs = gs.contiguous()
-        grad_c = grad_h = grad_g = None
-        if ctx.needs_input_grad[0]:
-            grad_c = plan.sigma(gs)
-        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
-            if plan.is_complex:
-                raise NotImplementedError("integral gradients of Sigma are provided for real problems")
-            # L = gs^T H c  ->  dL/dh = gamma(gs, c), dL/dg = Gamma(gs, c) / 2
-            gam, Gam = plan.rdm(gs, c)
-            if ctx.needs_input_grad[1]:
-                grad_h = _to(gam, ctx.h_meta)
-            if ctx.needs_input_grad[2]:
-                grad_g = _to(0.5 * Gam, ctx.g_meta)
-        return grad_c, grad_h, grad_g, None, None
+        want_c = ctx.needs_input_grad[0]
+        want_int = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        gc, gh, gg = ctx.plan.sigma_backward(c, gs.contiguous(), want_c, want_int)
+        return (gc, _to(gh, ctx.h_meta) if ctx.needs_input_grad[1] else None,
+                _to(gg, ctx.g_meta) if ctx.needs_input_grad[2] else None, None, None)

@@ -123,8 +123,11 @@ mw_status launch_diag(const DevPlan &p, hipStream_t s);
 mw_status launch_sigma(const DevPlan &p, int nroots, const void *c, void *sigma, hipStream_t s);
 mw_status launch_sigma_batched(int nprob, const DevPlan *const *plans, const int *nroots,
                                const void *const *c, void *const *sigma, hipStream_t s);
-mw_status launch_rdm(const DevPlan &p, int nroots, const void *bra, const void *ket,
-                     const double *weights, void *gamma, void *Gamma, hipStream_t s);
+// transition density matrices; weights (host) or dev_weights (device) per
+// root, nullable; Gamma is written scaled by fac_g and, when conj is set
+// (complex only), gamma and Gamma are written conjugated
+mw_status launch_rdm(const DevPlan &p, int nroots, const void *bra, const void *ket, const double *weights,
+                     const double *dev_weights, void *gamma, void *Gamma, double fac_g, bool conj, hipStream_t s);
 mw_status launch_connect(const DevPlan &p, int64_t *count, int64_t *out, hipStream_t s);
 
 }  // namespace mw

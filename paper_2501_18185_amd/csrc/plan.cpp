@@ -149,6 +149,9 @@ struct HostPlan {
     // spin-free and 40-pair spinor spaces for one, two and four roots
     int32_t tune_u = 4, tune_gl = 0;
     int64_t n_single_pairs = 0, n_double_pairs = 0, n_evals = 0;
+    // ordered double pairs inside groups of 64 members or more, which the
+    // double-group kernel evaluates once per unordered pair
+    int64_t n_double_pairs_large = 0;
     // device binding
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -502,10 +505,11 @@ static mw_status build_groups(HostPlan &P)
     });
     ent.clear();
     ent.shrink_to_fit();
-    P.n_single_pairs = P.n_double_pairs = P.n_evals = 0;
+    P.n_single_pairs = P.n_double_pairs = P.n_evals = P.n_double_pairs_large = 0;
     for (int64_t gi = 0; gi < ngroup; gi++) {
         P.n_single_pairs += single_pairs[gi];
         P.n_double_pairs += double_pairs[gi];
+        if (all[gi].len >= 64) P.n_double_pairs_large += double_pairs[gi];
         P.n_evals += (int64_t)all[gi].len * all[gi].len;
     }
     // packets: <= 64 consecutive members; large groups are cut into chunks of
@@ -944,6 +948,7 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     case 11: return (int64_t)P.pk_off.size() - 1;
     case 12: return P.npacket_double;
     case 13: return P.ncol;
+    case 14: return P.n_double_pairs_large;
     default: return -1;
     }
 }

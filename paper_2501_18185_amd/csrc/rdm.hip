@@ -29,8 +29,12 @@
 
 namespace mw {
 
+// Root weights w_k: host values passed by value, or (dev != nullptr) read
+// from device memory, so that an upstream gradient already on the device
+// weighs the roots without a copy to the host.
 struct RdmWeights {
     double w[64];
+    const double *dev;
 };
 
 template <bool CPLX>
@@ -42,8 +46,9 @@ __device__ __forceinline__ typename Scal<CPLX>::T pair_weight(const typename Sca
     T s = sc_zero(T());
     for (int k = 0; k < R; k++) {
         T t = sc_mul(sc_conj(bra[(size_t)I * R + k]), ket[(size_t)J * R + k]);
-        if constexpr (CPLX) s = make_double2(s.x + W.w[k] * t.x, s.y + W.w[k] * t.y);
-        else s += W.w[k] * t;
+        const double wk = W.dev ? W.dev[k] : W.w[k];
+        if constexpr (CPLX) s = make_double2(s.x + wk * t.x, s.y + wk * t.y);
+        else s += wk * t;
     }
     return s;
 }
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double
                                                          const double *__restrict__ dt1, const double *__restrict__ S,
                                                          const double *__restrict__ Cc, const double *__restrict__ Ee,
                                                          const double *__restrict__ D, double *__restrict__ gam,
-                                                         double *__restrict__ Gam, int sym)
+                                                         double *__restrict__ Gam, int sym, double fac_g)
 {
     const int n = p.n, M = p.M;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double
         v += s;
     }
     if (a == dd && b == c && a != b) v -= Dg(a, b) + Dg(n + a, n + b);
-    Gam[t] = v;
+    Gam[t] = fac_g * v;
     if (t < (int64_t)n * n) {
         const int pa = (int)(t / n), qa = (int)(t % n);
         gam[t] = S0[t] + S1[t] + (pa == qa ? Dg(pa, pa) + Dg(n + pa, n + pa) : 0.0);
@@ -386,7 +391,7 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
                                                              const double2 *__restrict__ Cc,
                                                              const double2 *__restrict__ D,
                                                              double2 *__restrict__ gam, double2 *__restrict__ Gam,
-                                                             int sym)
+                                                             int sym, double fac_g, int conj)
 {
     const int M = p.M, n = p.n;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,10 +408,12 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
     if (a == dd) v = sc_add(v, sc_neg(sc_add(inref(a) ? S[(size_t)c * M + b] : sc_zero(double2()), cpq(c, b, a)), true));
     if (a == b && c == dd && a != c) v = sc_add(v, D[(size_t)a * M + c]);
     if (a == dd && b == c && a != b) v = sc_add(v, sc_neg(D[(size_t)a * M + b], true));
-    Gam[t] = v;
+    if (conj) v = sc_conj(v);
+    Gam[t] = make_double2(fac_g * v.x, fac_g * v.y);
     if (t < (int64_t)M * M) {
         const int A = (int)(t / M), B = (int)(t % M);
-        gam[t] = sc_add(S[t], A == B ? D[t] : sc_zero(double2()));
+        const double2 gv = sc_add(S[t], A == B ? D[t] : sc_zero(double2()));
+        gam[t] = conj ? sc_conj(gv) : gv;
     }
 }
 
@@ -429,11 +436,12 @@ static void zero(double *x, int64_t n, hipStream_t s)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, x, n);
 }
 
-mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, const double *weights, void *gamma,
-                     void *Gamma, hipStream_t s)
+mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, const double *weights,
+                     const double *dev_weights, void *gamma, void *Gamma, double fac_g, bool conj, hipStream_t s)
 {
     RdmWeights W;
     for (int k = 0; k < 64; k++) W.w[k] = (weights && k < R) ? weights[k] : 1.0;
+    W.dev = dev_weights;
     // one vector as bra and ket (real weights): w_JI = conj(w_IJ)
     const bool sym = bra == ket;
     const int n = p.n, M = p.M;
@@ -476,7 +484,7 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
                            (const double *)part, D);
         hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, dab, dt0, dt1,
-                           S, Cc, Ee, D, (double *)gamma, (double *)Gamma, (int)sym);
+                           S, Cc, Ee, D, (double *)gamma, (double *)Gamma, (int)sym, fac_g);
         prof_end(t, s);
     } else {
         const int64_t m4 = mm * mm, np2 = (int64_t)p.npair * p.npair, m3 = mm * M;
@@ -511,7 +519,7 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
                            (const double2 *)part, D);
         hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, dt0, dt1, S,
-                           Cc, D, (double2 *)gamma, (double2 *)Gamma, (int)sym);
+                           Cc, D, (double2 *)gamma, (double2 *)Gamma, (int)sym, fac_g, (int)conj);
         prof_end(t, s);
     }
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "rdm kernel launch failed");
@@ -532,5 +540,5 @@ extern "C" mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *b
     if (!d) return fail(MW_EWORKSPACE, "plan has no workspace: call mw_plan_upload first");
     if (nroots < 1 || nroots > d->max_roots || nroots > 64) return fail(MW_EINVAL, "nroots must be in 1..max_roots");
     if (!bra || !ket || !gamma || !Gamma) return fail(MW_EINVAL, "NULL device pointer");
-    return launch_rdm(*d, nroots, bra, ket, weights, gamma, Gamma, (hipStream_t)stream);
+    return launch_rdm(*d, nroots, bra, ket, weights, nullptr, gamma, Gamma, 1.0, false, (hipStream_t)stream);
 }

@@ -22,7 +22,8 @@ STATUS = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOTSORTED", -3: "MW_EELEC", -4: 
           -5: "MW_EWORKSPACE", -6: "MW_EHIP", -7: "MW_ENOCONV", -8: "MW_EUNSUPPORTED"}
 INFO = {"ndet": 0, "groups": 1, "memberships": 2, "pairs": 3, "single_pairs": 4,
         "double_pairs": 5, "evaluations": 6, "workspace_bytes": 7, "scalar_bytes": 8,
-        "norb": 9, "kind": 10, "packets": 11, "double_packets": 12, "column_partials": 13}
+        "norb": 9, "kind": 10, "packets": 11, "double_packets": 12, "column_partials": 13,
+        "double_pairs_large_groups": 14}
 
 
 class MWError(RuntimeError):
@@ -59,6 +60,9 @@ def lib():
         L.mw_sigma_batched.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), vp]
         L.mw_diag.argtypes = [vp, vp, vp]
         L.mw_rdm_backward.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), vp, vp, vp]
+        L.mw_energy.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.mw_energy_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.mw_sigma_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.mw_davidson_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
         L.mw_davidson.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), C.c_double, i32,
                                   C.POINTER(i32), vp, sz, vp]
@@ -103,7 +107,8 @@ def lib():
                      "mw_sigma", "mw_sigma_batched", "mw_diag", "mw_rdm_backward", "mw_davidson_work_bytes",
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
                      "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched",
-                     "mw_pt2_work_bytes", "mw_pt2", "mw_select"):
+                     "mw_pt2_work_bytes", "mw_pt2", "mw_select", "mw_energy", "mw_energy_backward",
+                     "mw_sigma_backward"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -265,6 +270,52 @@ class Plan:
         _check(lib().mw_rdm_backward(self._plan, nroots, C.c_void_p(bra.data_ptr()), C.c_void_p(ket.data_ptr()),
                                      w, C.c_void_p(gam.data_ptr()), C.c_void_p(Gam.data_ptr()), _stream()))
         return gam, Gam
+
+    def _int_grads(self, device):
+        torch = _require_gpu()
+        m = self.norb if not self.is_complex else 2 * self.norb
+        return (torch.empty((m, m), dtype=self.dtype, device=device),
+                torch.empty((m, m, m, m), dtype=self.dtype, device=device))
+
+    @staticmethod
+    def _ptr(x):
+        return C.c_void_p(x.data_ptr()) if x is not None else None
+
+    def energy(self, c, sigma):
+        """Per-root energies Re c_k^H sigma_k (device float64 [nroots])."""
+        torch = _require_gpu()
+        c, sigma = self._vec(c), self._vec(sigma)
+        nroots = 1 if c.dim() == 1 else c.shape[1]
+        e = torch.empty(nroots, dtype=torch.float64, device=c.device)
+        _check(lib().mw_energy(self._plan, nroots, self._ptr(c), self._ptr(sigma), self._ptr(e), _stream()))
+        return e
+
+    def energy_backward(self, c, sigma, ge, want_c=True, want_integrals=True):
+        """Gradients of L = sum_k ge_k E_k (ge device float64 [nroots]):
+        (grad_c or None, grad_h or None, grad_g or None), computed in libmw."""
+        torch = _require_gpu()
+        c = self._vec(c)
+        sigma = self._vec(sigma) if want_c else None
+        ge = ge.to(device=c.device, dtype=torch.float64).reshape(-1).contiguous()
+        nroots = 1 if c.dim() == 1 else c.shape[1]
+        gc = torch.empty_like(c) if want_c else None
+        gh, gg = self._int_grads(c.device) if want_integrals else (None, None)
+        _check(lib().mw_energy_backward(self._plan, nroots, self._ptr(c), self._ptr(sigma), self._ptr(ge),
+                                        self._ptr(gc), self._ptr(gh), self._ptr(gg), _stream()))
+        return gc, gh, gg
+
+    def sigma_backward(self, c, gs, want_c=True, want_integrals=True):
+        """Vector-Jacobian products of sigma = H c for the upstream gradient
+        gs: (H gs or None, conj gamma(gs, c) or None, conj Gamma(gs, c) / 2 or
+        None), computed in libmw."""
+        torch = _require_gpu()
+        c, gs = self._vec(c), self._vec(gs)
+        nroots = 1 if c.dim() == 1 else c.shape[1]
+        gc = torch.empty_like(c) if want_c else None
+        gh, gg = self._int_grads(c.device) if want_integrals else (None, None)
+        _check(lib().mw_sigma_backward(self._plan, nroots, self._ptr(c), self._ptr(gs), self._ptr(gc),
+                                       self._ptr(gh), self._ptr(gg), _stream()))
+        return gc, gh, gg
 
     def davidson(self, c0, tol=1e-8, max_iter=100, check=True):
         """Lowest eigenpairs from start vectors c0 [ndet, nroots].

@@ -309,3 +309,28 @@ def test_sigma_spinor_full_sampled(torch):
     ref = sc.sigma(p, c, rows=rows)
     _say("rel err sampled", _rel(s[rows], ref))
     assert _rel(s[rows], ref) <= TOL
+
+
+def test_sigma_spinor_full_integer_exact(torch):
+    """Complex integer inputs on the 1,000,000-determinant spinor space of
+    the 40-pair N=20 recipe: h Hermitian and (PQ|RS) = (RS|PQ) =
+    conj((QP|SR)) with integer real and imaginary parts (|v| <= 32), integer
+    complex c; every partial sum is an exact integer in FP64, so sampled rows
+    equal the oracle bit for bit whatever the summation order."""
+    p0 = synth.workload(2)
+    M = 2 * p0.norb
+    rng = np.random.default_rng(31)
+    a = rng.integers(-4, 5, size=(M, M)) + 1j * rng.integers(-4, 5, size=(M, M))
+    h = a + a.conj().T
+    x = rng.integers(-8, 9, size=(M,) * 4) + 1j * rng.integers(-8, 9, size=(M,) * 4)
+    g = x + x.transpose(2, 3, 0, 1) + np.conj(x.transpose(1, 0, 3, 2)) + np.conj(x.transpose(3, 2, 1, 0))
+    del x
+    p = _prob("spinor", p0.norb, p0.nalpha, -1, p0.dets, h, g)
+    del p0
+    pl = _plan(p)
+    c = rng.integers(-3, 4, size=p.ndet) + 1j * rng.integers(-3, 4, size=p.ndet)
+    s = pl.sigma(_dev(torch, c)).cpu().numpy()
+    rows = np.unique(np.concatenate([np.arange(6), rng.choice(p.ndet, 30, replace=False), [p.ndet - 1]]))
+    ref = sc.sigma(p, c, rows=rows)
+    _say("integer spinor rows", len(rows), "max |sigma|", np.abs(ref).max())
+    assert np.array_equal(s[rows], ref)
