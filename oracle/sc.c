@@ -431,8 +431,11 @@ void orc_rdm_rows(int kind, int n, long ndet, const uint64_t *dets, int nroots,
  *   E2_k = sum_{A in Q} |sum_{J in P} H_AJ c_Jk|^2 / (E0_k - H_AA),
  * Q = the determinants outside P that one or two excitations reach from
  * some J in P (spin-free: N_alpha and N_beta kept).  Screening as in the
- * paper's PT2 procedure (step 4): a doubly excited pair (A, J) is left out
- * when |H_AJ| max_k |c_Jk| < qmin; qmin = 0 keeps everything.
+ * paper's PT2 procedure (step 4): the pair (A, J) is left out when the
+ * configuration of A is doubly excited from that of J and Table 1's bound
+ * H~ is below qmin / max_{nu,k} |C^J_{nu,k}| (the maximum over the
+ * determinants nu of J's configuration and the roots); qmin = 0 keeps
+ * everything.
  * Steps: every J lists its excitations A outside P; the (A, J) list is
  * sorted by A, then J; each numerator is summed in ascending J; the
  * contributions are added in ascending A. */
@@ -461,6 +464,115 @@ static int in_space(long ndet, const uint64_t *dets, uint64_t d0, uint64_t d1)
 }
 
 static double cx_abs(cx a) { return sqrt(a.re * a.re + a.im * a.im); }
+
+/* ------------------------------------------------------------------------ */
+/* Configurations (section 2.2) and the upper bounds of Table 1.
+ * The configuration of a determinant gives every spatial orbital (spin-free)
+ * or Kramers pair (spinor) p the occupation n_p = (bit p of word 0) + (bit p
+ * of word 1), 0, 1 or 2. */
+static int occ_num(const uint64_t *d, int p) { return (int)((d[0] >> p) & 1u) + (int)((d[1] >> p) & 1u); }
+
+/* Excitation level between the configurations of J and I: the electrons
+ * that move, sum over p of max(0, n_p(J) - n_p(I)).  For level 2, the
+ * orbitals that gain electrons in I (particles i <= k) and those that lose
+ * them (holes j <= l); an orbital whose occupation changes by 2 is listed
+ * twice. */
+static int cfg_excitation(const uint64_t *I, const uint64_t *J, int n, int *i, int *k, int *j, int *l)
+{
+    int part[4], hole[4], np = 0, nh = 0;
+    for (int p = 0; p < n; p++) {
+        int d = occ_num(I, p) - occ_num(J, p);
+        while (d > 0 && np < 4) { part[np++] = p; d--; }
+        while (d < 0 && nh < 4) { hole[nh++] = p; d++; }
+    }
+    if (np == 2 && nh == 2) { *i = part[0]; *k = part[1]; *j = hole[0]; *l = hole[1]; }
+    return nh;
+}
+
+/* |(ab|cd)| as Table 1 uses it.  Spin-free: the spatial integral.  Spinor
+ * (every vertex has both Kramers partners): the largest |(PQ|RS)| over P in
+ * pair a, Q in b, R in c, S in d, with P != R and Q != S (two electrons of
+ * one pair sit in both of its spinors). */
+static double g_bound(const ham_t *H, int a, int b, int c, int d)
+{
+    const int n = H->n;
+    if (H->kind == 0) return fabs(H->g[(((size_t)a * n + b) * n + c) * n + d]);
+    double m = 0.0;
+    for (int P = a; P < 2 * n; P += n)
+        for (int Q = b; Q < 2 * n; Q += n)
+            for (int R = c; R < 2 * n; R += n)
+                for (int S = d; S < 2 * n; S += n) {
+                    if (P == R || Q == S) continue;
+                    double v = cx_abs(g_so(H, P, Q, R, S));
+                    if (v > m) m = v;
+                }
+    return m;
+}
+
+/* Table 1, SD column: the upper bound H~ of |H_{I mu, J nu}| over the
+ * determinants of two configurations, I doubly excited from J, particles
+ * i, k and holes j, l. */
+static double table1_sd(const ham_t *H, int i, int k, int j, int l)
+{
+    if (i != k && j != l) {                   /* IntC 1-3: e_ij,kl and e_il,kj */
+        double x = g_bound(H, i, j, k, l), y = g_bound(H, i, l, k, j);
+        return x > y ? x : y;
+    }
+    if (i != k) return g_bound(H, i, j, k, j); /* IntC 4-5: e_ij,kj (l = j) */
+    if (j != l) return g_bound(H, i, l, i, j); /* IntC 6: e_il,ij (k = i) */
+    return g_bound(H, i, j, i, j);             /* IntC 7: e_ij,ij */
+}
+
+/* cm[j] = max over the roots k and over the determinants nu of the space
+ * with the configuration of determinant j of |c[nu][k]| (the
+ * max_{nu,k} |C^J_{nu,k}| of the screening).  Determinants are grouped by
+ * their configuration (occupied mask, doubly occupied mask) by sorting. */
+typedef struct { uint64_t occ, dbl; long j; } cfg_ent;
+
+static int cfg_ent_cmp(const void *x, const void *y)
+{
+    const cfg_ent *a = (const cfg_ent *)x, *b = (const cfg_ent *)y;
+    if (a->occ != b->occ) return a->occ < b->occ ? -1 : 1;
+    if (a->dbl != b->dbl) return a->dbl < b->dbl ? -1 : 1;
+    return (a->j > b->j) - (a->j < b->j);
+}
+
+static void cfg_cmax(long ndet, const uint64_t *dets, int nroots, const double *c, double *cm)
+{
+    cfg_ent *e = (cfg_ent *)malloc(sizeof(cfg_ent) * (size_t)(ndet > 0 ? ndet : 1));
+    for (long j = 0; j < ndet; j++) {
+        e[j].occ = dets[2 * j] | dets[2 * j + 1];
+        e[j].dbl = dets[2 * j] & dets[2 * j + 1];
+        e[j].j = j;
+    }
+    qsort(e, (size_t)ndet, sizeof(cfg_ent), cfg_ent_cmp);
+    for (long s = 0; s < ndet;) {
+        long t = s;
+        double m = 0.0;
+        while (t < ndet && e[t].occ == e[s].occ && e[t].dbl == e[s].dbl) {
+            for (int k = 0; k < nroots; k++) {
+                long j = e[t].j;
+                cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+                double a = cx_abs(cj);
+                if (a > m) m = a;
+            }
+            t++;
+        }
+        for (long u = s; u < t; u++) cm[e[u].j] = m;
+        s = t;
+    }
+    free(e);
+}
+
+/* Screening test of section 2.5 (step 4) for a determinant pair (A, J):
+ * true when the configuration of A is doubly excited from that of J and
+ * Table 1's bound is below qmin / max_{nu,k} |C^J_{nu,k}| (cmj). */
+static int pt2_screened(const ham_t *H, const uint64_t *A, const uint64_t *J, double cmj, double qmin)
+{
+    int i = -1, k = -1, j = -1, l = -1;
+    if (cfg_excitation(A, J, H->n, &i, &k, &j, &l) != 2) return 0;
+    return table1_sd(H, i, k, j, l) < qmin / cmj;
+}
 
 typedef struct { pt2_rec *r; long n, cap; } rec_buf;
 
@@ -516,14 +628,9 @@ void orc_pt2(int kind, int n, const double *h, const double *g, double ecore,
         }
     }
     qsort(B.r, (size_t)B.n, sizeof(pt2_rec), rec_cmp);
-    /* largest |c_Jk| per J for the screening */
+    /* largest |C| over the roots and the determinants of J's configuration */
     double *cmax = (double *)calloc((size_t)(ndet > 0 ? ndet : 1), sizeof(double));
-    for (long j = 0; j < ndet; j++)
-        for (int k = 0; k < nroots; k++) {
-            cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
-            double a = cx_abs(cj);
-            if (a > cmax[j]) cmax[j] = a;
-        }
+    cfg_cmax(ndet, dets, nroots, c, cmax);
     /* first record of every distinct A */
     long nA = 0;
     long *head = (long *)malloc(sizeof(long) * (size_t)(B.n + 1));
@@ -542,9 +649,8 @@ void orc_pt2(int kind, int n, const double *h, const double *g, double ecore,
         for (long u = head[a]; u < head[a + 1]; u++) {
             long j = B.r[u].j;
             const uint64_t *J = dets + 2 * j;
-            int pc = __builtin_popcountll(A[0] ^ J[0]) + __builtin_popcountll(A[1] ^ J[1]);
+            if (pt2_screened(&H, A, J, cmax[j], qmin)) continue;
             cx v = hij(&H, A, J, n);
-            if (pc == 4 && cx_abs(v) * cmax[j] < qmin) continue;
             u_cnt++;
             for (int k = 0; k < nroots; k++) {
                 cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
@@ -583,21 +689,33 @@ void orc_pt2(int kind, int n, const double *h, const double *g, double ecore,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Selection of external determinants by the iCIPT2 criterion (section 2.4):
- * A outside P, reached from some J in P by one or two excitations, is
- * selected when for that J
- *   max_k |H_AJ c_Jk| >= cmin  and  max_k |H_AJ c_Jk / (E0_k - H_AA)| >= cmin.
- * (The extra condition on the double-excitation upper bound is the first
- * one again for determinants, whose double element is a single
- * antisymmetrised integral.)  out (nullable): [max_out][2]; returns the
- * number of distinct selected determinants, which are written sorted. */
+/* Selection of external determinants by the iCIPT2 criterion (section 2.4,
+ * Eqs. (iCI_Selection-1) and (iCI_Selection-2)).  A outside P is selected
+ * when some configuration J of P (its determinants nu that the space holds)
+ * gives f(A, J) true:
+ *   max_{nu,k} |H_{A nu} C_{nu,k}| >= cmin  and
+ *   max_{nu,k} |H_{A nu} C_{nu,k} / (E0_k - H_AA)| >= cmin,
+ * and, when the configuration of A is doubly excited from J (case B),
+ *   max_{nu,k} |H~ C_{nu,k}| = H~ max_{nu,k} |C_{nu,k}| >= cmin
+ * with H~ Table 1's bound.  Steps: every determinant nu of P lists its
+ * single and double excitations A outside P with the two per-pair tests
+ * (pairs failing the bound test, or both per-pair tests, cannot make f
+ * true and are not kept); the list is sorted by A and J's configuration;
+ * A is selected when one configuration group has a pair passing the first
+ * test and a pair passing the second.  out (nullable): [max_out][2];
+ * returns the number of distinct selected determinants, written sorted. */
 typedef struct { uint64_t a0, a1; } det_key;
+typedef struct { uint64_t a0, a1, occ, dbl; int t1, t2; } sel_rec;
 
-static int key_cmp(const void *x, const void *y)
+static int sel_cmp(const void *x, const void *y)
 {
-    const det_key *a = (const det_key *)x, *b = (const det_key *)y;
+    const sel_rec *a = (const sel_rec *)x, *b = (const sel_rec *)y;
     if (a->a0 != b->a0) return a->a0 < b->a0 ? -1 : 1;
-    return (a->a1 > b->a1) - (a->a1 < b->a1);
+    if (a->a1 != b->a1) return a->a1 < b->a1 ? -1 : 1;
+    if (a->occ != b->occ) return a->occ < b->occ ? -1 : 1;
+    if (a->dbl != b->dbl) return a->dbl < b->dbl ? -1 : 1;
+    if (a->t1 != b->t1) return a->t1 - b->t1;
+    return a->t2 - b->t2;
 }
 
 long orc_select(int kind, int n, const double *h, const double *g, double ecore,
@@ -606,13 +724,15 @@ long orc_select(int kind, int n, const double *h, const double *g, double ecore,
 {
     ham_t H = {kind, n, h, g, ecore};
     const int M = 2 * n;
-    det_key *sel = NULL;
-    long ns = 0, cap = 0;
-    /* every J independently (any thread), its selections appended in turn */
+    double *cm = (double *)calloc((size_t)(ndet > 0 ? ndet : 1), sizeof(double));
+    cfg_cmax(ndet, dets, nroots, c, cm);
+    sel_rec *rec = NULL;
+    long nr = 0, cap = 0;
+    /* every J independently (any thread), its pairs appended in turn */
     #pragma omp parallel
     {
-        det_key *mine = NULL;
-        long nm = 0, cm = 0;
+        sel_rec *mine = NULL;
+        long nm = 0, cmn = 0;
         #pragma omp for schedule(dynamic, 1)
         for (long j = 0; j < ndet; j++) {
             const uint64_t *J = dets + 2 * j;
@@ -634,22 +754,30 @@ long orc_select(int kind, int n, const double *h, const double *g, double ecore,
                             flip(A, n, Q); flip(A, n, P);
                             if (S != Q) { flip(A, n, S); flip(A, n, R); }
                             if (in_space(ndet, dets, A[0], A[1])) continue;
+                            int ci = -1, ck = -1, cj = -1, cl = -1;
+                            if (cfg_excitation(A, J, n, &ci, &ck, &cj, &cl) == 2 &&
+                                !(table1_sd(&H, ci, ck, cj, cl) * cm[j] >= cmin))
+                                continue;                     /* case (B): the bound test */
                             cx v = hij(&H, A, J, n);
                             double haa = hij(&H, A, A, n).re;
                             double m1 = 0.0, m2 = 0.0;
                             for (int k = 0; k < nroots; k++) {
-                                cx cj = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
-                                double a = cx_abs(cx_mul(v, cj));
+                                cx cj_ = {c[2 * (j * nroots + k)], c[2 * (j * nroots + k) + 1]};
+                                double a = cx_abs(cx_mul(v, cj_));
                                 if (a > m1) m1 = a;
                                 double b = a / fabs(e0[k] - haa);
                                 if (b > m2) m2 = b;
                             }
-                            if (!(m1 >= cmin && m2 >= cmin)) continue;
-                            if (nm == cm) {
-                                cm = cm ? 2 * cm : 1024;
-                                mine = (det_key *)realloc(mine, sizeof(det_key) * (size_t)cm);
+                            int t1 = m1 >= cmin, t2 = m2 >= cmin;
+                            if (!t1 && !t2) continue;
+                            if (nm == cmn) {
+                                cmn = cmn ? 2 * cmn : 1024;
+                                mine = (sel_rec *)realloc(mine, sizeof(sel_rec) * (size_t)cmn);
                             }
-                            mine[nm].a0 = A[0]; mine[nm].a1 = A[1]; nm++;
+                            mine[nm].a0 = A[0]; mine[nm].a1 = A[1];
+                            mine[nm].occ = J[0] | J[1]; mine[nm].dbl = J[0] & J[1];
+                            mine[nm].t1 = t1; mine[nm].t2 = t2;
+                            nm++;
                         }
                     }
                 }
@@ -657,21 +785,41 @@ long orc_select(int kind, int n, const double *h, const double *g, double ecore,
         }
         #pragma omp critical
         {
-            if (ns + nm > cap) {
-                cap = ns + nm;
-                sel = (det_key *)realloc(sel, sizeof(det_key) * (size_t)(cap > 0 ? cap : 1));
+            if (nr + nm > cap) {
+                cap = nr + nm;
+                rec = (sel_rec *)realloc(rec, sizeof(sel_rec) * (size_t)(cap > 0 ? cap : 1));
             }
-            if (nm) memcpy(sel + ns, mine, sizeof(det_key) * (size_t)nm);
-            ns += nm;
+            if (nm) memcpy(rec + nr, mine, sizeof(sel_rec) * (size_t)nm);
+            nr += nm;
         }
         free(mine);
     }
-    qsort(sel, (size_t)ns, sizeof(det_key), key_cmp);
+    qsort(rec, (size_t)nr, sizeof(sel_rec), sel_cmp);
     long u = 0;
-    for (long i = 0; i < ns; i++)
-        if (i == 0 || sel[i].a0 != sel[u - 1].a0 || sel[i].a1 != sel[u - 1].a1) sel[u++] = sel[i];
-    if (out)
-        for (long i = 0; i < u && i < max_out; i++) { out[2 * i] = sel[i].a0; out[2 * i + 1] = sel[i].a1; }
-    free(sel);
+    for (long s = 0; s < nr;) {
+        /* the run of one A */
+        long e = s;
+        while (e < nr && rec[e].a0 == rec[s].a0 && rec[e].a1 == rec[s].a1) e++;
+        int selected = 0;
+        for (long g0 = s; g0 < e;) {
+            /* the group of one configuration of P */
+            long g1 = g0;
+            int any1 = 0, any2 = 0;
+            while (g1 < e && rec[g1].occ == rec[g0].occ && rec[g1].dbl == rec[g0].dbl) {
+                any1 |= rec[g1].t1;
+                any2 |= rec[g1].t2;
+                g1++;
+            }
+            if (any1 && any2) selected = 1;
+            g0 = g1;
+        }
+        if (selected) {
+            if (out && u < max_out) { out[2 * u] = rec[s].a0; out[2 * u + 1] = rec[s].a1; }
+            u++;
+        }
+        s = e;
+    }
+    free(rec);
+    free(cm);
     return u;
 }

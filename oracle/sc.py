@@ -195,7 +195,9 @@ def rdm(prob, bra, ket, weights=None, rows=None):
 def pt2(prob, c, e0, qmin=0.0):
     """Epstein-Nesbet second-order energies E2_k over the determinants that
     single and double excitations reach from the space (outside it), with
-    the doubles screening |H_AJ| max_k |c_Jk| < qmin.  ``c`` [ndet] or
+    the screening of section 2.5: (A, J) is left out when A's configuration
+    is doubly excited from J's and Table 1's bound is below qmin / max|C|
+    over J's configuration.  ``c`` [ndet] or
     [ndet][nroots], ``e0`` scalar or [nroots].  Returns (e2 [nroots],
     kept (A, J) pairs, number of external A)."""
     kind, h, g = _ham(prob)
@@ -215,9 +217,11 @@ def pt2(prob, c, e0, qmin=0.0):
 
 
 def select(prob, c, e0, cmin):
-    """Determinants outside the space selected by the iCIPT2 criterion
-    (max_k |H_AJ c_Jk| >= cmin and max_k |H_AJ c_Jk / (E0_k - H_AA)| >= cmin
-    for some J of the space); sorted [nsel][2] uint64."""
+    """Determinants outside the space selected by the iCIPT2 criterion of
+    section 2.4 for some configuration J of the space (max over J's
+    determinants and the roots of |H c| >= cmin and of |H c / (E0 - H_AA)|
+    >= cmin; for a doubly excited configuration also Table 1's bound times
+    max|C| >= cmin); sorted [nsel][2] uint64."""
     kind, h, g = _ham(prob)
     c = np.asarray(c)
     c2 = np.ascontiguousarray(c.reshape(len(c), -1), dtype=np.complex128)

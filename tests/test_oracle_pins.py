@@ -444,20 +444,70 @@ def test_gradient_central_differences():
 # Epstein-Nesbet second-order energy (section 2.5)
 # --------------------------------------------------------------------------
 
+def _occupations(d, n):
+    """Occupation of every spatial orbital / Kramers pair (0, 1, 2)."""
+    return np.array([((int(d[0]) >> p) & 1) + ((int(d[1]) >> p) & 1) for p in range(n)])
+
+
+def _cfg_double(dA, dJ, n):
+    """(particles, holes) when A's configuration is doubly excited from J's,
+    else None (an orbital whose occupation changes by 2 is listed twice)."""
+    diff = _occupations(dA, n) - _occupations(dJ, n)
+    parts = [p for p in range(n) for _ in range(max(int(diff[p]), 0))]
+    holes = [p for p in range(n) for _ in range(max(-int(diff[p]), 0))]
+    return (parts, holes) if len(holes) == 2 else None
+
+
+def _gabs(prob, a, b, c, d):
+    n = prob.norb
+    if prob.kind == "spinfree":
+        return abs(prob.g[a, b, c, d])
+    return max(abs(prob.g[P, Q, R, S]) for P in (a, a + n) for Q in (b, b + n) for R in (c, c + n)
+               for S in (d, d + n) if P != R and Q != S)
+
+
+def _bound(prob, parts, holes):
+    """Table 1's SD bound in one formula: max(|(ij|kl)|, |(il|kj)|) with
+    particles i, k and holes j, l covers IntC 1-7 (coincident indices give
+    the same integral twice)."""
+    (i, k), (j, l) = parts, holes
+    return max(_gabs(prob, i, j, k, l), _gabs(prob, i, l, k, j))
+
+
+def _cfg_cmax(dets, c2):
+    """max over the roots and the determinants of each determinant's
+    configuration of |c|."""
+    key = [(int(d[0]) | int(d[1]), int(d[0]) & int(d[1])) for d in dets]
+    best = {}
+    for k_, row in zip(key, np.abs(c2)):
+        best[k_] = max(best.get(k_, 0.0), float(row.max()))
+    return np.array([best[k_] for k_ in key])
+
+
 def _pt2_dense(p_full, H, pidx, c, e0, qmin=0.0):
     """E2_k = sum over A outside P of |sum_J H_AJ c_Jk|^2 / (e0_k - H_AA)
-    from a dense H over a complete space (tier A), doubles (A, J) dropped
-    when |H_AJ| max_k |c_Jk| < qmin; also the structural counts (connected
-    (A, J) pairs kept, distinct A)."""
+    from a dense H over a complete space (tier A); a pair (A, J) whose
+    configurations are doubly excited is dropped when the bound is below
+    qmin / max|c| over J's configuration; also the structural counts
+    (connected (A, J) pairs kept, distinct A)."""
     x = literal.packed(p_full)
     N = len(x)
+    n = p_full.norb
     outside = np.setdiff1d(np.arange(N), pidx)
     lvl = np.bitwise_count(x[outside][:, None] ^ x[pidx][None, :]).astype(np.int64)
     conn = (lvl == 2) | (lvl == 4)
     c2 = np.asarray(c).reshape(len(pidx), -1)
-    cmax = np.abs(c2).max(axis=1)
+    cm = _cfg_cmax(p_full.dets[pidx], c2)
+    keep = conn.copy()
+    if qmin > 0.0:
+        for a_, A in enumerate(outside):
+            for j_, J in enumerate(pidx):
+                if not conn[a_, j_]:
+                    continue
+                cd = _cfg_double(p_full.dets[A], p_full.dets[J], n)
+                if cd is not None and _bound(p_full, *cd) < qmin / cm[j_]:
+                    keep[a_, j_] = False
     HAP = H[np.ix_(outside, pidx)]
-    keep = conn & ~((lvl == 4) & (np.abs(HAP) * cmax[None, :] < qmin))
     num = (HAP * keep) @ c2
     den = np.asarray(e0)[None, :] - np.real(np.diag(H)[outside])[:, None]
     has = keep.any(axis=1)
@@ -514,8 +564,11 @@ def test_pt2_equals_dense_literal(kind, seed, npick):
 
 @pytest.mark.parametrize("kind", ["spinfree", "spinor"])
 def test_pt2_screening_rule(kind):
-    """qmin drops a double (A, J) when |H_AJ| max_k |c_Jk| < qmin: a huge
-    qmin leaves the singles only, a middle one a mask of the doubles."""
+    """Cross-check of the configuration screening against the dense literal
+    H with the rule evaluated separately (numpy, one bound formula): a huge
+    qmin keeps the pairs that are not configuration doubles only, middle
+    ones a mask of them.  (The hand-built pins of the rule are in
+    test_oracle_screening.py.)"""
     full, H, pidx, P, c, e0 = _pt2_case(kind, 4, 25)
     for qmin in (1e9, 0.02, 0.002):
         e2, kept, nq = sc.pt2(P, c, e0, qmin=qmin)
@@ -566,19 +619,38 @@ def test_pt2_w_minus_p_identity():
 # --------------------------------------------------------------------------
 
 def _select_dense(p_full, H, pidx, c, e0, cmin):
-    """The selection criterion evaluated on a dense H over a complete space:
-    A outside P is kept when some connected J of P has max_k |H_AJ c_Jk| >=
-    cmin and max_k |H_AJ c_Jk| / |E0_k - H_AA| >= cmin."""
+    """The selection criterion on a dense H over a complete space: A outside
+    P is kept when for some configuration of P, over its determinants nu
+    connected to A, max |H c| >= cmin and max |H c / (E0 - H_AA)| >= cmin
+    (maxima also over the roots), and for a doubly excited configuration
+    the bound times max|c| over the configuration >= cmin."""
     x = literal.packed(p_full)
+    n = p_full.norb
     outside = np.setdiff1d(np.arange(len(x)), pidx)
     lvl = np.bitwise_count(x[outside][:, None] ^ x[pidx][None, :]).astype(np.int64)
     conn = (lvl == 2) | (lvl == 4)
     c2 = np.asarray(c).reshape(len(pidx), -1)
+    cm = _cfg_cmax(p_full.dets[pidx], c2)
     hc = np.abs(H[np.ix_(outside, pidx)][:, :, None] * c2[None, :, :])   # [A][J][k]
     den = np.abs(np.asarray(e0)[None, None, :] - np.real(np.diag(H))[outside][:, None, None])
-    ok = conn & (hc.max(axis=2) >= cmin) & ((hc / den).max(axis=2) >= cmin)
-    sel = outside[ok.any(axis=1)]
-    return np.ascontiguousarray(p_full.dets[sel], dtype=np.uint64)
+    t1 = hc.max(axis=2) >= cmin
+    t2 = (hc / den).max(axis=2) >= cmin
+    cfg = [(int(d[0]) | int(d[1]), int(d[0]) & int(d[1])) for d in p_full.dets[pidx]]
+    sel = []
+    for a_, A in enumerate(outside):
+        groups = {}
+        for j_, J in enumerate(pidx):
+            if not conn[a_, j_]:
+                continue
+            g = groups.setdefault(cfg[j_], [True, False, False])
+            cd = _cfg_double(p_full.dets[A], p_full.dets[J], n)
+            if cd is not None and not (_bound(p_full, *cd) * cm[j_] >= cmin):
+                g[0] = False
+            g[1] |= bool(t1[a_, j_])
+            g[2] |= bool(t2[a_, j_])
+        if any(all(g) for g in groups.values()):
+            sel.append(A)
+    return np.ascontiguousarray(p_full.dets[np.array(sel, dtype=np.int64)], dtype=np.uint64).reshape(-1, 2)
 
 
 def test_select_hubbard():
