@@ -265,14 +265,20 @@ mw_status mw_ivi(mw_plan plan, int32_t nroots, double target, const void *c0, vo
  *   e2[k] = sum_{A in Q} |sum_{J in P} H_AJ c[J][k]|^2 / (e0[k] - H_AA),
  * Q = every determinant outside P that one or two excitations reach from a
  * J of P (spin-free: N_alpha and N_beta kept).  Screening as in the paper's
- * PT2 procedure: a doubly excited pair (A, J) is left out when
- * |H_AJ| max_k |c[J][k]| < qmin (qmin = 0 keeps every pair).
+ * PT2 procedure (step 4): the pair (A, J) is left out when the configuration
+ * of A (orbital or Kramers-pair occupations 0/1/2) is doubly excited from
+ * that of J and Table 1's upper bound H~ (SD column, IntC 1-7; spinor: the
+ * largest integral over the Kramers partners) is below qmin / max |c[nu][k]|
+ * over the determinants nu of J's configuration and the roots (qmin = 0
+ * keeps every pair).
  * c: device [ndet][nroots] (complex for spinor plans), 1 <= nroots <= 8;
  * e0, e2: HOST [nroots].  work: device scratch of work_bytes bytes; the
  * connections are generated in passes over hash buckets of A sized to fit
- * it (mw_pt2_work_bytes gives the size for one pass without screening;
- * less memory means more passes; MW_EWORKSPACE if too small for the bucket
- * tables or one bucket).  stats: HOST int64[5], nullable: kept (A, J)
+ * it (mw_pt2_work_bytes gives the size for one pass without screening when
+ * no bucket exceeds 1024 records; a larger bucket, of any size, is sorted in
+ * 12 bytes of scratch per position of its power-of-two range; less memory
+ * means more passes; MW_EWORKSPACE if too small for the bucket tables or
+ * one bucket).  stats: HOST int64[5], nullable: kept (A, J)
  * pairs with A in Q, number of A in Q, passes, buckets, excitations
  * enumerated per pass (ndet x singles and doubles of one determinant).
  * Host-driven, synchronises the stream; repeated calls give identical bits.
@@ -283,12 +289,14 @@ mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *bytes);
 mw_status mw_pt2(mw_plan plan, int32_t nroots, const void *c, const double *e0, double qmin, void *work,
                  size_t work_bytes, double *e2, int64_t *stats, mw_stream_t stream);
 
-/* Selection of external determinants by the iCIPT2 criterion (section 2.4):
- * A outside the plan's space P, reached from some J of P by one or two
- * excitations, is selected when for that J
- *   max_k |H_AJ c[J][k]| >= cmin  and  max_k |H_AJ c[J][k] / (e0[k] - H_AA)| >= cmin
- * (for determinants the upper bound of a double element is the element
- * itself, so the criterion for doubles reduces to the same two tests).
+/* Selection of external determinants by the iCIPT2 criterion (section 2.4,
+ * Eqs. (iCI_Selection-1) and (iCI_Selection-2)): A outside the plan's space
+ * P, reached from P by one or two excitations, is selected when for some
+ * configuration J of P, with nu over J's determinants in P,
+ *   max_{nu,k} |H_A,nu c[nu][k]| >= cmin  and
+ *   max_{nu,k} |H_A,nu c[nu][k] / (e0[k] - H_AA)| >= cmin
+ * and, when A's configuration is doubly excited from J's (case B),
+ *   H~ max_{nu,k} |c[nu][k]| >= cmin  (Table 1's bound, as for mw_pt2).
  * c: device [ndet][nroots] (complex for spinor plans), 1 <= nroots <= 8;
  * e0: HOST [nroots].  work / work_bytes: device scratch as for mw_pt2 (the
  * size mw_pt2_work_bytes gives is enough for one pass).  out: device

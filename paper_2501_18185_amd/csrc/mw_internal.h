@@ -63,6 +63,7 @@ struct DevPlan {
     const void *a_pair;        // antisymmetrised pairs [x][y] = (X0 Y0|X1 Y1) - (X0 Y1|X1 Y0), y colex
     const void *a_pair1;       // same values with the column pair y in lexicographic order
     const void *f_ref;         // F^omega (spin-free [2][n][n] by spin of the group; spinor [M][M])
+    const double *g_bound;     // spinor: Table 1 bound table [n]^4 over Kramers pairs; spin-free: null
     uint64_t ref0, ref1;       // reference string omega
     int64_t npacket_double;    // packets [0, npacket_double) hold double groups
     void *partial;             // [nmem][R] per-membership partial sums, member order (also RDM accumulators)

@@ -142,6 +142,8 @@ struct HostPlan {
     std::vector<uint32_t> mem_grp, slot_mem, pk_off, rowptr, grp_col;
     int64_t ncol = 0;  // column partial sums of large double groups
     std::vector<double> h, w_same, w_opp, g_ab, a_pair, a_pair1, f_ref;
+    // spinor plans: Table 1's |(ab|cd)| over Kramers pairs (see bound_table)
+    std::vector<double> g_bound;
     uint64_t ref0 = 0, ref1 = 0;
     int64_t npacket_double = 0;
     // launch defaults until mw_autotune picks its own: partner-loop unroll 4,
@@ -602,6 +604,45 @@ static inline int pair_index(int lo, int hi) { return hi * (hi - 1) / 2 + lo; }
 // lexicographic index of the pair lo < hi among m positions
 static inline int pair_lex(int lo, int hi, int m) { return lo * (2 * m - lo - 1) / 2 + (hi - lo - 1); }
 
+// |z| with each product rounded on its own (no fused multiply-add), the
+// rounding the screening's other magnitudes use
+static double cabs_rounded(double re, double im)
+{
+#pragma clang fp contract(off)
+    const double a = re * re;
+    const double b = im * im;
+    return std::sqrt(a + b);
+}
+
+// Spinor plans: B[a][b][c][d] = the largest |(PQ|RS)| over P in Kramers pair
+// a, Q in b, R in c, S in d with P != R and Q != S, the |(ab|cd)| of
+// Table 1 when every vertex carries both Kramers partners.  The bound of a
+// doubly excited configuration pair with particles i, k and holes j, l is
+// max(B[i][j][k][l], B[i][l][k][j]).
+static void bound_table(HostPlan &P, const std::complex<double> *g)
+{
+    const int n = P.n, Mm = 2 * n;
+    P.g_bound.assign((size_t)n * n * n * n, 0.0);
+    parallel_for(n, [&](int64_t a0, int64_t a1, unsigned) {
+        for (int64_t a = a0; a < a1; a++)
+            for (int b = 0; b < n; b++)
+                for (int c = 0; c < n; c++)
+                    for (int d = 0; d < n; d++) {
+                        double m = 0.0;
+                        for (int Pp = (int)a; Pp < Mm; Pp += n)
+                            for (int Q = b; Q < Mm; Q += n)
+                                for (int R = c; R < Mm; R += n)
+                                    for (int S = d; S < Mm; S += n) {
+                                        if (Pp == R || Q == S) continue;
+                                        const std::complex<double> v =
+                                            g[(((size_t)Pp * Mm + Q) * Mm + R) * Mm + S];
+                                        m = std::max(m, cabs_rounded(v.real(), v.imag()));
+                                    }
+                        P.g_bound[(((size_t)a * n + b) * n + c) * n + d] = m;
+                    }
+    });
+}
+
 static void repack(HostPlan &P, const mw_problem *p)
 {
     const int n = P.n;
@@ -672,6 +713,7 @@ static void repack(HostPlan &P, const mw_problem *p)
                             P.a_pair1[2 * k1 + 1] = v.imag();
                         }
         });
+        bound_table(P, g);
     }
 }
 
@@ -763,6 +805,7 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.a_pair = (const void *)take(a_pair.size() * 8);
     t.a_pair1 = (const void *)take(a_pair1.size() * 8);
     t.f_ref = (const void *)take(f_ref.size() * 8);
+    t.g_bound = g_bound.empty() ? nullptr : (const double *)take(g_bound.size() * 8);
     t.ref0 = ref0;
     t.ref1 = ref1;
     t.npacket_double = npacket_double;
@@ -870,7 +913,8 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) &&
               up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
-              up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8);
+              up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
+              up(d.g_bound, P.g_bound.data(), P.g_bound.size() * 8);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
     if (hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
@@ -914,7 +958,7 @@ mw_status mw_plan_update_integrals(mw_plan plan, const double *h, const double *
               up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) && up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
               up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) && up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
-              up(d.self, &P.dev, sizeof(DevPlan));
+              up(d.g_bound, P.g_bound.data(), P.g_bound.size() * 8) && up(d.self, &P.dev, sizeof(DevPlan));
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during integral update");
     st = launch_diag(d, s);
     if (st != MW_OK) return st;

@@ -7,14 +7,16 @@
 // The paper splits the space W of all such excitations into disjoint
 // subspaces W_i (by constraints on the highest occupied orbitals), stores
 // the connections of a batch of W_i, sorts them to find each A with its
-// partners J, and drops doubly excited A whose integral bound times
-// max_k |c_Jk| is below Q_min.  Here the disjoint subspaces are hash
-// buckets of A: every (A, J) pair generated from a J of P lands in the
-// bucket of A, so one bucket holds every partner of its A's.
+// partners J, and deletes the connection of a doubly excited configuration
+// A to J when Table 1's bound is below Q_min / max|C| over J's
+// configuration.  Here the disjoint subspaces are hash buckets of A: every
+// (A, J) pair generated from a J of P lands in the bucket of A, so one
+// bucket holds every partner of its A's.
 //
+//   k_cfg_*           configurations of P (hash table): max|C| over each
 //   k_pt2_enum<0>     every J lists its excitations (one workgroup per J),
 //                     drops A in P (exact hash set of the space) and counts
-//                     the kept pairs (doubles screened with Q_min)
+//                     the kept pairs (configuration doubles screened)
 //   k_pt2_enum<1>     the same pairs, counted per bucket
 //   k_pt2_enum<2>     the pairs of the buckets of one pass, written as
 //                     records {A, J} with H_AJ c_J at the bucket's offset
@@ -22,10 +24,11 @@
 //                     records by (hash bits of A, J) in registers, sums each
 //                     run's numerator across the wave by segmented scans,
 //                     adds |num|^2 / (E0 - H_AA) per external A
-//   k_pt2_bucket      the same for the rare larger buckets, one workgroup
-//                     each, sorting in LDS
-//   k_sel_*           the iCIPT2 selection: the same walk, the test per
-//                     pair, kept keys bucketed, sorted and made distinct
+//   k_pt2_bucket_big  the same for larger buckets of any size, one
+//                     workgroup each, sorting in global memory
+//   k_sel_*           the iCIPT2 selection: the same walk, the tests per
+//                     pair, kept keys bucketed, sorted, and decided per
+//                     (external determinant, configuration of P)
 //   k_pt2_sum1/2      per pass: bucket partial sums in a fixed order
 //
 // Passes over bucket ranges keep the records within the caller's work
@@ -46,9 +49,9 @@ namespace mw {
 
 namespace {
 
-constexpr int PT2_WCAP = 1024;     // records of a bucket sorted by one wave in registers
-constexpr int PT2_CAP = 1024;      // records of a bucket sorted by the block kernel (26 KB LDS)
-constexpr int PT2_CAP_BIG = 4096;  // oversized buckets (rare): a kernel with 104 KB LDS
+constexpr int PT2_WCAP = 1024;     // records of a bucket sorted by one wave in registers;
+                                   // larger buckets: one workgroup, sorted in global memory
+constexpr int SEL_CAP = 1024;      // selection keys of a bucket sorted in LDS; larger: global
 constexpr int PT2_MEAN = 400;      // target records per bucket
 constexpr int PT2_MAXR = 8;        // roots per call
 
@@ -132,6 +135,87 @@ __global__ __launch_bounds__(256) void k_set_keys(const uint64_t *__restrict__ d
     key[i] = d == 0xffffffffu ? make_ulonglong2(~0ULL, ~0ULL) : make_ulonglong2(dets[2 * (size_t)d], dets[2 * (size_t)d + 1]);
 }
 
+__device__ __forceinline__ double mag(double v) { return fabs(v); }
+// |v| without contraction, as re*re + im*im rounded term by term
+__device__ __forceinline__ double mag(double2 v) { return sqrt(__dadd_rn(__dmul_rn(v.x, v.x), __dmul_rn(v.y, v.y))); }
+
+// Configurations of the space (section 2.2): a determinant's configuration
+// is its occupied mask and doubly occupied mask over orbitals (spin-free) or
+// Kramers pairs (spinor).  An open-addressing table holds, per
+// configuration, the index of a determinant inserted with it; cslot[j] is
+// the slot of determinant j's configuration (the configuration's id here),
+// cmaxb[slot] the largest |c| over its determinants and the roots (as the
+// bits of a non-negative double, so an integer maximum orders them).
+__device__ __forceinline__ uint64_t cfg_hash(uint64_t d0, uint64_t d1)
+{
+    return hash_det(d0 | d1, d0 & d1);
+}
+
+__global__ __launch_bounds__(256) void k_cfg_insert(const uint64_t *__restrict__ dets, int64_t ndet, uint32_t *slot,
+                                                    uint64_t mask, uint32_t *cslot)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ndet) return;
+    const uint64_t o = dets[2 * j] | dets[2 * j + 1], d = dets[2 * j] & dets[2 * j + 1];
+    // at most ndet < table size / 2 configurations: a free slot is found
+    for (uint64_t s = cfg_hash(dets[2 * j], dets[2 * j + 1]) & mask;; s = (s + 1) & mask) {
+        const uint32_t cur = atomicCAS(&slot[s], 0xffffffffu, (uint32_t)j);
+        if (cur == 0xffffffffu) {
+            cslot[j] = (uint32_t)s;
+            return;
+        }
+        const uint64_t x0 = dets[2 * (size_t)cur], x1 = dets[2 * (size_t)cur + 1];
+        if ((x0 | x1) == o && (x0 & x1) == d) {
+            cslot[j] = (uint32_t)s;
+            return;
+        }
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_cfg_max(int64_t ndet, int R, const typename Scal<CPLX>::T *__restrict__ c,
+                                                 const uint32_t *__restrict__ cslot, unsigned long long *cmaxb)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ndet) return;
+    double m = 0.0;
+    for (int k = 0; k < R; k++) m = fmax(m, mag(c[(size_t)j * R + k]));
+    atomicMax(&cmaxb[cslot[j]], (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ __launch_bounds__(256) void k_cfg_gather(int64_t ndet, const uint32_t *__restrict__ cslot,
+                                                    const unsigned long long *__restrict__ cmaxb, double *cm)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ndet) return;
+    cm[j] = __longlong_as_double((long long)cmaxb[cslot[j]]);
+}
+
+// Table 1 (SD column) for the double excitation of J with holes Q, S and
+// particles P, R (global positions): 0 when the configuration of A is not
+// doubly excited from J's (a hole and a particle on one orbital or Kramers
+// pair cancel), else the bound max(|(pq|rs)|, |(ps|rq)|) over the orbitals
+// (spinor: the Kramers-pair table of the plan).  With particles i, k and
+// holes j, l this one formula gives IntC 1-3 max(|(ij|kl)|, |(il|kj)|),
+// IntC 4-5 |(ij|kj)| (l = j), IntC 6 |(il|ij)| (k = i) and IntC 7
+// |(ij|ij)|, because the two integrals coincide by symmetry in those cases.
+template <bool CPLX>
+__device__ __forceinline__ bool cfg_double(const DevPlan &p, int Q, int S, int P, int R, double &bound)
+{
+    const int n = p.n;
+    const int q = Q % n, s = S % n, a = P % n, r = R % n;
+    if (q == a || q == r || s == a || s == r) return false;
+    if constexpr (CPLX) {
+        const double *t = p.g_bound;
+        bound = fmax(t[(((size_t)a * n + q) * n + r) * n + s], t[(((size_t)a * n + s) * n + r) * n + q]);
+    } else {
+        // g_ab[q][s][p][r] = (pq|rs)
+        const double *g = (const double *)p.g_ab;
+        bound = fmax(fabs(g[(((size_t)q * n + s) * n + a) * n + r]), fabs(g[(((size_t)s * n + q) * n + a) * n + r]));
+    }
+    return true;
+}
+
 // colex pair k -> (lo, hi), k = hi (hi - 1) / 2 + lo
 __device__ __forceinline__ void pair_of(int k, int &lo, int &hi)
 {
@@ -167,9 +251,6 @@ __device__ __forceinline__ int between(uint64_t d0, uint64_t d1, int n, int a, i
     return below(d0, d1, n, hi) - below(d0, d1, n, lo) - (int)occ(d0, d1, n, lo);
 }
 
-__device__ __forceinline__ double mag(double v) { return fabs(v); }
-// |v| without contraction, as re*re + im*im rounded term by term
-__device__ __forceinline__ double mag(double2 v) { return sqrt(__dadd_rn(__dmul_rn(v.x, v.x), __dmul_rn(v.y, v.y))); }
 
 // Antisymmetrised double integral (PQ|RS) - (PS|RQ) for particles P < R
 // (in A) and holes Q < S (in J), without the phase.
@@ -224,15 +305,6 @@ __device__ __forceinline__ void decode(const ExcClasses &ex, const uint8_t (*ol)
     }
 }
 
-// Largest |c_Jk| over the roots (the screening weight of J).
-template <bool CPLX>
-__device__ __forceinline__ double cmax_of(const typename Scal<CPLX>::T *c, int R, int64_t J)
-{
-    double m = 0.0;
-    for (int k = 0; k < R; k++) m = fmax(m, mag(c[(size_t)J * R + k]));
-    return m;
-}
-
 // H_AA - H_JJ for A = J with holes Q (< S) replaced by particles P (< R)
 // (S = R = -1: a single), from the orbital energies of J, eps_X = h_XX +
 // sum_{Y in J, Y != X} V(X, Y), and V(X, Y) = (XX|YY) - (XY|YX):
@@ -281,11 +353,11 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
                                                   const uint64_t *__restrict__ off, unsigned long long *fill, Rec *rec,
                                                   typename Scal<CPLX>::T *val, const double *__restrict__ eps,
                                                   const double *__restrict__ vg, unsigned long long *total,
-                                                  int64_t jbase, uint32_t kmask)
+                                                  int64_t jbase, uint32_t kmask, const double *__restrict__ cm)
 {
     using T = typename Scal<CPLX>::T;
     __shared__ uint8_t ol[2][128], vl[2][128];
-    __shared__ double s_cmax;
+    __shared__ double s_qlim;
     __shared__ T s_c[PT2_MAXR];
     __shared__ double s_eps[128];
     __shared__ unsigned long long s_tot;
@@ -301,18 +373,23 @@ __global__ __launch_bounds__(256) void k_pt2_enum(DevPlan p, ExcClasses ex, DetS
             if (occ(j0, j1, n, X)) ol[s][no[s]++] = (uint8_t)X;
             else vl[s][nv[s]++] = (uint8_t)X;
         }
-        s_cmax = qmin > 0.0 ? cmax_of<CPLX>(c, R, J) : 0.0;
+        // section 2.5, step 4: a configuration double goes when its bound
+        // is below qmin / max|C| over the determinants of J's configuration
+        s_qlim = qmin > 0.0 ? qmin / cm[J] : 0.0;
         for (int k = 0; k < R; k++) s_c[k] = c[(size_t)J * R + k];
         s_tot = 0;
     }
     __syncthreads();
-    const double cm = s_cmax;
+    const double qlim = s_qlim;
     const int E = ex.start[ex.nclass];
     unsigned long long mine = 0;
     for (int e = threadIdx.x; e < E; e += blockDim.x) {
         int Q, S, P, Rr;
         decode(ex, ol, vl, e, Q, S, P, Rr);
-        if (S >= 0 && qmin > 0.0 && __dmul_rn(mag(double_value<CPLX>(p, P, Q, Rr, S)), cm) < qmin) continue;
+        if (S >= 0 && qmin > 0.0) {
+            double bound;
+            if (cfg_double<CPLX>(p, Q, S, P, Rr, bound) && bound < qlim) continue;
+        }
         uint64_t a0 = j0, a1 = j1;
         flip(a0, a1, n, Q);
         flip(a0, a1, n, P);
@@ -407,145 +484,6 @@ __global__ __launch_bounds__(256) void k_pt2_tables(DevPlan p, double *eps, doub
 }
 
 
-// One workgroup per bucket (blockIdx.x -> bucket b0 + blockIdx.x, or
-// list[blockIdx.x] for the oversized ones).  Buckets with more than CAP
-// records are left to the larger instance (their sums are written there).
-// The records are sorted by one 64-bit key (low hash bits of A, then J), so
-// the records of one A form a run in ascending J; a run whose hash bits are
-// shared by several A (a collision) takes its A's in ascending (a0, a1).
-template <bool CPLX, int CAP>
-__global__ __launch_bounds__(256) void k_pt2_bucket(int R, Roots roots, uint32_t b0, const uint32_t *__restrict__ list,
-                                                    const uint32_t *__restrict__ cnt,
-                                                    const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
-                                                    const typename Scal<CPLX>::T *__restrict__ val,
-                                                    double *__restrict__ part, unsigned long long *__restrict__ partc,
-                                                    uint32_t boff)
-{
-    using T = typename Scal<CPLX>::T;
-    static_assert(3 * CAP >= (PT2_MAXR + 2) * 256, "reduction area");
-    __shared__ uint64_t sm[3 * CAP];
-    __shared__ uint16_t si[CAP];  // record index of sorted position
-    uint64_t *sk = sm;            // sorted keys
-    uint64_t *s0 = sm + CAP, *s1 = sm + 2 * CAP;  // A of record i (bucket order)
-    const uint32_t b = list ? list[boff + blockIdx.x] : b0 + boff + blockIdx.x;
-    const uint32_t slot_out = b - b0;
-    const int m = (int)cnt[b];
-    if (m > CAP) return;  // handled by the larger instance
-    const uint64_t base = off[b];
-    int np2 = 1;
-    while (np2 < m) np2 <<= 1;
-    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
-        if (i < m) {
-            const Rec &r = rec[base + i];
-            sk[i] = r.key;
-            s0[i] = r.a0;
-            s1[i] = r.a1;
-        } else {
-            sk[i] = ~0ULL;
-        }
-        si[i] = (uint16_t)i;
-    }
-    __syncthreads();
-    // bitonic sort of (key, index) ascending; keys within a bucket are
-    // distinct unless two A share the hash bits and a partner J
-    for (int k = 2; k <= np2; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = threadIdx.x; i < np2; i += blockDim.x) {
-                const int l = i ^ jj;
-                if (l > i) {
-                    const bool up = (i & k) == 0;
-                    const uint64_t x = sk[i], y = sk[l];
-                    if ((x > y) == up) {
-                        const uint16_t xi = si[i];
-                        sk[i] = y; si[i] = si[l];
-                        sk[l] = x; si[l] = xi;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    double acc[PT2_MAXR];
-#pragma unroll
-    for (int k = 0; k < PT2_MAXR; k++) acc[k] = 0.0;
-    unsigned long long kept = 0, nq = 0;
-    // |sum over the records u of run [i, e) whose A is (a0, a1), in run
-    // order| ^ 2 / (E0 - H_AA), H_AA from the first of them
-    auto add_a = [&](int i, int e, uint64_t a0, uint64_t a1) {
-        T num[PT2_MAXR];
-#pragma unroll
-        for (int k = 0; k < PT2_MAXR; k++) num[k] = sc_zero(T());
-        int first = -1;
-        for (int u = i; u < e; u++) {
-            const int ru = si[u];
-            if (s0[ru] != a0 || s1[ru] != a1) continue;
-            if (first < 0) first = ru;
-            const T *v = val + (base + ru) * R;
-#pragma unroll
-            for (int k = 0; k < PT2_MAXR; k++)
-                if (k < R) num[k] = sc_add(num[k], v[k]);
-            kept++;
-        }
-        nq++;
-        const double haa = rec[base + first].haa;
-#pragma unroll
-        for (int k = 0; k < PT2_MAXR; k++) {
-            if (k >= R) continue;
-            double q;
-            if constexpr (CPLX) q = num[k].x * num[k].x + num[k].y * num[k].y;
-            else q = num[k] * num[k];
-            acc[k] += q / (roots.e0[k] - haa);
-        }
-    };
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const uint32_t hi = (uint32_t)(sk[i] >> 32);
-        if (i > 0 && (uint32_t)(sk[i - 1] >> 32) == hi) continue;  // not the first record of its run
-        int e = i + 1;
-        while (e < m && (uint32_t)(sk[e] >> 32) == hi) e++;
-        uint64_t c0 = s0[si[i]], c1 = s1[si[i]];
-        bool multi = false;
-        for (int u = i + 1; u < e && !multi; u++) multi = s0[si[u]] != c0 || s1[si[u]] != c1;
-        // several A in the run (rare): each in ascending (a0, a1), starting
-        // from the smallest
-        bool have = false;
-        for (;;) {
-            if (multi) {
-                bool found = false;
-                uint64_t b0_ = 0, b1_ = 0;
-                for (int u = i; u < e; u++) {
-                    const uint64_t x0 = s0[si[u]], x1 = s1[si[u]];
-                    if (have && (x0 < c0 || (x0 == c0 && x1 <= c1))) continue;
-                    if (!found || x0 < b0_ || (x0 == b0_ && x1 < b1_)) { b0_ = x0; b1_ = x1; found = true; }
-                }
-                if (!found) break;
-                c0 = b0_;
-                c1 = b1_;
-            }
-            add_a(i, e, c0, c1);
-            have = true;
-            if (!multi) break;
-        }
-    }
-    // fixed-order block reductions of the R sums and the two counts (as
-    // doubles: a block's counts are below 2^13, exact) in the freed sort area
-    __syncthreads();
-    double *red = reinterpret_cast<double *>(sm);
-    for (int k = 0; k < R; k++) red[k * 256 + threadIdx.x] = acc[k];
-    red[R * 256 + threadIdx.x] = (double)kept;
-    red[(R + 1) * 256 + threadIdx.x] = (double)nq;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < R + 2; k++) red[k * 256 + threadIdx.x] += red[k * 256 + threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < R; k++) part[(size_t)slot_out * R + k] = red[k * 256];
-        partc[2 * (size_t)slot_out] = (unsigned long long)red[R * 256];
-        partc[2 * (size_t)slot_out + 1] = (unsigned long long)red[(R + 1) * 256];
-    }
-}
-
 // One wave per bucket of at most PT2_WCAP records (four buckets per block):
 // the records are sorted in registers by a bitonic network over one 64-bit
 // key (22 hash bits of A, then J, then the record's index), E = 1, 2, 4, 8
@@ -595,53 +533,19 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&v)[16], int lane)
     }
 }
 
-template <bool CPLX, int RM>
-__global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uint32_t b0, int64_t nb,
-                                                         const uint32_t *__restrict__ cnt,
-                                                         const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
-                                                         const typename Scal<CPLX>::T *__restrict__ val,
-                                                         double *__restrict__ part,
-                                                         unsigned long long *__restrict__ partc, int64_t boff)
+// Sum the external determinants of one bucket from its records in sorted
+// order, over the lanes of one wave: sorted positions [0, m), hib_at(p) the
+// hash bits of the record at position p (equal within a run, one run per
+// external A unless hash bits collide), rid_at(p) its record index.  Adds
+// |num|^2 / (E0 - H_AA) per external determinant into the lane's acc, and
+// the kept pairs and external determinants into kept and nq.
+template <bool CPLX, int RM, class HibF, class RidF>
+__device__ __forceinline__ void wave_runs(int m, uint64_t base, HibF hib_at, RidF rid_at, int R, const Roots &roots,
+                                          const Rec *__restrict__ rec,
+                                          const typename Scal<CPLX>::T *__restrict__ val, int lane,
+                                          double (&acc)[RM], uint32_t &kept, uint32_t &nq)
 {
     using T = typename Scal<CPLX>::T;
-    __shared__ uint64_t sk[4][PT2_WCAP];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t bi = boff + (int64_t)blockIdx.x * 4 + wv;  // wave-uniform
-    const uint32_t b = b0 + (uint32_t)(bi < nb ? bi : 0);
-    const int m = bi < nb ? (int)cnt[b] : 0;
-    const bool mine = bi < nb && m <= PT2_WCAP;  // larger buckets go to the block kernels
-    const uint64_t base = mine ? off[b] : 0;
-    if (mine) {
-        int E = 1;
-        while (64 * E < m) E <<= 1;
-        uint64_t v[16];
-#pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int i = lane * E + q;
-            v[q] = ~0ULL;
-            if (q < E && i < m) {
-                const uint64_t key = rec[base + i].key;
-                v[q] = (((key >> 32) & 0x3FFFFFULL) << 42) | ((key & 0xFFFFFFFFULL) << 10) | (uint64_t)i;
-            }
-        }
-        if (E == 1) wave_bitonic<1>(v, lane);
-        else if (E == 2) wave_bitonic<2>(v, lane);
-        else if (E == 4) wave_bitonic<4>(v, lane);
-        else if (E == 8) wave_bitonic<8>(v, lane);
-        else wave_bitonic<16>(v, lane);
-#pragma unroll
-        for (int q = 0; q < 16; q++)
-            if (q < E) sk[wv][lane * E + q] = v[q];
-    }
-    __syncthreads();
-    if (!mine) return;
-    double acc[RM];
-#pragma unroll
-    for (int k = 0; k < RM; k++) acc[k] = 0.0;
-    uint32_t kept = 0, nq = 0;
-    const uint64_t *s = sk[wv];
-    auto hib = [](uint64_t x) { return (uint32_t)(x >> 42); };
-    auto ridx = [](uint64_t x) { return (int)(x & 1023); };
     // |sum over the records of run [i, e) whose A is (a0, a1), in run order
     // (ascending J)|^2 / (E0 - H_AA), H_AA from the first of them
     auto add_a = [&](int i, int e, uint64_t a0, uint64_t a1) {
@@ -650,7 +554,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         for (int k = 0; k < RM; k++) num[k] = sc_zero(T());
         int first = -1;
         for (int u = i; u < e; u++) {
-            const int ru = ridx(s[u]);
+            const int ru = rid_at(u);
             const Rec &x = rec[base + ru];
             if (x.a0 != a0 || x.a1 != a1) continue;
             if (first < 0) first = ru;
@@ -692,14 +596,13 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
     for (int t0 = 0; t0 < m; t0 += 64) {
         const int p = t0 + lane;
         const bool act = p < m;
-        const uint64_t key = act ? s[p] : 0;
         T x[RM];
 #pragma unroll
         for (int k = 0; k < RM; k++) x[k] = sc_zero(T());
         uint64_t a0 = 0, a1 = 0;
         double hh = 0.0;
         if (act) {
-            const uint64_t ri = base + (uint64_t)ridx(key);
+            const uint64_t ri = base + (uint64_t)rid_at(p);
             a0 = rec[ri].a0;
             a1 = rec[ri].a1;
             hh = rec[ri].haa;
@@ -709,7 +612,8 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         }
         const uint64_t u0 = shfl64(a0, lane ? lane - 1 : 0), u1 = shfl64(a1, lane ? lane - 1 : 0);
         const uint64_t pa0 = lane ? u0 : ca0, pa1 = lane ? u1 : ca1;
-        const bool head = act && (p == 0 || hib(s[p - 1]) != hib(key));
+        const uint32_t hk = act ? hib_at(p) : 0u;
+        const bool head = act && (p == 0 || hib_at(p - 1) != hk);
         int mul = (act && !head && (a0 != pa0 || a1 != pa1)) ? 1 : 0;
         uint32_t cn = act ? 1u : 0u;
         int hp = p;
@@ -744,7 +648,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
                 fl = fu;
             }
         }
-        const bool last = act && (p == m - 1 || hib(s[p + 1]) != hib(key));
+        const bool last = act && (p == m - 1 || hib_at(p + 1) != hk);
         if (last) {
             if (!mul) {
 #pragma unroll
@@ -766,7 +670,7 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
                     bool found = false;
                     uint64_t n0 = 0, n1 = 0;
                     for (int u = i; u < e; u++) {
-                        const Rec &y = rec[base + ridx(s[u])];
+                        const Rec &y = rec[base + rid_at(u)];
                         if (have && (y.a0 < c0 || (y.a0 == c0 && y.a1 <= c1))) continue;
                         if (!found || y.a0 < n0 || (y.a0 == n0 && y.a1 < n1)) { n0 = y.a0; n1 = y.a1; found = true; }
                     }
@@ -789,7 +693,15 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         ca0 = shfl64(a0, 63);
         ca1 = shfl64(a1, 63);
     }
-    // fixed butterfly over the wave
+}
+
+// fixed butterfly over the wave; lane 0 writes the bucket's energies and
+// counts to slot
+template <int RM>
+__device__ __forceinline__ void wave_store(double (&acc)[RM], uint32_t kept, uint32_t nq, int R, int lane,
+                                           uint64_t slot, double *__restrict__ part,
+                                           unsigned long long *__restrict__ partc)
+{
 #pragma unroll
     for (int k = 0; k < RM; k++) {
         if (k >= R) continue;
@@ -802,11 +714,129 @@ __global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uin
         nq += (uint32_t)__shfl_xor((int)nq, o);
     }
     if (lane == 0) {
-        const uint64_t slot = (uint64_t)bi;
         for (int k = 0; k < R; k++) part[slot * R + k] = acc[k];
         partc[2 * slot] = kept;
         partc[2 * slot + 1] = nq;
     }
+}
+
+template <bool CPLX, int RM>
+__global__ __launch_bounds__(256) void k_pt2_bucket_wave(int R, Roots roots, uint32_t b0, int64_t nb,
+                                                         const uint32_t *__restrict__ cnt,
+                                                         const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
+                                                         const typename Scal<CPLX>::T *__restrict__ val,
+                                                         double *__restrict__ part,
+                                                         unsigned long long *__restrict__ partc, int64_t boff)
+{
+    __shared__ uint64_t sk[4][PT2_WCAP];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t bi = boff + (int64_t)blockIdx.x * 4 + wv;  // wave-uniform
+    const uint32_t b = b0 + (uint32_t)(bi < nb ? bi : 0);
+    const int m = bi < nb ? (int)cnt[b] : 0;
+    const bool mine = bi < nb && m <= PT2_WCAP;  // larger buckets: k_pt2_bucket_big
+    const uint64_t base = mine ? off[b] : 0;
+    if (mine) {
+        int E = 1;
+        while (64 * E < m) E <<= 1;
+        uint64_t v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int i = lane * E + q;
+            v[q] = ~0ULL;
+            if (q < E && i < m) {
+                const uint64_t key = rec[base + i].key;
+                v[q] = (((key >> 32) & 0x3FFFFFULL) << 42) | ((key & 0xFFFFFFFFULL) << 10) | (uint64_t)i;
+            }
+        }
+        if (E == 1) wave_bitonic<1>(v, lane);
+        else if (E == 2) wave_bitonic<2>(v, lane);
+        else if (E == 4) wave_bitonic<4>(v, lane);
+        else if (E == 8) wave_bitonic<8>(v, lane);
+        else wave_bitonic<16>(v, lane);
+#pragma unroll
+        for (int q = 0; q < 16; q++)
+            if (q < E) sk[wv][lane * E + q] = v[q];
+    }
+    __syncthreads();
+    if (!mine) return;
+    double acc[RM];
+#pragma unroll
+    for (int k = 0; k < RM; k++) acc[k] = 0.0;
+    uint32_t kept = 0, nq = 0;
+    const uint64_t *s = sk[wv];
+    wave_runs<CPLX, RM>(
+        m, base, [&](int q) { return (uint32_t)(s[q] >> 42); }, [&](int q) { return (int)(s[q] & 1023); }, R, roots,
+        rec, val, lane, acc, kept, nq);
+    wave_store<RM>(acc, kept, nq, R, lane, (uint64_t)bi, part, partc);
+}
+
+// Ascending sort of the pairs (K[i], X[i]), i < np2 (a power of two), in
+// global memory by one workgroup: a bitonic network whose steps are
+// separated by barriers; in one step every pair of positions is handled by
+// one thread.
+__device__ __forceinline__ void block_bitonic(uint64_t *K, uint32_t *X, int64_t np2)
+{
+    for (int64_t k = 2; k <= np2; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t i = threadIdx.x; i < np2; i += blockDim.x) {
+                const int64_t l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t ki = K[i], kl = K[l];
+                    const uint32_t xi = X[i], xl = X[l];
+                    if ((ki != kl ? ki > kl : xi > xl) == up) {
+                        K[i] = kl;
+                        K[l] = ki;
+                        X[i] = xl;
+                        X[l] = xi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Buckets of more than PT2_WCAP records (any size: an external determinant
+// with very many partners, or a hash bucket far above the mean), one
+// workgroup each: the records' keys (hash bits of A, then J) and indices
+// are copied to the bucket's scratch (K, X at soff), sorted there, and one
+// wave sums the runs as the wave kernel does.  Every record of an external
+// determinant lies in its bucket, so its numerator is summed whole, in
+// ascending J.
+template <bool CPLX, int RM>
+__global__ __launch_bounds__(256) void k_pt2_bucket_big(int R, Roots roots, uint32_t b0,
+                                                        const uint32_t *__restrict__ list,
+                                                        const uint64_t *__restrict__ soff,
+                                                        const uint32_t *__restrict__ cnt,
+                                                        const uint64_t *__restrict__ off, const Rec *__restrict__ rec,
+                                                        const typename Scal<CPLX>::T *__restrict__ val, uint64_t *skey,
+                                                        uint32_t *sidx, double *__restrict__ part,
+                                                        unsigned long long *__restrict__ partc)
+{
+    const uint32_t b = list[blockIdx.x];
+    const int m = (int)cnt[b];
+    const uint64_t base = off[b];
+    int64_t np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    uint64_t *K = skey + soff[blockIdx.x];
+    uint32_t *X = sidx + soff[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < np2; i += blockDim.x) {
+        K[i] = i < m ? rec[base + i].key : ~0ULL;
+        X[i] = (uint32_t)i;
+    }
+    __syncthreads();
+    block_bitonic(K, X, np2);
+    if (threadIdx.x >= 64) return;  // one wave sums the runs; no barrier follows
+    const int lane = threadIdx.x;
+    double acc[RM];
+#pragma unroll
+    for (int k = 0; k < RM; k++) acc[k] = 0.0;
+    uint32_t kept = 0, nq = 0;
+    wave_runs<CPLX, RM>(
+        m, base, [&](int q) { return (uint32_t)(K[q] >> 32); }, [&](int q) { return (int)X[q]; }, R, roots, rec,
+        val, lane, acc, kept, nq);
+    wave_store<RM>(acc, kept, nq, R, lane, (uint64_t)(b - b0), part, partc);
 }
 
 // Fixed-order sums over the nb buckets of a pass in two stages: block g of
@@ -943,17 +973,66 @@ uint64_t set_size(int64_t ndet)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// configuration table of the space: slots, slot of each determinant, the
+// largest |c| per slot, and per determinant the largest |c| over its
+// configuration
+size_t cfg_bytes(int64_t ndet)
+{
+    return align256(4 * set_size(ndet)) + align256(4 * (size_t)ndet) + align256(8 * set_size(ndet)) +
+           align256(8 * (size_t)ndet);
+}
+
+struct CfgTable {
+    uint32_t *slot, *cslot;
+    unsigned long long *cmaxb;
+    double *cm;
+};
+
+// carve the configuration table out of the work buffer (take: the buffer's
+// bump allocator) and fill it for the vectors c
+template <bool CPLX, class Take>
+CfgTable cfg_table(const DevPlan &d, int R, const typename Scal<CPLX>::T *c, Take take, hipStream_t s)
+{
+    CfgTable t;
+    const uint64_t zs = set_size(d.ndet);
+    t.slot = (uint32_t *)take(4 * zs);
+    t.cslot = (uint32_t *)take(4 * (size_t)d.ndet);
+    t.cmaxb = (unsigned long long *)take(8 * zs);
+    t.cm = (double *)take(8 * (size_t)d.ndet);
+    if (d.ndet == 0) return t;
+    fill_u32(t.slot, (int64_t)zs, s, 0xffffffffu);
+    fill_u32((uint32_t *)t.cmaxb, 2 * (int64_t)zs, s, 0u);
+    const unsigned g = (unsigned)((d.ndet + 255) / 256);
+    hipLaunchKernelGGL(k_cfg_insert, dim3(g), dim3(256), 0, s, d.dets, d.ndet, t.slot, zs - 1, t.cslot);
+    hipLaunchKernelGGL(k_cfg_max<CPLX>, dim3(g), dim3(256), 0, s, d.ndet, R, c, (const uint32_t *)t.cslot, t.cmaxb);
+    hipLaunchKernelGGL(k_cfg_gather, dim3(g), dim3(256), 0, s, d.ndet, (const uint32_t *)t.cslot,
+                       (const unsigned long long *)t.cmaxb, t.cm);
+    return t;
+}
+
 // work-buffer layout (both the call and the size query use these)
 size_t fixed_bytes(int64_t ndet, int M)
 {
     return align256(8 * 16) + align256(8 * (PT2_MAXR + 2)) + align256(8 * (size_t)PT2_SUMB * PT2_MAXR) +
            align256(16 * (size_t)PT2_SUMB) + align256(8 * (size_t)ndet * M) + align256(8 * (size_t)M * M) +
-           align256(4 * set_size(ndet)) + align256(16 * set_size(ndet));
+           align256(4 * set_size(ndet)) + align256(16 * set_size(ndet)) + cfg_bytes(ndet);
 }
+
+// selection: 16 buckets per determinant of the space to start with
+int sel_lognb(int64_t ndet)
+{
+    int lognb = 4;
+    while (((int64_t)1 << lognb) < ndet * 16 && lognb < 24) lognb++;
+    return lognb;
+}
+
+// selection bucket tables: cnt, fill, ucnt, big (4 B); off, uoff, bigoff (8 B)
+size_t sel_table_bytes(int64_t NB) { return 4 * align256(4 * (size_t)NB) + 3 * align256(8 * (size_t)NB) + 1024; }
 
 size_t table_bytes(int64_t NB, int R)
 {
-    return align256(4 * (size_t)NB) * 2 + align256(8 * (size_t)NB) * 2 + align256(8 * (size_t)NB * R) +
+    // cnt, big; fill, off, bigoff; part; partc
+    return align256(4 * (size_t)NB) * 2 + align256(8 * (size_t)NB) * 3 + align256(8 * (size_t)NB * R) +
            align256(16 * (size_t)NB) + 1024 + 512;
 }
 
@@ -961,17 +1040,28 @@ size_t table_bytes(int64_t NB, int R)
 // selection of external determinants (iCIPT2 criterion, section 2.4)
 // ---------------------------------------------------------------------------
 
-// A is kept from J when max_k |H_AJ c_Jk| >= cmin and max_k |H_AJ c_Jk| /
-// |E0_k - H_AA| >= cmin (for determinants the bound on a double element is
-// the element itself).  MODE 0: count kept pairs; 1: per bucket; 2: write
-// the keys of the buckets [b0, b1).
+// Eqs. (iCI_Selection-1) and (iCI_Selection-2) per pair (A, nu), nu a
+// determinant of configuration J of P: the first test max_k |H c| >= cmin,
+// the second max_k |H c / (E0_k - H_AA)| >= cmin; when A's configuration is
+// doubly excited from J's (case B) the pair also needs H~ max|C| >= cmin,
+// Table 1's bound times the largest |C| over J's configuration, a test
+// shared by every determinant of J.  A is selected when one configuration J
+// has a pair passing the first test and a pair passing the second (the
+// maxima over nu of each test).  A pair passing neither cannot help and is
+// not kept; with one root the two tests compare one quantity |H c| with
+// two thresholds, so a configuration passes both exactly when one of its
+// pairs does, and only such pairs are kept.  Kept pairs carry the key A and
+// kx = configuration id << 2 | first << 1 | second.  MODE 0: count kept
+// pairs; 1: per bucket; 2: write the keys of the buckets [b0, b1).
 template <bool CPLX, int MODE>
 __global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetSet inP, int R,
                                                   const typename Scal<CPLX>::T *__restrict__ c, Roots roots,
                                                   double cmin, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt,
                                                   const uint64_t *__restrict__ off, uint32_t *fill, ulonglong2 *keys,
-                                                  const double *__restrict__ eps, const double *__restrict__ vg,
-                                                  unsigned long long *total, int64_t jbase)
+                                                  unsigned long long *kx, const double *__restrict__ eps,
+                                                  const double *__restrict__ vg, unsigned long long *total,
+                                                  int64_t jbase, const double *__restrict__ cm,
+                                                  const uint32_t *__restrict__ cslot)
 {
     using T = typename Scal<CPLX>::T;
     __shared__ uint8_t ol[2][128], vl[2][128];
@@ -996,6 +1086,8 @@ __global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetS
     double hjj;
     if constexpr (CPLX) hjj = ((const double2 *)p.diag)[J].x;
     else hjj = ((const double *)p.diag)[J];
+    const double cmj = cm[J];
+    const unsigned long long cfg = (unsigned long long)cslot[J] << 2;
     const int E = ex.start[ex.nclass];
     unsigned long long mine = 0;
     for (int e = threadIdx.x; e < E; e += blockDim.x) {
@@ -1010,6 +1102,10 @@ __global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetS
         }
         const uint64_t h = hash_det(a0, a1);
         if (in_set(inP, h, a0, a1)) continue;
+        if (S >= 0) {
+            double bound;
+            if (cfg_double<CPLX>(p, Q, S, P, Rr, bound) && !(bound * cmj >= cmin)) continue;
+        }
         const T v = exc_value<CPLX>(p, j0, j1, Q, S, P, Rr);
         const double haa = hjj + diag_delta(s_eps, vg, p.M, Q, S, P, Rr);
         double m1 = 0.0, m2 = 0.0;
@@ -1018,7 +1114,8 @@ __global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetS
             m1 = fmax(m1, a);
             m2 = fmax(m2, a / fabs(roots.e0[k] - haa));
         }
-        if (!(m1 >= cmin && m2 >= cmin)) continue;
+        const bool t1 = m1 >= cmin, t2 = m2 >= cmin;
+        if (R == 1 ? !(t1 && t2) : !(t1 || t2)) continue;
         if constexpr (MODE == 0) {
             mine++;
         } else {
@@ -1031,6 +1128,7 @@ __global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetS
                 if (k < cnt[b]) {
                     __builtin_nontemporal_store(a0, &keys[off[b] + k].x);
                     __builtin_nontemporal_store(a1, &keys[off[b] + k].y);
+                    __builtin_nontemporal_store(cfg | (t1 ? 2ULL : 0ULL) | (t2 ? 1ULL : 0ULL), &kx[off[b] + k]);
                 }
             }
         }
@@ -1042,18 +1140,81 @@ __global__ __launch_bounds__(256) void k_sel_enum(DevPlan p, ExcClasses ex, DetS
     }
 }
 
-// One workgroup per bucket: sort its keys in LDS, write the distinct ones
-// back to the front of the bucket's slice, ucnt[b] = how many.
-template <int CAP>
-__global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t *__restrict__ list,
-                                                    const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ off,
-                                                    ulonglong2 *keys, uint32_t *ucnt, uint32_t boff)
+// The selected determinants of one bucket from its keys sorted by (a0, a1,
+// kx) at positions [0, m): a distinct A is selected when, within one
+// configuration group of its records (equal kx >> 2), one record passed
+// the first test and one the second.  The workgroup's threads take
+// contiguous position ranges (a run starting in a thread's range is that
+// thread's, read to its end); an exclusive scan of their counts places the
+// selected A in sorted order at out.  Returns the count (every thread).
+template <class Get>
+__device__ uint32_t sel_compact(int64_t m, Get get, ulonglong2 *out, uint32_t *sc)
 {
-    __shared__ uint64_t s0[CAP], s1[CAP];
-    const uint32_t b = list ? list[boff + blockIdx.x] : b0 + boff + blockIdx.x;
+    const int64_t per = (m + 255) / 256;
+    const int64_t lo = min(m, (int64_t)threadIdx.x * per), hi = min(m, lo + per);
+    auto starts = [&](int64_t i) {
+        if (i == 0) return true;
+        const ulonglong2 x = get(i).k, y = get(i - 1).k;
+        return x.x != y.x || x.y != y.y;
+    };
+    auto selected = [&](int64_t i) {
+        const ulonglong2 a = get(i).k;
+        int64_t g0 = i;
+        while (g0 < m) {
+            const auto r0 = get(g0);
+            if (r0.k.x != a.x || r0.k.y != a.y) break;
+            const unsigned long long cfg = r0.x >> 2;
+            unsigned long long f = 0;
+            int64_t g1 = g0;
+            while (g1 < m) {
+                const auto r = get(g1);
+                if (r.k.x != a.x || r.k.y != a.y || (r.x >> 2) != cfg) break;
+                f |= r.x & 3ULL;
+                g1++;
+            }
+            if (f == 3) return true;
+            g0 = g1;
+        }
+        return false;
+    };
+    uint32_t cnt = 0;
+    for (int64_t i = lo; i < hi; i++)
+        if (starts(i) && selected(i)) cnt++;
+    sc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t u = sc[threadIdx.x] - cnt;
+    const uint32_t total = sc[255];
+    for (int64_t i = lo; i < hi; i++)
+        if (starts(i) && selected(i)) out[u++] = get(i).k;
+    return total;
+}
+
+struct SelKey {
+    ulonglong2 k;
+    unsigned long long x;
+};
+
+// Buckets of at most SEL_CAP keys, one workgroup each: the keys sorted in
+// LDS by (a0, a1, kx), the selected A written back to the front of the
+// bucket's slice, ucnt[b] = how many.
+__global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t *__restrict__ cnt,
+                                                    const uint64_t *__restrict__ off, ulonglong2 *keys,
+                                                    const unsigned long long *__restrict__ kx, uint32_t *ucnt,
+                                                    uint32_t boff)
+{
+    __shared__ uint64_t s0[SEL_CAP], s1[SEL_CAP], s2[SEL_CAP];
+    __shared__ uint32_t sc[256];
+    const uint32_t b = b0 + boff + blockIdx.x;
     const int m = (int)cnt[b];
-    if (m > CAP) return;  // handled by the larger instance
+    if (m > SEL_CAP) return;  // k_sel_unique_big
     ulonglong2 *kb = keys + off[b];
+    const unsigned long long *xb = kx + off[b];
     int np2 = 1;
     while (np2 < m) np2 <<= 1;
     for (int i = threadIdx.x; i < np2; i += blockDim.x) {
@@ -1061,9 +1222,9 @@ __global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t 
             const ulonglong2 k = kb[i];
             s0[i] = k.x;
             s1[i] = k.y;
+            s2[i] = xb[i];
         } else {
-            s0[i] = ~0ULL;
-            s1[i] = ~0ULL;
+            s0[i] = s1[i] = s2[i] = ~0ULL;
         }
     }
     __syncthreads();
@@ -1073,38 +1234,71 @@ __global__ __launch_bounds__(256) void k_sel_unique(uint32_t b0, const uint32_t 
                 const int l = i ^ jj;
                 if (l > i) {
                     const bool up = (i & k) == 0;
-                    const uint64_t x0 = s0[i], x1 = s1[i], y0 = s0[l], y1 = s1[l];
-                    const bool gt = x0 != y0 ? x0 > y0 : x1 > y1;
+                    const uint64_t x0 = s0[i], x1 = s1[i], x2 = s2[i], y0 = s0[l], y1 = s1[l], y2 = s2[l];
+                    const bool gt = x0 != y0 ? x0 > y0 : (x1 != y1 ? x1 > y1 : x2 > y2);
                     if (gt == up) {
-                        s0[i] = y0; s1[i] = y1;
-                        s0[l] = x0; s1[l] = x1;
+                        s0[i] = y0; s1[i] = y1; s2[i] = y2;
+                        s0[l] = x0; s1[l] = x1; s2[l] = x2;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    // compaction in sorted order: each thread takes a contiguous run of
-    // positions, an exclusive scan of the per-thread counts gives its output
-    // offset
+    const uint32_t u = sel_compact(
+        m, [&](int64_t i) { return SelKey{make_ulonglong2(s0[i], s1[i]), s2[i]}; }, kb, sc);
+    if (threadIdx.x == 0) ucnt[b] = u;
+}
+
+// Buckets of more than SEL_CAP keys (any size), one workgroup each: the
+// keys copied to the bucket's scratch (K0, K1, K2 at soff), sorted there by
+// a bitonic network in global memory, then compacted as above.
+__global__ __launch_bounds__(256) void k_sel_unique_big(const uint32_t *__restrict__ list,
+                                                        const uint64_t *__restrict__ soff,
+                                                        const uint32_t *__restrict__ cnt,
+                                                        const uint64_t *__restrict__ off, ulonglong2 *keys,
+                                                        const unsigned long long *__restrict__ kx, uint64_t *scr,
+                                                        uint64_t nscr, uint32_t *ucnt)
+{
     __shared__ uint32_t sc[256];
-    const int per = (m + 255) / 256;
-    const int lo = min(m, (int)threadIdx.x * per), hi = min(m, lo + per);
-    auto first = [&](int i) { return i == 0 || s0[i] != s0[i - 1] || s1[i] != s1[i - 1]; };
-    uint32_t c = 0;
-    for (int i = lo; i < hi; i++) c += first(i) ? 1u : 0u;
-    sc[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0u;
-        __syncthreads();
-        sc[threadIdx.x] += v;
-        __syncthreads();
+    const uint32_t b = list[blockIdx.x];
+    const int64_t m = cnt[b];
+    ulonglong2 *kb = keys + off[b];
+    const unsigned long long *xb = kx + off[b];
+    int64_t np2 = 1;
+    while (np2 < m) np2 <<= 1;
+    uint64_t *K0 = scr + soff[blockIdx.x], *K1 = K0 + nscr, *K2 = K1 + nscr;
+    for (int64_t i = threadIdx.x; i < np2; i += blockDim.x) {
+        if (i < m) {
+            const ulonglong2 k = kb[i];
+            K0[i] = k.x;
+            K1[i] = k.y;
+            K2[i] = xb[i];
+        } else {
+            K0[i] = K1[i] = K2[i] = ~0ULL;
+        }
     }
-    uint32_t u = sc[threadIdx.x] - c;
-    for (int i = lo; i < hi; i++)
-        if (first(i)) kb[u++] = make_ulonglong2(s0[i], s1[i]);
-    if (threadIdx.x == 255) ucnt[b] = sc[255];
+    __syncthreads();
+    for (int64_t k = 2; k <= np2; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t i = threadIdx.x; i < np2; i += blockDim.x) {
+                const int64_t l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t x0 = K0[i], x1 = K1[i], x2 = K2[i], y0 = K0[l], y1 = K1[l], y2 = K2[l];
+                    const bool gt = x0 != y0 ? x0 > y0 : (x1 != y1 ? x1 > y1 : x2 > y2);
+                    if (gt == up) {
+                        K0[i] = y0; K1[i] = y1; K2[i] = y2;
+                        K0[l] = x0; K1[l] = x1; K2[l] = x2;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t u = sel_compact(
+        m, [&](int64_t i) { return SelKey{make_ulonglong2(K0[i], K1[i]), K2[i]}; }, kb, sc);
+    if (threadIdx.x == 0) ucnt[b] = u;
 }
 
 // out[uoff[b] + i] = the i-th distinct key of bucket b (b in [b0, b0 + nb))
@@ -1136,7 +1330,7 @@ void launch_enum(const DevPlan &d, const ExcClasses &ex, const DetSet &inP, int 
                  double qmin, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt, const uint64_t *off,
                  unsigned long long *fill,
                  Rec *rec, typename Scal<CPLX>::T *val, const double *eps, const double *vg, unsigned long long *tot,
-                 hipStream_t s)
+                 const double *cm, hipStream_t s)
 {
     // hash bits kept in the records' sort key: all 32, or fewer when the
     // environment sets MW_PT2_KEY_BITS (1..31) to test runs of several A
@@ -1148,19 +1342,7 @@ void launch_enum(const DevPlan &d, const ExcClasses &ex, const DetSet &inP, int 
     for (int64_t j = 0; j < d.ndet; j += PT2_MAXGRID) {
         const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, d.ndet - j);
         hipLaunchKernelGGL((k_pt2_enum<CPLX, MODE>), dim3(g), dim3(256), 0, s, d, ex, inP, R, c, qmin, lognb, b0, b1,
-                           cnt, off, fill, rec, val, eps, vg, tot, j, kmask);
-    }
-}
-
-template <bool CPLX, int CAP>
-void launch_bucket(int64_t nblocks, int R, const Roots &roots, uint32_t b0, const uint32_t *list, const uint32_t *cnt,
-                   const uint64_t *off, const Rec *rec, const typename Scal<CPLX>::T *val, double *part,
-                   unsigned long long *partc, hipStream_t s)
-{
-    for (int64_t o = 0; o < nblocks; o += PT2_MAXGRID) {
-        const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, nblocks - o);
-        hipLaunchKernelGGL((k_pt2_bucket<CPLX, CAP>), dim3(g), dim3(256), 0, s, R, roots, b0, list, cnt, off, rec, val,
-                           part, partc, (uint32_t)o);
+                           cnt, off, fill, rec, val, eps, vg, tot, j, kmask, cm);
     }
 }
 
@@ -1218,7 +1400,7 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
     const uint64_t zs = set_size(d.ndet);
     uint32_t *sslot = (uint32_t *)take(4 * zs);
     ulonglong2 *skey = (ulonglong2 *)take(16 * zs);
-    if (used > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small");
+    if (used + cfg_bytes(d.ndet) > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small");
     const DetSet inP{skey, zs - 1};
     if (d.ndet > 0 && ex.start[ex.nclass] > 0) {
         fill_u32(sslot, (int64_t)zs, s, 0xffffffffu);
@@ -1228,114 +1410,129 @@ mw_status pt2_t(const DevPlan &d, int R, const void *cv, const double *e0, doubl
                            (const uint32_t *)sslot, zs, skey);
         const int64_t nt = std::max<int64_t>(d.ndet * d.M, (int64_t)d.M * d.M);
         hipLaunchKernelGGL(k_pt2_tables<CPLX>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, d, eps, vg);
+        // the largest |C| over every configuration (screening only)
+        const double *cm = nullptr;
+        if (qmin > 0.0) cm = cfg_table<CPLX>(d, R, c, take, s).cm;
         // kept pairs: counted when screening, else bounded by every excitation
         unsigned long long T_ = (unsigned long long)d.ndet * (unsigned long long)ex.start[ex.nclass];
         if (qmin > 0.0) {
             hipMemsetAsync(tot, 0, 8, s);
             launch_enum<CPLX, 0>(d, ex, inP, R, c, qmin, 0, 0u, 0u, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                 nullptr, tot, s);
+                                 nullptr, tot, cm, s);
             if (hipMemcpyAsync(&T_, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return fail(MW_EHIP, "pt2: counting pass failed");
         }
         st[4] = d.ndet * (int64_t)ex.start[ex.nclass];  // excitations enumerated per pass
         if (T_ > 0) {
+            // buckets of about PT2_MEAN records; any bucket, however large,
+            // is handled (over PT2_WCAP records by k_pt2_bucket_big), so the
+            // count is sized once
             int lognb = 0;
-            while (((uint64_t)PT2_MEAN << lognb) < T_ && lognb < 40) lognb++;
-            const size_t fixed = used;
-            std::vector<uint32_t> hc;
-            for (;;) {
-                const int64_t NB = (int64_t)1 << lognb;
-                used = fixed;
-                uint32_t *cnt = (uint32_t *)take(4 * (size_t)NB);
-                unsigned long long *fill = (unsigned long long *)take(8 * (size_t)NB);
-                uint64_t *off = (uint64_t *)take(8 * (size_t)NB);
-                double *part = (double *)take(8 * (size_t)NB * R);
-                unsigned long long *partc = (unsigned long long *)take(16 * (size_t)NB);
-                if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small for the bucket tables");
-                fill_u32(cnt, NB, s);
-                launch_enum<CPLX, 1>(d, ex, inP, R, c, qmin, lognb, 0u, 0u, cnt, nullptr, nullptr, nullptr, nullptr,
-                                     nullptr, nullptr, nullptr, s);
-                if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: counting launch failed");
-                hc.resize(NB);
-                if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess)
-                    return fail(MW_EHIP, "pt2: bucket counting failed");
-                const uint32_t mx = *std::max_element(hc.begin(), hc.end());
-                if (mx > (uint32_t)PT2_CAP_BIG) {
-                    // a bucket too large even for the larger kernel: split the
-                    // buckets (one A with more partners than that cannot be split)
-                    if (lognb >= 34) return fail(MW_EUNSUPPORTED, "pt2: an external determinant has too many partners");
-                    lognb++;
-                    continue;
+            while (((uint64_t)PT2_MEAN << lognb) < T_ && lognb < 32) lognb++;
+            const int64_t NB = (int64_t)1 << lognb;
+            uint32_t *cnt = (uint32_t *)take(4 * (size_t)NB);
+            unsigned long long *fill = (unsigned long long *)take(8 * (size_t)NB);
+            uint64_t *off = (uint64_t *)take(8 * (size_t)NB);
+            double *part = (double *)take(8 * (size_t)NB * R);
+            unsigned long long *partc = (unsigned long long *)take(16 * (size_t)NB);
+            uint32_t *big = (uint32_t *)take(4 * (size_t)NB);
+            uint64_t *bigoff = (uint64_t *)take(8 * (size_t)NB);
+            if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small for the bucket tables");
+            fill_u32(cnt, NB, s);
+            launch_enum<CPLX, 1>(d, ex, inP, R, c, qmin, lognb, 0u, 0u, cnt, nullptr, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, cm, s);
+            if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: counting launch failed");
+            std::vector<uint32_t> hc(NB);
+            if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(MW_EHIP, "pt2: bucket counting failed");
+            // passes over bucket ranges whose records (32 B + R values each)
+            // and, for the large buckets, sort scratch (12 B per position of
+            // the power-of-two range) fit the rest of the buffer
+            const size_t avail = work_bytes - used - 1024;
+            auto np2_of = [](uint64_t m) {
+                uint64_t q = 1;
+                while (q < m) q <<= 1;
+                return q;
+            };
+            auto pass_bytes = [&](uint64_t nrec, uint64_t nscr) {
+                return align256(nrec * sizeof(Rec)) + align256(nrec * R * sizeof(T)) + align256(8 * nscr) +
+                       align256(4 * nscr);
+            };
+            std::vector<uint64_t> ho(NB);
+            int64_t b0 = 0;
+            while (b0 < NB) {
+                uint64_t acc = 0, scr = 0;
+                int64_t b1 = b0;
+                std::vector<uint32_t> hb;
+                std::vector<uint64_t> hbo;
+                while (b1 < NB) {
+                    const uint64_t add = hc[b1] > (uint32_t)PT2_WCAP ? np2_of(hc[b1]) : 0;
+                    if (pass_bytes(acc + hc[b1], scr + add) > avail) break;
+                    ho[b1] = acc;
+                    acc += hc[b1];
+                    if (add) {
+                        hb.push_back((uint32_t)b1);
+                        hbo.push_back(scr);
+                    }
+                    scr += add;
+                    b1++;
                 }
-                uint32_t *big = (uint32_t *)take(4 * (size_t)NB);
-                if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "pt2: work buffer too small for the bucket tables");
-                // passes over bucket ranges whose records (32 B + R values
-                // each) fit the rest of the buffer
-                const size_t per = sizeof(Rec) + (size_t)R * sizeof(T);
-                const uint64_t cap_rec = (work_bytes - used - 512) / per;
+                if (b1 == b0) return fail(MW_EWORKSPACE, "pt2: work buffer too small for one bucket");
                 Rec *rec = (Rec *)(w + used);
-                T *val = (T *)(w + used + align256(cap_rec * sizeof(Rec)));
-                if ((char *)(val + cap_rec * R) > w + work_bytes) return fail(MW_EWORKSPACE, "pt2: layout overflow");
-                std::vector<uint64_t> ho(NB);
-                int64_t b0 = 0;
-                while (b0 < NB) {
-                    uint64_t acc = 0;
-                    int64_t b1 = b0;
-                    while (b1 < NB && acc + hc[b1] <= cap_rec) {
-                        ho[b1] = acc;
-                        acc += hc[b1];
-                        b1++;
+                T *val = (T *)((char *)rec + align256(acc * sizeof(Rec)));
+                uint64_t *skey2 = (uint64_t *)((char *)val + align256(acc * R * sizeof(T)));
+                uint32_t *sidx = (uint32_t *)((char *)skey2 + align256(8 * scr));
+                hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
+                hipLaunchKernelGGL(k_fill_cap, dim3((unsigned)((b1 - b0 + 255) / 256)), dim3(256), 0, s, fill + b0,
+                                   (const uint32_t *)cnt + b0, (int64_t)(b1 - b0));
+                ProfToken t = prof_begin("pt2_enum", s);
+                launch_enum<CPLX, 2>(d, ex, inP, R, c, qmin, lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, rec,
+                                     val, eps, vg, nullptr, cm, s);
+                prof_end(t, s);
+                t = prof_begin("pt2_bucket", s);
+                launch_bucket_wave<CPLX>(b1 - b0, R, roots, (uint32_t)b0, cnt, off, rec, val, part, partc, s);
+                prof_end(t, s);
+                if (!hb.empty()) {
+                    // one workgroup per large bucket (a grid of at most 2^22
+                    // workgroups per dispatch)
+                    hipMemcpyAsync(big, hb.data(), 4 * hb.size(), hipMemcpyHostToDevice, s);
+                    hipMemcpyAsync(bigoff, hbo.data(), 8 * hbo.size(), hipMemcpyHostToDevice, s);
+                    t = prof_begin("pt2_bucket_big", s);
+                    for (int64_t o = 0; o < (int64_t)hb.size(); o += PT2_MAXGRID) {
+                        const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, (int64_t)hb.size() - o);
+                        if (R == 1)
+                            hipLaunchKernelGGL((k_pt2_bucket_big<CPLX, 1>), dim3(g), dim3(256), 0, s, R, roots,
+                                               (uint32_t)b0, (const uint32_t *)big + o, (const uint64_t *)bigoff + o,
+                                               (const uint32_t *)cnt, (const uint64_t *)off, (const Rec *)rec,
+                                               (const T *)val, skey2, sidx, part, partc);
+                        else
+                            hipLaunchKernelGGL((k_pt2_bucket_big<CPLX, PT2_MAXR>), dim3(g), dim3(256), 0, s, R, roots,
+                                               (uint32_t)b0, (const uint32_t *)big + o, (const uint64_t *)bigoff + o,
+                                               (const uint32_t *)cnt, (const uint64_t *)off, (const Rec *)rec,
+                                               (const T *)val, skey2, sidx, part, partc);
                     }
-                    if (b1 == b0) return fail(MW_EWORKSPACE, "pt2: work buffer too small for one bucket");
-                    hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
-                    hipLaunchKernelGGL(k_fill_cap, dim3((unsigned)((b1 - b0 + 255) / 256)), dim3(256), 0, s, fill + b0,
-                                       (const uint32_t *)cnt + b0, (int64_t)(b1 - b0));
-                    ProfToken t = prof_begin("pt2_enum", s);
-                    launch_enum<CPLX, 2>(d, ex, inP, R, c, qmin, lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, rec,
-                                         val, eps, vg, nullptr, s);
                     prof_end(t, s);
-                    // buckets of this pass: up to PT2_WCAP records one wave
-                    // each; larger ones, listed, to the block kernels
-                    std::vector<uint32_t> hb;
-                    for (int64_t b = b0; b < b1; b++)
-                        if (hc[b] > (uint32_t)PT2_WCAP && hc[b] <= (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
-                    const int64_t nmid = (int64_t)hb.size();
-                    for (int64_t b = b0; b < b1; b++)
-                        if (hc[b] > (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
-                    t = prof_begin("pt2_bucket", s);
-                    launch_bucket_wave<CPLX>(b1 - b0, R, roots, (uint32_t)b0, cnt, off, rec, val, part, partc, s);
-                    if (!hb.empty()) {
-                        hipMemcpyAsync(big, hb.data(), 4 * hb.size(), hipMemcpyHostToDevice, s);
-                        if (nmid)
-                            launch_bucket<CPLX, PT2_CAP>(nmid, R, roots, (uint32_t)b0, big, cnt, off, rec, val, part,
-                                                         partc, s);
-                        if ((int64_t)hb.size() > nmid)
-                            launch_bucket<CPLX, PT2_CAP_BIG>((int64_t)hb.size() - nmid, R, roots, (uint32_t)b0,
-                                                             big + nmid, cnt, off, rec, val, part, partc, s);
-                    }
-                    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: pass launch failed");
-                    prof_end(t, s);
-                    hipLaunchKernelGGL(k_pt2_sum1, dim3(PT2_SUMB), dim3(256), 0, s, b1 - b0, R, (const double *)part,
-                                       (const unsigned long long *)partc, stmp, stmpc);
-                    hipLaunchKernelGGL(k_pt2_sum2, dim3(1), dim3(PT2_SUMB), 0, s, R, (const double *)stmp,
-                                       (const unsigned long long *)stmpc, sums, sumc);
-                    double hs[PT2_MAXR + 2];
-                    if (hipMemcpyAsync(hs, sums, 8 * (PT2_MAXR + 2), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                        hipStreamSynchronize(s) != hipSuccess)
-                        return fail(MW_EHIP, "pt2: pass failed");
-                    for (int k = 0; k < R; k++) e2[k] += hs[k];
-                    unsigned long long hcnt[2];
-                    memcpy(hcnt, hs + PT2_MAXR, 16);
-                    st[0] += (int64_t)hcnt[0];
-                    st[1] += (int64_t)hcnt[1];
-                    st[2]++;
-                    b0 = b1;
                 }
-                st[3] = NB;
-                break;
+                if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2: pass launch failed");
+                hipLaunchKernelGGL(k_pt2_sum1, dim3(PT2_SUMB), dim3(256), 0, s, b1 - b0, R, (const double *)part,
+                                   (const unsigned long long *)partc, stmp, stmpc);
+                hipLaunchKernelGGL(k_pt2_sum2, dim3(1), dim3(PT2_SUMB), 0, s, R, (const double *)stmp,
+                                   (const unsigned long long *)stmpc, sums, sumc);
+                double hs[PT2_MAXR + 2];
+                if (hipMemcpyAsync(hs, sums, 8 * (PT2_MAXR + 2), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return fail(MW_EHIP, "pt2: pass failed");
+                for (int k = 0; k < R; k++) e2[k] += hs[k];
+                unsigned long long hcnt[2];
+                memcpy(hcnt, hs + PT2_MAXR, 16);
+                st[0] += (int64_t)hcnt[0];
+                st[1] += (int64_t)hcnt[1];
+                st[2]++;
+                b0 = b1;
             }
+            st[3] = NB;
         }
     }
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "pt2 kernel launch failed");
@@ -1373,7 +1570,7 @@ mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, do
     const uint64_t zs = set_size(d.ndet);
     uint32_t *sslot = (uint32_t *)take(4 * zs);
     ulonglong2 *skey = (ulonglong2 *)take(16 * zs);
-    if (used > work_bytes) return fail(MW_EWORKSPACE, "select: work buffer too small");
+    if (used + cfg_bytes(d.ndet) > work_bytes) return fail(MW_EWORKSPACE, "select: work buffer too small");
     const DetSet inP{skey, zs - 1};
     if (d.ndet == 0 || ex.start[ex.nclass] == 0) return MW_OK;
     fill_u32(sslot, (int64_t)zs, s, 0xffffffffu);
@@ -1383,24 +1580,26 @@ mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, do
                        zs, skey);
     const int64_t nt = std::max<int64_t>(d.ndet * d.M, (int64_t)d.M * d.M);
     hipLaunchKernelGGL(k_pt2_tables<CPLX>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, d, eps, vg);
+    // configuration ids and the largest |C| over every configuration
+    const CfgTable cfg = cfg_table<CPLX>(d, R, c, take, s);
     auto enumerate = [&](auto mode, int lognb, uint32_t b0, uint32_t b1, uint32_t *cnt, const uint64_t *off,
-                         uint32_t *fill, ulonglong2 *keys) {
+                         uint32_t *fill, ulonglong2 *keys, unsigned long long *kx) {
         constexpr int MODE = decltype(mode)::value;
         for (int64_t j = 0; j < d.ndet; j += PT2_MAXGRID) {
             const unsigned g = (unsigned)std::min<int64_t>(PT2_MAXGRID, d.ndet - j);
             hipLaunchKernelGGL((k_sel_enum<CPLX, MODE>), dim3(g), dim3(256), 0, s, d, ex, inP, R, c, roots, cmin, lognb,
-                               b0, b1, cnt, off, fill, keys, (const double *)eps, (const double *)vg, tot, j);
+                               b0, b1, cnt, off, fill, keys, kx, (const double *)eps, (const double *)vg, tot, j,
+                               (const double *)cfg.cm, (const uint32_t *)cfg.cslot);
         }
     };
     // bucket count: 16 per determinant of the space to start with; the
-    // per-bucket counting pass also gives the total, and when a bucket holds
-    // more than the sort takes the count is redone with buckets sized from
-    // that total (no separate counting pass in the usual case)
-    int lognb = 10;
-    while (((int64_t)1 << lognb) < d.ndet * 16 && lognb < 24) lognb++;
+    // per-bucket counting pass gives the total too, and when the buckets
+    // average more than 4 PT2_MEAN keys the count is redone once with
+    // buckets sized from that total.  Buckets of any size are handled.
+    int lognb = sel_lognb(d.ndet);
     const size_t fixed = used;
     std::vector<uint32_t> hc, hu;
-    for (;;) {
+    for (int attempt = 0;; attempt++) {
         const int64_t NB = (int64_t)1 << lognb;
         used = fixed;
         uint32_t *cnt = (uint32_t *)take(4 * (size_t)NB);
@@ -1409,9 +1608,10 @@ mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, do
         uint32_t *big = (uint32_t *)take(4 * (size_t)NB);
         uint64_t *off = (uint64_t *)take(8 * (size_t)NB);
         uint64_t *uoff = (uint64_t *)take(8 * (size_t)NB);
+        uint64_t *bigoff = (uint64_t *)take(8 * (size_t)NB);
         if (used + 1024 > work_bytes) return fail(MW_EWORKSPACE, "select: work buffer too small for the bucket tables");
         fill_u32(cnt, NB, s);
-        enumerate(std::integral_constant<int, 1>(), lognb, 0u, 0u, cnt, nullptr, nullptr, nullptr);
+        enumerate(std::integral_constant<int, 1>(), lognb, 0u, 0u, cnt, nullptr, nullptr, nullptr, nullptr);
         if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "select: counting launch failed");
         hc.resize(NB);
         if (hipMemcpyAsync(hc.data(), cnt, 4 * (size_t)NB, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1420,45 +1620,65 @@ mw_status select_t(const DevPlan &d, int R, const void *cv, const double *e0, do
         uint64_t T_ = 0;
         for (uint32_t x : hc) T_ += x;
         if (T_ == 0) return MW_OK;
-        if (*std::max_element(hc.begin(), hc.end()) > (uint32_t)PT2_CAP_BIG) {
-            if (lognb >= 34) return fail(MW_EUNSUPPORTED, "select: a determinant is selected from too many partners");
-            int want = lognb + 1;
-            while (((uint64_t)PT2_MEAN << want) < T_ && want < 34) want++;
-            lognb = want;
+        if (attempt == 0 && T_ > (uint64_t)NB * 4 * PT2_MEAN && lognb < 32) {
+            while (((uint64_t)PT2_MEAN << lognb) < T_ && lognb < 32) lognb++;
             continue;
         }
-        const uint64_t cap = (work_bytes - used - 512) / sizeof(ulonglong2);
-        ulonglong2 *keys = (ulonglong2 *)(w + used);
+        // passes over bucket ranges whose keys (16 B + 8 B each) and, for the
+        // large buckets, sort scratch (24 B per position of the power-of-two
+        // range) fit the rest of the buffer
+        const size_t avail = work_bytes - used - 1024;
+        auto np2_of = [](uint64_t m) {
+            uint64_t q = 1;
+            while (q < m) q <<= 1;
+            return q;
+        };
+        auto pass_bytes = [&](uint64_t nk, uint64_t nscr) {
+            return align256(16 * nk) + align256(8 * nk) + align256(24 * nscr);
+        };
         std::vector<uint64_t> ho(NB), huo(NB);
         hu.resize(NB);
         uint64_t written = 0;
         int64_t b0 = 0;
         while (b0 < NB) {
-            uint64_t acc = 0;
+            uint64_t acc = 0, scr = 0;
             int64_t b1 = b0;
-            while (b1 < NB && acc + hc[b1] <= cap) {
+            std::vector<uint32_t> hb;
+            std::vector<uint64_t> hbo;
+            while (b1 < NB) {
+                const uint64_t add = hc[b1] > (uint32_t)SEL_CAP ? np2_of(hc[b1]) : 0;
+                if (pass_bytes(acc + hc[b1], scr + add) > avail) break;
                 ho[b1] = acc;
                 acc += hc[b1];
+                if (add) {
+                    hb.push_back((uint32_t)b1);
+                    hbo.push_back(scr);
+                }
+                scr += add;
                 b1++;
             }
             if (b1 == b0) return fail(MW_EWORKSPACE, "select: work buffer too small for one bucket");
+            ulonglong2 *keys = (ulonglong2 *)(w + used);
+            unsigned long long *kx = (unsigned long long *)((char *)keys + align256(16 * acc));
+            uint64_t *scrp = (uint64_t *)((char *)kx + align256(8 * acc));
             hipMemcpyAsync(off + b0, ho.data() + b0, 8 * (size_t)(b1 - b0), hipMemcpyHostToDevice, s);
             fill_u32(fill + b0, b1 - b0, s);
-            enumerate(std::integral_constant<int, 2>(), lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, keys);
-            std::vector<uint32_t> hb;
-            for (int64_t b = b0; b < b1; b++)
-                if (hc[b] > (uint32_t)PT2_CAP) hb.push_back((uint32_t)b);
+            enumerate(std::integral_constant<int, 2>(), lognb, (uint32_t)b0, (uint32_t)b1, cnt, off, fill, keys, kx);
             for (int64_t o = 0; o < b1 - b0; o += PT2_MAXGRID)
-                hipLaunchKernelGGL(k_sel_unique<PT2_CAP>, dim3((unsigned)std::min<int64_t>(PT2_MAXGRID, b1 - b0 - o)),
-                                   dim3(256), 0, s, (uint32_t)b0, (const uint32_t *)nullptr, (const uint32_t *)cnt,
-                                   (const uint64_t *)off, keys, ucnt, (uint32_t)o);
+                hipLaunchKernelGGL(k_sel_unique, dim3((unsigned)std::min<int64_t>(PT2_MAXGRID, b1 - b0 - o)), dim3(256),
+                                   0, s, (uint32_t)b0, (const uint32_t *)cnt, (const uint64_t *)off, keys,
+                                   (const unsigned long long *)kx, ucnt, (uint32_t)o);
             if (!hb.empty()) {
                 hipMemcpyAsync(big, hb.data(), 4 * hb.size(), hipMemcpyHostToDevice, s);
+                hipMemcpyAsync(bigoff, hbo.data(), 8 * hbo.size(), hipMemcpyHostToDevice, s);
+                ProfToken t = prof_begin("sel_unique_big", s);
                 for (int64_t o = 0; o < (int64_t)hb.size(); o += PT2_MAXGRID)
-                    hipLaunchKernelGGL(k_sel_unique<PT2_CAP_BIG>,
+                    hipLaunchKernelGGL(k_sel_unique_big,
                                        dim3((unsigned)std::min<int64_t>(PT2_MAXGRID, (int64_t)hb.size() - o)), dim3(256),
-                                       0, s, (uint32_t)b0, (const uint32_t *)big, (const uint32_t *)cnt,
-                                       (const uint64_t *)off, keys, ucnt, (uint32_t)o);
+                                       0, s, (const uint32_t *)big + o, (const uint64_t *)bigoff + o,
+                                       (const uint32_t *)cnt, (const uint64_t *)off, keys,
+                                       (const unsigned long long *)kx, scrp, scr, ucnt);
+                prof_end(t, s);
             }
             if (hipMemcpyAsync(hu.data() + b0, ucnt + b0, 4 * (size_t)(b1 - b0), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
@@ -1510,7 +1730,10 @@ extern "C" mw_status mw_pt2_work_bytes(mw_plan plan, int32_t nroots, size_t *byt
     uint64_t NB = 1;
     while (NB * PT2_MEAN < T) NB <<= 1;
     const size_t sc = cplx ? 16 : 8;
-    *bytes = fixed_bytes(d->ndet, d->M) + table_bytes((int64_t)NB, nroots) + 256 + T * (sizeof(Rec) + sc * nroots);
+    // the larger of the second-order energy's bucket tables and the
+    // selection's, so that the size serves mw_select too
+    const size_t tables = std::max(table_bytes((int64_t)NB, nroots), sel_table_bytes((int64_t)1 << sel_lognb(d->ndet)));
+    *bytes = fixed_bytes(d->ndet, d->M) + tables + 256 + T * (sizeof(Rec) + sc * nroots);
     return MW_OK;
 }
 

@@ -90,7 +90,8 @@ def test_pt2_spinor_complex(torch):
 
 @pytest.mark.parametrize("qmin", [1e-4, 1e-3])
 def test_pt2_screening(torch, qmin):
-    """The doubles screening |H_AJ| max_k |c_Jk| < qmin, same decisions."""
+    """Screening of configuration doubles by Table 1's bound against qmin /
+    max|C| over the configuration: the same decisions (exact counts)."""
     n = 12
     rng = synth.rng_for(5, 13, synth.SEED_SPACE)
     d = synth.random_space_spinfree(n, 4, 4, 500, rng)
@@ -99,6 +100,108 @@ def test_pt2_screening(torch, qmin):
     c = synth.ci_vectors(p.ndet, 1, np.random.default_rng(3))
     e2, st = _check(torch, p, c, -12.0, qmin=qmin)
     assert st["kept_pairs"] < sc.pt2(p, c, -12.0)[1]
+
+
+@pytest.mark.parametrize("qmin", [1e-4, 1e-3])
+def test_pt2_screening_roots_and_spinor(torch, qmin):
+    """The screening with three roots (max|C| over roots and the
+    configuration's determinants) on n=10 3a3b, and on a complex spinor
+    space (the bound over Kramers partners): exact counts, E2 1e-12."""
+    n = 10
+    rng = synth.rng_for(5, 17, synth.SEED_SPACE)
+    d = synth.random_space_spinfree(n, 3, 3, 500, rng)
+    p = _prob("spinfree", n, 3, 3, synth.complete_configurations(d, n)[:700], synth.one_body_real(n, rng),
+              synth.two_body_real(n, rng))
+    p.name = "sf-n10-3roots"
+    c = synth.ci_vectors(p.ndet, 3, np.random.default_rng(17))
+    _check(torch, p, c, -10.0 - np.arange(3), qmin=qmin)
+    rs = np.random.default_rng(18)
+    ds = synth.space_selected_spinor(8, 4, 900, rs)
+    q = _prob("spinor", 8, 4, -1, ds, synth.one_body_spinor(8, rs), synth.two_body_spinor(8, rs))
+    q.name = "spinor-screened"
+    _check(torch, q, synth.ci_vectors(q.ndet, 2, np.random.default_rng(19), complex_=True), [-9.0, -8.5], qmin=qmin)
+
+
+def _orbit8(g, p, q, r, s, v):
+    for a, b, c_, d in {(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r), (r, s, p, q), (s, r, p, q),
+                        (r, s, q, p), (s, r, q, p)}:
+        g[a, b, c_, d] = v
+
+
+def _hand(n, na, nb, dets, diag, orbits):
+    h = np.diag(np.asarray(diag, float))
+    g = np.zeros((n,) * 4)
+    for (pp, q, r, s_), v in orbits:
+        _orbit8(g, pp, q, r, s_, v)
+    d = np.array(sorted(dets), dtype=np.uint64)
+    pr = _prob("spinfree", n, na, nb, d, h, g)
+    pr.name = "hand"
+    return pr
+
+
+def test_pt2_hand_built_screening_cases(torch):
+    """The hand-built screening cases of the oracle's pins through mw_pt2:
+    a same-spin double with opposite-sign integrals (dropped by its bound),
+    an alpha-beta double kept by the exchange integral in its bound plus a
+    configuration single, the maximum over a configuration's determinants,
+    and a spinor bound set by a Kramers partner; counts exact, E2 1e-12."""
+    same = _hand(4, 2, 0, [[0b11, 0]], [-1, -1, 0.5, 0.5], [((2, 0, 3, 1), 0.6e-3), ((2, 1, 3, 0), -0.6e-3)])
+    for qmin in (0.0, 1e-3):
+        _check(torch, same, np.ones((1, 1)), -2.0, qmin=qmin)
+    ab = _hand(4, 1, 1, [[1, 2]], [-1, -1, 0.5, 0.5],
+               [((2, 0, 3, 1), 0.5e-3), ((2, 1, 3, 0), 2e-3), ((1, 0, 3, 1), 0.2e-3)])
+    _check(torch, ab, np.ones((1, 1)), -2.5, qmin=1e-3)
+    cfgmax = _hand(4, 1, 1, [[1, 2], [2, 1]], [-1, -1, 0.5, 0.5], [((2, 0, 3, 1), 1e-2)])
+    _check(torch, cfgmax, np.array([[1e-2], [1.0]]), -2.5, qmin=1e-3)
+    nk, M = 4, 8
+    h = np.diag(np.array([-1.0, -1.0, 0.5, 0.5] * 2)).astype(complex)
+    g = np.zeros((M,) * 4, complex)
+    for P, Q, R, S in [(6, 0, 3, 1), (3, 1, 6, 0), (0, 6, 1, 3), (1, 3, 0, 6)]:
+        g[P, Q, R, S] = 2e-3
+    sp = _prob("spinor", nk, 2, -1, np.array([[0b11, 0]]), h, g)
+    sp.name = "hand-spinor"
+    e2, st = _check(torch, sp, np.ones((1, 1), complex), -2.5, qmin=1e-3)
+    assert st["external"] == 25
+
+
+def _center_space(n, na, nb):
+    """Every single and double excitation of the lowest determinant A, A
+    left out: A is an external determinant with one partner per member."""
+    a0, a1 = (1 << na) - 1, (1 << nb) - 1
+    full = synth.space_fci(n, na, nb)
+    lvl = np.array([bin(int(x) ^ a0).count("1") + bin(int(y) ^ a1).count("1") for x, y in full])
+    return full[(lvl == 2) | (lvl == 4)], (a0, a1)
+
+
+@pytest.mark.parametrize("n,na,nb,partners", [(11, 4, 4, 1092), (16, 5, 5, 4235)])
+def test_pt2_select_large_buckets(torch, n, na, nb, partners):
+    """An external determinant connected to 1,092 or 4,235 determinants of
+    the space (every single and double of it): its bucket exceeds the wave
+    kernel's 1024 records (and the former 4096-record limit), so the
+    global-memory sort runs (profiled launches); E2 and counts equal the
+    oracle's, and the selection of the same space (cmin small) equals the
+    oracle's set and contains that determinant."""
+    from paper_2501_18185_amd import mw
+    d, (a0, a1) = _center_space(n, na, nb)
+    assert len(d) == partners
+    rng = np.random.default_rng(n)
+    p = _prob("spinfree", n, na, nb, d, synth.one_body_real(n, rng), synth.two_body_real(n, rng))
+    p.name = f"center-n{n}"
+    c = synth.ci_vectors(p.ndet, 1, np.random.default_rng(n + 1))
+    mw.profile(True)
+    _check(torch, p, c, -30.0)
+    mw.profile(False)
+    nbig, _ = mw.profile_read("pt2_bucket_big")
+    _say("large-bucket launches", nbig)
+    assert nbig >= 1
+    mw.profile(True)
+    got = _gpu_select(torch, p, c, -30.0, 1e-9)
+    mw.profile(False)
+    nsel, _ = mw.profile_read("sel_unique_big")
+    ref = sc.select(p, c, -30.0, 1e-9)
+    _say("selected", len(got), len(ref), "large-bucket launches", nsel)
+    assert nsel >= 1 and np.array_equal(got, ref)
+    assert [a0, a1] in got.tolist()
 
 
 def test_pt2_passes_and_reproducibility(torch):
@@ -203,6 +306,41 @@ def test_select_spinfree_vs_oracle(torch, cmin):
     assert np.array_equal(got, ref)
     if cmin == 0.0:
         assert len(got) == sc.pt2(p, c, e0)[2]
+
+
+@pytest.mark.parametrize("cmin", [1e-4, 1e-3])
+def test_select_three_roots_vs_oracle(torch, cmin):
+    """Three roots on a configuration-complete n=10 3a3b space: the tests'
+    maxima are taken over a configuration's determinants separately, so a
+    determinant can be selected without any single pair passing both; the
+    selected set equals the oracle's bit for bit."""
+    n = 10
+    rng = synth.rng_for(6, 10, synth.SEED_SPACE)
+    d = synth.random_space_spinfree(n, 3, 3, 400, rng)
+    p = _prob("spinfree", n, 3, 3, synth.complete_configurations(d, n), synth.one_body_real(n, rng),
+              synth.two_body_real(n, rng))
+    c = synth.ci_vectors(p.ndet, 3, np.random.default_rng(11))
+    e0 = [-10.0, -9.7, -9.4]
+    got = _gpu_select(torch, p, c, e0, cmin)
+    ref = sc.select(p, c, e0, cmin)
+    _say("selected 3 roots", len(got), len(ref))
+    assert np.array_equal(got, ref)
+
+
+def test_select_hand_built_cases(torch):
+    """The selection pins through mw_select: the case (B) bound test removes
+    a same-spin double whose element passes both tests; two roots whose
+    tests pass on different determinants of one configuration select A."""
+    same = _hand(4, 2, 0, [[0b11, 0]], [-1, -1, 0.5, 0.5], [((2, 0, 3, 1), 0.6e-3), ((2, 1, 3, 0), -0.6e-3)])
+    assert len(_gpu_select(torch, same, np.ones((1, 1)), 0.5, 1e-3)) == 0
+    x, y = 2e-3, 0.5e-3
+    q = _hand(3, 1, 1, [[1, 2], [2, 1]], [0.0, 0.0, 0.5], [((2, 1, 1, 0), y)])
+    q.h[2, 0] = q.h[0, 2] = x
+    c = np.array([[1.0, 0.0], [0.0, 1.0]])
+    e0 = [0.5 - 4.0, 0.5 - 0.25]
+    got = _gpu_select(torch, q, c, e0, 1e-3)
+    assert np.array_equal(got, sc.select(q, c, e0, 1e-3))
+    assert [4, 2] in got.tolist()
 
 
 def test_select_spinor_vs_oracle(torch):
