@@ -352,6 +352,19 @@ mw_status mw_csf_sigma(mw_csf csf, int32_t nroots, const double *c, double *sigm
                        mw_stream_t stream);
 mw_status mw_csf_destroy(mw_csf csf);
 
+/* mw_csf_sigma without a work argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  T c and H T c go to a static device array of
+ * 2^22 doubles (32 MiB) that the library holds on each device it runs on
+ * until the process ends; its address is taken once per device, on the
+ * first call with that device current (the device of the CSF basis and its
+ * plan).  Limit: 2 ndet nroots <= 2^22, else MW_EWORKSPACE and nothing is
+ * enqueued.  Calls no allocating routine.  Every call on a device shares
+ * that device's array: calls that overlap on one device (two streams, two
+ * threads) race and give wrong results; calls in one stream are ordered.
+ * The same results as mw_csf_sigma, bit for bit. */
+mw_status mw_csf_sigma_noalloc(mw_csf csf, int32_t nroots, const double *c, double *sigma, mw_stream_t stream);
+
 /* Lowest nroots eigenpairs of the Hamiltonian in the CSF basis (spin-pure
  * states of spin S): the block Davidson-Liu of mw_davidson over
  * mw_csf_sigma, preconditioned with D_mu = sum_I T_I,mu^2 H_II.  c0, c_out:

@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -348,6 +349,37 @@ static mw_status build_csf(mw_csf_s &C, const uint64_t *dets, int64_t N, int n, 
     return MW_OK;
 }
 
+// Device scratch of mw_csf_sigma_noalloc (for callers that cannot allocate):
+// the determinant vectors T c and H T c of one call, 2 ndet nroots doubles
+// at most CSF_SCRATCH_DOUBLES (32 MiB).  Each device holds its own copy of
+// this array from the library's load until the process ends.  Host code
+// never passes the array's name to a kernel: its device address is taken
+// once per device with hipGetSymbolAddress and kept in g_scratch_dev.
+constexpr size_t CSF_SCRATCH_DOUBLES = (size_t)1 << 22;
+static __device__ __align__(256) double scratch[CSF_SCRATCH_DOUBLES];
+
+constexpr int CSF_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[CSF_MAX_DEVICES];
+
+// device address of the scratch array on the current device
+static mw_status scratch_address(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MW_EHIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= CSF_MAX_DEVICES) return fail(MW_EUNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MW_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return MW_OK;
+}
+
 static mw_status csf_bound(mw_csf csf, int32_t nroots)
 {
     if (!csf) return fail(MW_EINVAL, "csf is NULL");
@@ -494,6 +526,27 @@ mw_status mw_csf_sigma(mw_csf csf, int32_t nroots, const double *c, double *sigm
     const DevPlan *d = mw_internal_devplan(csf->plan);
     if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace: call mw_plan_upload first");
     if (nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
+    double *cd = work, *sd = work + (size_t)csf->ndet * nroots;
+    if ((st = mw_csf_to_det(csf, nroots, c, cd, stream)) != MW_OK) return st;
+    if (csf->ndet > 0 && (st = launch_sigma(*d, nroots, cd, sd, (hipStream_t)stream)) != MW_OK) return st;
+    return mw_csf_from_det(csf, nroots, sd, sigma, stream);
+}
+
+mw_status mw_csf_sigma_noalloc(mw_csf csf, int32_t nroots, const double *c, double *sigma, mw_stream_t stream)
+{
+    mw_status st = csf_bound(csf, nroots);
+    if (st != MW_OK) return st;
+    if (!c || !sigma) return fail(MW_EINVAL, "c and sigma must be device pointers");
+    const DevPlan *d = mw_internal_devplan(csf->plan);
+    if (!d) return fail(MW_EWORKSPACE, "the plan has no workspace: call mw_plan_upload first");
+    if (nroots > d->max_roots) return fail(MW_EINVAL, "nroots must be in 1..max_roots of the plan");
+    const size_t need = 2 * (size_t)csf->ndet * (size_t)nroots;
+    if (need > CSF_SCRATCH_DOUBLES)
+        return fail(MW_EWORKSPACE, "mw_csf_sigma_noalloc: 2 ndet nroots = " + std::to_string(need) +
+                                       " doubles exceeds the static scratch of " +
+                                       std::to_string(CSF_SCRATCH_DOUBLES) + " doubles; use mw_csf_sigma");
+    double *work = nullptr;
+    if ((st = scratch_address(&work)) != MW_OK) return st;
     double *cd = work, *sd = work + (size_t)csf->ndet * nroots;
     if ((st = mw_csf_to_det(csf, nroots, c, cd, stream)) != MW_OK) return st;
     if (csf->ndet > 0 && (st = launch_sigma(*d, nroots, cd, sd, (hipStream_t)stream)) != MW_OK) return st;

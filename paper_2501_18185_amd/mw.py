@@ -92,6 +92,7 @@ def lib():
         L.mw_csf_to_det.argtypes = [vp, i32, vp, vp, vp]
         L.mw_csf_from_det.argtypes = [vp, i32, vp, vp, vp]
         L.mw_csf_sigma.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.mw_csf_sigma_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.mw_csf_destroy.argtypes = [vp]
         L.mw_csf_davidson_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
         L.mw_csf_davidson.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), C.c_double, i32, C.POINTER(i32), vp,
@@ -100,7 +101,7 @@ def lib():
         L.mw_csf_ivi.argtypes = [vp, i32, C.c_double, vp, vp, C.POINTER(C.c_double), C.c_double, i32,
                                  C.POINTER(i32), vp, sz, vp]
         for name in ("mw_csf_create", "mw_csf_workspace_bytes", "mw_csf_upload", "mw_csf_to_det",
-                     "mw_csf_from_det", "mw_csf_sigma", "mw_csf_destroy", "mw_csf_davidson_work_bytes",
+                     "mw_csf_from_det", "mw_csf_sigma", "mw_csf_sigma_noalloc", "mw_csf_destroy", "mw_csf_davidson_work_bytes",
                      "mw_csf_davidson", "mw_csf_ivi_work_bytes", "mw_csf_ivi"):
             getattr(L, name).restype = C.c_int
         for name in ("mw_plan_create", "mw_plan_workspace_bytes", "mw_plan_upload", "mw_plan_destroy",
@@ -501,6 +502,19 @@ class Csf:
             work = torch.empty(2 * self.plan.ndet * R, dtype=torch.float64, device=c.device)
         _check(lib().mw_csf_sigma(self._csf, R, C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()),
                                   C.c_void_p(work.data_ptr()), _stream()))
+        return out
+
+    def sigma_noalloc(self, c, out=None):
+        """sigma in the CSF basis through mw_csf_sigma_noalloc (the library's
+        static device scratch; out is the only buffer, allocated here when
+        not given)."""
+        torch = _require_gpu()
+        c = self._vec(c, self.ncsf)
+        R = 1 if c.dim() == 1 else c.shape[1]
+        if out is None:
+            out = torch.empty_like(c)
+        _check(lib().mw_csf_sigma_noalloc(self._csf, R, C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          _stream()))
         return out
 
     def _solve(self, c0, target, tol, max_iter, check):
