@@ -20,8 +20,9 @@
 //      partial.  No atomics.
 //  k_gather       (a few lanes per determinant and root):
 //      sigma_I = H_II c_I + sum of I's partials (fixed order), one write.
-//      Partials are written in member order (coalesced) and gathered
-//      through the determinant-major membership list.
+//      Partials are placed by determinant region (about 2 MB each) and
+//      writing XCD, and gathered through the determinant-major list of
+//      their positions: the region an XCD sums stays in its L2.
 //  k_diag         (one thread per determinant): H_II by Slater-Condon.
 //  k_batched_*    the same bodies over the packets of many problems.
 //
@@ -35,24 +36,12 @@
 #include "dev_common.h"
 
 // Partial sums are written once and read only by the gather, after the
-// group kernels: for one root, non-temporal stores keep them from
-// displacing integral rows and coefficients in L2 (0.3 % faster sigma on
-// the headline space); for 2-4 roots per lane (four times the bytes) they
-// were slower (4 roots: 18.66 against 17.91 ms) and plain stores are kept.
-template <int RC, typename T> __device__ __forceinline__ void nt_store(T v, T *p)
-{
-    if constexpr (RC == 1) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-template <int RC> __device__ __forceinline__ void nt_store(double2 v, double2 *p)
-{
-    if constexpr (RC == 1) {
-        __builtin_nontemporal_store(v.x, &p->x);
-        __builtin_nontemporal_store(v.y, &p->y);
-    } else {
-        *p = v;
-    }
-}
+// group kernels.  Their positions (the plan's slot_pos) are grouped by
+// determinant region and writing XCD, so a wave's stores are scattered over
+// the write frontiers of many regions; plain stores let L2 merge each
+// frontier line before it is written back (non-temporal stores measured
+// slower with this placement: sigma 9.74 against 9.62 ms).
+template <typename T> __device__ __forceinline__ void store_partial(T v, T *p) { *p = v; }
 
 namespace mw {
 
@@ -190,6 +179,8 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
     const uint32_t m = mfirst + lane;
     const bool act = m < mend;
     const uint2 me = p.mem[act ? m : mfirst];
+    // where this member's row partial goes (loaded now, used at the end)
+    const uint32_t mpos = act ? p.slot_pos[m] : 0u;
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
     const uint32_t negi = (me.y >> 16) & 1;
     const bool lay = (me.y >> 17) & 1;
@@ -216,6 +207,14 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
     for (uint32_t jj = j0 + 64 * a; jj < j1; jj += JS) {
         const uint32_t b = (jj - j0) >> 6;
         const uint32_t jb0 = j0 + 64 * b, jb1 = min(j1, jb0 + 64);
+        // position of the column partial this lane writes at the end of the
+        // pass (b > a), loaded before the pass's partner loads
+        uint32_t cpos = 0;
+        if (b > a && (lane & 7) == 0) {
+            const int vi = rs_value_of_lane(lane);
+            const uint32_t j = jj + vi / RC;
+            if (j < jb1 && vi % RC < nr) cpos = p.slot_pos[colbase + (j - j0) - 64 * (a + 1)];
+        }
         {
             T col[RS_NV];
             {
@@ -266,16 +265,15 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
                 const int vi = rs_value_of_lane(lane);
                 const uint32_t j = jj + vi / RC;
                 const int kk = vi % RC;
-                if (j < jb1 && kk < nr)
-                    nt_store<RC>(s, &partial[(colbase + (j - j0) - 64 * (a + 1)) * R + r0 + kk]);
+                if (j < jb1 && kk < nr) store_partial(s, &partial[(size_t)cpos * R + r0 + kk]);
             }
         }
     }
     if (act) {
-        T *out = partial + (size_t)m * R + r0;
+        T *out = partial + (size_t)mpos * R + r0;
 #pragma unroll
         for (int kk = 0; kk < RC; kk++)
-            if (kk < nr) nt_store<RC>(sc_add(acc[kk], dacc[kk]), &out[kk]);
+            if (kk < nr) store_partial(sc_add(acc[kk], dacc[kk]), &out[kk]);
     }
 }
 
@@ -301,6 +299,7 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
     const uint32_t m = mfirst + lane;
     const bool live = m < mend;
     const uint2 me = p.mem[live ? m : mfirst];
+    const uint32_t mpos = live ? p.slot_pos[m] : 0u;
     const uint32_t kk = live ? (me.y >> 24) & 63 : 0u;  // partners of this lane: steps [0, kk)
     const int lane0 = lane - (int)((me.y >> 18) & 63);  // lane of its group's first member
     const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
@@ -350,10 +349,10 @@ __device__ __forceinline__ void group_double_body(const DevPlan &p, int64_t wave
         }
     }
     if (!live) return;
-    T *out = partial + (size_t)m * R + r0;
+    T *out = partial + (size_t)mpos * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
-        if (k < nr) nt_store<RC>(acc[k], &out[k]);
+        if (k < nr) store_partial(acc[k], &out[k]);
 }
 
 // Workgroups are dealt to the 8 XCDs round robin (block b runs on XCD b % 8).
@@ -404,6 +403,7 @@ __device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave
     using T = typename Scal<CPLX>::T;
     const uint32_t mfirst = p.pk_off[wave], mend = p.pk_off[wave + 1];
     const uint32_t m = mfirst + lane;
+    const uint32_t mpos = m < mend ? p.slot_pos[m] : 0u;
     T acc[RC];
 #pragma unroll
     for (int k = 0; k < RC; k++) acc[k] = sc_zero(T());
@@ -460,10 +460,10 @@ __device__ __forceinline__ void group_single_body(const DevPlan &p, int64_t wave
         }
         if (!live) return;
     }
-    T *out = partial + (size_t)m * R + r0;
+    T *out = partial + (size_t)mpos * R + r0;
 #pragma unroll
     for (int k = 0; k < RC; k++)
-        if (k < nr) nt_store<RC>(acc[k], &out[k]);
+        if (k < nr) store_partial(acc[k], &out[k]);
 }
 
 template <bool CPLX, int RC>

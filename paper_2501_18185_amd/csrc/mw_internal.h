@@ -48,7 +48,8 @@ struct DevPlan {
     // members (group-major)
     const uint2 *mem;          // [nmem] {det, X | Y<<8 | (phi<0)<<16 | layout<<17}
     const uint32_t *mem_grp;   // [nmem] owning group
-    const uint32_t *slot_mem;  // partial-sum indices listed determinant by determinant
+    const uint32_t *slot_mem;  // partial-sum positions listed determinant by determinant
+    const uint32_t *slot_pos;  // [nmem + ncol] position of each logical partial slot
     const uint32_t *pk_off;    // [npacket+1] packets of <= 64 consecutive members
     // determinants
     const uint32_t *rowptr;    // [ndet+1] range of each determinant in slot_mem

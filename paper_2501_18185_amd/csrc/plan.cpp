@@ -140,6 +140,8 @@ struct HostPlan {
     std::vector<uint8_t> grp_type;
     std::vector<uint2> mem;
     std::vector<uint32_t> mem_grp, slot_mem, pk_off, rowptr, grp_col;
+    // position of each logical partial slot (membership, then column partials)
+    std::vector<uint32_t> slot_pos;
     int64_t ncol = 0;  // column partial sums of large double groups
     std::vector<double> h, w_same, w_opp, g_ab, a_pair, a_pair1, f_ref;
     // spinor plans: Table 1's |(ab|cd)| over Kramers pairs (see bound_table)
@@ -579,19 +581,90 @@ static mw_status build_groups(HostPlan &P)
         P.rowptr[P.mem[mi].x + 1] += 1 + (big ? t / 64 : 0);
     }
     for (int64_t i = 0; i < N; i++) P.rowptr[i + 1] += P.rowptr[i];
+    // Placement of the partial sums.  A logical slot (membership m, or nmem
+    // plus a column-partial index) is stored at slot_pos[slot].  Positions
+    // are grouped in regions of consecutive determinants holding about 2 MB
+    // of partials (the gather gives each XCD a contiguous eighth of the
+    // determinants, so the region it is summing stays in its L2), and inside
+    // a region by the XCD whose waves write them, in packet order: every
+    // region has one write frontier per XCD, written by that XCD only, whose
+    // lines fill in its L2 before they are written back.
+    const int64_t nslot = nmem + ncol;
+    const int sbytes = (P.cplx ? 16 : 8) * P.max_roots;
+    const int64_t reg_slots = std::max<int64_t>(4096, ((int64_t)2 << 20) / sbytes);
+    std::vector<uint32_t> reg_of(N);
+    int64_t nreg = 0;
+    {
+        int64_t acc = 0;
+        for (int64_t i = 0; i < N; i++) {
+            const int64_t c = (int64_t)P.rowptr[i + 1] - P.rowptr[i];
+            if (acc > 0 && acc + c > reg_slots) {
+                nreg++;
+                acc = 0;
+            }
+            reg_of[i] = (uint32_t)nreg;
+            acc += c;
+        }
+        nreg++;
+    }
+    // writer XCD of a packet: double-group packets w are launched with the
+    // XCD-aware block order (logical block w / 4 runs on XCD (w / 64) % 8),
+    // single-group packets in plain order (block (w - npd) / 4 on XCD
+    // block % 8)
+    const int64_t npk = (int64_t)P.pk_off.size() - 1, npd = P.npacket_double;
+    auto xcd_of = [&](int64_t w) -> int { return w < npd ? (int)((w / 64) % 8) : (int)(((w - npd) / 4) % 8); };
+    // the column-partial slots written by a packet: block a of a large
+    // double group writes [col0, col0 + k - 64 (a + 1))
+    auto col_range = [&](int64_t w, int64_t &c0, int64_t &c1, uint32_t &g, int64_t &k, int64_t &a) {
+        c0 = c1 = 0;
+        const uint32_t m0 = P.pk_off[w];
+        g = P.mem_grp[m0];
+        k = (int64_t)P.grp_off[g + 1] - P.grp_off[g];
+        const uint8_t ty = P.grp_type[g];
+        if (w >= npd || k < 64 || ty == G_SINGLE_A || ty == G_SINGLE_B || ty == G_SINGLE_S) return;
+        a = ((int64_t)m0 - P.grp_off[g]) / 64;
+        c0 = nmem + P.grp_col[g] + a * k - 32 * a * (a + 1);
+        c1 = c0 + (k - 64 * (a + 1));
+    };
+    std::vector<int64_t> start((size_t)nreg * 8 + 1, 0);
+    for (int64_t w = 0; w < npk; w++) {
+        const int x = xcd_of(w);
+        for (uint32_t m = P.pk_off[w]; m < P.pk_off[w + 1]; m++) start[(size_t)reg_of[P.mem[m].x] * 8 + x + 1]++;
+        int64_t c0, c1, k, a;
+        uint32_t g;
+        col_range(w, c0, c1, g, k, a);
+        for (int64_t cs = c0; cs < c1; cs++) {
+            const int64_t t = 64 * (a + 1) + (cs - c0);  // partner j's index in the group
+            start[(size_t)reg_of[P.mem[P.grp_off[g] + t].x] * 8 + x + 1]++;
+        }
+    }
+    for (size_t i = 1; i < start.size(); i++) start[i] += start[i - 1];
+    if (start.back() != nslot) return fail(MW_EINVAL, "internal: partial slots miscounted");
+    P.slot_pos.assign((size_t)nslot, 0);
+    for (int64_t w = 0; w < npk; w++) {
+        const int x = xcd_of(w);
+        for (uint32_t m = P.pk_off[w]; m < P.pk_off[w + 1]; m++)
+            P.slot_pos[m] = (uint32_t)start[(size_t)reg_of[P.mem[m].x] * 8 + x]++;
+        int64_t c0, c1, k, a;
+        uint32_t g;
+        col_range(w, c0, c1, g, k, a);
+        for (int64_t cs = c0; cs < c1; cs++) {
+            const int64_t t = 64 * (a + 1) + (cs - c0);
+            P.slot_pos[cs] = (uint32_t)start[(size_t)reg_of[P.mem[P.grp_off[g] + t].x] * 8 + x]++;
+        }
+    }
     std::vector<uint32_t> fillc(P.rowptr.begin(), P.rowptr.end() - 1);
     P.slot_mem.resize(P.rowptr[N]);
     for (int64_t mi = 0; mi < nmem; mi++) {
         const uint32_t det = P.mem[mi].x;
-        P.slot_mem[fillc[det]++] = (uint32_t)mi;
+        P.slot_mem[fillc[det]++] = P.slot_pos[mi];
         const uint32_t gi = P.mem_grp[mi];
         const int64_t t = (int64_t)mi - P.grp_off[gi];
         const int64_t k = (int64_t)P.grp_off[gi + 1] - P.grp_off[gi];
         const uint8_t ty = P.grp_type[gi];
         if (k < 64 || ty == G_SINGLE_A || ty == G_SINGLE_B || ty == G_SINGLE_S) continue;
         for (int64_t a = 0; a < t / 64; a++)
-            P.slot_mem[fillc[det]++] =
-                (uint32_t)(nmem + P.grp_col[gi] + a * k - 32 * a * (a + 1) + (t - 64 * (a + 1)));
+            P.slot_mem[fillc[det]++] = P.slot_pos[nmem + P.grp_col[gi] + a * k - 32 * a * (a + 1) + (t - 64 * (a + 1))];
     }
     return MW_OK;
 }
@@ -794,6 +867,7 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.mem = (const uint2 *)take(mem.size() * 8);
     t.mem_grp = (const uint32_t *)take(mem_grp.size() * 4);
     t.slot_mem = (const uint32_t *)take(slot_mem.size() * 4);
+    t.slot_pos = (const uint32_t *)take(slot_pos.size() * 4);
     t.pk_off = (const uint32_t *)take(pk_off.size() * 4);
     t.rowptr = (const uint32_t *)take(rowptr.size() * 4);
     t.dets = (const uint64_t *)take(dets.size() * 8);
@@ -904,6 +978,7 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.mem, P.mem.data(), P.mem.size() * 8) &&
               up(d.mem_grp, P.mem_grp.data(), P.mem_grp.size() * 4) &&
               up(d.slot_mem, P.slot_mem.data(), P.slot_mem.size() * 4) &&
+              up(d.slot_pos, P.slot_pos.data(), P.slot_pos.size() * 4) &&
               up(d.pk_off, P.pk_off.data(), P.pk_off.size() * 4) &&
               up(d.rowptr, P.rowptr.data(), P.rowptr.size() * 4) &&
               up(d.dets, P.dets.data(), P.dets.size() * 8) &&
