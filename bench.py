@@ -330,10 +330,14 @@ def leg_rdm(plan, c, prob):
     mw.profile(True)
     t_bwd = _time(lambda: plan.rdm(c1, c1), 3, warmup=1)
     mw.profile(False)
-    ng, mg = mw.profile_read("rdm_groups")
-    log(f"[bench] rdm: forward {t_fwd:.2f} ms, backward {t_bwd:.2f} ms")
+    nd, md = mw.profile_read("rdm_double")
+    ns, ms_ = mw.profile_read("rdm_single")
+    nq, mq = mw.profile_read("rdm_diag")
+    log(f"[bench] rdm: forward {t_fwd:.2f} ms, backward {t_bwd:.2f} ms (double pairs {md / max(nd, 1):.2f} ms, "
+        f"single pairs {ms_ / max(ns, 1):.2f} ms, diagonal and final pass {mq / max(nq, 1):.2f} ms)")
     return {"workload": prob.name, "forward_ms": t_fwd, "backward_ms": t_bwd,
-            "rdm_groups_ms": mg / max(ng, 1), "gamma_shape": [prob.norb] * 2, "Gamma_shape": [prob.norb] * 4}
+            "rdm_double_ms": md / max(nd, 1), "rdm_single_ms": ms_ / max(ns, 1), "rdm_diag_final_ms": mq / max(nq, 1),
+            "gamma_shape": [prob.norb] * 2, "Gamma_shape": [prob.norb] * 4}
 
 
 def leg_davidson(plan, prob, iters=10):

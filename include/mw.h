@@ -394,8 +394,10 @@ mw_status mw_csf_ivi(mw_csf csf, int32_t nroots, double target, const double *c0
 mw_status mw_connect_dump(mw_plan plan, int64_t *count, int64_t *out, mw_stream_t stream);
 
 /* Optional timing: while enabled, every kernel launch of the calls above is
- * bracketed by HIP events recorded on its stream ("group_sigma", "gather",
- * "rdm_groups", "rdm_diag", "batched_groups", "batched_gather").  Enabling
+ * bracketed by HIP events recorded on its stream ("group_sigma",
+ * "group_single", "gather", "rdm_double", "rdm_single", "rdm_diag",
+ * "batched_groups", "batched_gather", "pt2_enum", "pt2_bucket",
+ * "pt2_bucket_big", "sel_unique_big").  Enabling
  * clears earlier records.  mw_profile_read synchronises on the recorded
  * events and returns the number of launches and their summed duration (ms,
  * host outputs) for one kernel name. */

@@ -146,6 +146,61 @@ __global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const type
     }
 }
 
+// The contributions of one single pair (member i with det me.x adding
+// position Xi, partner with record o adding Xj; K the group's string).
+template <bool CPLX>
+__device__ __forceinline__ void rdm_single_pair(const DevPlan &p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
+                                                const typename Scal<CPLX>::T *__restrict__ ket, const RdmWeights &W,
+                                                typename Scal<CPLX>::T *__restrict__ S,
+                                                typename Scal<CPLX>::T *__restrict__ Cc, double *__restrict__ Ee,
+                                                uint8_t type, uint64_t k0, uint64_t k1, uint2 me, int Xi, uint32_t negi,
+                                                uint2 o)
+{
+    using T = typename Scal<CPLX>::T;
+    const int n = p.n;
+    const int Xj = o.y & 255;
+    T w = pair_weight<CPLX>(bra, ket, R, me.x, o.x, W);
+    w = sc_neg(w, (negi ^ ((o.y >> 16) & 1)) != 0);
+    if constexpr (!CPLX) {
+        const int s = type == G_SINGLE_A ? 0 : 1;
+        const int pp = Xi - s * n, qq = Xj - s * n;
+        // the member's orbital p (varying across the lanes of a large
+        // group, whose partner q is uniform) is the innermost index of
+        // every single accumulator, so the lanes' atomics coalesce
+        atomicAdd(&S[((size_t)s * n + qq) * n + pp], w);
+        // positions where K and omega differ: words (same spin, other
+        // spin); C[q][x][p] collects the Coulomb-like terms of every X,
+        // E[q][x][p] the exchange-like ones of X of the same spin (both
+        // n^3, L2-resident; expanded into Gamma by the final pass)
+        double *Cq = Cc + (size_t)qq * n * n + pp, *Eq = Ee + (size_t)qq * n * n + pp;
+        for (int part = 0; part < 4; part++) {
+            const bool same = part < 2;
+            const uint64_t kw = (same == (s == 0)) ? k0 : k1;
+            const uint64_t rw = (same == (s == 0)) ? p.ref0 : p.ref1;
+            const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
+            const double sw = (part & 1) ? -w : w;
+            for (uint64_t x = bits; x; x &= x - 1) {
+                const int xx = __builtin_ctzll(x);
+                atomicAdd(&Cq[(size_t)xx * n], sw);
+                if (same) atomicAdd(&Eq[(size_t)xx * n], sw);
+            }
+        }
+    } else {
+        const int M = p.M;
+        atom_add(&S[(size_t)Xj * M + Xi], w);
+        // C[Q][X][P] (M^3, P innermost) collects the four terms of every X
+        T *Cq = Cc + (size_t)Xj * M * M + Xi;
+        for (int part = 0; part < 4; part++) {
+            const uint64_t kw = (part < 2) ? k0 : k1;
+            const uint64_t rw = (part < 2) ? p.ref0 : p.ref1;
+            const int base = (part < 2) ? 0 : n;
+            const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
+            const T sw = sc_neg(w, (part & 1) != 0);
+            for (uint64_t x = bits; x; x &= x - 1) atom_add(&Cq[(size_t)(base + __builtin_ctzll(x)) * M], sw);
+        }
+    }
+}
+
 template <bool CPLX, bool SYM>
 __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
@@ -153,7 +208,6 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
                                                     typename Scal<CPLX>::T *__restrict__ Cc,
                                                     double *__restrict__ Ee, int64_t copy_stride)
 {
-    using T = typename Scal<CPLX>::T;
     const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (wave >= p.npacket) return;
@@ -165,8 +219,29 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
         Cc += o;
         if (Ee) Ee += o;
     }
-    const uint32_t m = p.pk_off[wave] + lane;
-    if (m >= p.pk_off[wave + 1]) return;
+    const uint32_t mfirst = p.pk_off[wave], mend = p.pk_off[wave + 1];
+    const uint32_t m = mfirst + lane;
+    if (((p.mem[mfirst].y >> 24) & 63) == 0) {
+        // a 64-member block of a large group: every lane visits the same
+        // partner in the same step (SYM: partners after the lane's member
+        // masked), so the lanes' atomics into S, C, E, whose innermost index
+        // is the member's position, coalesce into few requests
+        const uint32_t g = p.mem_grp[mfirst];
+        const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
+        const uint8_t type = p.grp_type[g];
+        const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
+        const bool act = m < mend;
+        const uint2 me = p.mem[act ? m : mfirst];
+        const int Xi = me.y & 255;
+        const uint32_t negi = (me.y >> 16) & 1;
+        for (uint32_t j = SYM ? mfirst + 1 : j0; j < j1; j++) {
+            const uint2 o = p.mem[j];
+            if (!act || (o.y & 255) == (uint32_t)Xi || (SYM && j <= m)) continue;
+            rdm_single_pair<CPLX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o);
+        }
+        return;
+    }
+    if (m >= mend) return;
     const uint32_t g = p.mem_grp[m];
     const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
     const uint8_t type = p.grp_type[g];
@@ -174,49 +249,11 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
     const int Xi = me.y & 255;
     const uint32_t negi = (me.y >> 16) & 1;
     const uint64_t k0 = p.grp_key[2 * g], k1 = p.grp_key[2 * g + 1];
-    const int n = p.n;
     // SYM: partners after i only; k_rdm_mirror adds the reversed pairs
     for (uint32_t j = SYM ? max(j0, m + 1) : j0; j < j1; j++) {
         const uint2 o = p.mem[j];
-        const int Xj = o.y & 255;
-        if (Xj == Xi) continue;
-        T w = pair_weight<CPLX>(bra, ket, R, me.x, o.x, W);
-        w = sc_neg(w, (negi ^ ((o.y >> 16) & 1)) != 0);
-        if constexpr (!CPLX) {
-            const int s = type == G_SINGLE_A ? 0 : 1;
-            const int pp = Xi - s * n, qq = Xj - s * n;
-            atomicAdd(&S[((size_t)s * n + pp) * n + qq], w);
-            // positions where K and omega differ: words (same spin, other
-            // spin); C[p][q][x] collects the Coulomb-like terms of every X,
-            // E[p][q][x] the exchange-like ones of X of the same spin (both
-            // n^3, L2-resident; expanded into Gamma by the final pass)
-            double *Cpq = Cc + ((size_t)pp * n + qq) * n, *Epq = Ee + ((size_t)pp * n + qq) * n;
-            for (int part = 0; part < 4; part++) {
-                const bool same = part < 2;
-                const uint64_t kw = (same == (s == 0)) ? k0 : k1;
-                const uint64_t rw = (same == (s == 0)) ? p.ref0 : p.ref1;
-                const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
-                const double sw = (part & 1) ? -w : w;
-                for (uint64_t x = bits; x; x &= x - 1) {
-                    const int xx = __builtin_ctzll(x);
-                    atomicAdd(&Cpq[xx], sw);
-                    if (same) atomicAdd(&Epq[xx], sw);
-                }
-            }
-        } else {
-            const int M = p.M;
-            atom_add(&S[(size_t)Xi * M + Xj], w);
-            // C[P][Q][X] (M^3) collects the four terms of every X
-            T *Cpq = Cc + ((size_t)Xi * M + Xj) * M;
-            for (int part = 0; part < 4; part++) {
-                const uint64_t kw = (part < 2) ? k0 : k1;
-                const uint64_t rw = (part < 2) ? p.ref0 : p.ref1;
-                const int base = (part < 2) ? 0 : n;
-                const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
-                const T sw = sc_neg(w, (part & 1) != 0);
-                for (uint64_t x = bits; x; x &= x - 1) atom_add(&Cpq[base + __builtin_ctzll(x)], sw);
-            }
-        }
+        if ((int)(o.y & 255) == Xi) continue;
+        rdm_single_pair<CPLX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o);
     }
 }
 
@@ -346,6 +383,25 @@ __global__ __launch_bounds__(256) void k_rdm_mirror(T *X, int m, int inner, int 
     *b = sc_add(vb, sc_conj(va));
 }
 
+// SYM pass for X[Q][x][P] (P innermost, x over m entries): X[Q][x][P] and
+// X[P][x][Q] (P < Q) both become their sum with the other's conjugate; the
+// `outer` blocks are independent.
+template <class T>
+__global__ __launch_bounds__(256) void k_rdm_mirror_qxp(T *X, int m, int outer)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)m * m * m;
+    if (t >= per * outer) return;
+    const int64_t o = t / per, r = t % per;
+    const int Q = (int)(r / ((int64_t)m * m)), x = (int)(r / m % m), P = (int)(r % m);
+    if (P >= Q) return;
+    T *a = X + o * per + ((int64_t)Q * m + x) * m + P;
+    T *b = X + o * per + ((int64_t)P * m + x) * m + Q;
+    const T va = *a, vb = *b;
+    *a = sc_add(va, sc_conj(vb));
+    *b = sc_add(vb, sc_conj(va));
+}
+
 __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double *__restrict__ dab,
                                                          const double *__restrict__ dt0,
                                                          const double *__restrict__ dt1, const double *__restrict__ S,
@@ -362,14 +418,16 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double
     // visited once and the reversed ones add the entry (q,p,s,r)
     double v = dab[g4(n, b, dd, a, c)] + dab[g4(n, dd, b, c, a)] + d_term(dt0, dt1, p.npair, n, a, b, c, dd);
     if (sym) v += dab[g4(n, a, c, b, dd)] + dab[g4(n, c, a, dd, b)] + d_term(dt0, dt1, p.npair, n, b, a, dd, c);
+    // S[s][q][p], C[q][x][p], E[q][x][p] (p innermost)
     const double *S0 = S, *S1 = S + (size_t)n * n;
     auto occ = [&](uint64_t w, int x) { return (double)((w >> x) & 1); };
-    auto cpq = [&](const double *X, int pp, int qq, int xx) { return X[((size_t)pp * n + qq) * n + xx]; };
+    auto sg = [&](const double *X, int pp, int qq) { return X[(size_t)qq * n + pp]; };
+    auto cpq = [&](const double *X, int pp, int qq, int xx) { return X[((size_t)qq * n + xx) * n + pp]; };
     // single excitations: reference string omega (through S) + corrections
-    if (c == dd) v += (S0[a * n + b] + S1[a * n + b]) * (occ(p.ref0, c) + occ(p.ref1, c)) + cpq(Cc, a, b, c);
-    if (a == b) v += (S0[c * n + dd] + S1[c * n + dd]) * (occ(p.ref0, a) + occ(p.ref1, a)) + cpq(Cc, c, dd, a);
-    if (b == c) v -= S0[a * n + dd] * occ(p.ref0, b) + S1[a * n + dd] * occ(p.ref1, b) + cpq(Ee, a, dd, b);
-    if (a == dd) v -= S0[c * n + b] * occ(p.ref0, a) + S1[c * n + b] * occ(p.ref1, a) + cpq(Ee, c, b, a);
+    if (c == dd) v += (sg(S0, a, b) + sg(S1, a, b)) * (occ(p.ref0, c) + occ(p.ref1, c)) + cpq(Cc, a, b, c);
+    if (a == b) v += (sg(S0, c, dd) + sg(S1, c, dd)) * (occ(p.ref0, a) + occ(p.ref1, a)) + cpq(Cc, c, dd, a);
+    if (b == c) v -= sg(S0, a, dd) * occ(p.ref0, b) + sg(S1, a, dd) * occ(p.ref1, b) + cpq(Ee, a, dd, b);
+    if (a == dd) v -= sg(S0, c, b) * occ(p.ref0, a) + sg(S1, c, b) * occ(p.ref1, a) + cpq(Ee, c, b, a);
     // diagonal terms from the occupation correlations D over 2n positions
     auto Dg = [&](int A, int B) { return D[(size_t)A * M + B]; };
     if (a == b && c == dd) {
@@ -381,7 +439,7 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_sf(DevPlan p, const double
     Gam[t] = fac_g * v;
     if (t < (int64_t)n * n) {
         const int pa = (int)(t / n), qa = (int)(t % n);
-        gam[t] = S0[t] + S1[t] + (pa == qa ? Dg(pa, pa) + Dg(n + pa, n + pa) : 0.0);
+        gam[t] = sg(S0, pa, qa) + sg(S1, pa, qa) + (pa == qa ? Dg(pa, pa) + Dg(n + pa, n + pa) : 0.0);
     }
 }
 
@@ -401,18 +459,20 @@ __global__ __launch_bounds__(256) void k_rdm_finalize_spinor(DevPlan p, const do
     double2 v = d_term(dt0, dt1, p.npair, M, a, b, c, dd);
     if (sym) v = sc_add(v, sc_conj(d_term(dt0, dt1, p.npair, M, b, a, dd, c)));
     auto inref = [&](int X) { return X < n ? ((p.ref0 >> X) & 1) : ((p.ref1 >> (X - n)) & 1); };
-    auto cpq = [&](int P, int Q, int X) { return Cc[((size_t)P * M + Q) * M + X]; };
-    if (c == dd) v = sc_add(v, sc_add(inref(c) ? S[(size_t)a * M + b] : sc_zero(double2()), cpq(a, b, c)));
-    if (a == b) v = sc_add(v, sc_add(inref(a) ? S[(size_t)c * M + dd] : sc_zero(double2()), cpq(c, dd, a)));
-    if (b == c) v = sc_add(v, sc_neg(sc_add(inref(b) ? S[(size_t)a * M + dd] : sc_zero(double2()), cpq(a, dd, b)), true));
-    if (a == dd) v = sc_add(v, sc_neg(sc_add(inref(a) ? S[(size_t)c * M + b] : sc_zero(double2()), cpq(c, b, a)), true));
+    // S[Q][P], C[Q][X][P] (P innermost)
+    auto cpq = [&](int P, int Q, int X) { return Cc[((size_t)Q * M + X) * M + P]; };
+    auto sg = [&](int P, int Q) { return S[(size_t)Q * M + P]; };
+    if (c == dd) v = sc_add(v, sc_add(inref(c) ? sg(a, b) : sc_zero(double2()), cpq(a, b, c)));
+    if (a == b) v = sc_add(v, sc_add(inref(a) ? sg(c, dd) : sc_zero(double2()), cpq(c, dd, a)));
+    if (b == c) v = sc_add(v, sc_neg(sc_add(inref(b) ? sg(a, dd) : sc_zero(double2()), cpq(a, dd, b)), true));
+    if (a == dd) v = sc_add(v, sc_neg(sc_add(inref(a) ? sg(c, b) : sc_zero(double2()), cpq(c, b, a)), true));
     if (a == b && c == dd && a != c) v = sc_add(v, D[(size_t)a * M + c]);
     if (a == dd && b == c && a != b) v = sc_add(v, sc_neg(D[(size_t)a * M + b], true));
     if (conj) v = sc_conj(v);
     Gam[t] = make_double2(fac_g * v.x, fac_g * v.y);
     if (t < (int64_t)M * M) {
         const int A = (int)(t / M), B = (int)(t % M);
-        const double2 gv = sc_add(S[t], A == B ? D[t] : sc_zero(double2()));
+        const double2 gv = sc_add(sg(A, B), A == B ? D[t] : sc_zero(double2()));
         gam[t] = conj ? sc_conj(gv) : gv;
     }
 }
@@ -457,17 +517,24 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         double *dab = (double *)p.partial, *dt0 = dab + n4, *dt1 = dt0 + np2, *S = dt1 + np2;
         double *Cc = S + 2 * (int64_t)n * n, *Ee = Cc + n3, *D = S + RDM_COPIES * cs, *part = D + mm;
         zero(dab, n4 + 2 * np2 + RDM_COPIES * cs, s);
-        ProfToken t = prof_begin("rdm_groups", s);
-        if (sym) {
-            if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8, true>), dim3(gdx), dim3(256), 0, s, p, R,
-                                       (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
-            if (gs) hipLaunchKernelGGL((k_rdm_single<false, true>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
-        } else {
-            if (gd) hipLaunchKernelGGL((k_rdm_double<false, 8, false>), dim3(gdx), dim3(256), 0, s, p, R,
-                                       (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
-            if (gs) hipLaunchKernelGGL((k_rdm_single<false, false>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
+        ProfToken t = prof_begin("rdm_double", s);
+        if (gd) {
+            if (sym)
+                hipLaunchKernelGGL((k_rdm_double<false, 8, true>), dim3(gdx), dim3(256), 0, s, p, R,
+                                   (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
+            else
+                hipLaunchKernelGGL((k_rdm_double<false, 8, false>), dim3(gdx), dim3(256), 0, s, p, R,
+                                   (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
+        }
+        prof_end(t, s);
+        t = prof_begin("rdm_single", s);
+        if (gs) {
+            if (sym)
+                hipLaunchKernelGGL((k_rdm_single<false, true>), dim3(gs), dim3(256), 0, s, p, R,
+                                   (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
+            else
+                hipLaunchKernelGGL((k_rdm_single<false, false>), dim3(gs), dim3(256), 0, s, p, R,
+                                   (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
         }
         prof_end(t, s);
         hipLaunchKernelGGL(k_rdm_fold<double>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
@@ -475,7 +542,7 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         if (sym) {
             hipLaunchKernelGGL(k_rdm_mirror<double>, dim3((unsigned)((2 * (int64_t)n * n + 255) / 256)), dim3(256), 0,
                                s, S, n, 1, 2);
-            hipLaunchKernelGGL(k_rdm_mirror<double>, dim3((unsigned)((2 * n3 + 255) / 256)), dim3(256), 0, s, Cc, n,
+            hipLaunchKernelGGL(k_rdm_mirror_qxp<double>, dim3((unsigned)((2 * n3 + 255) / 256)), dim3(256), 0, s, Cc,
                                n, 2);
         }
         t = prof_begin("rdm_diag", s);
@@ -493,24 +560,31 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2, *Cc = S + mm,
                 *D = S + RDM_COPIES * cs, *part = D + mm;
         zero((double *)dt0, 2 * (2 * np2 + RDM_COPIES * cs), s);
-        ProfToken t = prof_begin("rdm_groups", s);
-        if (sym) {
-            if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4, true>), dim3(gdx), dim3(256), 0, s, p, R,
-                                       (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
-            if (gs) hipLaunchKernelGGL((k_rdm_single<true, true>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
-        } else {
-            if (gd) hipLaunchKernelGGL((k_rdm_double<true, 4, false>), dim3(gdx), dim3(256), 0, s, p, R,
-                                       (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
-            if (gs) hipLaunchKernelGGL((k_rdm_single<true, false>), dim3(gs), dim3(256), 0, s, p, R,
-                                       (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
+        ProfToken t = prof_begin("rdm_double", s);
+        if (gd) {
+            if (sym)
+                hipLaunchKernelGGL((k_rdm_double<true, 4, true>), dim3(gdx), dim3(256), 0, s, p, R,
+                                   (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
+            else
+                hipLaunchKernelGGL((k_rdm_double<true, 4, false>), dim3(gdx), dim3(256), 0, s, p, R,
+                                   (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
+        }
+        prof_end(t, s);
+        t = prof_begin("rdm_single", s);
+        if (gs) {
+            if (sym)
+                hipLaunchKernelGGL((k_rdm_single<true, true>), dim3(gs), dim3(256), 0, s, p, R,
+                                   (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
+            else
+                hipLaunchKernelGGL((k_rdm_single<true, false>), dim3(gs), dim3(256), 0, s, p, R,
+                                   (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
         }
         prof_end(t, s);
         hipLaunchKernelGGL(k_rdm_fold<double2>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
                            RDM_COPIES);
         if (sym) {
             hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, S, M, 1, 1);
-            hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Cc, M, M,
+            hipLaunchKernelGGL(k_rdm_mirror_qxp<double2>, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Cc, M,
                                1);
         }
         t = prof_begin("rdm_diag", s);
