@@ -408,6 +408,26 @@ def leg_batched():
     pairs = sum(pl.info("pairs") for pl in plans)
     terms = (pairs + sum(p.ndet for p in probs)) * R
     log(f"[bench] batched: graph {t_batched:.2f} ms, 16x4-root {t_plain4:.2f} ms, 64x1-root {t_plain1:.2f} ms")
+    # energies and every gradient (c, h, g) of sum_i sum_k E_ik: batched
+    # sigma + batched energies + one captured graph of the gradient kernels,
+    # against the same calls made problem by problem
+    ges = [torch.ones(R, dtype=torch.float64, device="cuda") for _ in cs]
+    gouts = mw.energy_backward_batched(plans, cs, outs, ges)
+
+    def batched_grad():
+        mw.sigma_batched(plans, cs, outs)
+        mw.energy_batched(plans, cs, outs)
+        mw.energy_backward_batched(plans, cs, outs, ges, outs=gouts)
+
+    def plain_grad():
+        for pl, c, o, ge in zip(plans, cs, outs, ges):
+            pl.sigma(c, out=o)
+            pl.energy(c, o)
+            pl.energy_backward(c, o, ge)
+
+    t_grad_batched = _time(batched_grad, 5)
+    t_grad_plain = _time(plain_grad, 5)
+    log(f"[bench] batched energy+gradients: graph {t_grad_batched:.2f} ms, 16 plain {t_grad_plain:.2f} ms")
     return {"workload": "batch16-n16..48-6..12e-1e4..5e5-R4", "ndet_total": sum(p.ndet for p in probs),
             "pairs_total": pairs, "blocks_per_cu": bpc,
             "batched_graph_ms": t_batched, "plain_16x4_ms": t_plain4,
@@ -418,7 +438,9 @@ def leg_batched():
             # integral word and the partner's R coefficients
             "batched_algorithmic_GBps": pairs * (8 * R + 8) / (t_batched * 1e-3) / 1e9,
             "batched_hbm_frac": pairs * (8 * R + 8) / (t_batched * 1e-3) / (HBM_PEAK_GBS * 1e9),
-            "speedup_vs_16x4": t_plain4 / t_batched, "speedup_vs_64x1": t_plain1 / t_batched}
+            "speedup_vs_16x4": t_plain4 / t_batched, "speedup_vs_64x1": t_plain1 / t_batched,
+            "grad_batched_ms": t_grad_batched, "grad_plain_16_ms": t_grad_plain,
+            "grad_speedup": t_grad_plain / t_grad_batched}
 
 
 def leg_pt2():

@@ -136,8 +136,8 @@ mw_status mw_sigma(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_
  * plans, nroots, c, sigma are HOST arrays of length nprob (c[i], sigma[i]
  * device pointers; each plan at most once).  The launch sequence is captured
  * once into a HIP graph keyed by the argument tuple and replayed on later
- * calls with the same tuple; destroying or re-binding a plan drops its
- * graphs.  With the default launch parameters results equal nprob separate
+ * calls with the same tuple (at most 16 graphs are kept, the least recently
+ * used dropped first); destroying or re-binding a plan drops its graphs.  With the default launch parameters results equal nprob separate
  * mw_sigma calls with default parameters bit for bit; a tuned gather width
  * sums each determinant's partials in another fixed order. */
 mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots,
@@ -221,6 +221,25 @@ mw_status mw_energy_backward(mw_plan plan, int32_t nroots, const void *c, const 
  * Uses the plan's per-call scratch; asynchronous on stream. */
 mw_status mw_sigma_backward(mw_plan plan, int32_t nroots, const void *c, const void *gs, void *grad_c, void *grad_h,
                             void *grad_g, mw_stream_t stream);
+
+/* Batched energies and gradients (the differentiable batched path):
+ * nprob (1..32) plans, each at most once; plans, nroots and every pointer
+ * array are HOST arrays of length nprob whose entries are device pointers
+ * laid out as for mw_energy / mw_energy_backward.
+ * mw_energy_batched: e[i][k] = Re c_i,k^H sigma_i,k for every problem
+ * (after mw_sigma_batched), launched directly.
+ * mw_energy_backward_batched: mw_energy_backward for every problem (grad_c,
+ * grad_h, grad_g of L = sum_k ge[i][k] E_i,k; each entry may be NULL as for
+ * the single call).  The launch sequence of all problems is captured once
+ * into a HIP graph keyed by the argument tuple and replayed on later calls
+ * with the same tuple (at most 16 graphs are kept, the least recently used
+ * dropped first; destroying or re-binding a plan drops its graphs), so the
+ * many small kernels of the density-matrix passes cost one launch. */
+mw_status mw_energy_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots, const void *const *c,
+                            const void *const *sigma, double *const *e, mw_stream_t stream);
+mw_status mw_energy_backward_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots, const void *const *c,
+                                     const void *const *sigma, const double *const *ge, void *const *grad_c,
+                                     void *const *grad_h, void *const *grad_g, mw_stream_t stream);
 
 /* Lowest nroots eigenpairs by block Davidson-Liu over mw_sigma (section 2.4
  * uses sigma = H X products for the diagonalisation).  c0: device

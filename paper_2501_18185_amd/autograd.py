@@ -15,10 +15,15 @@ the transition density matrices between that gradient and c.
 ``h`` and ``g`` are CPU tensors laid out as in the problem (spin-free real
 n x n and n^4; spinor complex M x M and M^4).  When they differ from the
 integrals the plan holds, the plan is updated in place (no regrouping).
+``BatchedEnergy.apply(plans, ecores, *cs, *hs, *gs)`` does the same for
+several problems at once: the forward runs one batched sigma launch (a
+replayed HIP graph) and the batched energies, the backward one captured
+graph of every problem's gradient kernels.
+
 Only argument marshalling happens here: the energies, the scaling by the
 upstream gradient, the factor 1/2 and the conjugation of complex integral
 gradients all run in libmw (mw_energy, mw_energy_backward,
-mw_sigma_backward).
+mw_sigma_backward and their batched forms).
 """
 from __future__ import annotations
 
@@ -87,3 +92,35 @@ class Sigma(torch.autograd.Function):
         gc, gh, gg = ctx.plan.sigma_backward(c, gs.contiguous(), want_c, want_int)
         return (gc, _to(gh, ctx.h_meta) if ctx.needs_input_grad[1] else None,
                 _to(gg, ctx.g_meta) if ctx.needs_input_grad[2] else None, None, None)
+
+
+class BatchedEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plans, ecores, *tensors):
+        n = len(plans)
+        cs, hs, gs = tensors[:n], tensors[n:2 * n], tensors[2 * n:3 * n]
+        for pl, h, g, ec in zip(plans, hs, gs, ecores):
+            _sync_integrals(pl, h, g, ec)
+        cs = [c.contiguous() for c in cs]
+        sig = mw.sigma_batched(plans, cs)
+        es = mw.energy_batched(plans, cs, sig)
+        ctx.save_for_backward(*cs, *sig)
+        ctx.plans = plans
+        ctx.metas = [((h.dtype, h.device), (g.dtype, g.device)) for h, g in zip(hs, gs)]
+        return tuple(e.reshape(()) if c.dim() == 1 else e for e, c in zip(es, cs))
+
+    @staticmethod
+    def backward(ctx, *ges):
+        plans = ctx.plans
+        n = len(plans)
+        saved = ctx.saved_tensors
+        cs, sig = saved[:n], saved[n:]
+        want_c = any(ctx.needs_input_grad[2:2 + n])
+        want_int = any(ctx.needs_input_grad[2 + n:2 + 3 * n])
+        gc, gh, gg = mw.energy_backward_batched(plans, cs, sig, ges, want_c, want_int)
+        grads_c = [x if ctx.needs_input_grad[2 + i] else None for i, x in enumerate(gc)]
+        grads_h = [_to(x, m[0]) if ctx.needs_input_grad[2 + n + i] else None
+                   for i, (x, m) in enumerate(zip(gh, ctx.metas))]
+        grads_g = [_to(x, m[1]) if ctx.needs_input_grad[2 + 2 * n + i] else None
+                   for i, (x, m) in enumerate(zip(gg, ctx.metas))]
+        return (None, None, *grads_c, *grads_h, *grads_g)

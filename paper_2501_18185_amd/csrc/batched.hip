@@ -38,10 +38,17 @@ struct BatchEntry {
     int bpc = 0;  // persistent blocks per compute unit used when captured
     int u4 = 0;   // four-root partner unroll used when captured
     int gl = 0;   // gather lanes used when captured
+    uint64_t used = 0;  // last use, for the eviction of the least recent
 };
 
+// Graphs are keyed by the argument tuple (their kernels hold the device
+// pointers of c and sigma); at most BATCH_GRAPHS are kept, the least
+// recently used dropped first, so new output buffers on every call do not
+// accumulate graphs.
+constexpr size_t BATCH_GRAPHS = 16;
 std::mutex g_mu;
 std::map<BatchKey, BatchEntry> g_cache;
+uint64_t g_clock = 0;
 struct Tuned {
     int bpc, u4, gl;
 };
@@ -177,10 +184,13 @@ void drop(BatchEntry &e)
 
 }  // namespace
 
+void mw_internal_grad_forget(mw_plan plan);
+
 // Forget captured graphs that reference a plan (called when the plan is
 // destroyed or re-bound: the graphs hold its device addresses).
 void mw_internal_batched_forget(mw_plan plan)
 {
+    mw_internal_grad_forget(plan);
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto it = g_cache.begin(); it != g_cache.end();) {
         bool hit = false;
@@ -225,8 +235,16 @@ extern "C" mw_status mw_sigma_batched(int32_t nprob, const mw_plan *plans, const
         BatchEntry e;
         st = capture(a, cplx, bpc, e);
         if (st != MW_OK) return st;
+        if (g_cache.size() >= BATCH_GRAPHS) {
+            auto lru = g_cache.begin();
+            for (auto jt = g_cache.begin(); jt != g_cache.end(); ++jt)
+                if (jt->second.used < lru->second.used) lru = jt;
+            drop(lru->second);
+            g_cache.erase(lru);
+        }
         it = g_cache.emplace(key, e).first;
     }
+    it->second.used = ++g_clock;
     if (hipGraphLaunch(it->second.exec, (hipStream_t)stream) != hipSuccess) return fail(MW_EHIP, "hipGraphLaunch failed");
     return MW_OK;
 }

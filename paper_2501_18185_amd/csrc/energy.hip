@@ -18,6 +18,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "dev_common.h"
 #include "mw_internal.h"
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(256) void k_scale_roots(int64_t n, int R, double fa
     }
 }
 
-static mw_status launch_energy(const DevPlan &p, int R, const void *c, const void *sigma, double *e, hipStream_t s)
+mw_status launch_energy(const DevPlan &p, int R, const void *c, const void *sigma, double *e, hipStream_t s)
 {
     // block partials go to the plan's per-call scratch
     const int64_t cap = (int64_t)(p.scratch_bytes / (8 * (size_t)R));
@@ -102,6 +105,25 @@ static mw_status launch_energy(const DevPlan &p, int R, const void *c, const voi
                            (const double *)c, (const double *)sigma, part);
     hipLaunchKernelGGL(k_energy_final, dim3((unsigned)R), dim3(256), 0, s, (int)nblk, R, (const double *)part, e);
     if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "energy kernel launch failed");
+    return MW_OK;
+}
+
+// the gradients of L = sum_k ge_k E_k (arguments checked by the caller)
+mw_status launch_energy_backward(const DevPlan &p, int R, const void *c, const void *sigma, const double *ge,
+                                 void *grad_c, void *grad_h, void *grad_g, hipStream_t s)
+{
+    if (grad_c) {
+        const int64_t n = p.ndet * R;
+        const unsigned grid = (unsigned)((n + 255) / 256);
+        if (p.kind == MW_SPINOR)
+            hipLaunchKernelGGL(k_scale_roots<double2>, dim3(grid), dim3(256), 0, s, p.ndet, R, 2.0, ge,
+                               (const double2 *)sigma, (double2 *)grad_c);
+        else
+            hipLaunchKernelGGL(k_scale_roots<double>, dim3(grid), dim3(256), 0, s, p.ndet, R, 2.0, ge,
+                               (const double *)sigma, (double *)grad_c);
+        if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "gradient kernel launch failed");
+    }
+    if (grad_h) return launch_rdm(p, R, c, c, nullptr, ge, grad_h, grad_g, 0.5, true, s);
     return MW_OK;
 }
 
@@ -142,20 +164,7 @@ mw_status mw_energy_backward(mw_plan plan, int32_t nroots, const void *c, const 
     if (!c || !ge) return fail(MW_EINVAL, "c and ge must be device pointers");
     if ((grad_h == nullptr) != (grad_g == nullptr)) return fail(MW_EINVAL, "grad_h and grad_g go together");
     if (grad_c && !sigma) return fail(MW_EINVAL, "grad_c needs sigma");
-    hipStream_t s = (hipStream_t)stream;
-    if (grad_c) {
-        const int64_t n = d->ndet * nroots;
-        const unsigned grid = (unsigned)((n + 255) / 256);
-        if (d->kind == MW_SPINOR)
-            hipLaunchKernelGGL(k_scale_roots<double2>, dim3(grid), dim3(256), 0, s, d->ndet, nroots, 2.0, ge,
-                               (const double2 *)sigma, (double2 *)grad_c);
-        else
-            hipLaunchKernelGGL(k_scale_roots<double>, dim3(grid), dim3(256), 0, s, d->ndet, nroots, 2.0, ge,
-                               (const double *)sigma, (double *)grad_c);
-        if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "gradient kernel launch failed");
-    }
-    if (grad_h) return launch_rdm(*d, nroots, c, c, nullptr, ge, grad_h, grad_g, 0.5, true, s);
-    return MW_OK;
+    return launch_energy_backward(*d, nroots, c, sigma, ge, grad_c, grad_h, grad_g, (hipStream_t)stream);
 }
 
 mw_status mw_sigma_backward(mw_plan plan, int32_t nroots, const void *c, const void *gs, void *grad_c, void *grad_h,
@@ -173,6 +182,146 @@ mw_status mw_sigma_backward(mw_plan plan, int32_t nroots, const void *c, const v
         if (st != MW_OK) return st;
     }
     if (grad_h) return launch_rdm(*d, nroots, gs, c, nullptr, nullptr, grad_h, grad_g, 0.5, true, s);
+    return MW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of problems
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Captured gradient graphs, keyed by every argument of the call (the kernels
+// hold the device pointers); at most GRAD_GRAPHS are kept, the least
+// recently used dropped first.
+constexpr size_t GRAD_GRAPHS = 16;
+struct GradGraph {
+    std::vector<uintptr_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+std::mutex g_grad_mu;
+std::vector<GradGraph> g_grad;
+uint64_t g_grad_clock = 0;
+hipStream_t g_grad_stream = nullptr;
+
+void drop_graph(GradGraph &e)
+{
+    if (e.exec) hipGraphExecDestroy(e.exec);
+    if (e.graph) hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+}
+
+mw_status batch_plans(int32_t nprob, const mw_plan *plans, const int32_t *nroots, std::vector<const DevPlan *> &d)
+{
+    if (nprob < 1 || nprob > MW_MAXB) return fail(MW_EUNSUPPORTED, "nprob must be in 1..32");
+    if (!plans || !nroots) return fail(MW_EINVAL, "NULL argument");
+    d.resize(nprob);
+    for (int i = 0; i < nprob; i++) {
+        d[i] = mw_internal_devplan(plans[i]);
+        if (!d[i]) return fail(MW_EWORKSPACE, "plan " + std::to_string(i) + " has no workspace");
+        if (nroots[i] < 1 || nroots[i] > d[i]->max_roots || nroots[i] > 64)
+            return fail(MW_EINVAL, "nroots out of range for plan " + std::to_string(i));
+        for (int j = 0; j < i; j++)
+            if (plans[j] == plans[i]) return fail(MW_EINVAL, "a plan may appear once per batch");
+    }
+    return MW_OK;
+}
+
+}  // namespace
+
+// drop the captured gradient graphs that reference a plan (destroyed or
+// re-bound)
+void mw_internal_grad_forget(mw_plan plan)
+{
+    std::lock_guard<std::mutex> lk(g_grad_mu);
+    for (auto it = g_grad.begin(); it != g_grad.end();) {
+        if (!it->key.empty() && std::find(it->key.begin(), it->key.end(), (uintptr_t)plan) != it->key.end()) {
+            drop_graph(*it);
+            it = g_grad.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+extern "C" {
+
+mw_status mw_energy_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots, const void *const *c,
+                            const void *const *sigma, double *const *e, mw_stream_t stream)
+{
+    std::vector<const DevPlan *> d;
+    mw_status st = batch_plans(nprob, plans, nroots, d);
+    if (st != MW_OK) return st;
+    if (!c || !sigma || !e) return fail(MW_EINVAL, "NULL argument");
+    for (int i = 0; i < nprob; i++) {
+        if (!c[i] || !sigma[i] || !e[i]) return fail(MW_EINVAL, "NULL device pointer");
+        if (d[i]->ndet == 0) return fail(MW_EINVAL, "empty space");
+    }
+    for (int i = 0; i < nprob; i++)
+        if ((st = launch_energy(*d[i], nroots[i], c[i], sigma[i], e[i], (hipStream_t)stream)) != MW_OK) return st;
+    return MW_OK;
+}
+
+mw_status mw_energy_backward_batched(int32_t nprob, const mw_plan *plans, const int32_t *nroots, const void *const *c,
+                                     const void *const *sigma, const double *const *ge, void *const *grad_c,
+                                     void *const *grad_h, void *const *grad_g, mw_stream_t stream)
+{
+    std::vector<const DevPlan *> d;
+    mw_status st = batch_plans(nprob, plans, nroots, d);
+    if (st != MW_OK) return st;
+    if (!c || !sigma || !ge || !grad_c || !grad_h || !grad_g) return fail(MW_EINVAL, "NULL argument array");
+    std::vector<uintptr_t> key;
+    for (int i = 0; i < nprob; i++) {
+        if (!c[i] || !ge[i]) return fail(MW_EINVAL, "c and ge must be device pointers");
+        if ((grad_h[i] == nullptr) != (grad_g[i] == nullptr)) return fail(MW_EINVAL, "grad_h and grad_g go together");
+        if (grad_c[i] && !sigma[i]) return fail(MW_EINVAL, "grad_c needs sigma");
+        for (uintptr_t v : {(uintptr_t)plans[i], (uintptr_t)nroots[i], (uintptr_t)c[i], (uintptr_t)sigma[i],
+                            (uintptr_t)ge[i], (uintptr_t)grad_c[i], (uintptr_t)grad_h[i], (uintptr_t)grad_g[i]})
+            key.push_back(v);
+    }
+    std::lock_guard<std::mutex> lk(g_grad_mu);
+    GradGraph *hit = nullptr;
+    for (auto &e : g_grad)
+        if (e.key == key) hit = &e;
+    if (!hit) {
+        if (!g_grad_stream && hipStreamCreateWithFlags(&g_grad_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(MW_EHIP, "hipStreamCreateWithFlags failed");
+        if (hipStreamBeginCapture(g_grad_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(MW_EHIP, "hipStreamBeginCapture failed");
+        {
+            ProfSuppress quiet;
+            for (int i = 0; i < nprob && st == MW_OK; i++)
+                st = launch_energy_backward(*d[i], nroots[i], c[i], sigma[i], ge[i], grad_c[i], grad_h[i], grad_g[i],
+                                            g_grad_stream);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(g_grad_stream, &g);
+        if (st != MW_OK) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (ce != hipSuccess || !g) return fail(MW_EHIP, "hipStreamEndCapture failed");
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return fail(MW_EHIP, "hipGraphInstantiate failed");
+        }
+        if (g_grad.size() >= GRAD_GRAPHS) {
+            auto lru = std::min_element(g_grad.begin(), g_grad.end(),
+                                        [](const GradGraph &x, const GradGraph &y) { return x.used < y.used; });
+            drop_graph(*lru);
+            g_grad.erase(lru);
+        }
+        g_grad.push_back(GradGraph{key, g, ex, 0});
+        hit = &g_grad.back();
+    }
+    hit->used = ++g_grad_clock;
+    if (hipGraphLaunch(hit->exec, (hipStream_t)stream) != hipSuccess) return fail(MW_EHIP, "hipGraphLaunch failed");
     return MW_OK;
 }
 

@@ -119,6 +119,15 @@ struct ProfToken {
 bool prof_enabled();
 ProfToken prof_begin(const char *name, hipStream_t s);
 void prof_end(const ProfToken &t, hipStream_t s);
+// while alive on a thread, its launches record no timing events (graph capture)
+struct ProfSuppress {
+    ProfSuppress();
+    ~ProfSuppress();
+};
+// energies (energy.hip); the batched gradients replay them from a graph
+mw_status launch_energy(const DevPlan &p, int R, const void *c, const void *sigma, double *e, hipStream_t s);
+mw_status launch_energy_backward(const DevPlan &p, int R, const void *c, const void *sigma, const double *ge,
+                                 void *grad_c, void *grad_h, void *grad_g, hipStream_t s);
 
 // kernel launchers (kernels.hip)
 mw_status launch_diag(const DevPlan &p, hipStream_t s);

@@ -16,12 +16,18 @@ static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static std::map<std::string, std::vector<ProfRec>> g_prof;
 
-bool prof_enabled() { return g_prof_on; }
+// launches recorded into a HIP graph must not record events
+static thread_local int g_prof_suppress = 0;
+
+ProfSuppress::ProfSuppress() { g_prof_suppress++; }
+ProfSuppress::~ProfSuppress() { g_prof_suppress--; }
+
+bool prof_enabled() { return g_prof_on && !g_prof_suppress; }
 
 ProfToken prof_begin(const char *name, hipStream_t s)
 {
     ProfToken t{nullptr, nullptr, name};
-    if (!g_prof_on) return t;
+    if (!g_prof_on || g_prof_suppress) return t;
     if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return ProfToken{nullptr, nullptr, name};
     hipEventRecord(t.a, s);
     return t;

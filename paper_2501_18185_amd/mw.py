@@ -63,6 +63,9 @@ def lib():
         L.mw_energy.argtypes = [vp, i32, vp, vp, vp, vp]
         L.mw_energy_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.mw_sigma_backward.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        pv = C.POINTER(vp)
+        L.mw_energy_batched.argtypes = [i32, pv, C.POINTER(i32), pv, pv, pv, vp]
+        L.mw_energy_backward_batched.argtypes = [i32, pv, C.POINTER(i32), pv, pv, pv, pv, pv, pv, vp]
         L.mw_davidson_work_bytes.argtypes = [vp, i32, C.POINTER(sz)]
         L.mw_davidson.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), C.c_double, i32,
                                   C.POINTER(i32), vp, sz, vp]
@@ -109,7 +112,7 @@ def lib():
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
                      "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched",
                      "mw_pt2_work_bytes", "mw_pt2", "mw_select", "mw_energy", "mw_energy_backward",
-                     "mw_sigma_backward"):
+                     "mw_sigma_backward", "mw_energy_batched", "mw_energy_backward_batched"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -603,3 +606,44 @@ def autotune_batched(plans: Sequence[Plan], cs, outs=None):
     b = C.c_int32()
     _check(lib().mw_autotune_batched(n, P, R, Cp, Sp, _stream(), C.byref(b)))
     return b.value
+
+
+def _ptrs(xs):
+    return (C.c_void_p * len(xs))(*[None if x is None else x.data_ptr() for x in xs])
+
+
+def energy_batched(plans: Sequence[Plan], cs, sigmas):
+    """Per-problem energies Re c_k^H sigma_k (device float64 [nroots] each)."""
+    torch = _require_gpu()
+    cs = [p._vec(c) for p, c in zip(plans, cs)]
+    sigmas = [p._vec(x) for p, x in zip(plans, sigmas)]
+    R = [1 if c.dim() == 1 else c.shape[1] for c in cs]
+    es = [torch.empty(r, dtype=torch.float64, device=c.device) for r, c in zip(R, cs)]
+    n = len(plans)
+    _check(lib().mw_energy_batched(n, (C.c_void_p * n)(*[p._plan.value for p in plans]), (C.c_int32 * n)(*R),
+                                   _ptrs(cs), _ptrs(sigmas), _ptrs(es), _stream()))
+    return es
+
+
+def energy_backward_batched(plans: Sequence[Plan], cs, sigmas, ges, want_c=True, want_integrals=True, outs=None):
+    """Gradients of L = sum_i sum_k ge_i[k] E_i,k for every problem, from one
+    captured graph keyed by the buffers: lists (grad_c, grad_h, grad_g), with
+    None where not wanted.  ``outs`` (the three lists) reuses buffers, so
+    repeated calls replay the same graph."""
+    torch = _require_gpu()
+    cs = [p._vec(c) for p, c in zip(plans, cs)]
+    sigmas = [p._vec(x) for p, x in zip(plans, sigmas)]
+    ges = [g.to(device=c.device, dtype=torch.float64).reshape(-1).contiguous() for g, c in zip(ges, cs)]
+    R = [1 if c.dim() == 1 else c.shape[1] for c in cs]
+    if outs is None:
+        gc = [torch.empty_like(c) if want_c else None for c in cs]
+        ints = [p._int_grads(c.device) if want_integrals else (None, None) for p, c in zip(plans, cs)]
+        gh = [x[0] for x in ints]
+        gg = [x[1] for x in ints]
+    else:
+        gc, gh, gg = outs
+    n = len(plans)
+    _check(lib().mw_energy_backward_batched(n, (C.c_void_p * n)(*[p._plan.value for p in plans]),
+                                            (C.c_int32 * n)(*R), _ptrs(cs), _ptrs(sigmas), _ptrs(ges), _ptrs(gc),
+                                            _ptrs(gh), _ptrs(gg), _stream()))
+    return gc, gh, gg
