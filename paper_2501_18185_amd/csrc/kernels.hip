@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "mw_internal.h"
@@ -496,17 +497,24 @@ __device__ __forceinline__ void gather_body(const DevPlan &p, int64_t gt, int R,
     if (active) {
         I = t / R;
         k = (int)(t - I * R);
-        const uint32_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
-        // four slots in flight per lane; the additions keep the slot order
-        uint32_t s = s0 + sub;
-        for (; s < s1 && s1 - s > 3u * GL; s += 4 * GL) {
-            const uint32_t i0 = p.slot_mem[s], i1 = p.slot_mem[s + GL], i2 = p.slot_mem[s + 2 * GL],
-                           i3 = p.slot_mem[s + 3 * GL];
-            const T v0 = partial[(size_t)i0 * R + k], v1 = partial[(size_t)i1 * R + k],
-                    v2 = partial[(size_t)i2 * R + k], v3 = partial[(size_t)i3 * R + k];
-            acc = sc_add(sc_add(sc_add(sc_add(acc, v0), v1), v2), v3);
+        const uint64_t s0 = p.rowptr[I], s1 = p.rowptr[I + 1];
+        // eight slots in flight per lane: all eight positions are loaded,
+        // then all eight partials, so a determinant of up to 8 GL slots
+        // costs two dependent memory round trips after its row pointer; the
+        // additions keep the slot order (a slot past the end adds nothing)
+        constexpr int W = 8;
+        for (uint64_t s = s0 + sub; s < s1; s += W * GL) {
+            uint32_t ix[W];
+            T v[W];
+#pragma unroll
+            for (int j = 0; j < W; j++) ix[j] = s + (uint64_t)j * GL < s1 ? p.slot_mem[s + (uint64_t)j * GL] : 0u;
+#pragma unroll
+            for (int j = 0; j < W; j++)
+                v[j] = s + (uint64_t)j * GL < s1 ? partial[(size_t)ix[j] * R + k] : sc_zero(T());
+#pragma unroll
+            for (int j = 0; j < W; j++)
+                if (s + (uint64_t)j * GL < s1) acc = sc_add(acc, v[j]);
         }
-        for (; s < s1; s += GL) acc = sc_add(acc, partial[(size_t)p.slot_mem[s] * R + k]);
     }
 #pragma unroll
     for (int off = GL / 2; off > 0; off >>= 1) {
@@ -538,8 +546,8 @@ static void launch_double(const DevPlan &p, int R, int r0, const typename Scal<C
 }
 
 template <bool CPLX, int RC>
-static void launch_groups(const DevPlan &p, int R, int r0, const typename Scal<CPLX>::T *c,
-                          typename Scal<CPLX>::T *part, hipStream_t s)
+static void launch_double_groups(const DevPlan &p, int R, int r0, const typename Scal<CPLX>::T *c,
+                                 typename Scal<CPLX>::T *part, hipStream_t s)
 {
     if (p.npacket_double > 0) {
         ProfToken t = prof_begin("group_sigma", s);
@@ -549,6 +557,12 @@ static void launch_groups(const DevPlan &p, int R, int r0, const typename Scal<C
         else launch_double<CPLX, RC, 16>(p, R, r0, c, part, s);
         prof_end(t, s);
     }
+}
+
+template <bool CPLX, int RC>
+static void launch_single_groups(const DevPlan &p, int R, int r0, const typename Scal<CPLX>::T *c,
+                                 typename Scal<CPLX>::T *part, hipStream_t s)
+{
     const int64_t ns = p.npacket - p.npacket_double;
     if (ns > 0) {
         ProfToken t = prof_begin("group_single", s);
@@ -557,6 +571,57 @@ static void launch_groups(const DevPlan &p, int R, int r0, const typename Scal<C
         prof_end(t, s);
     }
 }
+
+template <bool CPLX, bool DBL>
+static void launch_chunks(const DevPlan &p, int R, const typename Scal<CPLX>::T *c, typename Scal<CPLX>::T *part,
+                          hipStream_t s)
+{
+    for (int r0 = 0; r0 < R; r0 += 4) {
+        const int left = R - r0;
+        if constexpr (DBL) {
+            if (left == 1) launch_double_groups<CPLX, 1>(p, R, r0, c, part, s);
+            else if (left == 2) launch_double_groups<CPLX, 2>(p, R, r0, c, part, s);
+            else launch_double_groups<CPLX, 4>(p, R, r0, c, part, s);
+        } else {
+            if (left == 1) launch_single_groups<CPLX, 1>(p, R, r0, c, part, s);
+            else if (left == 2) launch_single_groups<CPLX, 2>(p, R, r0, c, part, s);
+            else launch_single_groups<CPLX, 4>(p, R, r0, c, part, s);
+        }
+    }
+}
+
+// A second stream per device for the single-group kernels: they write
+// other partial sums than the double-group kernel, so the two run side by
+// side (the singles fill the compute units the memory-bound double kernel
+// leaves idle, and its tail) and are joined before the gather.  The fork
+// and join are enqueued under one lock (the events are shared); a caller
+// stream that is being captured into a graph gets the serial order instead,
+// so the side stream never becomes part of a capture.
+namespace {
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool failed = false;
+};
+std::mutex g_side_mu;
+SideStream g_side[64];
+
+SideStream *side_stream_locked()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    SideStream &x = g_side[dev];
+    if (!x.s && !x.failed) {
+        if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
+            x.failed = true;
+            x.s = nullptr;
+        }
+    }
+    return x.s ? &x : nullptr;
+}
+}  // namespace
 
 template <bool CPLX, int GL>
 static void launch_gather(const DevPlan &p, int R, const typename Scal<CPLX>::T *c,
@@ -579,11 +644,23 @@ static mw_status sigma_t(const DevPlan &p, int R, const void *c, void *sigma, hi
     using T = typename Scal<CPLX>::T;
     const T *cc = (const T *)c;
     T *part = (T *)p.partial;
-    for (int r0 = 0; r0 < R; r0 += 4) {
-        int left = R - r0;
-        if (left == 1) launch_groups<CPLX, 1>(p, R, r0, cc, part, s);
-        else if (left == 2) launch_groups<CPLX, 2>(p, R, r0, cc, part, s);
-        else launch_groups<CPLX, 4>(p, R, r0, cc, part, s);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool both = p.npacket_double > 0 && p.npacket > p.npacket_double;
+    if (both && hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        SideStream *x = side_stream_locked();
+        if (x && hipEventRecord(x->fork, s) == hipSuccess && hipStreamWaitEvent(x->s, x->fork, 0) == hipSuccess) {
+            launch_chunks<CPLX, false>(p, R, cc, part, x->s);
+            launch_chunks<CPLX, true>(p, R, cc, part, s);
+            if (hipEventRecord(x->join, x->s) != hipSuccess || hipStreamWaitEvent(s, x->join, 0) != hipSuccess)
+                return fail(MW_EHIP, "joining the single-group stream failed");
+        } else {
+            launch_chunks<CPLX, true>(p, R, cc, part, s);
+            launch_chunks<CPLX, false>(p, R, cc, part, s);
+        }
+    } else {
+        launch_chunks<CPLX, true>(p, R, cc, part, s);
+        launch_chunks<CPLX, false>(p, R, cc, part, s);
     }
     ProfToken t = prof_begin("gather", s);
     if (p.tune_gl <= 8) launch_gather<CPLX, 8>(p, R, cc, part, (T *)sigma, s);
