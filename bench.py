@@ -56,23 +56,26 @@ HBM_PEAK_GBS = 8000.0
 
 
 def measured_traffic(workload, R):
-    """HBM bytes per launch of the group kernel from the committed rocprofv3
-    counters (profiles/traffic.json), or None when the kernel sources changed
-    since they were taken or the workload differs."""
+    """HBM bytes per launch of each sigma kernel from the committed rocprofv3
+    counters (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by what the same counters read for a plain copy and fill of known
+    size), or {} when the kernel sources changed since they were taken or
+    the workload differs."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
-            t = json.load(f)["k_group_double"]
+            t = json.load(f)
         h = hashlib.sha256()
         for src in t["sources"]:
             with open(os.path.join(ROOT, src), "rb") as f:
                 h.update(f.read())
-        if h.hexdigest()[:16] != t["source_sha256_16"] or workload != "sci-n64" or R != 1:
-            return None
-        return t["fetch_kib_per_dispatch"] * 1024 * t["fetch_factor"] + \
-            t["write_kib_per_dispatch"] * 1024 * t["write_factor"]
+        if h.hexdigest()[:16] != t["source_sha256_16"]:
+            return {}
+        e = t["workloads"].get(f"{workload}/R{R}", {})
+        return {k: v["fetch_kib_per_dispatch"] * 1024 * t["fetch_factor"] +
+                v["write_kib_per_dispatch"] * 1024 * t["write_factor"] for k, v in e.items()}
     except (OSError, KeyError, ValueError):
-        return None
+        return {}
 
 
 def log(*a):
@@ -163,9 +166,16 @@ def main():
     sb = 16 if prob.is_complex else 8
     terms = (pairs + ndet) * R
     value = terms / (ms_step * 1e-3)
-    kern = kernel_rooflines(plan, R, sb, args.steps, n_grp, ms_grp, n_gat, ms_gat)
+    kern = kernel_rooflines(plan, R, sb, args.steps, n_grp, ms_grp, n_gat, ms_gat,
+                            traffic=measured_traffic(args.workload, R))
     step_bytes = pairs * (sb * R + sb) + ndet * (16 + 2 * sb * R)
     dbl = kern["k_group_double"]
+    # the per-term model (every ordered pair reads its partner's R
+    # coefficients and one integral word) unless the Hermitian half-work
+    # beats it (a fraction above 1), then the evaluated-pair model
+    ordered = dbl["frac"] <= 1.0
+    roof_bytes = dbl["bytes_per_launch"] if ordered else dbl["bytes_per_launch_evaluated_pairs"]
+    roof_ach = roof_bytes / (dbl["avg_ms"] * 1e-3) / 1e9 if dbl["avg_ms"] > 0 else 0.0
 
     out = {
         "metric": "nonzero H_IJ*c_J terms/sec (sigma = H c, FP64)",
@@ -198,13 +208,16 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": "k_group_double",
-            "achieved": dbl["achieved_GBps"],
+            "achieved": roof_ach,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": dbl["frac"],
-            "traffic": measured_traffic(args.workload, R),
-            "bytes_per_launch": dbl["bytes_per_launch"],
-            "unit_count": "double-excitation pairs (ordered) x (8 R + 8) B",
+            "frac": roof_ach / HBM_PEAK_GBS,
+            "traffic": dbl.get("traffic"),
+            "bytes_per_launch": roof_bytes,
+            "unit_count": ("double-excitation pairs (ordered) x (sb R + sb) B" if ordered else
+                           "double-excitation pairs evaluated (large groups once per unordered pair) "
+                           "x (sb R + sb) B") + f", sb = {sb}",
+            "frac_ordered_pairs": dbl["frac"],
             "frac_evaluated_pairs": dbl["frac_evaluated_pairs"],
             "kernels": kern,
         },
@@ -263,7 +276,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def kernel_rooflines(plan, R, sb, steps, n_grp, ms_grp, n_gat, ms_gat, n_sgl=None, ms_sgl=None):
+def kernel_rooflines(plan, R, sb, steps, n_grp, ms_grp, n_gat, ms_gat, n_sgl=None, ms_sgl=None, traffic=None):
     """Algorithmic bandwidth of the three sigma kernels from the plan's
     counts and the event times recorded by the library (launch stream).
 
@@ -303,6 +316,10 @@ def kernel_rooflines(plan, R, sb, steps, n_grp, ms_grp, n_gat, ms_gat, n_sgl=Non
         "frac_evaluated_pairs": (b_eval / t_d / 1e9 / HBM_PEAK_GBS) if n_grp else 0.0})
     res["k_group_single"] = entry(sp * per / max(n_sgl // steps, 1), n_sgl, ms_sgl)
     res["k_gather"] = entry(nslot * (4 + sb * R) + ndet * (4 + sb + 2 * sb * R), n_gat, ms_gat)
+    for k, v in (traffic or {}).items():
+        if k in res:
+            res[k]["traffic"] = v
+            res[k]["traffic_over_algorithmic"] = v / res[k]["bytes_per_launch"]
     return res
 
 
@@ -407,6 +424,16 @@ def leg_batched():
                               for x, o in zip(row, orow)], 5)
     pairs = sum(pl.info("pairs") for pl in plans)
     terms = (pairs + sum(p.ndet for p in probs)) * R
+    # byte models of the three batched kernels (per launch, all problems):
+    # per ordered pair R coefficients and one integral word; the gather as
+    # for plain sigma
+    dp = sum(pl.info("double_pairs") for pl in plans)
+    sp = sum(pl.info("single_pairs") for pl in plans)
+    nslot = sum(pl.info("memberships") + pl.info("column_partials") for pl in plans)
+    ndet = sum(p.ndet for p in probs)
+    kernel_bytes = {"k_batched_flat (double groups)": dp * (8 * R + 8),
+                    "k_batched_flat (single groups)": sp * (8 * R + 8),
+                    "k_batched_gather": nslot * (4 + 8 * R) + ndet * (4 + 8 + 16 * R)}
     log(f"[bench] batched: graph {t_batched:.2f} ms, 16x4-root {t_plain4:.2f} ms, 64x1-root {t_plain1:.2f} ms")
     # energies and every gradient (c, h, g) of sum_i sum_k E_ik: batched
     # sigma + batched energies + one captured graph of the gradient kernels,
@@ -429,7 +456,8 @@ def leg_batched():
     t_grad_plain = _time(plain_grad, 5)
     log(f"[bench] batched energy+gradients: graph {t_grad_batched:.2f} ms, 16 plain {t_grad_plain:.2f} ms")
     return {"workload": "batch16-n16..48-6..12e-1e4..5e5-R4", "ndet_total": sum(p.ndet for p in probs),
-            "pairs_total": pairs, "blocks_per_cu": bpc,
+            "pairs_total": pairs, "double_pairs_total": dp, "single_pairs_total": sp, "slots_total": nslot,
+            "kernel_bytes_per_launch": kernel_bytes, "blocks_per_cu": bpc,
             "batched_graph_ms": t_batched, "plain_16x4_ms": t_plain4,
             "plain_16x4_default_ms": t_plain4_default, "plain_16x4_tuned_ms": t_plain4_tuned,
             "plain_64x1_ms": t_plain1,
@@ -509,7 +537,7 @@ def leg_spinor(steps):
     na, ma = mw.profile_read("gather")
     ns, msg = mw.profile_read("group_single")
     # the warm-up calls of _time are recorded too: kernel averages are per launch
-    kern = kernel_rooflines(pl, 1, 16, n + 2, ng, mg, na, ma, ns, msg)
+    kern = kernel_rooflines(pl, 1, 16, n + 2, ng, mg, na, ma, ns, msg, traffic=measured_traffic("spinor-40kp", 1))
     pairs = pl.info("pairs")
     d = kern["k_group_double"]
     log(f"[bench] spinor: {ms:.2f} ms per sigma")

@@ -118,7 +118,10 @@ mw_status mw_plan_destroy(mw_plan plan);
  * 8 scalar size in bytes (8 or 16), 9 norb, 10 kind, 11 packets (waves of
  * the group launches), 12 packets of double groups, 13 column partial sums
  * of the large double groups, 14 ordered double-excitation pairs inside
- * groups of 64 members or more (evaluated once per unordered pair).
+ * groups of 64 members or more (evaluated once per unordered pair), 15
+ * double memberships listed under the density-matrix rows of their added
+ * pairs, 16 chunks of those lists (workgroups of the double-pair density
+ * kernel).
  * Returns -1 for an unknown plan or index. */
 int64_t mw_plan_info(mw_plan plan, int32_t what);
 

@@ -67,6 +67,19 @@ struct DevPlan {
     const double *g_bound;     // spinor: Table 1 bound table [n]^4 over Kramers pairs; spin-free: null
     uint64_t ref0, ref1;       // reference string omega
     int64_t npacket_double;    // packets [0, npacket_double) hold double groups
+    int64_t nmem_double;       // memberships [0, nmem_double) belong to double groups
+    // density-matrix rows: each double membership j (as the partner of a
+    // pair) listed under the accumulator row of its added pair, {j0, (j -
+    // j0) | L << 16} with [j0, j0 + L) its group; chunks {row, flags (1:
+    // alpha-beta row), first entry, end} in five classes [rdm_cls[c],
+    // rdm_cls[c + 1]): alpha-beta rows of wide groups, of small groups, pair
+    // rows of wide and of small groups, then the rows of the single
+    // memberships (by the added orbital or spinor); rdm_pos[j] = X | Y << 8,
+    // the positions added in membership j (Y = 255 for single groups)
+    const uint2 *rdm_ent;
+    const uint4 *rdm_chunk;
+    const uint16_t *rdm_pos;
+    int64_t rdm_cls[6];
     void *partial;             // [nmem][R] per-membership partial sums, member order (also RDM accumulators)
     size_t scratch_bytes;
     DevPlan *self;             // device copy of this struct (for batched launches)
@@ -82,6 +95,11 @@ constexpr int MW_MAXB = 32;
 // copies of the single-excitation density accumulators (S, C, E) that the
 // single-pair kernel spreads its atomics over
 constexpr int RDM_COPIES = 32;
+// density-matrix rows: groups of RDM_WIDE members or more are walked by a
+// wave (a member per lane), smaller ones by one lane each; a chunk holds
+// about RDM_CHUNK_WORK partner visits of one row
+constexpr int RDM_WIDE = 32;
+constexpr int64_t RDM_CHUNK_WORK = 1 << 17;
 struct BatchArgs {
     int nprob;
     const DevPlan *plans[MW_MAXB];   // device copies

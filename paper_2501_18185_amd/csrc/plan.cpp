@@ -147,7 +147,12 @@ struct HostPlan {
     // spinor plans: Table 1's |(ab|cd)| over Kramers pairs (see bound_table)
     std::vector<double> g_bound;
     uint64_t ref0 = 0, ref1 = 0;
-    int64_t npacket_double = 0;
+    int64_t npacket_double = 0, nmem_double = 0;
+    // density-matrix rows (see build_rdm_rows)
+    std::vector<uint2> rdm_ent;
+    std::vector<uint4> rdm_chunk;
+    std::vector<uint16_t> rdm_pos;
+    int64_t rdm_cls[6] = {0, 0, 0, 0, 0, 0};
     // launch defaults until mw_autotune picks its own: partner-loop unroll 4,
     // 16 gather lanes (32 for complex), the fastest measured on the n = 64
     // spin-free and 40-pair spinor spaces for one, two and four roots
@@ -677,6 +682,118 @@ static inline int pair_index(int lo, int hi) { return hi * (hi - 1) / 2 + lo; }
 // lexicographic index of the pair lo < hi among m positions
 static inline int pair_lex(int lo, int hi, int m) { return lo * (2 * m - lo - 1) / 2 + (hi - lo - 1); }
 
+// ---------------------------------------------------------------------------
+// density-matrix rows
+// ---------------------------------------------------------------------------
+
+// The double-pair accumulators of the density matrices are filled row by
+// row.  The row of a connected pair (I, J) is the pair added in J: alpha-beta
+// (X, Y) -> X n + Y - n, same-spin and spinor pairs -> their colex index
+// (after the n^2 alpha-beta rows of a spin-free plan).  Every double
+// membership j is listed under its row, as the partner of the pairs it forms
+// with the other members of its group; one workgroup sums a run of a row's
+// list in LDS and adds the row to the accumulator once, instead of one
+// device atomic per pair.  A row's list holds first the memberships of
+// groups of RDM_WIDE members or more (a wave walks the group, a member per
+// lane), then the others by increasing group size (a lane per membership,
+// so that the lanes of a wave loop alike), each in membership order; the
+// lists are cut into chunks of about RDM_CHUNK_WORK partner visits, the
+// alpha-beta chunks first, each class by decreasing work.  The single
+// memberships are listed the same way under the row of their added orbital
+// (spin-free, both spins) or spinor, whose accumulators (S, C, E) are
+// indexed by the partner's position first.
+static mw_status build_rdm_rows(HostPlan &P)
+{
+    P.rdm_ent.clear();
+    P.rdm_chunk.clear();
+    P.rdm_pos.clear();
+    for (auto &c : P.rdm_cls) c = 0;
+    const int64_t nmd = P.npacket_double > 0 ? (int64_t)P.pk_off[P.npacket_double] : 0;
+    const int64_t nmem = (int64_t)P.mem.size();
+    P.nmem_double = nmd;
+    if (nmem == 0) return MW_OK;
+    const int n = P.n;
+    const bool sf = P.kind == MW_SPIN_FREE;
+    // pairs of same-spin orbitals (spin-free) or of spinors (set again by repack)
+    const int64_t npair = sf ? (int64_t)n * (n - 1) / 2 : (int64_t)P.M * (P.M - 1) / 2;
+    const int64_t nab = sf ? (int64_t)n * n : 0, nrow_d = nab + npair;
+    // single rows: the partner's added orbital (spin-free, both spins) or spinor
+    const int64_t nrow = nrow_d + (sf ? n : P.M);
+    constexpr int NC = RDM_WIDE;  // class 0: wide groups; class L: groups of L < RDM_WIDE members
+    std::vector<uint32_t> key((size_t)nmem);
+    parallel_for(nmem, [&](int64_t b0, int64_t b1, unsigned) {
+        for (int64_t j = b0; j < b1; j++) {
+            const uint32_t g = P.mem_grp[j];
+            const uint32_t L = P.grp_off[g + 1] - P.grp_off[g];
+            if (L < 2) { key[j] = 0xffffffffu; continue; }
+            const int X = P.mem[j].y & 255, Y = (P.mem[j].y >> 8) & 255;
+            const uint8_t ty = P.grp_type[g];
+            int64_t row;
+            if (j >= nmd) row = nrow_d + (ty == G_SINGLE_B ? X - n : X);
+            else if (!sf) row = pair_index(X, Y);
+            else if (ty == G_AB) row = (int64_t)X * n + (Y - n);
+            else row = nab + (ty == G_BB ? pair_index(X - n, Y - n) : pair_index(X, Y));
+            key[j] = (uint32_t)(row * NC + (L >= (uint32_t)RDM_WIDE ? 0 : L));
+        }
+    });
+    std::vector<int64_t> start((size_t)(nrow * NC + 1), 0);
+    for (int64_t j = 0; j < nmem; j++)
+        if (key[j] != 0xffffffffu) start[key[j] + 1]++;
+    for (size_t k = 1; k < start.size(); k++) start[k] += start[k - 1];
+    const int64_t nent = start.back();
+    if (nent > 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many memberships for the density rows");
+    P.rdm_ent.resize((size_t)nent);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t j = 0; j < nmem; j++) {
+            if (key[j] == 0xffffffffu) continue;
+            const uint32_t g = P.mem_grp[j];
+            const uint32_t j0 = P.grp_off[g], L = P.grp_off[g + 1] - j0;
+            if (L >= 65536) return fail(MW_EUNSUPPORTED, "group too large for the density rows");
+            P.rdm_ent[fill[key[j]]++] = make_uint2(j0, (uint32_t)(j - j0) | (L << 16));
+        }
+    }
+    key.clear();
+    key.shrink_to_fit();
+    P.rdm_pos.resize((size_t)nmem);
+    for (int64_t j = 0; j < nmem; j++) P.rdm_pos[j] = (uint16_t)(P.mem[j].y & 0xffffu);
+    struct Ch {
+        uint4 c;
+        int64_t work;
+    };
+    // alpha-beta wide, alpha-beta small, pair wide, pair small, singles
+    std::vector<Ch> cls[5];
+    for (int64_t row = 0; row < nrow; row++) {
+        for (int part = 0; part < 2; part++) {
+            // part 0: the wide class; part 1: classes 1 .. NC-1 (contiguous)
+            const int64_t e0 = start[row * NC + (part ? 1 : 0)], e1 = start[row * NC + (part ? NC : 1)];
+            const uint32_t flags = row < nab ? 1u : 0u;
+            const uint32_t r = (uint32_t)(row < nab ? row : (row < nrow_d ? row - nab : row - nrow_d));
+            std::vector<Ch> &out = cls[row >= nrow_d ? 4 : (row < nab ? 0 : 2) + part];
+            int64_t a = e0, work = 0;
+            for (int64_t e = e0; e < e1; e++) {
+                work += (P.rdm_ent[e].y >> 16) - 1;
+                if (work >= RDM_CHUNK_WORK || e + 1 == e1) {
+                    out.push_back(Ch{make_uint4(r, flags, (uint32_t)a, (uint32_t)(e + 1)), work});
+                    a = e + 1;
+                    work = 0;
+                }
+            }
+        }
+    }
+    auto by_work = [](const Ch &x, const Ch &y) { return x.work > y.work; };
+    size_t tot = 0;
+    for (auto &v : cls) tot += v.size();
+    P.rdm_chunk.reserve(tot);
+    for (int c = 0; c < 5; c++) {
+        std::stable_sort(cls[c].begin(), cls[c].end(), by_work);
+        P.rdm_cls[c] = (int64_t)P.rdm_chunk.size();
+        for (auto &x : cls[c]) P.rdm_chunk.push_back(x.c);
+    }
+    P.rdm_cls[5] = (int64_t)P.rdm_chunk.size();
+    return MW_OK;
+}
+
 // |z| with each product rounded on its own (no fused multiply-add), the
 // rounding the screening's other magnitudes use
 static double cabs_rounded(double re, double im)
@@ -883,15 +1000,21 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.ref0 = ref0;
     t.ref1 = ref1;
     t.npacket_double = npacket_double;
+    t.nmem_double = nmem_double;
+    t.rdm_ent = (const uint2 *)take(rdm_ent.size() * 8);
+    t.rdm_chunk = (const uint4 *)take(rdm_chunk.size() * 16);
+    t.rdm_pos = (const uint16_t *)take(rdm_pos.size() * 2);
+    for (int c = 0; c < 6; c++) t.rdm_cls[c] = rdm_cls[c];
     // per-call scratch: sigma partials, or the density-matrix accumulators
-    // density-matrix accumulators: double pairs, RDM_COPIES copies of S and
-    // the single corrections (n^3 or M^3), occupation correlations and their
-    // 256 per-chunk partials
+    // (double pairs, RDM_COPIES copies of S and the single corrections (n^3
+    // or M^3), occupation correlations and their 256 per-chunk partials)
+    // followed by the bra coefficients gathered per double membership
     const size_t mm = (size_t)M * M;
     size_t rdm_bytes = kind == MW_SPIN_FREE
                            ? ((size_t)n * n * n * n + 2 * (size_t)npair * npair +
                               RDM_COPIES * (2 * (size_t)n * n + 2 * (size_t)n * n * n) + 257 * mm) * 8
                            : (2 * (size_t)npair * npair + RDM_COPIES * (mm + mm * M) + 257 * mm) * 16;
+    rdm_bytes = ((rdm_bytes + 255) & ~(size_t)255) + mem.size() * max_roots * sb;
     t.scratch_bytes = std::max(std::max<size_t>(1, mem.size() + (size_t)ncol) * (size_t)max_roots * sb, rdm_bytes);
     t.partial = (void *)take(t.scratch_bytes);
     t.self = (DevPlan *)take(sizeof(DevPlan));
@@ -937,6 +1060,8 @@ mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out
         P.max_roots = max_roots;
         P.dets.assign(prob->dets, prob->dets + 2 * prob->ndet);
         st = build_groups(P);
+        if (st != MW_OK) return st;
+        st = build_rdm_rows(P);
         if (st != MW_OK) return st;
         repack(P, prob);
         reference(P);
@@ -989,7 +1114,10 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) &&
               up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
               up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
-              up(d.g_bound, P.g_bound.data(), P.g_bound.size() * 8);
+              up(d.g_bound, P.g_bound.data(), P.g_bound.size() * 8) &&
+              up(d.rdm_ent, P.rdm_ent.data(), P.rdm_ent.size() * 8) &&
+              up(d.rdm_chunk, P.rdm_chunk.data(), P.rdm_chunk.size() * 16) &&
+              up(d.rdm_pos, P.rdm_pos.data(), P.rdm_pos.size() * 2);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
     if (hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
@@ -1068,6 +1196,8 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     case 12: return P.npacket_double;
     case 13: return P.ncol;
     case 14: return P.n_double_pairs_large;
+    case 15: return (int64_t)P.rdm_ent.size();
+    case 16: return (int64_t)P.rdm_chunk.size();
     default: return -1;
     }
 }

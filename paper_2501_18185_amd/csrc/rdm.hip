@@ -24,6 +24,8 @@
 //  the mirror image (the reversed pair's weight is the conjugate).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dev_common.h"
 #include "mw_internal.h"
 
@@ -57,12 +59,6 @@ __device__ __forceinline__ void atom_add(double *a, double v) { atomicAdd(a, v);
 
 __device__ __forceinline__ int rdm_pair_lex(int lo, int hi, int m) { return lo * (2 * m - lo - 1) / 2 + (hi - lo - 1); }
 
-// same XCD-aware block order as the sigma kernels
-__device__ __forceinline__ int64_t xcd_block_r(int64_t b)
-{
-    const int64_t x = b & 7, r = b >> 3;
-    return ((r / 16) * 8 + x) * 16 + (r % 16);
-}
 __device__ __forceinline__ void atom_add(double2 *a, double2 v)
 {
     atomicAdd(&a->x, v.x);
@@ -75,74 +71,228 @@ __device__ __forceinline__ size_t g4(int m, int a, int b, int c, int d)
     return (((size_t)a * m + b) * m + c) * m + d;
 }
 
-// Double pairs.  The accumulators are laid out like the integral tables of
-// sigma (row from the partner j, column from the member i) and use the same
-// per-member layout bit, so the 64 lanes of a wave add into a run of
-// neighbouring entries.  Alpha-beta: D_ab[q][s][p][r] holds G(p,q,r,s) =
-// sum of w over pairs with i adding (p alpha, r beta) and j adding (q, s);
-// layout-1 lanes add into D_ab[s][q][r][p], i.e. G(r,s,p,q), which changes
-// nothing because Gamma only needs G(p,q,r,s) + G(r,s,p,q).  Pair
-// accumulators DT0 (colex columns) and DT1 (lex columns) hold the
-// transposed antisymmetric pair matrix, D[(P,R)][(Q,S)] = DT0[QS][PR] +
-// DT1[QS][lex PR].
+// Double pairs, accumulated row by row.  The accumulator entry of a pair
+// (member i adding (P, R), partner j adding (Q, S)) has its row from j and
+// its column from i: alpha-beta D_ab[q][s][p][r] (row q n + s - n, column
+// p n + r - n) holds G(p,q,r,s); same-spin and spinor pairs the transposed
+// antisymmetric pair matrix, D[(P,R)][(Q,S)] = DT0[QS][PR] (colex pair
+// indices; DT1, the lexicographic half used by the final pass, stays zero).
+// The plan lists every double membership j under the row of its pair, in
+// chunks; a workgroup takes one chunk, adds w_ij of every member i of j's
+// group that is connected to j into an LDS copy of the row (LDS atomics:
+// the waves share it), then adds the row's nonzero entries to the
+// accumulator, one device atomic per entry and chunk instead of one per
+// pair.  w_ij = x_i y_j with x_i = phi_i conj(bra_i) gathered per membership
+// beforehand (so that a group's members are read contiguously) and y_j =
+// phi_j w_k ket_j.
 // SYM (bra and ket are one vector): the reversed pair (J, I) adds the
 // complex conjugate of w_IJ to the mirrored entry, so each unordered pair is
-// visited once (partners j after i in the group) and the final pass adds
+// visited once (members i before j in the group) and the final pass adds
 // the mirror image.
-template <bool CPLX, int U, bool SYM>
-__global__ __launch_bounds__(256) void k_rdm_double(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
-                                                    const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
-                                                    double *__restrict__ dab, typename Scal<CPLX>::T *__restrict__ dt0,
-                                                    typename Scal<CPLX>::T *__restrict__ dt1)
+
+// x[m][k] = phi_m conj(bra[det_m][k]) for every membership m
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_rdm_x(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
+                                               typename Scal<CPLX>::T *__restrict__ x)
+{
+    const int64_t nx = p.nmem * R;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nx; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = t / R;
+        const int k = (int)(t - m * R);
+        const uint2 me = p.mem[m];
+        x[t] = sc_neg(sc_conj(bra[(size_t)me.x * R + k]), ((me.y >> 16) & 1) != 0);
+    }
+}
+
+__device__ __forceinline__ void lds_add(double *a, double v) { atomicAdd(a, v); }
+__device__ __forceinline__ void lds_add(double2 *a, double2 v)
+{
+    atomicAdd(&a->x, v.x);
+    atomicAdd(&a->y, v.y);
+}
+__device__ __forceinline__ bool sc_nonzero(double v) { return v != 0.0; }
+__device__ __forceinline__ bool sc_nonzero(double2 v) { return v.x != 0.0 || v.y != 0.0; }
+__device__ __forceinline__ double lane_get(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l), hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double2 lane_get(double2 v, int l) { return make_double2(lane_get(v.x, l), lane_get(v.y, l)); }
+__device__ __forceinline__ uint32_t lane_get(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+// the value of lane l (per lane)
+__device__ __forceinline__ uint32_t lane_from(uint32_t v, int l) { return (uint32_t)__shfl((int)v, l, 64); }
+__device__ __forceinline__ double lane_from(double v, int l) { return __shfl(v, l, 64); }
+__device__ __forceinline__ double2 lane_from(double2 v, int l) { return make_double2(__shfl(v.x, l, 64), __shfl(v.y, l, 64)); }
+__device__ __forceinline__ uint64_t lane_from(uint64_t v, int l)
+{
+    return ((uint64_t)lane_from((uint32_t)(v >> 32), l) << 32) | lane_from((uint32_t)v, l);
+}
+
+// A wave takes a batch of 64 entries, one per lane with cnt visits; incl is
+// the inclusive prefix of cnt over the lanes.  Visit v (0 <= v < incl of
+// lane 63) belongs to the entry of the returned lane (binary search over the
+// prefix), so that all lanes walk the batch's visits together.
+__device__ __forceinline__ int visit_entry(uint32_t incl, uint32_t v)
+{
+    int t = 0;
+#pragma unroll
+    for (int b = 32; b >= 1; b >>= 1)
+        if (lane_from(incl, t + b - 1) <= v) t += b;
+    return t;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// y_j = phi_j sum-weight w_k ket_jk for root k
+template <bool CPLX>
+__device__ __forceinline__ typename Scal<CPLX>::T rdm_y(const typename Scal<CPLX>::T *__restrict__ ket, int R, int k,
+                                                        uint2 mj, const RdmWeights &W)
 {
     using T = typename Scal<CPLX>::T;
-    const int64_t wave = xcd_block_r(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wave >= p.npacket_double) return;
-    const uint32_t m = p.pk_off[wave] + lane;
-    if (m >= p.pk_off[wave + 1]) return;
-    const uint32_t g = p.mem_grp[m];
-    const uint32_t j0 = p.grp_off[g], j1 = p.grp_off[g + 1];
-    const uint8_t type = p.grp_type[g];
-    const uint2 me = p.mem[m];
-    const int Xi = me.y & 255, Yi = (me.y >> 8) & 255;
-    const uint32_t negi = (me.y >> 16) & 1;
-    const bool lay = (me.y >> 17) & 1;
+    const T v = ket[(size_t)mj.x * R + k];
+    const double wk = W.dev ? W.dev[k] : W.w[k];
+    T r;
+    if constexpr (CPLX) r = make_double2(wk * v.x, wk * v.y);
+    else r = wk * v;
+    return sc_neg(r, ((mj.y >> 16) & 1) != 0);
+}
+
+// column of member i's pair in its row
+template <bool CPLX>
+__device__ __forceinline__ int rdm_col(bool ab, int n, int X, int Y)
+{
+    if (ab) return X * n + (Y - n);
+    if constexpr (CPLX) return pair_idx(X, Y);
+    else return X >= n ? pair_idx(X - n, Y - n) : pair_idx(X, Y);
+}
+
+template <bool CPLX, bool SYM, bool WIDE>
+__global__ __launch_bounds__(256) void k_rdm_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
+                                                  const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
+                                                  typename Scal<CPLX>::T *__restrict__ acc, int ncols, int64_t c0)
+{
+    using T = typename Scal<CPLX>::T;
+    extern __shared__ __align__(16) double rdm_lds_raw[];
+    T *row = (T *)rdm_lds_raw;
+    const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
+    const bool ab = (ch.y & 1) != 0;
     const int n = p.n;
-    const bool ab = !CPLX && type == G_AB;
-    const int off = (!CPLX && type == G_BB) ? n : 0;
-    const int mpos = CPLX ? p.M : n;
-    size_t col;
-    if (ab) col = lay ? (size_t)(Yi - n) * n + Xi : (size_t)Xi * n + (Yi - n);
-    else col = lay ? (size_t)rdm_pair_lex(Xi - off, Yi - off, mpos) : (size_t)pair_idx(Xi - off, Yi - off);
-    T *dst_pair = lay ? dt1 : dt0;
-    // SYM: a large group's blocks before this packet hold no later partner
-    const uint32_t js = SYM ? max(j0, p.pk_off[wave]) : j0;
-    for (uint32_t j = js; j < j1; j += U) {
-        uint2 o[U];
-        bool hit[U];
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) row[t] = sc_zero(T());
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if constexpr (WIDE) {
+        // groups of RDM_WIDE members or more: a wave loads the records of 64
+        // entries (a lane each), then walks their members in steps of 64
+        // (a member per lane), four steps in flight
+        for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += 256u) {
+            const uint32_t e = base + lane;
+            const bool ok = e < ch.w;
+            const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
+            const uint32_t j0 = en.x, L = en.y >> 16;
+            const uint2 mj = ok ? p.mem[j0 + (en.y & 0xffffu)] : make_uint2(0u, 0u);
+            const T y = ok ? rdm_y<CPLX>(ket, R, 0, mj, W) : sc_zero(T());
+            const uint32_t cnt = ok ? (SYM ? (en.y & 0xffffu) : L) : 0u;  // members visited: [j0, j0 + cnt)
+            const uint32_t nb = (cnt + 63) / 64;
+            // inclusive prefix of the step counts over the lanes
+            const uint32_t incl = wave_incl_scan(nb, lane);
+            const uint32_t total = lane_get(incl, 63);
+            for (uint32_t s0 = 0; s0 < total; s0 += 4) {
+                uint32_t pi[4], pj[4], ii[4], dj[4];
+                T xv[4], yv[4];
+                bool act[4];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const bool in = j + u < j1 && (!SYM || j + u > m);
-            o[u] = p.mem[in ? j + u : j0];
-            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
-            hit[u] = in && !(Xj == Xi || Xj == Yi || Yj == Xi || Yj == Yi);
-        }
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t st = s0 + u;
+                    // the entry of step st: the lanes whose inclusive prefix
+                    // is <= st come before it
+                    const int t0 = (int)__popcll(__ballot(incl <= st));
+                    const int t = t0 < 64 ? t0 : 63;
+                    const uint32_t off = (st - (lane_get(incl, t) - lane_get(nb, t))) * 64 + lane;
+                    act[u] = st < total && off < lane_get(cnt, t);
+                    ii[u] = lane_get(j0, t) + off;
+                    pj[u] = lane_get(mj.y, t);
+                    dj[u] = lane_get(mj.x, t);
+                    yv[u] = lane_get(y, t);
+                    pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
+                    xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
+                }
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (!hit[u]) continue;
-            const int Xj = o[u].y & 255, Yj = (o[u].y >> 8) & 255;
-            T w = pair_weight<CPLX>(bra, ket, R, me.x, o[u].x, W);
-            w = sc_neg(w, (negi ^ ((o[u].y >> 16) & 1)) != 0);
-            if constexpr (!CPLX) {
-                if (ab) {
-                    const size_t row = lay ? (size_t)(Yj - n) * n + Xj : (size_t)Xj * n + (Yj - n);
-                    atomicAdd(&dab[row * n * n + col], w);
-                    continue;
+                for (int u = 0; u < 4; u++) {
+                    const int Xi = pi[u] & 255, Yi = (pi[u] >> 8) & 255, Xj = pj[u] & 255, Yj = (pj[u] >> 8) & 255;
+                    if (!act[u] || Xi == Xj || Xi == Yj || Yi == Xj || Yi == Yj) continue;
+                    T w;
+                    if (R == 1) {
+                        w = sc_mul(xv[u], yv[u]);
+                    } else {
+                        // several roots: the partner's y_k from memory
+                        const uint2 mjt = make_uint2(dj[u], pj[u]);
+                        w = sc_zero(T());
+                        for (int k = 0; k < R; k++)
+                            w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
+                    }
+                    lds_add(&row[rdm_col<CPLX>(ab, n, Xi, Yi)], w);
                 }
             }
-            atom_add(&dst_pair[(size_t)pair_idx(Xj - off, Yj - off) * p.npair + col], w);
         }
+    } else {
+        // smaller groups: the visits of 64 entries (a lane each) are walked
+        // by the lanes together, 64 at a time, four steps in flight
+        for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += 256u) {
+            const uint32_t e = base + lane;
+            const bool ok = e < ch.w;
+            const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
+            const uint32_t j0 = en.x, jo = en.y & 0xffffu, L = en.y >> 16;
+            const uint2 mj = ok ? p.mem[j0 + jo] : make_uint2(0u, 0u);
+            const T y = ok ? rdm_y<CPLX>(ket, R, 0, mj, W) : sc_zero(T());
+            const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
+            const uint32_t incl = wave_incl_scan(cnt, lane);
+            const uint32_t total = lane_get(incl, 63);
+            for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
+                uint32_t pi[4], pj[4], ii[4], dj[4];
+                T xv[4], yv[4];
+                bool act[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t v = v0 + 64u * u + lane;
+                    act[u] = v < total;
+                    const int t = visit_entry(incl, v);
+                    ii[u] = lane_from(j0, t) + (v - (lane_from(incl, t) - lane_from(cnt, t)));
+                    pj[u] = lane_from(mj.y, t);
+                    dj[u] = lane_from(mj.x, t);
+                    yv[u] = lane_from(y, t);
+                    pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
+                    xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int Xi = pi[u] & 255, Yi = (pi[u] >> 8) & 255, Xj = pj[u] & 255, Yj = (pj[u] >> 8) & 255;
+                    if (!act[u] || Xi == Xj || Xi == Yj || Yi == Xj || Yi == Yj) continue;
+                    T w;
+                    if (R == 1) {
+                        w = sc_mul(xv[u], yv[u]);
+                    } else {
+                        const uint2 mjt = make_uint2(dj[u], pj[u]);
+                        w = sc_zero(T());
+                        for (int k = 0; k < R; k++)
+                            w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
+                    }
+                    lds_add(&row[rdm_col<CPLX>(ab, n, Xi, Yi)], w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    T *dst = acc + (size_t)ch.x * ncols;
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) {
+        const T v = row[t];
+        if (sc_nonzero(v)) atom_add(&dst[t], v);
     }
 }
 
@@ -254,6 +404,127 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
         const uint2 o = p.mem[j];
         if ((int)(o.y & 255) == Xi) continue;
         rdm_single_pair<CPLX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o);
+    }
+}
+
+// Single pairs, accumulated row by row like the double pairs.  The row is
+// the partner j's added orbital q (spin-free, either spin) or spinor Q; a
+// workgroup holds in LDS the row's S entries (S[s][q][p] for both spins;
+// spinor S[Q][P]) and its C and E blocks (C[q][x][p], E[q][x][p]; spinor
+// C[Q][X][P]), walks the visits of its chunk's entries with all lanes (64
+// entries per wave batch, four steps in flight), and adds the nonzero
+// entries to copy 0 of the accumulators.  Per pair the same terms as
+// rdm_single_pair: S, then the positions where the group's string K and
+// the reference omega differ.
+template <bool CPLX, bool SYM>
+__global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
+                                                         const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
+                                                         typename Scal<CPLX>::T *__restrict__ S,
+                                                         typename Scal<CPLX>::T *__restrict__ Cc,
+                                                         double *__restrict__ Ee, int64_t c0)
+{
+    using T = typename Scal<CPLX>::T;
+    extern __shared__ __align__(16) double rdm_lds_raw[];
+    const int n = p.n, M = p.M;
+    const int nS = CPLX ? M : 2 * n, nC = CPLX ? M * M : n * n;
+    const int ncols = CPLX ? nS + nC : nS + 2 * nC;
+    T *lS = (T *)rdm_lds_raw, *lC = lS + nS;
+    double *lE = CPLX ? nullptr : (double *)(lS + nS + nC);
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) lS[t] = sc_zero(T());
+    __syncthreads();
+    const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
+    const int q = (int)ch.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += 256u) {
+        const uint32_t e = base + lane;
+        const bool ok = e < ch.w;
+        const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
+        const uint32_t j0 = en.x, jo = en.y & 0xffffu, L = en.y >> 16;
+        const uint32_t jj = j0 + jo;
+        const uint2 mj = ok ? p.mem[jj] : make_uint2(0u, 0u);
+        const uint32_t g = ok ? p.mem_grp[jj] : 0u;
+        const uint64_t k0 = ok ? p.grp_key[2 * (size_t)g] : 0ULL, k1 = ok ? p.grp_key[2 * (size_t)g + 1] : 0ULL;
+        const uint32_t sb = ok && p.grp_type[g] == G_SINGLE_B ? 1u : 0u;
+        const T y = ok ? rdm_y<CPLX>(ket, R, 0, mj, W) : sc_zero(T());
+        const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
+        const uint32_t incl = wave_incl_scan(cnt, lane);
+        const uint32_t total = lane_get(incl, 63);
+        for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
+            uint32_t pi[4], pj[4], ii[4], dj[4], sp[4];
+            uint64_t kk0[4], kk1[4];
+            T xv[4], yv[4];
+            bool act[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t v = v0 + 64u * u + lane;
+                act[u] = v < total;
+                const int t = visit_entry(incl, v);
+                ii[u] = lane_from(j0, t) + (v - (lane_from(incl, t) - lane_from(cnt, t)));
+                pj[u] = lane_from(mj.y, t);
+                dj[u] = lane_from(mj.x, t);
+                sp[u] = lane_from(sb, t);
+                kk0[u] = lane_from(k0, t);
+                kk1[u] = lane_from(k1, t);
+                yv[u] = lane_from(y, t);
+                pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
+                xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int Xi = pi[u] & 255, Xj = pj[u] & 255;
+                if (!act[u] || Xi == Xj) continue;
+                T w;
+                if (R == 1) {
+                    w = sc_mul(xv[u], yv[u]);
+                } else {
+                    const uint2 mjt = make_uint2(dj[u], pj[u]);
+                    w = sc_zero(T());
+                    for (int k = 0; k < R; k++)
+                        w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
+                }
+                if constexpr (!CPLX) {
+                    const int s = (int)sp[u], pp = Xi - s * n;
+                    lds_add(&lS[s * n + pp], w);
+                    for (int part = 0; part < 4; part++) {
+                        const bool same = part < 2;
+                        const uint64_t kw = (same == (s == 0)) ? kk0[u] : kk1[u];
+                        const uint64_t rw = (same == (s == 0)) ? p.ref0 : p.ref1;
+                        const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
+                        const double sw = (part & 1) ? -w : w;
+                        for (uint64_t b = bits; b; b &= b - 1) {
+                            const int xx = __builtin_ctzll(b);
+                            lds_add(&lC[xx * n + pp], sw);
+                            if (same) lds_add(&lE[xx * n + pp], sw);
+                        }
+                    }
+                } else {
+                    lds_add(&lS[Xi], w);
+                    for (int part = 0; part < 4; part++) {
+                        const uint64_t kw = (part < 2) ? kk0[u] : kk1[u];
+                        const uint64_t rw = (part < 2) ? p.ref0 : p.ref1;
+                        const int bpos = (part < 2) ? 0 : n;
+                        const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
+                        const T sw = sc_neg(w, (part & 1) != 0);
+                        for (uint64_t b = bits; b; b &= b - 1) lds_add(&lC[(bpos + __builtin_ctzll(b)) * M + Xi], sw);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // S: spin-free S[s][q][p] (lS[s n + p]); spinor S[Q][P]; C (and E) rows
+    // of q: C + q nC
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) {
+        const T v = lS[t];
+        if (!sc_nonzero(v)) continue;
+        if (t < nS) {
+            if constexpr (CPLX) atom_add(&S[(size_t)q * M + t], v);
+            else atom_add(&S[((size_t)(t / n) * n + q) * n + (t % n)], v);
+        } else if (t < nS + nC) {
+            atom_add(&Cc[(size_t)q * nC + (t - nS)], v);
+        } else {
+            if constexpr (!CPLX) atom_add(&Ee[(size_t)q * nC + (t - nS - nC)], v);
+        }
     }
 }
 
@@ -483,17 +754,86 @@ __global__ void k_zero(double *x, int64_t n)
         x[t] = 0.0;
 }
 
-static unsigned xcd_grid_r(int64_t blocks)
-{
-    const int64_t q = 8 * 16;
-    return (unsigned)((blocks + q - 1) / q * q);
-}
-
 static void zero(double *x, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;
     int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, x, n);
+}
+
+// x per membership (k_rdm_x), before the row kernels
+template <bool CPLX>
+static void launch_rdm_x(const DevPlan &p, int R, const typename Scal<CPLX>::T *bra, typename Scal<CPLX>::T *x,
+                         hipStream_t s)
+{
+    if (p.rdm_cls[5] == 0) return;
+    const int64_t nx = p.nmem * R;
+    hipLaunchKernelGGL(k_rdm_x<CPLX>, dim3((unsigned)std::min<int64_t>((nx + 255) / 256, 1 << 20)), dim3(256), 0, s, p,
+                       R, bra, x);
+}
+
+// the single-pair accumulators (copy 0 of S, C, E), row by row; the
+// per-pair atomic kernel over the single packets when a row does not fit
+// in the LDS of a workgroup (spinor spaces of more than 100 spinors)
+template <bool CPLX>
+static mw_status launch_rdm_single_rows(const DevPlan &p, int R, const typename Scal<CPLX>::T *bra,
+                                        const typename Scal<CPLX>::T *ket, const RdmWeights &W, bool sym,
+                                        typename Scal<CPLX>::T *S, typename Scal<CPLX>::T *Cc, double *Ee,
+                                        const typename Scal<CPLX>::T *x, int64_t copy_stride, hipStream_t s)
+{
+    const int n = p.n, M = p.M;
+    const size_t lds = CPLX ? (size_t)(M + (size_t)M * M) * 16 : (size_t)(2 * n + 2 * (size_t)n * n) * 8;
+    if (lds <= 160 * 1024) {
+        const int64_t c0 = p.rdm_cls[4], nch = p.rdm_cls[5] - c0;
+        if (nch <= 0) return MW_OK;
+        auto kern = sym ? k_rdm_single_rows<CPLX, true> : k_rdm_single_rows<CPLX, false>;
+        if (lds > 65536 &&
+            hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return fail(MW_EHIP, "hipFuncSetAttribute failed");
+        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(256), lds, s, p, R, ket, x, W, S, Cc, Ee, c0);
+        return MW_OK;
+    }
+    const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
+    if (gs == 0) return MW_OK;
+    if (sym)
+        hipLaunchKernelGGL((k_rdm_single<CPLX, true>), dim3(gs), dim3(256), 0, s, p, R, bra, ket, W, S, Cc, Ee,
+                           copy_stride);
+    else
+        hipLaunchKernelGGL((k_rdm_single<CPLX, false>), dim3(gs), dim3(256), 0, s, p, R, bra, ket, W, S, Cc, Ee,
+                           copy_stride);
+    return MW_OK;
+}
+
+// the double-pair accumulators, row by row (k_rdm_rows over the alpha-beta
+// chunks into acc_ab and the pair chunks into acc_pair)
+// (an LDS row of up to 160 KB: n^2 doubles, or npair scalars)
+template <bool CPLX>
+static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CPLX>::T *bra,
+                                 const typename Scal<CPLX>::T *ket, const RdmWeights &W, bool sym,
+                                 typename Scal<CPLX>::T *acc_ab, typename Scal<CPLX>::T *acc_pair,
+                                 typename Scal<CPLX>::T *x, hipStream_t s)
+{
+    using T = typename Scal<CPLX>::T;
+    (void)bra;
+    auto go = [&](int c, T *acc, int ncols) -> mw_status {
+        const int64_t c0 = p.rdm_cls[c], nch = p.rdm_cls[c + 1] - c0;
+        if (nch <= 0) return MW_OK;
+        const size_t lds = (size_t)ncols * sizeof(T);
+        if (lds > 160 * 1024) return fail(MW_EUNSUPPORTED, "density-matrix row exceeds the LDS of a workgroup");
+        const bool wide = (c & 1) == 0;
+        auto kern = sym ? (wide ? k_rdm_rows<CPLX, true, true> : k_rdm_rows<CPLX, true, false>)
+                        : (wide ? k_rdm_rows<CPLX, false, true> : k_rdm_rows<CPLX, false, false>);
+        if (lds > 65536 &&
+            hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return fail(MW_EHIP, "hipFuncSetAttribute failed");
+        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(256), lds, s, p, R, ket, x, W, acc, ncols, c0);
+        return MW_OK;
+    };
+    for (int c = 0; c < 4; c++) {
+        mw_status st = go(c, c < 2 ? acc_ab : acc_pair, c < 2 ? p.n * p.n : p.npair);
+        if (st != MW_OK) return st;
+    }
+    return MW_OK;
 }
 
 mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, const double *weights,
@@ -505,9 +845,6 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
     // one vector as bra and ket (real weights): w_JI = conj(w_IJ)
     const bool sym = bra == ket;
     const int n = p.n, M = p.M;
-    const unsigned gd = (unsigned)((p.npacket_double + 3) / 4);
-    const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
-    const unsigned gdx = xcd_grid_r((p.npacket_double + 3) / 4);
     const int64_t mm = (int64_t)M * M;
     const unsigned gred = (unsigned)((mm + 255) / 256);
     if (p.kind == MW_SPIN_FREE) {
@@ -516,27 +853,20 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         const int64_t cs = 2 * (int64_t)n * n + 2 * n3;
         double *dab = (double *)p.partial, *dt0 = dab + n4, *dt1 = dt0 + np2, *S = dt1 + np2;
         double *Cc = S + 2 * (int64_t)n * n, *Ee = Cc + n3, *D = S + RDM_COPIES * cs, *part = D + mm;
+        // bra coefficients per double membership, after the accumulators
+        double *xb = (double *)((char *)p.partial + ((((size_t)(part - dab) + RDM_OCC_CHUNKS * mm) * 8 + 255) &
+                                                     ~(size_t)255));
         zero(dab, n4 + 2 * np2 + RDM_COPIES * cs, s);
+        launch_rdm_x<false>(p, R, (const double *)bra, xb, s);
         ProfToken t = prof_begin("rdm_double", s);
-        if (gd) {
-            if (sym)
-                hipLaunchKernelGGL((k_rdm_double<false, 8, true>), dim3(gdx), dim3(256), 0, s, p, R,
-                                   (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
-            else
-                hipLaunchKernelGGL((k_rdm_double<false, 8, false>), dim3(gdx), dim3(256), 0, s, p, R,
-                                   (const double *)bra, (const double *)ket, W, dab, dt0, dt1);
-        }
+        mw_status st = launch_rdm_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, dab, dt0, xb, s);
         prof_end(t, s);
+        if (st != MW_OK) return st;
         t = prof_begin("rdm_single", s);
-        if (gs) {
-            if (sym)
-                hipLaunchKernelGGL((k_rdm_single<false, true>), dim3(gs), dim3(256), 0, s, p, R,
-                                   (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
-            else
-                hipLaunchKernelGGL((k_rdm_single<false, false>), dim3(gs), dim3(256), 0, s, p, R,
-                                   (const double *)bra, (const double *)ket, W, S, Cc, Ee, cs);
-        }
+        st = launch_rdm_single_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, S, Cc, Ee, xb, cs,
+                                           s);
         prof_end(t, s);
+        if (st != MW_OK) return st;
         hipLaunchKernelGGL(k_rdm_fold<double>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
                            RDM_COPIES);
         if (sym) {
@@ -559,27 +889,20 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         const int64_t cs = mm + m3;
         double2 *dt0 = (double2 *)p.partial, *dt1 = dt0 + np2, *S = dt1 + np2, *Cc = S + mm,
                 *D = S + RDM_COPIES * cs, *part = D + mm;
+        double2 *xb = (double2 *)((char *)p.partial + ((((size_t)(part - dt0) + RDM_OCC_CHUNKS * mm) * 16 + 255) &
+                                                       ~(size_t)255));
         zero((double *)dt0, 2 * (2 * np2 + RDM_COPIES * cs), s);
+        launch_rdm_x<true>(p, R, (const double2 *)bra, xb, s);
         ProfToken t = prof_begin("rdm_double", s);
-        if (gd) {
-            if (sym)
-                hipLaunchKernelGGL((k_rdm_double<true, 4, true>), dim3(gdx), dim3(256), 0, s, p, R,
-                                   (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
-            else
-                hipLaunchKernelGGL((k_rdm_double<true, 4, false>), dim3(gdx), dim3(256), 0, s, p, R,
-                                   (const double2 *)bra, (const double2 *)ket, W, (double *)nullptr, dt0, dt1);
-        }
+        mw_status st = launch_rdm_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym,
+                                             (double2 *)nullptr, dt0, xb, s);
         prof_end(t, s);
+        if (st != MW_OK) return st;
         t = prof_begin("rdm_single", s);
-        if (gs) {
-            if (sym)
-                hipLaunchKernelGGL((k_rdm_single<true, true>), dim3(gs), dim3(256), 0, s, p, R,
-                                   (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
-            else
-                hipLaunchKernelGGL((k_rdm_single<true, false>), dim3(gs), dim3(256), 0, s, p, R,
-                                   (const double2 *)bra, (const double2 *)ket, W, S, Cc, (double *)nullptr, cs);
-        }
+        st = launch_rdm_single_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym, S, Cc,
+                                          (double *)nullptr, xb, cs, s);
         prof_end(t, s);
+        if (st != MW_OK) return st;
         hipLaunchKernelGGL(k_rdm_fold<double2>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
                            RDM_COPIES);
         if (sym) {

@@ -23,7 +23,7 @@ STATUS = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOTSORTED", -3: "MW_EELEC", -4: 
 INFO = {"ndet": 0, "groups": 1, "memberships": 2, "pairs": 3, "single_pairs": 4,
         "double_pairs": 5, "evaluations": 6, "workspace_bytes": 7, "scalar_bytes": 8,
         "norb": 9, "kind": 10, "packets": 11, "double_packets": 12, "column_partials": 13,
-        "double_pairs_large_groups": 14}
+        "double_pairs_large_groups": 14, "rdm_row_entries": 15, "rdm_row_chunks": 16}
 
 
 class MWError(RuntimeError):
