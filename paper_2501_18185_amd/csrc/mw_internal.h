@@ -75,10 +75,12 @@ struct DevPlan {
     // rdm_cls[c + 1]): alpha-beta rows of wide groups, of small groups, pair
     // rows of wide and of small groups, then the rows of the single
     // memberships (by the added orbital or spinor); rdm_pos[j] = X | Y << 8,
-    // the positions added in membership j (Y = 255 for single groups)
+    // the positions added in membership j (Y = 255 for single groups);
+    // rdm_ent_det[e] = the determinant of entry e's membership | sign << 31
     const uint2 *rdm_ent;
     const uint4 *rdm_chunk;
     const uint16_t *rdm_pos;
+    const uint32_t *rdm_ent_det;
     int64_t rdm_cls[6];
     void *partial;             // [nmem][R] per-membership partial sums, member order (also RDM accumulators)
     size_t scratch_bytes;

@@ -152,6 +152,7 @@ struct HostPlan {
     std::vector<uint2> rdm_ent;
     std::vector<uint4> rdm_chunk;
     std::vector<uint16_t> rdm_pos;
+    std::vector<uint32_t> rdm_ent_det;
     int64_t rdm_cls[6] = {0, 0, 0, 0, 0, 0};
     // launch defaults until mw_autotune picks its own: partner-loop unroll 4,
     // 16 gather lanes (32 for complex), the fastest measured on the n = 64
@@ -707,6 +708,7 @@ static mw_status build_rdm_rows(HostPlan &P)
     P.rdm_ent.clear();
     P.rdm_chunk.clear();
     P.rdm_pos.clear();
+    P.rdm_ent_det.clear();
     for (auto &c : P.rdm_cls) c = 0;
     const int64_t nmd = P.npacket_double > 0 ? (int64_t)P.pk_off[P.npacket_double] : 0;
     const int64_t nmem = (int64_t)P.mem.size();
@@ -742,7 +744,9 @@ static mw_status build_rdm_rows(HostPlan &P)
     for (size_t k = 1; k < start.size(); k++) start[k] += start[k - 1];
     const int64_t nent = start.back();
     if (nent > 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many memberships for the density rows");
+    if (P.ndet >= (int64_t)1 << 31) return fail(MW_EUNSUPPORTED, "too many determinants for the density rows");
     P.rdm_ent.resize((size_t)nent);
+    P.rdm_ent_det.resize((size_t)nent);
     {
         std::vector<int64_t> fill(start.begin(), start.end() - 1);
         for (int64_t j = 0; j < nmem; j++) {
@@ -750,7 +754,10 @@ static mw_status build_rdm_rows(HostPlan &P)
             const uint32_t g = P.mem_grp[j];
             const uint32_t j0 = P.grp_off[g], L = P.grp_off[g + 1] - j0;
             if (L >= 65536) return fail(MW_EUNSUPPORTED, "group too large for the density rows");
-            P.rdm_ent[fill[key[j]]++] = make_uint2(j0, (uint32_t)(j - j0) | (L << 16));
+            const int64_t e = fill[key[j]]++;
+            P.rdm_ent[e] = make_uint2(j0, (uint32_t)(j - j0) | (L << 16));
+            // the partner's determinant and sign (bit 31)
+            P.rdm_ent_det[e] = P.mem[j].x | (((P.mem[j].y >> 16) & 1u) << 31);
         }
     }
     key.clear();
@@ -1004,6 +1011,7 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.rdm_ent = (const uint2 *)take(rdm_ent.size() * 8);
     t.rdm_chunk = (const uint4 *)take(rdm_chunk.size() * 16);
     t.rdm_pos = (const uint16_t *)take(rdm_pos.size() * 2);
+    t.rdm_ent_det = (const uint32_t *)take(rdm_ent_det.size() * 4);
     for (int c = 0; c < 6; c++) t.rdm_cls[c] = rdm_cls[c];
     // per-call scratch: sigma partials, or the density-matrix accumulators
     // (double pairs, RDM_COPIES copies of S and the single corrections (n^3
@@ -1117,7 +1125,8 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.g_bound, P.g_bound.data(), P.g_bound.size() * 8) &&
               up(d.rdm_ent, P.rdm_ent.data(), P.rdm_ent.size() * 8) &&
               up(d.rdm_chunk, P.rdm_chunk.data(), P.rdm_chunk.size() * 16) &&
-              up(d.rdm_pos, P.rdm_pos.data(), P.rdm_pos.size() * 2);
+              up(d.rdm_pos, P.rdm_pos.data(), P.rdm_pos.size() * 2) &&
+              up(d.rdm_ent_det, P.rdm_ent_det.data(), P.rdm_ent_det.size() * 4);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
     if (hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");

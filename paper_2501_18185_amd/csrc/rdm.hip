@@ -6,22 +6,25 @@
 // Every ordered pair (I, J) connected inside a group contributes
 // w_IJ = phi_I phi_J sum_k w_k conj(bra_Ik) ket_Jk:
 //  double group, I adds (P<R), J adds (Q<S):  Gamma_PQRS += w, Gamma_RSPQ += w,
-//      Gamma_PSRQ -= w, Gamma_RQPS -= w.  One device atomic per pair goes to
-//      an accumulator (spin-free alpha-beta: a full [n]^4 array G_ab; same
-//      spin and spinor: the antisymmetric pair matrix D[(P,R)][(Q,S)]); a
-//      final pass expands it into Gamma.
+//      Gamma_PSRQ -= w, Gamma_RQPS -= w, collected in an accumulator
+//      (spin-free alpha-beta: a full [n]^4 array G_ab; same spin and
+//      spinor: the antisymmetric pair matrix D[(P,R)][(Q,S)]) that a final
+//      pass expands into Gamma.
 //  single group, I adds P, J adds Q (K the common N-1 string):
 //      gamma_PQ += w and, for every X in K, Gamma_PQXX += w, Gamma_XXPQ += w,
 //      Gamma_PXXQ -= w, Gamma_XQPX -= w (spin-free: the exchange-like two
 //      only for X of the spin of P).  The sum over K is split into the
 //      reference string omega (applied once at the end through the
 //      accumulated S_PQ = sum of w) plus the few positions where K and omega
-//      differ (direct atomics into compact C and E arrays, spread over
-//      copies that are folded before the final pass).
+//      differ (compact C and E arrays).
 //  diagonal I = J: gamma_PP += w, Gamma_PPRR += w, Gamma_PRRP -= w (P != R),
 //      from the occupation correlations of every determinant.
 //  One vector as bra and ket: each unordered pair once; the final pass adds
 //  the mirror image (the reversed pair's weight is the conjugate).
+// The pair accumulators are filled row by row (the row of a pair is the
+// partner J's added pair or position): the plan lists every membership
+// under its row, a workgroup sums a chunk of a row's list in LDS and adds the
+// row to the accumulator once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -164,6 +167,28 @@ __device__ __forceinline__ typename Scal<CPLX>::T rdm_y(const typename Scal<CPLX
     return sc_neg(r, ((mj.y >> 16) & 1) != 0);
 }
 
+// y_j of the first root for the partner of entry e: its determinant and
+// sign come with the entry (read in entry order), only ket_j is gathered
+template <bool CPLX>
+__device__ __forceinline__ typename Scal<CPLX>::T entry_y(const DevPlan &p, int R,
+                                                          const typename Scal<CPLX>::T *__restrict__ ket,
+                                                          const RdmWeights &W, uint32_t e, uint32_t &dj)
+{
+    const uint32_t d = p.rdm_ent_det[e];
+    dj = d;
+    return rdm_y<CPLX>(ket, R, 0, make_uint2(d & 0x7fffffffu, (d >> 31) << 16), W);
+}
+
+// the pair (a < b) of positions of a colex pair index r = b (b - 1) / 2 + a
+__device__ __forceinline__ void pair_of_index(int r, int &a, int &b)
+{
+    int hi = (int)((1.0 + sqrt(1.0 + 8.0 * (double)r)) * 0.5);
+    while (hi * (hi - 1) / 2 > r) hi--;
+    while ((hi + 1) * hi / 2 <= r) hi++;
+    b = hi;
+    a = r - hi * (hi - 1) / 2;
+}
+
 // column of member i's pair in its row
 template <bool CPLX>
 __device__ __forceinline__ int rdm_col(bool ab, int n, int X, int Y)
@@ -173,8 +198,14 @@ __device__ __forceinline__ int rdm_col(bool ab, int n, int X, int Y)
     else return X >= n ? pair_idx(X - n, Y - n) : pair_idx(X, Y);
 }
 
+// (wide groups: 256 threads per workgroup; the flattened visits of small
+// groups, longer-latency chains per batch: 512, more waves per LDS row)
+// The row's pair is the partner's: alpha-beta row r = a n + b - n, pair
+// row r = b (b - 1) / 2 + a (same-spin positions reduced by n for beta);
+// member i of the same group is connected to the partner when their pairs
+// share no position.
 template <bool CPLX, bool SYM, bool WIDE>
-__global__ __launch_bounds__(256) void k_rdm_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
+__global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
                                                   const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
                                                   typename Scal<CPLX>::T *__restrict__ acc, int ncols, int64_t c0)
 {
@@ -184,27 +215,44 @@ __global__ __launch_bounds__(256) void k_rdm_rows(DevPlan p, int R, const typena
     const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
     const bool ab = (ch.y & 1) != 0;
     const int n = p.n;
+    int pa, pb;
+    if (ab) {
+        pa = (int)ch.x / n;
+        pb = n + (int)ch.x % n;
+    } else {
+        pair_of_index((int)ch.x, pa, pb);
+    }
+    // member positions in the row's space, and the connection test
+    auto reduce = [&](uint32_t pos, int &xi, int &yi) {
+        xi = pos & 255;
+        yi = (pos >> 8) & 255;
+        if (!CPLX && !ab && xi >= n) {
+            xi -= n;
+            yi -= n;
+        }
+    };
     for (int t = threadIdx.x; t < ncols; t += blockDim.x) row[t] = sc_zero(T());
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t stride = blockDim.x;  // 64 entries per wave
     if constexpr (WIDE) {
         // groups of RDM_WIDE members or more: a wave loads the records of 64
         // entries (a lane each), then walks their members in steps of 64
         // (a member per lane), four steps in flight
-        for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += 256u) {
+        for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += stride) {
             const uint32_t e = base + lane;
             const bool ok = e < ch.w;
             const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
             const uint32_t j0 = en.x, L = en.y >> 16;
-            const uint2 mj = ok ? p.mem[j0 + (en.y & 0xffffu)] : make_uint2(0u, 0u);
-            const T y = ok ? rdm_y<CPLX>(ket, R, 0, mj, W) : sc_zero(T());
+            uint32_t dj = 0u;
+            const T y = ok ? entry_y<CPLX>(p, R, ket, W, e, dj) : sc_zero(T());
             const uint32_t cnt = ok ? (SYM ? (en.y & 0xffffu) : L) : 0u;  // members visited: [j0, j0 + cnt)
             const uint32_t nb = (cnt + 63) / 64;
             // inclusive prefix of the step counts over the lanes
             const uint32_t incl = wave_incl_scan(nb, lane);
             const uint32_t total = lane_get(incl, 63);
             for (uint32_t s0 = 0; s0 < total; s0 += 4) {
-                uint32_t pi[4], pj[4], ii[4], dj[4];
+                uint32_t pi[4], ii[4], djs[4];
                 T xv[4], yv[4];
                 bool act[4];
 #pragma unroll
@@ -217,45 +265,45 @@ __global__ __launch_bounds__(256) void k_rdm_rows(DevPlan p, int R, const typena
                     const uint32_t off = (st - (lane_get(incl, t) - lane_get(nb, t))) * 64 + lane;
                     act[u] = st < total && off < lane_get(cnt, t);
                     ii[u] = lane_get(j0, t) + off;
-                    pj[u] = lane_get(mj.y, t);
-                    dj[u] = lane_get(mj.x, t);
+                    djs[u] = lane_get(dj, t);
                     yv[u] = lane_get(y, t);
                     pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
                     xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
                 }
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
-                    const int Xi = pi[u] & 255, Yi = (pi[u] >> 8) & 255, Xj = pj[u] & 255, Yj = (pj[u] >> 8) & 255;
-                    if (!act[u] || Xi == Xj || Xi == Yj || Yi == Xj || Yi == Yj) continue;
+                    int xi, yi;
+                    reduce(pi[u], xi, yi);
+                    if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
                     T w;
                     if (R == 1) {
                         w = sc_mul(xv[u], yv[u]);
                     } else {
                         // several roots: the partner's y_k from memory
-                        const uint2 mjt = make_uint2(dj[u], pj[u]);
+                        const uint2 mjt = make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16);
                         w = sc_zero(T());
                         for (int k = 0; k < R; k++)
                             w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
                     }
-                    lds_add(&row[rdm_col<CPLX>(ab, n, Xi, Yi)], w);
+                    lds_add(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w);
                 }
             }
         }
     } else {
         // smaller groups: the visits of 64 entries (a lane each) are walked
         // by the lanes together, 64 at a time, four steps in flight
-        for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += 256u) {
+        for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += stride) {
             const uint32_t e = base + lane;
             const bool ok = e < ch.w;
             const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
             const uint32_t j0 = en.x, jo = en.y & 0xffffu, L = en.y >> 16;
-            const uint2 mj = ok ? p.mem[j0 + jo] : make_uint2(0u, 0u);
-            const T y = ok ? rdm_y<CPLX>(ket, R, 0, mj, W) : sc_zero(T());
+            uint32_t dj = 0u;
+            const T y = ok ? entry_y<CPLX>(p, R, ket, W, e, dj) : sc_zero(T());
             const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
             const uint32_t incl = wave_incl_scan(cnt, lane);
             const uint32_t total = lane_get(incl, 63);
             for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
-                uint32_t pi[4], pj[4], ii[4], dj[4];
+                uint32_t pi[4], ii[4], djs[4];
                 T xv[4], yv[4];
                 bool act[4];
 #pragma unroll
@@ -264,26 +312,26 @@ __global__ __launch_bounds__(256) void k_rdm_rows(DevPlan p, int R, const typena
                     act[u] = v < total;
                     const int t = visit_entry(incl, v);
                     ii[u] = lane_from(j0, t) + (v - (lane_from(incl, t) - lane_from(cnt, t)));
-                    pj[u] = lane_from(mj.y, t);
-                    dj[u] = lane_from(mj.x, t);
+                    djs[u] = lane_from(dj, t);
                     yv[u] = lane_from(y, t);
                     pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
                     xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
                 }
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
-                    const int Xi = pi[u] & 255, Yi = (pi[u] >> 8) & 255, Xj = pj[u] & 255, Yj = (pj[u] >> 8) & 255;
-                    if (!act[u] || Xi == Xj || Xi == Yj || Yi == Xj || Yi == Yj) continue;
+                    int xi, yi;
+                    reduce(pi[u], xi, yi);
+                    if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
                     T w;
                     if (R == 1) {
                         w = sc_mul(xv[u], yv[u]);
                     } else {
-                        const uint2 mjt = make_uint2(dj[u], pj[u]);
+                        const uint2 mjt = make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16);
                         w = sc_zero(T());
                         for (int k = 0; k < R; k++)
                             w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
                     }
-                    lds_add(&row[rdm_col<CPLX>(ab, n, Xi, Yi)], w);
+                    lds_add(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w);
                 }
             }
         }
@@ -826,7 +874,7 @@ static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CP
         if (lds > 65536 &&
             hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return fail(MW_EHIP, "hipFuncSetAttribute failed");
-        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(256), lds, s, p, R, ket, x, W, acc, ncols, c0);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(wide ? 256 : 512), lds, s, p, R, ket, x, W, acc, ncols, c0);
         return MW_OK;
     };
     for (int c = 0; c < 4; c++) {
