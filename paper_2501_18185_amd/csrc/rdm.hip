@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dev_common.h"
 #include "mw_internal.h"
@@ -167,16 +168,35 @@ __device__ __forceinline__ typename Scal<CPLX>::T rdm_y(const typename Scal<CPLX
     return sc_neg(r, ((mj.y >> 16) & 1) != 0);
 }
 
-// y_j of the first root for the partner of entry e: its determinant and
-// sign come with the entry (read in entry order), only ket_j is gathered
-template <bool CPLX>
-__device__ __forceinline__ typename Scal<CPLX>::T entry_y(const DevPlan &p, int R,
-                                                          const typename Scal<CPLX>::T *__restrict__ ket,
-                                                          const RdmWeights &W, uint32_t e, uint32_t &dj)
+// y_jk of roots k < RY (zero beyond R) for a partner record mj
+template <bool CPLX, int RY>
+__device__ __forceinline__ void partner_ys(const typename Scal<CPLX>::T *__restrict__ ket, int R, uint2 mj,
+                                           const RdmWeights &W, bool ok, typename Scal<CPLX>::T (&y)[RY])
 {
-    const uint32_t d = p.rdm_ent_det[e];
-    dj = d;
-    return rdm_y<CPLX>(ket, R, 0, make_uint2(d & 0x7fffffffu, (d >> 31) << 16), W);
+#pragma unroll
+    for (int k = 0; k < RY; k++) y[k] = (ok && k < R) ? rdm_y<CPLX>(ket, R, k, mj, W) : sc_zero(typename Scal<CPLX>::T());
+}
+
+// w = sum over roots of x_ik y_jk: RM = 1 (one root), 4 (up to four roots,
+// the partner's y in registers) or 0 (any count, y_jk read per pair)
+template <bool CPLX, int RM, int RY>
+__device__ __forceinline__ typename Scal<CPLX>::T pair_w(const typename Scal<CPLX>::T (&xv)[RY],
+                                                         const typename Scal<CPLX>::T (&yv)[RY],
+                                                         const typename Scal<CPLX>::T *__restrict__ x,
+                                                         const typename Scal<CPLX>::T *__restrict__ ket, int R,
+                                                         uint32_t i, uint2 mj, const RdmWeights &W)
+{
+    using T = typename Scal<CPLX>::T;
+    if constexpr (RM == 0) {
+        T w = sc_zero(T());
+        for (int k = 0; k < R; k++) w = sc_add(w, sc_mul(x[(size_t)i * R + k], rdm_y<CPLX>(ket, R, k, mj, W)));
+        return w;
+    } else {
+        T w = sc_mul(xv[0], yv[0]);
+#pragma unroll
+        for (int k = 1; k < RY; k++) w = sc_add(w, sc_mul(xv[k], yv[k]));
+        return w;
+    }
 }
 
 // the pair (a < b) of positions of a colex pair index r = b (b - 1) / 2 + a
@@ -204,12 +224,13 @@ __device__ __forceinline__ int rdm_col(bool ab, int n, int X, int Y)
 // row r = b (b - 1) / 2 + a (same-spin positions reduced by n for beta);
 // member i of the same group is connected to the partner when their pairs
 // share no position.
-template <bool CPLX, bool SYM, bool WIDE>
+template <bool CPLX, bool SYM, bool WIDE, int RM>
 __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
                                                   const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
                                                   typename Scal<CPLX>::T *__restrict__ acc, int ncols, int64_t c0)
 {
     using T = typename Scal<CPLX>::T;
+    constexpr int RY = RM == 4 ? 4 : 1;
     extern __shared__ __align__(16) double rdm_lds_raw[];
     T *row = (T *)rdm_lds_raw;
     const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
@@ -244,8 +265,9 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
             const bool ok = e < ch.w;
             const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
             const uint32_t j0 = en.x, L = en.y >> 16;
-            uint32_t dj = 0u;
-            const T y = ok ? entry_y<CPLX>(p, R, ket, W, e, dj) : sc_zero(T());
+            const uint32_t dj = ok ? p.rdm_ent_det[e] : 0u;
+            T y[RY];
+            partner_ys<CPLX, RY>(ket, R, make_uint2(dj & 0x7fffffffu, (dj >> 31) << 16), W, ok, y);
             const uint32_t cnt = ok ? (SYM ? (en.y & 0xffffu) : L) : 0u;  // members visited: [j0, j0 + cnt)
             const uint32_t nb = (cnt + 63) / 64;
             // inclusive prefix of the step counts over the lanes
@@ -253,7 +275,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
             const uint32_t total = lane_get(incl, 63);
             for (uint32_t s0 = 0; s0 < total; s0 += 4) {
                 uint32_t pi[4], ii[4], djs[4];
-                T xv[4], yv[4];
+                T xv[4][RY], yv[4][RY];
                 bool act[4];
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
@@ -266,25 +288,20 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
                     act[u] = st < total && off < lane_get(cnt, t);
                     ii[u] = lane_get(j0, t) + off;
                     djs[u] = lane_get(dj, t);
-                    yv[u] = lane_get(y, t);
+#pragma unroll
+                    for (int k = 0; k < RY; k++) {
+                        yv[u][k] = lane_get(y[k], t);
+                        xv[u][k] = act[u] && k < R ? x[(size_t)ii[u] * R + k] : sc_zero(T());
+                    }
                     pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
-                    xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
                 }
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     int xi, yi;
                     reduce(pi[u], xi, yi);
                     if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
-                    T w;
-                    if (R == 1) {
-                        w = sc_mul(xv[u], yv[u]);
-                    } else {
-                        // several roots: the partner's y_k from memory
-                        const uint2 mjt = make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16);
-                        w = sc_zero(T());
-                        for (int k = 0; k < R; k++)
-                            w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
-                    }
+                    const T w = pair_w<CPLX, RM, RY>(xv[u], yv[u], x, ket, R, ii[u],
+                                                      make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16), W);
                     lds_add(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w);
                 }
             }
@@ -297,14 +314,15 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
             const bool ok = e < ch.w;
             const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
             const uint32_t j0 = en.x, jo = en.y & 0xffffu, L = en.y >> 16;
-            uint32_t dj = 0u;
-            const T y = ok ? entry_y<CPLX>(p, R, ket, W, e, dj) : sc_zero(T());
+            const uint32_t dj = ok ? p.rdm_ent_det[e] : 0u;
+            T y[RY];
+            partner_ys<CPLX, RY>(ket, R, make_uint2(dj & 0x7fffffffu, (dj >> 31) << 16), W, ok, y);
             const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
             const uint32_t incl = wave_incl_scan(cnt, lane);
             const uint32_t total = lane_get(incl, 63);
             for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
                 uint32_t pi[4], ii[4], djs[4];
-                T xv[4], yv[4];
+                T xv[4][RY], yv[4][RY];
                 bool act[4];
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
@@ -313,24 +331,20 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
                     const int t = visit_entry(incl, v);
                     ii[u] = lane_from(j0, t) + (v - (lane_from(incl, t) - lane_from(cnt, t)));
                     djs[u] = lane_from(dj, t);
-                    yv[u] = lane_from(y, t);
+#pragma unroll
+                    for (int k = 0; k < RY; k++) {
+                        yv[u][k] = lane_from(y[k], t);
+                        xv[u][k] = act[u] && k < R ? x[(size_t)ii[u] * R + k] : sc_zero(T());
+                    }
                     pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
-                    xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
                 }
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     int xi, yi;
                     reduce(pi[u], xi, yi);
                     if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
-                    T w;
-                    if (R == 1) {
-                        w = sc_mul(xv[u], yv[u]);
-                    } else {
-                        const uint2 mjt = make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16);
-                        w = sc_zero(T());
-                        for (int k = 0; k < R; k++)
-                            w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
-                    }
+                    const T w = pair_w<CPLX, RM, RY>(xv[u], yv[u], x, ket, R, ii[u],
+                                                      make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16), W);
                     lds_add(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w);
                 }
             }
@@ -464,7 +478,7 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
 // entries to copy 0 of the accumulators.  Per pair the same terms as
 // rdm_single_pair: S, then the positions where the group's string K and
 // the reference omega differ.
-template <bool CPLX, bool SYM>
+template <bool CPLX, bool SYM, int RM>
 __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
                                                          const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
                                                          typename Scal<CPLX>::T *__restrict__ S,
@@ -472,6 +486,7 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
                                                          double *__restrict__ Ee, int64_t c0)
 {
     using T = typename Scal<CPLX>::T;
+    constexpr int RY = RM == 4 ? 4 : 1;
     extern __shared__ __align__(16) double rdm_lds_raw[];
     const int n = p.n, M = p.M;
     const int nS = CPLX ? M : 2 * n, nC = CPLX ? M * M : n * n;
@@ -493,14 +508,15 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
         const uint32_t g = ok ? p.mem_grp[jj] : 0u;
         const uint64_t k0 = ok ? p.grp_key[2 * (size_t)g] : 0ULL, k1 = ok ? p.grp_key[2 * (size_t)g + 1] : 0ULL;
         const uint32_t sb = ok && p.grp_type[g] == G_SINGLE_B ? 1u : 0u;
-        const T y = ok ? rdm_y<CPLX>(ket, R, 0, mj, W) : sc_zero(T());
+        T y[RY];
+        partner_ys<CPLX, RY>(ket, R, mj, W, ok, y);
         const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
         const uint32_t incl = wave_incl_scan(cnt, lane);
         const uint32_t total = lane_get(incl, 63);
         for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
             uint32_t pi[4], pj[4], ii[4], dj[4], sp[4];
             uint64_t kk0[4], kk1[4];
-            T xv[4], yv[4];
+            T xv[4][RY], yv[4][RY];
             bool act[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
@@ -513,23 +529,18 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
                 sp[u] = lane_from(sb, t);
                 kk0[u] = lane_from(k0, t);
                 kk1[u] = lane_from(k1, t);
-                yv[u] = lane_from(y, t);
+#pragma unroll
+                for (int k = 0; k < RY; k++) {
+                    yv[u][k] = lane_from(y[k], t);
+                    xv[u][k] = act[u] && k < R ? x[(size_t)ii[u] * R + k] : sc_zero(T());
+                }
                 pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
-                xv[u] = act[u] ? x[(size_t)ii[u] * R] : sc_zero(T());
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const int Xi = pi[u] & 255, Xj = pj[u] & 255;
                 if (!act[u] || Xi == Xj) continue;
-                T w;
-                if (R == 1) {
-                    w = sc_mul(xv[u], yv[u]);
-                } else {
-                    const uint2 mjt = make_uint2(dj[u], pj[u]);
-                    w = sc_zero(T());
-                    for (int k = 0; k < R; k++)
-                        w = sc_add(w, sc_mul(x[(size_t)ii[u] * R + k], rdm_y<CPLX>(ket, R, k, mjt, W)));
-                }
+                const T w = pair_w<CPLX, RM, RY>(xv[u], yv[u], x, ket, R, ii[u], make_uint2(dj[u], pj[u]), W);
                 if constexpr (!CPLX) {
                     const int s = (int)sp[u], pp = Xi - s * n;
                     lds_add(&lS[s * n + pp], w);
@@ -834,7 +845,12 @@ static mw_status launch_rdm_single_rows(const DevPlan &p, int R, const typename 
     if (lds <= 160 * 1024) {
         const int64_t c0 = p.rdm_cls[4], nch = p.rdm_cls[5] - c0;
         if (nch <= 0) return MW_OK;
-        auto kern = sym ? k_rdm_single_rows<CPLX, true> : k_rdm_single_rows<CPLX, false>;
+        auto pick = [&](auto rm) {
+            constexpr int RM = decltype(rm)::value;
+            return sym ? k_rdm_single_rows<CPLX, true, RM> : k_rdm_single_rows<CPLX, false, RM>;
+        };
+        auto kern = R == 1 ? pick(std::integral_constant<int, 1>{})
+                           : (R <= 4 ? pick(std::integral_constant<int, 4>{}) : pick(std::integral_constant<int, 0>{}));
         if (lds > 65536 &&
             hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return fail(MW_EHIP, "hipFuncSetAttribute failed");
@@ -869,8 +885,13 @@ static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CP
         const size_t lds = (size_t)ncols * sizeof(T);
         if (lds > 160 * 1024) return fail(MW_EUNSUPPORTED, "density-matrix row exceeds the LDS of a workgroup");
         const bool wide = (c & 1) == 0;
-        auto kern = sym ? (wide ? k_rdm_rows<CPLX, true, true> : k_rdm_rows<CPLX, true, false>)
-                        : (wide ? k_rdm_rows<CPLX, false, true> : k_rdm_rows<CPLX, false, false>);
+        auto pick = [&](auto rm) {
+            constexpr int RM = decltype(rm)::value;
+            return sym ? (wide ? k_rdm_rows<CPLX, true, true, RM> : k_rdm_rows<CPLX, true, false, RM>)
+                       : (wide ? k_rdm_rows<CPLX, false, true, RM> : k_rdm_rows<CPLX, false, false, RM>);
+        };
+        auto kern = R == 1 ? pick(std::integral_constant<int, 1>{})
+                           : (R <= 4 ? pick(std::integral_constant<int, 4>{}) : pick(std::integral_constant<int, 0>{}));
         if (lds > 65536 &&
             hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return fail(MW_EHIP, "hipFuncSetAttribute failed");

@@ -102,6 +102,29 @@ def test_rdm_transition_weighted_roots(torch):
     assert _rel(g1, r1) <= TOL and _rel(g2, r2) <= TOL
 
 
+@pytest.mark.parametrize("kind,nroots", [("spinfree", 4), ("spinfree", 6), ("spinor", 4), ("spinor", 5)])
+def test_rdm_many_roots(torch, kind, nroots):
+    """Weighted roots with the partner's coefficients of up to four roots
+    held in registers (4) and read per pair (more than four): one vector as
+    bra and ket and a separate ket, against the oracle (1e-12)."""
+    if kind == "spinfree":
+        p = synth.workload(4)
+        c = synth.ci_vectors(p.ndet, nroots, np.random.default_rng(21))
+        k = synth.ci_vectors(p.ndet, nroots, np.random.default_rng(22))
+    else:
+        p = _spinor_problem(8, 6, 2000, 3)
+        c = synth.ci_vectors(p.ndet, nroots, np.random.default_rng(21), complex_=True)
+        k = synth.ci_vectors(p.ndet, nroots, np.random.default_rng(22), complex_=True)
+    pl = _plan(p, max_roots=nroots)
+    w = list(np.linspace(0.9, 0.1, nroots))
+    cd = _dev(torch, c)
+    for ket, ket_d in ((c, cd), (k, _dev(torch, k))):
+        g1, g2 = (x.cpu().numpy() for x in pl.rdm(cd, ket_d, weights=w))
+        r1, r2 = sc.rdm(p, c, ket, weights=w)
+        _say(kind, nroots, _rel(g1, r1), _rel(g2, r2))
+        assert _rel(g1, r1) <= TOL and _rel(g2, r2) <= TOL
+
+
 def test_rdm_spinor(torch):
     """Complex spinor space (8 pairs, N=6): transition RDMs over spinors."""
     p = _spinor_problem(8, 6, 2000, 3)
