@@ -738,32 +738,61 @@ static mw_status build_rdm_rows(HostPlan &P)
             key[j] = (uint32_t)(row * NC + (L >= (uint32_t)RDM_WIDE ? 0 : L));
         }
     });
-    std::vector<int64_t> start((size_t)(nrow * NC + 1), 0);
-    for (int64_t j = 0; j < nmem; j++)
-        if (key[j] != 0xffffffffu) start[key[j] + 1]++;
-    for (size_t k = 1; k < start.size(); k++) start[k] += start[k - 1];
+    // stable counting sort by key, in parallel: per-thread counts over the
+    // contiguous membership ranges of parallel_for, then each thread
+    // scatters its range from its own offsets (membership order kept)
+    const int64_t nbin = nrow * NC;
+    const unsigned T = n_threads();
+    std::vector<uint32_t> cnt((size_t)T * nbin, 0);
+    std::atomic<bool> too_large{false};
+    parallel_for(nmem, [&](int64_t b0, int64_t b1, unsigned t) {
+        uint32_t *c = cnt.data() + (size_t)t * nbin;
+        for (int64_t j = b0; j < b1; j++) {
+            if (key[j] == 0xffffffffu) continue;
+            c[key[j]]++;
+            const uint32_t g = P.mem_grp[j];
+            if (P.grp_off[g + 1] - P.grp_off[g] >= 65536) too_large = true;
+        }
+    });
+    if (too_large) return fail(MW_EUNSUPPORTED, "group too large for the density rows");
+    std::vector<int64_t> start((size_t)(nbin + 1), 0);
+    {
+        int64_t acc = 0;
+        for (int64_t b = 0; b < nbin; b++) {
+            start[b] = acc;
+            for (unsigned t = 0; t < T; t++) {
+                const uint32_t c = cnt[(size_t)t * nbin + b];
+                cnt[(size_t)t * nbin + b] = (uint32_t)acc;  // this thread's first slot in bin b
+                acc += c;
+                if (acc > 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many memberships for the density rows");
+            }
+        }
+        start[nbin] = acc;
+    }
     const int64_t nent = start.back();
-    if (nent > 0xffffffffLL) return fail(MW_EUNSUPPORTED, "too many memberships for the density rows");
     if (P.ndet >= (int64_t)1 << 31) return fail(MW_EUNSUPPORTED, "too many determinants for the density rows");
     P.rdm_ent.resize((size_t)nent);
     P.rdm_ent_det.resize((size_t)nent);
-    {
-        std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t j = 0; j < nmem; j++) {
+    parallel_for(nmem, [&](int64_t b0, int64_t b1, unsigned t) {
+        uint32_t *fill = cnt.data() + (size_t)t * nbin;
+        for (int64_t j = b0; j < b1; j++) {
             if (key[j] == 0xffffffffu) continue;
             const uint32_t g = P.mem_grp[j];
             const uint32_t j0 = P.grp_off[g], L = P.grp_off[g + 1] - j0;
-            if (L >= 65536) return fail(MW_EUNSUPPORTED, "group too large for the density rows");
             const int64_t e = fill[key[j]]++;
             P.rdm_ent[e] = make_uint2(j0, (uint32_t)(j - j0) | (L << 16));
             // the partner's determinant and sign (bit 31)
             P.rdm_ent_det[e] = P.mem[j].x | (((P.mem[j].y >> 16) & 1u) << 31);
         }
-    }
+    });
+    cnt.clear();
+    cnt.shrink_to_fit();
     key.clear();
     key.shrink_to_fit();
     P.rdm_pos.resize((size_t)nmem);
-    for (int64_t j = 0; j < nmem; j++) P.rdm_pos[j] = (uint16_t)(P.mem[j].y & 0xffffu);
+    parallel_for(nmem, [&](int64_t b0, int64_t b1, unsigned) {
+        for (int64_t j = b0; j < b1; j++) P.rdm_pos[j] = (uint16_t)(P.mem[j].y & 0xffffu);
+    });
     struct Ch {
         uint4 c;
         int64_t work;
