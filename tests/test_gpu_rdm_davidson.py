@@ -125,6 +125,44 @@ def test_rdm_many_roots(torch, kind, nroots):
         assert _rel(g1, r1) <= TOL and _rel(g2, r2) <= TOL
 
 
+def test_rdm_spinor_rows_beyond_64k_lds(torch):
+    """Spinor space of 102 spinors, two electrons (all 5,151 determinants):
+    one double group of 5,151 members whose pair rows (5,151 complex
+    entries, 82 KB) need more than 64 KB of LDS per workgroup, and single
+    rows (102 + 102^2 complex entries, 168 KB) that exceed a workgroup's
+    LDS and take the per-pair atomic kernel instead.  The density matrices
+    do not depend on the integrals (zero two-electron integrals here).  The
+    bra is supported on 300 sampled rows (so the oracle sums over those
+    rows only); one vector as bra and ket, and a separate full ket, two
+    weighted roots, against the oracle."""
+    nk = 51
+    M = 2 * nk
+    dets = []
+    for a in range(M):
+        for b in range(a + 1, M):
+            w = [0, 0]
+            for x in (a, b):
+                w[x // nk] |= 1 << (x % nk)
+            dets.append(w)
+    dets.sort(key=lambda d: (d[0], d[1]))
+    h = np.diag(np.linspace(-2.0, 1.0, M)).astype(np.complex128)
+    g = np.zeros((M, M, M, M), np.complex128)
+    p = synth.Problem("spinor", nk, 2, -1, np.array(dets, np.uint64), h, g, 0.0)
+    pl = _plan(p, max_roots=2)
+    rows = np.sort(np.random.default_rng(5).choice(p.ndet, 300, replace=False))
+    c = np.zeros((p.ndet, 2), np.complex128)
+    c[rows] = synth.ci_vectors(p.ndet, 2, np.random.default_rng(31), complex_=True)[rows]
+    k = synth.ci_vectors(p.ndet, 2, np.random.default_rng(32), complex_=True)
+    w = [0.75, 0.25]
+    cd = _dev(torch, c)
+    for ket, ket_d in ((c, cd), (k, _dev(torch, k))):
+        g1, g2 = (x.cpu().numpy() for x in pl.rdm(cd, ket_d, weights=w))
+        r1, r2 = sc.rdm(p, c, ket, weights=w, rows=rows)
+        _say("spinor M=102", _rel(g1, r1), _rel(g2, r2))
+        assert _rel(g1, r1) <= TOL and _rel(g2, r2) <= TOL
+        del g1, g2, r1, r2
+
+
 def test_rdm_spinor(torch):
     """Complex spinor space (8 pairs, N=6): transition RDMs over spinors."""
     p = _spinor_problem(8, 6, 2000, 3)
