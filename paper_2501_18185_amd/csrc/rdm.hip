@@ -231,6 +231,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
 {
     using T = typename Scal<CPLX>::T;
     constexpr int RY = RM == 4 ? 4 : 1;
+    constexpr int UW = 8, US = 4;  // steps of 64 visits in flight per wave (wide, small)
     extern __shared__ __align__(16) double rdm_lds_raw[];
     T *row = (T *)rdm_lds_raw;
     const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
     if constexpr (WIDE) {
         // groups of RDM_WIDE members or more: a wave loads the records of 64
         // entries (a lane each), then walks their members in steps of 64
-        // (a member per lane), four steps in flight
+        // (a member per lane), UW steps in flight
         for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += stride) {
             const uint32_t e = base + lane;
             const bool ok = e < ch.w;
@@ -273,12 +274,12 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
             // inclusive prefix of the step counts over the lanes
             const uint32_t incl = wave_incl_scan(nb, lane);
             const uint32_t total = lane_get(incl, 63);
-            for (uint32_t s0 = 0; s0 < total; s0 += 4) {
-                uint32_t pi[4], ii[4], djs[4];
-                T xv[4][RY], yv[4][RY];
-                bool act[4];
+            for (uint32_t s0 = 0; s0 < total; s0 += UW) {
+                uint32_t pi[UW], ii[UW], djs[UW];
+                T xv[UW][RY], yv[UW][RY];
+                bool act[UW];
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < UW; u++) {
                     const uint32_t st = s0 + u;
                     // the entry of step st: the lanes whose inclusive prefix
                     // is <= st come before it
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
                     pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < UW; u++) {
                     int xi, yi;
                     reduce(pi[u], xi, yi);
                     if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
@@ -308,24 +309,34 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
         }
     } else {
         // smaller groups: the visits of 64 entries (a lane each) are walked
-        // by the lanes together, 64 at a time, four steps in flight
+        // by the lanes together, 64 at a time, US steps in flight
         for (uint32_t base = ch.z + 64u * wv; base < ch.w; base += stride) {
             const uint32_t e = base + lane;
             const bool ok = e < ch.w;
             const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
             const uint32_t j0 = en.x, jo = en.y & 0xffffu, L = en.y >> 16;
-            const uint32_t dj = ok ? p.rdm_ent_det[e] : 0u;
-            T y[RY];
-            partner_ys<CPLX, RY>(ket, R, make_uint2(dj & 0x7fffffffu, (dj >> 31) << 16), W, ok, y);
+            const uint32_t dj = ok && !(SYM && RM == 1) ? p.rdm_ent_det[e] : 0u;
             const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
+            T y[RY];
+            if (SYM && RM == 1) {
+                // one vector, one root: y_j = w_0 conj(x_j), read from the
+                // lines of the members it pairs with (no determinant gather);
+                // entries without visits read nothing
+                const double w0 = W.dev ? W.dev[0] : W.w[0];
+                const T xj = cnt ? sc_conj(x[j0 + jo]) : sc_zero(T());
+                if constexpr (CPLX) y[0] = make_double2(w0 * xj.x, w0 * xj.y);
+                else y[0] = w0 * xj;
+            } else {
+                partner_ys<CPLX, RY>(ket, R, make_uint2(dj & 0x7fffffffu, (dj >> 31) << 16), W, ok, y);
+            }
             const uint32_t incl = wave_incl_scan(cnt, lane);
             const uint32_t total = lane_get(incl, 63);
-            for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
-                uint32_t pi[4], ii[4], djs[4];
-                T xv[4][RY], yv[4][RY];
-                bool act[4];
+            for (uint32_t v0 = 0; v0 < total; v0 += 64u * US) {
+                uint32_t pi[US], ii[US], djs[US];
+                T xv[US][RY], yv[US][RY];
+                bool act[US];
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < US; u++) {
                     const uint32_t v = v0 + 64u * u + lane;
                     act[u] = v < total;
                     const int t = visit_entry(incl, v);
@@ -339,7 +350,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
                     pi[u] = act[u] ? (uint32_t)p.rdm_pos[ii[u]] : 0u;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < US; u++) {
                     int xi, yi;
                     reduce(pi[u], xi, yi);
                     if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
