@@ -161,6 +161,15 @@ mw_status mw_sigma_batched_direct(int32_t nprob, const mw_plan *plans, const int
 mw_status mw_autotune(mw_plan plan, int32_t nroots, const void *c, void *sigma, mw_stream_t stream,
                       int32_t *choice);
 
+/* The launch parameters of mw_sigma as one code, unroll * 100 + lanes (the
+ * value mw_autotune reports), so that a tuned choice can be kept with the
+ * problem and restored without timing again: mw_plan_get_tuning writes the
+ * plan's current code to *code (host), mw_plan_set_tuning sets it (unroll
+ * 4, 8 or 16, 16 for real plans only; lanes 8, 16 or 32; MW_EINVAL
+ * otherwise).  Host only; results do not depend on the choice. */
+mw_status mw_plan_get_tuning(mw_plan plan, int32_t *code);
+mw_status mw_plan_set_tuning(mw_plan plan, int32_t code);
+
 /* Autotuner for mw_sigma_batched: times the flat grid and persistent grids
  * of 1, 2, 4, 8, 16 blocks per compute unit, a partner unroll of 4 or 8 for
  * four-root passes and a gather width of 8, 16 or 32 lanes per determinant,

@@ -1261,6 +1261,30 @@ __attribute__((visibility("hidden"))) int mw_internal_space(mw_plan plan, const 
     return 1;
 }
 
+mw_status mw_plan_get_tuning(mw_plan plan, int32_t *code)
+{
+    if (!plan || !code) return fail(MW_EINVAL, "NULL argument");
+    const HostPlan &P = plan->p;
+    const int gl = P.tune_gl ? P.tune_gl : (P.kind == MW_SPINOR ? 32 : 16);
+    *code = P.tune_u * 100 + gl;
+    return MW_OK;
+}
+
+mw_status mw_plan_set_tuning(mw_plan plan, int32_t code)
+{
+    if (!plan) return fail(MW_EINVAL, "plan is NULL");
+    const int u = code / 100, gl = code % 100;
+    if ((u != 4 && u != 8 && u != 16) || (gl != 8 && gl != 16 && gl != 32))
+        return fail(MW_EINVAL, "tuning code must be unroll*100+lanes, unroll 4/8/16, lanes 8/16/32");
+    if (u == 16 && plan->p.kind == MW_SPINOR) return fail(MW_EINVAL, "unroll 16 is for real plans only");
+    HostPlan &P = plan->p;
+    P.tune_u = u;
+    P.tune_gl = gl;
+    P.dev.tune_u = u;
+    P.dev.tune_gl = gl;
+    return MW_OK;
+}
+
 // set the tunables (host copy; the device copy keeps the upload values,
 // which only the batched kernels read and they do not use these fields)
 __attribute__((visibility("hidden"))) void mw_internal_set_tune(mw_plan plan, int32_t u, int32_t gl)

@@ -74,6 +74,8 @@ def lib():
         L.mw_sigma_batched_direct.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp),
                                               i32, vp]
         L.mw_autotune.argtypes = [vp, i32, vp, vp, vp, C.POINTER(i32)]
+        L.mw_plan_get_tuning.argtypes = [vp, C.POINTER(i32)]
+        L.mw_plan_set_tuning.argtypes = [vp, i32]
         L.mw_autotune_batched.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), vp,
                                           C.POINTER(i32)]
         L.mw_profile.argtypes = [i32]
@@ -112,6 +114,7 @@ def lib():
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
                      "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched",
                      "mw_pt2_work_bytes", "mw_pt2", "mw_select", "mw_energy", "mw_energy_backward",
+                     "mw_plan_get_tuning", "mw_plan_set_tuning",
                      "mw_sigma_backward", "mw_energy_batched", "mw_energy_backward_batched"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -188,6 +191,18 @@ class Plan:
             h = np.ascontiguousarray(np.real(h), dtype=np.float64)
             g = np.ascontiguousarray(np.real(g), dtype=np.float64)
         _check(lib().mw_plan_update_integrals(self._plan, h.ctypes.data, g.ctypes.data, float(ecore), _stream()))
+
+    @property
+    def tuning(self) -> int:
+        """Launch parameters of sigma as unroll * 100 + gather lanes (the
+        autotuner's code); assign a saved code to restore a tuned choice."""
+        v = C.c_int32()
+        _check(lib().mw_plan_get_tuning(self._plan, C.byref(v)))
+        return v.value
+
+    @tuning.setter
+    def tuning(self, code: int):
+        _check(lib().mw_plan_set_tuning(self._plan, int(code)))
 
     def autotune(self, c, out=None):
         """Pick the fastest launch parameters for this plan; returns the choice code."""

@@ -127,3 +127,21 @@ def test_ivi_needs_uploaded_plan():
     it = C.c_int32()
     assert mw.lib().mw_ivi(pl._plan, 1, float("nan"), C.c_void_p(16), C.c_void_p(32), ev, 1e-8, 10, C.byref(it),
                            C.c_void_p(256), 1 << 20, None) == -5
+
+
+def test_tuning_code_round_trip():
+    """The sigma launch parameters are read and restored as one code
+    (unroll * 100 + lanes) on the host; invalid codes are refused."""
+    from paper_2501_18185_amd import mw
+    pl = mw.Plan(synth.workload(0), upload=False)
+    assert pl.tuning == 416  # defaults: unroll 4, 16 gather lanes (real)
+    for code in (408, 816, 1632):
+        pl.tuning = code
+        assert pl.tuning == code
+    for bad in (0, 316, 412, 1664, 2016):
+        with pytest.raises(mw.MWError):
+            pl.tuning = bad
+    assert pl.tuning == 1632
+    q = mw.Plan(synth.workload(0), upload=False)
+    q.tuning = pl.tuning  # a saved choice restored on another plan
+    assert q.tuning == 1632
