@@ -204,16 +204,60 @@ class Plan:
     def tuning(self, code: int):
         _check(lib().mw_plan_set_tuning(self._plan, int(code)))
 
-    def autotune(self, c, out=None):
-        """Pick the fastest launch parameters for this plan; returns the choice code."""
+    def tuning_key(self, nroots: int, arch: str) -> str:
+        """Key of this plan's tuned launch parameters in a tuning cache: the
+        GPU architecture and the shape of the product (kind, orbitals,
+        determinants, connected pairs, roots)."""
+        kind = "spinor" if self.is_complex else "spinfree"
+        return f"{arch}|{kind}|n{self.norb}|d{self.ndet}|p{self.info('pairs')}|r{int(nroots)}"
+
+    def load_tuning(self, cache: str, nroots: int, arch: str) -> bool:
+        """Apply the code stored for this plan in the JSON file ``cache``;
+        False when the file or the key is absent."""
+        import json
+        try:
+            with open(cache) as f:
+                code = json.load(f).get(self.tuning_key(nroots, arch))
+        except (OSError, ValueError):
+            return False
+        if code is None:
+            return False
+        self.tuning = int(code)
+        return True
+
+    def save_tuning(self, cache: str, nroots: int, arch: str):
+        """Store this plan's current code in the JSON file ``cache`` (other
+        keys kept)."""
+        import json
+        try:
+            with open(cache) as f:
+                data = json.load(f)
+        except (OSError, ValueError):
+            data = {}
+        data[self.tuning_key(nroots, arch)] = self.tuning
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+
+    def autotune(self, c, out=None, cache: Optional[str] = None):
+        """Pick the fastest launch parameters for this plan; returns the
+        choice code.  With ``cache`` (a JSON file) a choice stored for this
+        architecture and shape is applied without timing, and a new one is
+        stored."""
         torch = _require_gpu()
         c = self._vec(c)
         nroots = 1 if c.dim() == 1 else c.shape[1]
+        arch = torch.cuda.get_device_properties(c.device).gcnArchName.split(":")[0] if cache else ""
+        if cache and self.load_tuning(cache, nroots, arch):
+            return self.tuning
         if out is None:
             out = torch.empty_like(c)
         ch = C.c_int32()
         _check(lib().mw_autotune(self._plan, nroots, C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()),
                                  _stream(), C.byref(ch)))
+        if cache:
+            self.save_tuning(cache, nroots, arch)
         return ch.value
 
     def close(self):

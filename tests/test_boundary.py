@@ -145,3 +145,20 @@ def test_tuning_code_round_trip():
     q = mw.Plan(synth.workload(0), upload=False)
     q.tuning = pl.tuning  # a saved choice restored on another plan
     assert q.tuning == 1632
+
+
+def test_tuning_cache_file(tmp_path):
+    """A tuned code stored in a cache file under (architecture, shape) is
+    applied to a plan of the same shape and not to another shape."""
+    from paper_2501_18185_amd import mw
+    cache = str(tmp_path / "tuning.json")
+    a = mw.Plan(synth.workload(0), upload=False)
+    assert not a.load_tuning(cache, 1, "gfx950")
+    a.tuning = 832
+    a.save_tuning(cache, 1, "gfx950")
+    b = mw.Plan(synth.workload(0), upload=False)
+    assert b.load_tuning(cache, 1, "gfx950") and b.tuning == 832
+    assert not b.load_tuning(cache, 2, "gfx950")   # other root count
+    assert not b.load_tuning(cache, 1, "gfx942")   # other architecture
+    other = mw.Plan(synth.workload(4), upload=False)
+    assert not other.load_tuning(cache, 1, "gfx950")

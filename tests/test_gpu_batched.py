@@ -148,6 +148,25 @@ def test_plain_autotune_keeps_accuracy(torch):
     assert _rel(pl.sigma(c).cpu().numpy(), sc.sigma(p, c.cpu().numpy())) <= 1e-12
 
 
+def test_autotune_cache_round_trip(torch, tmp_path):
+    """autotune(cache=...) stores the choice under the GPU architecture and
+    shape; a second plan of the same space takes it from the file."""
+    import json
+
+    from paper_2501_18185_amd import mw
+    p = synth.workload(0)
+    cache = str(tmp_path / "tune.json")
+    pl = mw.Plan(p, max_roots=2)
+    c = torch.from_numpy(synth.ci_vectors(p.ndet, 2, np.random.default_rng(3))).cuda()
+    first = pl.autotune(c, cache=cache)
+    data = json.load(open(cache))
+    assert list(data.values()) == [first] and list(data)[0].startswith("gfx")
+    q = mw.Plan(p, max_roots=2)
+    q.tuning = 416 if first != 416 else 832
+    assert q.autotune(c, cache=cache) == first and q.tuning == first
+    assert _rel(q.sigma(c).cpu().numpy(), sc.sigma(p, c.cpu().numpy())) <= 1e-12
+
+
 def test_batched_rejects_bad_arguments(torch, batch):
     from paper_2501_18185_amd import mw
     probs, plans, cs, R = batch
