@@ -81,6 +81,11 @@ struct DevPlan {
     const uint4 *rdm_chunk;
     const uint16_t *rdm_pos;
     const uint32_t *rdm_ent_det;
+    // entries [rdm_single_e0, end) are single memberships: their group's
+    // string K in rdm_skey[e - rdm_single_e0], and bit 15 of the entry's
+    // second word set for a beta (spin-free) group
+    const ulonglong2 *rdm_skey;
+    int64_t rdm_single_e0;
     int64_t rdm_cls[6];
     void *partial;             // [nmem][R] per-membership partial sums, member order (also RDM accumulators)
     size_t scratch_bytes;

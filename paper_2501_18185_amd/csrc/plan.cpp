@@ -153,6 +153,8 @@ struct HostPlan {
     std::vector<uint4> rdm_chunk;
     std::vector<uint16_t> rdm_pos;
     std::vector<uint32_t> rdm_ent_det;
+    std::vector<ulonglong2> rdm_skey;
+    int64_t rdm_single_e0 = 0;
     int64_t rdm_cls[6] = {0, 0, 0, 0, 0, 0};
     // launch defaults until mw_autotune picks its own: partner-loop unroll 4,
     // 16 gather lanes (32 for complex), the fastest measured on the n = 64
@@ -709,6 +711,8 @@ static mw_status build_rdm_rows(HostPlan &P)
     P.rdm_chunk.clear();
     P.rdm_pos.clear();
     P.rdm_ent_det.clear();
+    P.rdm_skey.clear();
+    P.rdm_single_e0 = 0;
     for (auto &c : P.rdm_cls) c = 0;
     const int64_t nmd = P.npacket_double > 0 ? (int64_t)P.pk_off[P.npacket_double] : 0;
     const int64_t nmem = (int64_t)P.mem.size();
@@ -787,6 +791,18 @@ static mw_status build_rdm_rows(HostPlan &P)
     });
     cnt.clear();
     cnt.shrink_to_fit();
+    // single entries (the rows after the double rows): the group's string K
+    // and the spin of a spin-free group, so the kernel reads no group table
+    P.rdm_single_e0 = start[nrow_d * NC];
+    P.rdm_skey.resize((size_t)(nent - P.rdm_single_e0));
+    parallel_for(nent - P.rdm_single_e0, [&](int64_t b0, int64_t b1, unsigned) {
+        for (int64_t t = b0; t < b1; t++) {
+            uint2 &en = P.rdm_ent[P.rdm_single_e0 + t];
+            const uint32_t g = P.mem_grp[en.x];
+            P.rdm_skey[t] = make_ulonglong2(P.grp_key[2 * (size_t)g], P.grp_key[2 * (size_t)g + 1]);
+            if (P.grp_type[g] == G_SINGLE_B) en.y |= 1u << 15;
+        }
+    });
     key.clear();
     key.shrink_to_fit();
     P.rdm_pos.resize((size_t)nmem);
@@ -1041,6 +1057,8 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.rdm_chunk = (const uint4 *)take(rdm_chunk.size() * 16);
     t.rdm_pos = (const uint16_t *)take(rdm_pos.size() * 2);
     t.rdm_ent_det = (const uint32_t *)take(rdm_ent_det.size() * 4);
+    t.rdm_skey = (const ulonglong2 *)take(rdm_skey.size() * 16);
+    t.rdm_single_e0 = rdm_single_e0;
     for (int c = 0; c < 6; c++) t.rdm_cls[c] = rdm_cls[c];
     // per-call scratch: sigma partials, or the density-matrix accumulators
     // (double pairs, RDM_COPIES copies of S and the single corrections (n^3
@@ -1155,7 +1173,8 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
               up(d.rdm_ent, P.rdm_ent.data(), P.rdm_ent.size() * 8) &&
               up(d.rdm_chunk, P.rdm_chunk.data(), P.rdm_chunk.size() * 16) &&
               up(d.rdm_pos, P.rdm_pos.data(), P.rdm_pos.size() * 2) &&
-              up(d.rdm_ent_det, P.rdm_ent_det.data(), P.rdm_ent_det.size() * 4);
+              up(d.rdm_ent_det, P.rdm_ent_det.data(), P.rdm_ent_det.size() * 4) &&
+              up(d.rdm_skey, P.rdm_skey.data(), P.rdm_skey.size() * 16);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
     if (hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");

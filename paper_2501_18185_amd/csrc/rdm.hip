@@ -513,15 +513,26 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
         const uint32_t e = base + lane;
         const bool ok = e < ch.w;
         const uint2 en = ok ? p.rdm_ent[e] : make_uint2(0u, 0u);
-        const uint32_t j0 = en.x, jo = en.y & 0xffffu, L = en.y >> 16;
-        const uint32_t jj = j0 + jo;
-        const uint2 mj = ok ? p.mem[jj] : make_uint2(0u, 0u);
-        const uint32_t g = ok ? p.mem_grp[jj] : 0u;
-        const uint64_t k0 = ok ? p.grp_key[2 * (size_t)g] : 0ULL, k1 = ok ? p.grp_key[2 * (size_t)g + 1] : 0ULL;
-        const uint32_t sb = ok && p.grp_type[g] == G_SINGLE_B ? 1u : 0u;
-        T y[RY];
-        partner_ys<CPLX, RY>(ket, R, mj, W, ok, y);
+        const uint32_t j0 = en.x, jo = en.y & 0x7fffu, L = en.y >> 16;
+        const uint32_t sb = (en.y >> 15) & 1u;
         const uint32_t cnt = ok ? (SYM ? jo : L) : 0u;
+        // the entry carries the group's string, the spin and the partner's
+        // determinant; the partner's position is the row's
+        const ulonglong2 kk = ok ? p.rdm_skey[e - p.rdm_single_e0] : make_ulonglong2(0ULL, 0ULL);
+        const uint64_t k0 = kk.x, k1 = kk.y;
+        const uint32_t dj = ok && !(SYM && RM == 1) ? p.rdm_ent_det[e] : 0u;
+        const uint2 mj = make_uint2(dj & 0x7fffffffu, ((dj >> 31) << 16) | (uint32_t)(q + (CPLX ? 0 : (int)sb * n)));
+        T y[RY];
+        if (SYM && RM == 1) {
+            // one vector, one root: y_j = w_0 conj(x_j) from the lines of the
+            // members it pairs with
+            const double w0 = W.dev ? W.dev[0] : W.w[0];
+            const T xj = cnt ? sc_conj(x[j0 + jo]) : sc_zero(T());
+            if constexpr (CPLX) y[0] = make_double2(w0 * xj.x, w0 * xj.y);
+            else y[0] = w0 * xj;
+        } else {
+            partner_ys<CPLX, RY>(ket, R, mj, W, ok, y);
+        }
         const uint32_t incl = wave_incl_scan(cnt, lane);
         const uint32_t total = lane_get(incl, 63);
         for (uint32_t v0 = 0; v0 < total; v0 += 256u) {
