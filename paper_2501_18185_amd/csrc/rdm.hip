@@ -617,23 +617,35 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
 // determinant chunk, reduced in a fixed order.
 constexpr int RDM_OCC_CHUNKS = 256;
 
+// position of the k-th (from 0) set bit of w, k < popcount(w): the largest
+// p with at most k set bits below it (binary lifting over the bit index)
+__device__ __forceinline__ int nth_bit(uint64_t w, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step; step >>= 1)
+        if (__popcll(w & ((1ULL << (pos + step)) - 1)) <= k) pos += step;
+    return pos;
+}
+
 // Block (x, y) of 1024 threads adds w_I into an LDS copy of rows
-// [A0, A0 + ROWS) of D for every determinant of chunk x, each lane holding
-// B = lane, lane + 64 and the wave walking the occupied A of the
-// determinant (LDS atomics: the 16 waves take different determinants); then
-// it writes its rows of the chunk's partial matrix.
+// [A0, A0 + ROWS) of D for every determinant of chunk x, a wave per
+// determinant over its pairs of occupied positions (LDS atomics: the 16
+// waves take different determinants); then it writes its rows of the
+// chunk's partial matrix.
 template <bool CPLX>
 __global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                       const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
                                                       typename Scal<CPLX>::T *__restrict__ part)
 {
     using T = typename Scal<CPLX>::T;
-    constexpr int ROWS = CPLX ? 64 : 128;  // 128 KB of LDS
-    __shared__ T ds[ROWS * 128];
+    constexpr int ROWS = CPLX ? 64 : 128;
+    constexpr int MP = 129;  // LDS row stride: rows of one column fall in different banks (132 KB)
+    __shared__ T ds[ROWS * MP];
     const int n = p.n, M = p.M;
     const int A0 = (int)blockIdx.y * ROWS, A1 = min(M, A0 + ROWS);
     const int rows = A1 - A0;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) ds[t] = sc_zero(T());
+    for (int t = threadIdx.x; t < rows * MP; t += blockDim.x) ds[t] = sc_zero(T());
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int64_t chunk = (p.ndet + gridDim.x - 1) / gridDim.x;
@@ -649,9 +661,36 @@ __global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const ty
         m0 = d0 & range(min(A0, n), min(A1, n));
         m1 = d1 & range(max(A0 - n, 0), max(min(A1 - n, 64), 0));
     };
-    for (int64_t I = lo + wv; I < hi; I += nw) {
-        const uint64_t d0 = p.dets[2 * I], d1 = p.dets[2 * I + 1];
-        const T w = pair_weight<CPLX>(bra, ket, R, (uint32_t)I, (uint32_t)I, W);
+    // a wave takes 64 consecutive determinants at a time: each lane loads
+    // one determinant and its weight, then the wave walks them one by one
+    // (one memory round trip per 64 determinants)
+    for (int64_t Ib = lo + 64 * (int64_t)wv; Ib < hi; Ib += 64 * (int64_t)nw) {
+      const int64_t Il = Ib + lane;
+      const bool okl = Il < hi;
+      const uint64_t dl0 = okl ? p.dets[2 * Il] : 0ULL, dl1 = okl ? p.dets[2 * Il + 1] : 0ULL;
+      const T wl = okl ? pair_weight<CPLX>(bra, ket, R, (uint32_t)Il, (uint32_t)Il, W) : sc_zero(T());
+      const int cnt = (int)min<int64_t>(64, hi - Ib);
+      for (int tdet = 0; tdet < cnt; tdet++) {
+        const uint64_t d0 = ((uint64_t)lane_get((uint32_t)(dl0 >> 32), tdet) << 32) | lane_get((uint32_t)dl0, tdet);
+        const uint64_t d1 = ((uint64_t)lane_get((uint32_t)(dl1 >> 32), tdet) << 32) | lane_get((uint32_t)dl1, tdet);
+        const T w = lane_get(wl, tdet);
+        const int c0 = __popcll(d0), nocc = c0 + __popcll(d1);
+        if (nocc <= 64) {
+            // lane l holds the l-th occupied global position; the wave then
+            // adds w at every (A, B) pair of occupied positions, 64 pairs per
+            // instruction (instead of one instruction per A over all B)
+            int pos = 0;
+            if (lane < c0) pos = nth_bit(d0, lane);
+            else if (lane < nocc) pos = n + nth_bit(d1, lane - c0);
+            const int np2 = nocc * nocc;
+            for (int k0 = 0; k0 < np2; k0 += 64) {
+                const int k = k0 + lane;
+                const int a = k < np2 ? k / nocc : 0, b = k < np2 ? k - a * nocc : 0;
+                const int A = __shfl(pos, a, 64), B = __shfl(pos, b, 64);
+                if (k < np2 && A >= A0 && A < A1) atom_add(ds + (size_t)(A - A0) * MP + B, w);
+            }
+            continue;
+        }
         const int B0 = lane, B1 = lane + 64;
         const bool o0 = B0 < M && (B0 < n ? (d0 >> B0) & 1 : (d1 >> (B0 - n)) & 1);
         const bool o1 = B1 < M && (B1 < n ? (d0 >> B1) & 1 : (d1 >> (B1 - n)) & 1);
@@ -660,15 +699,16 @@ __global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const ty
         for (int word = 0; word < 2; word++) {
             for (uint64_t x = word ? m1 : m0; x; x &= x - 1) {
                 const int A = __builtin_ctzll(x) + (word ? n : 0);
-                T *row = ds + (size_t)(A - A0) * M;
+                T *row = ds + (size_t)(A - A0) * MP;
                 if (o0) atom_add(row + B0, w);
                 if (o1) atom_add(row + B1, w);
             }
         }
+      }
     }
     __syncthreads();
     T *out = part + (size_t)blockIdx.x * M * M + (size_t)A0 * M;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) out[t] = ds[t];
+    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) out[t] = ds[(t / M) * MP + t % M];
 }
 
 template <typename T>
