@@ -200,12 +200,21 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
     }
     const size_t colbase = (size_t)p.nmem + p.grp_col[g] + (size_t)a * k - 32 * (size_t)a * (a + 1);
     // passes of JS partners over the blocks b >= a (64 is a multiple of JS,
-    // so a pass never straddles two blocks); the partner records of the next
-    // pass (wave-uniform) are loaded while this pass runs
+    // so a pass never straddles two blocks), from the group's last pass down:
+    // since 64 is a multiple of JS, every block of the group starts at the
+    // same pass and the blocks walk the same partners at about the same
+    // time, so the partner records and coefficients one block reads are in
+    // L2 for the others (spinor sigma 11.5 -> 11.2 ms; the real space
+    // 9.59 -> 9.49 ms in the same run).  The partner records of the next
+    // pass (wave-uniform) are loaded while this pass runs.
+    const uint32_t jfirst = j0 + 64 * a;
+    const uint32_t jlast = jfirst + (j1 - 1 - jfirst) / JS * JS;  // start of the last pass
     uint2 onext[JS];
 #pragma unroll
-    for (int u = 0; u < JS; u++) onext[u] = p.mem[min(j0 + 64 * a + u, j1 - 1)];
-    for (uint32_t jj = j0 + 64 * a; jj < j1; jj += JS) {
+    for (int u = 0; u < JS; u++) onext[u] = p.mem[min(jlast + u, j1 - 1)];
+    // one pass over partners jj .. jj + JS - 1, loading the records of the
+    // pass starting at jnext meanwhile
+    auto pass = [&](const uint32_t jj, const uint32_t jnext) {
         const uint32_t b = (jj - j0) >> 6;
         const uint32_t jb0 = j0 + 64 * b, jb1 = min(j1, jb0 + 64);
         // position of the column partial this lane writes at the end of the
@@ -226,7 +235,7 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
 #pragma unroll
                 for (int u = 0; u < JS; u++) {
                     o[u] = onext[u];
-                    onext[u] = p.mem[min(jj + JS + u, j1 - 1)];
+                    onext[u] = p.mem[min(jnext + u, j1 - 1)];
                 }
 #pragma unroll
                 for (int u = 0; u < JS; u++) {
@@ -269,6 +278,10 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
                 if (j < jb1 && kk < nr) store_partial(s, &partial[(size_t)cpos * R + r0 + kk]);
             }
         }
+    };
+    for (uint32_t jj = jlast + JS; jj > jfirst;) {
+        jj -= JS;
+        pass(jj, jj > jfirst ? jj - JS : jj);
     }
     if (act) {
         T *out = partial + (size_t)mpos * R + r0;
