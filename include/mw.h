@@ -88,6 +88,31 @@ typedef struct mw_plan_s *mw_plan;
  * max_roots (>= 1) bounds nroots of later calls.  *out receives the plan. */
 mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out);
 
+/* The same plan with its grouping built on the current device (section 2.3
+ * grouping, done as radix sorts of the (N-1)/(N-2)-electron strings, scans
+ * and per-group kernels): the determinants, packets, partial-sum placement
+ * and density-matrix rows come out bit for bit as mw_plan_create's, so
+ * every product of the plan is bitwise the same.  Validation and the
+ * integral repacking stay on the host.  Allocates temporary DEVICE memory
+ * (about 24 bytes per string entry, N (n_e + n_e (n_e - 1) / 2) entries for
+ * n_e electrons) and keeps the index in device allocations owned by the
+ * plan until the first mw_plan_upload copies it into the workspace and
+ * frees them; such a plan is uploaded once (a second upload returns
+ * MW_EINVAL).  Runs on `stream` and synchronises it.  MW_EUNSUPPORTED when
+ * the entries reach 2^32 or a group exceeds 2^20 members (the host build
+ * has neither limit), MW_EHIP on a failed allocation or launch. */
+mw_status mw_plan_create_device(const mw_problem *prob, int32_t max_roots, mw_stream_t stream, mw_plan *out);
+
+/* Where index array `which` of a bound plan lives in its workspace: byte
+ * offset and size (host outs), to compare plans or read them back.  which =
+ * 0 group offsets, 1 group strings, 2 group kinds, 3 column-partial starts,
+ * 4 memberships, 5 membership groups, 6 determinant-major slot lists, 7 slot
+ * positions, 8 packet offsets, 9 slot-list row pointers, 10 density-row
+ * entries, 11 density-row chunks, 12 density-row positions, 13 density-row
+ * determinants, 14 density-row single strings.  MW_EINVAL for an unbound
+ * plan or an index outside 0..14. */
+mw_status mw_plan_array(mw_plan plan, int32_t which, size_t *offset, size_t *bytes);
+
 /* Device workspace size (bytes, host out) the plan needs, including the
  * per-call scratch for max_roots roots. */
 mw_status mw_plan_workspace_bytes(mw_plan plan, size_t *bytes);
@@ -121,7 +146,7 @@ mw_status mw_plan_destroy(mw_plan plan);
  * groups of 64 members or more (evaluated once per unordered pair), 15
  * double memberships listed under the density-matrix rows of their added
  * pairs, 16 chunks of those lists (workgroups of the double-pair density
- * kernel).
+ * kernel), 17 1 when the grouping was built on the device, else 0.
  * Returns -1 for an unknown plan or index. */
 int64_t mw_plan_info(mw_plan plan, int32_t what);
 

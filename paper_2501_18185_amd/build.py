@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmw.so")
-SOURCES = ["plan.cpp", "kernels.hip", "api.cpp", "profile.cpp", "rdm.hip", "davidson.hip", "batched.hip", "pt2.hip", "csf.hip", "energy.hip"]
+SOURCES = ["plan.cpp", "plan_dev.hip", "kernels.hip", "api.cpp", "profile.cpp", "rdm.hip", "davidson.hip", "batched.hip", "pt2.hip", "csf.hip", "energy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -26,7 +26,7 @@
 #include <numeric>
 #include <thread>
 
-#include "mw_internal.h"
+#include "plan_host.h"
 
 namespace mw {
 
@@ -129,49 +129,6 @@ static inline bool key_less(const KeyEntry &a, const KeyEntry &b)
     return a.det < b.det;
 }
 
-struct HostPlan {
-    int32_t kind = 0, n = 0, M = 0, npair = 0, nalpha = 0, nbeta = 0, max_roots = 1;
-    int64_t ndet = 0;
-    double ecore = 0.0;
-    bool cplx = false;
-    std::vector<uint64_t> dets;
-    std::vector<uint32_t> grp_off;
-    std::vector<uint64_t> grp_key;
-    std::vector<uint8_t> grp_type;
-    std::vector<uint2> mem;
-    std::vector<uint32_t> mem_grp, slot_mem, pk_off, rowptr, grp_col;
-    // position of each logical partial slot (membership, then column partials)
-    std::vector<uint32_t> slot_pos;
-    int64_t ncol = 0;  // column partial sums of large double groups
-    std::vector<double> h, w_same, w_opp, g_ab, a_pair, a_pair1, f_ref;
-    // spinor plans: Table 1's |(ab|cd)| over Kramers pairs (see bound_table)
-    std::vector<double> g_bound;
-    uint64_t ref0 = 0, ref1 = 0;
-    int64_t npacket_double = 0, nmem_double = 0;
-    // density-matrix rows (see build_rdm_rows)
-    std::vector<uint2> rdm_ent;
-    std::vector<uint4> rdm_chunk;
-    std::vector<uint16_t> rdm_pos;
-    std::vector<uint32_t> rdm_ent_det;
-    std::vector<ulonglong2> rdm_skey;
-    int64_t rdm_single_e0 = 0;
-    int64_t rdm_cls[6] = {0, 0, 0, 0, 0, 0};
-    // launch defaults until mw_autotune picks its own: partner-loop unroll 4,
-    // 16 gather lanes (32 for complex), the fastest measured on the n = 64
-    // spin-free and 40-pair spinor spaces for one, two and four roots
-    int32_t tune_u = 4, tune_gl = 0;
-    int64_t n_single_pairs = 0, n_double_pairs = 0, n_evals = 0;
-    // ordered double pairs inside groups of 64 members or more, which the
-    // double-group kernel evaluates once per unordered pair
-    int64_t n_double_pairs_large = 0;
-    // device binding
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    bool bound = false;
-    DevPlan dev{};
-    size_t layout(DevPlan *d, char *base) const;
-    size_t scalar_bytes() const { return cplx ? 16 : 8; }
-};
 
 // ---------------------------------------------------------------------------
 // validation
@@ -408,14 +365,14 @@ static mw_status build_groups(HostPlan &P)
     // kind and then by their first member, so that determinants close in the
     // given order find their partial sums close together when the gather
     // reads them (and a packet's members read neighbouring coefficients);
-    // remaining ties by position in the partition/key order, so the order is
-    // total and deterministic.
-    parallel_sort(all, [](const Run &a, const Run &b) {
+    // remaining ties by the shared string K (first word, then second), so the
+    // order is total and does not depend on how the keys were partitioned.
+    parallel_sort(all, [&](const Run &a, const Run &b) {
         if (a.single != b.single) return a.single < b.single;
         if (a.len != b.len) return a.len > b.len;
         if (a.kind != b.kind) return a.kind < b.kind;
         if (a.det != b.det) return a.det < b.det;
-        return a.start < b.start;
+        return key_less(ent[a.start], ent[b.start]);
     });
 
     const int64_t ngroup = (int64_t)all.size();
@@ -592,7 +549,8 @@ static mw_status build_groups(HostPlan &P)
     // Placement of the partial sums.  A logical slot (membership m, or nmem
     // plus a column-partial index) is stored at slot_pos[slot].  Positions
     // are grouped in regions of consecutive determinants holding about 2 MB
-    // of partials (the gather gives each XCD a contiguous eighth of the
+    // of partials: determinant i belongs to region rowptr[i] / reg_slots
+    // (the gather gives each XCD a contiguous eighth of the
     // determinants, so the region it is summing stays in its L2), and inside
     // a region by the XCD whose waves write them, in packet order: every
     // region has one write frontier per XCD, written by that XCD only, whose
@@ -601,20 +559,8 @@ static mw_status build_groups(HostPlan &P)
     const int sbytes = (P.cplx ? 16 : 8) * P.max_roots;
     const int64_t reg_slots = std::max<int64_t>(4096, ((int64_t)2 << 20) / sbytes);
     std::vector<uint32_t> reg_of(N);
-    int64_t nreg = 0;
-    {
-        int64_t acc = 0;
-        for (int64_t i = 0; i < N; i++) {
-            const int64_t c = (int64_t)P.rowptr[i + 1] - P.rowptr[i];
-            if (acc > 0 && acc + c > reg_slots) {
-                nreg++;
-                acc = 0;
-            }
-            reg_of[i] = (uint32_t)nreg;
-            acc += c;
-        }
-        nreg++;
-    }
+    for (int64_t i = 0; i < N; i++) reg_of[i] = (uint32_t)(P.rowptr[i] / reg_slots);
+    const int64_t nreg = N > 0 ? (int64_t)reg_of[N - 1] + 1 : 1;
     // writer XCD of a packet: double-group packets w are launched with the
     // XCD-aware block order (logical block w / 4 runs on XCD (w / 64) % 8),
     // single-group packets in plain order (block (w - npd) / 4 on XCD
@@ -1012,6 +958,21 @@ static void reference(HostPlan &P)
 // workspace layout
 // ---------------------------------------------------------------------------
 
+Counts HostPlan::counts() const
+{
+    if (dix.on) return dix.cnt;
+    Counts c;
+    c.ngroup = (int64_t)grp_type.size();
+    c.nmem = (int64_t)mem.size();
+    c.nslot_mem = (int64_t)slot_mem.size();
+    c.nslot = (int64_t)slot_pos.size();
+    c.npk = (int64_t)pk_off.size() - 1;
+    c.nrdm_ent = (int64_t)rdm_ent.size();
+    c.nrdm_chunk = (int64_t)rdm_chunk.size();
+    c.nrdm_skey = (int64_t)rdm_skey.size();
+    return c;
+}
+
 size_t HostPlan::layout(DevPlan *d, char *base) const
 {
     size_t off = 0;
@@ -1022,23 +983,25 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
         return p;
     };
     const size_t sb = scalar_bytes();
+    const Counts c = counts();
+    const size_t ng = (size_t)c.ngroup, nm = (size_t)c.nmem;
     DevPlan t{};
     t.kind = kind; t.n = n; t.M = M; t.npair = npair; t.ndet = ndet;
-    t.nmem = (int64_t)mem.size();
-    t.npacket = (int64_t)pk_off.size() - 1;
+    t.nmem = c.nmem;
+    t.npacket = c.npk;
     t.max_roots = max_roots;
     t.ecore = ecore;
-    t.grp_off = (const uint32_t *)take(grp_off.size() * 4);
-    t.grp_key = (const uint64_t *)take(grp_key.size() * 8);
-    t.grp_type = (const uint8_t *)take(grp_type.size());
-    t.grp_col = (const uint32_t *)take(grp_col.size() * 4);
+    t.grp_off = (const uint32_t *)take((ng + 1) * 4);
+    t.grp_key = (const uint64_t *)take(ng * 16);
+    t.grp_type = (const uint8_t *)take(ng);
+    t.grp_col = (const uint32_t *)take(ng * 4);
     t.ncol = ncol;
-    t.mem = (const uint2 *)take(mem.size() * 8);
-    t.mem_grp = (const uint32_t *)take(mem_grp.size() * 4);
-    t.slot_mem = (const uint32_t *)take(slot_mem.size() * 4);
-    t.slot_pos = (const uint32_t *)take(slot_pos.size() * 4);
-    t.pk_off = (const uint32_t *)take(pk_off.size() * 4);
-    t.rowptr = (const uint32_t *)take(rowptr.size() * 4);
+    t.mem = (const uint2 *)take(nm * 8);
+    t.mem_grp = (const uint32_t *)take(nm * 4);
+    t.slot_mem = (const uint32_t *)take((size_t)c.nslot_mem * 4);
+    t.slot_pos = (const uint32_t *)take((size_t)c.nslot * 4);
+    t.pk_off = (const uint32_t *)take(((size_t)c.npk + 1) * 4);
+    t.rowptr = (const uint32_t *)take(((size_t)ndet + 1) * 4);
     t.dets = (const uint64_t *)take(dets.size() * 8);
     t.diag = (void *)take((size_t)ndet * sb);
     t.h = (const void *)take(h.size() * 8);
@@ -1053,11 +1016,11 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     t.ref1 = ref1;
     t.npacket_double = npacket_double;
     t.nmem_double = nmem_double;
-    t.rdm_ent = (const uint2 *)take(rdm_ent.size() * 8);
-    t.rdm_chunk = (const uint4 *)take(rdm_chunk.size() * 16);
-    t.rdm_pos = (const uint16_t *)take(rdm_pos.size() * 2);
-    t.rdm_ent_det = (const uint32_t *)take(rdm_ent_det.size() * 4);
-    t.rdm_skey = (const ulonglong2 *)take(rdm_skey.size() * 16);
+    t.rdm_ent = (const uint2 *)take((size_t)c.nrdm_ent * 8);
+    t.rdm_chunk = (const uint4 *)take((size_t)c.nrdm_chunk * 16);
+    t.rdm_pos = (const uint16_t *)take(nm * 2);
+    t.rdm_ent_det = (const uint32_t *)take((size_t)c.nrdm_ent * 4);
+    t.rdm_skey = (const ulonglong2 *)take((size_t)c.nrdm_skey * 16);
     t.rdm_single_e0 = rdm_single_e0;
     for (int c = 0; c < 6; c++) t.rdm_cls[c] = rdm_cls[c];
     // per-call scratch: sigma partials, or the density-matrix accumulators
@@ -1069,8 +1032,8 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
                            ? ((size_t)n * n * n * n + 2 * (size_t)npair * npair +
                               RDM_COPIES * (2 * (size_t)n * n + 2 * (size_t)n * n * n) + 257 * mm) * 8
                            : (2 * (size_t)npair * npair + RDM_COPIES * (mm + mm * M) + 257 * mm) * 16;
-    rdm_bytes = ((rdm_bytes + 255) & ~(size_t)255) + mem.size() * max_roots * sb;
-    t.scratch_bytes = std::max(std::max<size_t>(1, mem.size() + (size_t)ncol) * (size_t)max_roots * sb, rdm_bytes);
+    rdm_bytes = ((rdm_bytes + 255) & ~(size_t)255) + nm * max_roots * sb;
+    t.scratch_bytes = std::max(std::max<size_t>(1, nm + (size_t)ncol) * (size_t)max_roots * sb, rdm_bytes);
     t.partial = (void *)take(t.scratch_bytes);
     t.self = (DevPlan *)take(sizeof(DevPlan));
     t.counter = (uint32_t *)take(256);
@@ -1094,7 +1057,7 @@ extern "C" {
 
 const char *mw_last_error(void) { return g_last_error.c_str(); }
 
-mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out)
+static mw_status plan_create(const mw_problem *prob, int32_t max_roots, bool device, hipStream_t s, mw_plan *out)
 {
     if (!out) return fail(MW_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1114,18 +1077,71 @@ mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out
         P.cplx = prob->kind == MW_SPINOR;
         P.max_roots = max_roots;
         P.dets.assign(prob->dets, prob->dets + 2 * prob->ndet);
-        st = build_groups(P);
-        if (st != MW_OK) return st;
-        st = build_rdm_rows(P);
-        if (st != MW_OK) return st;
+        if (device) {
+            st = build_index_device(P, s);
+            if (st != MW_OK) {
+                P.dix.release();
+                return st;
+            }
+        } else {
+            st = build_groups(P);
+            if (st != MW_OK) return st;
+            st = build_rdm_rows(P);
+            if (st != MW_OK) return st;
+        }
         repack(P, prob);
         reference(P);
     } catch (const std::bad_alloc &) {
+        if (pl) pl->p.dix.release();
         return fail(MW_EUNSUPPORTED, "host memory exhausted while building the plan");
     } catch (const std::exception &e) {
+        if (pl) pl->p.dix.release();
         return fail(MW_EINVAL, std::string("plan build failed: ") + e.what());
     }
     *out = pl.release();
+    return MW_OK;
+}
+
+mw_status mw_plan_create(const mw_problem *prob, int32_t max_roots, mw_plan *out)
+{
+    return plan_create(prob, max_roots, false, nullptr, out);
+}
+
+mw_status mw_plan_create_device(const mw_problem *prob, int32_t max_roots, mw_stream_t stream, mw_plan *out)
+{
+    return plan_create(prob, max_roots, true, (hipStream_t)stream, out);
+}
+
+mw_status mw_plan_array(mw_plan plan, int32_t which, size_t *offset, size_t *bytes)
+{
+    if (!plan || !offset || !bytes) return fail(MW_EINVAL, "NULL argument");
+    const HostPlan &P = plan->p;
+    if (!P.bound) return fail(MW_EINVAL, "plan is not uploaded");
+    const DevPlan &d = P.dev;
+    const Counts c = P.counts();
+    const size_t ng = (size_t)c.ngroup, nm = (size_t)c.nmem;
+    const void *ptr = nullptr;
+    size_t nb = 0;
+    switch (which) {
+    case 0: ptr = d.grp_off; nb = (ng + 1) * 4; break;
+    case 1: ptr = d.grp_key; nb = ng * 16; break;
+    case 2: ptr = d.grp_type; nb = ng; break;
+    case 3: ptr = d.grp_col; nb = ng * 4; break;
+    case 4: ptr = d.mem; nb = nm * 8; break;
+    case 5: ptr = d.mem_grp; nb = nm * 4; break;
+    case 6: ptr = d.slot_mem; nb = (size_t)c.nslot_mem * 4; break;
+    case 7: ptr = d.slot_pos; nb = (size_t)c.nslot * 4; break;
+    case 8: ptr = d.pk_off; nb = ((size_t)c.npk + 1) * 4; break;
+    case 9: ptr = d.rowptr; nb = ((size_t)P.ndet + 1) * 4; break;
+    case 10: ptr = d.rdm_ent; nb = (size_t)c.nrdm_ent * 8; break;
+    case 11: ptr = d.rdm_chunk; nb = (size_t)c.nrdm_chunk * 16; break;
+    case 12: ptr = d.rdm_pos; nb = nm * 2; break;
+    case 13: ptr = d.rdm_ent_det; nb = (size_t)c.nrdm_ent * 4; break;
+    case 14: ptr = d.rdm_skey; nb = (size_t)c.nrdm_skey * 16; break;
+    default: return fail(MW_EINVAL, "array index out of range (0 .. 14)");
+    }
+    *offset = (size_t)((const char *)ptr - (const char *)P.ws);
+    *bytes = nb;
     return MW_OK;
 }
 
@@ -1151,6 +1167,47 @@ mw_status mw_plan_upload(mw_plan plan, void *workspace, size_t bytes, mw_stream_
         if (!nb) return true;
         return hipMemcpyAsync((void *)dst, src, nb, hipMemcpyHostToDevice, s) == hipSuccess;
     };
+    if (P.dix.on && P.moved)
+        return fail(MW_EINVAL, "a plan built on the device is uploaded once (its index now lives in the first workspace)");
+    if (P.dix.on) {
+        // device-built index: copied inside the device, then released
+        const DevIndex &x = P.dix;
+        const Counts &c = x.cnt;
+        auto dd = [&](const void *dst, const void *src, size_t nb) -> bool {
+            if (!nb) return true;
+            return hipMemcpyAsync((void *)dst, src, nb, hipMemcpyDeviceToDevice, s) == hipSuccess;
+        };
+        const size_t ng = (size_t)c.ngroup, nm = (size_t)c.nmem;
+        bool ok = dd(d.grp_off, x.grp_off, (ng + 1) * 4) && dd(d.grp_key, x.grp_key, ng * 16) &&
+                  dd(d.grp_type, x.grp_type, ng) && dd(d.grp_col, x.grp_col, ng * 4) && dd(d.mem, x.mem, nm * 8) &&
+                  dd(d.mem_grp, x.mem_grp, nm * 4) && dd(d.slot_mem, x.slot_mem, (size_t)c.nslot_mem * 4) &&
+                  dd(d.slot_pos, x.slot_pos, (size_t)c.nslot * 4) &&
+                  dd(d.pk_off, x.pk_off, ((size_t)c.npk + 1) * 4) &&
+                  dd(d.rowptr, x.rowptr, ((size_t)P.ndet + 1) * 4) &&
+                  dd(d.rdm_ent, x.rdm_ent, (size_t)c.nrdm_ent * 8) &&
+                  dd(d.rdm_chunk, x.rdm_chunk, (size_t)c.nrdm_chunk * 16) && dd(d.rdm_pos, x.rdm_pos, nm * 2) &&
+                  dd(d.rdm_ent_det, x.rdm_ent_det, (size_t)c.nrdm_ent * 4) &&
+                  dd(d.rdm_skey, x.rdm_skey, (size_t)c.nrdm_skey * 16) &&
+                  up(d.dets, P.dets.data(), P.dets.size() * 8) && up(d.h, P.h.data(), P.h.size() * 8) &&
+                  up(d.w_same, P.w_same.data(), P.w_same.size() * 8) &&
+                  up(d.w_opp, P.w_opp.data(), P.w_opp.size() * 8) && up(d.g_ab, P.g_ab.data(), P.g_ab.size() * 8) &&
+                  up(d.a_pair, P.a_pair.data(), P.a_pair.size() * 8) &&
+                  up(d.a_pair1, P.a_pair1.data(), P.a_pair1.size() * 8) &&
+                  up(d.f_ref, P.f_ref.data(), P.f_ref.size() * 8) &&
+                  up(d.g_bound, P.g_bound.data(), P.g_bound.size() * 8) &&
+                  hipMemcpyAsync(d.self, &d, sizeof(DevPlan), hipMemcpyHostToDevice, s) == hipSuccess;
+        if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during plan upload");
+        mw_status st = launch_diag(d, s);
+        if (st != MW_OK) return st;
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "hipStreamSynchronize failed after upload");
+        P.dix.release();
+        P.moved = true;
+        P.ws = workspace;
+        P.ws_bytes = bytes;
+        P.dev = d;
+        P.bound = true;
+        return MW_OK;
+    }
     bool ok = up(d.grp_off, P.grp_off.data(), P.grp_off.size() * 4) &&
               up(d.grp_key, P.grp_key.data(), P.grp_key.size() * 8) &&
               up(d.grp_type, P.grp_type.data(), P.grp_type.size()) &&
@@ -1228,7 +1285,10 @@ mw_status mw_plan_update_integrals(mw_plan plan, const double *h, const double *
 
 mw_status mw_plan_destroy(mw_plan plan)
 {
-    if (plan) mw_internal_batched_forget(plan);
+    if (plan) {
+        mw_internal_batched_forget(plan);
+        plan->p.dix.release();
+    }
     delete plan;
     return MW_OK;
 }
@@ -1239,8 +1299,8 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     const HostPlan &P = plan->p;
     switch (what) {
     case 0: return P.ndet;
-    case 1: return (int64_t)P.grp_type.size();
-    case 2: return (int64_t)P.mem.size();
+    case 1: return P.counts().ngroup;
+    case 2: return P.counts().nmem;
     case 3: return P.n_single_pairs + P.n_double_pairs;
     case 4: return P.n_single_pairs;
     case 5: return P.n_double_pairs;
@@ -1249,12 +1309,13 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     case 8: return (int64_t)P.scalar_bytes();
     case 9: return P.n;
     case 10: return P.kind;
-    case 11: return (int64_t)P.pk_off.size() - 1;
+    case 11: return P.counts().npk;
     case 12: return P.npacket_double;
     case 13: return P.ncol;
     case 14: return P.n_double_pairs_large;
-    case 15: return (int64_t)P.rdm_ent.size();
-    case 16: return (int64_t)P.rdm_chunk.size();
+    case 15: return P.counts().nrdm_ent;
+    case 16: return P.counts().nrdm_chunk;
+    case 17: return P.dix.on ? 1 : 0;
     default: return -1;
     }
 }

@@ -23,7 +23,11 @@ STATUS = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOTSORTED", -3: "MW_EELEC", -4: 
 INFO = {"ndet": 0, "groups": 1, "memberships": 2, "pairs": 3, "single_pairs": 4,
         "double_pairs": 5, "evaluations": 6, "workspace_bytes": 7, "scalar_bytes": 8,
         "norb": 9, "kind": 10, "packets": 11, "double_packets": 12, "column_partials": 13,
-        "double_pairs_large_groups": 14, "rdm_row_entries": 15, "rdm_row_chunks": 16}
+        "double_pairs_large_groups": 14, "rdm_row_entries": 15, "rdm_row_chunks": 16, "built_on_device": 17}
+
+# index arrays of a bound plan, in the order of mw_plan_array
+PLAN_ARRAYS = ("grp_off", "grp_key", "grp_type", "grp_col", "mem", "mem_grp", "slot_mem", "slot_pos",
+               "pk_off", "rowptr", "rdm_ent", "rdm_chunk", "rdm_pos", "rdm_ent_det", "rdm_skey")
 
 
 class MWError(RuntimeError):
@@ -51,6 +55,8 @@ def lib():
         vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         L.mw_last_error.restype = C.c_char_p
         L.mw_plan_create.argtypes = [C.POINTER(_Problem), i32, C.POINTER(vp)]
+        L.mw_plan_create_device.argtypes = [C.POINTER(_Problem), i32, vp, C.POINTER(vp)]
+        L.mw_plan_array.argtypes = [vp, i32, C.POINTER(sz), C.POINTER(sz)]
         L.mw_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
         L.mw_plan_upload.argtypes = [vp, vp, sz, vp]
         L.mw_plan_destroy.argtypes = [vp]
@@ -146,10 +152,15 @@ class Plan:
     ``problem`` needs ``kind`` ("spinfree"/"spinor"), ``norb``, ``nalpha``,
     ``nbeta``, ``dets`` ([ndet][2] uint64, sorted), ``h``, ``g`` and
     ``ecore``.  ``upload=False`` builds the host plan only (no GPU needed),
-    which is enough for :meth:`info`.
+    which is enough for :meth:`info`.  ``build="device"`` groups the
+    determinants on the current GPU (``mw_plan_create_device``: the same
+    arrays as the host build) and always uploads.
     """
 
-    def __init__(self, problem, max_roots: int = 1, device: str = "cuda", upload: bool = True):
+    def __init__(self, problem, max_roots: int = 1, device: str = "cuda", upload: bool = True,
+                 build: str = "host"):
+        if build not in ("host", "device"):
+            raise ValueError("build must be 'host' or 'device'")
         L = lib()
         self.kind = MW_SPIN_FREE if problem.kind == "spinfree" else MW_SPINOR
         self.is_complex = self.kind == MW_SPINOR
@@ -166,7 +177,12 @@ class Plan:
         pr = _Problem(self.kind, self.norb, int(problem.nalpha), int(problem.nbeta), self.ndet,
                       self._dets.ctypes.data, self._h.ctypes.data, self._g.ctypes.data, float(problem.ecore))
         h = C.c_void_p()
-        _check(L.mw_plan_create(C.byref(pr), self.max_roots, C.byref(h)))
+        if build == "device":
+            _require_gpu()
+            _check(L.mw_plan_create_device(C.byref(pr), self.max_roots, _stream(), C.byref(h)))
+            upload = True
+        else:
+            _check(L.mw_plan_create(C.byref(pr), self.max_roots, C.byref(h)))
         self._plan = h
         # the integrals are repacked inside the plan; drop the big host copies
         self._g = None
@@ -275,6 +291,13 @@ class Plan:
     # -- queries ------------------------------------------------------------
     def info(self, what: str) -> int:
         return int(lib().mw_plan_info(self._plan, INFO[what]))
+
+    def array(self, name: str):
+        """Bytes of one index array of the bound plan (a view of the
+        workspace; names as in ``PLAN_ARRAYS``)."""
+        off, nb = C.c_size_t(), C.c_size_t()
+        _check(lib().mw_plan_array(self._plan, PLAN_ARRAYS.index(name), C.byref(off), C.byref(nb)))
+        return self.workspace[off.value:off.value + nb.value]
 
     @property
     def dtype(self):
