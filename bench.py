@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--workload", default="sci-n64", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=30000, help="rows of the CPU oracle sample (0: skip)")
     ap.add_argument("--legs", default="batched,spinor,rdm,davidson,ivi,pt2,csf")
+    ap.add_argument("--plan", default="device", choices=["device", "host"],
+                    help="where the plan's grouping is built (the arrays are the same)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -121,10 +123,13 @@ def main():
     prob = synth.workload(k)
     log(f"[bench] workload {args.workload}: ndet={prob.ndet} generated in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    plan = mw.Plan(prob, max_roots=args.roots)
+    # the grouping is built on the device by default (the same arrays as the host build)
+    plan = mw.Plan(prob, max_roots=args.roots, build=args.plan)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
     log(f"[bench] plan: groups={plan.info('groups')} memberships={plan.info('memberships')} "
         f"pairs={plan.info('pairs')} workspace={plan.info('workspace_bytes') / 2**30:.2f} GiB "
-        f"in {time.perf_counter() - t0:.1f}s")
+        f"built on the {args.plan} in {plan_s:.2f}s")
     R = args.roots
     c_np = synth.ci_vectors(prob.ndet, R, synth.rng_for(k, 0, synth.SEED_C), complex_=prob.is_complex)
     c = torch.from_numpy(c_np).cuda()
@@ -201,6 +206,8 @@ def main():
             "double_pairs": plan.info("double_pairs"),
             "double_pairs_large_groups": plan.info("double_pairs_large_groups"),
             "sigma_builds_per_s": 1e3 / ms_step,
+            "plan_build_s": plan_s,
+            "plan_built_on": args.plan,
             "effective_hbm_frac_step": step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
             "group_sigma_ms": ms_grp / max(n_grp, 1),
             "gather_ms": ms_gat / max(n_gat, 1),
@@ -367,6 +374,7 @@ def leg_davidson(plan, prob, iters=10):
     i0 = int(np.argmin(dg))
     c0 = torch.zeros((prob.ndet, 1), dtype=plan.dtype, device="cuda")
     c0[i0, 0] = 1.0
+    plan.davidson(c0, tol=1e-12, max_iter=1, check=False)  # untimed: first-call allocations
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
     ev, X, it, conv = plan.davidson(c0, tol=1e-12, max_iter=iters, check=False)
@@ -384,6 +392,7 @@ def leg_ivi(plan, prob, steps=10):
     dg = plan.diag().cpu().numpy()
     c0 = torch.zeros((prob.ndet, 1), dtype=plan.dtype, device="cuda")
     c0[int(np.argmin(dg)), 0] = 1.0
+    plan.ivi(c0, tol=1e-12, max_iter=1, check=False)  # untimed: first-call allocations
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
     ev, X, it, conv = plan.ivi(c0, tol=1e-12, max_iter=steps, check=False)

@@ -858,15 +858,15 @@ static void repack(HostPlan &P, const mw_problem *p)
         P.npair = np;
         P.a_pair.resize((size_t)np * np);
         P.a_pair1.resize((size_t)np * np);
-        parallel_for(n, [&](int64_t x10, int64_t x11, unsigned) {
-            for (int64_t x1 = x10; x1 < x11; x1++)
-                for (int x0 = 0; x0 < x1; x0++)
-                    for (int y1 = 1; y1 < n; y1++)
-                        for (int y0 = 0; y0 < y1; y0++) {
-                            const double v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
-                            P.a_pair[(size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1)] = v;
-                            P.a_pair1[(size_t)pair_index(x0, (int)x1) * np + pair_lex(y0, y1, n)] = v;
-                        }
+        // one item per x1 (its work grows with x1), taken dynamically
+        parallel_items(n, [&](int64_t x1) {
+            for (int x0 = 0; x0 < x1; x0++)
+                for (int y1 = 1; y1 < n; y1++)
+                    for (int y0 = 0; y0 < y1; y0++) {
+                        const double v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
+                        P.a_pair[(size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1)] = v;
+                        P.a_pair1[(size_t)pair_index(x0, (int)x1) * np + pair_lex(y0, y1, n)] = v;
+                    }
         });
     } else {
         const int Mm = 2 * n;
@@ -887,19 +887,18 @@ static void repack(HostPlan &P, const mw_problem *p)
         P.npair = np;
         P.a_pair.resize(2 * (size_t)np * np);
         P.a_pair1.resize(2 * (size_t)np * np);
-        parallel_for(Mm, [&](int64_t x10, int64_t x11, unsigned) {
-            for (int64_t x1 = x10; x1 < x11; x1++)
-                for (int x0 = 0; x0 < x1; x0++)
-                    for (int y1 = 1; y1 < Mm; y1++)
-                        for (int y0 = 0; y0 < y1; y0++) {
-                            cd v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
-                            size_t k = (size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1);
-                            size_t k1 = (size_t)pair_index(x0, (int)x1) * np + pair_lex(y0, y1, Mm);
-                            P.a_pair[2 * k] = v.real();
-                            P.a_pair[2 * k + 1] = v.imag();
-                            P.a_pair1[2 * k1] = v.real();
-                            P.a_pair1[2 * k1 + 1] = v.imag();
-                        }
+        parallel_items(Mm, [&](int64_t x1) {
+            for (int x0 = 0; x0 < x1; x0++)
+                for (int y1 = 1; y1 < Mm; y1++)
+                    for (int y0 = 0; y0 < y1; y0++) {
+                        cd v = G(x0, y0, (int)x1, y1) - G(x0, y1, (int)x1, y0);
+                        size_t k = (size_t)pair_index(x0, (int)x1) * np + pair_index(y0, y1);
+                        size_t k1 = (size_t)pair_index(x0, (int)x1) * np + pair_lex(y0, y1, Mm);
+                        P.a_pair[2 * k] = v.real();
+                        P.a_pair[2 * k + 1] = v.imag();
+                        P.a_pair1[2 * k1] = v.real();
+                        P.a_pair1[2 * k1 + 1] = v.imag();
+                    }
         });
         bound_table(P, g);
     }

@@ -21,8 +21,8 @@
 //     memberships by determinant) and the slot placement (a stable sort of
 //     the slots, in packet order, by region and writing XCD);
 //  7. density rows: a stable sort of memberships by accumulator row and
-//     class, chunks cut greedily per row (one thread per row segment) and
-//     ordered by work on the host.
+//     class, chunks cut greedily per row segment (binary searches over the
+//     prefix sums of the partner visits) and ordered by work on the host.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -696,7 +696,11 @@ __global__ void k_rdm_pos(uint32_t nmem, const uint2 *mem, uint16_t *pos)
 }
 
 // segments (row, part): part 0 the wide class, part 1 the classes 1 .. 31;
-// chunks cut when the partner visits reach RDM_CHUNK_WORK (host rule)
+// a chunk is cut after the first entry at which its partner visits reach
+// RDM_CHUNK_WORK, or at the segment's end (the host rule).  With the
+// visits' prefix sums pw (pw[e] = visits of entries before e) the end of
+// the chunk starting at a is found by a binary search, so a thread walks
+// its segment chunk by chunk instead of entry by entry.
 __device__ __forceinline__ void seg_range(const uint32_t *start, uint64_t sg, uint32_t &e0, uint32_t &e1)
 {
     const uint64_t row = sg / 2, part = sg % 2;
@@ -704,7 +708,28 @@ __device__ __forceinline__ void seg_range(const uint32_t *start, uint64_t sg, ui
     e1 = start[row * RDM_WIDE + (part ? RDM_WIDE : 1)];
 }
 
-__global__ void k_chunk_counts(uint32_t nseg, const uint32_t *start, const uint2 *ent, uint32_t *cnt)
+__global__ void k_visits(uint32_t nent, const uint2 *ent, uint64_t *w)
+{
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e <= nent; e += (uint64_t)gridDim.x * blockDim.x)
+        w[e] = e < nent ? (uint64_t)((ent[e].y >> 16) - 1) : 0;
+}
+
+// last entry of the chunk starting at a (a < e1)
+__device__ __forceinline__ uint32_t chunk_end(const uint64_t *pw, uint32_t a, uint32_t e1)
+{
+    const uint64_t target = pw[a] + (uint64_t)RDM_CHUNK_WORK;
+    // smallest e in [a, e1) with pw[e + 1] >= target, else e1 - 1
+    uint32_t lo = a, hi = e1 - 1;
+    if (pw[e1] < target) return e1 - 1;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (pw[mid + 1] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ void k_chunk_counts(uint32_t nseg, const uint32_t *start, const uint64_t *pw, uint32_t *cnt)
 {
     for (uint64_t sg = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; sg <= nseg; sg += (uint64_t)gridDim.x * blockDim.x) {
         if (sg == nseg) {
@@ -714,19 +739,12 @@ __global__ void k_chunk_counts(uint32_t nseg, const uint32_t *start, const uint2
         uint32_t e0, e1;
         seg_range(start, sg, e0, e1);
         uint32_t c = 0;
-        int64_t work = 0;
-        for (uint32_t e = e0; e < e1; e++) {
-            work += (ent[e].y >> 16) - 1;
-            if (work >= RDM_CHUNK_WORK || e + 1 == e1) {
-                c++;
-                work = 0;
-            }
-        }
+        for (uint32_t a = e0; a < e1; c++) a = chunk_end(pw, a, e1) + 1;
         cnt[sg] = c;
     }
 }
 
-__global__ void k_chunk_fill(uint32_t nseg, int64_t nab, int64_t nrow_d, const uint32_t *start, const uint2 *ent,
+__global__ void k_chunk_fill(uint32_t nseg, int64_t nab, int64_t nrow_d, const uint32_t *start, const uint64_t *pw,
                              const uint32_t *coff, uint4 *chunk, int64_t *cwork)
 {
     for (uint64_t sg = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; sg < nseg; sg += (uint64_t)gridDim.x * blockDim.x) {
@@ -735,17 +753,12 @@ __global__ void k_chunk_fill(uint32_t nseg, int64_t nab, int64_t nrow_d, const u
         const int64_t row = (int64_t)(sg / 2);
         const uint32_t flags = row < nab ? 1u : 0u;
         const uint32_t r = (uint32_t)(row < nab ? row : (row < nrow_d ? row - nab : row - nrow_d));
-        uint32_t o = coff[sg], a = e0;
-        int64_t work = 0;
-        for (uint32_t e = e0; e < e1; e++) {
-            work += (ent[e].y >> 16) - 1;
-            if (work >= RDM_CHUNK_WORK || e + 1 == e1) {
-                chunk[o] = make_uint4(r, flags, a, e + 1);
-                cwork[o] = work;
-                o++;
-                a = e + 1;
-                work = 0;
-            }
+        uint32_t o = coff[sg];
+        for (uint32_t a = e0; a < e1; o++) {
+            const uint32_t e = chunk_end(pw, a, e1);
+            chunk[o] = make_uint4(r, flags, a, e + 1);
+            cwork[o] = (int64_t)(pw[e + 1] - pw[a]);
+            a = e + 1;
         }
     }
 }
@@ -1128,8 +1141,12 @@ mw_status build_index_device(HostPlan &P, hipStream_t s)
         // chunks per segment, then ordered by work inside each class on the host
         const uint32_t nseg = (uint32_t)(nrow * 2);
         uint32_t *cc = tmp.get<uint32_t>((size_t)nseg + 1), *co = tmp.get<uint32_t>((size_t)nseg + 1);
-        NEED(cc && co);
-        k_chunk_counts<<<grid_for((int64_t)nseg + 1), TPB, 0, s>>>(nseg, start, X.rdm_ent, cc);
+        uint64_t *vis = tmp.get<uint64_t>((size_t)nent + 1), *pw = tmp.get<uint64_t>((size_t)nent + 1);
+        NEED(cc && co && vis && pw);
+        k_visits<<<grid_for((int64_t)nent + 1), TPB, 0, s>>>(nent, X.rdm_ent, vis);
+        CKL("k_visits");
+        CK(excl_scan(vis, pw, (size_t)nent + 1, s));
+        k_chunk_counts<<<grid_for((int64_t)nseg + 1), TPB, 0, s>>>(nseg, start, pw, cc);
         CKL("k_chunk_counts");
         CK(excl_scan(cc, co, (size_t)nseg + 1, s));
         uint32_t nch = 0;
@@ -1137,7 +1154,7 @@ mw_status build_index_device(HostPlan &P, hipStream_t s)
         uint4 *dch = tmp.get<uint4>(nch);
         int64_t *dwk = tmp.get<int64_t>(nch);
         NEED(dch && dwk);
-        k_chunk_fill<<<grid_for(nseg), TPB, 0, s>>>(nseg, nab, nrow_d, start, X.rdm_ent, co, dch, dwk);
+        k_chunk_fill<<<grid_for(nseg), TPB, 0, s>>>(nseg, nab, nrow_d, start, pw, co, dch, dwk);
         CKL("k_chunk_fill");
         std::vector<uint4> hch(nch);
         std::vector<int64_t> hwk(nch);
