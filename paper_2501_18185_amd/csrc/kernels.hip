@@ -204,17 +204,19 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
     // since 64 is a multiple of JS, every block of the group starts at the
     // same pass and the blocks walk the same partners at about the same
     // time, so the partner records and coefficients one block reads are in
-    // L2 for the others (spinor sigma 11.5 -> 11.2 ms; the real space
-    // 9.59 -> 9.49 ms in the same run).  The partner records of the next
-    // pass (wave-uniform) are loaded while this pass runs.
+    // L2 for the others (spinor sigma 11.5 -> 11.2 ms).  The partner records
+    // of the next pass (wave-uniform) are loaded while this pass runs.
     const uint32_t jfirst = j0 + 64 * a;
     const uint32_t jlast = jfirst + (j1 - 1 - jfirst) / JS * JS;  // start of the last pass
     uint2 onext[JS];
 #pragma unroll
     for (int u = 0; u < JS; u++) onext[u] = p.mem[min(jlast + u, j1 - 1)];
-    // one pass over partners jj .. jj + JS - 1, loading the records of the
-    // pass starting at jnext meanwhile
-    auto pass = [&](const uint32_t jj, const uint32_t jnext) {
+    // one pass over partners jj .. jj + JS - 1 per iteration, loading the
+    // records of the pass starting at jnext meanwhile (the body stays inside
+    // the loop: as a lambda it spilled scalar registers)
+    for (uint32_t jj = jlast + JS; jj > jfirst;) {
+        jj -= JS;
+        const uint32_t jnext = jj > jfirst ? jj - JS : jj;
         const uint32_t b = (jj - j0) >> 6;
         const uint32_t jb0 = j0 + 64 * b, jb1 = min(j1, jb0 + 64);
         // position of the column partial this lane writes at the end of the
@@ -278,10 +280,6 @@ __device__ __forceinline__ void group_double_half(const DevPlan &p, uint32_t mfi
                 if (j < jb1 && kk < nr) store_partial(s, &partial[(size_t)cpos * R + r0 + kk]);
             }
         }
-    };
-    for (uint32_t jj = jlast + JS; jj > jfirst;) {
-        jj -= JS;
-        pass(jj, jj > jfirst ? jj - JS : jj);
     }
     if (act) {
         T *out = partial + (size_t)mpos * R + r0;
