@@ -32,8 +32,9 @@ Further legs reported in the same line (skip with --legs none):
             determinants from it;
   csf       sigma in the CSF basis (spin-adapted, S = 0) of the
             configuration-complete singles-and-doubles space of n=64
-            10a10b, 1 and 4 roots, against the determinant sigma of the
-            same space.
+            10a10b and of an open-shell-rich space (n=32 8a8b, 10 and 12
+            open shells), 1 and 4 roots, against the determinant sigma of
+            the same space.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
                        [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
@@ -563,35 +564,45 @@ def leg_spinor(steps):
 
 def leg_csf(steps):
     """CSF-basis sigma (T^T H T c) against the determinant sigma of the same
-    configuration-complete space."""
+    configuration-complete space: the singles-and-doubles space of n=64
+    10a10b, and an open-shell-rich space (n=32 8a8b, 10 and 12 open shells)
+    where the determinants outnumber the CSFs most."""
     import torch
     from paper_2501_18185_amd import mw, synth
-    t0 = time.perf_counter()
-    p = synth.workload(6)
-    res = {"workload": p.name, "ndet": p.ndet}
-    for R in (1, 4):
-        pl = mw.Plan(p, max_roots=R)
-        cb = mw.Csf(pl, 0)
-        if R == 1:
-            log(f"[bench] csf: ndet={p.ndet} ncsf={cb.ncsf} configurations={cb.info('configurations')} "
-                f"ready in {time.perf_counter() - t0:.1f}s")
-            res.update({"ncsf": cb.ncsf, "configurations": cb.info("configurations")})
-        c = torch.from_numpy(synth.ci_vectors(cb.ncsf, R, synth.rng_for(6, 0, synth.SEED_C))).cuda()
-        o = torch.empty_like(c)
-        x = cb.to_det(c)
-        y = torch.empty_like(x)
-        work = torch.empty(2 * p.ndet * R, dtype=torch.float64, device="cuda")
-        n = max(steps // 2, 3)
-        ms_csf = _time(lambda: cb.sigma(c, out=o, work=work), n)
-        ms_det = _time(lambda: pl.sigma(x, out=y), n)
-        ms_t = _time(lambda: cb.to_det(c, out=x), n)
-        ms_tt = _time(lambda: cb.from_det(y, out=o), n)
-        log(f"[bench] csf: {R} roots, {ms_csf:.2f} ms per CSF sigma, {ms_det:.2f} ms determinant sigma")
-        res[f"roots{R}"] = {"ms_per_csf_sigma": ms_csf, "ms_per_det_sigma": ms_det, "to_det_ms": ms_t,
-                            "from_det_ms": ms_tt}
-        del pl, cb, c, o, x, y, work
-        torch.cuda.empty_cache()
-    return res
+    out = {}
+    for wk, tag in ((6, "sd"), (7, "open")):
+        t0 = time.perf_counter()
+        p = synth.workload(wk)
+        res = {"workload": p.name, "ndet": p.ndet}
+        for R in (1, 4):
+            pl = mw.Plan(p, max_roots=R, build="device")
+            cb = mw.Csf(pl, 0)
+            if R == 1:
+                log(f"[bench] csf {tag}: ndet={p.ndet} ncsf={cb.ncsf} configurations={cb.info('configurations')} "
+                    f"max open shells={cb.info('max_open')} ready in {time.perf_counter() - t0:.1f}s")
+                res.update({"ncsf": cb.ncsf, "configurations": cb.info("configurations"),
+                            "max_open_shells": cb.info("max_open"),
+                            "plan_workspace_bytes": pl.info("workspace_bytes"),
+                            "csf_workspace_bytes": cb.info("workspace_bytes")})
+            c = torch.from_numpy(synth.ci_vectors(cb.ncsf, R, synth.rng_for(wk, 0, synth.SEED_C))).cuda()
+            o = torch.empty_like(c)
+            x = cb.to_det(c)
+            y = torch.empty_like(x)
+            work = torch.empty(2 * p.ndet * R, dtype=torch.float64, device="cuda")
+            n = max(steps // 2, 3)
+            ms_csf = _time(lambda: cb.sigma(c, out=o, work=work), n)
+            ms_det = _time(lambda: pl.sigma(x, out=y), n)
+            ms_t = _time(lambda: cb.to_det(c, out=x), n)
+            ms_tt = _time(lambda: cb.from_det(y, out=o), n)
+            log(f"[bench] csf {tag}: {R} roots, {ms_csf:.2f} ms per CSF sigma, {ms_det:.2f} ms determinant sigma, "
+                f"transforms {ms_t:.3f} + {ms_tt:.3f} ms")
+            res[f"roots{R}"] = {"ms_per_csf_sigma": ms_csf, "ms_per_det_sigma": ms_det, "to_det_ms": ms_t,
+                                "from_det_ms": ms_tt, "vector_bytes_det": p.ndet * R * 8,
+                                "vector_bytes_csf": cb.ncsf * R * 8}
+            del pl, cb, c, o, x, y, work
+            torch.cuda.empty_cache()
+        out[tag] = res
+    return out
 
 
 if __name__ == "__main__":

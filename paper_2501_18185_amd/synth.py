@@ -405,6 +405,31 @@ def complete_configurations(dets, n):
     return sort_unique(np.concatenate(out0), np.concatenate(out1))
 
 
+def space_open_shell_rich(n, na, opens, nconf, rng):
+    """nconf distinct random configurations of 2 na electrons in n orbitals
+    for each open-shell count in ``opens`` (na - k/2 doubly occupied
+    orbitals, k open ones, chosen uniformly without overlap), closed over
+    their spin placements at M_S = 0."""
+    w0, w1 = [], []
+    for k in opens:
+        nd = na - k // 2
+        seen = set()
+        while len(seen) < nconf:
+            perm = rng.permutation(n)
+            docc = int(sum(1 << int(p) for p in perm[:nd]))
+            opn = int(sum(1 << int(p) for p in perm[nd:nd + k]))
+            if (docc, opn) in seen:
+                continue
+            seen.add((docc, opn))
+            # one determinant per configuration: the lowest k/2 open orbitals alpha
+            op = [p for p in range(n) if opn >> p & 1]
+            up = sum(1 << p for p in op[:k // 2])
+            w0.append(docc | up)
+            w1.append(docc | (opn & ~up))
+    seed = sort_unique(np.array(w0, np.uint64), np.array(w1, np.uint64))
+    return complete_configurations(seed, n)
+
+
 def random_space_spinfree(n, na, nb, ndet, rng):
     """ndet distinct determinants drawn uniformly from the full space (tiny n)."""
     full = space_fci(n, na, nb)
@@ -465,7 +490,8 @@ def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
     40 pairs N=20 1e6; 3 batch problem i; 4 FD case n=10 3a3b FCI; 5 the
     variational space of the second-order energy, n=64 10a10b 2e4; 6 the
     singles-and-doubles space of n=64 10a10b, complete over its
-    configurations, for the CSF basis).
+    configurations, for the CSF basis; 7 an open-shell-rich
+    configuration-complete space, n=32 8a8b with 10 and 12 open shells).
 
     ``scale`` < 1 shrinks the random part of selected spaces (for tests)."""
     if k == 0:
@@ -507,6 +533,15 @@ def workload(k: int, i: int = 0, scale: float = 1.0) -> Problem:
         _, _, w0, w1 = _hf_and_sd_spinfree(n, na, na)
         return Problem("spinfree", n, na, na, sort_unique(w0, w1), one_body_real(n, rng_for(1, 0, SEED_H)),
                        two_body_real(n, rng_for(1, 0, SEED_G)), name="sd-n64-10a10b")
+    if k == 7:
+        # open-shell-rich configuration-complete space for the CSF basis:
+        # n=32 8a8b, random configurations with 10 or 12 open shells (3 or
+        # 2 doubly occupied orbitals), every spin placement of each
+        n, na = 32, 8
+        nconf = int(1000 * scale) if scale != 1.0 else 1000
+        d = space_open_shell_rich(n, na, (10, 12), nconf, rng_for(7, 0, SEED_SPACE))
+        return Problem("spinfree", n, na, na, d, one_body_real(n, rng_for(7, 0, SEED_H)),
+                       two_body_real(n, rng_for(7, 0, SEED_G)), name="open-n32-8a8b")
     if k == 4:
         n, na, nb = 10, 3, 3
         return Problem("spinfree", n, na, nb, space_fci(n, na, nb),

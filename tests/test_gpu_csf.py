@@ -58,13 +58,18 @@ def _case(name):
     if name == "trunc-14-5a3b":
         d = synth.space_truncated_spinfree(14, 5, 3, 2000, np.random.default_rng(23))
         return _prob(14, 5, 3, synth.complete_configurations(d, 14), seed=24)
+    if name == "open-12-4a4b":
+        # open-shell-rich: configurations with 4 and 6 open shells
+        d = synth.space_open_shell_rich(12, 4, (4, 6), 20, np.random.default_rng(27))
+        return _prob(12, 4, 4, d, seed=28)
     if name == "random-12-3a3b":
         d = synth.random_space_spinfree(12, 3, 3, 300, np.random.default_rng(25))
         return _prob(12, 3, 3, synth.complete_configurations(d, 12), seed=26)
     raise ValueError(name)
 
 
-CASES = ["fci-6-3-3", "fci-6-4-2", "fci-7-4-3", "fci-5-4-1", "trunc-16-4a4b", "trunc-14-5a3b", "random-12-3a3b"]
+CASES = ["fci-6-3-3", "fci-6-4-2", "fci-7-4-3", "fci-5-4-1", "trunc-16-4a4b", "trunc-14-5a3b", "random-12-3a3b",
+         "open-12-4a4b"]
 
 
 def _basis(prob, max_roots):

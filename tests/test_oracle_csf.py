@@ -207,3 +207,19 @@ def test_selected_space_sigma_and_completeness():
         csf.expansion(q, 0)
     with pytest.raises(ValueError):
         csf.expansion(p, 2)
+
+
+def test_open_shell_rich_space_recipe():
+    """The open-shell-rich input recipe: electron counts per spin, only the
+    requested open-shell counts, closed over configurations, and the
+    expected number of spin placements per configuration."""
+    from math import comb
+    n, na = 12, 4
+    d = synth.space_open_shell_rich(n, na, (4, 6), 20, np.random.default_rng(5))
+    a, b = d[:, 0], d[:, 1]
+    assert (np.bitwise_count(a) == na).all() and (np.bitwise_count(b) == na).all()
+    k = np.bitwise_count(a ^ b)
+    assert set(np.unique(k).tolist()) == {4, 6}
+    assert np.array_equal(synth.complete_configurations(d, n), d)
+    # 20 configurations of each kind, C(k, k/2) placements each
+    assert (k == 4).sum() == 20 * comb(4, 2) and (k == 6).sum() == 20 * comb(6, 3)
