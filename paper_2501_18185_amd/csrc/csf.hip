@@ -31,7 +31,12 @@
 // Device: k_csf_to_det (one thread per determinant and root: a row of the
 // table times the configuration's CSF coefficients) and k_csf_from_det (one
 // thread per CSF and root: a column of the table against the
-// configuration's determinants).
+// configuration's determinants) for configurations of few determinants;
+// configurations of CSF_BIG_ROWS determinants or more go by open-shell
+// count through k_csf_to_det_cls / k_csf_from_det_cls, which stage a batch
+// of configurations in LDS so that each table row is read once per batch
+// (the block-diagonal transform is then a product of the shared table with
+// the batch's coefficients).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,6 +68,22 @@ struct DevCsf {
     const uint32_t *cfg_tab;   // [ncfg] offset of its table (doubles)
     const uint32_t *csf_cfg;   // [ncsf] configuration of each CSF
     const double *tab;         // coupling tables, [placements][paths] per open-shell count
+    const double *tabT;        // the same tables transposed, [paths][placements], same offsets
+    const uint32_t *cls_dets;  // determinants of the class kernels' configurations (see CsfClass)
+    const uint32_t *cls_csf0;  // first CSF of each of those configurations
+};
+
+// Configurations with this many determinants or more (8 open shells and up
+// at S = 0) are transformed by the class kernels: a block stages a batch of
+// configurations of one open-shell count and reads each table row once for
+// the whole batch, instead of once per configuration.
+constexpr uint32_t CSF_BIG_ROWS = 64;
+
+// the configurations of one open-shell count handled by the class kernels
+struct CsfClass {
+    const uint32_t *dets;  // [count][nd]: determinant | negative << 31, by configuration then rank
+    const uint32_t *csf0;  // [count]: first CSF of each configuration
+    uint32_t count, nd, f, toff;
 };
 
 template <class T>
@@ -130,6 +151,7 @@ __global__ __launch_bounds__(256) void k_csf_to_det(DevCsf q, int R, const doubl
     const int r = (int)(t - I * R);
     const uint2 info = q.det_info[I];
     const uint32_t cfg = info.x & 0x7fffffffu;
+    if (q.cfg_det[cfg + 1] - q.cfg_det[cfg] >= CSF_BIG_ROWS) return;  // class kernel
     const uint32_t c0 = q.cfg_csf[cfg], f = q.cfg_csf[cfg + 1] - c0;
     const double *row = q.tab + q.cfg_tab[cfg] + (size_t)info.y * f;
     const double *xc = x + (size_t)c0 * R + r;
@@ -148,6 +170,7 @@ __global__ __launch_bounds__(256) void k_csf_from_det(DevCsf q, int R, const dou
     const uint32_t cfg = q.csf_cfg[j];
     const uint32_t c0 = q.cfg_csf[cfg], f = q.cfg_csf[cfg + 1] - c0, mu = (uint32_t)j - c0;
     const uint32_t d0 = q.cfg_det[cfg], nd = q.cfg_det[cfg + 1] - d0;
+    if (nd >= CSF_BIG_ROWS) return;  // class kernel
     const double *col = q.tab + q.cfg_tab[cfg] + mu;
     double acc = 0.0;
     for (uint32_t k = 0; k < nd; k++) {
@@ -156,6 +179,95 @@ __global__ __launch_bounds__(256) void k_csf_from_det(DevCsf q, int R, const dou
         acc = fma(col[(size_t)k * f], (e >> 31) ? -v : v, acc);
     }
     x[t] = acc;
+}
+
+// The class kernels: block column by = a batch of NB configurations of one
+// open-shell count (RC roots from r0), grid-strided over the batches; the
+// last batch repeats its last configuration in the unused places (computed,
+// not written), so the inner loops carry no bounds tests.
+// to_det: a thread per table row (placement) accumulates the row times the
+// batch's CSF coefficients, staged in LDS, over the paths in increasing
+// order (the order of k_csf_to_det, so the values are the same bits).
+template <int RC, int NB>
+__global__ __launch_bounds__(256) void k_csf_to_det_cls(DevCsf q, CsfClass cl, int R, int r0,
+                                                        const double *__restrict__ x, double *__restrict__ y)
+{
+    extern __shared__ double xs[];  // [NB][f][RC]
+    const uint32_t f = cl.f, nd = cl.nd;
+    const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t by = blockIdx.y; by * (uint32_t)NB < cl.count; by += gridDim.y) {
+        const uint32_t b0 = by * (uint32_t)NB;
+        const uint32_t nb = min((uint32_t)NB, cl.count - b0);
+        for (uint32_t i = threadIdx.x; i < (uint32_t)NB * f * RC; i += blockDim.x) {
+            const uint32_t cb = i / (f * RC), rem = i - cb * f * RC, mu = rem / RC, r = rem - mu * RC;
+            xs[i] = x[(size_t)(cl.csf0[b0 + min(cb, nb - 1)] + mu) * R + r0 + r];
+        }
+        __syncthreads();
+        if (row < nd) {
+            double acc[NB * RC];
+#pragma unroll
+            for (int i = 0; i < NB * RC; i++) acc[i] = 0.0;
+            const double *col = q.tabT + cl.toff + row;  // T[row][mu] = tabT[mu][row]
+#pragma unroll 2
+            for (uint32_t mu = 0; mu < f; mu++) {
+                const double t = col[(size_t)mu * nd];
+#pragma unroll
+                for (int i = 0; i < NB * RC; i++) acc[i] = fma(t, xs[((size_t)(i / RC) * f + mu) * RC + i % RC], acc[i]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NB; cb++)
+                if ((uint32_t)cb < nb) {
+                    const uint32_t e = cl.dets[(size_t)(b0 + cb) * nd + row];
+                    double *out = y + (size_t)(e & 0x7fffffffu) * R + r0;
+#pragma unroll
+                    for (int r = 0; r < RC; r++) out[r] = (e >> 31) ? -acc[cb * RC + r] : acc[cb * RC + r];
+                }
+        }
+        __syncthreads();
+    }
+}
+
+// from_det: a thread per path mu accumulates the table column against the
+// batch's signed determinant values, staged in LDS, over the placements in
+// increasing order (the order of k_csf_from_det).
+template <int RC, int NB>
+__global__ __launch_bounds__(256) void k_csf_from_det_cls(DevCsf q, CsfClass cl, int R, int r0,
+                                                          const double *__restrict__ y, double *__restrict__ x)
+{
+    extern __shared__ double ys[];  // [NB][nd][RC]
+    const uint32_t f = cl.f, nd = cl.nd;
+    const uint32_t mu = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t by = blockIdx.y; by * (uint32_t)NB < cl.count; by += gridDim.y) {
+        const uint32_t b0 = by * (uint32_t)NB;
+        const uint32_t nb = min((uint32_t)NB, cl.count - b0);
+        for (uint32_t i = threadIdx.x; i < (uint32_t)NB * nd * RC; i += blockDim.x) {
+            const uint32_t cb = i / (nd * RC), rem = i - cb * nd * RC, k = rem / RC, r = rem - k * RC;
+            const uint32_t e = cl.dets[(size_t)(b0 + min(cb, nb - 1)) * nd + k];
+            const double v = y[(size_t)(e & 0x7fffffffu) * R + r0 + r];
+            ys[i] = (e >> 31) ? -v : v;
+        }
+        __syncthreads();
+        if (mu < f) {
+            double acc[NB * RC];
+#pragma unroll
+            for (int i = 0; i < NB * RC; i++) acc[i] = 0.0;
+            const double *col = q.tab + cl.toff + mu;
+#pragma unroll 2
+            for (uint32_t k = 0; k < nd; k++) {
+                const double t = col[(size_t)k * f];
+#pragma unroll
+                for (int i = 0; i < NB * RC; i++) acc[i] = fma(t, ys[((size_t)(i / RC) * nd + k) * RC + i % RC], acc[i]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NB; cb++)
+                if ((uint32_t)cb < nb) {
+                    double *out = x + (size_t)(cl.csf0[b0 + cb] + mu) * R + r0;
+#pragma unroll
+                    for (int r = 0; r < RC; r++) out[r] = acc[cb * RC + r];
+                }
+        }
+        __syncthreads();
+    }
 }
 
 // D_mu = sum over the configuration's determinants of T_I,mu^2 H_II
@@ -186,7 +298,16 @@ struct mw_csf_s {
     int64_t ndet = 0, ncsf = 0, ncfg = 0;
     std::vector<uint2> det_info;
     std::vector<uint32_t> cfg_det, cfg_dets, cfg_csf, cfg_tab, csf_cfg;
-    std::vector<double> tab;
+    std::vector<double> tab, tabT;
+    // class kernels: configurations with CSF_BIG_ROWS determinants or more,
+    // by open-shell count; the others go through the per-element kernels
+    std::vector<uint32_t> cls_dets, cls_csf0;
+    struct Cls {
+        uint32_t first, count, nd, f, toff;  // first: index of its first configuration in cls_csf0
+        size_t dfirst;                       // index of its first determinant in cls_dets
+    };
+    std::vector<Cls> cls;
+    int64_t small_det = 0, small_csf = 0;
     bool bound = false;
     DevCsf dev{};
 
@@ -200,7 +321,8 @@ struct mw_csf_s {
         size_t a_info = take<uint2>(off, det_info.size()), a_cd = take<uint32_t>(off, cfg_det.size()),
                a_cds = take<uint32_t>(off, cfg_dets.size()), a_cc = take<uint32_t>(off, cfg_csf.size()),
                a_ct = take<uint32_t>(off, cfg_tab.size()), a_sc = take<uint32_t>(off, csf_cfg.size()),
-               a_tab = take<double>(off, tab.size());
+               a_tab = take<double>(off, tab.size()), a_tabT = take<double>(off, tabT.size()),
+               a_cld = take<uint32_t>(off, cls_dets.size()), a_clc = take<uint32_t>(off, cls_csf0.size());
         if (d && base) {
             t.det_info = (const uint2 *)(base + a_info);
             t.cfg_det = (const uint32_t *)(base + a_cd);
@@ -209,6 +331,9 @@ struct mw_csf_s {
             t.cfg_tab = (const uint32_t *)(base + a_ct);
             t.csf_cfg = (const uint32_t *)(base + a_sc);
             t.tab = (const double *)(base + a_tab);
+            t.tabT = (const double *)(base + a_tabT);
+            t.cls_dets = (const uint32_t *)(base + a_cld);
+            t.cls_csf0 = (const uint32_t *)(base + a_clc);
             *d = t;
         }
         return off + 256;
@@ -308,6 +433,29 @@ static mw_status build_csf(mw_csf_s &C, const uint64_t *dets, int64_t N, int n, 
     }
     C.cfg_tab.resize(ncfg);
     for (int64_t c = 0; c < ncfg; c++) C.cfg_tab[c] = (uint32_t)toff[kc[c]];
+    // transposed tables, and the configurations of the class kernels
+    C.tabT.assign(C.tab.size(), 0.0);
+    C.cls.clear();
+    C.cls_dets.clear();
+    C.cls_csf0.clear();
+    C.small_det = C.small_csf = 0;
+    for (int k = 0; k <= CSF_MAXOPEN; k++) {
+        if (!used[k]) continue;
+        const int64_t nd = binom(k, (k + s) / 2), f = fk[k];
+        for (int64_t r = 0; r < nd; r++)
+            for (int64_t mu = 0; mu < f; mu++) C.tabT[toff[k] + mu * nd + r] = C.tab[toff[k] + r * f + mu];
+        if (nd < (int64_t)CSF_BIG_ROWS) continue;
+        mw_csf_s::Cls cl{(uint32_t)C.cls_csf0.size(), 0, (uint32_t)nd, (uint32_t)f, (uint32_t)toff[k], 0};
+        for (int64_t c = 0; c < ncfg; c++)
+            if (kc[c] == k) C.cls_csf0.push_back((uint32_t)c);  // configuration ids for now
+        cl.count = (uint32_t)C.cls_csf0.size() - cl.first;
+        C.cls.push_back(cl);
+    }
+    for (int64_t c = 0; c < ncfg; c++)
+        if (C.cfg_det[c + 1] - C.cfg_det[c] < CSF_BIG_ROWS) {
+            C.small_det += C.cfg_det[c + 1] - C.cfg_det[c];
+            C.small_csf += C.cfg_csf[c + 1] - C.cfg_csf[c];
+        }
     C.csf_cfg.resize(ncsf);
     for (int64_t c = 0; c < ncfg; c++)
         for (uint32_t j = C.cfg_csf[c]; j < C.cfg_csf[c + 1]; j++) C.csf_cfg[j] = (uint32_t)c;
@@ -338,6 +486,15 @@ static mw_status build_csf(mw_csf_s &C, const uint64_t *dets, int64_t N, int n, 
         uint32_t &slot = C.cfg_dets[C.cfg_det[c] + rank];
         if (slot != 0xffffffffu) return fail(MW_EINVAL, "internal: two determinants share a placement");
         slot = (uint32_t)i | (neg << 31);
+    }
+    // the class kernels' determinant lists (configuration ids become first CSFs)
+    for (auto &cl : C.cls) {
+        cl.dfirst = C.cls_dets.size();
+        for (uint32_t i = cl.first; i < cl.first + cl.count; i++) {
+            const uint32_t c = C.cls_csf0[i];
+            C.cls_dets.insert(C.cls_dets.end(), C.cfg_dets.begin() + C.cfg_det[c], C.cfg_dets.begin() + C.cfg_det[c + 1]);
+            C.cls_csf0[i] = C.cfg_csf[c];
+        }
     }
     (void)n;
     (void)na;
@@ -391,6 +548,79 @@ static mw_status csf_bound(mw_csf csf, int32_t nroots)
 static unsigned grid_of(int64_t items)
 {
     return (unsigned)((items + 255) / 256);
+}
+
+// the class kernels for RC roots from r0 (to_det: x CSF -> y determinants)
+template <int RC, int NB>
+static mw_status launch_cls_nb(const DevCsf &dev, const mw_csf_s::Cls &k, const CsfClass &cl, size_t lds, int R,
+                               int r0, const double *in, double *out, hipStream_t s, bool to_det)
+{
+    static std::once_flag once;
+    std::call_once(once, []() {
+        // LDS beyond 64 KB for one configuration of 3432 placements and 4 roots
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_csf_to_det_cls<RC, NB>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_csf_from_det_cls<RC, NB>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    const unsigned ny = (unsigned)std::min<uint32_t>((k.count + NB - 1) / NB, 65535u);
+    if (to_det)
+        hipLaunchKernelGGL((k_csf_to_det_cls<RC, NB>), dim3((k.nd + 255) / 256, ny), dim3(256), lds, s, dev,
+                           cl, R, r0, in, out);
+    else {
+        const unsigned bx = std::min<unsigned>(256, (k.f + 63) / 64 * 64);
+        hipLaunchKernelGGL((k_csf_from_det_cls<RC, NB>), dim3((k.f + bx - 1) / bx, ny), dim3(bx), lds, s,
+                           dev, cl, R, r0, in, out);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF class kernel launch failed");
+    return MW_OK;
+}
+
+template <int RC>
+static mw_status launch_cls_rc(const mw_csf_s &C, int R, int r0, const double *in, double *out, hipStream_t s,
+                               bool to_det)
+{
+    for (const auto &k : C.cls) {
+        if (!to_det && k.f == 0) continue;  // no CSF to write (to_det still writes the zeros)
+        const CsfClass cl{C.dev.cls_dets + k.dfirst, C.dev.cls_csf0 + k.first, k.count, k.nd, k.f, k.toff};
+        // LDS per configuration
+        const size_t per = std::max<size_t>(1, (size_t)(to_det ? k.f : k.nd)) * RC * sizeof(double);
+        // configurations per block (a power of two): bounded by the
+        // accumulators and 48 KB of LDS, and small enough to leave about
+        // 512 blocks for the GPU
+        const size_t gx = to_det ? (k.nd + 255) / 256 : (k.f + 255) / 256;
+        const size_t cap = std::min<size_t>(std::min<size_t>(16 / RC, 49152 / per),
+                                            std::max<size_t>(1, (size_t)k.count * gx / 512));
+        int nb = 1;
+        while (nb * 2 <= (int)cap) nb *= 2;
+        const size_t lds = (size_t)nb * per;
+        if (lds > 160 * 1024) return fail(MW_EUNSUPPORTED, "CSF class kernel: configuration too large for LDS");
+        const DevCsf &d = C.dev;
+        mw_status st = MW_OK;
+        bool done = false;
+        if constexpr (RC == 1)
+            if (nb >= 16) st = launch_cls_nb<RC, 16>(d, k, cl, lds, R, r0, in, out, s, to_det), done = true;
+        if constexpr (RC <= 2)
+            if (!done && nb >= 8) st = launch_cls_nb<RC, 8>(d, k, cl, lds, R, r0, in, out, s, to_det), done = true;
+        if (!done && nb >= 4) st = launch_cls_nb<RC, 4>(d, k, cl, lds, R, r0, in, out, s, to_det);
+        else if (!done && nb >= 2) st = launch_cls_nb<RC, 2>(d, k, cl, lds, R, r0, in, out, s, to_det);
+        else if (!done) st = launch_cls_nb<RC, 1>(d, k, cl, lds, R, r0, in, out, s, to_det);
+        if (st != MW_OK) return st;
+    }
+    return MW_OK;
+}
+
+static mw_status launch_cls(const mw_csf_s &C, int R, const double *in, double *out, hipStream_t s, bool to_det)
+{
+    for (int r0 = 0; r0 < R; r0 += 4) {
+        const int rc = std::min(4, R - r0);
+        mw_status st = rc == 1   ? launch_cls_rc<1>(C, R, r0, in, out, s, to_det)
+                       : rc == 2 ? launch_cls_rc<2>(C, R, r0, in, out, s, to_det)
+                       : rc == 3 ? launch_cls_rc<3>(C, R, r0, in, out, s, to_det)
+                                 : launch_cls_rc<4>(C, R, r0, in, out, s, to_det);
+        if (st != MW_OK) return st;
+    }
+    return MW_OK;
 }
 
 // accessors for the Davidson driver (not exported)
@@ -481,7 +711,9 @@ mw_status mw_csf_upload(mw_csf csf, void *workspace, size_t bytes, mw_stream_t s
               up(d.cfg_dets, C.cfg_dets.data(), C.cfg_dets.size() * 4) &&
               up(d.cfg_csf, C.cfg_csf.data(), C.cfg_csf.size() * 4) &&
               up(d.cfg_tab, C.cfg_tab.data(), C.cfg_tab.size() * 4) &&
-              up(d.csf_cfg, C.csf_cfg.data(), C.csf_cfg.size() * 4) && up(d.tab, C.tab.data(), C.tab.size() * 8);
+              up(d.csf_cfg, C.csf_cfg.data(), C.csf_cfg.size() * 4) && up(d.tab, C.tab.data(), C.tab.size() * 8) &&
+              up(d.tabT, C.tabT.data(), C.tabT.size() * 8) && up(d.cls_dets, C.cls_dets.data(), C.cls_dets.size() * 4) &&
+              up(d.cls_csf0, C.cls_csf0.data(), C.cls_csf0.size() * 4);
     if (!ok) return fail(MW_EHIP, "hipMemcpyAsync failed during CSF upload");
     // the host vectors are read by the copies above: wait before returning
     if (hipStreamSynchronize(s) != hipSuccess) return fail(MW_EHIP, "hipStreamSynchronize failed after CSF upload");
@@ -499,9 +731,12 @@ mw_status mw_csf_to_det(mw_csf csf, int32_t nroots, const double *x, double *y, 
     if (items == 0) return MW_OK;
     // one dispatch counts its work-items in 32 bits
     if (items > ((int64_t)1 << 32) - 256) return fail(MW_EUNSUPPORTED, "too many determinants x roots");
-    hipLaunchKernelGGL(k_csf_to_det, dim3(grid_of(items)), dim3(256), 0, (hipStream_t)stream, csf->dev, nroots, x, y);
-    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
-    return MW_OK;
+    if (csf->small_det > 0) {
+        hipLaunchKernelGGL(k_csf_to_det, dim3(grid_of(items)), dim3(256), 0, (hipStream_t)stream, csf->dev, nroots, x,
+                           y);
+        if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
+    }
+    return launch_cls(*csf, nroots, x, y, (hipStream_t)stream, true);
 }
 
 mw_status mw_csf_from_det(mw_csf csf, int32_t nroots, const double *y, double *x, mw_stream_t stream)
@@ -512,10 +747,12 @@ mw_status mw_csf_from_det(mw_csf csf, int32_t nroots, const double *y, double *x
     const int64_t items = csf->ncsf * nroots;
     if (items == 0) return MW_OK;
     if (items > ((int64_t)1 << 32) - 256) return fail(MW_EUNSUPPORTED, "too many CSFs x roots");
-    hipLaunchKernelGGL(k_csf_from_det, dim3(grid_of(items)), dim3(256), 0, (hipStream_t)stream, csf->dev, nroots, y,
-                       x);
-    if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
-    return MW_OK;
+    if (csf->small_csf > 0) {
+        hipLaunchKernelGGL(k_csf_from_det, dim3(grid_of(items)), dim3(256), 0, (hipStream_t)stream, csf->dev, nroots,
+                           y, x);
+        if (hipGetLastError() != hipSuccess) return fail(MW_EHIP, "CSF kernel launch failed");
+    }
+    return launch_cls(*csf, nroots, y, x, (hipStream_t)stream, false);
 }
 
 mw_status mw_csf_sigma(mw_csf csf, int32_t nroots, const double *c, double *sigma, double *work, mw_stream_t stream)
