@@ -131,3 +131,12 @@ def test_device_plan_full_size(torch):
     ph, pd = _compare(torch, mw, "sci-n64-2e6", prob)
     c = torch.from_numpy(synth.ci_vectors(prob.ndet, 1, np.random.default_rng(5))).cuda()
     assert torch.equal(ph.sigma(c), pd.sigma(c))
+
+
+def test_device_plan_full_size_spinor(torch):
+    """The 1,000,000-determinant 40-pair spinor space: the same arrays."""
+    from paper_2501_18185_amd import mw
+    prob = synth.workload(2)
+    ph, pd = _compare(torch, mw, "spinor-40kp-1e6", prob)
+    c = torch.from_numpy(synth.ci_vectors(prob.ndet, 1, np.random.default_rng(6), complex_=True)).cuda()
+    assert torch.equal(ph.sigma(c), pd.sigma(c))
