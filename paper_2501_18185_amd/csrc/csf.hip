@@ -555,14 +555,14 @@ template <int RC, int NB>
 static mw_status launch_cls_nb(const DevCsf &dev, const mw_csf_s::Cls &k, const CsfClass &cl, size_t lds, int R,
                                int r0, const double *in, double *out, hipStream_t s, bool to_det)
 {
-    static std::once_flag once;
-    std::call_once(once, []() {
-        // LDS beyond 64 KB for one configuration of 3432 placements and 4 roots
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_csf_to_det_cls<RC, NB>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_csf_from_det_cls<RC, NB>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    });
+    if (lds > 64 * 1024) {
+        // one configuration of up to 3432 placements and 4 roots (set on the
+        // current device before each such launch)
+        const void *fn = to_det ? reinterpret_cast<const void *>(&k_csf_to_det_cls<RC, NB>)
+                                : reinterpret_cast<const void *>(&k_csf_from_det_cls<RC, NB>);
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return fail(MW_EHIP, "CSF class kernel: LDS attribute not set");
+    }
     const unsigned ny = (unsigned)std::min<uint32_t>((k.count + NB - 1) / NB, 65535u);
     if (to_det)
         hipLaunchKernelGGL((k_csf_to_det_cls<RC, NB>), dim3((k.nd + 255) / 256, ny), dim3(256), lds, s, dev,

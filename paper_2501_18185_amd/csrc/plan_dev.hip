@@ -1092,11 +1092,8 @@ mw_status build_index_device(HostPlan &P, hipStream_t s)
     }
 
     // ---- 7: density rows ----
-    const uint32_t nmd = P.npacket_double > 0 ? [&]() {
-        uint32_t v = 0;
-        (void)down(&v, X.pk_off + P.npacket_double, 1, s);
-        return v;
-    }() : 0u;
+    uint32_t nmd = 0;  // memberships of double groups
+    if (P.npacket_double > 0) CK(down(&nmd, X.pk_off + P.npacket_double, 1, s));
     P.nmem_double = nmd;
     P.rdm_single_e0 = 0;
     for (auto &c : P.rdm_cls) c = 0;

@@ -237,14 +237,16 @@ def test_csf_twelve_open_shells_equals_oracle(torch):
 def test_csf_fourteen_open_shells_properties(torch, two_s):
     """The largest open-shell count (14; 3432 or 3003 determinants, 429 or
     1001 CSFs, the largest coupling table): T^T T = 1 and a symmetric CSF
-    Hamiltonian."""
+    Hamiltonian, for four roots."""
     n = 14
     na = 7 + two_s // 2
     prob = _prob(n, na, n - na, _all_open(n, na), seed=32)
     _say(f"case all-open n=14, 2S={two_s}: ndet {prob.ndet}")
-    pl, cb = _basis(prob, 2)
+    # four roots: one configuration's 3432 signed determinant values need
+    # 110 KB of LDS in the batched transform
+    pl, cb = _basis(prob, 4)
     assert cb.ncsf == len(csf.paths(14, two_s)) and cb.info("max_open") == 14
-    c = np.random.default_rng(7).standard_normal((cb.ncsf, 2))
+    c = np.random.default_rng(7).standard_normal((cb.ncsf, 4))
     gc = _dev(torch, c)
     assert _rel(cb.from_det(cb.to_det(gc)).cpu().numpy(), c) < 1e-13
     s = cb.sigma(gc).cpu().numpy()
