@@ -24,9 +24,12 @@
  * out [ndet][nroots] (roots contiguous), in that scalar type.
  *
  * Memory ownership: problem data (dets, h, g) are HOST pointers read only
- * during mw_plan_create.  Every other buffer argument is a DEVICE pointer
- * owned by the caller unless marked host.  libmw never allocates or frees
- * device memory: a plan lives in a caller-provided device workspace.
+ * during mw_plan_create (or mw_plan_create_device).  Every other buffer
+ * argument is a DEVICE pointer owned by the caller unless marked host.  A
+ * plan lives in a caller-provided device workspace; libmw allocates device
+ * memory only inside mw_plan_create_device (its sort temporaries, freed
+ * before it returns, and the index it hands to the first mw_plan_upload,
+ * freed there).
  *
  * Streams: device work is enqueued on the given hipStream_t (0 = default
  * stream) and is asynchronous unless stated otherwise.
