@@ -154,13 +154,15 @@ class Plan:
     ``ecore``.  ``upload=False`` builds the host plan only (no GPU needed),
     which is enough for :meth:`info`.  ``build="device"`` groups the
     determinants on the current GPU (``mw_plan_create_device``: the same
-    arrays as the host build) and always uploads.
+    arrays as the host build) and always uploads; ``build="auto"`` (the
+    default) does so when the plan is uploaded, and takes the host build
+    when the space is beyond the device build's limits (MW_EUNSUPPORTED).
     """
 
     def __init__(self, problem, max_roots: int = 1, device: str = "cuda", upload: bool = True,
-                 build: str = "host"):
-        if build not in ("host", "device"):
-            raise ValueError("build must be 'host' or 'device'")
+                 build: str = "auto"):
+        if build not in ("auto", "host", "device"):
+            raise ValueError("build must be 'auto', 'host' or 'device'")
         L = lib()
         self.kind = MW_SPIN_FREE if problem.kind == "spinfree" else MW_SPINOR
         self.is_complex = self.kind == MW_SPINOR
@@ -177,11 +179,18 @@ class Plan:
         pr = _Problem(self.kind, self.norb, int(problem.nalpha), int(problem.nbeta), self.ndet,
                       self._dets.ctypes.data, self._h.ctypes.data, self._g.ctypes.data, float(problem.ecore))
         h = C.c_void_p()
-        if build == "device":
-            _require_gpu()
-            _check(L.mw_plan_create_device(C.byref(pr), self.max_roots, _stream(), C.byref(h)))
-            upload = True
-        else:
+        on_device = build == "device" or (build == "auto" and upload)
+        if on_device:
+            torch = _require_gpu()
+            dev = torch.device(device)
+            with torch.cuda.device(dev if dev.index is not None else torch.cuda.current_device()):
+                st = L.mw_plan_create_device(C.byref(pr), self.max_roots, _stream(), C.byref(h))
+            if st == -8 and build == "auto":  # MW_EUNSUPPORTED: beyond the device build's limits
+                on_device = False
+            else:
+                _check(st)
+                upload = True
+        if not on_device:
             _check(L.mw_plan_create(C.byref(pr), self.max_roots, C.byref(h)))
         self._plan = h
         # the integrals are repacked inside the plan; drop the big host copies

@@ -66,7 +66,7 @@ def _spaces():
 
 def _compare(torch, mw, name, prob, max_roots=1):
     t0 = time.perf_counter()
-    ph = mw.Plan(prob, max_roots=max_roots)
+    ph = mw.Plan(prob, max_roots=max_roots, build="host")
     t1 = time.perf_counter()
     pd = mw.Plan(prob, max_roots=max_roots, build="device")
     torch.cuda.synchronize()
