@@ -304,3 +304,37 @@ def test_csf_ivi_interior_singlets(torch, seed):
     c1[int(np.argmin(dgc)), 0] = 1.0
     ev1, _, it1, conv1 = cb.ivi(_dev(torch, c1), tol=1e-9, max_iter=300)
     assert conv1 and abs(ev1[0] - e[0]) < 1e-10 * max(1.0, abs(e[0]))
+
+
+@pytest.mark.parametrize("R", [1, 3])
+def test_csf_batched_transforms_equal_oracle(torch, R):
+    """1101 configurations with 10 open shells (252 determinants and 42
+    singlets each): the transforms stage two configurations per block (and
+    one in the last, padded batch).  T c and T^T y of configurations at
+    several batch positions against the oracle's configuration blocks."""
+    n, na = 14, 6
+    d = synth.space_open_shell_rich(n, na, (10,), 1101, np.random.default_rng(41))
+    prob = _prob(n, na, na, d, seed=42)
+    _say(f"case batched open-shell transforms: ndet {prob.ndet}, {R} roots")
+    pl, cb = _basis(prob, R)
+    assert cb.info("configurations") == 1101 and cb.ncsf == 1101 * 42
+    rng = np.random.default_rng(43 + R)
+    x = rng.standard_normal((cb.ncsf, R))
+    y = rng.standard_normal((prob.ndet, R))
+    gx = cb.to_det(_dev(torch, x)).cpu().numpy()
+    gy = cb.from_det(_dev(torch, y)).cpu().numpy()
+    cfgs, of = csf.configurations(prob.dets)
+    index = {(int(a), int(b)): i for i, (a, b) in enumerate(prob.dets)}
+    for c in (0, 1, 2, 513, 1098, 1099, 1100):
+        block, f = csf.config_block(cfgs[c][0], cfgs[c][1], n, 0)
+        assert f == 42
+        tx = np.zeros((prob.ndet, R))
+        ty = np.zeros((f, R))
+        for mu, w0, w1, v in block:
+            i = index[(w0, w1)]
+            tx[i] += v * x[42 * c + mu]
+            ty[mu] += v * y[i]
+        rows = np.flatnonzero(of == c)
+        assert len(rows) == 252
+        assert _rel(gx[rows], tx[rows]) < TOL, c
+        assert _rel(gy[42 * c:42 * c + 42], ty) < TOL, c
