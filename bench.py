@@ -19,6 +19,10 @@ Further legs reported in the same line (skip with --legs none):
             spin, 1e4-5e5 determinants) with 4 roots each: one graph-replayed
             persistent launch vs 16 plain 4-root calls vs 64 plain 1-root
             calls;
+  batched_small
+            32 small spin-free problems (16-20 orbitals, 5-6 electrons per
+            spin, 8e3-2e4 determinants), 4 roots: the graph vs 32 plain
+            4-root calls;
   spinor    complex sigma over 40 Kramers pairs, 20 electrons, 1e6
             determinants;
   rdm       forward sigma + energy and backward density matrices (gamma,
@@ -38,7 +42,7 @@ Further legs reported in the same line (skip with --legs none):
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
                        [--workload sci-n64|fci-n8|spinor-40kp|fci-n10]
-                       [--cpu-rows 30000] [--legs batched,spinor,rdm,davidson,ivi,pt2,csf|none]
+                       [--cpu-rows 30000] [--legs batched,batched_small,spinor,rdm,davidson,ivi,pt2,csf|none]
 """
 from __future__ import annotations
 
@@ -99,7 +103,7 @@ def main():
     ap.add_argument("--roots", type=int, default=1)
     ap.add_argument("--workload", default="sci-n64", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=30000, help="rows of the CPU oracle sample (0: skip)")
-    ap.add_argument("--legs", default="batched,spinor,rdm,davidson,ivi,pt2,csf")
+    ap.add_argument("--legs", default="batched,batched_small,spinor,rdm,davidson,ivi,pt2,csf")
     ap.add_argument("--plan", default="device", choices=["device", "host"],
                     help="where the plan's grouping is built (the arrays are the same)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -250,6 +254,8 @@ def main():
         out["legs"]["pt2"] = leg_pt2()
     if "csf" in legs:
         out["legs"]["csf"] = leg_csf(args.steps)
+    if "batched_small" in legs:
+        out["legs"]["batched_small"] = leg_batched_small()
 
     if args.cpu_rows > 0:
         from oracle import sc
@@ -479,6 +485,35 @@ def leg_batched():
             "speedup_vs_16x4": t_plain4 / t_batched, "speedup_vs_64x1": t_plain1 / t_batched,
             "grad_batched_ms": t_grad_batched, "grad_plain_16_ms": t_grad_plain,
             "grad_speedup": t_grad_plain / t_grad_batched}
+
+
+def leg_batched_small():
+    """32 small problems x 4 roots (each far from filling the GPU alone):
+    batched graph vs 32 plain launches, where batching pays off."""
+    import torch
+    from paper_2501_18185_amd import mw, synth
+    t0 = time.perf_counter()
+    probs = []
+    for i in range(32):
+        n, ne = 16 + i % 5, 5 + i % 2
+        rng = synth.rng_for(8, i, synth.SEED_SPACE)
+        d = synth.space_selected_spinfree(n, ne, ne, 8000 + 400 * i, rng)
+        probs.append(synth.Problem("spinfree", n, ne, ne, d, synth.one_body_real(n, synth.rng_for(8, i, synth.SEED_H)),
+                                   synth.two_body_real(n, synth.rng_for(8, i, synth.SEED_G))))
+    plans = [mw.Plan(p, max_roots=4) for p in probs]
+    R = 4
+    cs = [torch.from_numpy(synth.ci_vectors(p.ndet, R, synth.rng_for(8, i, synth.SEED_C))).cuda()
+          for i, p in enumerate(probs)]
+    outs = [torch.empty_like(c) for c in cs]
+    ndet = sum(p.ndet for p in probs)
+    log(f"[bench] batched small: 32 problems, {ndet} dets, ready in {time.perf_counter() - t0:.1f}s")
+    mw.autotune_batched(plans, cs, outs)
+    t_batched = _time(lambda: mw.sigma_batched(plans, cs, outs), 20)
+    t_plain = _time(lambda: [pl.sigma(c, out=o) for pl, c, o in zip(plans, cs, outs)], 20)
+    log(f"[bench] batched small: graph {t_batched:.3f} ms, 32x4-root {t_plain:.3f} ms")
+    return {"workload": "batch32-n16..20-5..6e-8e3..2e4-R4", "ndet_total": ndet,
+            "pairs_total": sum(pl.info("pairs") for pl in plans),
+            "batched_graph_ms": t_batched, "plain_32x4_ms": t_plain, "speedup": t_plain / t_batched}
 
 
 def leg_pt2():
