@@ -26,6 +26,7 @@
 // under its row, a workgroup sums a chunk of a row's list in LDS and adds the
 // row to the accumulator once.
 #include <hip/hip_runtime.h>
+#include <mutex>
 
 #include <algorithm>
 #include <type_traits>
@@ -967,6 +968,67 @@ static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CP
     return MW_OK;
 }
 
+// A second stream per device for the occupation correlations and the
+// single-pair rows: they fill other accumulators than the double-pair rows,
+// so they run beside the bra gather and the double rows (the single rows
+// after the gather, which they read) and are joined before the final pass.  The fork and
+// join events are shared, so the launch sequence holds a lock; a caller
+// stream that is being captured into a graph gets the serial order.
+namespace {
+struct RdmSide {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, xready = nullptr, join = nullptr;
+    bool failed = false;
+};
+std::mutex g_rdm_side_mu;
+RdmSide g_rdm_side[64];
+
+RdmSide *rdm_side_locked()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    RdmSide &x = g_rdm_side[dev];
+    if (!x.s && !x.failed) {
+        if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&x.xready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
+            x.failed = true;
+            x.s = nullptr;
+        }
+    }
+    return x.s ? &x : nullptr;
+}
+
+// the side stream waits for the gathered bra (k_rdm_x on s)
+bool rdm_wait_x(hipStream_t s, RdmSide *x)
+{
+    if (!x) return true;
+    return hipEventRecord(x->xready, s) == hipSuccess && hipStreamWaitEvent(x->s, x->xready, 0) == hipSuccess;
+}
+
+// fork: work enqueued on the returned stream runs beside s (s itself when
+// s is being captured or no side stream exists); the lock stays held
+hipStream_t rdm_fork(hipStream_t s, std::unique_lock<std::mutex> &lk, RdmSide *&x)
+{
+    x = nullptr;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return s;
+    lk.lock();
+    RdmSide *y = rdm_side_locked();
+    if (!y || hipEventRecord(y->fork, s) != hipSuccess || hipStreamWaitEvent(y->s, y->fork, 0) != hipSuccess)
+        return s;
+    x = y;
+    return y->s;
+}
+
+bool rdm_join(hipStream_t s, RdmSide *x)
+{
+    if (!x) return true;
+    return hipEventRecord(x->join, x->s) == hipSuccess && hipStreamWaitEvent(s, x->join, 0) == hipSuccess;
+}
+}  // namespace
+
 mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, const double *weights,
                      const double *dev_weights, void *gamma, void *Gamma, double fac_g, bool conj, hipStream_t s)
 {
@@ -988,29 +1050,39 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         double *xb = (double *)((char *)p.partial + ((((size_t)(part - dab) + RDM_OCC_CHUNKS * mm) * 8 + 255) &
                                                      ~(size_t)255));
         zero(dab, n4 + 2 * np2 + RDM_COPIES * cs, s);
+        std::unique_lock<std::mutex> lk(g_rdm_side_mu, std::defer_lock);
+        RdmSide *side = nullptr;
+        const hipStream_t s2 = rdm_fork(s, lk, side);
+        // beside the bra gather and the double rows (s2): the occupation
+        // correlations, then (once the gathered bra is there) the single
+        // rows and their folds
+        ProfToken t = prof_begin("rdm_diag", s2);
+        hipLaunchKernelGGL(k_rdm_occ_lds<false>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 127) / 128)), dim3(1024), 0, s2,
+                           p, R, (const double *)bra, (const double *)ket, W, part);
+        hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s2, M, RDM_OCC_CHUNKS,
+                           (const double *)part, D);
+        prof_end(t, s2);
         launch_rdm_x<false>(p, R, (const double *)bra, xb, s);
-        ProfToken t = prof_begin("rdm_double", s);
-        mw_status st = launch_rdm_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, dab, dt0, xb, s);
-        prof_end(t, s);
+        if (!rdm_wait_x(s, side)) return fail(MW_EHIP, "ordering the density-matrix side stream failed");
+        t = prof_begin("rdm_single", s2);
+        mw_status st = launch_rdm_single_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, S, Cc, Ee,
+                                                     xb, cs, s2);
+        prof_end(t, s2);
         if (st != MW_OK) return st;
-        t = prof_begin("rdm_single", s);
-        st = launch_rdm_single_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, S, Cc, Ee, xb, cs,
-                                           s);
-        prof_end(t, s);
-        if (st != MW_OK) return st;
-        hipLaunchKernelGGL(k_rdm_fold<double>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
+        hipLaunchKernelGGL(k_rdm_fold<double>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s2, S, cs,
                            RDM_COPIES);
         if (sym) {
             hipLaunchKernelGGL(k_rdm_mirror<double>, dim3((unsigned)((2 * (int64_t)n * n + 255) / 256)), dim3(256), 0,
-                               s, S, n, 1, 2);
-            hipLaunchKernelGGL(k_rdm_mirror_qxp<double>, dim3((unsigned)((2 * n3 + 255) / 256)), dim3(256), 0, s, Cc,
+                               s2, S, n, 1, 2);
+            hipLaunchKernelGGL(k_rdm_mirror_qxp<double>, dim3((unsigned)((2 * n3 + 255) / 256)), dim3(256), 0, s2, Cc,
                                n, 2);
         }
-        t = prof_begin("rdm_diag", s);
-        hipLaunchKernelGGL(k_rdm_occ_lds<false>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 127) / 128)), dim3(1024), 0, s,
-                           p, R, (const double *)bra, (const double *)ket, W, part);
-        hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
-                           (const double *)part, D);
+        t = prof_begin("rdm_double", s);
+        st = launch_rdm_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, dab, dt0, xb, s);
+        prof_end(t, s);
+        if (st != MW_OK) return st;
+        if (!rdm_join(s, side)) return fail(MW_EHIP, "joining the density-matrix side stream failed");
+        t = prof_begin("rdm_final", s);
         hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, dab, dt0, dt1,
                            S, Cc, Ee, D, (double *)gamma, (double *)Gamma, (int)sym, fac_g);
         prof_end(t, s);
@@ -1023,29 +1095,37 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         double2 *xb = (double2 *)((char *)p.partial + ((((size_t)(part - dt0) + RDM_OCC_CHUNKS * mm) * 16 + 255) &
                                                        ~(size_t)255));
         zero((double *)dt0, 2 * (2 * np2 + RDM_COPIES * cs), s);
+        std::unique_lock<std::mutex> lk(g_rdm_side_mu, std::defer_lock);
+        RdmSide *side = nullptr;
+        const hipStream_t s2 = rdm_fork(s, lk, side);
+        ProfToken t = prof_begin("rdm_diag", s2);
+        hipLaunchKernelGGL(k_rdm_occ_lds<true>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(1024), 0, s2, p,
+                           R, (const double2 *)bra, (const double2 *)ket, W, part);
+        hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s2, M, RDM_OCC_CHUNKS,
+                           (const double2 *)part, D);
+        prof_end(t, s2);
         launch_rdm_x<true>(p, R, (const double2 *)bra, xb, s);
-        ProfToken t = prof_begin("rdm_double", s);
-        mw_status st = launch_rdm_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym,
-                                             (double2 *)nullptr, dt0, xb, s);
-        prof_end(t, s);
+        if (!rdm_wait_x(s, side)) return fail(MW_EHIP, "ordering the density-matrix side stream failed");
+        t = prof_begin("rdm_single", s2);
+        mw_status st = launch_rdm_single_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym, S, Cc,
+                                                    (double *)nullptr, xb, cs, s2);
+        prof_end(t, s2);
         if (st != MW_OK) return st;
-        t = prof_begin("rdm_single", s);
-        st = launch_rdm_single_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym, S, Cc,
-                                          (double *)nullptr, xb, cs, s);
-        prof_end(t, s);
-        if (st != MW_OK) return st;
-        hipLaunchKernelGGL(k_rdm_fold<double2>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s, S, cs,
+        hipLaunchKernelGGL(k_rdm_fold<double2>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s2, S, cs,
                            RDM_COPIES);
         if (sym) {
-            hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s, S, M, 1, 1);
-            hipLaunchKernelGGL(k_rdm_mirror_qxp<double2>, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s, Cc, M,
+            hipLaunchKernelGGL(k_rdm_mirror<double2>, dim3((unsigned)((mm + 255) / 256)), dim3(256), 0, s2, S, M, 1,
+                               1);
+            hipLaunchKernelGGL(k_rdm_mirror_qxp<double2>, dim3((unsigned)((m3 + 255) / 256)), dim3(256), 0, s2, Cc, M,
                                1);
         }
-        t = prof_begin("rdm_diag", s);
-        hipLaunchKernelGGL(k_rdm_occ_lds<true>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(1024), 0, s, p,
-                           R, (const double2 *)bra, (const double2 *)ket, W, part);
-        hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s, M, RDM_OCC_CHUNKS,
-                           (const double2 *)part, D);
+        t = prof_begin("rdm_double", s);
+        st = launch_rdm_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym, (double2 *)nullptr, dt0,
+                                   xb, s);
+        prof_end(t, s);
+        if (st != MW_OK) return st;
+        if (!rdm_join(s, side)) return fail(MW_EHIP, "joining the density-matrix side stream failed");
+        t = prof_begin("rdm_final", s);
         hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, dt0, dt1, S,
                            Cc, D, (double2 *)gamma, (double2 *)Gamma, (int)sym, fac_g, (int)conj);
         prof_end(t, s);
