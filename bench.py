@@ -370,9 +370,17 @@ def leg_rdm(plan, c, prob):
     log(f"[bench] rdm: forward {t_fwd:.2f} ms, backward {t_bwd:.2f} ms (double pairs {md / max(nd, 1):.2f} ms; "
         f"beside them single pairs {ms_ / max(ns, 1):.2f} ms and occupation correlations {mq / max(nq, 1):.2f} ms; "
         f"final pass {mf / max(nf, 1):.2f} ms)")
+    # the fixed-point mode (integer atomics, order-independent bits)
+    plan.rdm_fixed_point = True
+    try:
+        t_fix = _time(lambda: plan.rdm(c1, c1), 3, warmup=1)
+    finally:
+        plan.rdm_fixed_point = False
+    log(f"[bench] rdm: backward in fixed point {t_fix:.2f} ms")
     return {"workload": prob.name, "forward_ms": t_fwd, "backward_ms": t_bwd,
             "rdm_double_ms": md / max(nd, 1), "rdm_single_ms": ms_ / max(ns, 1), "rdm_occ_ms": mq / max(nq, 1),
-            "rdm_final_ms": mf / max(nf, 1), "gamma_shape": [prob.norb] * 2, "Gamma_shape": [prob.norb] * 4}
+            "rdm_final_ms": mf / max(nf, 1), "backward_fixed_point_ms": t_fix,
+            "gamma_shape": [prob.norb] * 2, "Gamma_shape": [prob.norb] * 4}
 
 
 def leg_davidson(plan, prob, iters=10):

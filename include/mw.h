@@ -149,7 +149,8 @@ mw_status mw_plan_destroy(mw_plan plan);
  * groups of 64 members or more (evaluated once per unordered pair), 15
  * double memberships listed under the density-matrix rows of their added
  * pairs, 16 chunks of those lists (workgroups of the double-pair density
- * kernel), 17 1 when the grouping was built on the device, else 0.
+ * kernel), 17 1 when the grouping was built on the device, else 0,
+ * 18 the density-matrix mode (mw_plan_set_rdm_mode).
  * Returns -1 for an unknown plan or index. */
 int64_t mw_plan_info(mw_plan plan, int32_t what);
 
@@ -218,13 +219,31 @@ mw_status mw_diag(mw_plan plan, void *out, mw_stream_t stream);
  * Gamma [n][n][n][n] real; spinor: [M][M] and [M]^4 complex.  bra, ket
  * device [ndet][nroots]; weights HOST [nroots] or NULL (all 1); gamma, Gamma
  * device outputs, overwritten.  For E = c^H H c, dE/dh = gamma and dE/dg =
- * Gamma / 2.  Connectivity is recomputed, never stored.  Uses device atomics:
- * results are reproducible to rounding, not bitwise.  When bra and ket are
+ * Gamma / 2.  Connectivity is recomputed, never stored.  The plan's
+ * density-matrix mode (mw_plan_set_rdm_mode) decides how contributions are
+ * summed: floating-point atomics (default; reproducible to rounding, not
+ * bitwise) or 64-bit fixed point (the same bits on every call).  When bra and ket are
  * the same pointer, each unordered pair is visited once and the reversed
  * pair's contribution (the complex conjugate) is added in the final pass:
  * the same matrices to rounding, half the atomics. */
 mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *bra, const void *ket,
                           const double *weights, void *gamma, void *Gamma, mw_stream_t stream);
+
+/* Density-matrix mode of the plan, for mw_rdm_backward, mw_energy_backward,
+ * mw_sigma_backward and the batched backward.  The sums of section 3.4's
+ * density matrices over connected pairs are order-independent in exact
+ * arithmetic; in floating point the atomics make them depend on arrival
+ * order.  mode 0 (default): floating-point atomics.  mode 1: every
+ * contribution v is rounded to the integer nearest v 2^s and summed with
+ * 64-bit integer atomics (exact and associative, also where a partial sum
+ * wraps), then scaled back by 2^-s, so the results do not depend on the
+ * order of arrival, the launch configuration or stream overlap: the same
+ * inputs give the same bits.  s is set per call on the device from
+ * B = max_k |w_k| ||bra||_F ||ket||_F, which bounds every accumulated entry:
+ * s = 60 - e for B in [2^(e-1), 2^e), so each contribution is rounded to
+ * at most B 2^-60 (absolute).  Scaling bra or ket by a power of two scales
+ * the results exactly.  Host only; MW_EINVAL for other modes. */
+mw_status mw_plan_set_rdm_mode(mw_plan plan, int32_t mode);
 
 /* Energies e_k = Re sum_I conj(c_Ik) sigma_Ik (the expectation value
  * c^H H c of section 2.4 when sigma = H c, unnormalised), one per root:

@@ -281,7 +281,8 @@ mw_status mw_energy_backward_batched(int32_t nprob, const mw_plan *plans, const 
         if ((grad_h[i] == nullptr) != (grad_g[i] == nullptr)) return fail(MW_EINVAL, "grad_h and grad_g go together");
         if (grad_c[i] && !sigma[i]) return fail(MW_EINVAL, "grad_c needs sigma");
         for (uintptr_t v : {(uintptr_t)plans[i], (uintptr_t)nroots[i], (uintptr_t)c[i], (uintptr_t)sigma[i],
-                            (uintptr_t)ge[i], (uintptr_t)grad_c[i], (uintptr_t)grad_h[i], (uintptr_t)grad_g[i]})
+                            (uintptr_t)ge[i], (uintptr_t)grad_c[i], (uintptr_t)grad_h[i], (uintptr_t)grad_g[i],
+                            (uintptr_t)d[i]->rdm_fixed})
             key.push_back(v);
     }
     std::lock_guard<std::mutex> lk(g_grad_mu);

@@ -92,6 +92,7 @@ struct DevPlan {
     DevPlan *self;             // device copy of this struct (for batched launches)
     uint32_t *counter;         // device work counter (batched launches)
     int32_t tune_u, tune_gl;   // tuned partner-loop unroll and gather lanes
+    int32_t rdm_fixed;         // 1: density matrices accumulated in 64-bit fixed point (order-independent)
 };
 
 struct HostPlan;
@@ -107,6 +108,10 @@ constexpr int RDM_COPIES = 32;
 // about RDM_CHUNK_WORK partner visits of one row
 constexpr int RDM_WIDE = 32;
 constexpr int64_t RDM_CHUNK_WORK = 1 << 17;
+// fixed-point density matrices: the scale and the per-block norm partials
+// of its bound, after the gathered bra coefficients in the scratch
+constexpr int RDM_FX_BLOCKS = 256;
+constexpr size_t RDM_FX_BYTES = 256 + RDM_FX_BLOCKS * 16;
 struct BatchArgs {
     int nprob;
     const DevPlan *plans[MW_MAXB];   // device copies

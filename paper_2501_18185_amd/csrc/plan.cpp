@@ -1025,19 +1025,21 @@ size_t HostPlan::layout(DevPlan *d, char *base) const
     // per-call scratch: sigma partials, or the density-matrix accumulators
     // (double pairs, RDM_COPIES copies of S and the single corrections (n^3
     // or M^3), occupation correlations and their 256 per-chunk partials)
-    // followed by the bra coefficients gathered per double membership
+    // followed by the bra coefficients gathered per double membership and
+    // the fixed-point scale
     const size_t mm = (size_t)M * M;
     size_t rdm_bytes = kind == MW_SPIN_FREE
                            ? ((size_t)n * n * n * n + 2 * (size_t)npair * npair +
                               RDM_COPIES * (2 * (size_t)n * n + 2 * (size_t)n * n * n) + 257 * mm) * 8
                            : (2 * (size_t)npair * npair + RDM_COPIES * (mm + mm * M) + 257 * mm) * 16;
-    rdm_bytes = ((rdm_bytes + 255) & ~(size_t)255) + nm * max_roots * sb;
+    rdm_bytes = ((rdm_bytes + 255) & ~(size_t)255) + ((nm * max_roots * sb + 255) & ~(size_t)255) + RDM_FX_BYTES;
     t.scratch_bytes = std::max(std::max<size_t>(1, nm + (size_t)ncol) * (size_t)max_roots * sb, rdm_bytes);
     t.partial = (void *)take(t.scratch_bytes);
     t.self = (DevPlan *)take(sizeof(DevPlan));
     t.counter = (uint32_t *)take(256);
     t.tune_u = tune_u;
     t.tune_gl = tune_gl ? tune_gl : (kind == MW_SPINOR ? 32 : 16);
+    t.rdm_fixed = rdm_fixed;
     if (d) *d = t;
     return off + 256;
 }
@@ -1315,6 +1317,7 @@ int64_t mw_plan_info(mw_plan plan, int32_t what)
     case 15: return P.counts().nrdm_ent;
     case 16: return P.counts().nrdm_chunk;
     case 17: return P.dix.on ? 1 : 0;
+    case 18: return P.rdm_fixed;
     default: return -1;
     }
 }
@@ -1361,6 +1364,15 @@ mw_status mw_plan_set_tuning(mw_plan plan, int32_t code)
     P.tune_gl = gl;
     P.dev.tune_u = u;
     P.dev.tune_gl = gl;
+    return MW_OK;
+}
+
+mw_status mw_plan_set_rdm_mode(mw_plan plan, int32_t mode)
+{
+    if (!plan) return fail(MW_EINVAL, "plan is NULL");
+    if (mode != 0 && mode != 1) return fail(MW_EINVAL, "density-matrix mode must be 0 (atomic) or 1 (fixed point)");
+    plan->p.rdm_fixed = mode;
+    plan->p.dev.rdm_fixed = mode;
     return MW_OK;
 }
 

@@ -63,6 +63,7 @@ struct HostPlan {
     // 16 gather lanes (32 for complex), the fastest measured on the n = 64
     // spin-free and 40-pair spinor spaces for one, two and four roots
     int32_t tune_u = 4, tune_gl = 0;
+    int32_t rdm_fixed = 0;
     int64_t n_single_pairs = 0, n_double_pairs = 0, n_evals = 0;
     // ordered double pairs inside groups of 64 members or more, which the
     // double-group kernel evaluates once per unordered pair

@@ -117,6 +117,63 @@ __device__ __forceinline__ void lds_add(double2 *a, double2 v)
 }
 __device__ __forceinline__ bool sc_nonzero(double v) { return v != 0.0; }
 __device__ __forceinline__ bool sc_nonzero(double2 v) { return v.x != 0.0 || v.y != 0.0; }
+
+// How the pair weights are summed.  FX = false: floating-point atomics, in
+// the order of arrival.  FX = true: each contribution v becomes the integer
+// nearest v sc (sc = 2^s, set per call from a bound on every accumulated
+// entry) and is added with 64-bit integer atomics, which are exact and
+// associative (in two's complement also where a partial sum wraps), so the
+// sums, and the doubles they are converted back to, do not depend on the
+// order of arrival.  An accumulator slot of A has the size of the scalar T.
+__device__ __forceinline__ unsigned long long fx_of(double v, double sc)
+{
+    return (unsigned long long)__double2ll_rn(v * sc);
+}
+template <bool CPLX, bool FX>
+struct RdmAcc;
+template <bool CPLX>
+struct RdmAcc<CPLX, false> {
+    using T = typename Scal<CPLX>::T;
+    using A = T;
+    static __device__ __forceinline__ A zero() { return sc_zero(T()); }
+    static __device__ __forceinline__ bool nz(A v) { return sc_nonzero(v); }
+    static __device__ __forceinline__ void lds(A *a, T v, double) { lds_add(a, v); }
+    static __device__ __forceinline__ void dev(T *a, T v, double) { atom_add(a, v); }
+    static __device__ __forceinline__ void flush(T *a, A v) { atom_add(a, v); }
+    static __device__ __forceinline__ T value(A v, double) { return v; }
+};
+template <>
+struct RdmAcc<false, true> {
+    using A = unsigned long long;
+    static __device__ __forceinline__ A zero() { return 0ULL; }
+    static __device__ __forceinline__ bool nz(A v) { return v != 0ULL; }
+    static __device__ __forceinline__ void lds(A *a, double v, double sc) { atomicAdd(a, fx_of(v, sc)); }
+    static __device__ __forceinline__ void dev(double *a, double v, double sc) { atomicAdd((A *)a, fx_of(v, sc)); }
+    static __device__ __forceinline__ void flush(double *a, A v) { atomicAdd((A *)a, v); }
+    static __device__ __forceinline__ double value(A v, double inv) { return (double)(long long)v * inv; }
+};
+template <>
+struct RdmAcc<true, true> {
+    using A = ulonglong2;
+    static __device__ __forceinline__ A zero() { return make_ulonglong2(0ULL, 0ULL); }
+    static __device__ __forceinline__ bool nz(A v) { return v.x != 0ULL || v.y != 0ULL; }
+    static __device__ __forceinline__ void lds(A *a, double2 v, double sc)
+    {
+        atomicAdd(&a->x, fx_of(v.x, sc));
+        atomicAdd(&a->y, fx_of(v.y, sc));
+    }
+    static __device__ __forceinline__ void dev(double2 *a, double2 v, double sc) { lds((A *)a, v, sc); }
+    static __device__ __forceinline__ void flush(double2 *a, A v)
+    {
+        A *d = (A *)a;
+        atomicAdd(&d->x, v.x);
+        atomicAdd(&d->y, v.y);
+    }
+    static __device__ __forceinline__ double2 value(A v, double inv)
+    {
+        return make_double2((double)(long long)v.x * inv, (double)(long long)v.y * inv);
+    }
+};
 __device__ __forceinline__ double lane_get(double v, int l)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l), hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
@@ -225,16 +282,20 @@ __device__ __forceinline__ int rdm_col(bool ab, int n, int X, int Y)
 // row r = b (b - 1) / 2 + a (same-spin positions reduced by n for beta);
 // member i of the same group is connected to the partner when their pairs
 // share no position.
-template <bool CPLX, bool SYM, bool WIDE, int RM>
+template <bool CPLX, bool SYM, bool WIDE, int RM, bool FX>
 __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
                                                   const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
-                                                  typename Scal<CPLX>::T *__restrict__ acc, int ncols, int64_t c0)
+                                                  typename Scal<CPLX>::T *__restrict__ acc, int ncols, int64_t c0,
+                                                  const double *__restrict__ fx)
 {
     using T = typename Scal<CPLX>::T;
+    using AC = RdmAcc<CPLX, FX>;
+    using A = typename AC::A;
     constexpr int RY = RM == 4 ? 4 : 1;
     constexpr int UW = 8, US = 4;  // steps of 64 visits in flight per wave (wide, small)
     extern __shared__ __align__(16) double rdm_lds_raw[];
-    T *row = (T *)rdm_lds_raw;
+    A *row = (A *)rdm_lds_raw;
+    const double sc = FX ? fx[0] : 0.0;
     const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
     const bool ab = (ch.y & 1) != 0;
     const int n = p.n;
@@ -254,7 +315,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
             yi -= n;
         }
     };
-    for (int t = threadIdx.x; t < ncols; t += blockDim.x) row[t] = sc_zero(T());
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) row[t] = AC::zero();
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t stride = blockDim.x;  // 64 entries per wave
@@ -304,7 +365,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
                     if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
                     const T w = pair_w<CPLX, RM, RY>(xv[u], yv[u], x, ket, R, ii[u],
                                                       make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16), W);
-                    lds_add(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w);
+                    AC::lds(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w, sc);
                 }
             }
         }
@@ -357,7 +418,7 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
                     if (!act[u] || xi == pa || xi == pb || yi == pa || yi == pb) continue;
                     const T w = pair_w<CPLX, RM, RY>(xv[u], yv[u], x, ket, R, ii[u],
                                                       make_uint2(djs[u] & 0x7fffffffu, (djs[u] >> 31) << 16), W);
-                    lds_add(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w);
+                    AC::lds(&row[rdm_col<CPLX>(ab, n, pi[u] & 255, (pi[u] >> 8) & 255)], w, sc);
                 }
             }
         }
@@ -365,22 +426,23 @@ __global__ __launch_bounds__(WIDE ? 256 : 512) void k_rdm_rows(DevPlan p, int R,
     __syncthreads();
     T *dst = acc + (size_t)ch.x * ncols;
     for (int t = threadIdx.x; t < ncols; t += blockDim.x) {
-        const T v = row[t];
-        if (sc_nonzero(v)) atom_add(&dst[t], v);
+        const A v = row[t];
+        if (AC::nz(v)) AC::flush(&dst[t], v);
     }
 }
 
 // The contributions of one single pair (member i with det me.x adding
 // position Xi, partner with record o adding Xj; K the group's string).
-template <bool CPLX>
+template <bool CPLX, bool FX>
 __device__ __forceinline__ void rdm_single_pair(const DevPlan &p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                 const typename Scal<CPLX>::T *__restrict__ ket, const RdmWeights &W,
                                                 typename Scal<CPLX>::T *__restrict__ S,
                                                 typename Scal<CPLX>::T *__restrict__ Cc, double *__restrict__ Ee,
                                                 uint8_t type, uint64_t k0, uint64_t k1, uint2 me, int Xi, uint32_t negi,
-                                                uint2 o)
+                                                uint2 o, double sc)
 {
     using T = typename Scal<CPLX>::T;
+    using AC = RdmAcc<CPLX, FX>;
     const int n = p.n;
     const int Xj = o.y & 255;
     T w = pair_weight<CPLX>(bra, ket, R, me.x, o.x, W);
@@ -391,7 +453,7 @@ __device__ __forceinline__ void rdm_single_pair(const DevPlan &p, int R, const t
         // the member's orbital p (varying across the lanes of a large
         // group, whose partner q is uniform) is the innermost index of
         // every single accumulator, so the lanes' atomics coalesce
-        atomicAdd(&S[((size_t)s * n + qq) * n + pp], w);
+        AC::dev(&S[((size_t)s * n + qq) * n + pp], w, sc);
         // positions where K and omega differ: words (same spin, other
         // spin); C[q][x][p] collects the Coulomb-like terms of every X,
         // E[q][x][p] the exchange-like ones of X of the same spin (both
@@ -405,13 +467,13 @@ __device__ __forceinline__ void rdm_single_pair(const DevPlan &p, int R, const t
             const double sw = (part & 1) ? -w : w;
             for (uint64_t x = bits; x; x &= x - 1) {
                 const int xx = __builtin_ctzll(x);
-                atomicAdd(&Cq[(size_t)xx * n], sw);
-                if (same) atomicAdd(&Eq[(size_t)xx * n], sw);
+                AC::dev(&Cq[(size_t)xx * n], sw, sc);
+                if (same) AC::dev(&Eq[(size_t)xx * n], sw, sc);
             }
         }
     } else {
         const int M = p.M;
-        atom_add(&S[(size_t)Xj * M + Xi], w);
+        AC::dev(&S[(size_t)Xj * M + Xi], w, sc);
         // C[Q][X][P] (M^3, P innermost) collects the four terms of every X
         T *Cq = Cc + (size_t)Xj * M * M + Xi;
         for (int part = 0; part < 4; part++) {
@@ -420,18 +482,20 @@ __device__ __forceinline__ void rdm_single_pair(const DevPlan &p, int R, const t
             const int base = (part < 2) ? 0 : n;
             const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
             const T sw = sc_neg(w, (part & 1) != 0);
-            for (uint64_t x = bits; x; x &= x - 1) atom_add(&Cq[(size_t)(base + __builtin_ctzll(x)) * M], sw);
+            for (uint64_t x = bits; x; x &= x - 1) AC::dev(&Cq[(size_t)(base + __builtin_ctzll(x)) * M], sw, sc);
         }
     }
 }
 
-template <bool CPLX, bool SYM>
+template <bool CPLX, bool SYM, bool FX>
 __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                     const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
                                                     typename Scal<CPLX>::T *__restrict__ S,
                                                     typename Scal<CPLX>::T *__restrict__ Cc,
-                                                    double *__restrict__ Ee, int64_t copy_stride)
+                                                    double *__restrict__ Ee, int64_t copy_stride,
+                                                    const double *__restrict__ fx)
 {
+    const double sc = FX ? fx[0] : 0.0;
     const int64_t wave = p.npacket_double + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (wave >= p.npacket) return;
@@ -461,7 +525,7 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
         for (uint32_t j = SYM ? mfirst + 1 : j0; j < j1; j++) {
             const uint2 o = p.mem[j];
             if (!act || (o.y & 255) == (uint32_t)Xi || (SYM && j <= m)) continue;
-            rdm_single_pair<CPLX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o);
+            rdm_single_pair<CPLX, FX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o, sc);
         }
         return;
     }
@@ -477,7 +541,7 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
     for (uint32_t j = SYM ? max(j0, m + 1) : j0; j < j1; j++) {
         const uint2 o = p.mem[j];
         if ((int)(o.y & 255) == Xi) continue;
-        rdm_single_pair<CPLX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o);
+        rdm_single_pair<CPLX, FX>(p, R, bra, ket, W, S, Cc, Ee, type, k0, k1, me, Xi, negi, o, sc);
     }
 }
 
@@ -490,22 +554,27 @@ __global__ __launch_bounds__(256) void k_rdm_single(DevPlan p, int R, const type
 // entries to copy 0 of the accumulators.  Per pair the same terms as
 // rdm_single_pair: S, then the positions where the group's string K and
 // the reference omega differ.
-template <bool CPLX, bool SYM, int RM>
+template <bool CPLX, bool SYM, int RM, bool FX>
 __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ ket,
                                                          const typename Scal<CPLX>::T *__restrict__ x, RdmWeights W,
                                                          typename Scal<CPLX>::T *__restrict__ S,
                                                          typename Scal<CPLX>::T *__restrict__ Cc,
-                                                         double *__restrict__ Ee, int64_t c0)
+                                                         double *__restrict__ Ee, int64_t c0,
+                                                         const double *__restrict__ fx)
 {
     using T = typename Scal<CPLX>::T;
+    using AC = RdmAcc<CPLX, FX>;
+    using AR = RdmAcc<false, FX>;  // the real E block (spin-free)
+    using A = typename AC::A;
     constexpr int RY = RM == 4 ? 4 : 1;
     extern __shared__ __align__(16) double rdm_lds_raw[];
+    const double sc = FX ? fx[0] : 0.0;
     const int n = p.n, M = p.M;
     const int nS = CPLX ? M : 2 * n, nC = CPLX ? M * M : n * n;
     const int ncols = CPLX ? nS + nC : nS + 2 * nC;
-    T *lS = (T *)rdm_lds_raw, *lC = lS + nS;
-    double *lE = CPLX ? nullptr : (double *)(lS + nS + nC);
-    for (int t = threadIdx.x; t < ncols; t += blockDim.x) lS[t] = sc_zero(T());
+    A *lS = (A *)rdm_lds_raw, *lC = lS + nS;
+    typename AR::A *lE = CPLX ? nullptr : (typename AR::A *)(lS + nS + nC);
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) lS[t] = AC::zero();
     __syncthreads();
     const uint4 ch = p.rdm_chunk[c0 + blockIdx.x];
     const int q = (int)ch.x;
@@ -566,7 +635,7 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
                 const T w = pair_w<CPLX, RM, RY>(xv[u], yv[u], x, ket, R, ii[u], make_uint2(dj[u], pj[u]), W);
                 if constexpr (!CPLX) {
                     const int s = (int)sp[u], pp = Xi - s * n;
-                    lds_add(&lS[s * n + pp], w);
+                    AC::lds(&lS[s * n + pp], w, sc);
                     for (int part = 0; part < 4; part++) {
                         const bool same = part < 2;
                         const uint64_t kw = (same == (s == 0)) ? kk0[u] : kk1[u];
@@ -575,19 +644,19 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
                         const double sw = (part & 1) ? -w : w;
                         for (uint64_t b = bits; b; b &= b - 1) {
                             const int xx = __builtin_ctzll(b);
-                            lds_add(&lC[xx * n + pp], sw);
-                            if (same) lds_add(&lE[xx * n + pp], sw);
+                            AC::lds(&lC[xx * n + pp], sw, sc);
+                            if (same) AR::lds(&lE[xx * n + pp], sw, sc);
                         }
                     }
                 } else {
-                    lds_add(&lS[Xi], w);
+                    AC::lds(&lS[Xi], w, sc);
                     for (int part = 0; part < 4; part++) {
                         const uint64_t kw = (part < 2) ? kk0[u] : kk1[u];
                         const uint64_t rw = (part < 2) ? p.ref0 : p.ref1;
                         const int bpos = (part < 2) ? 0 : n;
                         const uint64_t bits = (part & 1) ? (rw & ~kw) : (kw & ~rw);
                         const T sw = sc_neg(w, (part & 1) != 0);
-                        for (uint64_t b = bits; b; b &= b - 1) lds_add(&lC[(bpos + __builtin_ctzll(b)) * M + Xi], sw);
+                        for (uint64_t b = bits; b; b &= b - 1) AC::lds(&lC[(bpos + __builtin_ctzll(b)) * M + Xi], sw, sc);
                     }
                 }
             }
@@ -597,15 +666,15 @@ __global__ __launch_bounds__(256) void k_rdm_single_rows(DevPlan p, int R, const
     // S: spin-free S[s][q][p] (lS[s n + p]); spinor S[Q][P]; C (and E) rows
     // of q: C + q nC
     for (int t = threadIdx.x; t < ncols; t += blockDim.x) {
-        const T v = lS[t];
-        if (!sc_nonzero(v)) continue;
+        const A v = lS[t];
+        if (!AC::nz(v)) continue;
         if (t < nS) {
-            if constexpr (CPLX) atom_add(&S[(size_t)q * M + t], v);
-            else atom_add(&S[((size_t)(t / n) * n + q) * n + (t % n)], v);
+            if constexpr (CPLX) AC::flush(&S[(size_t)q * M + t], v);
+            else AC::flush(&S[((size_t)(t / n) * n + q) * n + (t % n)], v);
         } else if (t < nS + nC) {
-            atom_add(&Cc[(size_t)q * nC + (t - nS)], v);
+            AC::flush(&Cc[(size_t)q * nC + (t - nS)], v);
         } else {
-            if constexpr (!CPLX) atom_add(&Ee[(size_t)q * nC + (t - nS - nC)], v);
+            if constexpr (!CPLX) AC::flush(&Ee[(size_t)q * nC + (t - nS - nC)], v);
         }
     }
 }
@@ -633,20 +702,24 @@ __device__ __forceinline__ int nth_bit(uint64_t w, int k)
 // [A0, A0 + ROWS) of D for every determinant of chunk x, a wave per
 // determinant over its pairs of occupied positions (LDS atomics: the 16
 // waves take different determinants); then it writes its rows of the
-// chunk's partial matrix.
-template <bool CPLX>
+// chunk's partial matrix (FX: the exact fixed-point sums, converted).
+template <bool CPLX, bool FX>
 __global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const typename Scal<CPLX>::T *__restrict__ bra,
                                                       const typename Scal<CPLX>::T *__restrict__ ket, RdmWeights W,
-                                                      typename Scal<CPLX>::T *__restrict__ part)
+                                                      typename Scal<CPLX>::T *__restrict__ part,
+                                                      const double *__restrict__ fx)
 {
     using T = typename Scal<CPLX>::T;
+    using AC = RdmAcc<CPLX, FX>;
+    using AT = typename AC::A;
     constexpr int ROWS = CPLX ? 64 : 128;
     constexpr int MP = 129;  // LDS row stride: rows of one column fall in different banks (132 KB)
-    __shared__ T ds[ROWS * MP];
+    __shared__ AT ds[ROWS * MP];
+    const double sc = FX ? fx[0] : 0.0, inv = FX ? fx[1] : 0.0;
     const int n = p.n, M = p.M;
     const int A0 = (int)blockIdx.y * ROWS, A1 = min(M, A0 + ROWS);
     const int rows = A1 - A0;
-    for (int t = threadIdx.x; t < rows * MP; t += blockDim.x) ds[t] = sc_zero(T());
+    for (int t = threadIdx.x; t < rows * MP; t += blockDim.x) ds[t] = AC::zero();
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int64_t chunk = (p.ndet + gridDim.x - 1) / gridDim.x;
@@ -688,7 +761,7 @@ __global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const ty
                 const int k = k0 + lane;
                 const int a = k < np2 ? k / nocc : 0, b = k < np2 ? k - a * nocc : 0;
                 const int A = __shfl(pos, a, 64), B = __shfl(pos, b, 64);
-                if (k < np2 && A >= A0 && A < A1) atom_add(ds + (size_t)(A - A0) * MP + B, w);
+                if (k < np2 && A >= A0 && A < A1) AC::lds(ds + (size_t)(A - A0) * MP + B, w, sc);
             }
             continue;
         }
@@ -700,16 +773,16 @@ __global__ __launch_bounds__(1024) void k_rdm_occ_lds(DevPlan p, int R, const ty
         for (int word = 0; word < 2; word++) {
             for (uint64_t x = word ? m1 : m0; x; x &= x - 1) {
                 const int A = __builtin_ctzll(x) + (word ? n : 0);
-                T *row = ds + (size_t)(A - A0) * MP;
-                if (o0) atom_add(row + B0, w);
-                if (o1) atom_add(row + B1, w);
+                AT *row = ds + (size_t)(A - A0) * MP;
+                if (o0) AC::lds(row + B0, w, sc);
+                if (o1) AC::lds(row + B1, w, sc);
             }
         }
       }
     }
     __syncthreads();
     T *out = part + (size_t)blockIdx.x * M * M + (size_t)A0 * M;
-    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) out[t] = ds[(t / M) * MP + t % M];
+    for (int t = threadIdx.x; t < rows * M; t += blockDim.x) out[t] = AC::value(ds[(t / M) * MP + t % M], inv);
 }
 
 template <typename T>
@@ -883,6 +956,99 @@ static void zero(double *x, int64_t n, hipStream_t s)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, x, n);
 }
 
+// Fixed-point scale sc = 2^s.  Every accumulated entry is a sum over a
+// subset of the connected pairs of one operator index of w_IJ = sum_k w_k
+// conj(bra_Ik) ket_Jk, and that operator takes each determinant to at most
+// one other, so by Cauchy-Schwarz |entry| <= B = max_k |w_k| ||bra||_F
+// ||ket||_F; with B in [2^(e-1), 2^e), s = 60 - e keeps |entry sc| < 2^60.
+// The norms: per-block sums of squares over a fixed partition (a
+// grid-stride loop of RDM_FX_BLOCKS blocks, a tree in LDS), added in block
+// order by one block, so the scale is the same on every call.
+__device__ __forceinline__ void block_tree2(double *a, double *b)
+{
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            a[threadIdx.x] += a[threadIdx.x + o];
+            b[threadIdx.x] += b[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rdm_fx_norms(int64_t nb, const double *__restrict__ bra, int64_t nk,
+                                                      const double *__restrict__ ket, double *__restrict__ part)
+{
+    __shared__ double sa[256], sb[256];
+    const int64_t G = (int64_t)gridDim.x * blockDim.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nb; t += G) a += bra[t] * bra[t];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nk; t += G) b += ket[t] * ket[t];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    block_tree2(sa, sb);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa[0];
+        part[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
+// fx[0] = 2^s, fx[1] = 2^-s (sym: the ket is the bra)
+__global__ __launch_bounds__(256) void k_rdm_fx_scale(const double *__restrict__ part, int sym, RdmWeights W, int R,
+                                                      double *__restrict__ fx)
+{
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < RDM_FX_BLOCKS; i += blockDim.x) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    block_tree2(sa, sb);
+    if (threadIdx.x != 0) return;
+    double wmax = 0.0;
+    for (int k = 0; k < R; k++) wmax = fmax(wmax, fabs(W.dev ? W.dev[k] : W.w[k]));
+    const double nb = sqrt(sa[0]), nk = sym ? nb : sqrt(sb[0]);
+    const double big = 1.79e308;
+    int s = 0;
+    if (wmax > 0.0 && nb > 0.0 && nk > 0.0 && wmax <= big && nb <= big && nk <= big) {
+        // the exponent of the product without forming it (no overflow)
+        int ew, eb, ek, em;
+        const double fw = frexp(wmax, &ew), fb = frexp(nb, &eb), fk = frexp(nk, &ek);
+        frexp(fw * fb * fk, &em);
+        s = max(-1000, min(1000, 60 - (ew + eb + ek + em)));
+    }
+    fx[0] = ldexp(1.0, s);
+    fx[1] = ldexp(1.0, -s);
+}
+
+// the fixed-point accumulators back to doubles, in place
+__global__ __launch_bounds__(256) void k_rdm_fx_float(double *X, int64_t n, const double *__restrict__ fx)
+{
+    const double inv = fx[1];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        X[t] = (double)__double_as_longlong(X[t]) * inv;
+}
+
+static void fx_float(double *x, int64_t n, const double *fx, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_rdm_fx_float, dim3((unsigned)blocks), dim3(256), 0, s, x, n, fx);
+}
+
+// scale of one call: norms of bra and ket (nd doubles each)
+static void fx_scale(const void *bra, const void *ket, int64_t nd, bool sym, const RdmWeights &W, int R, double *fx,
+                     hipStream_t s)
+{
+    double *part = fx + 32;
+    hipLaunchKernelGGL(k_rdm_fx_norms, dim3(RDM_FX_BLOCKS), dim3(256), 0, s, nd, (const double *)bra,
+                       sym ? (int64_t)0 : nd, (const double *)ket, part);
+    hipLaunchKernelGGL(k_rdm_fx_scale, dim3(1), dim3(256), 0, s, (const double *)part, (int)sym, W, R, fx);
+}
+
 // x per membership (k_rdm_x), before the row kernels
 template <bool CPLX>
 static void launch_rdm_x(const DevPlan &p, int R, const typename Scal<CPLX>::T *bra, typename Scal<CPLX>::T *x,
@@ -901,33 +1067,37 @@ template <bool CPLX>
 static mw_status launch_rdm_single_rows(const DevPlan &p, int R, const typename Scal<CPLX>::T *bra,
                                         const typename Scal<CPLX>::T *ket, const RdmWeights &W, bool sym,
                                         typename Scal<CPLX>::T *S, typename Scal<CPLX>::T *Cc, double *Ee,
-                                        const typename Scal<CPLX>::T *x, int64_t copy_stride, hipStream_t s)
+                                        const typename Scal<CPLX>::T *x, int64_t copy_stride, const double *fx,
+                                        hipStream_t s)
 {
     const int n = p.n, M = p.M;
+    const bool fxm = fx != nullptr;
     const size_t lds = CPLX ? (size_t)(M + (size_t)M * M) * 16 : (size_t)(2 * n + 2 * (size_t)n * n) * 8;
     if (lds <= 160 * 1024) {
         const int64_t c0 = p.rdm_cls[4], nch = p.rdm_cls[5] - c0;
         if (nch <= 0) return MW_OK;
-        auto pick = [&](auto rm) {
+        auto pick = [&](auto rm, auto fc) {
             constexpr int RM = decltype(rm)::value;
-            return sym ? k_rdm_single_rows<CPLX, true, RM> : k_rdm_single_rows<CPLX, false, RM>;
+            constexpr bool F = decltype(fc)::value;
+            return sym ? k_rdm_single_rows<CPLX, true, RM, F> : k_rdm_single_rows<CPLX, false, RM, F>;
         };
-        auto kern = R == 1 ? pick(std::integral_constant<int, 1>{})
-                           : (R <= 4 ? pick(std::integral_constant<int, 4>{}) : pick(std::integral_constant<int, 0>{}));
+        auto pickr = [&](auto fc) {
+            return R == 1 ? pick(std::integral_constant<int, 1>{}, fc)
+                          : (R <= 4 ? pick(std::integral_constant<int, 4>{}, fc)
+                                    : pick(std::integral_constant<int, 0>{}, fc));
+        };
+        auto kern = fxm ? pickr(std::true_type{}) : pickr(std::false_type{});
         if (lds > 65536 &&
             hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return fail(MW_EHIP, "hipFuncSetAttribute failed");
-        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(256), lds, s, p, R, ket, x, W, S, Cc, Ee, c0);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(256), lds, s, p, R, ket, x, W, S, Cc, Ee, c0, fx);
         return MW_OK;
     }
     const unsigned gs = (unsigned)((p.npacket - p.npacket_double + 3) / 4);
     if (gs == 0) return MW_OK;
-    if (sym)
-        hipLaunchKernelGGL((k_rdm_single<CPLX, true>), dim3(gs), dim3(256), 0, s, p, R, bra, ket, W, S, Cc, Ee,
-                           copy_stride);
-    else
-        hipLaunchKernelGGL((k_rdm_single<CPLX, false>), dim3(gs), dim3(256), 0, s, p, R, bra, ket, W, S, Cc, Ee,
-                           copy_stride);
+    auto kern = sym ? (fxm ? k_rdm_single<CPLX, true, true> : k_rdm_single<CPLX, true, false>)
+                    : (fxm ? k_rdm_single<CPLX, false, true> : k_rdm_single<CPLX, false, false>);
+    hipLaunchKernelGGL(kern, dim3(gs), dim3(256), 0, s, p, R, bra, ket, W, S, Cc, Ee, copy_stride, fx);
     return MW_OK;
 }
 
@@ -938,8 +1108,9 @@ template <bool CPLX>
 static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CPLX>::T *bra,
                                  const typename Scal<CPLX>::T *ket, const RdmWeights &W, bool sym,
                                  typename Scal<CPLX>::T *acc_ab, typename Scal<CPLX>::T *acc_pair,
-                                 typename Scal<CPLX>::T *x, hipStream_t s)
+                                 typename Scal<CPLX>::T *x, const double *fx, hipStream_t s)
 {
+    const bool fxm = fx != nullptr;
     using T = typename Scal<CPLX>::T;
     (void)bra;
     auto go = [&](int c, T *acc, int ncols) -> mw_status {
@@ -948,17 +1119,23 @@ static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CP
         const size_t lds = (size_t)ncols * sizeof(T);
         if (lds > 160 * 1024) return fail(MW_EUNSUPPORTED, "density-matrix row exceeds the LDS of a workgroup");
         const bool wide = (c & 1) == 0;
-        auto pick = [&](auto rm) {
+        auto pick = [&](auto rm, auto fc) {
             constexpr int RM = decltype(rm)::value;
-            return sym ? (wide ? k_rdm_rows<CPLX, true, true, RM> : k_rdm_rows<CPLX, true, false, RM>)
-                       : (wide ? k_rdm_rows<CPLX, false, true, RM> : k_rdm_rows<CPLX, false, false, RM>);
+            constexpr bool F = decltype(fc)::value;
+            return sym ? (wide ? k_rdm_rows<CPLX, true, true, RM, F> : k_rdm_rows<CPLX, true, false, RM, F>)
+                       : (wide ? k_rdm_rows<CPLX, false, true, RM, F> : k_rdm_rows<CPLX, false, false, RM, F>);
         };
-        auto kern = R == 1 ? pick(std::integral_constant<int, 1>{})
-                           : (R <= 4 ? pick(std::integral_constant<int, 4>{}) : pick(std::integral_constant<int, 0>{}));
+        auto pickr = [&](auto fc) {
+            return R == 1 ? pick(std::integral_constant<int, 1>{}, fc)
+                          : (R <= 4 ? pick(std::integral_constant<int, 4>{}, fc)
+                                    : pick(std::integral_constant<int, 0>{}, fc));
+        };
+        auto kern = fxm ? pickr(std::true_type{}) : pickr(std::false_type{});
         if (lds > 65536 &&
             hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return fail(MW_EHIP, "hipFuncSetAttribute failed");
-        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(wide ? 256 : 512), lds, s, p, R, ket, x, W, acc, ncols, c0);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nch), dim3(wide ? 256 : 512), lds, s, p, R, ket, x, W, acc, ncols, c0,
+                           fx);
         return MW_OK;
     };
     for (int c = 0; c < 4; c++) {
@@ -1049,7 +1226,11 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         // bra coefficients per double membership, after the accumulators
         double *xb = (double *)((char *)p.partial + ((((size_t)(part - dab) + RDM_OCC_CHUNKS * mm) * 8 + 255) &
                                                      ~(size_t)255));
+        // fixed point: the scale after the gathered bra
+        double *fx = p.rdm_fixed ? (double *)((char *)xb + (((size_t)p.nmem * p.max_roots * 8 + 255) & ~(size_t)255))
+                                 : nullptr;
         zero(dab, n4 + 2 * np2 + RDM_COPIES * cs, s);
+        if (fx) fx_scale(bra, ket, p.ndet * R, sym, W, R, fx, s);
         std::unique_lock<std::mutex> lk(g_rdm_side_mu, std::defer_lock);
         RdmSide *side = nullptr;
         const hipStream_t s2 = rdm_fork(s, lk, side);
@@ -1057,8 +1238,9 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         // correlations, then (once the gathered bra is there) the single
         // rows and their folds
         ProfToken t = prof_begin("rdm_diag", s2);
-        hipLaunchKernelGGL(k_rdm_occ_lds<false>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 127) / 128)), dim3(1024), 0, s2,
-                           p, R, (const double *)bra, (const double *)ket, W, part);
+        auto occk = fx ? k_rdm_occ_lds<false, true> : k_rdm_occ_lds<false, false>;
+        hipLaunchKernelGGL(occk, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 127) / 128)), dim3(1024), 0, s2, p, R,
+                           (const double *)bra, (const double *)ket, W, part, (const double *)fx);
         hipLaunchKernelGGL(k_rdm_occ_reduce<double>, dim3(gred), dim3(256), 0, s2, M, RDM_OCC_CHUNKS,
                            (const double *)part, D);
         prof_end(t, s2);
@@ -1066,9 +1248,10 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         if (!rdm_wait_x(s, side)) return fail(MW_EHIP, "ordering the density-matrix side stream failed");
         t = prof_begin("rdm_single", s2);
         mw_status st = launch_rdm_single_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, S, Cc, Ee,
-                                                     xb, cs, s2);
+                                                     xb, cs, fx, s2);
         prof_end(t, s2);
         if (st != MW_OK) return st;
+        if (fx) fx_float(S, RDM_COPIES * cs, fx, s2);
         hipLaunchKernelGGL(k_rdm_fold<double>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s2, S, cs,
                            RDM_COPIES);
         if (sym) {
@@ -1078,9 +1261,10 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
                                n, 2);
         }
         t = prof_begin("rdm_double", s);
-        st = launch_rdm_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, dab, dt0, xb, s);
+        st = launch_rdm_rows<false>(p, R, (const double *)bra, (const double *)ket, W, sym, dab, dt0, xb, fx, s);
         prof_end(t, s);
         if (st != MW_OK) return st;
+        if (fx) fx_float(dab, n4 + np2, fx, s);  // dab and dt0 (dt1 stays zero)
         if (!rdm_join(s, side)) return fail(MW_EHIP, "joining the density-matrix side stream failed");
         t = prof_begin("rdm_final", s);
         hipLaunchKernelGGL(k_rdm_finalize_sf, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, p, dab, dt0, dt1,
@@ -1094,13 +1278,18 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
                 *D = S + RDM_COPIES * cs, *part = D + mm;
         double2 *xb = (double2 *)((char *)p.partial + ((((size_t)(part - dt0) + RDM_OCC_CHUNKS * mm) * 16 + 255) &
                                                        ~(size_t)255));
+        double *fx = p.rdm_fixed
+                         ? (double *)((char *)xb + (((size_t)p.nmem * p.max_roots * 16 + 255) & ~(size_t)255))
+                         : nullptr;
         zero((double *)dt0, 2 * (2 * np2 + RDM_COPIES * cs), s);
+        if (fx) fx_scale(bra, ket, 2 * p.ndet * R, sym, W, R, fx, s);
         std::unique_lock<std::mutex> lk(g_rdm_side_mu, std::defer_lock);
         RdmSide *side = nullptr;
         const hipStream_t s2 = rdm_fork(s, lk, side);
         ProfToken t = prof_begin("rdm_diag", s2);
-        hipLaunchKernelGGL(k_rdm_occ_lds<true>, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(1024), 0, s2, p,
-                           R, (const double2 *)bra, (const double2 *)ket, W, part);
+        auto occk = fx ? k_rdm_occ_lds<true, true> : k_rdm_occ_lds<true, false>;
+        hipLaunchKernelGGL(occk, dim3(RDM_OCC_CHUNKS, (unsigned)((M + 63) / 64)), dim3(1024), 0, s2, p, R,
+                           (const double2 *)bra, (const double2 *)ket, W, part, (const double *)fx);
         hipLaunchKernelGGL(k_rdm_occ_reduce<double2>, dim3(gred), dim3(256), 0, s2, M, RDM_OCC_CHUNKS,
                            (const double2 *)part, D);
         prof_end(t, s2);
@@ -1108,9 +1297,10 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         if (!rdm_wait_x(s, side)) return fail(MW_EHIP, "ordering the density-matrix side stream failed");
         t = prof_begin("rdm_single", s2);
         mw_status st = launch_rdm_single_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym, S, Cc,
-                                                    (double *)nullptr, xb, cs, s2);
+                                                    (double *)nullptr, xb, cs, fx, s2);
         prof_end(t, s2);
         if (st != MW_OK) return st;
+        if (fx) fx_float((double *)S, 2 * RDM_COPIES * cs, fx, s2);
         hipLaunchKernelGGL(k_rdm_fold<double2>, dim3((unsigned)((cs + 255) / 256)), dim3(256), 0, s2, S, cs,
                            RDM_COPIES);
         if (sym) {
@@ -1121,9 +1311,10 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         }
         t = prof_begin("rdm_double", s);
         st = launch_rdm_rows<true>(p, R, (const double2 *)bra, (const double2 *)ket, W, sym, (double2 *)nullptr, dt0,
-                                   xb, s);
+                                   xb, fx, s);
         prof_end(t, s);
         if (st != MW_OK) return st;
+        if (fx) fx_float((double *)dt0, 2 * np2, fx, s);
         if (!rdm_join(s, side)) return fail(MW_EHIP, "joining the density-matrix side stream failed");
         t = prof_begin("rdm_final", s);
         hipLaunchKernelGGL(k_rdm_finalize_spinor, dim3((unsigned)((m4 + 255) / 256)), dim3(256), 0, s, p, dt0, dt1, S,

@@ -23,7 +23,8 @@ STATUS = {0: "MW_OK", -1: "MW_EINVAL", -2: "MW_ENOTSORTED", -3: "MW_EELEC", -4: 
 INFO = {"ndet": 0, "groups": 1, "memberships": 2, "pairs": 3, "single_pairs": 4,
         "double_pairs": 5, "evaluations": 6, "workspace_bytes": 7, "scalar_bytes": 8,
         "norb": 9, "kind": 10, "packets": 11, "double_packets": 12, "column_partials": 13,
-        "double_pairs_large_groups": 14, "rdm_row_entries": 15, "rdm_row_chunks": 16, "built_on_device": 17}
+        "double_pairs_large_groups": 14, "rdm_row_entries": 15, "rdm_row_chunks": 16, "built_on_device": 17,
+        "rdm_fixed": 18}
 
 # index arrays of a bound plan, in the order of mw_plan_array
 PLAN_ARRAYS = ("grp_off", "grp_key", "grp_type", "grp_col", "mem", "mem_grp", "slot_mem", "slot_pos",
@@ -82,6 +83,7 @@ def lib():
         L.mw_autotune.argtypes = [vp, i32, vp, vp, vp, C.POINTER(i32)]
         L.mw_plan_get_tuning.argtypes = [vp, C.POINTER(i32)]
         L.mw_plan_set_tuning.argtypes = [vp, i32]
+        L.mw_plan_set_rdm_mode.argtypes = [vp, i32]
         L.mw_autotune_batched.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), vp,
                                           C.POINTER(i32)]
         L.mw_profile.argtypes = [i32]
@@ -120,7 +122,7 @@ def lib():
                      "mw_davidson", "mw_connect_dump", "mw_profile", "mw_profile_read",
                      "mw_plan_update_integrals", "mw_sigma_batched_direct", "mw_autotune", "mw_autotune_batched",
                      "mw_pt2_work_bytes", "mw_pt2", "mw_select", "mw_energy", "mw_energy_backward",
-                     "mw_plan_get_tuning", "mw_plan_set_tuning",
+                     "mw_plan_get_tuning", "mw_plan_set_tuning", "mw_plan_set_rdm_mode",
                      "mw_sigma_backward", "mw_energy_batched", "mw_energy_backward_batched"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -228,6 +230,17 @@ class Plan:
     @tuning.setter
     def tuning(self, code: int):
         _check(lib().mw_plan_set_tuning(self._plan, int(code)))
+
+    @property
+    def rdm_fixed_point(self) -> bool:
+        """Density-matrix mode: False (default) sums contributions with
+        floating-point atomics (reproducible to rounding), True with 64-bit
+        fixed-point integer atomics (the same bits on every call)."""
+        return self.info("rdm_fixed") == 1
+
+    @rdm_fixed_point.setter
+    def rdm_fixed_point(self, on: bool):
+        _check(lib().mw_plan_set_rdm_mode(self._plan, 1 if on else 0))
 
     def tuning_key(self, nroots: int, arch: str) -> str:
         """Key of this plan's tuned launch parameters in a tuning cache: the

@@ -162,3 +162,17 @@ def test_tuning_cache_file(tmp_path):
     assert not b.load_tuning(cache, 1, "gfx942")   # other architecture
     other = mw.Plan(synth.workload(4), upload=False)
     assert not other.load_tuning(cache, 1, "gfx950")
+
+
+def test_rdm_mode_is_host_state_with_status_codes():
+    """mw_plan_set_rdm_mode: 0 and 1 accepted (read back as statistic 18),
+    anything else MW_EINVAL, a NULL plan MW_EINVAL; no device needed."""
+    pl = mw.Plan(synth.workload(0), upload=False)
+    assert pl.info("rdm_fixed") == 0 and not pl.rdm_fixed_point
+    pl.rdm_fixed_point = True
+    assert pl.info("rdm_fixed") == 1 and pl.rdm_fixed_point
+    assert mw.lib().mw_plan_set_rdm_mode(pl._plan, 2) == -1
+    assert mw.lib().mw_plan_set_rdm_mode(None, 1) == -1
+    assert pl.info("rdm_fixed") == 1
+    pl.rdm_fixed_point = False
+    assert pl.info("rdm_fixed") == 0
