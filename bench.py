@@ -47,6 +47,7 @@ Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--roots 1]
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -153,6 +154,11 @@ def main():
     torch.cuda.synchronize()
     log("[bench] warmup done")
 
+    # Python's cyclic garbage collector is run before and held off during
+    # the timed steps: a full collection (tens of ms) landing on the first
+    # step would leave the GPU idle (the same is done in _time)
+    gc.collect()
+    gc.disable()
     mw.profile(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -164,6 +170,7 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     mw.profile(False)
     ms_step = ev0.elapsed_time(ev1) / args.steps
     n_grp, ms_grp = mw.profile_read("group_sigma")
@@ -344,11 +351,16 @@ def _time(fn, steps, warmup=2):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+    finally:
+        gc.enable()
     return e0.elapsed_time(e1) / steps
 
 
