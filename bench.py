@@ -572,6 +572,17 @@ def leg_pt2():
                     "pairs_kept": st["kept_pairs"], "external_dets": st["external"], "passes": st["passes"],
                     "buckets": st["buckets"], "kept_pairs_per_s": st["kept_pairs"] / dt,
                     "emit_ms": t_enum, "bucket_ms": t_bucket}
+        # Each kept pair is one record: 32 bytes (A, H_AA, hash key and J)
+        # and 8 bytes of H_AJ c_J, claimed with one returning device atomic
+        # and written by the emit passes, read once by the bucket kernels.
+        # The emit is bound by the claims (memory-side atomics; no published
+        # peak), so the record bytes are set against HBM for scale only.
+        kept = st["kept_pairs"]
+        rec_bytes = 2 * 40 * kept
+        hbm = rec_bytes / max((t_enum + t_bucket) * 1e-3, 1e-12) / 1e9
+        res[key]["roofline"] = {"bound": "memory-side atomics", "kernel": "k_pt2_enum emit passes",
+                                "achieved": kept / max(t_enum * 1e-3, 1e-12), "unit": "claims/s",
+                                "record_bytes": rec_bytes, "record_GBps": hbm, "record_frac_of_hbm": hbm / 8000.0}
         log(f"[bench] pt2 {key}: E2 = {e2[0]:.10f}, {st['kept_pairs']} pairs, {st['external']} external dets, "
             f"{st['passes']} passes, {dt:.2f}s (emit {t_enum:.0f} ms, buckets {t_bucket:.0f} ms)")
     # selection of the next determinants from the same state (one call,
