@@ -207,6 +207,9 @@ std::mutex g_grad_mu;
 std::vector<GradGraph> g_grad;
 uint64_t g_grad_clock = 0;
 hipStream_t g_grad_stream = nullptr;
+// the second branch of the density-matrix backward inside the captures
+hipStream_t g_grad_side = nullptr;
+hipEvent_t g_grad_ev[3] = {nullptr, nullptr, nullptr};
 
 void drop_graph(GradGraph &e)
 {
@@ -292,10 +295,20 @@ mw_status mw_energy_backward_batched(int32_t nprob, const mw_plan *plans, const 
     if (!hit) {
         if (!g_grad_stream && hipStreamCreateWithFlags(&g_grad_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(MW_EHIP, "hipStreamCreateWithFlags failed");
+        if (!g_grad_side) {
+            hipStream_t t = nullptr;
+            if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess)
+                return fail(MW_EHIP, "hipStreamCreateWithFlags failed");
+            for (auto &e : g_grad_ev)
+                if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                    return fail(MW_EHIP, "hipEventCreateWithFlags failed");
+            g_grad_side = t;
+        }
         if (hipStreamBeginCapture(g_grad_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(MW_EHIP, "hipStreamBeginCapture failed");
         {
             ProfSuppress quiet;
+            RdmCaptureSide branch(g_grad_side, g_grad_ev[0], g_grad_ev[1], g_grad_ev[2]);
             for (int i = 0; i < nprob && st == MW_OK; i++)
                 st = launch_energy_backward(*d[i], nroots[i], c[i], sigma[i], ge[i], grad_c[i], grad_h[i], grad_g[i],
                                             g_grad_stream);

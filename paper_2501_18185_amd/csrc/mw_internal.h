@@ -169,6 +169,14 @@ mw_status launch_sigma_batched(int nprob, const DevPlan *const *plans, const int
 // (complex only), gamma and Gamma are written conjugated
 mw_status launch_rdm(const DevPlan &p, int nroots, const void *bra, const void *ket, const double *weights,
                      const double *dev_weights, void *gamma, void *Gamma, double fac_g, bool conj, hipStream_t s);
+// While alive on a thread, launch_rdm on a stream that this thread is
+// capturing puts its side branch (occupation correlations, single rows) on
+// `side`, a stream that is used only inside captures, joined through the
+// three events; without it a capture gets the serial order.
+struct RdmCaptureSide {
+    RdmCaptureSide(hipStream_t side, hipEvent_t fork, hipEvent_t xready, hipEvent_t join);
+    ~RdmCaptureSide();
+};
 mw_status launch_connect(const DevPlan &p, int64_t *count, int64_t *out, hipStream_t s);
 
 }  // namespace mw

@@ -1149,8 +1149,10 @@ static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CP
 // single-pair rows: they fill other accumulators than the double-pair rows,
 // so they run beside the bra gather and the double rows (the single rows
 // after the gather, which they read) and are joined before the final pass.  The fork and
-// join events are shared, so the launch sequence holds a lock; a caller
-// stream that is being captured into a graph gets the serial order.
+// join events are shared, so the launch sequence holds a lock.  A caller
+// stream that is being captured into a graph gets the serial order, unless
+// the capturing thread lends a stream of its own (RdmCaptureSide), which
+// then joins the capture as the second branch.
 namespace {
 struct RdmSide {
     hipStream_t s = nullptr;
@@ -1159,6 +1161,7 @@ struct RdmSide {
 };
 std::mutex g_rdm_side_mu;
 RdmSide g_rdm_side[64];
+thread_local RdmSide t_rdm_cap;  // lent by a capturer (RdmCaptureSide)
 
 RdmSide *rdm_side_locked()
 {
@@ -1190,7 +1193,16 @@ hipStream_t rdm_fork(hipStream_t s, std::unique_lock<std::mutex> &lk, RdmSide *&
 {
     x = nullptr;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return s;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return s;
+    if (cap != hipStreamCaptureStatusNone) {
+        // a capture: the lent stream joins it through the fork event
+        RdmSide *y = &t_rdm_cap;
+        if (cap != hipStreamCaptureStatusActive || !y->s || hipEventRecord(y->fork, s) != hipSuccess ||
+            hipStreamWaitEvent(y->s, y->fork, 0) != hipSuccess)
+            return s;
+        x = y;
+        return y->s;
+    }
     lk.lock();
     RdmSide *y = rdm_side_locked();
     if (!y || hipEventRecord(y->fork, s) != hipSuccess || hipStreamWaitEvent(y->s, y->fork, 0) != hipSuccess)
@@ -1205,6 +1217,16 @@ bool rdm_join(hipStream_t s, RdmSide *x)
     return hipEventRecord(x->join, x->s) == hipSuccess && hipStreamWaitEvent(s, x->join, 0) == hipSuccess;
 }
 }  // namespace
+
+RdmCaptureSide::RdmCaptureSide(hipStream_t side, hipEvent_t fork, hipEvent_t xready, hipEvent_t join)
+{
+    t_rdm_cap.s = side;
+    t_rdm_cap.fork = fork;
+    t_rdm_cap.xready = xready;
+    t_rdm_cap.join = join;
+}
+
+RdmCaptureSide::~RdmCaptureSide() { t_rdm_cap = RdmSide(); }
 
 mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, const double *weights,
                      const double *dev_weights, void *gamma, void *Gamma, double fac_g, bool conj, hipStream_t s)

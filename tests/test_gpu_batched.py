@@ -204,8 +204,9 @@ def test_batched_energy_gradients_equal_per_problem(torch, batch):
     weighted per root): energies equal the oracle's c^T sigma, and every
     gradient (c, h, g) equals the per-problem Energy gradients within
     1e-12; the oracle's weighted density matrices check one problem
-    directly.  The raw batched backward replays its captured graph with the
-    same bits."""
+    directly.  The raw batched backward replays its captured graph (the
+    density-matrix backward as two branches) within 1e-12 of its first
+    run (float atomics; the fixed-point mode's bits are tested elsewhere)."""
     from paper_2501_18185_amd import mw
     from paper_2501_18185_amd.autograd import BatchedEnergy, Energy
     probs, plans, cs, R = batch
