@@ -389,7 +389,17 @@ def leg_rdm(plan, c, prob):
     finally:
         plan.rdm_fixed_point = False
     log(f"[bench] rdm: backward in fixed point {t_fix:.2f} ms")
-    return {"workload": prob.name, "forward_ms": t_fwd, "backward_ms": t_bwd,
+    # the double-pair rows: with one vector each unordered connected double
+    # pair is visited once, reading the member's position (2 B) and its
+    # gathered coefficient (8 B); counters of these launches are kept in
+    # profiles/rdm_sci-n64.md
+    t_rows = md / max(nd, 1)
+    rows_bytes = plan.info("double_pairs") // 2 * (2 + 8)
+    rows_gbps = rows_bytes / max(t_rows * 1e-3, 1e-12) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_rdm_rows (four launches)", "achieved": rows_gbps, "peak": 8000.0,
+            "unit": "GB/s", "frac": rows_gbps / 8000.0, "bytes_per_backward": rows_bytes,
+            "unit_count": "unordered double pairs x (2 B position + 8 B gathered coefficient)", "traffic": None}
+    return {"workload": prob.name, "forward_ms": t_fwd, "backward_ms": t_bwd, "roofline": roof,
             "rdm_double_ms": md / max(nd, 1), "rdm_single_ms": ms_ / max(ns, 1), "rdm_occ_ms": mq / max(nq, 1),
             "rdm_final_ms": mf / max(nf, 1), "backward_fixed_point_ms": t_fix,
             "gamma_shape": [prob.norb] * 2, "Gamma_shape": [prob.norb] * 4}
