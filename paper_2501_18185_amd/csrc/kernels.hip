@@ -634,6 +634,13 @@ SideStream *side_stream_locked()
 }
 }  // namespace
 
+hipStream_t device_side_stream()
+{
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideStream *x = side_stream_locked();
+    return x ? x->s : nullptr;
+}
+
 template <bool CPLX, int GL>
 static void launch_gather(const DevPlan &p, int R, const typename Scal<CPLX>::T *c,
                           const typename Scal<CPLX>::T *part, typename Scal<CPLX>::T *sigma, hipStream_t s)

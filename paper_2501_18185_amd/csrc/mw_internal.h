@@ -162,6 +162,12 @@ mw_status launch_energy_backward(const DevPlan &p, int R, const void *c, const v
 // kernel launchers (kernels.hip)
 mw_status launch_diag(const DevPlan &p, hipStream_t s);
 mw_status launch_sigma(const DevPlan &p, int nroots, const void *c, void *sigma, hipStream_t s);
+// the current device's second stream (null if it cannot be created): the
+// single-group kernels of sigma and the side branch of the density-matrix
+// backward share it, each with its own fork and join events, so that the
+// library adds one stream per device (hardware queues are few and streams
+// are spread over them in creation order)
+hipStream_t device_side_stream();
 mw_status launch_sigma_batched(int nprob, const DevPlan *const *plans, const int *nroots,
                                const void *const *c, void *const *sigma, hipStream_t s);
 // transition density matrices; weights (host) or dev_weights (device) per

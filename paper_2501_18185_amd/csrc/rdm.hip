@@ -1145,8 +1145,8 @@ static mw_status launch_rdm_rows(const DevPlan &p, int R, const typename Scal<CP
     return MW_OK;
 }
 
-// A second stream per device for the occupation correlations and the
-// single-pair rows: they fill other accumulators than the double-pair rows,
+// The device's second stream (the one sigma's single groups use) for the
+// occupation correlations and the single-pair rows: they fill other accumulators than the double-pair rows,
 // so they run beside the bra gather and the double rows (the single rows
 // after the gather, which they read) and are joined before the final pass.  The fork and
 // join events are shared, so the launch sequence holds a lock.  A caller
@@ -1169,7 +1169,8 @@ RdmSide *rdm_side_locked()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     RdmSide &x = g_rdm_side[dev];
     if (!x.s && !x.failed) {
-        if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess ||
+        // the device's side stream, shared with sigma's single groups
+        if (!(x.s = device_side_stream()) ||
             hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&x.xready, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
