@@ -1253,7 +1253,11 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
         double *fx = p.rdm_fixed ? (double *)((char *)xb + (((size_t)p.nmem * p.max_roots * 8 + 255) & ~(size_t)255))
                                  : nullptr;
         zero(dab, n4 + 2 * np2 + RDM_COPIES * cs, s);
-        if (fx) fx_scale(bra, ket, p.ndet * R, sym, W, R, fx, s);
+        if (fx) {
+            ProfToken ts = prof_begin("rdm_fx_scale", s);
+            fx_scale(bra, ket, p.ndet * R, sym, W, R, fx, s);
+            prof_end(ts, s);
+        }
         std::unique_lock<std::mutex> lk(g_rdm_side_mu, std::defer_lock);
         RdmSide *side = nullptr;
         const hipStream_t s2 = rdm_fork(s, lk, side);
@@ -1305,7 +1309,11 @@ mw_status launch_rdm(const DevPlan &p, int R, const void *bra, const void *ket, 
                          ? (double *)((char *)xb + (((size_t)p.nmem * p.max_roots * 16 + 255) & ~(size_t)255))
                          : nullptr;
         zero((double *)dt0, 2 * (2 * np2 + RDM_COPIES * cs), s);
-        if (fx) fx_scale(bra, ket, 2 * p.ndet * R, sym, W, R, fx, s);
+        if (fx) {
+            ProfToken ts = prof_begin("rdm_fx_scale", s);
+            fx_scale(bra, ket, 2 * p.ndet * R, sym, W, R, fx, s);
+            prof_end(ts, s);
+        }
         std::unique_lock<std::mutex> lk(g_rdm_side_mu, std::defer_lock);
         RdmSide *side = nullptr;
         const hipStream_t s2 = rdm_fork(s, lk, side);

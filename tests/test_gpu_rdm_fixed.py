@@ -113,9 +113,15 @@ def test_fixed_point_rdm_equals_oracle_and_repeats_bitwise(torch, name):
     pl = mw.Plan(p, max_roots=R)
     bd = _dev(torch, c)
     kd = None if k is None else _dev(torch, k)
+    mw.profile(True)
     a1, a2 = (x.cpu().numpy() for x in _rdm(pl, bd, kd, w))
+    mw.profile(False)
+    assert mw.profile_read("rdm_fx_scale")[0] == 0  # float atomics: no fixed-point scale
     pl.rdm_fixed_point = True
+    mw.profile(True)
     f1, f2 = (x.cpu().numpy() for x in _rdm(pl, bd, kd, w))
+    mw.profile(False)
+    assert mw.profile_read("rdm_fx_scale")[0] == 1  # the fixed-point path ran
     for _ in range(2):
         g1, g2 = (x.cpu().numpy() for x in _rdm(pl, bd, kd, w))
         assert np.array_equal(g1, f1) and np.array_equal(g2, f2), name
