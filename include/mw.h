@@ -241,8 +241,10 @@ mw_status mw_rdm_backward(mw_plan plan, int32_t nroots, const void *bra, const v
  * inputs give the same bits.  s is set per call on the device from
  * B = max_k |w_k| ||bra||_F ||ket||_F, which bounds every accumulated entry:
  * s = 60 - e for B in [2^(e-1), 2^e), so each contribution is rounded to
- * at most B 2^-60 (absolute).  Scaling bra or ket by a power of two scales
- * the results exactly.  Host only; MW_EINVAL for other modes. */
+ * at most B 2^-60 (absolute).  The norms are computed as a largest
+ * magnitude times a scaled sum of squares, so no square overflows or
+ * underflows; scaling bra or ket by a power of two scales the results
+ * exactly.  Host only; MW_EINVAL for other modes. */
 mw_status mw_plan_set_rdm_mode(mw_plan plan, int32_t mode);
 
 /* Energies e_k = Re sum_I conj(c_Ik) sigma_Ik (the expectation value

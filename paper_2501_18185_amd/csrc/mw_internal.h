@@ -111,7 +111,7 @@ constexpr int64_t RDM_CHUNK_WORK = 1 << 17;
 // fixed-point density matrices: the scale and the per-block norm partials
 // of its bound, after the gathered bra coefficients in the scratch
 constexpr int RDM_FX_BLOCKS = 256;
-constexpr size_t RDM_FX_BYTES = 256 + RDM_FX_BLOCKS * 16;
+constexpr size_t RDM_FX_BYTES = 256 + RDM_FX_BLOCKS * 32;
 struct BatchArgs {
     int nprob;
     const DevPlan *plans[MW_MAXB];   // device copies

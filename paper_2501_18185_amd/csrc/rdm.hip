@@ -961,15 +961,47 @@ static void zero(double *x, int64_t n, hipStream_t s)
 // conj(bra_Ik) ket_Jk, and that operator takes each determinant to at most
 // one other, so by Cauchy-Schwarz |entry| <= B = max_k |w_k| ||bra||_F
 // ||ket||_F; with B in [2^(e-1), 2^e), s = 60 - e keeps |entry sc| < 2^60.
-// The norms: per-block sums of squares over a fixed partition (a
-// grid-stride loop of RDM_FX_BLOCKS blocks, a tree in LDS), added in block
-// order by one block, so the scale is the same on every call.
-__device__ __forceinline__ void block_tree2(double *a, double *b)
+// The norms are kept as (m, q): the largest magnitude m and the sum q of
+// (x / m)^2, so that ||x||^2 = m^2 q neither overflows nor underflows (the
+// scaled sum of square of two-norm routines), over a fixed partition (a
+// grid-stride loop of RDM_FX_BLOCKS blocks, a tree in LDS) combined in
+// block order by one block, so the scale is the same on every call, and
+// scaling bra or ket by 2^k shifts s by exactly k.
+__device__ __forceinline__ void norm_add(double &m, double &q, double x)
+{
+    x = fabs(x);
+    if (x == 0.0) return;
+    if (x > m) {
+        const double r = m / x;
+        q = 1.0 + q * r * r;
+        m = x;
+    } else {
+        const double r = x / m;
+        q += r * r;
+    }
+}
+
+__device__ __forceinline__ void norm_merge(double &m, double &q, double m2, double q2)
+{
+    if (m2 == 0.0) return;
+    if (m2 > m) {
+        const double r = m / m2;
+        q = q2 + q * r * r;
+        m = m2;
+    } else {
+        const double r = m2 / m;
+        q += q2 * r * r;
+    }
+}
+
+// the four (m, q) of bra and ket over the block, into lane 0's slots
+__device__ __forceinline__ void block_tree_norms(double *mb, double *qb, double *mk, double *qk)
 {
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            a[threadIdx.x] += a[threadIdx.x + o];
-            b[threadIdx.x] += b[threadIdx.x + o];
+        const int t = (int)threadIdx.x;
+        if (t < o) {
+            norm_merge(mb[t], qb[t], mb[t + o], qb[t + o]);
+            norm_merge(mk[t], qk[t], mk[t + o], qk[t + o]);
         }
         __syncthreads();
     }
@@ -978,18 +1010,23 @@ __device__ __forceinline__ void block_tree2(double *a, double *b)
 __global__ __launch_bounds__(256) void k_rdm_fx_norms(int64_t nb, const double *__restrict__ bra, int64_t nk,
                                                       const double *__restrict__ ket, double *__restrict__ part)
 {
-    __shared__ double sa[256], sb[256];
+    __shared__ double smb[256], sqb[256], smk[256], sqk[256];
     const int64_t G = (int64_t)gridDim.x * blockDim.x;
-    double a = 0.0, b = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nb; t += G) a += bra[t] * bra[t];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nk; t += G) b += ket[t] * ket[t];
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
+    double mb = 0.0, qb = 0.0, mk = 0.0, qk = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nb; t += G) norm_add(mb, qb, bra[t]);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nk; t += G) norm_add(mk, qk, ket[t]);
+    smb[threadIdx.x] = mb;
+    sqb[threadIdx.x] = qb;
+    smk[threadIdx.x] = mk;
+    sqk[threadIdx.x] = qk;
     __syncthreads();
-    block_tree2(sa, sb);
+    block_tree_norms(smb, sqb, smk, sqk);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = sa[0];
-        part[2 * blockIdx.x + 1] = sb[0];
+        double *o = part + 4 * (size_t)blockIdx.x;
+        o[0] = smb[0];
+        o[1] = sqb[0];
+        o[2] = smk[0];
+        o[3] = sqk[0];
     }
 }
 
@@ -997,28 +1034,36 @@ __global__ __launch_bounds__(256) void k_rdm_fx_norms(int64_t nb, const double *
 __global__ __launch_bounds__(256) void k_rdm_fx_scale(const double *__restrict__ part, int sym, RdmWeights W, int R,
                                                       double *__restrict__ fx)
 {
-    __shared__ double sa[256], sb[256];
-    double a = 0.0, b = 0.0;
+    __shared__ double smb[256], sqb[256], smk[256], sqk[256];
+    double mb = 0.0, qb = 0.0, mk = 0.0, qk = 0.0;
     for (int i = threadIdx.x; i < RDM_FX_BLOCKS; i += blockDim.x) {
-        a += part[2 * i];
-        b += part[2 * i + 1];
+        norm_merge(mb, qb, part[4 * i], part[4 * i + 1]);
+        norm_merge(mk, qk, part[4 * i + 2], part[4 * i + 3]);
     }
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
+    smb[threadIdx.x] = mb;
+    sqb[threadIdx.x] = qb;
+    smk[threadIdx.x] = mk;
+    sqk[threadIdx.x] = qk;
     __syncthreads();
-    block_tree2(sa, sb);
+    block_tree_norms(smb, sqb, smk, sqk);
     if (threadIdx.x != 0) return;
     double wmax = 0.0;
     for (int k = 0; k < R; k++) wmax = fmax(wmax, fabs(W.dev ? W.dev[k] : W.w[k]));
-    const double nb = sqrt(sa[0]), nk = sym ? nb : sqrt(sb[0]);
+    double f[5] = {wmax, smb[0], sqrt(sqb[0]), sym ? smb[0] : smk[0], sqrt(sym ? sqb[0] : sqk[0])};
     const double big = 1.79e308;
+    bool ok = true;
+    for (double v : f) ok = ok && v > 0.0 && v <= big;
     int s = 0;
-    if (wmax > 0.0 && nb > 0.0 && nk > 0.0 && wmax <= big && nb <= big && nk <= big) {
-        // the exponent of the product without forming it (no overflow)
-        int ew, eb, ek, em;
-        const double fw = frexp(wmax, &ew), fb = frexp(nb, &eb), fk = frexp(nk, &ek);
-        frexp(fw * fb * fk, &em);
-        s = max(-1000, min(1000, 60 - (ew + eb + ek + em)));
+    if (ok) {
+        // the exponent of the product of the five factors without forming it
+        int e = 0, ei;
+        double mant = 1.0;
+        for (double v : f) {
+            mant *= frexp(v, &ei);
+            e += ei;
+        }
+        frexp(mant, &ei);
+        s = max(-1000, min(1000, 60 - (e + ei)));
     }
     fx[0] = ldexp(1.0, s);
     fx[1] = ldexp(1.0, -s);
@@ -1043,7 +1088,7 @@ static void fx_float(double *x, int64_t n, const double *fx, hipStream_t s)
 static void fx_scale(const void *bra, const void *ket, int64_t nd, bool sym, const RdmWeights &W, int R, double *fx,
                      hipStream_t s)
 {
-    double *part = fx + 32;
+    double *part = fx + 32;  // RDM_FX_BLOCKS x (m, q of bra, m, q of ket)
     hipLaunchKernelGGL(k_rdm_fx_norms, dim3(RDM_FX_BLOCKS), dim3(256), 0, s, nd, (const double *)bra,
                        sym ? (int64_t)0 : nd, (const double *)ket, part);
     hipLaunchKernelGGL(k_rdm_fx_scale, dim3(1), dim3(256), 0, s, (const double *)part, (int)sym, W, R, fx);

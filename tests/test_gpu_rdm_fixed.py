@@ -142,7 +142,8 @@ def test_fixed_point_rdm_equals_oracle_and_repeats_bitwise(torch, name):
 
 @pytest.mark.parametrize("name", ["sci-3roots", "spinor-2roots"])
 def test_fixed_point_rdm_scales_exactly(torch, name):
-    """bra 2^7 and ket 2^-3: both matrices exactly 2^4 times the unscaled."""
+    """bra 2^7 and ket 2^-3: both matrices exactly 2^4 times the unscaled;
+    bra 2^-600 and 2^700 likewise; a zero bra gives exact zeros."""
     from paper_2501_18185_amd import mw
     p, c, k, w, R = _case(name)
     pl = mw.Plan(p, max_roots=R)
@@ -150,6 +151,12 @@ def test_fixed_point_rdm_scales_exactly(torch, name):
     g1, g2 = (x.cpu().numpy() for x in pl.rdm(_dev(torch, c), _dev(torch, k), weights=w))
     h1, h2 = (x.cpu().numpy() for x in pl.rdm(_dev(torch, c * 128.0), _dev(torch, k / 8.0), weights=w))
     assert np.array_equal(h1, 16.0 * g1) and np.array_equal(h2, 16.0 * g2)
+    # far from 1, where the squares of the coefficients underflow (2^-600)
+    # or overflow (2^700) in double: the scale follows the bound's exponent
+    for e in (-600, 700):
+        f = 2.0 ** e
+        h1, h2 = (x.cpu().numpy() for x in pl.rdm(_dev(torch, c * f), _dev(torch, k), weights=w))
+        assert np.array_equal(h1, f * g1) and np.array_equal(h2, f * g2), e
     z1, z2 = (x.cpu().numpy() for x in pl.rdm(_dev(torch, 0.0 * c), _dev(torch, k), weights=w))
     assert not np.any(z1) and not np.any(z2)
 
