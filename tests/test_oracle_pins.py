@@ -410,6 +410,37 @@ def test_rdm_identities_and_energy(kind):
     assert ev.min() > -1e-12 and ev.max() < occmax + 1e-12
 
 
+@pytest.mark.parametrize("kind", ["spinfree", "spinor"])
+def test_rdm_entries_bounded_by_norms(kind):
+    """Each operator a+_P a_Q or a+_P a+_R a_S a_Q takes a determinant to at
+    most one determinant (with a sign), so by Cauchy-Schwarz every transition
+    matrix element is at most ||bra|| ||ket|| in magnitude; spin summation
+    adds two (gamma) or four (Gamma) such elements.  Checked on the oracle
+    for random unnormalised vectors and for a bra concentrated on one
+    determinant; the fixed-point density matrices scale their integers by
+    this bound."""
+    rng = np.random.default_rng(41)
+    if kind == "spinfree":
+        n, na, nb = 5, 2, 2
+        d = synth.space_fci(n, na, nb)
+        p = _prob(kind, n, na, nb, d, *_random_real(n, 42))
+        f1, f2 = 2.0, 4.0
+        vec = lambda: rng.normal(size=len(d)) * rng.uniform(0.1, 10.0)
+    else:
+        nk, N = 3, 3
+        d = _spinor_space(nk, N)
+        p = _prob(kind, nk, N, -1, d, *_random_spinor(nk, 43))
+        f1, f2 = 1.0, 1.0
+        vec = lambda: (rng.normal(size=len(d)) + 1j * rng.normal(size=len(d))) * rng.uniform(0.1, 10.0)
+    one = np.zeros(len(d), dtype=complex if kind == "spinor" else float)
+    one[len(d) // 2] = 3.0
+    for bra, ket in ((vec(), vec()), (vec(), vec()), (one, vec()), (one, one)):
+        g1, g2 = sc.rdm(p, bra, ket)
+        b = np.linalg.norm(bra) * np.linalg.norm(ket)
+        assert np.abs(g1).max() <= f1 * b * (1 + 1e-12)
+        assert np.abs(g2).max() <= f2 * b * (1 + 1e-12)
+
+
 def _sym_direction_real(n, rng):
     """Random h and g directions carrying the 8-fold symmetry."""
     dh = rng.normal(size=(n, n)); dh = dh + dh.T
